@@ -1,0 +1,158 @@
+"""CPU oracle for DPG record retrieval, sorting and foreign-key joins.
+
+TEST INFRASTRUCTURE ONLY: the test suite, ``__graft_entry__.smoke()`` and the
+CPU-baseline leg of ``bench.py`` may import this package; the library under
+``paper_cs_0308004_amd`` never does.  The arithmetic lives in ``oracle.c``
+(plain C, compiled with gcc by :func:`build`); this module only marshals numpy
+arrays into it.
+
+Every function follows a passage of Cooperman, Ma and Nguyen, "DPG: A
+Cache-Efficient Accelerator for Sorting and for Join Operators":
+
+* :func:`retrieve` -- the record-retrieval problem of Section 2 (D[i] = R[S_rid[i]]).
+* :func:`dpg_phases` -- Figure 1 (Section 2.1) run phase by phase, 0-based.
+* :func:`sort_records` -- the three-phase key-pointer sort of Section 3.
+* :func:`fk_join_fact_order` / :func:`fk_join_dim_order` -- the DPG-Move and
+  DPG-Sort goals of Section 4.2.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+OK, EINVAL, ERANGE = 0, 1, 2
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: oracle status {code}")
+        self.code = code
+
+
+def build(defines: tuple[str, ...] = (), out_path: str | None = None) -> str:
+    """Compile oracle.c into a shared library with gcc and return its path."""
+    out = out_path or _LIB_PATH
+    cmd = ["gcc", "-O2", "-std=c11", "-shared", "-fPIC", "-Wall", "-Wextra", "-o", out, _SRC]
+    cmd[1:1] = [f"-D{d}" for d in defines]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+def _stale() -> bool:
+    return (not os.path.exists(_LIB_PATH)) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+
+
+_I64, _I32, _VP = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p
+
+
+def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
+    lib.oracle_retrieve.argtypes = [_VP, _I64, _I32, _VP, _I64, _VP]
+    lib.oracle_dpg_phases.argtypes = [_VP, _I64, _I32, _VP, _I64, _I64, _VP, _VP, _VP, _VP]
+    lib.oracle_sort_records.argtypes = [_VP, _I64, _I32, _I32, _I32, _VP, _VP]
+    join = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP]
+    lib.oracle_fk_join_fact_order.argtypes = join
+    lib.oracle_fk_join_dim_order.argtypes = join
+    for f in (lib.oracle_retrieve, lib.oracle_dpg_phases, lib.oracle_sort_records,
+              lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order):
+        f.restype = ctypes.c_int
+    return lib
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load the oracle library (building it first when the C source is newer)."""
+    global _lib
+    if path is not None:
+        return _bind(ctypes.CDLL(path))
+    if _lib is None:
+        if _stale():
+            build()
+        _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data) if a.size else ctypes.c_void_p(0)
+
+
+def _records(a: np.ndarray, rec_bytes: int) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.uint8)
+    if a.size % rec_bytes:
+        raise ValueError("byte array is not a whole number of records")
+    return a.reshape(-1, rec_bytes)
+
+
+def retrieve(src: np.ndarray, rids: np.ndarray, rec_bytes: int | None = None, lib=None) -> np.ndarray:
+    """dst[i] = src[rids[i]] (Section 2).  ``src`` is (N, R) uint8 or flat with rec_bytes."""
+    lib = lib or load()
+    if rec_bytes is None:
+        rec_bytes = src.shape[1]
+    s = _records(src, rec_bytes)
+    r = np.ascontiguousarray(rids, dtype=np.int32)
+    dst = np.empty((r.size, rec_bytes), dtype=np.uint8)
+    rc = lib.oracle_retrieve(_ptr(s), s.shape[0], rec_bytes, _ptr(r), r.size, _ptr(dst))
+    if rc:
+        raise OracleError(rc, "retrieve")
+    return dst
+
+
+def dpg_phases(src: np.ndarray, rids: np.ndarray, run_len: int, lib=None):
+    """Figure 1 phase by phase.  Returns (rid_run, run_off, record_run, dst)."""
+    lib = lib or load()
+    s = _records(src, src.shape[1])
+    rec_bytes = s.shape[1]
+    r = np.ascontiguousarray(rids, dtype=np.int32)
+    n_runs = -(-s.shape[0] // run_len)
+    rid_run = np.empty(r.size, dtype=np.int32)
+    run_off = np.empty(n_runs + 1, dtype=np.int64)
+    record_run = np.empty((r.size, rec_bytes), dtype=np.uint8)
+    dst = np.empty((r.size, rec_bytes), dtype=np.uint8)
+    rc = lib.oracle_dpg_phases(_ptr(s), s.shape[0], rec_bytes, _ptr(r), r.size, run_len,
+                               _ptr(rid_run), _ptr(run_off), _ptr(record_run), _ptr(dst))
+    if rc:
+        raise OracleError(rc, "dpg_phases")
+    return rid_run, run_off, record_run, dst
+
+
+def sort_records(src: np.ndarray, key_offset: int = 0, key_bytes: int = 10, lib=None):
+    """Three-phase key-pointer sort (Section 3).  Returns (dst, perm)."""
+    lib = lib or load()
+    s = _records(src, src.shape[1])
+    n, rec_bytes = s.shape
+    dst = np.empty_like(s)
+    perm = np.empty(n, dtype=np.int64)
+    rc = lib.oracle_sort_records(_ptr(s), n, rec_bytes, key_offset, key_bytes, _ptr(dst), _ptr(perm))
+    if rc:
+        raise OracleError(rc, "sort_records")
+    return dst, perm
+
+
+def _join(fn_name: str, fact: np.ndarray, dim: np.ndarray, fk_offset: int, lib=None) -> np.ndarray:
+    lib = lib or load()
+    f = _records(fact, fact.shape[1])
+    d = _records(dim, dim.shape[1])
+    out = np.empty((f.shape[0], f.shape[1] + d.shape[1]), dtype=np.uint8)
+    rc = getattr(lib, fn_name)(_ptr(f), f.shape[0], f.shape[1], fk_offset,
+                               _ptr(d), d.shape[0], d.shape[1], _ptr(out))
+    if rc:
+        raise OracleError(rc, fn_name)
+    return out
+
+
+def fk_join_fact_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, lib=None) -> np.ndarray:
+    """DPG-Move goal (Section 4.2.1): out[i] = fact[i] || dim[fk_i]."""
+    return _join("oracle_fk_join_fact_order", fact, dim, fk_offset, lib)
+
+
+def fk_join_dim_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, lib=None) -> np.ndarray:
+    """DPG-Sort goal (Section 4.2.1): joined rows in foreign-key order, ties in fact order."""
+    return _join("oracle_fk_join_dim_order", fact, dim, fk_offset, lib)

@@ -1,0 +1,283 @@
+/*
+ * CPU oracle for DPG record retrieval, DPG sorting and the two DPG foreign-key
+ * joins (Cooperman, Ma, Nguyen, "DPG: A Cache-Efficient Accelerator for Sorting
+ * and for Join Operators", arXiv cs/0308004).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a deliberately plain, slow and
+ * obviously correct statement of what the GPU library computes.  Only the test
+ * suite, the smoke check and the CPU-baseline leg of the benchmark load it.  It
+ * shares no code, header, table or helper with the HIP library, and nothing in
+ * the library may call it.
+ *
+ * Conventions (readings of the paper, listed again in the design notes):
+ *   - rids are 0-based and must lie in [0, n_src) (Section 2.1 says rid values
+ *     lie between 0 and N; Figure 1 is written 1-based, the text and the worked
+ *     example of Section 2.2 are 0-based).  An rid outside that range is an
+ *     error, never clamped.
+ *   - a record is rec_bytes contiguous bytes; record r starts at byte r*rec_bytes.
+ *   - sort keys compare as unsigned bytes, lexicographically (memcmp order); equal
+ *     keys keep the original record index order, which makes the result unique.
+ *   - join rows: the fact (referencing) row bytes followed by the dimension
+ *     (referenced, indexed) row bytes.  Dimension ids are dense, so the index
+ *     lookup of Section 4.2.2 maps a foreign key k to rid_F = k.
+ *
+ * Return codes: 0 success, 1 invalid argument, 2 rid / foreign key out of range.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORACLE_OK 0
+#define ORACLE_EINVAL 1
+#define ORACLE_ERANGE 2
+
+/* ------------------------------------------------------------------------- */
+/* Record retrieval: the problem statement of Section 2, D[i] = R[S_rid[i]].   */
+/* ------------------------------------------------------------------------- */
+int oracle_retrieve(const uint8_t *src, int64_t n_src, int32_t rec_bytes,
+                    const int32_t *rids, int64_t n_rids, uint8_t *dst)
+{
+    if (rec_bytes <= 0 || n_src < 0 || n_rids < 0)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n_rids; ++i) {
+        int64_t r = rids[i];
+        if (r < 0 || r >= n_src)
+            return ORACLE_ERANGE;
+    }
+    for (int64_t i = 0; i < n_rids; ++i) {
+        int64_t r = rids[i];
+#ifdef ORACLE_MUTANT_SHORT_COPY
+        memcpy(dst + i * (int64_t)rec_bytes, src + r * (int64_t)rec_bytes, (size_t)rec_bytes - 4);
+#elif defined(ORACLE_MUTANT_NEIGHBOUR)
+        int64_t q = (r + 1 < n_src) ? r + 1 : r;
+        memcpy(dst + i * (int64_t)rec_bytes, src + q * (int64_t)rec_bytes, (size_t)rec_bytes);
+#else
+        memcpy(dst + i * (int64_t)rec_bytes, src + r * (int64_t)rec_bytes, (size_t)rec_bytes);
+#endif
+    }
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Figure 1 of Section 2.1 carried out phase by phase, 0-based.  Used only to   */
+/* check the phase invariants and the worked example of Section 2.2; parity   */
+/* of the library is always checked against oracle_retrieve.                   */
+/*                                                                             */
+/* run_len  : L, records per run (region) of the input file                    */
+/* rid_run  : out, n_rids entries: the RID runs stored one after another        */
+/* run_off  : out, n_runs+1 entries: run i occupies rid_run[run_off[i] ..       */
+/*            run_off[i+1])                                                   */
+/* record_run: out, n_rids*rec_bytes bytes: the INTERNAL runs, same layout     */
+/* dst      : out, the gathered output                                        */
+/* ------------------------------------------------------------------------- */
+int oracle_dpg_phases(const uint8_t *src, int64_t n_src, int32_t rec_bytes,
+                      const int32_t *rids, int64_t n_rids, int64_t run_len,
+                      int32_t *rid_run, int64_t *run_off, uint8_t *record_run,
+                      uint8_t *dst)
+{
+    if (rec_bytes <= 0 || n_src < 0 || n_rids < 0 || run_len <= 0)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n_rids; ++i)
+        if (rids[i] < 0 || rids[i] >= n_src)
+            return ORACLE_ERANGE;
+    int64_t n_runs = (n_src + run_len - 1) / run_len;
+    int64_t *count = calloc((size_t)(n_runs + 1), sizeof(int64_t));
+    int64_t *cursor = calloc((size_t)(n_runs + 1), sizeof(int64_t));
+    uint8_t *cache = malloc((size_t)(run_len * rec_bytes) + 1);
+    if (!count || !cursor || !cache) {
+        free(count); free(cursor); free(cache);
+        return ORACLE_EINVAL;
+    }
+
+    /* Phase I, Distribute: every rid is appended, in RID order, to the run that
+     * holds it; the run of rid r is floor(r / L).  Runs are sized by a count
+     * first so that duplicated rids and skew fit (Section 2.3). */
+    for (int64_t i = 0; i < n_rids; ++i)
+        count[rids[i] / run_len]++;
+    run_off[0] = 0;
+    for (int64_t b = 0; b < n_runs; ++b)
+        run_off[b + 1] = run_off[b] + count[b];
+    for (int64_t b = 0; b < n_runs; ++b)
+        cursor[b] = run_off[b];
+    for (int64_t i = 0; i < n_rids; ++i) {
+        int64_t b = rids[i] / run_len;
+        rid_run[cursor[b]++] = rids[i];
+    }
+
+    /* Phase II, Probe: load input run b into the "cache", then append, in the
+     * order of RID run b, the records it names to INTERNAL run b. */
+    for (int64_t b = 0; b < n_runs; ++b) {
+        int64_t first = b * run_len;
+        int64_t len = n_src - first < run_len ? n_src - first : run_len;
+        memcpy(cache, src + first * (int64_t)rec_bytes, (size_t)(len * rec_bytes));
+        for (int64_t k = run_off[b]; k < run_off[b + 1]; ++k) {
+            int64_t local = rid_run[k] - first;
+            memcpy(record_run + k * (int64_t)rec_bytes, cache + local * (int64_t)rec_bytes,
+                   (size_t)rec_bytes);
+        }
+    }
+
+    /* Phase III, Gather: walk RID again; for rid r take the next unread record
+     * of INTERNAL run floor(r / L) and append it to the output. */
+    for (int64_t b = 0; b < n_runs; ++b)
+        cursor[b] = run_off[b];
+    for (int64_t i = 0; i < n_rids; ++i) {
+        int64_t b = rids[i] / run_len;
+        memcpy(dst + i * (int64_t)rec_bytes, record_run + cursor[b] * (int64_t)rec_bytes,
+               (size_t)rec_bytes);
+        cursor[b]++;
+    }
+    free(count); free(cursor); free(cache);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Three-phase key-pointer sort of Section 3: (1) extract key-pointer pairs,   */
+/* (2) sort the pairs, (3) copy the records in the sorted order.               */
+/* ------------------------------------------------------------------------- */
+#define ORACLE_MAX_KEY 64
+typedef struct {
+    uint8_t key[ORACLE_MAX_KEY];
+    int64_t index;
+} key_pointer;
+
+static int32_t g_key_bytes;
+
+static int compare_key_pointer(const void *pa, const void *pb)
+{
+    const key_pointer *a = (const key_pointer *)pa;
+    const key_pointer *b = (const key_pointer *)pb;
+    int c = memcmp(a->key, b->key, (size_t)g_key_bytes);
+    if (c != 0)
+        return c;
+#ifdef ORACLE_MUTANT_TIES_DESCENDING
+    return (a->index < b->index) ? 1 : (a->index > b->index ? -1 : 0);
+#else
+    return (a->index < b->index) ? -1 : (a->index > b->index ? 1 : 0);
+#endif
+}
+
+int oracle_sort_records(const uint8_t *src, int64_t n, int32_t rec_bytes,
+                        int32_t key_offset, int32_t key_bytes,
+                        uint8_t *dst, int64_t *perm)
+{
+    if (n < 0 || rec_bytes <= 0 || key_offset < 0 || key_bytes <= 0 ||
+        key_bytes > ORACLE_MAX_KEY || key_offset + key_bytes > rec_bytes)
+        return ORACLE_EINVAL;
+    if (n == 0)
+        return ORACLE_OK;
+    key_pointer *pairs = malloc((size_t)n * sizeof(key_pointer));
+    if (!pairs)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n; ++i) {
+        memcpy(pairs[i].key, src + i * (int64_t)rec_bytes + key_offset, (size_t)key_bytes);
+        pairs[i].index = i;
+    }
+    g_key_bytes = key_bytes;
+    qsort(pairs, (size_t)n, sizeof(key_pointer), compare_key_pointer);
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t r = pairs[j].index;
+        memcpy(dst + j * (int64_t)rec_bytes, src + r * (int64_t)rec_bytes, (size_t)rec_bytes);
+        if (perm)
+            perm[j] = r;
+    }
+    free(pairs);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Foreign-key joins of Section 4.2.1.  The fact relation references the       */
+/* dimension relation; the little-endian uint32 at fk_offset of a fact row is  */
+/* the dimension row id.                                                       */
+/* ------------------------------------------------------------------------- */
+static uint32_t read_le_u32(const uint8_t *p)
+{
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+static void emit_joined_row(uint8_t *out_row, const uint8_t *fact_row, int32_t fact_bytes,
+                            const uint8_t *dim_row, int32_t dim_bytes)
+{
+    memcpy(out_row, fact_row, (size_t)fact_bytes);
+    memcpy(out_row + fact_bytes, dim_row, (size_t)dim_bytes);
+}
+
+static int check_join_args(int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
+                           int64_t n_dim, int32_t dim_bytes)
+{
+    if (n_fact < 0 || n_dim < 0 || fact_bytes <= 0 || dim_bytes <= 0 || fk_offset < 0 ||
+        fk_offset + 4 > fact_bytes)
+        return ORACLE_EINVAL;
+    return ORACLE_OK;
+}
+
+/* DPG-Move goal: dimension rows brought into fact (rid_R) order. */
+int oracle_fk_join_fact_order(const uint8_t *fact, int64_t n_fact, int32_t fact_bytes,
+                              int32_t fk_offset, const uint8_t *dim, int64_t n_dim,
+                              int32_t dim_bytes, uint8_t *out)
+{
+    int rc = check_join_args(n_fact, fact_bytes, fk_offset, n_dim, dim_bytes);
+    if (rc)
+        return rc;
+    int64_t out_bytes = (int64_t)fact_bytes + dim_bytes;
+    for (int64_t i = 0; i < n_fact; ++i)
+        if ((int64_t)read_le_u32(fact + i * (int64_t)fact_bytes + fk_offset) >= n_dim)
+            return ORACLE_ERANGE;
+    for (int64_t i = 0; i < n_fact; ++i) {
+        const uint8_t *f = fact + i * (int64_t)fact_bytes;
+        int64_t k = read_le_u32(f + fk_offset);
+        emit_joined_row(out + i * out_bytes, f, fact_bytes, dim + k * (int64_t)dim_bytes, dim_bytes);
+    }
+    return ORACLE_OK;
+}
+
+typedef struct {
+    uint32_t fk;
+    int64_t rid;
+} rid_pair;
+
+static int compare_rid_pair(const void *pa, const void *pb)
+{
+    const rid_pair *a = (const rid_pair *)pa;
+    const rid_pair *b = (const rid_pair *)pb;
+    if (a->fk != b->fk)
+        return a->fk < b->fk ? -1 : 1;
+#ifdef ORACLE_MUTANT_UNSTABLE_JOIN
+    return (a->rid < b->rid) ? 1 : (a->rid > b->rid ? -1 : 0);
+#else
+    return (a->rid < b->rid) ? -1 : (a->rid > b->rid ? 1 : 0);
+#endif
+}
+
+/* DPG-Sort goal: rid pairs sorted by rid_F (the foreign key), fact rows brought
+ * into that order; equal keys keep fact (rid_R) order. */
+int oracle_fk_join_dim_order(const uint8_t *fact, int64_t n_fact, int32_t fact_bytes,
+                             int32_t fk_offset, const uint8_t *dim, int64_t n_dim,
+                             int32_t dim_bytes, uint8_t *out)
+{
+    int rc = check_join_args(n_fact, fact_bytes, fk_offset, n_dim, dim_bytes);
+    if (rc)
+        return rc;
+    if (n_fact == 0)
+        return ORACLE_OK;
+    int64_t out_bytes = (int64_t)fact_bytes + dim_bytes;
+    rid_pair *pairs = malloc((size_t)n_fact * sizeof(rid_pair));
+    if (!pairs)
+        return ORACLE_EINVAL;
+    for (int64_t i = 0; i < n_fact; ++i) {
+        pairs[i].fk = read_le_u32(fact + i * (int64_t)fact_bytes + fk_offset);
+        pairs[i].rid = i;
+        if ((int64_t)pairs[i].fk >= n_dim) {
+            free(pairs);
+            return ORACLE_ERANGE;
+        }
+    }
+    qsort(pairs, (size_t)n_fact, sizeof(rid_pair), compare_rid_pair);
+    for (int64_t j = 0; j < n_fact; ++j) {
+        const uint8_t *f = fact + pairs[j].rid * (int64_t)fact_bytes;
+        emit_joined_row(out + j * out_bytes, f, fact_bytes,
+                        dim + (int64_t)pairs[j].fk * dim_bytes, dim_bytes);
+    }
+    free(pairs);
+    return ORACLE_OK;
+}

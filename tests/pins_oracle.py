@@ -1,0 +1,273 @@
+"""Pins for the CPU oracle: checks against what the paper and plain mathematics
+fix, never against the oracle's own formula.
+
+Each ``pin_*`` function takes a loaded oracle library and raises
+AssertionError on a mismatch, so the same pins also run against deliberately
+broken builds of the oracle (see test_oracle_mutants.py).
+"""
+from __future__ import annotations
+
+import itertools
+import os
+
+import numpy as np
+
+import oracle
+from paper_cs_0308004_amd import synth
+
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def distinct_records(n: int, rec_bytes: int, seed: int = 7) -> np.ndarray:
+    """n records whose contents are pairwise distinct in every 4-byte word.
+
+    Word w of record r holds the little-endian uint32 r * 4099 + w * 65537 + seed,
+    so a copied record identifies its source even if only part was copied."""
+    r = np.arange(n, dtype=np.uint64)[:, None]
+    w = np.arange(rec_bytes // 4, dtype=np.uint64)[None, :]
+    words = ((r * np.uint64(4099) + w * np.uint64(65537) + np.uint64(seed)) & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    return words.view(np.uint8).reshape(n, rec_bytes)
+
+
+def identify(dst: np.ndarray, src: np.ndarray) -> np.ndarray:
+    """For each row of dst, the index of the equal row of src (-1 if none)."""
+    table = {src[r].tobytes(): r for r in range(src.shape[0])}
+    return np.array([table.get(dst[i].tobytes(), -1) for i in range(dst.shape[0])], dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------
+# retrieval (problem statement of Section 2)
+# ---------------------------------------------------------------------------
+def pin_retrieve_brute_force(lib):
+    """Every rid sequence for N <= 4, M <= 4: output record i is exactly source record rids[i]."""
+    for rec_bytes in (4, 8, 12, 100):
+        for n in range(1, 5):
+            src = distinct_records(n, rec_bytes)
+            for m in range(0, 5):
+                for seq in itertools.product(range(n), repeat=m):
+                    rids = np.array(seq, dtype=np.int32)
+                    dst = oracle.retrieve(src, rids, lib=lib)
+                    assert dst.shape == (m, rec_bytes)
+                    got = identify(dst, src)
+                    assert np.array_equal(got, rids.astype(np.int64)), (rec_bytes, n, seq, got)
+
+
+def pin_retrieve_closed_forms(lib):
+    """Identity, reversal, an affine permutation and a blocked permutation."""
+    for rec_bytes in (8, 100, 256):
+        n = 1 << 10
+        src = synth.record_bytes(n, rec_bytes, seed=11)
+        ident = np.arange(n, dtype=np.int32)
+        assert np.array_equal(oracle.retrieve(src, ident, lib=lib), src)
+        assert np.array_equal(oracle.retrieve(src, ident[::-1].copy(), lib=lib), src[::-1])
+        a, c = 389, 77  # i -> (a*i + c) mod 2^10 is a bijection because a is odd
+        aff = ((a * ident.astype(np.int64) + c) % n).astype(np.int32)
+        dst = oracle.retrieve(src, aff, lib=lib)
+        for i in (0, 1, 2, 500, n - 1):
+            assert np.array_equal(dst[i], src[(a * i + c) % n])
+        blocked = synth.rids_blocked(n, rec_bytes, seed=3)
+        run = 4096 // rec_bytes
+        dst = oracle.retrieve(src, blocked, lib=lib)
+        pieces, pos = [], 0
+        while pos < n:  # each run is a contiguous ascending slice of the source
+            start = int(blocked[pos])
+            length = min(run - start % run, n - start)
+            pieces.append(src[start:start + length])
+            pos += length
+        assert np.array_equal(dst, np.concatenate(pieces))
+
+
+def pin_retrieve_multiset(lib):
+    """A permutation moves every record exactly once; with replacement the
+    number of copies of each record equals the number of times its rid occurs."""
+    n, rec_bytes = 3000, 12
+    src = distinct_records(n, rec_bytes)
+    perm = synth.rids_permutation(n, seed=5)
+    got = identify(oracle.retrieve(src, perm, lib=lib), src)
+    assert np.array_equal(np.sort(got), np.arange(n))
+    rids = synth.rids_uniform(n, 2 * n, seed=9)
+    got = identify(oracle.retrieve(src, rids, lib=lib), src)
+    assert np.array_equal(np.bincount(got, minlength=n), np.bincount(rids, minlength=n))
+
+
+def pin_retrieve_errors(lib):
+    src = distinct_records(4, 8)
+    for bad in (4, -1, 1 << 30):
+        try:
+            oracle.retrieve(src, np.array([0, bad], dtype=np.int32), lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == oracle.ERANGE
+        else:
+            raise AssertionError(f"rid {bad} accepted")
+    assert oracle.retrieve(src, np.zeros(0, np.int32), lib=lib).shape == (0, 8)
+
+
+# ---------------------------------------------------------------------------
+# Figure 1 / Section 2.2
+# ---------------------------------------------------------------------------
+def load_fig2():
+    keys, rids, facts = [], [], {}
+    with open(os.path.join(GOLDEN_DIR, "fig2_example.txt")) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            parts = line.split()
+            if len(parts) == 2 and len(parts[0]) == 1:
+                keys.append(parts[0])
+                rids.append(int(parts[1]))
+            else:
+                facts[parts[0]] = parts[1:]
+    return keys, rids, facts
+
+
+def pin_fig2_example(lib):
+    keys, rids, facts = load_fig2()
+    n = len(keys)
+    run_len = int(facts["run_len"][0])
+    # record r carries the key whose rid is r, as one byte, padded to 4 bytes
+    src = np.zeros((n, 4), dtype=np.uint8)
+    for k, r in zip(keys, rids):
+        src[r, 0] = ord(k)
+    input_run0 = [chr(src[r, 0]) for r in range(run_len)]
+    assert input_run0 == facts["input_run0_keys"]
+    rid_arr = np.array(rids, dtype=np.int32)
+    rid_run, run_off, record_run, dst = oracle.dpg_phases(src, rid_arr, run_len, lib=lib)
+    assert [r // run_len for r in rids[:4]] == [int(x) for x in facts["first_four_runs"]]
+    assert list(rid_run[run_off[0]:run_off[1]]) == [int(x) for x in facts["rid_run0"]]
+    internal0 = [chr(record_run[k, 0]) for k in range(run_off[0], run_off[1])]
+    assert internal0 == facts["internal_run0_keys"]
+    out_keys = [chr(dst[i, 0]) for i in range(n)]
+    assert out_keys == sorted(keys)  # the output is the records in key order
+    assert np.array_equal(dst, oracle.retrieve(src, rid_arr, lib=lib))
+
+
+def pin_phase_invariants(lib):
+    """Section 2.1: RID run b of a permutation is a permutation of [bL, (b+1)L);
+    INTERNAL run b holds the records of input run b; runs keep RID order; the
+    gathered output equals the definition."""
+    rec_bytes = 8
+    for n, run_len in ((1000, 64), (1 << 12, 256), (777, 1000)):
+        src = distinct_records(n, rec_bytes)
+        rids = synth.rids_permutation(n, seed=n)
+        rid_run, run_off, record_run, dst = oracle.dpg_phases(src, rids, run_len, lib=lib)
+        n_runs = -(-n // run_len)
+        assert run_off[0] == 0 and run_off[-1] == n and len(run_off) == n_runs + 1
+        position = np.empty(n, dtype=np.int64)
+        position[rids] = np.arange(n)
+        for b in range(n_runs):
+            run = rid_run[run_off[b]:run_off[b + 1]]
+            lo, hi = b * run_len, min(n, (b + 1) * run_len)
+            assert np.array_equal(np.sort(run), np.arange(lo, hi))
+            assert np.all(np.diff(position[run]) > 0)  # stable: RID order kept
+            got = identify(record_run[run_off[b]:run_off[b + 1]], src)
+            assert np.array_equal(got, run)
+        assert np.array_equal(identify(dst, src), rids.astype(np.int64))
+    # duplicates (Section 2's non-permutation case): runs are sized by counts
+    n, run_len = 500, 32
+    src = distinct_records(n, rec_bytes)
+    rids = synth.rids_uniform(n, 3 * n, seed=1)
+    rid_run, run_off, record_run, dst = oracle.dpg_phases(src, rids, run_len, lib=lib)
+    counts = np.bincount(rids // run_len, minlength=-(-n // run_len))
+    assert np.array_equal(np.diff(run_off), counts)
+    assert np.array_equal(identify(dst, src), rids.astype(np.int64))
+
+
+# ---------------------------------------------------------------------------
+# Section 3: key-pointer sort
+# ---------------------------------------------------------------------------
+def _check_sorted(src, dst, perm, key_offset, key_bytes):
+    n = src.shape[0]
+    assert np.array_equal(np.sort(perm), np.arange(n)), "perm is not a permutation"
+    assert np.array_equal(dst, src[perm])
+    keys = dst[:, key_offset:key_offset + key_bytes]
+    for j in range(1, n):
+        a, b = keys[j - 1].tobytes(), keys[j].tobytes()
+        assert a <= b, f"keys out of order at {j}"
+        if a == b:
+            assert perm[j - 1] < perm[j], f"equal keys not in index order at {j}"
+
+
+def pin_sort_random(lib):
+    for n, rec_bytes in ((1000, 100), (513, 12), (1, 16)):
+        src = synth.record_bytes(n, rec_bytes, seed=n + rec_bytes)
+        dst, perm = oracle.sort_records(src, 0, 10, lib=lib)
+        _check_sorted(src, dst, perm, 0, 10)
+        # numpy's stable lexsort on the key columns gives the same unique order
+        order = np.lexsort(tuple(src[:, j] for j in range(9, -1, -1)))
+        assert np.array_equal(perm, order)
+
+
+def pin_sort_ties(lib):
+    rng = np.random.default_rng(0)
+    n, rec_bytes = 600, 16
+    src = rng.integers(0, 256, size=(n, rec_bytes), dtype=np.uint8)
+    src[:, 0:8] = rng.integers(0, 3, size=(n, 1), dtype=np.uint8)  # 3 distinct 8-byte prefixes
+    src[:, 8:10] = rng.integers(0, 2, size=(n, 2), dtype=np.uint8)  # bytes 8, 9 decide within
+    dst, perm = oracle.sort_records(src, 0, 10, lib=lib)
+    _check_sorted(src, dst, perm, 0, 10)
+    same = np.zeros((50, rec_bytes), dtype=np.uint8)
+    same[:, 10:] = np.arange(50, dtype=np.uint8)[:, None]
+    dst, perm = oracle.sort_records(same, 0, 10, lib=lib)
+    assert np.array_equal(perm, np.arange(50))
+    desc = np.zeros((40, 12), dtype=np.uint8)
+    desc[:, 9] = np.arange(40, 0, -1, dtype=np.uint8)  # strictly decreasing keys
+    dst, perm = oracle.sort_records(desc, 0, 10, lib=lib)
+    assert np.array_equal(perm, np.arange(39, -1, -1))
+    # key at a non-zero offset
+    dst, perm = oracle.sort_records(src, 6, 4, lib=lib)
+    _check_sorted(src, dst, perm, 6, 4)
+
+
+# ---------------------------------------------------------------------------
+# Section 4.2.1: foreign-key joins
+# ---------------------------------------------------------------------------
+def _join_inputs(n_fact, n_dim, s, seed):
+    fact = synth.fact_table(n_fact, n_dim, s, seed)
+    dim = synth.dim_table(n_dim, seed)
+    fk = fact[:, 0:4].copy().view(np.uint32).reshape(-1).astype(np.int64)
+    return fact, dim, fk
+
+
+def pin_join_fact_order(lib):
+    for n_fact, n_dim, s in ((5000, 300, 0.0), (4000, 1 << 10, 1.2), (1, 1, 0.0)):
+        fact, dim, fk = _join_inputs(n_fact, n_dim, s, seed=n_fact)
+        out = oracle.fk_join_fact_order(fact, dim, 0, lib=lib)
+        assert out.shape == (n_fact, 80)
+        assert np.array_equal(out[:, :16], fact)
+        assert np.array_equal(out[:, 16:20], out[:, 0:4])  # dimension id == foreign key
+        assert np.array_equal(out[:, 16:], dim[fk])
+
+
+def pin_join_dim_order(lib):
+    for n_fact, n_dim, s in ((5000, 300, 0.8), (3000, 64, 1.2), (2, 5, 0.0)):
+        fact, dim, fk = _join_inputs(n_fact, n_dim, s, seed=n_fact + 1)
+        out = oracle.fk_join_dim_order(fact, dim, 0, lib=lib)
+        ofk = out[:, 0:4].copy().view(np.uint32).reshape(-1)
+        assert np.all(np.diff(ofk.astype(np.int64)) >= 0)
+        assert np.array_equal(np.bincount(ofk, minlength=n_dim), np.bincount(fk, minlength=n_dim))
+        assert np.array_equal(out[:, 16:20], out[:, 0:4])
+        # fact rows carry distinct payloads; recover each row's fact index
+        rid_r = identify(out[:, :16], fact)
+        assert np.array_equal(rid_r, np.argsort(fk, kind="stable"))
+        assert np.array_equal(out[:, 16:], dim[ofk])
+
+
+def pin_join_errors(lib):
+    fact, dim, fk = _join_inputs(100, 50, 0.0, seed=3)
+    fact = fact.copy()
+    fact[17, 0:4] = np.array([50], dtype=np.uint32).view(np.uint8)
+    for fn in (oracle.fk_join_fact_order, oracle.fk_join_dim_order):
+        try:
+            fn(fact, dim, 0, lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == oracle.ERANGE
+        else:
+            raise AssertionError("foreign key out of range accepted")
+
+
+ALL_PINS = [
+    pin_retrieve_brute_force, pin_retrieve_closed_forms, pin_retrieve_multiset, pin_retrieve_errors,
+    pin_fig2_example, pin_phase_invariants, pin_sort_random, pin_sort_ties,
+    pin_join_fact_order, pin_join_dim_order, pin_join_errors,
+]
