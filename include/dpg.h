@@ -1,0 +1,146 @@
+/*
+ * dpg.h -- C ABI of libdpg, MI355X (gfx950) distribute-probe-gather record
+ * retrieval and the operators built on it.
+ *
+ * Method: Cooperman, Ma and Nguyen, "DPG: A Cache-Efficient Accelerator for
+ * Sorting and for Join Operators" (arXiv cs/0308004).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.   Every data pointer is a DEVICE pointer owned by the caller.  The
+ *           library never allocates device memory: scratch space comes from
+ *           the caller as `workspace`, sized by the matching *_workspace_bytes
+ *           query, 256-byte aligned.  Inputs are never written.
+ * Streams.  Work is enqueued on the caller's `stream` and is asynchronous
+ *           unless a documented check (check_rids / check_fk) needs the host
+ *           to read a device flag, in which case the call synchronizes the
+ *           stream once.
+ * Records.  A record is rec_bytes contiguous bytes, rec_bytes a multiple of 4
+ *           in [4, 4096]; record r starts at byte r * rec_bytes.  Record
+ *           buffers must be 4-byte aligned (16-byte alignment enables wider
+ *           loads).  rids are 0-based int32 in [0, n_src).
+ * Errors.   Arguments are validated on the host before anything is enqueued;
+ *           on an error the call enqueues nothing and outputs are untouched.
+ *           A failing HIP call returns DPG_ERR_HIP (outputs unspecified).
+ * Results.  Outputs are bit-exact and deterministic: identical across runs,
+ *           algorithms, plans, tuning choices and batch membership.
+ * Threads.  A dpg_ctx may be used from one host thread at a time.
+ */
+#ifndef DPG_H_
+#define DPG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DPG_OK = 0,
+    DPG_ERR_INVALID_ARG = 1,         /* bad pointer, size, alignment, overlap or enum */
+    DPG_ERR_RID_OUT_OF_RANGE = 2,    /* a rid outside [0, n_src) (only detected when asked) */
+    DPG_ERR_FK_OUT_OF_RANGE = 3,     /* a foreign key outside [0, n_dim) (only when asked) */
+    DPG_ERR_WORKSPACE_TOO_SMALL = 4, /* workspace_bytes below the *_workspace_bytes query */
+    DPG_ERR_UNSUPPORTED = 5,         /* valid request this build cannot serve */
+    DPG_ERR_HIP = 6,                 /* a HIP runtime call failed */
+    DPG_ERR_BUSY = 7                 /* serving: no capacity for the request right now */
+} dpg_status;
+
+typedef enum {
+    DPG_ALGO_AUTO = 0,   /* planner / autotuner picks the faster of the two */
+    DPG_ALGO_DIRECT = 1, /* direct retrieval: read src[rid] in rid-list order (Section 1) */
+    DPG_ALGO_DPG = 2     /* distribute-probe-gather (Section 2.1, Figure 1) */
+} dpg_algo;
+
+typedef enum {
+    DPG_PROBE_AUTO = 0,
+    DPG_PROBE_CACHED = 1, /* probe reads each source run through L2 / Infinity Cache */
+    DPG_PROBE_LDS = 2     /* probe stages each source run in LDS with coalesced loads */
+} dpg_probe;
+
+/* Tunables, settable per context.  0 always means "automatic". */
+typedef enum {
+    DPG_OPT_LOG2_RUN = 1,   /* L = 2^v source records per run (Section 2.1 "Constraints") */
+    DPG_OPT_PROBE = 2,      /* a dpg_probe value */
+    DPG_OPT_DIST_TILE = 3,  /* rids per distribute tile (multiple of 64) */
+    DPG_OPT_XCD_REMAP = 4,  /* 1 (default): tiles of one XCD are contiguous; 2: off */
+    DPG_OPT_USE_TUNED = 5   /* 1 (default): consult the autotune table; 2: ignore it */
+} dpg_option;
+
+typedef struct dpg_ctx dpg_ctx;
+
+/* Create a context bound to HIP device `device` (reads its properties once).
+ * Allocates host memory only.  Returns DPG_ERR_HIP if the device is absent. */
+dpg_status dpg_create(int device, dpg_ctx **out);
+void dpg_destroy(dpg_ctx *ctx);
+const char *dpg_status_string(dpg_status status);
+
+dpg_status dpg_set_option(dpg_ctx *ctx, dpg_option option, int64_t value);
+dpg_status dpg_get_option(const dpg_ctx *ctx, dpg_option option, int64_t *value);
+
+/* ------------------------------------------------------------------------- */
+/* Record retrieval (Section 2): dst[i] = src[rids[i]] for i in [0, n_rids).  */
+/* ------------------------------------------------------------------------- */
+
+/* The plan the library would run for a retrieval of this shape.  Host only;
+ * `ctx` may be NULL (then MI355X defaults are assumed: 256 CUs, 160 KiB LDS). */
+typedef struct {
+    int32_t algo;          /* DPG_ALGO_DIRECT or DPG_ALGO_DPG */
+    int32_t probe;         /* DPG_PROBE_CACHED or DPG_PROBE_LDS (DPG only) */
+    int32_t log2_run;      /* L = 2^log2_run source records per run */
+    int32_t dist_tile;     /* rids per distribute tile */
+    int64_t n_runs;        /* B = ceil(n_src / L), the paper's NUM_RUNS */
+    int64_t n_tiles;       /* ceil(n_rids / dist_tile) */
+    size_t workspace_bytes;
+    /* After a DPG retrieval the workspace holds the phase products at these
+     * byte offsets (0 when algo is direct), for inspection or pipelining:
+     *   run_off  int32[n_runs + 1]  start of RID run b in rid_run (Phase I)
+     *   rid_run  int32[n_rids]      the RID runs, one after another, each in
+     *                               rid-list order (Phase I)
+     *   internal n_rids records     the INTERNAL runs (Phase II)          */
+    size_t ws_run_off;
+    size_t ws_rid_run;
+    size_t ws_internal;
+} dpg_plan;
+
+dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
+                             int64_t n_rids, dpg_algo algo, dpg_plan *out);
+
+/* Bytes of workspace dpg_retrieve needs for this shape, algorithm and the
+ * context's current options (256 for direct retrieval: the flag word used by
+ * check_rids).  Returns 0 for arguments dpg_retrieve would reject. */
+size_t dpg_retrieve_workspace_bytes(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
+                                    int64_t n_rids, dpg_algo algo);
+
+/* Copy records of `src` (n_src records) into `dst` (n_rids records) in the
+ * order of `rids` (Section 2; Figure 1 gives the DPG algorithm, Section 2.3
+ * its skewed case; duplicated rids are allowed).
+ *   check_rids = 1: validate every rid on the device first (one extra read of
+ *     rids plus one stream synchronization); an out-of-range rid returns
+ *     DPG_ERR_RID_OUT_OF_RANGE with dst untouched.
+ *   check_rids = 0: an out-of-range rid is undefined behaviour.
+ * src and dst must not overlap.  n_rids == 0 returns DPG_OK, enqueuing nothing. */
+dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t rec_bytes,
+                        const int32_t *rids, int64_t n_rids, void *dst,
+                        void *workspace, size_t workspace_bytes, dpg_algo algo,
+                        int check_rids, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Per-kernel timing.  When enabled, every kernel the context launches is     */
+/* bracketed by HIP events on its own stream, and its algorithmic bytes (what */
+/* the algorithm must read and write, excluding cache effects) are recorded.  */
+/* ------------------------------------------------------------------------- */
+dpg_status dpg_profile_enable(dpg_ctx *ctx, int on);
+dpg_status dpg_profile_reset(dpg_ctx *ctx);
+/* Synchronizes the recorded events and folds them into per-kernel totals.
+ * *n_kernels receives the number of distinct kernels seen. */
+dpg_status dpg_profile_collect(dpg_ctx *ctx, int32_t *n_kernels);
+dpg_status dpg_profile_entry(const dpg_ctx *ctx, int32_t index, const char **name,
+                             int64_t *launches, double *total_ms, double *total_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPG_H_ */

@@ -1,0 +1,188 @@
+// Record copy by index: dst[k] = src[idx[k]].
+//
+// One kernel serves three roles:
+//   * direct retrieval (idx = the rid list; Section 1's "standard approach"),
+//   * the DPG probe when source runs are read through the caches
+//     (idx = the RID runs, dst = INTERNAL; Section 2.1, Phase II),
+//   * the DPG gather (idx = slot of each rid in INTERNAL, src = INTERNAL;
+//     Section 2.1, Phase III).
+//
+// Layout: a workgroup owns a tile of consecutive outputs.  The tile's indices
+// are staged in LDS, then the tile's (record, element) pairs are flattened over
+// the 256 lanes, so each wave's loads cover whole records and its stores are
+// one contiguous span of dst.  Every thread issues all of its loads before its
+// first store, keeping PER independent loads in flight.
+#include "dev_common.h"
+#include "dpg_internal.h"
+
+namespace dpg {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename E, int WE>
+struct GatherShape {
+    static constexpr int kEDw = sizeof(E) / 4;
+    static constexpr int kInRange = (WE > 0 && WE * kEDw >= 16 && WE * kEDw <= 64);
+    static constexpr int PER = kInRange ? WE : 32 / kEDw;        // elements per thread
+    static constexpr int TILE = WE > 0 ? (256 * PER) / WE : 0;   // records per workgroup
+};
+
+template <typename E, int WE>
+__device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int32_t *__restrict__ idx,
+                                            E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,
+                                            uint32_t magic, int tile_rt, int remap) {
+    extern __shared__ int32_t s_idx[];
+    using S = GatherShape<E, WE>;
+    constexpr int PER = S::PER;
+    const int we = WE > 0 ? WE : we_rt;
+    const int tile = WE > 0 ? S::TILE : tile_rt;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x, remap);
+    const int64_t base = t * tile;
+    const int cnt = (int)min((int64_t)tile, n - base);
+    // An index outside [0, limit) reads record 0 instead (undefined result, no
+    // out-of-bounds access).
+    for (int j = threadIdx.x; j < cnt; j += 256) {
+        const int32_t r = idx[base + j];
+        s_idx[j] = (r >= 0 && (int64_t)r < limit) ? r : 0;
+    }
+    __syncthreads();
+    const int total = cnt * we;
+    E v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        if (e < total) {
+            int j;
+            if constexpr (WE > 0) j = e / WE;
+            else j = (int)__umulhi((uint32_t)e, magic);
+            const int w = e - j * we;
+            v[k] = src[(int64_t)s_idx[j] * we + w];
+        }
+    }
+    E *out = dst + base * we;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        if (e < total) out[e] = v[k];
+    }
+}
+
+// Three kernel symbols for the three roles, so profiles tell them apart.
+#define DPG_GATHER_KERNEL(NAME)                                                                              \
+    template <typename E, int WE>                                                                            \
+    __global__ __launch_bounds__(256) void NAME(const E *__restrict__ src, const int32_t *__restrict__ idx, \
+                                                E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,    \
+                                                uint32_t magic, int tile_rt, int remap) {                    \
+        gather_tile<E, WE>(src, idx, dst, n, limit, we_rt, magic, tile_rt, remap);                          \
+    }
+DPG_GATHER_KERNEL(k_direct_gather)
+DPG_GATHER_KERNEL(k_probe_cached)
+DPG_GATHER_KERNEL(k_gather_phase)
+#undef DPG_GATHER_KERNEL
+
+template <typename E, int WE>
+static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx, void *dst, int64_t n,
+                                  int64_t limit, int we, int remap, hipStream_t stream) {
+    using S = GatherShape<E, WE>;
+    int tile;
+    uint32_t magic = 0;
+    if constexpr (WE > 0) {
+        tile = S::TILE;
+    } else {
+        tile = (256 * S::PER) / we;
+        if (tile < 1 || we < 2) return DPG_ERR_UNSUPPORTED;
+        magic = (uint32_t)((0x100000000ull + (uint64_t)we - 1) / (uint64_t)we);
+    }
+    const int64_t grid = (n + tile - 1) / tile;
+    if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
+    const size_t lds = (size_t)tile * sizeof(int32_t);
+    if (role == K_PROBE_CACHED)
+        hipLaunchKernelGGL((k_probe_cached<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, idx,
+                           (E *)dst, n, limit, we, magic, tile, remap);
+    else if (role == K_GATHER_PHASE)
+        hipLaunchKernelGGL((k_gather_phase<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, idx,
+                           (E *)dst, n, limit, we, magic, tile, remap);
+    else
+        hipLaunchKernelGGL((k_direct_gather<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src,
+                           idx, (E *)dst, n, limit, we, magic, tile, remap);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t limit, const int32_t *idx,
+                         void *dst, int64_t n, int rec_bytes, double alg_bytes, hipStream_t stream) {
+    if (n <= 0) return DPG_OK;
+    ProfScope prof(ctx, kernel_id, alg_bytes, stream);
+    const int remap = xcd_remap_flag(ctx);
+    const uintptr_t al = (uintptr_t)src | (uintptr_t)dst;
+    if (rec_bytes % 16 == 0 && al % 16 == 0) {
+        const int we = rec_bytes / 16;
+        switch (we) {
+            case 1: return launch_gather_t<u32x4, 1>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            case 2: return launch_gather_t<u32x4, 2>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            case 4: return launch_gather_t<u32x4, 4>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            case 8: return launch_gather_t<u32x4, 8>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            case 16: return launch_gather_t<u32x4, 16>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            default: return launch_gather_t<u32x4, 0>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        }
+    }
+    if (rec_bytes % 8 == 0 && al % 8 == 0) {
+        const int we = rec_bytes / 8;
+        if (we == 1) return launch_gather_t<u32x2, 1>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        return launch_gather_t<u32x2, 0>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+    }
+    const int we = rec_bytes / 4;
+    switch (we) {
+        case 1: return launch_gather_t<uint32_t, 1>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        case 3: return launch_gather_t<uint32_t, 3>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        case 25: return launch_gather_t<uint32_t, 25>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        default: return launch_gather_t<uint32_t, 0>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = value;
+}
+
+dpg_status launch_fill_i32(dpg_ctx *ctx, int32_t *p, int64_t n, int32_t value, hipStream_t stream) {
+    if (n <= 0) return DPG_OK;
+    ProfScope prof(ctx, K_FILL, 4.0 * n, stream);
+    const int64_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)grid), dim3(256), 0, stream, p, n, value);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+// Every id in [0, limit)?  Sets *flag to 1 otherwise (vector atomic).
+__global__ __launch_bounds__(256) void k_check_ids(const int32_t *__restrict__ ids, int64_t n, int64_t limit,
+                                                   int32_t *flag) {
+    int bad = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int32_t v = ids[i];
+        bad |= (v < 0) | ((int64_t)v >= limit);
+    }
+    if (__any(bad) && __lane_id() == 0) atomicOr(flag, 1);
+}
+
+dpg_status check_ids(dpg_ctx *ctx, const int32_t *ids, int64_t n, int64_t limit, int32_t *flag_dev,
+                     hipStream_t stream, bool *bad) {
+    *bad = false;
+    if (n <= 0) return DPG_OK;
+    dpg_status st = launch_fill_i32(ctx, flag_dev, 1, 0, stream);
+    if (st != DPG_OK) return st;
+    {
+        ProfScope prof(ctx, K_CHECK_IDS, 4.0 * n, stream);
+        int64_t grid = (n + 255) / 256;
+        if (grid > (int64_t)ctx->n_cu * 16) grid = (int64_t)ctx->n_cu * 16;
+        hipLaunchKernelGGL(k_check_ids, dim3((unsigned)grid), dim3(256), 0, stream, ids, n, limit, flag_dev);
+        DPG_HIP(hipGetLastError());
+    }
+    DPG_HIP(hipMemcpyAsync(ctx->host_flag, flag_dev, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    DPG_HIP(hipStreamSynchronize(stream));
+    *bad = (*ctx->host_flag != 0);
+    return DPG_OK;
+}
+
+}  // namespace dpg

@@ -1,0 +1,171 @@
+// Internal declarations of libdpg: context, profiling, kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/dpg.h"
+
+#define DPG_HIP(expr)                                  \
+    do {                                               \
+        hipError_t dpg_e_ = (expr);                    \
+        if (dpg_e_ != hipSuccess) return DPG_ERR_HIP;  \
+    } while (0)
+
+namespace dpg {
+
+constexpr int kMaxRecBytes = 4096;
+constexpr size_t kAlign = 256;
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+inline int ilog2_ceil(int64_t x) {
+    int k = 0;
+    while ((int64_t(1) << k) < x) ++k;
+    return k;
+}
+inline int bit_length(uint64_t x) {
+    int k = 0;
+    while (x) { ++k; x >>= 1; }
+    return k;
+}
+
+// Kernels the library launches; names appear in the profile and must match
+// the HIP kernel symbol stems so rocprof summaries can be matched.
+enum KernelId {
+    K_DIRECT_GATHER = 0, // direct retrieval (Section 1's standard approach)
+    K_DIST_HIST,         // Phase I count pass
+    K_SCAN_CHUNKS,       // Phase I bucket boundaries (column chunk sums)
+    K_SCAN_COLS,
+    K_SCAN_BASE,
+    K_SCAN_APPLY,
+    K_DIST_SCATTER,      // Phase I append pass
+    K_PROBE_CACHED,      // Phase II, source run read through the caches
+    K_PROBE_LDS,         // Phase II, source run staged in LDS
+    K_GATHER_PHASE,      // Phase III
+    K_CHECK_IDS,
+    K_FILL,
+    K_SORT_EXTRACT,
+    K_RADIX_HIST,
+    K_RADIX_SCATTER,
+    K_TIE_MARK,
+    K_TIE_FIX,
+    K_JOIN_EXTRACT,
+    K_JOIN_ASSEMBLE,
+    K_JOIN_STREAM,
+    K_BATCH,
+    K_COUNT
+};
+const char *kernel_name(int id);
+
+struct ProfRecord {
+    int kernel;
+    double bytes;
+    hipEvent_t start, stop;
+};
+
+struct ProfTotal {
+    int64_t launches = 0;
+    double ms = 0, bytes = 0;
+};
+
+struct TuneKey {
+    int32_t rec_bytes;
+    int32_t log2_n_src;
+    int32_t log2_n_rids;
+    bool operator<(const TuneKey &o) const {
+        if (rec_bytes != o.rec_bytes) return rec_bytes < o.rec_bytes;
+        if (log2_n_src != o.log2_n_src) return log2_n_src < o.log2_n_src;
+        return log2_n_rids < o.log2_n_rids;
+    }
+};
+
+struct TuneEntry {
+    int32_t algo, probe, log2_run, dist_tile;
+    double ms;
+};
+
+}  // namespace dpg
+
+struct dpg_ctx {
+    int device = 0;
+    int n_cu = 256;
+    size_t lds_bytes = 160 * 1024;
+    size_t l2_bytes = 4u << 20;
+    // options
+    int64_t opt_log2_run = 0, opt_probe = 0, opt_dist_tile = 0, opt_xcd = 1, opt_use_tuned = 1;
+    // profiling
+    bool profiling = false;
+    std::vector<dpg::ProfRecord> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::map<int, dpg::ProfTotal> totals;
+    std::vector<int> total_order;
+    // autotune table
+    std::map<dpg::TuneKey, dpg::TuneEntry> tuned;
+    // pinned host word used to read device flags
+    int32_t *host_flag = nullptr;
+};
+
+namespace dpg {
+
+// Profiling scope: records events around one launch when profiling is on.
+struct ProfScope {
+    dpg_ctx *ctx;
+    int kernel;
+    double bytes;
+    hipStream_t stream;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    ProfScope(dpg_ctx *c, int k, double b, hipStream_t s);
+    ~ProfScope();
+};
+
+// Retrieval plan (resolved), shared by retrieve, sort, join and batch.
+struct RetrievePlan {
+    int algo = DPG_ALGO_DIRECT;
+    int probe = DPG_PROBE_CACHED;
+    int log2_run = 0;
+    int dist_tile = 0;
+    int64_t n_runs = 0, n_tiles = 0;
+    int64_t n_src = 0, n_rids = 0;
+    int rec_bytes = 0;
+    // workspace layout (byte offsets)
+    size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0, off_items = 0;
+    size_t off_run = 0, off_inv = 0, off_internal = 0, off_flag = 0;
+    int64_t n_chunks = 0;      // column-scan chunks of the count matrix
+    int32_t probe_chunk = 0;   // run entries per LDS-probe work item
+    size_t workspace = 0;
+};
+
+dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool need_ptr);
+bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn);
+dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
+                              int64_t n_rids, int algo, RetrievePlan *plan);
+
+// Enqueue a planned retrieval (arguments already validated).
+dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
+                        void *dst, void *ws, hipStream_t stream);
+// Device check that every id lies in [0, limit); synchronizes; *bad = 1 if not.
+dpg_status check_ids(dpg_ctx *ctx, const int32_t *ids, int64_t n, int64_t limit, int32_t *flag_dev,
+                     hipStream_t stream, bool *bad);
+
+// ---- kernel launchers (copy.hip) ----
+// dst[k] = src[idx[k]] (records of rec_bytes) for k in [0, n).
+// An index outside [0, limit) copies record 0 (never an out-of-bounds access).
+dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t limit, const int32_t *idx,
+                         void *dst, int64_t n, int rec_bytes, double alg_bytes, hipStream_t stream);
+dpg_status launch_fill_i32(dpg_ctx *ctx, int32_t *p, int64_t n, int32_t value, hipStream_t stream);
+
+// ---- distribute (distribute.hip) ----
+dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,
+                             hipStream_t stream);
+// ---- probe (probe.hip) ----
+dpg_status launch_probe_lds(dpg_ctx *ctx, const RetrievePlan &p, const void *src, void *ws,
+                            hipStream_t stream);
+
+int xcd_remap_flag(const dpg_ctx *ctx);
+
+}  // namespace dpg

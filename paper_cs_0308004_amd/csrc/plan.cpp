@@ -1,0 +1,167 @@
+// Retrieval planner: chooses between direct retrieval and DPG and, for DPG,
+// the run length L, the probe flavour and the distribute tile.  Pure host code.
+//
+// The two constraints of Section 2.1 ("Constraints") become:
+//   * Phase II: one source run must fit the store that absorbs the probe's
+//     random reads.  With the LDS probe that store is the workgroup's LDS
+//     (L*R <= 64 KiB); with the cached probe it is the XCD's 4 MiB L2, shared
+//     by the runs its in-flight workgroups touch, so L*R is kept near 1 MiB.
+//   * Phases I and III: one buffer per run must fit the cache.  Here that is
+//     the LDS table of B running positions in the distribute (B <= 8192) and
+//     the B INTERNAL streams the gather reads, which the L2 and Infinity Cache
+//     hold comfortably at B <= 8192.
+// L is a power of two so the run of rid r is r >> log2(L) (Section 2.1).
+#include <cstring>
+
+#include "dpg_internal.h"
+
+namespace dpg {
+
+constexpr int64_t kMaxRuns = 8192;
+constexpr size_t kLdsRegionBytes = 64 * 1024;
+constexpr size_t kCachedRegionBytes = 1 << 20;
+
+dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool need_ptr) {
+    if (n < 0 || n > INT32_MAX) return DPG_ERR_INVALID_ARG;
+    if (rec_bytes < 4 || rec_bytes > kMaxRecBytes || rec_bytes % 4 != 0) return DPG_ERR_INVALID_ARG;
+    if (need_ptr && n > 0 && ptr == nullptr) return DPG_ERR_INVALID_ARG;
+    if (((uintptr_t)ptr) % 4 != 0) return DPG_ERR_INVALID_ARG;
+    return DPG_OK;
+}
+
+bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn) {
+    if (an == 0 || bn == 0) return false;
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + bn && b0 < a0 + an;
+}
+
+static int floor_log2(uint64_t x) {
+    int k = -1;
+    while (x) { ++k; x >>= 1; }
+    return k;
+}
+
+static void layout_workspace(RetrievePlan *p) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    p->off_flag = take(sizeof(int32_t));
+    if (p->algo == DPG_ALGO_DPG) {
+        const int64_t B = p->n_runs, M = p->n_rids;
+        p->off_cnt = take((size_t)p->n_tiles * B * 4);
+        p->off_csum = take((size_t)p->n_chunks * B * 4);
+        p->off_total = take((size_t)B * 4);
+        p->off_bucket = take((size_t)(B + 1) * 4);
+        p->off_items = take((size_t)(B + 1) * 4);
+        p->off_run = take((size_t)M * 4);
+        p->off_inv = take((size_t)M * 4);
+        p->off_internal = take((size_t)M * p->rec_bytes);
+    }
+    p->workspace = off;
+}
+
+static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile) {
+    const int64_t N = p->n_src > 0 ? p->n_src : 1, M = p->n_rids;
+    const int R = p->rec_bytes;
+    const int lg_n = ilog2_ceil(N);
+    const int lg_lds = floor_log2(kLdsRegionBytes / (size_t)R);
+    if (probe == DPG_PROBE_AUTO) probe = DPG_PROBE_CACHED;
+    if (probe == DPG_PROBE_LDS && lg_lds < 0) probe = DPG_PROBE_CACHED;
+    int lg;
+    if (log2_run > 0) {
+        lg = log2_run;
+    } else if (probe == DPG_PROBE_LDS) {
+        lg = lg_lds;
+    } else {
+        lg = floor_log2(kCachedRegionBytes / (size_t)R);
+        if (lg < 0) lg = 0;
+    }
+    if (lg > lg_n) lg = lg_n;
+    // B <= kMaxRuns: lengthen the runs if needed
+    while (((N + ((int64_t)1 << lg) - 1) >> lg) > kMaxRuns) ++lg;
+    if (probe == DPG_PROBE_LDS && lg > lg_lds) probe = DPG_PROBE_CACHED;
+    p->probe = probe;
+    p->log2_run = lg;
+    p->n_runs = (N + ((int64_t)1 << lg) - 1) >> lg;
+    // A tile holds at least 4 rids per run on average, so the count matrix
+    // (tiles x runs) stays below a quarter of the rid list.
+    int64_t T = dist_tile > 0 ? dist_tile : 4 * p->n_runs;
+    if (dist_tile <= 0 && T < 1024) T = 1024;
+    T = (T + 63) / 64 * 64;
+    p->dist_tile = (int)T;
+    p->n_tiles = M > 0 ? (M + T - 1) / T : 0;
+    p->n_chunks = (p->n_tiles + 31) / 32;
+    if (probe == DPG_PROBE_LDS) {
+        int64_t P = (int64_t)1 << lg;
+        if (P < 256) P = 256;
+        if (P > 4096) P = 4096;
+        const int64_t cap = ((int64_t)1 << 20) / (R / 4);
+        if (P > cap) P = cap;
+        p->probe_chunk = (int32_t)P;
+    }
+}
+
+dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo,
+                              RetrievePlan *p) {
+    if (n_src < 0 || n_src > INT32_MAX || n_rids < 0 || n_rids > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
+    if (rec_bytes < 4 || rec_bytes > kMaxRecBytes || rec_bytes % 4 != 0) return DPG_ERR_INVALID_ARG;
+    if (algo < DPG_ALGO_AUTO || algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
+    *p = RetrievePlan();
+    p->n_src = n_src;
+    p->n_rids = n_rids;
+    p->rec_bytes = rec_bytes;
+    int probe = ctx ? (int)ctx->opt_probe : 0;
+    int log2_run = ctx ? (int)ctx->opt_log2_run : 0;
+    int dist_tile = ctx ? (int)ctx->opt_dist_tile : 0;
+    if (algo == DPG_ALGO_AUTO) {
+        algo = rec_bytes <= 8 ? DPG_ALGO_DPG : DPG_ALGO_DIRECT;
+        if (ctx && ctx->opt_use_tuned != 2) {
+            const TuneKey key{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
+            auto it = ctx->tuned.find(key);
+            if (it != ctx->tuned.end()) {
+                algo = it->second.algo;
+                if (!probe) probe = it->second.probe;
+                if (!log2_run) log2_run = it->second.log2_run;
+                if (!dist_tile) dist_tile = it->second.dist_tile;
+            }
+        }
+    }
+    p->algo = algo;
+    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile);
+    layout_workspace(p);
+    return DPG_OK;
+}
+
+}  // namespace dpg
+
+extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids,
+                                        dpg_algo algo, dpg_plan *out) {
+    if (!out) return DPG_ERR_INVALID_ARG;
+    dpg::RetrievePlan p;
+    const dpg_status st = dpg::make_retrieve_plan(ctx, n_src, rec_bytes, n_rids, algo, &p);
+    if (st != DPG_OK) return st;
+    std::memset(out, 0, sizeof(*out));
+    out->algo = p.algo;
+    out->probe = p.algo == DPG_ALGO_DPG ? p.probe : 0;
+    out->log2_run = p.log2_run;
+    out->dist_tile = p.dist_tile;
+    out->n_runs = p.n_runs;
+    out->n_tiles = p.n_tiles;
+    out->workspace_bytes = p.workspace;
+    if (p.algo == DPG_ALGO_DPG && n_rids > 0) {
+        out->ws_run_off = p.off_bucket;
+        out->ws_rid_run = p.off_run;
+        out->ws_internal = p.off_internal;
+    }
+    return DPG_OK;
+}
+
+extern "C" size_t dpg_retrieve_workspace_bytes(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
+                                               int64_t n_rids, dpg_algo algo) {
+    dpg::RetrievePlan p;
+    if (dpg::make_retrieve_plan(ctx, n_src, rec_bytes, n_rids, algo, &p) != DPG_OK) return 0;
+    return p.workspace;
+}

@@ -1,0 +1,186 @@
+"""ctypes binding over libdpg (include/dpg.h).
+
+Argument marshalling only: every step of every operation runs in the HIP
+kernels of libdpg.so.  Device buffers are torch tensors (or raw device
+addresses); the stream is torch's current stream unless one is given.  If the
+library has not been built, :func:`lib` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpg.so")
+
+OK, ERR_INVALID_ARG, ERR_RID_OUT_OF_RANGE, ERR_FK_OUT_OF_RANGE = 0, 1, 2, 3
+ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_BUSY = 4, 5, 6, 7
+
+ALGO_AUTO, ALGO_DIRECT, ALGO_DPG = 0, 1, 2
+PROBE_AUTO, PROBE_CACHED, PROBE_LDS = 0, 1, 2
+OPT_LOG2_RUN, OPT_PROBE, OPT_DIST_TILE, OPT_XCD_REMAP, OPT_USE_TUNED = 1, 2, 3, 4, 5
+
+_VP, _I32, _I64, _SZ, _DBL = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+
+
+class DPGError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        msg = lib().dpg_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})")
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("algo", _I32), ("probe", _I32), ("log2_run", _I32), ("dist_tile", _I32),
+                ("n_runs", _I64), ("n_tiles", _I64), ("workspace_bytes", _SZ),
+                ("ws_run_off", _SZ), ("ws_rid_run", _SZ), ("ws_internal", _SZ)]
+
+
+# name -> (restype, argtypes); mirrors include/dpg.h
+SIGNATURES = {
+    "dpg_create": (_I32, [ctypes.c_int, ctypes.POINTER(_VP)]),
+    "dpg_destroy": (None, [_VP]),
+    "dpg_status_string": (ctypes.c_char_p, [_I32]),
+    "dpg_set_option": (_I32, [_VP, _I32, _I64]),
+    "dpg_get_option": (_I32, [_VP, _I32, ctypes.POINTER(_I64)]),
+    "dpg_plan_retrieve": (_I32, [_VP, _I64, _I32, _I64, _I32, ctypes.POINTER(Plan)]),
+    "dpg_retrieve_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
+    "dpg_retrieve": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
+    "dpg_profile_reset": (_I32, [_VP]),
+    "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
+    "dpg_profile_entry": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_I64),
+                                 ctypes.POINTER(_DBL), ctypes.POINTER(_DBL)]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libdpg.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_cs_0308004_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise DPGError(status, what)
+
+
+def _addr(t) -> int:
+    if t is None:
+        return 0
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _rec_bytes(t) -> int:
+    if t.dim() != 2:
+        raise ValueError("record tensors are (n, rec_bytes) uint8")
+    return t.shape[1] * t.element_size()
+
+
+class Context:
+    """Owns a dpg_ctx bound to one HIP device."""
+
+    def __init__(self, device: int = 0):
+        h = _VP()
+        _check(lib().dpg_create(device, ctypes.byref(h)), "dpg_create")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().dpg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # ---- options -------------------------------------------------------
+    def set_option(self, option: int, value: int):
+        _check(lib().dpg_set_option(self.handle, option, value), "dpg_set_option")
+
+    def get_option(self, option: int) -> int:
+        v = _I64()
+        _check(lib().dpg_get_option(self.handle, option, ctypes.byref(v)), "dpg_get_option")
+        return v.value
+
+    # ---- retrieval -----------------------------------------------------
+    def plan_retrieve(self, n_src: int, rec_bytes: int, n_rids: int, algo: int = ALGO_AUTO) -> Plan:
+        return plan_retrieve(n_src, rec_bytes, n_rids, algo, self)
+
+    def retrieve_workspace_bytes(self, n_src: int, rec_bytes: int, n_rids: int, algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_retrieve_workspace_bytes(self.handle, n_src, rec_bytes, n_rids, algo)
+
+    def retrieve(self, src, rids, dst=None, algo: int = ALGO_AUTO, check_rids: bool = False, workspace=None,
+                 stream=None):
+        """dst[i] = src[rids[i]]; src is an (N, R) uint8 device tensor, rids int32."""
+        import torch
+
+        n_src, rec_bytes = src.shape[0], _rec_bytes(src)
+        n_rids = rids.numel()
+        if dst is None:
+            dst = torch.empty((n_rids, src.shape[1]), dtype=src.dtype, device=src.device)
+        need = self.retrieve_workspace_bytes(n_src, rec_bytes, n_rids, algo)
+        if workspace is None:
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=src.device)
+        st = lib().dpg_retrieve(self.handle, _addr(src), n_src, rec_bytes, _addr(rids), n_rids, _addr(dst),
+                                _addr(workspace), workspace.numel(), algo, int(check_rids), _stream(stream))
+        _check(st, "dpg_retrieve")
+        return dst
+
+    # ---- profiling -----------------------------------------------------
+    def profile_enable(self, on: bool = True):
+        _check(lib().dpg_profile_enable(self.handle, int(on)), "dpg_profile_enable")
+
+    def profile_reset(self):
+        _check(lib().dpg_profile_reset(self.handle), "dpg_profile_reset")
+
+    def profile_collect(self) -> dict:
+        """{kernel name: {"launches", "ms", "bytes"}} accumulated since the last reset."""
+        n = _I32()
+        _check(lib().dpg_profile_collect(self.handle, ctypes.byref(n)), "dpg_profile_collect")
+        out = {}
+        for i in range(n.value):
+            name, launches, ms, by = ctypes.c_char_p(), _I64(), _DBL(), _DBL()
+            _check(lib().dpg_profile_entry(self.handle, i, ctypes.byref(name), ctypes.byref(launches),
+                                           ctypes.byref(ms), ctypes.byref(by)), "dpg_profile_entry")
+            out[name.value.decode()] = {"launches": launches.value, "ms": ms.value, "bytes": by.value}
+        return out
+
+
+def plan_retrieve(n_src: int, rec_bytes: int, n_rids: int, algo: int = ALGO_AUTO, ctx: Context | None = None) -> Plan:
+    p = Plan()
+    _check(lib().dpg_plan_retrieve(ctx.handle if ctx else None, n_src, rec_bytes, n_rids, algo, ctypes.byref(p)),
+           "dpg_plan_retrieve")
+    return p

@@ -1,0 +1,112 @@
+"""The C-ABI library without a GPU: it loads, exports what include/dpg.h
+declares, plans sensibly and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_cs_0308004_amd import dpg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", fn)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names |= set(re.findall(r"\b(dpg_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(dpg.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    # every declared function has a ctypes signature in the binding
+    assert set(declared_functions()) <= set(dpg.SIGNATURES)
+
+
+def test_status_strings():
+    lib = dpg.lib()
+    for code in range(8):
+        assert lib.dpg_status_string(code)
+    assert lib.dpg_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("rec_bytes", [4, 8, 16, 32, 64, 100, 128, 256, 4096])
+def test_plan_constraints(rec_bytes):
+    for n in (1, 1000, 1 << 20, 1 << 26):
+        p = dpg.plan_retrieve(n, rec_bytes, n, dpg.ALGO_DPG)
+        L = 1 << p.log2_run
+        assert p.algo == dpg.ALGO_DPG
+        assert p.n_runs == -(-n // L) and 1 <= p.n_runs <= 8192
+        assert p.dist_tile % 64 == 0 and p.n_tiles == -(-n // p.dist_tile)
+        assert p.n_tiles * p.n_runs <= max(n, 1024 * 8192) // 4 + 8192
+        if p.probe == dpg.PROBE_LDS:
+            assert L * rec_bytes <= 64 * 1024
+        # workspace holds the runs, inv and INTERNAL at least
+        assert p.workspace_bytes >= n * (8 + rec_bytes)
+        assert p.ws_internal + n * rec_bytes <= p.workspace_bytes
+        assert p.ws_rid_run + 4 * n <= p.workspace_bytes
+        d = dpg.plan_retrieve(n, rec_bytes, n, dpg.ALGO_DIRECT)
+        assert d.algo == dpg.ALGO_DIRECT and d.workspace_bytes == 256
+
+
+def test_plan_lds_probe_fits():
+    lib = dpg.lib()
+    # with a NULL context the default options apply: cached probe
+    p = dpg.plan_retrieve(1 << 20, 100, 1 << 20, dpg.ALGO_DPG)
+    assert p.probe == dpg.PROBE_CACHED
+    assert lib.dpg_retrieve_workspace_bytes(None, 100, 6, 10, 0) == 0  # rejected shape
+
+
+# fake, aligned device addresses: validation never dereferences them
+SRC, DST, RIDS, WS = 0x10000000, 0x20000000, 0x30000000, 0x40000000
+
+
+def call(n_src=100, rec=8, rids=RIDS, n=10, dst=DST, ws=WS, ws_bytes=1 << 24, algo=0, check=0, src=SRC, ctx=None):
+    return dpg.lib().dpg_retrieve(ctx, src, n_src, rec, rids, n, dst, ws, ws_bytes, algo, check, None)
+
+
+def test_retrieve_argument_validation():
+    E = dpg
+    assert call() == E.ERR_INVALID_ARG  # valid arguments, but no context
+    assert call(rec=6) == E.ERR_INVALID_ARG
+    assert call(rec=0) == E.ERR_INVALID_ARG
+    assert call(rec=4100) == E.ERR_INVALID_ARG
+    assert call(n_src=-1) == E.ERR_INVALID_ARG
+    assert call(n=-1) == E.ERR_INVALID_ARG
+    assert call(n_src=1 << 31) == E.ERR_INVALID_ARG
+    assert call(rids=0) == E.ERR_INVALID_ARG
+    assert call(dst=0) == E.ERR_INVALID_ARG
+    assert call(src=0) == E.ERR_INVALID_ARG
+    assert call(src=SRC + 2) == E.ERR_INVALID_ARG
+    assert call(algo=7) == E.ERR_INVALID_ARG
+    assert call(check=2) == E.ERR_INVALID_ARG
+    # overlapping src and dst
+    assert call(dst=SRC + 400) == E.ERR_INVALID_ARG
+    # no source records but rids to retrieve: every rid is out of range
+    assert call(n_src=0, src=0) == E.ERR_RID_OUT_OF_RANGE
+    # workspace: too small, missing, misaligned, overlapping
+    need = dpg.lib().dpg_retrieve_workspace_bytes(None, 100, 8, 10, dpg.ALGO_DPG)
+    assert call(algo=dpg.ALGO_DPG, ws_bytes=need - 1) == E.ERR_WORKSPACE_TOO_SMALL
+    assert call(algo=dpg.ALGO_DPG, ws=0, ws_bytes=need) == E.ERR_INVALID_ARG
+    assert call(algo=dpg.ALGO_DPG, ws=WS + 16, ws_bytes=need) == E.ERR_INVALID_ARG
+    assert call(algo=dpg.ALGO_DPG, ws=DST, ws_bytes=need) == E.ERR_INVALID_ARG
+    # empty rid list with valid arguments passes validation (then needs a context)
+    assert call(n=0, rids=0, dst=0, ws=0, ws_bytes=0) == E.ERR_INVALID_ARG
+
+
+def test_options_need_context():
+    lib = dpg.lib()
+    assert lib.dpg_set_option(None, dpg.OPT_LOG2_RUN, 3) == dpg.ERR_INVALID_ARG
+    v = ctypes.c_int64()
+    assert lib.dpg_get_option(None, dpg.OPT_LOG2_RUN, ctypes.byref(v)) == dpg.ERR_INVALID_ARG

@@ -1,0 +1,222 @@
+"""Retrieval on the GPU through the C ABI, compared byte for byte with the CPU
+oracle on the same seeded inputs (Section 2's definition; Figure 1's phases)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_cs_0308004_amd import dpg, synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dpg.Context(0)
+    yield c
+    c.close()
+
+
+def configure(ctx, probe=0, log2_run=0, dist_tile=0, xcd=1):
+    ctx.set_option(dpg.OPT_PROBE, probe)
+    ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
+    ctx.set_option(dpg.OPT_DIST_TILE, dist_tile)
+    ctx.set_option(dpg.OPT_XCD_REMAP, xcd)
+
+
+def make_rids(kind, n_src, n_rids, rec_bytes, seed):
+    if kind == "perm":
+        assert n_rids == n_src
+        return synth.rids_permutation(n_src, seed)
+    if kind == "uniform":
+        return synth.rids_uniform(n_src, n_rids, seed)
+    if kind == "blocked":
+        return synth.rids_blocked(n_src, rec_bytes, seed)
+    if kind == "same":
+        return np.full(n_rids, n_src // 2, dtype=np.int32)
+    if kind == "identity":
+        return np.arange(n_rids, dtype=np.int32) % n_src
+    if kind == "reverse":
+        return (n_src - 1 - np.arange(n_rids, dtype=np.int64) % n_src).astype(np.int32)
+    raise ValueError(kind)
+
+
+VARIANTS = {
+    "direct": (dpg.ALGO_DIRECT, {}),
+    "dpg-cached": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED)),
+    "dpg-lds": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_LDS)),
+    "dpg-short-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=3)),
+    "dpg-lds-short-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_LDS, log2_run=4)),
+    "dpg-small-tiles": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=6, dist_tile=128)),
+    "dpg-no-xcd-remap": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, xcd=2)),
+    "auto": (dpg.ALGO_AUTO, {}),
+}
+
+CASES = [
+    # (n_src, n_rids, rec_bytes, rid kind)
+    (1000, 1000, 100, "perm"),
+    (4099, 4099, 100, "perm"),
+    (65537, 65537, 100, "perm"),
+    (20000, 50000, 100, "uniform"),
+    (30011, 30011, 100, "blocked"),
+    (5000, 7000, 100, "same"),
+    (10000, 10000, 8, "perm"),
+    (12345, 30000, 16, "uniform"),
+    (7777, 7777, 4, "perm"),
+    (3001, 3001, 12, "reverse"),
+    (9000, 9000, 36, "perm"),
+    (8192, 8192, 64, "blocked"),
+    (4000, 4000, 128, "identity"),
+    (2500, 6000, 256, "uniform"),
+    (300, 700, 4096, "uniform"),
+    (1, 5, 100, "same"),
+    (3, 1, 24, "uniform"),
+]
+
+
+@pytest.mark.parametrize("variant", list(VARIANTS))
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"N{c[0]}-M{c[1]}-R{c[2]}-{c[3]}")
+def test_retrieve_matches_oracle(ctx, case, variant):
+    n_src, n_rids, rec_bytes, kind = case
+    algo, opts = VARIANTS[variant]
+    seed = synth.SEED_BASE + n_src + rec_bytes
+    src = synth.record_bytes(n_src, rec_bytes, seed)
+    rids = make_rids(kind, n_src, n_rids, rec_bytes, seed)
+    expect = oracle.retrieve(src, rids)
+    configure(ctx, **opts)
+    try:
+        got = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=algo)
+        torch.cuda.synchronize()
+    finally:
+        configure(ctx)
+    assert np.array_equal(got.cpu().numpy(), expect), f"{variant} {case}"
+
+
+def test_empty_rid_list(ctx):
+    src = torch.zeros((10, 8), dtype=torch.uint8, device=DEV)
+    rids = torch.zeros(0, dtype=torch.int32, device=DEV)
+    for algo in (dpg.ALGO_DIRECT, dpg.ALGO_DPG):
+        out = ctx.retrieve(src, rids, algo=algo)
+        assert out.shape == (0, 8)
+
+
+@pytest.mark.parametrize("algo", [dpg.ALGO_DIRECT, dpg.ALGO_DPG])
+def test_check_rids_rejects_and_leaves_dst(ctx, algo):
+    src = torch.arange(400, dtype=torch.int32, device=DEV).view(torch.uint8).reshape(100, 16)
+    for bad in (100, -1, 1 << 30):
+        rids = torch.arange(50, dtype=torch.int32, device=DEV)
+        rids[37] = bad
+        dst = torch.full((50, 16), 7, dtype=torch.uint8, device=DEV)
+        with pytest.raises(dpg.DPGError) as e:
+            ctx.retrieve(src, rids, dst=dst, algo=algo, check_rids=True)
+        assert e.value.status == dpg.ERR_RID_OUT_OF_RANGE
+        assert bool((dst == 7).all())
+    rids = torch.arange(50, dtype=torch.int32, device=DEV)
+    out = ctx.retrieve(src, rids, algo=algo, check_rids=True)
+    assert torch.equal(out, src[:50])
+
+
+def test_phase_products_match_figure1(ctx):
+    """The distribute and probe intermediates equal the oracle's Figure 1 run:
+    RID runs (stable, in RID order), their offsets, and INTERNAL."""
+    for (n, m, rec, kind, probe, lg) in [(5000, 5000, 100, "perm", dpg.PROBE_CACHED, 8),
+                                         (3000, 9000, 16, "uniform", dpg.PROBE_LDS, 0),
+                                         (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0),
+                                         (4096, 4096, 8, "same", dpg.PROBE_LDS, 5)]:
+        src = synth.record_bytes(n, rec, seed=n)
+        rids = make_rids(kind, n, m, rec, seed=n)
+        configure(ctx, probe=probe, log2_run=lg)
+        try:
+            plan = ctx.plan_retrieve(n, rec, m, dpg.ALGO_DPG)
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV)
+            out = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=dpg.ALGO_DPG,
+                               workspace=ws)
+            torch.cuda.synchronize()
+        finally:
+            configure(ctx)
+        rid_run, run_off, record_run, dst = oracle.dpg_phases(src, rids, 1 << plan.log2_run)
+        w = ws.cpu().numpy()
+        g_off = w[plan.ws_run_off: plan.ws_run_off + 4 * (plan.n_runs + 1)].view(np.int32)
+        g_run = w[plan.ws_rid_run: plan.ws_rid_run + 4 * m].view(np.int32)
+        g_int = w[plan.ws_internal: plan.ws_internal + rec * m].reshape(m, rec)
+        assert np.array_equal(g_off.astype(np.int64), run_off)
+        assert np.array_equal(g_run, rid_run)
+        assert np.array_equal(g_int, record_run)
+        assert np.array_equal(out.cpu().numpy(), dst)
+
+
+def test_deterministic_and_variant_independent(ctx):
+    n, rec = 200003, 100
+    src = torch.from_numpy(synth.record_bytes(n, rec, seed=1)).to(DEV)
+    rids = torch.from_numpy(synth.rids_uniform(n, 300000, seed=1)).to(DEV)
+    outs = []
+    for algo, opts in VARIANTS.values():
+        configure(ctx, **opts)
+        try:
+            outs.append(ctx.retrieve(src, rids, algo=algo))
+            outs.append(ctx.retrieve(src, rids, algo=algo))
+        finally:
+            configure(ctx)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+
+
+def test_torch_generator_matches_numpy_on_gpu():
+    a = synth.record_bytes(5000, 100, seed=3, first=11)
+    b = synth.record_bytes(5000, 100, seed=3, first=11, backend="torch", device=DEV, chunk_records=1234)
+    assert np.array_equal(a, b.cpu().numpy())
+    for n in (1 << 16, 100003):
+        pa = synth.rids_permutation(n, seed=4)
+        pb = synth.rids_permutation(n, seed=4, backend="torch", device=DEV)
+        assert np.array_equal(pa, pb.cpu().numpy())
+    fa = synth.fact_table(10000, 1 << 12, 1.2, seed=5)
+    fb = synth.fact_table(10000, 1 << 12, 1.2, seed=5, backend="torch", device=DEV)
+    assert np.array_equal(fa, fb.cpu().numpy())
+
+
+def full_size_sample_check(out, n_src, rec_bytes, seed, rids_np, n_samples=20000):
+    """Sampled parity at full size: the oracle evaluates the sampled outputs one
+    by one from the generator (records_at), never from the device."""
+    m = rids_np.size
+    rng = np.random.default_rng(seed)
+    idx = np.unique(np.concatenate([rng.integers(0, m, n_samples), [0, m - 1]]))
+    want_src = synth.records_at(rids_np[idx], rec_bytes, seed)
+    got = out[torch.from_numpy(idx).to(out.device)].cpu().numpy()
+    assert np.array_equal(got, want_src)
+
+
+@pytest.mark.parametrize("algo", [dpg.ALGO_DPG, dpg.ALGO_DIRECT])
+def test_full_size_headline_config(ctx, algo):
+    """2^26 records of 100 B, random permutation: the benchmark's workload and
+    launch configuration.  Sampled outputs against the oracle, plus the
+    permutation invariant on a key column."""
+    n, rec = 1 << 26, 100
+    seed = synth.SEED_BASE + 1
+    src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
+    rids_t = synth.rids_permutation(n, seed, backend="torch", device=DEV)
+    rids_np = synth.rids_permutation(n, seed)
+    assert np.array_equal(rids_t[:1000].cpu().numpy(), rids_np[:1000])
+    out = ctx.retrieve(src, rids_t, algo=algo)
+    torch.cuda.synchronize()
+    full_size_sample_check(out, n, rec, seed, rids_np)
+    # permutation invariant over all 2^26 outputs: the multiset of 8-byte key
+    # prefixes is preserved
+    ka = torch.sort(src[:, :8].contiguous().view(torch.int64).reshape(-1))[0]
+    kb = torch.sort(out[:, :8].contiguous().view(torch.int64).reshape(-1))[0]
+    assert torch.equal(ka, kb)
+    del src, out, ka, kb
+    torch.cuda.empty_cache()
+
+
+def test_config1_full_oracle(ctx):
+    """2^20 records of 100 B, random permutation: every output byte vs the oracle."""
+    n, rec = 1 << 20, 100
+    seed = synth.SEED_BASE
+    src = synth.record_bytes(n, rec, seed)
+    rids = synth.rids_permutation(n, seed)
+    expect = oracle.retrieve(src, rids)
+    for algo in (dpg.ALGO_DIRECT, dpg.ALGO_DPG):
+        got = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=algo)
+        assert np.array_equal(got.cpu().numpy(), expect)
