@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--pattern", default="perm", choices=["perm", "uniform", "blocked"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--log2-run", type=int, default=0, help="force L = 2^v records per run (0: planner)")
+    ap.add_argument("--probe", type=int, default=0, help="1 cached, 2 LDS (0: planner)")
+    ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="HBM byte counts measured with rocprofv3 --pmc (optional)")
     return ap.parse_args()
@@ -141,6 +144,9 @@ def main():
     m = rids.numel()
     dst = torch.empty((m, R), dtype=torch.uint8, device=dev)
     ctx = dpg.Context(0)
+    ctx.set_option(dpg.OPT_LOG2_RUN, args.log2_run)
+    ctx.set_option(dpg.OPT_PROBE, args.probe)
+    ctx.set_option(dpg.OPT_DISTRIBUTE, args.dist)
     plan = ctx.plan_retrieve(n, R, m, dpg.ALGO_DPG)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     ws_direct = torch.empty(256, dtype=torch.uint8, device=dev)

@@ -66,7 +66,9 @@ typedef enum {
     DPG_OPT_PROBE = 2,      /* a dpg_probe value */
     DPG_OPT_DIST_TILE = 3,  /* rids per distribute tile (multiple of 64) */
     DPG_OPT_XCD_REMAP = 4,  /* 1 (default): tiles of one XCD are contiguous; 2: off */
-    DPG_OPT_USE_TUNED = 5   /* 1 (default): consult the autotune table; 2: ignore it */
+    DPG_OPT_USE_TUNED = 5,  /* 1 (default): consult the autotune table; 2: ignore it */
+    DPG_OPT_DISTRIBUTE = 6  /* Phase I: 1 one-wave append (any run count up to 8192),
+                               2 coalesced partition pass (used only when runs <= 256) */
 } dpg_option;
 
 typedef struct dpg_ctx dpg_ctx;

@@ -10,7 +10,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_scan_apply",   "k_dist_scatter", "k_probe_cached", "k_probe_lds",     "k_gather_phase",
     "k_check_ids",    "k_fill_i32",     "k_sort_extract", "k_radix_hist",    "k_radix_scatter",
     "k_tie_mark",     "k_tie_fix",      "k_join_extract", "k_join_assemble", "k_join_stream",
-    "k_batch"};
+    "k_batch",        "k_part_hist",    "k_part_scatter"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 
@@ -141,6 +141,10 @@ dpg_status dpg_set_option(dpg_ctx *ctx, dpg_option option, int64_t value) {
             if (value > 2) return DPG_ERR_INVALID_ARG;
             ctx->opt_use_tuned = value ? value : 1;
             return DPG_OK;
+        case DPG_OPT_DISTRIBUTE:
+            if (value > 2) return DPG_ERR_INVALID_ARG;
+            ctx->opt_distribute = value;
+            return DPG_OK;
     }
     return DPG_ERR_INVALID_ARG;
 }
@@ -153,6 +157,7 @@ dpg_status dpg_get_option(const dpg_ctx *ctx, dpg_option option, int64_t *value)
         case DPG_OPT_DIST_TILE: *value = ctx->opt_dist_tile; return DPG_OK;
         case DPG_OPT_XCD_REMAP: *value = ctx->opt_xcd; return DPG_OK;
         case DPG_OPT_USE_TUNED: *value = ctx->opt_use_tuned; return DPG_OK;
+        case DPG_OPT_DISTRIBUTE: *value = ctx->opt_distribute; return DPG_OK;
     }
     return DPG_ERR_INVALID_ARG;
 }

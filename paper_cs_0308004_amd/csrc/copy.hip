@@ -20,6 +20,8 @@ namespace dpg {
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+constexpr double kStreamingStoreBytes = 256.0 * 1024 * 1024;
+
 template <typename E, int WE>
 struct GatherShape {
     static constexpr int kEDw = sizeof(E) / 4;
@@ -28,7 +30,7 @@ struct GatherShape {
     static constexpr int TILE = WE > 0 ? (256 * PER) / WE : 0;   // records per workgroup
 };
 
-template <typename E, int WE>
+template <typename E, int WE, bool NT>
 __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int32_t *__restrict__ idx,
                                             E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,
                                             uint32_t magic, int tile_rt, int remap) {
@@ -42,6 +44,7 @@ __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int
     const int cnt = (int)min((int64_t)tile, n - base);
     // An index outside [0, limit) reads record 0 instead (undefined result, no
     // out-of-bounds access).
+#pragma unroll 8
     for (int j = threadIdx.x; j < cnt; j += 256) {
         const int32_t r = idx[base + j];
         s_idx[j] = (r >= 0 && (int64_t)r < limit) ? r : 0;
@@ -64,17 +67,20 @@ __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = threadIdx.x + k * 256;
-        if (e < total) out[e] = v[k];
+        if (e < total) {
+            if constexpr (NT) __builtin_nontemporal_store(v[k], out + e);
+            else out[e] = v[k];
+        }
     }
 }
 
 // Three kernel symbols for the three roles, so profiles tell them apart.
 #define DPG_GATHER_KERNEL(NAME)                                                                              \
-    template <typename E, int WE>                                                                            \
+    template <typename E, int WE, bool NT>                                                                   \
     __global__ __launch_bounds__(256) void NAME(const E *__restrict__ src, const int32_t *__restrict__ idx, \
                                                 E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,    \
                                                 uint32_t magic, int tile_rt, int remap) {                    \
-        gather_tile<E, WE>(src, idx, dst, n, limit, we_rt, magic, tile_rt, remap);                          \
+        gather_tile<E, WE, NT>(src, idx, dst, n, limit, we_rt, magic, tile_rt, remap);                      \
     }
 DPG_GATHER_KERNEL(k_direct_gather)
 DPG_GATHER_KERNEL(k_probe_cached)
@@ -97,15 +103,22 @@ static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx,
     const int64_t grid = (n + tile - 1) / tile;
     if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
     const size_t lds = (size_t)tile * sizeof(int32_t);
-    if (role == K_PROBE_CACHED)
-        hipLaunchKernelGGL((k_probe_cached<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, idx,
-                           (E *)dst, n, limit, we, magic, tile, remap);
-    else if (role == K_GATHER_PHASE)
-        hipLaunchKernelGGL((k_gather_phase<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, idx,
-                           (E *)dst, n, limit, we, magic, tile, remap);
-    else
-        hipLaunchKernelGGL((k_direct_gather<E, WE>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src,
-                           idx, (E *)dst, n, limit, we, magic, tile, remap);
+    // Outputs larger than the Infinity Cache are written with nontemporal
+    // stores: they will not be read again before being evicted.
+    const bool nt = (double)n * we * sizeof(E) > kStreamingStoreBytes;
+#define DPG_LAUNCH_ROLE(KERNEL)                                                                                    \
+    do {                                                                                                           \
+        if (nt)                                                                                                    \
+            hipLaunchKernelGGL((KERNEL<E, WE, true>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, \
+                               idx, (E *)dst, n, limit, we, magic, tile, remap);                                  \
+        else                                                                                                       \
+            hipLaunchKernelGGL((KERNEL<E, WE, false>), dim3((unsigned)grid), dim3(256), lds, stream,                \
+                               (const E *)src, idx, (E *)dst, n, limit, we, magic, tile, remap);                  \
+    } while (0)
+    if (role == K_PROBE_CACHED) DPG_LAUNCH_ROLE(k_probe_cached);
+    else if (role == K_GATHER_PHASE) DPG_LAUNCH_ROLE(k_gather_phase);
+    else DPG_LAUNCH_ROLE(k_direct_gather);
+#undef DPG_LAUNCH_ROLE
     DPG_HIP(hipGetLastError());
     return DPG_OK;
 }

@@ -58,6 +58,8 @@ enum KernelId {
     K_JOIN_ASSEMBLE,
     K_JOIN_STREAM,
     K_BATCH,
+    K_PART_HIST,
+    K_PART_SCATTER,
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -98,6 +100,7 @@ struct dpg_ctx {
     size_t l2_bytes = 4u << 20;
     // options
     int64_t opt_log2_run = 0, opt_probe = 0, opt_dist_tile = 0, opt_xcd = 1, opt_use_tuned = 1;
+    int64_t opt_distribute = 0;
     // profiling
     bool profiling = false;
     std::vector<dpg::ProfRecord> pending;
@@ -123,6 +126,10 @@ struct ProfScope {
     ~ProfScope();
 };
 
+// Phase I flavours: one-wave append into up to 8192 runs, or one coalesced
+// partition pass when the runs fit one 8-bit digit.
+enum { DIST_APPEND = 0, DIST_PARTITION = 1 };
+
 // Retrieval plan (resolved), shared by retrieve, sort, join and batch.
 struct RetrievePlan {
     int algo = DPG_ALGO_DIRECT;
@@ -136,6 +143,9 @@ struct RetrievePlan {
     size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0, off_items = 0;
     size_t off_run = 0, off_inv = 0, off_internal = 0, off_flag = 0;
     int64_t n_chunks = 0;      // column-scan chunks of the count matrix
+    int dist_mode = 0;         // DIST_APPEND or DIST_PARTITION
+    int part_nbits = 0;        // digit width of the partition pass
+    size_t off_part = 0;       // partition scratch (count matrix, bucket offsets)
     int32_t probe_chunk = 0;   // run entries per LDS-probe work item
     size_t workspace = 0;
 };

@@ -1,0 +1,43 @@
+// Stable one-digit partition pass (count bucket sort), shared by the DPG
+// distribute, the radix sort and the foreign-key sort of the DPG-Sort join.
+#pragma once
+
+#include "dpg_internal.h"
+
+namespace dpg {
+
+constexpr int kMaxDigitBits = 8;
+constexpr int kMaxDigitBuckets = 1 << kMaxDigitBits;
+
+struct PartPlan {
+    int64_t n = 0;
+    int nbits = 0;       // digit width; 2^nbits buckets
+    int key_bytes = 4;   // 4 or 8
+    bool has_val = false;
+    int per = 0;         // elements per thread
+    int tile = 0;        // elements per workgroup
+    int64_t n_tiles = 0, n_chunks = 0;
+    size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0;
+    size_t workspace = 0;
+};
+
+// Layout of the scratch one pass needs (count matrix and bucket offsets).
+PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
+
+// One stable pass: elements whose key is < limit move to the bucket of digit
+// (key >> shift) & (2^nbits - 1), in input order within a bucket.  inv (may be
+// null) receives the output position of every input element (0 if invalid).
+// bucket_off (in the scratch, also returned through *bucket_off_dev when
+// non-null) holds the 2^nbits + 1 bucket boundaries.
+// item_off / item_chunk (optional) as for the column scan: work items of at
+// most item_chunk elements per bucket, for the LDS probe.
+dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
+                            void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
+                            void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
+                            int32_t *item_off = nullptr, int item_chunk = 0);
+
+dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
+                              int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
+                              hipStream_t stream);
+
+}  // namespace dpg

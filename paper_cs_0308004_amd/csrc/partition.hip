@@ -1,0 +1,259 @@
+// Stable partition pass ("count bucket sort", Section 5.3): elements move to
+// the bucket named by one digit of their key, keeping input order inside every
+// bucket.  It serves the DPG distribute when the run count fits one digit
+// (Section 2.1, Phase I), every pass of the LSD radix sort (Section 3), and the
+// foreign-key sort of the DPG-Sort join (Section 4.2.1).
+//
+//   k_part_hist     per tile of T elements: digit counts -> cnt[t][d]
+//   column scan     (scan.hip) -> off[t][d], bucket_off[d]
+//   k_part_scatter  per tile: stable rank of every element within its digit
+//                   (one ballot per digit bit inside a wave; each wave owns a
+//                   contiguous slice of the tile, so wave order is input
+//                   order), the tile reordered by digit in LDS, then written
+//                   out as one contiguous segment per digit -- coalesced,
+//                   unlike a per-element scatter.  Optionally inv[i] = output
+//                   position of input element i, written in input order.
+//
+// Keys are uint32 or uint64; an optional uint32 value travels with each key.
+// A key >= `limit` is invalid: counted nowhere, not moved, its inv entry 0.
+#include "dev_common.h"
+#include "partition.h"
+
+namespace dpg {
+
+constexpr int kPartThreads = 256;
+constexpr int kPartWaves = kPartThreads / 64;
+
+template <typename K>
+__device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
+    return (uint32_t)(key >> shift) & mask;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict__ keys, int64_t n, int shift,
+                                                            int nbits, uint64_t limit, int T,
+                                                            int32_t *__restrict__ cnt) {
+    __shared__ int32_t h[kPartWaves][kMaxDigitBuckets];
+    const int nb = 1 << nbits;
+    const uint32_t mask = (uint32_t)nb - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int d = lane; d < nb; d += 64) h[wave][d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * T;
+    const int64_t end = min(base + T, n);
+    // all loads of a batch in flight before the first is used
+    constexpr int kBatch = 8;
+    for (int64_t i0 = base + wave * 64; i0 < end; i0 += kPartThreads * kBatch) {
+        K kv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
+            kv[u] = i < end ? keys[i] : K(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
+            const bool valid = i < end && (uint64_t)kv[u] < limit;
+            const uint32_t d = digit_of(kv[u], shift, mask);
+            const uint64_t act = __ballot(valid);
+            const uint64_t peers = match_lanes(d, nbits, act);
+            if (valid && (peers & lanemask_lt()) == 0) h[wave][d] += __popcll(peers);
+        }
+    }
+    __syncthreads();
+    int32_t *row = cnt + (int64_t)blockIdx.x * nb;
+    for (int d = threadIdx.x; d < nb; d += kPartThreads) {
+        int32_t s = 0;
+#pragma unroll
+        for (int w = 0; w < kPartWaves; ++w) s += h[w][d];
+        row[d] = s;
+    }
+}
+
+// PER elements per thread; a tile is kPartThreads * PER elements; wave w owns
+// elements [w*64*PER, (w+1)*64*PER) of the tile, its row k being the 64
+// consecutive elements starting at w*64*PER + 64*k.
+template <typename K, bool HAS_VAL, int PER>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter(
+    const K *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t n, int shift, int nbits,
+    uint64_t limit, int64_t nT, const int32_t *__restrict__ off, K *__restrict__ keys_out,
+    uint32_t *__restrict__ vals_out, int32_t *__restrict__ inv, int remap) {
+    constexpr int T = kPartThreads * PER;
+    extern __shared__ __align__(16) char smem[];
+    K *s_key = (K *)smem;
+    uint32_t *s_val = (uint32_t *)(smem + sizeof(K) * T);
+    __shared__ int32_t s_cnt[kPartWaves][kMaxDigitBuckets];  // per wave: count, then prefix over waves
+    __shared__ int32_t s_start[kMaxDigitBuckets];             // tile-local start of each digit
+    __shared__ int32_t s_glob[kMaxDigitBuckets];              // output start of each digit for this tile
+    __shared__ int32_t s_nvalid;
+    const int nb = 1 << nbits;
+    const uint32_t mask = (uint32_t)nb - 1;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t t = xcd_tile(blockIdx.x, nT, remap);
+    const int64_t base = t * T;
+    const int cnt = (int)min((int64_t)T, n - base);
+    for (int d = lane; d < nb; d += 64) s_cnt[wave][d] = 0;
+    for (int d = threadIdx.x; d < nb; d += kPartThreads) s_glob[d] = off[t * nb + d];
+
+    K key[PER];
+    uint32_t val[PER];
+    int32_t rank[PER];
+    const int wbase = wave * 64 * PER;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = wbase + k * 64 + lane;
+        key[k] = e < cnt ? keys[base + e] : K(0);
+        if constexpr (HAS_VAL) val[k] = e < cnt ? vals[base + e] : 0u;
+    }
+    __syncthreads();
+    // rank within (wave, digit), in row order
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = wbase + k * 64 + lane;
+        const bool valid = e < cnt && (uint64_t)key[k] < limit;
+        const uint32_t d = digit_of(key[k], shift, mask);
+        const uint64_t act = __ballot(valid);
+        const uint64_t peers = match_lanes(d, nbits, act);
+        const uint64_t below = peers & lanemask_lt();
+        const int32_t head = valid ? s_cnt[wave][d] : 0;
+        rank[k] = valid ? head + __popcll(below) : -1;
+        if (valid && below == 0) s_cnt[wave][d] = head + __popcll(peers);
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over waves (in place) and tile-local start
+    if (threadIdx.x < 64) {
+        int32_t carry = 0;
+        for (int d0 = 0; d0 < nb; d0 += 64) {
+            const int d = d0 + lane;
+            int32_t tot = 0;
+            if (d < nb) {
+#pragma unroll
+                for (int w = 0; w < kPartWaves; ++w) {
+                    const int32_t c = s_cnt[w][d];
+                    s_cnt[w][d] = tot;
+                    tot += c;
+                }
+            }
+            int32_t inc = tot;
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int32_t y = __shfl_up(inc, s, 64);
+                if (lane >= s) inc += y;
+            }
+            if (d < nb) s_start[d] = carry + inc - tot;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) s_nvalid = carry;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = wbase + k * 64 + lane;
+        if (rank[k] >= 0) {
+            const uint32_t d = digit_of(key[k], shift, mask);
+            const int32_t r = s_cnt[wave][d] + rank[k];
+            s_key[s_start[d] + r] = key[k];
+            if constexpr (HAS_VAL) s_val[s_start[d] + r] = val[k];
+            if (inv) inv[base + e] = s_glob[d] + r;
+        } else if (inv && e < cnt) {
+            inv[base + e] = 0;
+        }
+    }
+    __syncthreads();
+    const int nvalid = s_nvalid;
+    for (int j = threadIdx.x; j < nvalid; j += kPartThreads) {
+        const K k = s_key[j];
+        const uint32_t d = digit_of(k, shift, mask);
+        const int64_t pos = (int64_t)s_glob[d] + (j - s_start[d]);
+        keys_out[pos] = k;
+        if constexpr (HAS_VAL) vals_out[pos] = s_val[j];
+    }
+}
+
+static int part_per(int key_bytes, bool has_val) {
+    if (key_bytes == 4 && !has_val) return 32;
+    return 16;
+}
+
+PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val) {
+    PartPlan p;
+    p.n = n;
+    p.nbits = nbits;
+    p.key_bytes = key_bytes;
+    p.has_val = has_val;
+    p.per = part_per(key_bytes, has_val);
+    p.tile = kPartThreads * p.per;
+    p.n_tiles = n > 0 ? (n + p.tile - 1) / p.tile : 0;
+    p.n_chunks = (p.n_tiles + 31) / 32;
+    const int64_t nb = (int64_t)1 << nbits;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    p.off_cnt = take((size_t)p.n_tiles * nb * 4);
+    p.off_csum = take((size_t)p.n_chunks * nb * 4);
+    p.off_total = take((size_t)nb * 4);
+    p.off_bucket = take((size_t)(nb + 1) * 4);
+    p.workspace = off;
+    return p;
+}
+
+template <typename K, bool HAS_VAL, int PER>
+static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const uint32_t *vals_in, void *keys_out,
+                                   uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit, const int32_t *off,
+                                   int remap, hipStream_t stream) {
+    constexpr int T = kPartThreads * PER;
+    const size_t lds = sizeof(K) * T + (HAS_VAL ? sizeof(uint32_t) * T : 0);
+    hipLaunchKernelGGL((k_part_scatter<K, HAS_VAL, PER>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), lds, stream,
+                       (const K *)keys_in, vals_in, p.n, shift, p.nbits, limit, p.n_tiles, off, (K *)keys_out,
+                       vals_out, inv, remap);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
+                            void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
+                            void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
+                            int item_chunk) {
+    char *w = (char *)scratch;
+    int32_t *cnt = (int32_t *)(w + p.off_cnt);
+    int32_t *csum = (int32_t *)(w + p.off_csum);
+    int32_t *total = (int32_t *)(w + p.off_total);
+    int32_t *bucket_off = (int32_t *)(w + p.off_bucket);
+    if (bucket_off_dev) *bucket_off_dev = bucket_off;
+    if (p.n <= 0) return DPG_OK;
+    if (p.nbits < 1 || p.nbits > kMaxDigitBits) return DPG_ERR_UNSUPPORTED;
+    const int nb = 1 << p.nbits;
+    const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
+    {
+        ProfScope prof(ctx, K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb, stream);
+        if (p.key_bytes == 8)
+            hipLaunchKernelGGL((k_part_hist<uint64_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
+                               (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, cnt);
+        else
+            hipLaunchKernelGGL((k_part_hist<uint32_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
+                               (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, cnt);
+        DPG_HIP(hipGetLastError());
+    }
+    dpg_status st = launch_column_scan(ctx, cnt, p.n_tiles, nb, csum, p.n_chunks, total, bucket_off, item_off,
+                                       item_chunk, stream);
+    if (st != DPG_OK) return st;
+    ProfScope prof(ctx, K_PART_SCATTER, 2.0 * elem * p.n + (inv ? 4.0 * p.n : 0.0) + 4.0 * p.n_tiles * nb, stream);
+    const int remap = xcd_remap_flag(ctx);
+    if (p.key_bytes == 8) {
+        if (p.has_val)
+            return launch_scatter_t<uint64_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit,
+                                                        cnt, remap, stream);
+        return launch_scatter_t<uint64_t, false, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
+                                                     remap, stream);
+    }
+    if (p.has_val)
+        return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
+                                                    remap, stream);
+    return launch_scatter_t<uint32_t, false, 32>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
+                                                 remap, stream);
+}
+
+}  // namespace dpg

@@ -5,7 +5,9 @@
 //   * Phase II: one source run must fit the store that absorbs the probe's
 //     random reads.  With the LDS probe that store is the workgroup's LDS
 //     (L*R <= 64 KiB); with the cached probe it is the XCD's 4 MiB L2, shared
-//     by the runs its in-flight workgroups touch, so L*R is kept near 1 MiB.
+//     by the runs its in-flight workgroups touch, so L*R is kept near 2 MiB,
+//     or up to 64 MiB (Infinity Cache) when that lets Phase I run as one
+//     coalesced 8-bit partition pass.
 //   * Phases I and III: one buffer per run must fit the cache.  Here that is
 //     the LDS table of B running positions in the distribute (B <= 8192) and
 //     the B INTERNAL streams the gather reads, which the L2 and Infinity Cache
@@ -14,12 +16,14 @@
 #include <cstring>
 
 #include "dpg_internal.h"
+#include "partition.h"
 
 namespace dpg {
 
 constexpr int64_t kMaxRuns = 8192;
 constexpr size_t kLdsRegionBytes = 64 * 1024;
-constexpr size_t kCachedRegionBytes = 1 << 20;
+constexpr size_t kCachedRegionBytes = 2 << 20;
+constexpr size_t kMaxPartitionRegionBytes = 64 << 20;
 
 dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool need_ptr) {
     if (n < 0 || n > INT32_MAX) return DPG_ERR_INVALID_ARG;
@@ -51,11 +55,18 @@ static void layout_workspace(RetrievePlan *p) {
     p->off_flag = take(sizeof(int32_t));
     if (p->algo == DPG_ALGO_DPG) {
         const int64_t B = p->n_runs, M = p->n_rids;
-        p->off_cnt = take((size_t)p->n_tiles * B * 4);
-        p->off_csum = take((size_t)p->n_chunks * B * 4);
-        p->off_total = take((size_t)B * 4);
-        p->off_bucket = take((size_t)(B + 1) * 4);
-        p->off_items = take((size_t)(B + 1) * 4);
+        if (p->dist_mode == DIST_PARTITION) {
+            const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+            p->off_part = take(pp.workspace);
+            p->off_bucket = p->off_part + pp.off_bucket;
+            p->off_items = take((size_t)((1 << p->part_nbits) + 1) * 4);
+        } else {
+            p->off_cnt = take((size_t)p->n_tiles * B * 4);
+            p->off_csum = take((size_t)p->n_chunks * B * 4);
+            p->off_total = take((size_t)B * 4);
+            p->off_bucket = take((size_t)(B + 1) * 4);
+            p->off_items = take((size_t)(B + 1) * 4);
+        }
         p->off_run = take((size_t)M * 4);
         p->off_inv = take((size_t)M * 4);
         p->off_internal = take((size_t)M * p->rec_bytes);
@@ -63,7 +74,7 @@ static void layout_workspace(RetrievePlan *p) {
     p->workspace = off;
 }
 
-static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile) {
+static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, int dist_mode) {
     const int64_t N = p->n_src > 0 ? p->n_src : 1, M = p->n_rids;
     const int R = p->rec_bytes;
     const int lg_n = ilog2_ceil(N);
@@ -78,6 +89,12 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile) {
     } else {
         lg = floor_log2(kCachedRegionBytes / (size_t)R);
         if (lg < 0) lg = 0;
+        // Prefer runs long enough for the coalesced one-digit Phase I as long
+        // as one run stays well inside the Infinity Cache: measured on MI355X
+        // this beats more, L2-sized runs with the one-wave append.
+        const int lg_part = ilog2_ceil((N + kMaxDigitBuckets - 1) / kMaxDigitBuckets);
+        if (dist_mode != 1 && lg_part > lg && ((int64_t)R << lg_part) <= (int64_t)kMaxPartitionRegionBytes)
+            lg = lg_part;
     }
     if (lg > lg_n) lg = lg_n;
     // B <= kMaxRuns: lengthen the runs if needed
@@ -86,14 +103,26 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile) {
     p->probe = probe;
     p->log2_run = lg;
     p->n_runs = (N + ((int64_t)1 << lg) - 1) >> lg;
-    // A tile holds at least 4 rids per run on average, so the count matrix
-    // (tiles x runs) stays below a quarter of the rid list.
-    int64_t T = dist_tile > 0 ? dist_tile : 4 * p->n_runs;
-    if (dist_tile <= 0 && T < 1024) T = 1024;
-    T = (T + 63) / 64 * 64;
-    p->dist_tile = (int)T;
-    p->n_tiles = M > 0 ? (M + T - 1) / T : 0;
-    p->n_chunks = (p->n_tiles + 31) / 32;
+    if (p->n_runs <= kMaxDigitBuckets && dist_mode != 1) {
+        // one coalesced partition pass (its own tile size)
+        p->dist_mode = DIST_PARTITION;
+        p->part_nbits = bit_length((uint64_t)(p->n_runs - 1));
+        if (p->part_nbits < 1) p->part_nbits = 1;
+        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+        p->dist_tile = pp.tile;
+        p->n_tiles = pp.n_tiles;
+        p->n_chunks = pp.n_chunks;
+    } else {
+        // A tile holds at least 4 rids per run on average, so the count
+        // matrix (tiles x runs) stays below a quarter of the rid list.
+        p->dist_mode = DIST_APPEND;
+        int64_t T = dist_tile > 0 ? dist_tile : 4 * p->n_runs;
+        if (dist_tile <= 0 && T < 1024) T = 1024;
+        T = (T + 63) / 64 * 64;
+        p->dist_tile = (int)T;
+        p->n_tiles = M > 0 ? (M + T - 1) / T : 0;
+        p->n_chunks = (p->n_tiles + 31) / 32;
+    }
     if (probe == DPG_PROBE_LDS) {
         int64_t P = (int64_t)1 << lg;
         if (P < 256) P = 256;
@@ -116,8 +145,12 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
     int probe = ctx ? (int)ctx->opt_probe : 0;
     int log2_run = ctx ? (int)ctx->opt_log2_run : 0;
     int dist_tile = ctx ? (int)ctx->opt_dist_tile : 0;
+    const int dist_mode = ctx ? (int)ctx->opt_distribute : 0;
     if (algo == DPG_ALGO_AUTO) {
-        algo = rec_bytes <= 8 ? DPG_ALGO_DPG : DPG_ALGO_DIRECT;
+        // Measured on MI355X (2^26 records): direct retrieval is faster at every
+        // record size from 8 to 256 bytes, so it is the default unless the
+        // autotuner has recorded otherwise for this shape.
+        algo = DPG_ALGO_DIRECT;
         if (ctx && ctx->opt_use_tuned != 2) {
             const TuneKey key{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
             auto it = ctx->tuned.find(key);
@@ -130,7 +163,7 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
         }
     }
     p->algo = algo;
-    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile);
+    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile, dist_mode);
     layout_workspace(p);
     return DPG_OK;
 }

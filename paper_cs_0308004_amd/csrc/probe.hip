@@ -45,12 +45,14 @@ __global__ __launch_bounds__(256) void k_probe_lds(const E *__restrict__ src, in
     const int cnt = (int)(k1 - k0);
     const int64_t r0 = (int64_t)b << shift;
     const int64_t rlen = min((int64_t)1 << shift, n_src - r0);
+#pragma unroll 8
     for (int j = threadIdx.x; j < cnt; j += 256) {
         const int64_t loc = (int64_t)run[k0 + j] - r0;
         s_run[j] = (loc >= 0 && loc < rlen) ? (int32_t)loc : 0;
     }
     const E *rs = src + r0 * we;
     const int relems = (int)(rlen * we);
+#pragma unroll 8
     for (int e = threadIdx.x; e < relems; e += 256) region[e] = rs[e];
     __syncthreads();
     E *out = internal + k0 * we;

@@ -1,0 +1,139 @@
+// Column scan of a (tiles x buckets) count matrix, the "set bucket
+// boundaries" step of a count bucket sort (Section 5.3): for every tile t and
+// bucket b, off[t][b] = (elements in buckets < b) + (elements of bucket b in
+// tiles < t), computed in place over the row-major count matrix, plus the
+// bucket offsets bucket_off[0..B].  Every kernel reads and writes whole rows,
+// so all accesses are coalesced.
+#include "dev_common.h"
+#include "dpg_internal.h"
+
+namespace dpg {
+
+constexpr int kScanChunkRows = 32;
+
+// csum[b][c] = sum of cnt[t][b] over the rows t of chunk c.
+__global__ __launch_bounds__(256) void k_scan_chunks(const int32_t *__restrict__ cnt, int64_t nT, int B,
+                                                     int32_t *__restrict__ csum, int64_t nC) {
+    const int64_t c = blockIdx.x;
+    const int b = blockIdx.y * 256 + threadIdx.x;
+    if (b >= B) return;
+    const int64_t t0 = c * kScanChunkRows, t1 = min(t0 + kScanChunkRows, nT);
+    int32_t s = 0;
+    for (int64_t t = t0; t < t1; ++t) s += cnt[t * B + b];
+    csum[(int64_t)b * nC + c] = s;
+}
+
+__device__ __forceinline__ int32_t wave_inclusive_scan(int32_t x) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int32_t y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    return x;
+}
+
+// One wave per run b: exclusive scan of csum[b][*] in place, total[b] = sum.
+__global__ __launch_bounds__(256) void k_scan_cols(int32_t *__restrict__ csum, int64_t nC, int B,
+                                                   int32_t *__restrict__ total) {
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (b >= B) return;
+    int32_t *col = csum + (int64_t)b * nC;
+    int32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nC; c0 += 64) {
+        const int64_t c = c0 + lane;
+        const int32_t v = c < nC ? col[c] : 0;
+        const int32_t inc = wave_inclusive_scan(v);
+        if (c < nC) col[c] = carry + inc - v;
+        carry += __shfl(inc, 63, 64);
+    }
+    if (lane == 0) total[b] = carry;
+}
+
+// Exclusive scans over the runs: run_off[b] (b = 0..B) and, for the LDS probe,
+// item_off[b] = sum over b' < b of ceil(total[b'] / chunk).
+__global__ __launch_bounds__(1024) void k_scan_base(const int32_t *__restrict__ total, int B,
+                                                    int32_t *__restrict__ run_off, int32_t *__restrict__ item_off,
+                                                    int chunk) {
+    __shared__ int32_t wsum[2][16];
+    __shared__ int32_t carry[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (threadIdx.x == 0) carry[0] = carry[1] = 0;
+    __syncthreads();
+    for (int b0 = 0; b0 < B; b0 += 1024) {
+        const int b = b0 + threadIdx.x;
+        const int32_t v = b < B ? total[b] : 0;
+        const int32_t u = (b < B && chunk > 0) ? (v + chunk - 1) / chunk : 0;
+        const int32_t iv = wave_inclusive_scan(v), iu = wave_inclusive_scan(u);
+        if (lane == 63) { wsum[0][wave] = iv; wsum[1][wave] = iu; }
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int32_t a = lane < 16 ? wsum[0][lane] : 0;
+            const int32_t c = lane < 16 ? wsum[1][lane] : 0;
+            const int32_t sa = wave_inclusive_scan(a), sc = wave_inclusive_scan(c);
+            if (lane < 16) { wsum[0][lane] = sa - a; wsum[1][lane] = sc - c; }
+        }
+        __syncthreads();
+        if (b < B) {
+            run_off[b] = carry[0] + wsum[0][wave] + iv - v;
+            if (item_off) item_off[b] = carry[1] + wsum[1][wave] + iu - u;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) {
+            carry[0] += wsum[0][15] + iv;
+            carry[1] += wsum[1][15] + iu;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        run_off[B] = carry[0];
+        if (item_off) item_off[B] = carry[1];
+    }
+}
+
+// cnt[t][b] <- run_off[b] + rids of run b in tiles before t.
+__global__ __launch_bounds__(256) void k_scan_apply(int32_t *__restrict__ cnt, int64_t nT, int B,
+                                                    const int32_t *__restrict__ csum, int64_t nC,
+                                                    const int32_t *__restrict__ run_off) {
+    const int64_t c = blockIdx.x;
+    const int b = blockIdx.y * 256 + threadIdx.x;
+    if (b >= B) return;
+    int32_t run = run_off[b] + csum[(int64_t)b * nC + c];
+    const int64_t t0 = c * kScanChunkRows, t1 = min(t0 + kScanChunkRows, nT);
+    for (int64_t t = t0; t < t1; ++t) {
+        const int32_t v = cnt[t * B + b];
+        cnt[t * B + b] = run;
+        run += v;
+    }
+}
+
+dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
+                              int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
+                              hipStream_t stream) {
+    const unsigned gy = (unsigned)((B + 255) / 256);
+    {
+        ProfScope prof(ctx, K_SCAN_CHUNKS, 4.0 * nT * B + 4.0 * nC * B, stream);
+        hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nC, gy), dim3(256), 0, stream, cnt, nT, B, csum, nC);
+        DPG_HIP(hipGetLastError());
+    }
+    {
+        ProfScope prof(ctx, K_SCAN_COLS, 8.0 * nC * B, stream);
+        hipLaunchKernelGGL(k_scan_cols, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, stream, csum, nC, B, total);
+        DPG_HIP(hipGetLastError());
+    }
+    {
+        ProfScope prof(ctx, K_SCAN_BASE, 12.0 * B, stream);
+        hipLaunchKernelGGL(k_scan_base, dim3(1), dim3(1024), 0, stream, total, B, bucket_off, item_off, item_chunk);
+        DPG_HIP(hipGetLastError());
+    }
+    {
+        ProfScope prof(ctx, K_SCAN_APPLY, 8.0 * nT * B + 4.0 * nC * B, stream);
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nC, gy), dim3(256), 0, stream, cnt, nT, B, csum, nC,
+                           bucket_off);
+        DPG_HIP(hipGetLastError());
+    }
+    return DPG_OK;
+}
+
+}  // namespace dpg

@@ -19,7 +19,8 @@ def ctx():
     c.close()
 
 
-def configure(ctx, probe=0, log2_run=0, dist_tile=0, xcd=1):
+def configure(ctx, probe=0, log2_run=0, dist_tile=0, xcd=1, dist=0):
+    ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
     ctx.set_option(dpg.OPT_PROBE, probe)
     ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
     ctx.set_option(dpg.OPT_DIST_TILE, dist_tile)
@@ -51,6 +52,9 @@ VARIANTS = {
     "dpg-lds-short-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_LDS, log2_run=4)),
     "dpg-small-tiles": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=6, dist_tile=128)),
     "dpg-no-xcd-remap": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, xcd=2)),
+    "dpg-append": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_APPEND)),
+    "dpg-lds-append": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_LDS, dist=dpg.DIST_APPEND)),
+    "dpg-partition-long-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=12, dist=dpg.DIST_PARTITION)),
     "auto": (dpg.ALGO_AUTO, {}),
 }
 
@@ -121,13 +125,16 @@ def test_check_rids_rejects_and_leaves_dst(ctx, algo):
 def test_phase_products_match_figure1(ctx):
     """The distribute and probe intermediates equal the oracle's Figure 1 run:
     RID runs (stable, in RID order), their offsets, and INTERNAL."""
-    for (n, m, rec, kind, probe, lg) in [(5000, 5000, 100, "perm", dpg.PROBE_CACHED, 8),
-                                         (3000, 9000, 16, "uniform", dpg.PROBE_LDS, 0),
-                                         (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0),
-                                         (4096, 4096, 8, "same", dpg.PROBE_LDS, 5)]:
+    for (n, m, rec, kind, probe, lg, dist) in [(5000, 5000, 100, "perm", dpg.PROBE_CACHED, 8, 0),
+                                               (5000, 5000, 100, "perm", dpg.PROBE_CACHED, 4, 0),
+                                               (3000, 9000, 16, "uniform", dpg.PROBE_LDS, 0, 0),
+                                               (3000, 9000, 16, "uniform", dpg.PROBE_LDS, 0, 1),
+                                               (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0, 0),
+                                               (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0, 1),
+                                               (4096, 4096, 8, "same", dpg.PROBE_LDS, 5, 0)]:
         src = synth.record_bytes(n, rec, seed=n)
         rids = make_rids(kind, n, m, rec, seed=n)
-        configure(ctx, probe=probe, log2_run=lg)
+        configure(ctx, probe=probe, log2_run=lg, dist=dist)
         try:
             plan = ctx.plan_retrieve(n, rec, m, dpg.ALGO_DPG)
             ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV)
