@@ -55,6 +55,11 @@ typedef enum {
 } dpg_algo;
 
 typedef enum {
+    DPG_JOIN_FACT_ORDER = 0, /* DPG-Move join: output in fact (rid_R) order (Section 4.2.1) */
+    DPG_JOIN_DIM_ORDER = 1   /* DPG-Sort join: output in foreign-key (rid_F) order */
+} dpg_join_order;
+
+typedef enum {
     DPG_PROBE_AUTO = 0,
     DPG_PROBE_CACHED = 1, /* probe reads each source run through L2 / Infinity Cache */
     DPG_PROBE_LDS = 2     /* probe stages each source run in LDS with coalesced loads */
@@ -128,6 +133,53 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
                         const int32_t *rids, int64_t n_rids, void *dst,
                         void *workspace, size_t workspace_bytes, dpg_algo algo,
                         int check_rids, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Sorting (Section 3): three-phase key-pointer sort with DPG as the copy      */
+/* phase.  Records are ordered by key bytes [key_offset, key_offset+key_bytes) */
+/* compared as unsigned bytes, lexicographically; records with equal keys keep */
+/* their input order, so the output is unique.                                 */
+/* ------------------------------------------------------------------------- */
+
+/* Workspace for dpg_sort_records (0 for arguments it would reject). */
+size_t dpg_sort_workspace_bytes(const dpg_ctx *ctx, int64_t n, int32_t rec_bytes, int32_t key_offset,
+                                int32_t key_bytes, dpg_algo copy_algo);
+
+/* dst[j] = src[perm[j]] where perm sorts the records by key.  perm_out
+ * (nullable, uint32[n]) receives perm.  key_bytes in [1, 64].  copy_algo picks
+ * the retrieval used for the copy phase (DPG, direct, or AUTO).  For keys
+ * longer than 8 bytes the call synchronizes the stream once, to learn whether
+ * two records share their first 8 key bytes (then the pairs are sorted over
+ * the whole key).  src, dst, perm_out and workspace must not overlap. */
+dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes,
+                            int32_t key_offset, int32_t key_bytes, void *dst, uint32_t *perm_out,
+                            void *workspace, size_t workspace_bytes, dpg_algo copy_algo,
+                            hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Foreign-key joins (Section 4.2.1).  The fact relation (the paper's R)       */
+/* references the dimension relation (the indexed F): the little-endian       */
+/* uint32 at byte fk_offset (a multiple of 4) of a fact row is the number of  */
+/* the dimension row it joins (dense ids, so rid_F = fk).  Every fact row      */
+/* yields one joined row of fact_bytes + dim_bytes bytes: the fact row          */
+/* followed by its dimension row.                                             */
+/*   DPG_JOIN_FACT_ORDER (DPG-Move): out[i] joins fact row i.                 */
+/*   DPG_JOIN_DIM_ORDER  (DPG-Sort): rows ordered by foreign key; rows with   */
+/*     equal keys keep fact order.                                            */
+/* algo picks how the moved relation is retrieved: DPG, direct, or AUTO.      */
+/* ------------------------------------------------------------------------- */
+size_t dpg_fk_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_fact, int32_t fact_bytes,
+                                   int32_t fk_offset, int64_t n_dim, int32_t dim_bytes,
+                                   dpg_join_order order, dpg_algo algo);
+
+/* check_fk = 1: verify every foreign key is < n_dim first (one extra pass and
+ * one stream synchronization); otherwise an out-of-range key is undefined
+ * behaviour (no out-of-bounds access, unspecified row contents).  out must
+ * not overlap fact, dim or workspace. */
+dpg_status dpg_fk_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t fact_bytes,
+                       int32_t fk_offset, const void *dim, int64_t n_dim, int32_t dim_bytes,
+                       void *out, dpg_join_order order, void *workspace, size_t workspace_bytes,
+                       dpg_algo algo, int check_fk, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Per-kernel timing.  When enabled, every kernel the context launches is     */

@@ -9,7 +9,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_direct_gather", "k_dist_hist",    "k_scan_chunks",  "k_scan_cols",     "k_scan_base",
     "k_scan_apply",   "k_dist_scatter", "k_probe_cached", "k_probe_lds",     "k_gather_phase",
     "k_check_ids",    "k_fill_i32",     "k_sort_extract", "k_radix_hist",    "k_radix_scatter",
-    "k_tie_mark",     "k_tie_fix",      "k_join_extract", "k_join_assemble", "k_join_stream",
+    "k_tie_check",    "k_tie_fix",      "k_join_extract", "k_join_assemble", "k_join_stream",
     "k_batch",        "k_part_hist",    "k_part_scatter"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
@@ -40,6 +40,18 @@ ProfScope::~ProfScope() {
     ctx->pending.push_back(ProfRecord{kernel, bytes, ev0, ev1});
 }
 
+dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
+                                void *ws, hipStream_t stream) {
+    const double R = p.rec_bytes, M = (double)p.n_rids;
+    char *w = (char *)ws;
+    dpg_status st = launch_distribute(ctx, p, rids, ws, stream);
+    if (st != DPG_OK) return st;
+    if (p.probe == DPG_PROBE_LDS) return launch_probe_lds(ctx, p, src, ws, stream);
+    const double touched = (double)(p.n_src < p.n_rids ? p.n_src : p.n_rids);
+    return launch_gather(ctx, K_PROBE_CACHED, src, p.n_src, (const int32_t *)(w + p.off_run), w + p.off_internal,
+                         p.n_rids, p.rec_bytes, 4.0 * M + R * touched + R * M, stream);
+}
+
 dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids, void *dst,
                         void *ws, hipStream_t stream) {
     const double R = p.rec_bytes, M = (double)p.n_rids;
@@ -48,19 +60,10 @@ dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, co
         return launch_gather(ctx, K_DIRECT_GATHER, src, p.n_src, rids, dst, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M,
                              stream);
     char *w = (char *)ws;
-    dpg_status st = launch_distribute(ctx, p, rids, ws, stream);
+    const dpg_status st = run_distribute_probe(ctx, p, src, rids, ws, stream);
     if (st != DPG_OK) return st;
-    void *internal = w + p.off_internal;
-    if (p.probe == DPG_PROBE_LDS) {
-        st = launch_probe_lds(ctx, p, src, ws, stream);
-    } else {
-        const double touched = (double)(p.n_src < p.n_rids ? p.n_src : p.n_rids);
-        st = launch_gather(ctx, K_PROBE_CACHED, src, p.n_src, (const int32_t *)(w + p.off_run), internal, p.n_rids,
-                           p.rec_bytes, 4.0 * M + R * touched + R * M, stream);
-    }
-    if (st != DPG_OK) return st;
-    return launch_gather(ctx, K_GATHER_PHASE, internal, p.n_rids, (const int32_t *)(w + p.off_inv), dst, p.n_rids,
-                         p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
+    return launch_gather(ctx, K_GATHER_PHASE, w + p.off_internal, p.n_rids, (const int32_t *)(w + p.off_inv), dst,
+                         p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
 }
 
 }  // namespace dpg

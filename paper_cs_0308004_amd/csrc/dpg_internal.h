@@ -155,6 +155,11 @@ bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn);
 dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
                               int64_t n_rids, int algo, RetrievePlan *plan);
 
+// Phases I and II of a planned DPG retrieval: afterwards the workspace holds
+// INTERNAL (at off_internal) and inv (at off_inv), so a caller can fuse Phase
+// III into its own kernel.
+dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
+                                void *ws, hipStream_t stream);
 // Enqueue a planned retrieval (arguments already validated).
 dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
                         void *dst, void *ws, hipStream_t stream);

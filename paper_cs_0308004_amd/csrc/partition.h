@@ -24,7 +24,8 @@ struct PartPlan {
 // Layout of the scratch one pass needs (count matrix and bucket offsets).
 PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 
-// One stable pass: elements whose key is < limit move to the bucket of digit
+// One stable pass: elements whose key is < limit (any key if limit is 0) move
+// to the bucket of digit
 // (key >> shift) & (2^nbits - 1), in input order within a bucket.  inv (may be
 // null) receives the output position of every input element (0 if invalid).
 // bucket_off (in the scratch, also returned through *bucket_off_dev when

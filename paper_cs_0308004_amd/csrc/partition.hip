@@ -15,7 +15,8 @@
 //                   position of input element i, written in input order.
 //
 // Keys are uint32 or uint64; an optional uint32 value travels with each key.
-// A key >= `limit` is invalid: counted nowhere, not moved, its inv entry 0.
+// A key >= `limit` is invalid: counted nowhere, not moved, its inv entry 0
+// (limit 0: every key is valid).
 #include "dev_common.h"
 #include "partition.h"
 
@@ -53,7 +54,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
-            const bool valid = i < end && (uint64_t)kv[u] < limit;
+            const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
             const uint32_t d = digit_of(kv[u], shift, mask);
             const uint64_t act = __ballot(valid);
             const uint64_t peers = match_lanes(d, nbits, act);
@@ -110,7 +111,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = wbase + k * 64 + lane;
-        const bool valid = e < cnt && (uint64_t)key[k] < limit;
+        const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
         const uint32_t d = digit_of(key[k], shift, mask);
         const uint64_t act = __ballot(valid);
         const uint64_t peers = match_lanes(d, nbits, act);

@@ -17,6 +17,7 @@ OK, ERR_INVALID_ARG, ERR_RID_OUT_OF_RANGE, ERR_FK_OUT_OF_RANGE = 0, 1, 2, 3
 ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_BUSY = 4, 5, 6, 7
 
 ALGO_AUTO, ALGO_DIRECT, ALGO_DPG = 0, 1, 2
+JOIN_FACT_ORDER, JOIN_DIM_ORDER = 0, 1
 PROBE_AUTO, PROBE_CACHED, PROBE_LDS = 0, 1, 2
 OPT_LOG2_RUN, OPT_PROBE, OPT_DIST_TILE, OPT_XCD_REMAP, OPT_USE_TUNED, OPT_DISTRIBUTE = 1, 2, 3, 4, 5, 6
 DIST_AUTO, DIST_APPEND, DIST_PARTITION = 0, 1, 2
@@ -47,6 +48,10 @@ SIGNATURES = {
     "dpg_plan_retrieve": (_I32, [_VP, _I64, _I32, _I64, _I32, ctypes.POINTER(Plan)]),
     "dpg_retrieve_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
     "dpg_retrieve": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_sort_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I32, _I32]),
+    "dpg_sort_records": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _SZ, _I32, _VP]),
+    "dpg_fk_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32]),
+    "dpg_fk_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _SZ, _I32, _I32, _VP]),
     "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
     "dpg_profile_reset": (_I32, [_VP]),
     "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
@@ -159,6 +164,51 @@ class Context:
                                 _addr(workspace), workspace.numel(), algo, int(check_rids), _stream(stream))
         _check(st, "dpg_retrieve")
         return dst
+
+    # ---- sorting -------------------------------------------------------
+    def sort_workspace_bytes(self, n: int, rec_bytes: int, key_offset: int = 0, key_bytes: int = 10,
+                             algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_sort_workspace_bytes(self.handle, n, rec_bytes, key_offset, key_bytes, algo)
+
+    def sort_records(self, src, key_offset: int = 0, key_bytes: int = 10, dst=None, perm=None,
+                     algo: int = ALGO_AUTO, workspace=None, stream=None, want_perm: bool = True):
+        """Sort (N, R) uint8 records by key bytes; returns (dst, perm or None)."""
+        import torch
+
+        n, rec_bytes = src.shape[0], _rec_bytes(src)
+        if dst is None:
+            dst = torch.empty_like(src)
+        if perm is None and want_perm:
+            perm = torch.empty(n, dtype=torch.int32, device=src.device)
+        if workspace is None:
+            need = self.sort_workspace_bytes(n, rec_bytes, key_offset, key_bytes, algo)
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=src.device)
+        st = lib().dpg_sort_records(self.handle, _addr(src), n, rec_bytes, key_offset, key_bytes, _addr(dst),
+                                    _addr(perm), _addr(workspace), workspace.numel(), algo, _stream(stream))
+        _check(st, "dpg_sort_records")
+        return dst, perm
+
+    # ---- joins ---------------------------------------------------------
+    def fk_join_workspace_bytes(self, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes, order, algo=ALGO_AUTO):
+        return lib().dpg_fk_join_workspace_bytes(self.handle, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes,
+                                                 order, algo)
+
+    def fk_join(self, fact, dim, fk_offset: int = 0, order: int = JOIN_FACT_ORDER, out=None, algo: int = ALGO_AUTO,
+                check_fk: bool = False, workspace=None, stream=None):
+        """Joined rows fact || dim[fk]; fact is (F, fact_bytes) uint8, dim (D, dim_bytes) uint8."""
+        import torch
+
+        n_fact, fb = fact.shape[0], _rec_bytes(fact)
+        n_dim, db = dim.shape[0], _rec_bytes(dim)
+        if out is None:
+            out = torch.empty((n_fact, fb + db), dtype=torch.uint8, device=fact.device)
+        if workspace is None:
+            need = self.fk_join_workspace_bytes(n_fact, fb, fk_offset, n_dim, db, order, algo)
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=fact.device)
+        st = lib().dpg_fk_join(self.handle, _addr(fact), n_fact, fb, fk_offset, _addr(dim), n_dim, db, _addr(out),
+                               order, _addr(workspace), workspace.numel(), algo, int(check_fk), _stream(stream))
+        _check(st, "dpg_fk_join")
+        return out
 
     # ---- profiling -----------------------------------------------------
     def profile_enable(self, on: bool = True):

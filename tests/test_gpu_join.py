@@ -1,0 +1,108 @@
+"""DPG-Move and DPG-Sort foreign-key joins (Section 4.2.1) on the GPU through
+the C ABI, against the CPU oracle byte for byte."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_cs_0308004_amd import dpg, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dpg.Context(0)
+    yield c
+    c.close()
+
+
+CASES = [
+    # (n_fact, n_dim, s (Zipf), fact_bytes, dim_bytes, permute ids)
+    (1, 1, 0.0, 16, 64, True),
+    (1000, 300, 0.0, 16, 64, True),
+    (50000, 4096, 0.8, 16, 64, True),
+    (70001, 1 << 12, 1.2, 16, 64, True),
+    (70001, 1 << 12, 1.2, 16, 64, False),
+    (30000, 70000, 0.0, 16, 64, True),
+    (20000, 1 << 17, 0.0, 16, 64, True),
+    (9000, 500, 0.8, 24, 36, True),
+    (5000, 100, 0.0, 8, 4, True),
+]
+
+
+@pytest.mark.parametrize("algo", [dpg.ALGO_DPG, dpg.ALGO_DIRECT])
+@pytest.mark.parametrize("order", [dpg.JOIN_FACT_ORDER, dpg.JOIN_DIM_ORDER], ids=["move", "sort"])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"F{c[0]}-D{c[1]}-s{c[2]}-f{c[3]}-d{c[4]}-p{int(c[5])}")
+def test_join_matches_oracle(ctx, case, order, algo):
+    n_fact, n_dim, s, fb, db, perm_ids = case
+    seed = synth.SEED_BASE + 3 + n_fact
+    fact = synth.fact_table(n_fact, n_dim, s, seed, fact_bytes=fb, permute_ids=perm_ids)
+    dim = synth.dim_table(n_dim, seed, dim_bytes=db)
+    fn = oracle.fk_join_fact_order if order == dpg.JOIN_FACT_ORDER else oracle.fk_join_dim_order
+    want = fn(fact, dim, 0)
+    got = ctx.fk_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 0, order, algo=algo)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("order", [dpg.JOIN_FACT_ORDER, dpg.JOIN_DIM_ORDER])
+def test_join_fk_offset_and_check(ctx, order):
+    n_fact, n_dim = 4000, 777
+    rng = np.random.default_rng(5)
+    fact = rng.integers(0, 256, size=(n_fact, 20), dtype=np.uint8)
+    fk = rng.integers(0, n_dim, n_fact).astype(np.uint32)
+    fact[:, 8:12] = fk.view(np.uint8).reshape(-1, 4)
+    dim = synth.dim_table(n_dim, seed=9, dim_bytes=32)
+    fn = oracle.fk_join_fact_order if order == dpg.JOIN_FACT_ORDER else oracle.fk_join_dim_order
+    want = fn(fact, dim, 8)
+    for algo in (dpg.ALGO_DPG, dpg.ALGO_DIRECT):
+        got = ctx.fk_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 8, order, algo=algo,
+                          check_fk=True)
+        assert np.array_equal(got.cpu().numpy(), want)
+        bad = fact.copy()
+        bad[1234, 8:12] = np.array([n_dim], dtype=np.uint32).view(np.uint8)
+        out = torch.full((n_fact, 52), 9, dtype=torch.uint8, device=DEV)
+        with pytest.raises(dpg.DPGError) as e:
+            ctx.fk_join(torch.from_numpy(bad).to(DEV), torch.from_numpy(dim).to(DEV), 8, order, out=out, algo=algo,
+                        check_fk=True)
+        assert e.value.status == dpg.ERR_FK_OUT_OF_RANGE
+        assert bool((out == 9).all())
+
+
+def test_join_full_size_sampled(ctx):
+    """Dimension 2^24 x 64 B, fact 2^28 x 16 B with Zipf(1.2) keys: the
+    benchmark's join workload.  Sampled rows against the oracle evaluated row
+    by row from the generator; the dimension-order output is checked in full for
+    nondecreasing keys, and its fact rows are a permutation of the input's."""
+    n_dim, n_fact, s = 1 << 24, 1 << 28, 1.2
+    seed = synth.SEED_BASE + 3
+    fact = synth.fact_table(n_fact, n_dim, s, seed, backend="torch", device=DEV)
+    dim = synth.dim_table(n_dim, seed, backend="torch", device=DEV)
+    idx = np.unique(np.random.default_rng(4).integers(0, n_fact, 20000))
+    fact_rows = synth.records_at(idx, 16, seed, synth.STREAM_FACT)
+    fk = synth.zipf_fk_at(n_dim, s, idx.astype(np.uint64), seed)
+    fact_rows[:, 0:4] = fk.astype(np.uint32).view(np.uint8).reshape(-1, 4)
+    dim_rows = synth.records_at(fk, 64, seed, synth.STREAM_DIM)
+    dim_rows[:, 0:4] = fk.astype(np.uint32).view(np.uint8).reshape(-1, 4)
+    # the oracle on a small problem holding just the sampled rows: mini fact
+    # row k points at mini dimension row k, then its key bytes are restored
+    mini_fact = fact_rows.copy()
+    mini_fact[:, 0:4] = np.arange(idx.size, dtype=np.uint32).view(np.uint8).reshape(-1, 4)
+    want = oracle.fk_join_fact_order(mini_fact, dim_rows, 0)
+    want[:, 0:4] = fact_rows[:, 0:4]
+    out = ctx.fk_join(fact, dim, 0, dpg.JOIN_FACT_ORDER, algo=dpg.ALGO_DPG)
+    torch.cuda.synchronize()
+    assert np.array_equal(out[torch.from_numpy(idx).to(DEV)].cpu().numpy(), want)
+    del out
+    out = ctx.fk_join(fact, dim, 0, dpg.JOIN_DIM_ORDER, algo=dpg.ALGO_DPG)
+    torch.cuda.synchronize()
+    ofk = out[:, 0:4].contiguous().view(torch.int32).reshape(-1).long()
+    assert bool((ofk[1:] >= ofk[:-1]).all())
+    assert torch.equal(out[:, 16:20], out[:, 0:4])
+    a = torch.sort(fact[:, 4:12].contiguous().view(torch.int64).reshape(-1))[0]
+    b = torch.sort(out[:, 4:12].contiguous().view(torch.int64).reshape(-1))[0]
+    assert torch.equal(a, b)
+    del fact, dim, out, ofk, a, b
+    torch.cuda.empty_cache()
