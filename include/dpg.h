@@ -182,6 +182,50 @@ dpg_status dpg_fk_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t f
                        dpg_algo algo, int check_fk, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Batches: many retrieval / join requests of uneven size in one call.  All   */
+/* direct-algorithm work of the batch (direct retrievals, direct fact-order   */
+/* joins) runs in ONE launch of a persistent, queue-driven kernel; requests   */
+/* planned as DPG and dimension-order joins run their own phase sequence in   */
+/* the same stream.  Every output equals that of the request run alone.       */
+/* ------------------------------------------------------------------------- */
+typedef enum { DPG_REQ_RETRIEVE = 0, DPG_REQ_FK_JOIN = 1 } dpg_request_kind;
+
+typedef struct {
+    int32_t kind;          /* dpg_request_kind */
+    int32_t algo;          /* dpg_algo for the retrieval (or the moved relation) */
+    const void *src;       /* retrieve: source records; join: dimension rows */
+    int64_t n_src;         /* rows of src */
+    int32_t rec_bytes;     /* retrieve: record size; join: dimension row size */
+    int32_t fact_bytes;    /* join: fact row size */
+    const int32_t *rids;   /* retrieve: n rids */
+    const void *fact;      /* join: n fact rows */
+    int64_t n;             /* retrieve: number of rids; join: number of fact rows */
+    int32_t fk_offset;     /* join: byte offset of the uint32 foreign key */
+    int32_t order;         /* join: dpg_join_order */
+    void *dst;             /* output rows (n x rec_bytes, or n x (fact_bytes + rec_bytes)) */
+} dpg_request;
+
+/* Workspace for dpg_batch_run (0 if a request is invalid). */
+size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n);
+/* Validates every request first (same rules as the single calls, no device
+ * checks of rids or keys); on any error nothing is enqueued. */
+dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream);
+
+/* A captured graph of the persistent batch launch, bound to a workspace: each
+ * dpg_batch_graph_launch uploads the new requests' descriptors and replays
+ * the graph.  Graph batches carry direct-algorithm work only (a request that
+ * would be planned as DPG, or a dimension-order join, returns
+ * DPG_ERR_UNSUPPORTED).  Capture needs a non-default stream. */
+typedef struct dpg_batch_graph dpg_batch_graph;
+size_t dpg_batch_graph_workspace_bytes(const dpg_ctx *ctx, int32_t max_requests);
+dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *workspace,
+                                  size_t workspace_bytes, hipStream_t stream, dpg_batch_graph **out);
+dpg_status dpg_batch_graph_launch(dpg_batch_graph *graph, const dpg_request *reqs, int32_t n,
+                                  hipStream_t stream);
+void dpg_batch_graph_destroy(dpg_batch_graph *graph);
+
+/* ------------------------------------------------------------------------- */
 /* Per-kernel timing.  When enabled, every kernel the context launches is     */
 /* bracketed by HIP events on its own stream, and its algorithmic bytes (what */
 /* the algorithm must read and write, excluding cache effects) are recorded.  */

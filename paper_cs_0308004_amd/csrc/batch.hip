@@ -1,0 +1,444 @@
+// Batched execution of many retrieval / join requests of uneven size.
+//
+// Direct-algorithm work of every request in the batch (retrievals planned as
+// direct, and fact-order joins planned as direct) runs in ONE launch of the
+// persistent kernel k_batch: a fixed grid of workgroups pulls work items from
+// a device queue (one atomic counter); an item is a tile of output rows of one
+// request.  Each output row is A[ia] || B[ib] (retrieval: src[rid], no B;
+// fact-order join: fact[i] || dim[fk_i]), so one kernel serves both kinds and
+// every record size.  Every workgroup leaves the loop once the queue is
+// exhausted; nothing waits on the host.
+//
+// Requests planned as DPG, and dimension-order joins, run their own phase
+// sequence (the same code as dpg_retrieve / dpg_fk_join) in the same stream,
+// so every request's output is bit-identical alone and in any batch.
+//
+// The batch header (item count, descriptor count) lives in device memory, so a
+// captured graph of [reset queue, k_batch] can be replayed with new requests:
+// only the descriptor upload changes (dpg_batch_graph_*).
+#include <algorithm>
+#include <vector>
+
+#include "dev_common.h"
+#include "dpg_internal.h"
+#include "partition.h"
+
+namespace dpg {
+
+struct BatchDesc {
+    const uint32_t *a;      // retrieval source records / fact rows
+    const int32_t *idx_a;   // rids (retrieval) or null (row i of A)
+    const uint32_t *b;      // dimension rows (join) or null
+    uint32_t *out;
+    int64_t lim_a, lim_b;   // row counts of A and B (indices outside read row 0)
+    int64_t n_rows;         // output rows
+    int64_t item_start;     // first work item of this request
+    int32_t wa, wb;         // dwords taken from A and from B per output row
+    int32_t fk_word;        // word of the A row holding the foreign key (join)
+    int32_t tile_rows;      // output rows per work item
+    uint32_t magic;         // ceil(2^32 / (wa + wb)) for the row division
+    int32_t request;        // index in the caller's request array
+};
+
+struct BatchHeader {
+    int64_t total_items;
+    int32_t n_desc;
+    int32_t pad;
+};
+
+constexpr int kBatchThreads = 256;
+constexpr int kBatchPer = 16;
+constexpr int kBatchMaxTileRows = 2048;
+constexpr int kBatchItemWords = 16384;  // ~64 KiB of output per work item
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__restrict__ hdr,
+                                                         const BatchDesc *__restrict__ descs,
+                                                         uint32_t *__restrict__ queue,
+                                                         uint32_t *__restrict__ done) {
+    __shared__ int64_t s_item;
+    __shared__ int s_req;
+    __shared__ int32_t s_ia[kBatchMaxTileRows];
+    __shared__ int32_t s_ib[kBatchMaxTileRows];
+    const int64_t total_items = hdr->total_items;
+    const int n_desc = hdr->n_desc;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const int64_t item = (int64_t)atomicAdd(queue, 1u);
+            s_item = item;
+            int r = -1;
+            if (item < total_items) {
+                int lo = 0, hi = n_desc - 1;  // last descriptor with item_start <= item
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (descs[mid].item_start <= item) lo = mid;
+                    else hi = mid - 1;
+                }
+                r = lo;
+            }
+            s_req = r;
+        }
+        __syncthreads();
+        const int64_t item = s_item;
+        const int r = s_req;
+        if (item >= total_items) break;  // queue exhausted: uniform exit
+        const BatchDesc d = descs[r];
+        const int W = d.wa + d.wb;
+        const int64_t row0 = (item - d.item_start) * d.tile_rows;
+        const int rows = (int)min((int64_t)d.tile_rows, d.n_rows - row0);
+        for (int j = threadIdx.x; j < rows; j += kBatchThreads) {
+            int64_t ia = d.idx_a ? (int64_t)d.idx_a[row0 + j] : row0 + j;
+            ia = (ia >= 0 && ia < d.lim_a) ? ia : 0;
+            int64_t ib = 0;
+            if (d.wb > 0) {
+                ib = (int64_t)d.a[ia * d.wa + d.fk_word];
+                ib = (ib >= 0 && ib < d.lim_b) ? ib : 0;
+            }
+            s_ia[j] = (int32_t)ia;
+            s_ib[j] = (int32_t)ib;
+        }
+        __syncthreads();
+        const int total = rows * W;
+        uint32_t *o = d.out + row0 * W;
+        for (int e0 = 0; e0 < total; e0 += kBatchThreads * kBatchPer) {
+            uint32_t v[kBatchPer];
+#pragma unroll
+            for (int k = 0; k < kBatchPer; ++k) {
+                const int e = e0 + threadIdx.x + k * kBatchThreads;
+                if (e < total) {
+                    const int j = (int)__umulhi((uint32_t)e, d.magic);
+                    const int w = e - j * W;
+                    v[k] = w < d.wa ? d.a[(int64_t)s_ia[j] * d.wa + w] : d.b[(int64_t)s_ib[j] * d.wb + (w - d.wa)];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kBatchPer; ++k) {
+                const int e = e0 + threadIdx.x + k * kBatchThreads;
+                if (e < total) o[e] = v[k];
+            }
+        }
+        if (threadIdx.x == 0 && done) atomicAdd(&done[d.request], 1u);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+struct BatchRequestPlan {
+    bool direct = false;    // handled by k_batch
+    int64_t items = 0;      // work items (direct) ...
+    size_t ws_bytes = 0;    // ... or workspace of its own phase sequence
+};
+
+static dpg_status validate_request(const dpg_request &q) {
+    if (q.kind == DPG_REQ_RETRIEVE) {
+        dpg_status st = validate_records(q.n_src, q.rec_bytes, q.src, q.n > 0);
+        if (st != DPG_OK) return st;
+        if (q.n < 0 || q.n > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && (!q.rids || !q.dst)) return DPG_ERR_INVALID_ARG;
+        if (((uintptr_t)q.rids | (uintptr_t)q.dst) % 4) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && q.n_src == 0) return DPG_ERR_RID_OUT_OF_RANGE;
+        if (ranges_overlap(q.src, (size_t)q.n_src * q.rec_bytes, q.dst, (size_t)q.n * q.rec_bytes))
+            return DPG_ERR_INVALID_ARG;
+        return DPG_OK;
+    }
+    if (q.kind == DPG_REQ_FK_JOIN) {
+        if (q.n < 0 || q.n > INT32_MAX - 1 || q.n_src < 0 || q.n_src > INT32_MAX) return DPG_ERR_INVALID_ARG;
+        if (q.fact_bytes < 4 || q.fact_bytes > kMaxRecBytes || q.fact_bytes % 4) return DPG_ERR_INVALID_ARG;
+        if (q.rec_bytes < 4 || q.rec_bytes > kMaxRecBytes || q.rec_bytes % 4) return DPG_ERR_INVALID_ARG;
+        if (q.fk_offset < 0 || q.fk_offset % 4 || q.fk_offset + 4 > q.fact_bytes) return DPG_ERR_INVALID_ARG;
+        if (q.order != DPG_JOIN_FACT_ORDER && q.order != DPG_JOIN_DIM_ORDER) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && (!q.fact || !q.dst)) return DPG_ERR_INVALID_ARG;
+        if (q.n_src > 0 && !q.src) return DPG_ERR_INVALID_ARG;
+        if (((uintptr_t)q.fact | (uintptr_t)q.src | (uintptr_t)q.dst) % 4) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && q.n_src == 0) return DPG_ERR_FK_OUT_OF_RANGE;
+        const size_t ob = (size_t)q.n * (q.fact_bytes + q.rec_bytes);
+        if (ranges_overlap(q.dst, ob, q.fact, (size_t)q.n * q.fact_bytes) ||
+            ranges_overlap(q.dst, ob, q.src, (size_t)q.n_src * q.rec_bytes))
+            return DPG_ERR_INVALID_ARG;
+        return DPG_OK;
+    }
+    return DPG_ERR_INVALID_ARG;
+}
+
+static int tile_rows_for(int words) {
+    int rows = kBatchItemWords / words;
+    if (rows < 1) rows = 1;
+    if (rows > kBatchMaxTileRows) rows = kBatchMaxTileRows;
+    return rows;
+}
+
+static dpg_status plan_request(const dpg_ctx *ctx, const dpg_request &q, BatchRequestPlan *bp) {
+    *bp = BatchRequestPlan();
+    if (q.algo < DPG_ALGO_AUTO || q.algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
+    if (q.kind == DPG_REQ_RETRIEVE) {
+        RetrievePlan rp;
+        const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp);
+        if (st != DPG_OK) return st;
+        if (rp.algo == DPG_ALGO_DIRECT) {
+            bp->direct = true;
+            const int tr = tile_rows_for(q.rec_bytes / 4);
+            bp->items = (q.n + tr - 1) / tr;
+        } else {
+            bp->ws_bytes = rp.workspace;
+        }
+        return DPG_OK;
+    }
+    const size_t ws = dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
+                                                  (dpg_join_order)q.order, (dpg_algo)q.algo);
+    if (ws == 0) return DPG_ERR_INVALID_ARG;
+    RetrievePlan rp;
+    const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp);
+    if (st != DPG_OK) return st;
+    if (q.order == DPG_JOIN_FACT_ORDER && rp.algo == DPG_ALGO_DIRECT) {
+        bp->direct = true;
+        const int tr = tile_rows_for((q.fact_bytes + q.rec_bytes) / 4);
+        bp->items = (q.n + tr - 1) / tr;
+    } else {
+        bp->ws_bytes = ws;
+    }
+    return DPG_OK;
+}
+
+struct BatchLayout {
+    size_t off_hdr = 0, off_desc = 0, off_queue = 0, off_done = 0, off_req = 0;
+    std::vector<size_t> req_off;  // per request: workspace of its own phase sequence
+    size_t total = 0;
+};
+
+static BatchLayout batch_layout(int32_t n_desc_cap, int32_t n, const std::vector<BatchRequestPlan> &plans) {
+    BatchLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    L.off_hdr = take(sizeof(BatchHeader));
+    L.off_queue = take(sizeof(uint32_t));
+    L.off_desc = take((size_t)(n_desc_cap > 0 ? n_desc_cap : 1) * sizeof(BatchDesc));
+    L.off_done = take((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    L.req_off.assign(plans.size(), 0);
+    for (size_t i = 0; i < plans.size(); ++i)
+        if (!plans[i].direct && plans[i].ws_bytes) L.req_off[i] = take(plans[i].ws_bytes);
+    L.total = off;
+    return L;
+}
+
+static dpg_status plan_batch(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n,
+                             std::vector<BatchRequestPlan> *plans) {
+    if (n < 0 || (n > 0 && !reqs)) return DPG_ERR_INVALID_ARG;
+    plans->resize(n);
+    for (int32_t i = 0; i < n; ++i) {
+        dpg_status st = validate_request(reqs[i]);
+        if (st != DPG_OK) return st;
+        st = plan_request(ctx, reqs[i], &(*plans)[i]);
+        if (st != DPG_OK) return st;
+    }
+    return DPG_OK;
+}
+
+// Descriptors of the direct work, in request order.
+static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans,
+                        std::vector<BatchDesc> *descs, BatchHeader *hdr) {
+    descs->clear();
+    int64_t items = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!plans[i].direct || plans[i].items == 0) continue;
+        const dpg_request &q = reqs[i];
+        BatchDesc d{};
+        if (q.kind == DPG_REQ_RETRIEVE) {
+            d.a = (const uint32_t *)q.src;
+            d.idx_a = q.rids;
+            d.lim_a = q.n_src;
+            d.wa = q.rec_bytes / 4;
+            d.wb = 0;
+        } else {
+            d.a = (const uint32_t *)q.fact;
+            d.idx_a = nullptr;
+            d.lim_a = q.n;
+            d.b = (const uint32_t *)q.src;
+            d.lim_b = q.n_src;
+            d.wa = q.fact_bytes / 4;
+            d.wb = q.rec_bytes / 4;
+            d.fk_word = q.fk_offset / 4;
+        }
+        d.out = (uint32_t *)q.dst;
+        d.n_rows = q.n;
+        d.tile_rows = tile_rows_for(d.wa + d.wb);
+        d.magic = (uint32_t)((0x100000000ull + (uint64_t)(d.wa + d.wb) - 1) / (uint64_t)(d.wa + d.wb));
+        d.item_start = items;
+        d.request = i;
+        items += plans[i].items;
+        descs->push_back(d);
+    }
+    hdr->total_items = items;
+    hdr->n_desc = (int32_t)descs->size();
+    hdr->pad = 0;
+}
+
+static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans) {
+    double b = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        if (!plans[i].direct) continue;
+        const dpg_request &q = reqs[i];
+        const double row = q.kind == DPG_REQ_RETRIEVE ? q.rec_bytes : q.fact_bytes + q.rec_bytes;
+        b += (double)q.n * (2.0 * row + (q.kind == DPG_REQ_RETRIEVE ? 4.0 : 0.0));
+    }
+    return b;
+}
+
+static int batch_grid(const dpg_ctx *ctx) { return ctx->n_cu * 4; }
+
+static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &L, double bytes, bool with_done,
+                                      hipStream_t stream) {
+    dpg_status st = launch_fill_i32(ctx, (int32_t *)(w + L.off_queue), 1, 0, stream);
+    if (st != DPG_OK) return st;
+    ProfScope prof(ctx, K_BATCH, bytes, stream);
+    hipLaunchKernelGGL(k_batch, dim3((unsigned)batch_grid(ctx)), dim3(kBatchThreads), 0, stream,
+                       (const BatchHeader *)(w + L.off_hdr), (const BatchDesc *)(w + L.off_desc),
+                       (uint32_t *)(w + L.off_queue), with_done ? (uint32_t *)(w + L.off_done) : nullptr);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+// The phase sequences of requests not handled by k_batch.
+static dpg_status run_own_sequences(dpg_ctx *ctx, const dpg_request *reqs, int32_t n,
+                                    const std::vector<BatchRequestPlan> &plans, char *w, const BatchLayout &L,
+                                    hipStream_t stream) {
+    for (int32_t i = 0; i < n; ++i) {
+        if (plans[i].direct) continue;
+        const dpg_request &q = reqs[i];
+        dpg_status st;
+        if (q.kind == DPG_REQ_RETRIEVE)
+            st = dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w + L.req_off[i],
+                              plans[i].ws_bytes, (dpg_algo)q.algo, 0, stream);
+        else
+            st = dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
+                             (dpg_join_order)q.order, w + L.req_off[i], plans[i].ws_bytes, (dpg_algo)q.algo, 0,
+                             stream);
+        if (st != DPG_OK) return st;
+    }
+    return DPG_OK;
+}
+
+}  // namespace dpg
+
+struct dpg_batch_graph {
+    dpg_ctx *ctx = nullptr;
+    int32_t max_requests = 0;
+    char *ws = nullptr;
+    dpg::BatchLayout layout;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+using namespace dpg;
+
+extern "C" {
+
+size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n) {
+    std::vector<BatchRequestPlan> plans;
+    if (plan_batch(ctx, reqs, n, &plans) != DPG_OK) return 0;
+    return batch_layout(n, n, plans).total;
+}
+
+dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void *workspace, size_t workspace_bytes,
+                         hipStream_t stream) {
+    std::vector<BatchRequestPlan> plans;
+    dpg_status st = plan_batch(ctx, reqs, n, &plans);
+    if (st != DPG_OK) return st;
+    const BatchLayout L = batch_layout(n, n, plans);
+    if (n > 0) {
+        if (workspace_bytes < L.total) return DPG_ERR_WORKSPACE_TOO_SMALL;
+        if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
+    }
+    if (!ctx) return DPG_ERR_INVALID_ARG;
+    if (n == 0) return DPG_OK;
+    char *w = (char *)workspace;
+    std::vector<BatchDesc> descs;
+    BatchHeader hdr;
+    build_descs(reqs, n, plans, &descs, &hdr);
+    if (hdr.total_items > 0) {
+        // pageable source: the copy is staged before hipMemcpyAsync returns
+        DPG_HIP(hipMemcpyAsync(w + L.off_hdr, &hdr, sizeof(hdr), hipMemcpyHostToDevice, stream));
+        DPG_HIP(hipMemcpyAsync(w + L.off_desc, descs.data(), descs.size() * sizeof(BatchDesc),
+                               hipMemcpyHostToDevice, stream));
+        st = launch_batch_kernel(ctx, w, L, batch_bytes(reqs, n, plans), false, stream);
+        if (st != DPG_OK) return st;
+    }
+    return run_own_sequences(ctx, reqs, n, plans, w, L, stream);
+}
+
+size_t dpg_batch_graph_workspace_bytes(const dpg_ctx *ctx, int32_t max_requests) {
+    (void)ctx;
+    if (max_requests < 1) return 0;
+    std::vector<BatchRequestPlan> none;
+    return batch_layout(max_requests, max_requests, none).total;
+}
+
+dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream, dpg_batch_graph **out) {
+    if (!ctx || !out || max_requests < 1) return DPG_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::vector<BatchRequestPlan> none;
+    const BatchLayout L = batch_layout(max_requests, max_requests, none);
+    if (workspace_bytes < L.total) return DPG_ERR_WORKSPACE_TOO_SMALL;
+    if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
+    dpg_batch_graph *g = new dpg_batch_graph();
+    g->ctx = ctx;
+    g->max_requests = max_requests;
+    g->ws = (char *)workspace;
+    g->layout = L;
+    // capture [reset queue, k_batch]; profiling events are not captured
+    const bool prof = ctx->profiling;
+    ctx->profiling = false;
+    dpg_status st = DPG_OK;
+    if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) st = DPG_ERR_HIP;
+    if (st == DPG_OK) {
+        st = launch_batch_kernel(ctx, g->ws, L, 0, false, stream);
+        hipGraph_t graph = nullptr;
+        if (hipStreamEndCapture(stream, &graph) != hipSuccess) st = DPG_ERR_HIP;
+        g->graph = graph;
+        if (st == DPG_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) st = DPG_ERR_HIP;
+    }
+    ctx->profiling = prof;
+    if (st != DPG_OK) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return DPG_OK;
+}
+
+dpg_status dpg_batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream) {
+    if (!g) return DPG_ERR_INVALID_ARG;
+    if (n > g->max_requests) return DPG_ERR_INVALID_ARG;
+    std::vector<BatchRequestPlan> plans;
+    dpg_status st = plan_batch(g->ctx, reqs, n, &plans);
+    if (st != DPG_OK) return st;
+    for (int32_t i = 0; i < n; ++i)
+        if (!plans[i].direct) return DPG_ERR_UNSUPPORTED;  // graph batches carry direct work only
+    if (n == 0) return DPG_OK;
+    std::vector<BatchDesc> descs;
+    BatchHeader hdr;
+    build_descs(reqs, n, plans, &descs, &hdr);
+    DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_hdr, &hdr, sizeof(hdr), hipMemcpyHostToDevice, stream));
+    if (!descs.empty())
+        DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_desc, descs.data(), descs.size() * sizeof(BatchDesc),
+                               hipMemcpyHostToDevice, stream));
+    ProfScope prof(g->ctx, K_BATCH, batch_bytes(reqs, n, plans), stream);
+    DPG_HIP(hipGraphLaunch(g->exec, stream));
+    return DPG_OK;
+}
+
+void dpg_batch_graph_destroy(dpg_batch_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+}  // extern "C"

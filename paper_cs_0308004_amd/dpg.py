@@ -38,6 +38,26 @@ class Plan(ctypes.Structure):
                 ("ws_run_off", _SZ), ("ws_rid_run", _SZ), ("ws_internal", _SZ)]
 
 
+REQ_RETRIEVE, REQ_FK_JOIN = 0, 1
+
+
+class Request(ctypes.Structure):
+    """dpg_request: one retrieval or join of a batch."""
+    _fields_ = [("kind", _I32), ("algo", _I32), ("src", _VP), ("n_src", _I64), ("rec_bytes", _I32),
+                ("fact_bytes", _I32), ("rids", _VP), ("fact", _VP), ("n", _I64), ("fk_offset", _I32),
+                ("order", _I32), ("dst", _VP)]
+
+
+def retrieve_request(src, rids, dst, algo: int = ALGO_AUTO) -> Request:
+    return Request(REQ_RETRIEVE, algo, _addr(src), src.shape[0], _rec_bytes(src), 0, _addr(rids), None,
+                   rids.numel(), 0, 0, _addr(dst))
+
+
+def join_request(fact, dim, dst, fk_offset: int = 0, order: int = 0, algo: int = ALGO_AUTO) -> Request:
+    return Request(REQ_FK_JOIN, algo, _addr(dim), dim.shape[0], _rec_bytes(dim), _rec_bytes(fact), None,
+                   _addr(fact), fact.shape[0], fk_offset, order, _addr(dst))
+
+
 # name -> (restype, argtypes); mirrors include/dpg.h
 SIGNATURES = {
     "dpg_create": (_I32, [ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -52,6 +72,12 @@ SIGNATURES = {
     "dpg_sort_records": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_fk_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32]),
     "dpg_fk_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_batch_workspace_bytes": (_SZ, [_VP, ctypes.POINTER(Request), _I32]),
+    "dpg_batch_run": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP, _SZ, _VP]),
+    "dpg_batch_graph_workspace_bytes": (_SZ, [_VP, _I32]),
+    "dpg_batch_graph_create": (_I32, [_VP, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
+    "dpg_batch_graph_launch": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP]),
+    "dpg_batch_graph_destroy": (None, [_VP]),
     "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
     "dpg_profile_reset": (_I32, [_VP]),
     "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
@@ -210,6 +236,24 @@ class Context:
         _check(st, "dpg_fk_join")
         return out
 
+    # ---- batches -------------------------------------------------------
+    def batch_workspace_bytes(self, reqs) -> int:
+        arr = (Request * len(reqs))(*reqs)
+        return lib().dpg_batch_workspace_bytes(self.handle, arr, len(reqs))
+
+    def batch_run(self, reqs, workspace=None, stream=None):
+        import torch
+
+        arr = (Request * len(reqs))(*reqs)
+        if workspace is None:
+            need = lib().dpg_batch_workspace_bytes(self.handle, arr, len(reqs))
+            if need == 0 and len(reqs):
+                raise DPGError(ERR_INVALID_ARG, "dpg_batch_workspace_bytes")
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        _check(lib().dpg_batch_run(self.handle, arr, len(reqs), _addr(workspace), workspace.numel(),
+                                   _stream(stream)), "dpg_batch_run")
+        return workspace
+
     # ---- profiling -----------------------------------------------------
     def profile_enable(self, on: bool = True):
         _check(lib().dpg_profile_enable(self.handle, int(on)), "dpg_profile_enable")
@@ -235,3 +279,32 @@ def plan_retrieve(n_src: int, rec_bytes: int, n_rids: int, algo: int = ALGO_AUTO
     _check(lib().dpg_plan_retrieve(ctx.handle if ctx else None, n_src, rec_bytes, n_rids, algo, ctypes.byref(p)),
            "dpg_plan_retrieve")
     return p
+
+
+class BatchGraph:
+    """A captured persistent-batch launch bound to its own workspace."""
+
+    def __init__(self, ctx: Context, max_requests: int, stream):
+        import torch
+
+        need = lib().dpg_batch_graph_workspace_bytes(ctx.handle, max_requests)
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        h = _VP()
+        _check(lib().dpg_batch_graph_create(ctx.handle, max_requests, _addr(self.workspace), need, _stream(stream),
+                                            ctypes.byref(h)), "dpg_batch_graph_create")
+        self.handle = h
+
+    def launch(self, reqs, stream):
+        arr = (Request * len(reqs))(*reqs)
+        _check(lib().dpg_batch_graph_launch(self.handle, arr, len(reqs), _stream(stream)), "dpg_batch_graph_launch")
+
+    def close(self):
+        if self.handle:
+            lib().dpg_batch_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

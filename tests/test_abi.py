@@ -110,3 +110,29 @@ def test_options_need_context():
     assert lib.dpg_set_option(None, dpg.OPT_LOG2_RUN, 3) == dpg.ERR_INVALID_ARG
     v = ctypes.c_int64()
     assert lib.dpg_get_option(None, dpg.OPT_LOG2_RUN, ctypes.byref(v)) == dpg.ERR_INVALID_ARG
+
+
+def test_batch_validation_without_device():
+    lib = dpg.lib()
+    good = dpg.Request(dpg.REQ_RETRIEVE, dpg.ALGO_DIRECT, SRC, 100, 16, 0, RIDS, None, 10, 0, 0, DST)
+    join = dpg.Request(dpg.REQ_FK_JOIN, dpg.ALGO_DIRECT, SRC, 100, 64, 16, None, RIDS, 10, 0, 0, DST)
+    arr = (dpg.Request * 2)(good, join)
+    need = lib.dpg_batch_workspace_bytes(None, arr, 2)
+    assert need > 0
+    assert lib.dpg_batch_run(None, arr, 2, WS, need, None) == dpg.ERR_INVALID_ARG  # no context
+    assert lib.dpg_batch_run(None, arr, 2, WS, need - 1, None) == dpg.ERR_WORKSPACE_TOO_SMALL
+    bad = dpg.Request.from_buffer_copy(good)
+    bad.rec_bytes = 6
+    arr2 = (dpg.Request * 2)(good, bad)
+    assert lib.dpg_batch_workspace_bytes(None, arr2, 2) == 0
+    assert lib.dpg_batch_run(None, arr2, 2, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
+    bad = dpg.Request.from_buffer_copy(join)
+    bad.fk_offset = 14
+    arr3 = (dpg.Request * 1)(bad)
+    assert lib.dpg_batch_run(None, arr3, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
+    bad = dpg.Request.from_buffer_copy(good)
+    bad.kind = 5
+    arr4 = (dpg.Request * 1)(bad)
+    assert lib.dpg_batch_run(None, arr4, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
+    assert lib.dpg_batch_graph_workspace_bytes(None, 0) == 0
+    assert lib.dpg_batch_graph_workspace_bytes(None, 16) > 0

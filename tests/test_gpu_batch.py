@@ -1,0 +1,126 @@
+"""Batches: many retrieval and join requests of uneven size in one call (one
+persistent launch for the direct work), and the captured-graph variant.  Every
+request's output must equal the same request run alone, and the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_cs_0308004_amd import dpg, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dpg.Context(0)
+    yield c
+    c.close()
+
+
+def make_mix(n_req, seed, kinds=("retrieve", "join"), algos=(dpg.ALGO_DIRECT, dpg.ALGO_DPG, dpg.ALGO_AUTO),
+             orders=(0, 1), max_log2=16):
+    """Requests with log-uniform sizes and record sizes from {16, 64, 100, 256}."""
+    rng = np.random.default_rng(seed)
+    reqs, keep, expects = [], [], []
+    for k in range(n_req):
+        kind = kinds[rng.integers(0, len(kinds))]
+        algo = int(algos[rng.integers(0, len(algos))])
+        n = int(np.exp(rng.uniform(np.log(1), np.log(1 << max_log2))))
+        if kind == "retrieve":
+            rec = int(rng.choice([16, 64, 100, 256]))
+            n_src = max(1, int(n * rng.uniform(0.5, 2.0)))
+            src = synth.record_bytes(n_src, rec, seed=seed * 1000 + k)
+            rids = synth.rids_uniform(n_src, n, seed=seed * 1000 + k)
+            expects.append(oracle.retrieve(src, rids))
+            s_t, r_t = torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV)
+            dst = torch.empty((n, rec), dtype=torch.uint8, device=DEV)
+            reqs.append(dpg.retrieve_request(s_t, r_t, dst, algo))
+            keep.append((s_t, r_t, dst))
+        else:
+            order = int(orders[rng.integers(0, len(orders))])
+            n_dim = max(1, n // 8)
+            fact = synth.fact_table(n, n_dim, 0.8, seed=seed * 1000 + k)
+            dim = synth.dim_table(n_dim, seed=seed * 1000 + k)
+            fn = oracle.fk_join_fact_order if order == 0 else oracle.fk_join_dim_order
+            expects.append(fn(fact, dim, 0))
+            f_t, d_t = torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV)
+            dst = torch.empty((n, 80), dtype=torch.uint8, device=DEV)
+            reqs.append(dpg.join_request(f_t, d_t, dst, 0, order, algo))
+            keep.append((f_t, d_t, dst))
+    return reqs, keep, expects
+
+
+def test_batch_matches_alone_and_oracle(ctx):
+    reqs, keep, expects = make_mix(120, seed=7)
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    batched = [k[2].clone() for k in keep]
+    for k, want in zip(keep, expects):
+        assert np.array_equal(k[2].cpu().numpy(), want)
+    # each request alone, through the single-request entry points
+    for q, k, got in zip(reqs, keep, batched):
+        k[2].fill_(0)
+        if q.kind == dpg.REQ_RETRIEVE:
+            ctx.retrieve(k[0], k[1], dst=k[2], algo=q.algo)
+        else:
+            ctx.fk_join(k[0], k[1], 0, q.order, out=k[2], algo=q.algo)
+        torch.cuda.synchronize()
+        assert torch.equal(k[2], got)
+
+
+def test_batch_single_and_empty(ctx):
+    reqs, keep, expects = make_mix(1, seed=3, kinds=("retrieve",))
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    assert np.array_equal(keep[0][2].cpu().numpy(), expects[0])
+    ctx.batch_run([])
+
+
+def test_batch_rejects_invalid_request(ctx):
+    reqs, keep, _ = make_mix(5, seed=4, kinds=("retrieve",))
+    bad = list(reqs)
+    q = dpg.Request.from_buffer_copy(bad[2])
+    q.rec_bytes = 6
+    bad[2] = q
+    for k in keep:
+        k[2].fill_(3)
+    with pytest.raises(dpg.DPGError) as e:
+        ctx.batch_run(bad, workspace=torch.empty(1 << 20, dtype=torch.uint8, device=DEV))
+    assert e.value.status == dpg.ERR_INVALID_ARG
+    torch.cuda.synchronize()
+    for k in keep:
+        assert bool((k[2] == 3).all())
+
+
+def test_graph_replays_match_eager(ctx):
+    stream = torch.cuda.Stream()
+    graph = dpg.BatchGraph(ctx, 256, stream)
+    for round_, (n_req, seed) in enumerate([(200, 11), (37, 12), (200, 11), (5, 13)]):
+        reqs, keep, expects = make_mix(n_req, seed, algos=(dpg.ALGO_DIRECT, dpg.ALGO_AUTO), orders=(0,))
+        torch.cuda.synchronize()  # inputs were uploaded on the default stream
+        with torch.cuda.stream(stream):
+            graph.launch(reqs, stream)
+        stream.synchronize()
+        for k, want in zip(keep, expects):
+            assert np.array_equal(k[2].cpu().numpy(), want), f"replay {round_}"
+        # eager work of the program's own between replays
+        x = torch.randn(1 << 20, device=DEV)
+        torch.cuda.synchronize()
+        assert float(x.abs().sum()) > 0
+    # DPG-planned requests are not graph work
+    reqs, keep, _ = make_mix(3, seed=14, algos=(dpg.ALGO_DPG,), kinds=("retrieve",))
+    with pytest.raises(dpg.DPGError) as e:
+        graph.launch(reqs, stream)
+    assert e.value.status == dpg.ERR_UNSUPPORTED
+    graph.close()
+
+
+def test_batch_large_mixed_sizes(ctx):
+    """A batch shaped like the serving workload: sizes up to 2^22 records."""
+    reqs, keep, expects = make_mix(12, seed=21, kinds=("retrieve",), algos=(dpg.ALGO_AUTO,), max_log2=22)
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    for k, want in zip(keep, expects):
+        assert np.array_equal(k[2].cpu().numpy(), want)
