@@ -226,6 +226,78 @@ dpg_status dpg_batch_graph_launch(dpg_batch_graph *graph, const dpg_request *req
 void dpg_batch_graph_destroy(dpg_batch_graph *graph);
 
 /* ------------------------------------------------------------------------- */
+/* Device-memory arena: first-fit allocator with coalescing over an address   */
+/* range the caller owns.  Host bookkeeping only (never touches the memory).  */
+/* The serving engine carves request outputs and workspaces out of one.       */
+/* ------------------------------------------------------------------------- */
+typedef struct dpg_arena dpg_arena;
+/* align: power of two dividing base. */
+dpg_status dpg_arena_create(uintptr_t base, size_t bytes, size_t align, dpg_arena **out);
+/* DPG_ERR_BUSY when no free block is large enough. */
+dpg_status dpg_arena_alloc(dpg_arena *arena, size_t bytes, uintptr_t *addr);
+/* DPG_ERR_INVALID_ARG for an address the arena did not hand out (or freed). */
+dpg_status dpg_arena_free(dpg_arena *arena, uintptr_t addr);
+dpg_status dpg_arena_stats(const dpg_arena *arena, size_t *in_use, size_t *high_water,
+                           size_t *largest_free, size_t *free_blocks);
+void dpg_arena_destroy(dpg_arena *arena);
+
+/* ------------------------------------------------------------------------- */
+/* Serving: continuous batching under an HBM budget.  A scheduler thread      */
+/* admits submitted requests in arrival order while their output (plus, for   */
+/* requests that run on their own, their workspace) fits the arena, and      */
+/* launches admitted requests on the first free stream slot: consecutive     */
+/* direct-work requests together as one persistent batch launch (a graph     */
+/* replay with use_graph), others alone.  Requests arriving while batches run */
+/* are admitted and launched on the next free slot, so their work overlaps on */
+/* the device.  With max_batch_requests = 1 every request is launched alone   */
+/* through its single-request entry point (the per-request baseline).        */
+/* While a server exists its scheduler thread owns the context: do not use   */
+/* the context from other threads.                                           */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    void *arena;                 /* device memory the server may use (the budget) */
+    size_t arena_bytes;
+    int32_t max_inflight;        /* stream slots, 1..16 */
+    int32_t max_batch_requests;  /* requests per launch; 1 = per-request launches */
+    int32_t use_graph;           /* 1: replay a captured batch graph per launch */
+    int32_t reserved;
+} dpg_server_config;
+
+typedef enum {
+    DPG_TICKET_QUEUED = 0,   /* waiting for memory */
+    DPG_TICKET_ADMITTED = 1, /* memory reserved, waiting for a slot */
+    DPG_TICKET_RUNNING = 2,
+    DPG_TICKET_DONE = 3,     /* output ready until released */
+    DPG_TICKET_FAILED = 4    /* status says why (DPG_ERR_BUSY: larger than the budget) */
+} dpg_ticket_state;
+
+typedef struct {
+    int64_t submitted, completed, failed, batches;
+    double p50_ms, p99_ms, max_ms, mean_ms;  /* submit -> completion, completed requests */
+    double bytes_delivered;                  /* output bytes of completed requests */
+    double span_s;                           /* first submit -> last completion */
+    size_t arena_in_use, arena_high_water;
+} dpg_server_stats;
+
+typedef struct dpg_server dpg_server;
+dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_server **out);
+/* Queue a request (its dst is ignored: the output is allocated in the arena at
+ * admission).  Invalid requests are accepted as FAILED tickets. */
+dpg_status dpg_server_submit(dpg_server *server, const dpg_request *req, uint64_t *ticket);
+/* *dst: device address of the output once DONE (valid until released). */
+dpg_status dpg_server_poll(dpg_server *server, uint64_t ticket, int32_t *state, dpg_status *status,
+                           void **dst, double *latency_ms);
+/* Next finished (DONE or FAILED) ticket in completion order; waits up to
+ * timeout_ms; DPG_ERR_BUSY if none finished in that time. */
+dpg_status dpg_server_next_completed(dpg_server *server, int32_t timeout_ms, uint64_t *ticket);
+/* Free a finished ticket and its output memory. */
+dpg_status dpg_server_release(dpg_server *server, uint64_t ticket);
+dpg_status dpg_server_stats_get(dpg_server *server, dpg_server_stats *out);
+dpg_status dpg_server_reset_stats(dpg_server *server);
+/* Finishes all submitted work, then frees the server (not the arena). */
+void dpg_server_destroy(dpg_server *server);
+
+/* ------------------------------------------------------------------------- */
 /* Per-kernel timing.  When enabled, every kernel the context launches is     */
 /* bracketed by HIP events on its own stream, and its algorithmic bytes (what */
 /* the algorithm must read and write, excluding cache effects) are recorded.  */

@@ -322,6 +322,20 @@ static dpg_status run_own_sequences(dpg_ctx *ctx, const dpg_request *reqs, int32
     return DPG_OK;
 }
 
+dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, bool *direct, size_t *own_ws) {
+    dpg_status st = validate_request(q);
+    if (st != DPG_OK) return st;
+    BatchRequestPlan bp;
+    st = plan_request(ctx, q, &bp);
+    if (st != DPG_OK) return st;
+    *direct = bp.direct;
+    *own_ws = q.kind == DPG_REQ_RETRIEVE
+                  ? dpg_retrieve_workspace_bytes(ctx, q.n_src, q.rec_bytes, q.n, (dpg_algo)q.algo)
+                  : dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
+                                                (dpg_join_order)q.order, (dpg_algo)q.algo);
+    return *own_ws > 0 || q.n == 0 ? DPG_OK : DPG_ERR_INVALID_ARG;
+}
+
 }  // namespace dpg
 
 struct dpg_batch_graph {

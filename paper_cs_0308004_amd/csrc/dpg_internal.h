@@ -183,4 +183,9 @@ dpg_status launch_probe_lds(dpg_ctx *ctx, const RetrievePlan &p, const void *src
 
 int xcd_remap_flag(const dpg_ctx *ctx);
 
+// Validate one batch request and tell whether a batch would run it as direct
+// work inside the persistent launch; *own_ws is the workspace it needs when run
+// through its single-request entry point.
+dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, bool *direct, size_t *own_ws);
+
 }  // namespace dpg

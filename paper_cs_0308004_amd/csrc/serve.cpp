@@ -1,0 +1,540 @@
+// Serving engine: continuous batching of retrieval / join requests under an
+// HBM budget.
+//
+//   * Arena: the caller hands the server one device region (the budget); a
+//     first-fit allocator with coalescing carves request outputs and batch
+//     workspaces out of it, so admission accounts for every byte the server
+//     uses.
+//   * Admission: requests are admitted in arrival order (head-of-line order,
+//     no overtaking) while their output -- and, for requests that run on
+//     their own, their workspace -- fits the arena; a request larger than the
+//     whole arena fails at once.  Batches of direct work use a descriptor
+//     workspace each slot owns, so launching never allocates.
+//   * Batching: whenever one of the `max_inflight` stream slots is free, the
+//     run of direct-work requests at the head of the admitted queue (up to
+//     max_batch_requests) is launched there as one persistent batch -- a
+//     replay of the slot's captured graph, or dpg_batch_run -- and any other
+//     request alone through its single-request entry point.  With batches of
+//     one, every request takes that path (the per-request baseline).
+//     Requests arriving while batches run are admitted and launched on the
+//     next free slot, so their work overlaps on the device.
+//   * Completion: a batch's event marks all its requests done; their latency
+//     is completion time minus submit time (host steady clock).  Outputs stay
+//     valid until released.
+// One scheduler thread owns the context and all HIP calls.
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "dpg_internal.h"
+
+namespace dpg {
+
+using Clock = std::chrono::steady_clock;
+
+// First-fit allocator over [0, size) with coalescing; offsets are aligned.
+class Arena {
+   public:
+    Arena(size_t size, size_t align) : size_(size), align_(align) {
+        if (size_ > 0) free_[0] = size_;
+    }
+    // returns false when no free block fits
+    bool alloc(size_t bytes, size_t *off) {
+        const size_t need = align_up(bytes ? bytes : 1, align_);
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= need) {
+                *off = it->first;
+                const size_t rest = it->second - need;
+                const size_t at = it->first;
+                free_.erase(it);
+                if (rest) free_[at + need] = rest;
+                used_[at] = need;
+                in_use_ += need;
+                high_water_ = std::max(high_water_, in_use_);
+                return true;
+            }
+        }
+        return false;
+    }
+    bool release(size_t off) {
+        auto u = used_.find(off);
+        if (u == used_.end()) return false;
+        size_t start = off, len = u->second;
+        in_use_ -= len;
+        used_.erase(u);
+        auto next = free_.lower_bound(start);
+        if (next != free_.end() && start + len == next->first) {
+            len += next->second;
+            next = free_.erase(next);
+        }
+        if (next != free_.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == start) {
+                start = prev->first;
+                len += prev->second;
+                free_.erase(prev);
+            }
+        }
+        free_[start] = len;
+        return true;
+    }
+    size_t size() const { return size_; }
+    size_t in_use() const { return in_use_; }
+    size_t high_water() const { return high_water_; }
+    size_t largest_free() const {
+        size_t m = 0;
+        for (auto &f : free_) m = std::max(m, f.second);
+        return m;
+    }
+    size_t free_blocks() const { return free_.size(); }
+
+   private:
+    size_t size_, align_;
+    size_t in_use_ = 0, high_water_ = 0;
+    std::map<size_t, size_t> free_;  // offset -> length
+    std::map<size_t, size_t> used_;  // offset -> length
+};
+
+}  // namespace dpg
+
+struct dpg_arena {
+    dpg::Arena arena;
+    uintptr_t base;
+    dpg_arena(uintptr_t b, size_t size, size_t align) : arena(size, align), base(b) {}
+};
+
+namespace dpg {
+
+enum TicketState { T_QUEUED = 0, T_ADMITTED = 1, T_RUNNING = 2, T_DONE = 3, T_FAILED = 4 };
+
+struct Ticket {
+    dpg_request req{};
+    int state = T_QUEUED;
+    dpg_status status = DPG_OK;
+    bool batched = false;          // runs inside a slot's persistent batch launch
+    size_t out_off = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0;
+    bool has_out = false, has_ws = false;
+    Clock::time_point submit, done;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t event = nullptr;
+    bool busy = false;
+    std::vector<uint64_t> tickets;
+    dpg_batch_graph *graph = nullptr;
+    size_t batch_ws_off = 0, batch_ws_bytes = 0;  // descriptors of a batch of direct work
+};
+
+static size_t output_bytes(const dpg_request &q) {
+    const int64_t row = q.kind == DPG_REQ_RETRIEVE ? q.rec_bytes : (int64_t)q.fact_bytes + q.rec_bytes;
+    return (size_t)(q.n > 0 ? q.n : 0) * (size_t)(row > 0 ? row : 0);
+}
+
+}  // namespace dpg
+
+struct dpg_server {
+    dpg_ctx *ctx = nullptr;
+    dpg_server_config cfg{};
+    dpg::Arena *arena = nullptr;
+    char *base = nullptr;
+    std::vector<dpg::Slot> slots;
+    std::mutex mu;
+    std::condition_variable cv, done_cv;
+    std::unordered_map<uint64_t, dpg::Ticket> tickets;
+    std::deque<uint64_t> pending;   // submitted, not admitted
+    std::deque<uint64_t> admitted;  // output reserved, waiting for a slot
+    std::deque<uint64_t> completed; // finished, not yet reported by next_completed
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread thread;
+    dpg_status fatal = DPG_OK;
+    // statistics
+    std::vector<double> latencies_ms;
+    int64_t submitted = 0, n_completed = 0, n_failed = 0, batches = 0;
+    double bytes_delivered = 0;
+    dpg::Clock::time_point first_submit, last_done;
+    bool any_submit = false;
+};
+
+namespace dpg {
+
+static void finish_batch(dpg_server *s, Slot &sl, dpg_status st) {
+    const auto now = Clock::now();
+    for (uint64_t t : sl.tickets) {
+        auto it = s->tickets.find(t);
+        if (it == s->tickets.end()) continue;
+        Ticket &tk = it->second;
+        tk.done = now;
+        if (tk.has_ws) s->arena->release(tk.ws_off);
+        tk.has_ws = false;
+        if (st == DPG_OK) {
+            tk.state = T_DONE;
+            s->n_completed++;
+            s->bytes_delivered += (double)tk.out_bytes;
+            s->latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - tk.submit).count());
+        } else {
+            tk.state = T_FAILED;
+            tk.status = st;
+            s->n_failed++;
+        }
+        s->completed.push_back(t);
+    }
+    s->last_done = now;
+    sl.tickets.clear();
+    sl.busy = false;
+}
+
+// Launch `batch` on the slot: batched tickets together in one persistent
+// launch (graph replay when available), or one unbatched ticket through its
+// single-request entry point with the workspace reserved at admission.
+static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> &batch) {
+    dpg_ctx *ctx = s->ctx;
+    dpg_status st = DPG_OK;
+    const Ticket &first = s->tickets[batch[0]];
+    if (!first.batched) {
+        const dpg_request &q = first.req;
+        char *w = first.has_ws ? s->base + first.ws_off : nullptr;
+        st = q.kind == DPG_REQ_RETRIEVE
+                 ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w, first.ws_bytes,
+                                (dpg_algo)q.algo, 0, sl.stream)
+                 : dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
+                               (dpg_join_order)q.order, w, first.ws_bytes, (dpg_algo)q.algo, 0, sl.stream);
+    } else {
+        std::vector<dpg_request> reqs;
+        reqs.reserve(batch.size());
+        for (uint64_t t : batch) reqs.push_back(s->tickets[t].req);
+        const int32_t n = (int32_t)reqs.size();
+        if (sl.graph)
+            st = dpg_batch_graph_launch(sl.graph, reqs.data(), n, sl.stream);
+        else
+            st = dpg_batch_run(ctx, reqs.data(), n, s->base + sl.batch_ws_off, sl.batch_ws_bytes, sl.stream);
+    }
+    if (st != DPG_OK) return st;
+    if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
+    sl.tickets = batch;
+    sl.busy = true;
+    s->batches++;
+    for (uint64_t t : batch) s->tickets[t].state = T_RUNNING;
+    return DPG_OK;
+}
+
+static void scheduler(dpg_server *s) {
+    (void)hipSetDevice(s->ctx->device);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        bool changed = false;
+        // 1. completions
+        for (Slot &sl : s->slots) {
+            if (!sl.busy) continue;
+            const hipError_t q = hipEventQuery(sl.event);
+            if (q == hipSuccess) {
+                finish_batch(s, sl, DPG_OK);
+                changed = true;
+            } else if (q != hipErrorNotReady) {
+                finish_batch(s, sl, DPG_ERR_HIP);
+                changed = true;
+            }
+        }
+        // 2. admission, in arrival order: reserve the output and, for work
+        //    that runs on its own, its workspace
+        while (!s->pending.empty()) {
+            const uint64_t t = s->pending.front();
+            Ticket &tk = s->tickets[t];
+            if (tk.out_bytes + tk.ws_bytes > s->arena->size()) {
+                tk.state = T_FAILED;
+                tk.status = DPG_ERR_BUSY;
+                s->n_failed++;
+                s->completed.push_back(t);
+                s->pending.pop_front();
+                changed = true;
+                continue;
+            }
+            if (tk.out_bytes > 0) {
+                if (!s->arena->alloc(tk.out_bytes, &tk.out_off)) break;
+                tk.has_out = true;
+            }
+            if (tk.ws_bytes > 0) {
+                if (!s->arena->alloc(tk.ws_bytes, &tk.ws_off)) {
+                    if (tk.has_out) s->arena->release(tk.out_off);
+                    tk.has_out = false;
+                    break;
+                }
+                tk.has_ws = true;
+            }
+            tk.req.dst = tk.has_out ? s->base + tk.out_off : nullptr;
+            tk.state = T_ADMITTED;
+            s->admitted.push_back(t);
+            s->pending.pop_front();
+            changed = true;
+        }
+        // 3. launches on free slots: the run of batched tickets at the head
+        //    (up to max_batch_requests), or the single unbatched head ticket
+        for (Slot &sl : s->slots) {
+            if (sl.busy || s->admitted.empty()) continue;
+            std::vector<uint64_t> batch;
+            const bool batched = s->tickets[s->admitted.front()].batched;
+            while (!s->admitted.empty() && (int32_t)batch.size() < s->cfg.max_batch_requests &&
+                   s->tickets[s->admitted.front()].batched == batched) {
+                batch.push_back(s->admitted.front());
+                s->admitted.pop_front();
+                if (!batched) break;
+            }
+            const dpg_status st = launch_on_slot(s, sl, batch);
+            if (st != DPG_OK) {
+                sl.tickets = batch;
+                finish_batch(s, sl, st);
+            }
+            changed = true;
+        }
+        if (changed) s->done_cv.notify_all();
+        bool inflight = false;
+        for (Slot &sl : s->slots) inflight |= sl.busy;
+        if (s->stop && !inflight && s->pending.empty() && s->admitted.empty()) break;
+        if (inflight) {
+            // work on the device: poll its events again shortly
+            lk.unlock();
+            std::this_thread::yield();
+            lk.lock();
+        } else if (!changed) {
+            s->cv.wait_for(lk, std::chrono::milliseconds(5));
+        }
+    }
+}
+
+static double percentile(std::vector<double> v, double p) {
+    if (v.empty()) return 0;
+    std::sort(v.begin(), v.end());
+    const double pos = p * (double)(v.size() - 1);
+    const size_t lo = (size_t)pos;
+    const size_t hi = std::min(lo + 1, v.size() - 1);
+    return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
+}  // namespace dpg
+
+using namespace dpg;
+
+extern "C" {
+
+dpg_status dpg_arena_create(uintptr_t base, size_t bytes, size_t align, dpg_arena **out) {
+    if (!out || align == 0 || (align & (align - 1)) || base % align) return DPG_ERR_INVALID_ARG;
+    *out = new dpg_arena(base, bytes, align);
+    return DPG_OK;
+}
+
+dpg_status dpg_arena_alloc(dpg_arena *a, size_t bytes, uintptr_t *addr) {
+    if (!a || !addr) return DPG_ERR_INVALID_ARG;
+    size_t off = 0;
+    if (!a->arena.alloc(bytes, &off)) return DPG_ERR_BUSY;
+    *addr = a->base + off;
+    return DPG_OK;
+}
+
+dpg_status dpg_arena_free(dpg_arena *a, uintptr_t addr) {
+    if (!a || addr < a->base) return DPG_ERR_INVALID_ARG;
+    return a->arena.release(addr - a->base) ? DPG_OK : DPG_ERR_INVALID_ARG;
+}
+
+dpg_status dpg_arena_stats(const dpg_arena *a, size_t *in_use, size_t *high_water, size_t *largest_free,
+                           size_t *free_blocks) {
+    if (!a) return DPG_ERR_INVALID_ARG;
+    if (in_use) *in_use = a->arena.in_use();
+    if (high_water) *high_water = a->arena.high_water();
+    if (largest_free) *largest_free = a->arena.largest_free();
+    if (free_blocks) *free_blocks = a->arena.free_blocks();
+    return DPG_OK;
+}
+
+void dpg_arena_destroy(dpg_arena *a) { delete a; }
+
+dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_server **out) {
+    if (!ctx || !cfg || !out) return DPG_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (!cfg->arena || cfg->arena_bytes < kAlign || ((uintptr_t)cfg->arena) % kAlign) return DPG_ERR_INVALID_ARG;
+    if (cfg->max_inflight < 1 || cfg->max_inflight > 16 || cfg->max_batch_requests < 1) return DPG_ERR_INVALID_ARG;
+    dpg_server *s = new dpg_server();
+    s->ctx = ctx;
+    s->cfg = *cfg;
+    s->base = (char *)cfg->arena;
+    s->arena = new Arena(cfg->arena_bytes, kAlign);
+    s->slots.resize(cfg->max_inflight);
+    dpg_status st = DPG_OK;
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    if (hipSetDevice(ctx->device) != hipSuccess) st = DPG_ERR_HIP;
+    for (Slot &sl : s->slots) {
+        if (st != DPG_OK) break;
+        if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&sl.event, hipEventDisableTiming) != hipSuccess) {
+            st = DPG_ERR_HIP;
+            break;
+        }
+        if (cfg->max_batch_requests > 1) {
+            sl.batch_ws_bytes = dpg_batch_graph_workspace_bytes(ctx, cfg->max_batch_requests);
+            if (!s->arena->alloc(sl.batch_ws_bytes, &sl.batch_ws_off)) {
+                st = DPG_ERR_WORKSPACE_TOO_SMALL;
+                break;
+            }
+            if (cfg->use_graph)
+                st = dpg_batch_graph_create(ctx, cfg->max_batch_requests, s->base + sl.batch_ws_off,
+                                            sl.batch_ws_bytes, sl.stream, &sl.graph);
+        }
+    }
+    (void)hipSetDevice(prev);
+    if (st != DPG_OK) {
+        for (Slot &sl : s->slots) {
+            if (sl.graph) dpg_batch_graph_destroy(sl.graph);
+            if (sl.event) (void)hipEventDestroy(sl.event);
+            if (sl.stream) (void)hipStreamDestroy(sl.stream);
+        }
+        delete s->arena;
+        delete s;
+        return st;
+    }
+    s->thread = std::thread(scheduler, s);
+    *out = s;
+    return DPG_OK;
+}
+
+dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ticket) {
+    if (!s || !req || !ticket) return DPG_ERR_INVALID_ARG;
+    Ticket tk;
+    tk.req = *req;
+    tk.req.dst = nullptr;
+    tk.out_bytes = output_bytes(*req);
+    tk.submit = Clock::now();
+    bool direct = false;
+    size_t own_ws = 0;
+    // the output will live in the arena: validate against the arena's address
+    tk.req.dst = s->base;
+    tk.status = plan_batch_request(s->ctx, tk.req, &direct, &own_ws);
+    tk.req.dst = nullptr;
+    if (tk.status == DPG_OK) {
+        tk.batched = direct && s->cfg.max_batch_requests > 1;
+        tk.ws_bytes = tk.batched ? 0 : own_ws;
+    } else {
+        tk.state = T_FAILED;
+    }
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) return DPG_ERR_INVALID_ARG;
+        *ticket = s->next_ticket++;
+        if (!s->any_submit) {
+            s->first_submit = tk.submit;
+            s->any_submit = true;
+        }
+        s->submitted++;
+        const bool failed = tk.state == T_FAILED;
+        if (failed) {
+            tk.done = tk.submit;
+            s->n_failed++;
+        }
+        s->tickets.emplace(*ticket, tk);
+        if (failed) s->completed.push_back(*ticket);
+        else s->pending.push_back(*ticket);
+    }
+    s->cv.notify_one();
+    return DPG_OK;
+}
+
+dpg_status dpg_server_poll(dpg_server *s, uint64_t ticket, int32_t *state, dpg_status *status, void **dst,
+                           double *latency_ms) {
+    if (!s) return DPG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return DPG_ERR_INVALID_ARG;
+    const Ticket &tk = it->second;
+    if (state) *state = tk.state;
+    if (status) *status = tk.status;
+    if (dst) *dst = tk.state == T_DONE ? tk.req.dst : nullptr;
+    if (latency_ms)
+        *latency_ms = tk.state >= T_DONE ? std::chrono::duration<double, std::milli>(tk.done - tk.submit).count() : 0;
+    return DPG_OK;
+}
+
+dpg_status dpg_server_next_completed(dpg_server *s, int32_t timeout_ms, uint64_t *ticket) {
+    if (!s || !ticket) return DPG_ERR_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(s->mu);
+    const auto deadline = Clock::now() + std::chrono::milliseconds(timeout_ms > 0 ? timeout_ms : 0);
+    while (s->completed.empty()) {
+        if (timeout_ms <= 0 || s->done_cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            if (s->completed.empty()) return DPG_ERR_BUSY;
+        }
+    }
+    *ticket = s->completed.front();
+    s->completed.pop_front();
+    return DPG_OK;
+}
+
+dpg_status dpg_server_release(dpg_server *s, uint64_t ticket) {
+    if (!s) return DPG_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        auto it = s->tickets.find(ticket);
+        if (it == s->tickets.end()) return DPG_ERR_INVALID_ARG;
+        if (it->second.state < T_DONE) return DPG_ERR_BUSY;
+        if (it->second.has_out) s->arena->release(it->second.out_off);
+        s->tickets.erase(it);
+    }
+    s->cv.notify_one();
+    return DPG_OK;
+}
+
+dpg_status dpg_server_stats_get(dpg_server *s, dpg_server_stats *out) {
+    if (!s || !out) return DPG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = dpg_server_stats{};
+    out->submitted = s->submitted;
+    out->completed = s->n_completed;
+    out->failed = s->n_failed;
+    out->batches = s->batches;
+    out->p50_ms = percentile(s->latencies_ms, 0.50);
+    out->p99_ms = percentile(s->latencies_ms, 0.99);
+    out->max_ms = s->latencies_ms.empty() ? 0 : *std::max_element(s->latencies_ms.begin(), s->latencies_ms.end());
+    double sum = 0;
+    for (double v : s->latencies_ms) sum += v;
+    out->mean_ms = s->latencies_ms.empty() ? 0 : sum / (double)s->latencies_ms.size();
+    out->bytes_delivered = s->bytes_delivered;
+    out->span_s = s->any_submit && s->n_completed
+                      ? std::chrono::duration<double>(s->last_done - s->first_submit).count()
+                      : 0;
+    out->arena_in_use = s->arena->in_use();
+    out->arena_high_water = s->arena->high_water();
+    return DPG_OK;
+}
+
+dpg_status dpg_server_reset_stats(dpg_server *s) {
+    if (!s) return DPG_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> g(s->mu);
+    s->latencies_ms.clear();
+    s->submitted = s->n_completed = s->n_failed = s->batches = 0;
+    s->bytes_delivered = 0;
+    s->any_submit = false;
+    return DPG_OK;
+}
+
+void dpg_server_destroy(dpg_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+    }
+    s->cv.notify_all();
+    if (s->thread.joinable()) s->thread.join();
+    for (Slot &sl : s->slots) {
+        if (sl.graph) dpg_batch_graph_destroy(sl.graph);
+        if (sl.event) (void)hipEventDestroy(sl.event);
+        if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    }
+    delete s->arena;
+    delete s;
+}
+
+}  // extern "C"

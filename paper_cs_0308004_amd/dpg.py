@@ -58,6 +58,23 @@ def join_request(fact, dim, dst, fk_offset: int = 0, order: int = 0, algo: int =
                    _addr(fact), fact.shape[0], fk_offset, order, _addr(dst))
 
 
+TICKET_QUEUED, TICKET_ADMITTED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED = 0, 1, 2, 3, 4
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("arena", _VP), ("arena_bytes", _SZ), ("max_inflight", _I32), ("max_batch_requests", _I32),
+                ("use_graph", _I32), ("reserved", _I32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", _I64), ("completed", _I64), ("failed", _I64), ("batches", _I64),
+                ("p50_ms", _DBL), ("p99_ms", _DBL), ("max_ms", _DBL), ("mean_ms", _DBL),
+                ("bytes_delivered", _DBL), ("span_s", _DBL), ("arena_in_use", _SZ), ("arena_high_water", _SZ)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 # name -> (restype, argtypes); mirrors include/dpg.h
 SIGNATURES = {
     "dpg_create": (_I32, [ctypes.c_int, ctypes.POINTER(_VP)]),
@@ -78,6 +95,21 @@ SIGNATURES = {
     "dpg_batch_graph_create": (_I32, [_VP, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
     "dpg_batch_graph_launch": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP]),
     "dpg_batch_graph_destroy": (None, [_VP]),
+    "dpg_arena_create": (_I32, [ctypes.c_size_t, _SZ, _SZ, ctypes.POINTER(_VP)]),
+    "dpg_arena_alloc": (_I32, [_VP, _SZ, ctypes.POINTER(ctypes.c_size_t)]),
+    "dpg_arena_free": (_I32, [_VP, ctypes.c_size_t]),
+    "dpg_arena_stats": (_I32, [_VP, ctypes.POINTER(_SZ), ctypes.POINTER(_SZ), ctypes.POINTER(_SZ),
+                               ctypes.POINTER(_SZ)]),
+    "dpg_arena_destroy": (None, [_VP]),
+    "dpg_server_create": (_I32, [_VP, ctypes.POINTER(ServerConfig), ctypes.POINTER(_VP)]),
+    "dpg_server_submit": (_I32, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "dpg_server_poll": (_I32, [_VP, ctypes.c_uint64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                               ctypes.POINTER(_VP), ctypes.POINTER(_DBL)]),
+    "dpg_server_next_completed": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_uint64)]),
+    "dpg_server_release": (_I32, [_VP, ctypes.c_uint64]),
+    "dpg_server_stats_get": (_I32, [_VP, ctypes.POINTER(ServerStats)]),
+    "dpg_server_reset_stats": (_I32, [_VP]),
+    "dpg_server_destroy": (None, [_VP]),
     "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
     "dpg_profile_reset": (_I32, [_VP]),
     "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
@@ -308,3 +340,119 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+class Arena:
+    """Host bookkeeping of a device address range (no device access)."""
+
+    def __init__(self, base: int, size: int, align: int = 256):
+        h = _VP()
+        _check(lib().dpg_arena_create(base, size, align, ctypes.byref(h)), "dpg_arena_create")
+        self.handle = h
+
+    def alloc(self, nbytes: int):
+        a = ctypes.c_size_t()
+        st = lib().dpg_arena_alloc(self.handle, nbytes, ctypes.byref(a))
+        if st == ERR_BUSY:
+            return None
+        _check(st, "dpg_arena_alloc")
+        return a.value
+
+    def free(self, addr: int):
+        _check(lib().dpg_arena_free(self.handle, addr), "dpg_arena_free")
+
+    def stats(self):
+        v = [_SZ() for _ in range(4)]
+        _check(lib().dpg_arena_stats(self.handle, *[ctypes.byref(x) for x in v]), "dpg_arena_stats")
+        return dict(zip(("in_use", "high_water", "largest_free", "free_blocks"), (x.value for x in v)))
+
+    def close(self):
+        if self.handle:
+            lib().dpg_arena_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over a device arena of `arena_bytes`."""
+
+    def __init__(self, ctx: Context, arena_bytes: int, max_inflight: int = 4, max_batch_requests: int = 64,
+                 use_graph: bool = True):
+        import torch
+
+        self.ctx = ctx
+        self.arena_mem = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        torch.cuda.synchronize()
+        cfg = ServerConfig(self.arena_mem.data_ptr(), arena_bytes, max_inflight, max_batch_requests,
+                           int(use_graph), 0)
+        h = _VP()
+        _check(lib().dpg_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "dpg_server_create")
+        self.handle = h
+
+    def submit(self, req: Request) -> int:
+        t = ctypes.c_uint64()
+        _check(lib().dpg_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "dpg_server_submit")
+        return t.value
+
+    def poll(self, ticket: int):
+        state, status, dst, lat = _I32(), _I32(), _VP(), _DBL()
+        _check(lib().dpg_server_poll(self.handle, ticket, ctypes.byref(state), ctypes.byref(status),
+                                     ctypes.byref(dst), ctypes.byref(lat)), "dpg_server_poll")
+        return state.value, status.value, dst.value, lat.value
+
+    def next_completed(self, timeout_ms: int = 1000):
+        t = ctypes.c_uint64()
+        st = lib().dpg_server_next_completed(self.handle, timeout_ms, ctypes.byref(t))
+        if st == ERR_BUSY:
+            return None
+        _check(st, "dpg_server_next_completed")
+        return t.value
+
+    def release(self, ticket: int):
+        _check(lib().dpg_server_release(self.handle, ticket), "dpg_server_release")
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().dpg_server_stats_get(self.handle, ctypes.byref(s)), "dpg_server_stats_get")
+        return s.as_dict()
+
+    def reset_stats(self):
+        _check(lib().dpg_server_reset_stats(self.handle), "dpg_server_reset_stats")
+
+    def close(self):
+        if self.handle:
+            lib().dpg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_hip = None
+
+
+def copy_device_bytes(addr: int, nbytes: int, device: int = 0):
+    """A new uint8 device tensor holding nbytes copied from device address addr
+    (hipMemcpy, device to device)."""
+    global _hip
+    import torch
+
+    if _hip is None:
+        _hip = ctypes.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [_VP, _VP, _SZ, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    out = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
+    if nbytes:
+        torch.cuda.synchronize()
+        rc = _hip.hipMemcpy(out.data_ptr(), addr, nbytes, 3)  # hipMemcpyDeviceToDevice
+        if rc != 0:
+            raise RuntimeError(f"hipMemcpy failed: {rc}")
+    return out

@@ -1,0 +1,71 @@
+"""The serving engine's device-memory arena: host bookkeeping only, so it is
+exercised here without a GPU against a plain Python model of the free list."""
+import numpy as np
+import pytest
+
+from paper_cs_0308004_amd import dpg
+
+BASE = 1 << 32
+
+
+def test_alloc_free_coalesce():
+    a = dpg.Arena(BASE, 1 << 20, 256)
+    x = a.alloc(100)
+    y = a.alloc(1000)
+    z = a.alloc(256)
+    assert x == BASE and y == BASE + 256 and z == BASE + 256 + 1024
+    assert a.stats()["in_use"] == 256 + 1024 + 256
+    a.free(y)
+    assert a.stats()["free_blocks"] == 2
+    w = a.alloc(900)  # first fit reuses the hole
+    assert w == y
+    a.free(w)
+    a.free(x)
+    a.free(z)
+    st = a.stats()
+    assert st["in_use"] == 0 and st["free_blocks"] == 1 and st["largest_free"] == 1 << 20
+    assert st["high_water"] == 256 + 1024 + 256
+
+
+def test_exhaustion_and_bad_free():
+    a = dpg.Arena(BASE, 4096, 256)
+    blocks = [a.alloc(1000) for _ in range(4)]
+    assert all(b is not None for b in blocks)
+    assert a.alloc(1) is None
+    with pytest.raises(dpg.DPGError):
+        a.free(BASE + 17)
+    a.free(blocks[1])
+    with pytest.raises(dpg.DPGError):
+        a.free(blocks[1])  # double free
+    assert a.alloc(1024) == blocks[1]
+    with pytest.raises(dpg.DPGError):
+        dpg.Arena(BASE + 3, 4096, 256)  # misaligned base
+
+
+def test_random_against_model():
+    """Random alloc/free sequences: the arena never hands out overlapping
+    blocks, stays within its range, and its byte count matches the model."""
+    rng = np.random.default_rng(0)
+    size = 1 << 22
+    a = dpg.Arena(BASE, size, 256)
+    live = {}
+    for step in range(5000):
+        if live and rng.random() < 0.45:
+            addr = list(live)[rng.integers(0, len(live))]
+            a.free(addr)
+            del live[addr]
+        else:
+            n = int(rng.integers(1, 200000))
+            addr = a.alloc(n)
+            need = -(-n // 256) * 256
+            if addr is None:
+                assert a.stats()["largest_free"] < need
+                continue
+            assert addr % 256 == 0 and BASE <= addr and addr + need <= BASE + size
+            for b, m in live.items():
+                assert addr + need <= b or b + m <= addr
+            live[addr] = need
+        assert a.stats()["in_use"] == sum(live.values())
+    for addr in list(live):
+        a.free(addr)
+    assert a.stats()["free_blocks"] == 1

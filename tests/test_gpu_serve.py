@@ -1,0 +1,160 @@
+"""The serving engine on the GPU: continuous batching under an HBM budget.
+Every request's output must be the same alone and in the mix (bit for bit),
+and equal the oracle; the arena is never exceeded; oversize and invalid
+requests fail cleanly."""
+import threading
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_cs_0308004_amd import dpg, synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = dpg.Context(0)
+    yield c
+    c.close()
+
+
+def build_requests(n_req, seed, max_log2=15):
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_req):
+        n = int(np.exp(rng.uniform(0, np.log(1 << max_log2))))
+        if rng.random() < 0.75:
+            rec = int(rng.choice([16, 64, 100, 256]))
+            n_src = max(1, n)
+            src = synth.record_bytes(n_src, rec, seed=seed * 7919 + k)
+            rids = synth.rids_permutation(n_src, seed=seed * 7919 + k)
+            want = oracle.retrieve(src, rids)
+            s_t, r_t = torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV)
+            algo = int(rng.choice([dpg.ALGO_AUTO, dpg.ALGO_DIRECT, dpg.ALGO_DPG]))
+            req = dpg.Request(dpg.REQ_RETRIEVE, algo, s_t.data_ptr(), n_src, rec, 0, r_t.data_ptr(), None, n, 0, 0,
+                              None)
+            out.append((req, (s_t, r_t), want))
+        else:
+            n_dim = max(1, n // 16)
+            rec = int(rng.choice([16, 64, 100, 256]))
+            order = int(rng.integers(0, 2))
+            fact = synth.fact_table(n, n_dim, 0.0, seed=seed * 7919 + k)
+            dim = synth.dim_table(n_dim, seed=seed * 7919 + k, dim_bytes=rec)
+            fn = oracle.fk_join_fact_order if order == 0 else oracle.fk_join_dim_order
+            want = fn(fact, dim, 0)
+            f_t, d_t = torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV)
+            algo = int(rng.choice([dpg.ALGO_AUTO, dpg.ALGO_DIRECT, dpg.ALGO_DPG]))
+            req = dpg.Request(dpg.REQ_FK_JOIN, algo, d_t.data_ptr(), n_dim, rec, 16, None, f_t.data_ptr(), n, 0,
+                              order, None)
+            out.append((req, (f_t, d_t), want))
+    torch.cuda.synchronize()
+    return out
+
+
+def run_all(server, reqs, gap_s=0.0):
+    """Submit (optionally spaced in time), collect every output by polling its
+    own tickets (safe with several submitting threads), release."""
+    tickets = {}
+    for i, (req, _, _) in enumerate(reqs):
+        tickets[server.submit(req)] = i
+        if gap_s:
+            time.sleep(gap_s)
+    got = {}
+    waiting = set(tickets)
+    deadline = time.time() + 120
+    while waiting:
+        assert time.time() < deadline, "server did not finish"
+        for t in list(waiting):
+            state, status, dst, lat = server.poll(t)
+            if state < dpg.TICKET_DONE:
+                continue
+            i = tickets[t]
+            assert state == dpg.TICKET_DONE, (i, state, status)
+            assert lat > 0
+            nbytes = reqs[i][2].nbytes
+            got[i] = dpg.copy_device_bytes(dst, nbytes).cpu().numpy().reshape(reqs[i][2].shape)
+            server.release(t)
+            waiting.discard(t)
+        time.sleep(0.0005)
+    return got
+
+
+@pytest.mark.parametrize("mode", ["graph", "batch", "per-request"])
+def test_server_outputs_match_oracle(ctx, mode):
+    reqs = build_requests(160, seed=1)
+    kw = dict(graph=dict(max_batch_requests=64, use_graph=True),
+              batch=dict(max_batch_requests=64, use_graph=False),
+              **{"per-request": dict(max_batch_requests=1, use_graph=False)})[mode]
+    server = dpg.Server(ctx, 1 << 30, max_inflight=3, **kw)
+    try:
+        got = run_all(server, reqs)
+        for i, (_, _, want) in enumerate(reqs):
+            assert np.array_equal(got[i], want), i
+        st = server.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
+        assert st["arena_high_water"] <= 1 << 30
+        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+        if mode != "per-request":
+            assert st["batches"] < len(reqs)
+    finally:
+        server.close()
+
+
+def test_alone_equals_in_the_mix(ctx):
+    """Each request submitted on its own, then all of them at once while a
+    second thread keeps submitting: outputs identical."""
+    reqs = build_requests(60, seed=2)
+    server = dpg.Server(ctx, 1 << 30, max_inflight=4, max_batch_requests=32)
+    try:
+        alone = {}
+        for i in range(len(reqs)):
+            alone[i] = run_all(server, [reqs[i]])[0]
+        mix_a, mix_b = {}, {}
+
+        def second():
+            mix_b.update(run_all(server, reqs[30:], gap_s=0.0005))
+
+        th = threading.Thread(target=second)
+        th.start()
+        mix_a.update(run_all(server, reqs[:30], gap_s=0.0003))
+        th.join()
+        for i in range(len(reqs)):
+            mixed = mix_a[i] if i < 30 else mix_b[i - 30]
+            assert np.array_equal(alone[i], mixed), i
+            assert np.array_equal(alone[i], reqs[i][2]), i
+    finally:
+        server.close()
+
+
+def test_budget_backpressure_and_failures(ctx):
+    """A small arena: requests wait for memory (never exceeding it), a request
+    larger than the arena fails with BUSY, an invalid one with INVALID_ARG."""
+    budget = 8 << 20
+    reqs = build_requests(40, seed=3, max_log2=13)
+    server = dpg.Server(ctx, budget, max_inflight=2, max_batch_requests=8)
+    try:
+        big_src = torch.zeros((1 << 17, 100), dtype=torch.uint8, device=DEV)
+        big_rids = torch.zeros(1 << 17, dtype=torch.int32, device=DEV)
+        big = dpg.Request(dpg.REQ_RETRIEVE, dpg.ALGO_DIRECT, big_src.data_ptr(), 1 << 17, 100, 0,
+                          big_rids.data_ptr(), None, 1 << 17, 0, 0, None)
+        bad = dpg.Request.from_buffer_copy(reqs[0][0])
+        bad.rec_bytes = 6
+        tb = server.submit(big)
+        tbad = server.submit(bad)
+        got = run_all(server, reqs)
+        for i, (_, _, want) in enumerate(reqs):
+            assert np.array_equal(got[i], want)
+        for t, status in ((tb, dpg.ERR_BUSY), (tbad, dpg.ERR_INVALID_ARG)):
+            state, st, dst, _ = server.poll(t)
+            assert state == dpg.TICKET_FAILED and st == status and dst is None
+            server.release(t)
+        st = server.stats()
+        assert st["arena_high_water"] <= budget
+        assert st["failed"] == 2
+    finally:
+        server.close()
