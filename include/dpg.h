@@ -135,6 +135,29 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
                         int check_rids, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Autotuning.  dpg_autotune_retrieve times every candidate plan for one     */
+/* retrieval shape on the caller's buffers (direct retrieval; DPG with each  */
+/* run length whose runs hold 256 KiB to 64 MiB of source -- the region-size */
+/* constraint of Section 2.1 -- with both probes and both Phase I flavours)  */
+/* and records the fastest in the context's table; DPG_ALGO_AUTO uses that   */
+/* entry for shapes in the same power-of-two size class.  dst is overwritten */
+/* (with the correct result); the call synchronizes the stream.              */
+/* ------------------------------------------------------------------------- */
+size_t dpg_autotune_workspace_bytes(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
+                                    int64_t n_rids);
+/* dpg_only = 1: consider DPG plans only (to find the best DPG configuration). */
+dpg_status dpg_autotune_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t rec_bytes,
+                                 const int32_t *rids, int64_t n_rids, void *dst, void *workspace,
+                                 size_t workspace_bytes, int32_t reps, int32_t dpg_only,
+                                 hipStream_t stream, dpg_plan *best, double *best_ms);
+int32_t dpg_tune_count(const dpg_ctx *ctx);
+dpg_status dpg_tune_clear(dpg_ctx *ctx);
+/* Text file, one line per shape; load merges into the table and rejects
+ * malformed lines with DPG_ERR_INVALID_ARG. */
+dpg_status dpg_tune_save(const dpg_ctx *ctx, const char *path);
+dpg_status dpg_tune_load(dpg_ctx *ctx, const char *path);
+
+/* ------------------------------------------------------------------------- */
 /* Sorting (Section 3): three-phase key-pointer sort with DPG as the copy      */
 /* phase.  Records are ordered by key bytes [key_offset, key_offset+key_bytes) */
 /* compared as unsigned bytes, lexicographically; records with equal keys keep */
@@ -246,8 +269,9 @@ void dpg_arena_destroy(dpg_arena *arena);
 /* admits submitted requests in arrival order while their output (plus, for   */
 /* requests that run on their own, their workspace) fits the arena, and      */
 /* launches admitted requests on the first free stream slot: consecutive     */
-/* direct-work requests together as one persistent batch launch (a graph     */
-/* replay with use_graph), others alone.  Requests arriving while batches run */
+/* small direct-work requests together as one persistent batch launch (a     */
+/* graph replay with use_graph), others alone through their dedicated        */
+/* kernels.  Requests arriving while batches run                             */
 /* are admitted and launched on the next free slot, so their work overlaps on */
 /* the device.  With max_batch_requests = 1 every request is launched alone   */
 /* through its single-request entry point (the per-request baseline).        */
@@ -260,6 +284,10 @@ typedef struct {
     int32_t max_inflight;        /* stream slots, 1..16 */
     int32_t max_batch_requests;  /* requests per launch; 1 = per-request launches */
     int32_t use_graph;           /* 1: replay a captured batch graph per launch */
+    int32_t batch_max_kib;       /* direct-work requests with larger outputs run alone
+                                    through their dedicated kernels (0: 4096 KiB) */
+    int32_t batch_window_us;     /* a partial batch waits up to this long for more
+                                    requests before launching (0: launch at once) */
     int32_t reserved;
 } dpg_server_config;
 
@@ -277,6 +305,7 @@ typedef struct {
     double bytes_delivered;                  /* output bytes of completed requests */
     double span_s;                           /* first submit -> last completion */
     size_t arena_in_use, arena_high_water;
+    double launch_s;                         /* host time the scheduler spent enqueueing work */
 } dpg_server_stats;
 
 typedef struct dpg_server dpg_server;

@@ -17,6 +17,7 @@
 // captured graph of [reset queue, k_batch] can be replayed with new requests:
 // only the descriptor upload changes (dpg_batch_graph_*).
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "dev_common.h"
@@ -36,8 +37,10 @@ struct BatchDesc {
     int32_t wa, wb;         // dwords taken from A and from B per output row
     int32_t fk_word;        // word of the A row holding the foreign key (join)
     int32_t tile_rows;      // output rows per work item
-    uint32_t magic;         // ceil(2^32 / (wa + wb)) for the row division
+    uint32_t magic;         // ceil(2^32 / ((wa + wb) / vec)) for the row division
     int32_t request;        // index in the caller's request array
+    int32_t vec;            // dwords per access: 4 when rows and pointers are 16-byte aligned, else 1
+    int32_t nt;             // nontemporal output stores
 };
 
 struct BatchHeader {
@@ -50,6 +53,41 @@ constexpr int kBatchThreads = 256;
 constexpr int kBatchPer = 16;
 constexpr int kBatchMaxTileRows = 2048;
 constexpr int kBatchItemWords = 16384;  // ~64 KiB of output per work item
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Copy the item's rows: element e of the flattened (row, element) space with
+// VEC dwords per element.
+template <typename E, bool NT>
+__device__ __forceinline__ void batch_copy(const BatchDesc &d, const int32_t *s_ia, const int32_t *s_ib, int rows,
+                                           int64_t row0) {
+    constexpr int VEC = sizeof(E) / 4;
+    const int wa = d.wa / VEC, wb = d.wb / VEC, W = wa + wb;
+    const E *A = (const E *)d.a;
+    const E *B = (const E *)d.b;
+    E *o = (E *)d.out + row0 * W;
+    const int total = rows * W;
+    for (int e0 = 0; e0 < total; e0 += kBatchThreads * kBatchPer) {
+        E v[kBatchPer];
+#pragma unroll
+        for (int k = 0; k < kBatchPer; ++k) {
+            const int e = e0 + threadIdx.x + k * kBatchThreads;
+            if (e < total) {
+                const int j = W == 1 ? e : (int)__umulhi((uint32_t)e, d.magic);
+                const int w = e - j * W;
+                v[k] = w < wa ? A[(int64_t)s_ia[j] * wa + w] : B[(int64_t)s_ib[j] * wb + (w - wa)];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kBatchPer; ++k) {
+            const int e = e0 + threadIdx.x + k * kBatchThreads;
+            if (e < total) {
+                if constexpr (NT) __builtin_nontemporal_store(v[k], o + e);
+                else o[e] = v[k];
+            }
+        }
+    }
+}
 
 __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__restrict__ hdr,
                                                          const BatchDesc *__restrict__ descs,
@@ -82,7 +120,6 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__re
         const int r = s_req;
         if (item >= total_items) break;  // queue exhausted: uniform exit
         const BatchDesc d = descs[r];
-        const int W = d.wa + d.wb;
         const int64_t row0 = (item - d.item_start) * d.tile_rows;
         const int rows = (int)min((int64_t)d.tile_rows, d.n_rows - row0);
         for (int j = threadIdx.x; j < rows; j += kBatchThreads) {
@@ -97,24 +134,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__re
             s_ib[j] = (int32_t)ib;
         }
         __syncthreads();
-        const int total = rows * W;
-        uint32_t *o = d.out + row0 * W;
-        for (int e0 = 0; e0 < total; e0 += kBatchThreads * kBatchPer) {
-            uint32_t v[kBatchPer];
-#pragma unroll
-            for (int k = 0; k < kBatchPer; ++k) {
-                const int e = e0 + threadIdx.x + k * kBatchThreads;
-                if (e < total) {
-                    const int j = (int)__umulhi((uint32_t)e, d.magic);
-                    const int w = e - j * W;
-                    v[k] = w < d.wa ? d.a[(int64_t)s_ia[j] * d.wa + w] : d.b[(int64_t)s_ib[j] * d.wb + (w - d.wa)];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kBatchPer; ++k) {
-                const int e = e0 + threadIdx.x + k * kBatchThreads;
-                if (e < total) o[e] = v[k];
-            }
+        if (d.vec == 4) {
+            if (d.nt) batch_copy<u32x4, true>(d, s_ia, s_ib, rows, row0);
+            else batch_copy<u32x4, false>(d, s_ia, s_ib, rows, row0);
+        } else {
+            if (d.nt) batch_copy<uint32_t, true>(d, s_ia, s_ib, rows, row0);
+            else batch_copy<uint32_t, false>(d, s_ia, s_ib, rows, row0);
         }
         if (threadIdx.x == 0 && done) atomicAdd(&done[d.request], 1u);
         __syncthreads();
@@ -266,7 +291,11 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
         d.out = (uint32_t *)q.dst;
         d.n_rows = q.n;
         d.tile_rows = tile_rows_for(d.wa + d.wb);
-        d.magic = (uint32_t)((0x100000000ull + (uint64_t)(d.wa + d.wb) - 1) / (uint64_t)(d.wa + d.wb));
+        const uintptr_t al = (uintptr_t)d.a | (uintptr_t)d.b | (uintptr_t)d.out;
+        d.vec = (d.wa % 4 == 0 && d.wb % 4 == 0 && al % 16 == 0) ? 4 : 1;
+        const uint64_t we = (uint64_t)(d.wa + d.wb) / (uint64_t)d.vec;
+        d.magic = we > 1 ? (uint32_t)((0x100000000ull + we - 1) / we) : 0u;  // one element per row: j = e
+        d.nt = (double)q.n * (d.wa + d.wb) * 4 > 256.0 * 1024 * 1024 ? 1 : 0;
         d.item_start = items;
         d.request = i;
         items += plans[i].items;
@@ -345,6 +374,11 @@ struct dpg_batch_graph {
     dpg::BatchLayout layout;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // pinned staging of header + descriptors, so the upload is asynchronous;
+    // `uploaded` marks when the previous upload has been consumed
+    char *staging = nullptr;
+    hipEvent_t uploaded = nullptr;
+    bool upload_pending = false;
 };
 
 using namespace dpg;
@@ -404,6 +438,16 @@ dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *work
     g->max_requests = max_requests;
     g->ws = (char *)workspace;
     g->layout = L;
+    if (hipHostMalloc((void **)&g->staging, L.off_desc - L.off_hdr + (size_t)max_requests * sizeof(BatchDesc),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&g->uploaded, hipEventDisableTiming) != hipSuccess) {
+        if (g->staging) (void)hipHostFree(g->staging);
+        delete g;
+        return DPG_ERR_HIP;
+    }
+    // the copied span also covers the queue word between header and
+    // descriptors (the graph zeroes it again before k_batch runs)
+    std::memset(g->staging, 0, L.off_desc - L.off_hdr);
     // capture [reset queue, k_batch]; profiling events are not captured
     const bool prof = ctx->profiling;
     ctx->profiling = false;
@@ -418,9 +462,7 @@ dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *work
     }
     ctx->profiling = prof;
     if (st != DPG_OK) {
-        if (g->exec) (void)hipGraphExecDestroy(g->exec);
-        if (g->graph) (void)hipGraphDestroy(g->graph);
-        delete g;
+        dpg_batch_graph_destroy(g);
         return st;
     }
     *out = g;
@@ -428,6 +470,15 @@ dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *work
 }
 
 dpg_status dpg_batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream) {
+    return dpg::batch_graph_launch(g, reqs, n, stream, true);
+}
+
+}  // extern "C"
+
+namespace dpg {
+
+dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream,
+                              bool replay) {
     if (!g) return DPG_ERR_INVALID_ARG;
     if (n > g->max_requests) return DPG_ERR_INVALID_ARG;
     std::vector<BatchRequestPlan> plans;
@@ -439,19 +490,34 @@ dpg_status dpg_batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, i
     std::vector<BatchDesc> descs;
     BatchHeader hdr;
     build_descs(reqs, n, plans, &descs, &hdr);
-    DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_hdr, &hdr, sizeof(hdr), hipMemcpyHostToDevice, stream));
+    // the staging buffer may still feed the previous upload
+    if (g->upload_pending) DPG_HIP(hipEventSynchronize(g->uploaded));
+    // header and descriptors keep their workspace layout: one contiguous copy
+    const size_t span = g->layout.off_desc - g->layout.off_hdr + descs.size() * sizeof(BatchDesc);
+    std::memcpy(g->staging, &hdr, sizeof(hdr));
     if (!descs.empty())
-        DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_desc, descs.data(), descs.size() * sizeof(BatchDesc),
-                               hipMemcpyHostToDevice, stream));
+        std::memcpy(g->staging + (g->layout.off_desc - g->layout.off_hdr), descs.data(),
+                    descs.size() * sizeof(BatchDesc));
+    DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_hdr, g->staging, span, hipMemcpyHostToDevice, stream));
+    DPG_HIP(hipEventRecord(g->uploaded, stream));
+    g->upload_pending = true;
+    if (!replay) return launch_batch_kernel(g->ctx, g->ws, g->layout, batch_bytes(reqs, n, plans), false, stream);
     ProfScope prof(g->ctx, K_BATCH, batch_bytes(reqs, n, plans), stream);
     DPG_HIP(hipGraphLaunch(g->exec, stream));
     return DPG_OK;
 }
 
+}  // namespace dpg
+
+extern "C" {
+
 void dpg_batch_graph_destroy(dpg_batch_graph *g) {
     if (!g) return;
+    if (g->upload_pending) (void)hipEventSynchronize(g->uploaded);
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->uploaded) (void)hipEventDestroy(g->uploaded);
+    if (g->staging) (void)hipHostFree(g->staging);
     delete g;
 }
 

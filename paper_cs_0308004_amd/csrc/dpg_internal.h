@@ -87,7 +87,7 @@ struct TuneKey {
 };
 
 struct TuneEntry {
-    int32_t algo, probe, log2_run, dist_tile;
+    int32_t algo, probe, log2_run, dist_tile, dist_mode;
     double ms;
 };
 
@@ -154,6 +154,11 @@ dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool 
 bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn);
 dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
                               int64_t n_rids, int algo, RetrievePlan *plan);
+// The same with every choice explicit (0 = automatic), ignoring options and
+// the tuning table; algo must be DIRECT or DPG.
+dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo, int probe,
+                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan);
+TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
 
 // Phases I and II of a planned DPG retrieval: afterwards the workspace holds
 // INTERNAL (at off_internal) and inv (at off_inv), so a caller can fuse Phase
@@ -187,5 +192,9 @@ int xcd_remap_flag(const dpg_ctx *ctx);
 // work inside the persistent launch; *own_ws is the workspace it needs when run
 // through its single-request entry point.
 dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, bool *direct, size_t *own_ws);
+// Upload a batch into a bound batch graph's workspace and run it: replay the
+// captured graph, or (replay = false) launch its two kernels directly.
+dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream,
+                              bool replay);
 
 }  // namespace dpg

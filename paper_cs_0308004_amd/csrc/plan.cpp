@@ -133,39 +133,49 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     }
 }
 
-dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo,
-                              RetrievePlan *p) {
+TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids) {
+    return TuneKey{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
+}
+
+dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo, int probe,
+                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *p) {
     if (n_src < 0 || n_src > INT32_MAX || n_rids < 0 || n_rids > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
     if (rec_bytes < 4 || rec_bytes > kMaxRecBytes || rec_bytes % 4 != 0) return DPG_ERR_INVALID_ARG;
-    if (algo < DPG_ALGO_AUTO || algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
+    if (algo != DPG_ALGO_DIRECT && algo != DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
     *p = RetrievePlan();
     p->n_src = n_src;
     p->n_rids = n_rids;
     p->rec_bytes = rec_bytes;
+    p->algo = algo;
+    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile, dist_mode);
+    layout_workspace(p);
+    return DPG_OK;
+}
+
+dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo,
+                              RetrievePlan *p) {
+    if (algo < DPG_ALGO_AUTO || algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
     int probe = ctx ? (int)ctx->opt_probe : 0;
     int log2_run = ctx ? (int)ctx->opt_log2_run : 0;
     int dist_tile = ctx ? (int)ctx->opt_dist_tile : 0;
-    const int dist_mode = ctx ? (int)ctx->opt_distribute : 0;
+    int dist_mode = ctx ? (int)ctx->opt_distribute : 0;
     if (algo == DPG_ALGO_AUTO) {
         // Measured on MI355X (2^26 records): direct retrieval is faster at every
         // record size from 8 to 256 bytes, so it is the default unless the
         // autotuner has recorded otherwise for this shape.
         algo = DPG_ALGO_DIRECT;
         if (ctx && ctx->opt_use_tuned != 2) {
-            const TuneKey key{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
-            auto it = ctx->tuned.find(key);
+            auto it = ctx->tuned.find(tune_key(rec_bytes, n_src, n_rids));
             if (it != ctx->tuned.end()) {
                 algo = it->second.algo;
                 if (!probe) probe = it->second.probe;
                 if (!log2_run) log2_run = it->second.log2_run;
                 if (!dist_tile) dist_tile = it->second.dist_tile;
+                if (!dist_mode) dist_mode = it->second.dist_mode;
             }
         }
     }
-    p->algo = algo;
-    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile, dist_mode);
-    layout_workspace(p);
-    return DPG_OK;
+    return make_retrieve_plan_explicit(n_src, rec_bytes, n_rids, algo, probe, log2_run, dist_tile, dist_mode, p);
 }
 
 }  // namespace dpg

@@ -11,11 +11,15 @@
 //     whole arena fails at once.  Batches of direct work use a descriptor
 //     workspace each slot owns, so launching never allocates.
 //   * Batching: whenever one of the `max_inflight` stream slots is free, the
-//     run of direct-work requests at the head of the admitted queue (up to
-//     max_batch_requests) is launched there as one persistent batch -- a
-//     replay of the slot's captured graph, or dpg_batch_run -- and any other
-//     request alone through its single-request entry point.  With batches of
-//     one, every request takes that path (the per-request baseline).
+//     run of small direct-work requests at the head of the admitted queue (up
+//     to max_batch_requests, outputs up to batch_max_kib each) is launched
+//     there as one persistent batch -- a replay of the slot's captured graph,
+//     or the same two kernels launched directly -- after waiting up to
+//     batch_window_us for a partial batch to fill; any other request runs
+//     alone through its
+//     single-request entry point, whose dedicated kernels are faster for
+//     large outputs and need no batching to hide launch cost.  With batches
+//     of one, every request takes that path (the per-request baseline).
 //     Requests arriving while batches run are admitted and launched on the
 //     next free slot, so their work overlaps on the device.
 //   * Completion: a batch's event marks all its requests done; their latency
@@ -120,7 +124,7 @@ struct Ticket {
     bool batched = false;          // runs inside a slot's persistent batch launch
     size_t out_off = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0;
     bool has_out = false, has_ws = false;
-    Clock::time_point submit, done;
+    Clock::time_point submit, admit, done;
 };
 
 struct Slot {
@@ -158,6 +162,7 @@ struct dpg_server {
     // statistics
     std::vector<double> latencies_ms;
     int64_t submitted = 0, n_completed = 0, n_failed = 0, batches = 0;
+    double launch_s = 0;  // host time spent enqueueing work
     double bytes_delivered = 0;
     dpg::Clock::time_point first_submit, last_done;
     bool any_submit = false;
@@ -211,10 +216,7 @@ static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> 
         reqs.reserve(batch.size());
         for (uint64_t t : batch) reqs.push_back(s->tickets[t].req);
         const int32_t n = (int32_t)reqs.size();
-        if (sl.graph)
-            st = dpg_batch_graph_launch(sl.graph, reqs.data(), n, sl.stream);
-        else
-            st = dpg_batch_run(ctx, reqs.data(), n, s->base + sl.batch_ws_off, sl.batch_ws_bytes, sl.stream);
+        st = batch_graph_launch(sl.graph, reqs.data(), n, sl.stream, s->cfg.use_graph != 0);
     }
     if (st != DPG_OK) return st;
     if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
@@ -270,23 +272,43 @@ static void scheduler(dpg_server *s) {
             }
             tk.req.dst = tk.has_out ? s->base + tk.out_off : nullptr;
             tk.state = T_ADMITTED;
+            tk.admit = Clock::now();
             s->admitted.push_back(t);
             s->pending.pop_front();
             changed = true;
         }
         // 3. launches on free slots: the run of batched tickets at the head
         //    (up to max_batch_requests), or the single unbatched head ticket
+        bool window_wait = false;
         for (Slot &sl : s->slots) {
             if (sl.busy || s->admitted.empty()) continue;
             std::vector<uint64_t> batch;
             const bool batched = s->tickets[s->admitted.front()].batched;
+            if (batched && s->cfg.batch_window_us > 0 && !s->stop) {
+                // a partial batch waits (up to the window) for more requests
+                size_t run = 0;
+                for (uint64_t t : s->admitted) {
+                    if (!s->tickets[t].batched || (int32_t)run >= s->cfg.max_batch_requests) break;
+                    ++run;
+                }
+                const double waited =
+                    std::chrono::duration<double, std::micro>(Clock::now() - s->tickets[s->admitted.front()].admit)
+                        .count();
+                if ((int32_t)run < s->cfg.max_batch_requests && run == s->admitted.size() &&
+                    waited < s->cfg.batch_window_us) {
+                    window_wait = true;
+                    break;
+                }
+            }
             while (!s->admitted.empty() && (int32_t)batch.size() < s->cfg.max_batch_requests &&
                    s->tickets[s->admitted.front()].batched == batched) {
                 batch.push_back(s->admitted.front());
                 s->admitted.pop_front();
                 if (!batched) break;
             }
+            const auto t_launch = Clock::now();
             const dpg_status st = launch_on_slot(s, sl, batch);
+            s->launch_s += std::chrono::duration<double>(Clock::now() - t_launch).count();
             if (st != DPG_OK) {
                 sl.tickets = batch;
                 finish_batch(s, sl, st);
@@ -297,8 +319,8 @@ static void scheduler(dpg_server *s) {
         bool inflight = false;
         for (Slot &sl : s->slots) inflight |= sl.busy;
         if (s->stop && !inflight && s->pending.empty() && s->admitted.empty()) break;
-        if (inflight) {
-            // work on the device: poll its events again shortly
+        if (inflight || window_wait) {
+            // work on the device, or a batch window open: check again shortly
             lk.unlock();
             std::this_thread::yield();
             lk.lock();
@@ -382,9 +404,10 @@ dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_ser
                 st = DPG_ERR_WORKSPACE_TOO_SMALL;
                 break;
             }
-            if (cfg->use_graph)
-                st = dpg_batch_graph_create(ctx, cfg->max_batch_requests, s->base + sl.batch_ws_off,
-                                            sl.batch_ws_bytes, sl.stream, &sl.graph);
+            // the bound batch object (pinned descriptor staging; its graph is
+            // replayed only with use_graph)
+            st = dpg_batch_graph_create(ctx, cfg->max_batch_requests, s->base + sl.batch_ws_off, sl.batch_ws_bytes,
+                                        sl.stream, &sl.graph);
         }
     }
     (void)hipSetDevice(prev);
@@ -417,7 +440,8 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
     tk.status = plan_batch_request(s->ctx, tk.req, &direct, &own_ws);
     tk.req.dst = nullptr;
     if (tk.status == DPG_OK) {
-        tk.batched = direct && s->cfg.max_batch_requests > 1;
+        const size_t max_batched = (size_t)(s->cfg.batch_max_kib > 0 ? s->cfg.batch_max_kib : 4096) << 10;
+        tk.batched = direct && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
         tk.ws_bytes = tk.batched ? 0 : own_ws;
     } else {
         tk.state = T_FAILED;
@@ -507,6 +531,7 @@ dpg_status dpg_server_stats_get(dpg_server *s, dpg_server_stats *out) {
                       : 0;
     out->arena_in_use = s->arena->in_use();
     out->arena_high_water = s->arena->high_water();
+    out->launch_s = s->launch_s;
     return DPG_OK;
 }
 
@@ -516,6 +541,7 @@ dpg_status dpg_server_reset_stats(dpg_server *s) {
     s->latencies_ms.clear();
     s->submitted = s->n_completed = s->n_failed = s->batches = 0;
     s->bytes_delivered = 0;
+    s->launch_s = 0;
     s->any_submit = false;
     return DPG_OK;
 }

@@ -63,13 +63,14 @@ TICKET_QUEUED, TICKET_ADMITTED, TICKET_RUNNING, TICKET_DONE, TICKET_FAILED = 0, 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("arena", _VP), ("arena_bytes", _SZ), ("max_inflight", _I32), ("max_batch_requests", _I32),
-                ("use_graph", _I32), ("reserved", _I32)]
+                ("use_graph", _I32), ("batch_max_kib", _I32), ("batch_window_us", _I32), ("reserved", _I32)]
 
 
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", _I64), ("completed", _I64), ("failed", _I64), ("batches", _I64),
                 ("p50_ms", _DBL), ("p99_ms", _DBL), ("max_ms", _DBL), ("mean_ms", _DBL),
-                ("bytes_delivered", _DBL), ("span_s", _DBL), ("arena_in_use", _SZ), ("arena_high_water", _SZ)]
+                ("bytes_delivered", _DBL), ("span_s", _DBL), ("arena_in_use", _SZ), ("arena_high_water", _SZ),
+                ("launch_s", _DBL)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -110,6 +111,13 @@ SIGNATURES = {
     "dpg_server_stats_get": (_I32, [_VP, ctypes.POINTER(ServerStats)]),
     "dpg_server_reset_stats": (_I32, [_VP]),
     "dpg_server_destroy": (None, [_VP]),
+    "dpg_autotune_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64]),
+    "dpg_autotune_retrieve": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _I32, _VP,
+                                     ctypes.POINTER(Plan), ctypes.POINTER(_DBL)]),
+    "dpg_tune_count": (_I32, [_VP]),
+    "dpg_tune_clear": (_I32, [_VP]),
+    "dpg_tune_save": (_I32, [_VP, ctypes.c_char_p]),
+    "dpg_tune_load": (_I32, [_VP, ctypes.c_char_p]),
     "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
     "dpg_profile_reset": (_I32, [_VP]),
     "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
@@ -222,6 +230,35 @@ class Context:
                                 _addr(workspace), workspace.numel(), algo, int(check_rids), _stream(stream))
         _check(st, "dpg_retrieve")
         return dst
+
+    # ---- autotuning ----------------------------------------------------
+    def autotune_retrieve(self, src, rids, dst=None, reps: int = 3, dpg_only: bool = False, stream=None):
+        """Time the candidate plans; returns (best Plan, ms per retrieval)."""
+        import torch
+
+        n_src, rec_bytes = src.shape[0], _rec_bytes(src)
+        n = rids.numel()
+        if dst is None:
+            dst = torch.empty((n, src.shape[1]), dtype=src.dtype, device=src.device)
+        need = lib().dpg_autotune_workspace_bytes(self.handle, n_src, rec_bytes, n)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=src.device)
+        best, ms = Plan(), _DBL()
+        _check(lib().dpg_autotune_retrieve(self.handle, _addr(src), n_src, rec_bytes, _addr(rids), n, _addr(dst),
+                                           _addr(ws), ws.numel(), reps, int(dpg_only), _stream(stream),
+                                           ctypes.byref(best), ctypes.byref(ms)), "dpg_autotune_retrieve")
+        return best, ms.value
+
+    def tune_count(self) -> int:
+        return lib().dpg_tune_count(self.handle)
+
+    def tune_clear(self):
+        _check(lib().dpg_tune_clear(self.handle), "dpg_tune_clear")
+
+    def tune_save(self, path: str):
+        _check(lib().dpg_tune_save(self.handle, path.encode()), "dpg_tune_save")
+
+    def tune_load(self, path: str):
+        _check(lib().dpg_tune_load(self.handle, path.encode()), "dpg_tune_load")
 
     # ---- sorting -------------------------------------------------------
     def sort_workspace_bytes(self, n: int, rec_bytes: int, key_offset: int = 0, key_bytes: int = 10,
@@ -382,14 +419,14 @@ class Server:
     """Continuous-batching server over a device arena of `arena_bytes`."""
 
     def __init__(self, ctx: Context, arena_bytes: int, max_inflight: int = 4, max_batch_requests: int = 64,
-                 use_graph: bool = True):
+                 use_graph: bool = True, batch_max_kib: int = 0, batch_window_us: int = 0):
         import torch
 
         self.ctx = ctx
         self.arena_mem = torch.empty(arena_bytes, dtype=torch.uint8, device=f"cuda:{ctx.device}")
         torch.cuda.synchronize()
         cfg = ServerConfig(self.arena_mem.data_ptr(), arena_bytes, max_inflight, max_batch_requests,
-                           int(use_graph), 0)
+                           int(use_graph), batch_max_kib, batch_window_us, 0)
         h = _VP()
         _check(lib().dpg_server_create(ctx.handle, ctypes.byref(cfg), ctypes.byref(h)), "dpg_server_create")
         self.handle = h

@@ -29,7 +29,7 @@ def make_mix(n_req, seed, kinds=("retrieve", "join"), algos=(dpg.ALGO_DIRECT, dp
         algo = int(algos[rng.integers(0, len(algos))])
         n = int(np.exp(rng.uniform(np.log(1), np.log(1 << max_log2))))
         if kind == "retrieve":
-            rec = int(rng.choice([16, 64, 100, 256]))
+            rec = int(rng.choice([4, 12, 16, 64, 100, 256]))
             n_src = max(1, int(n * rng.uniform(0.5, 2.0)))
             src = synth.record_bytes(n_src, rec, seed=seed * 1000 + k)
             rids = synth.rids_uniform(n_src, n, seed=seed * 1000 + k)

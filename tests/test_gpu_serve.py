@@ -87,8 +87,8 @@ def run_all(server, reqs, gap_s=0.0):
 @pytest.mark.parametrize("mode", ["graph", "batch", "per-request"])
 def test_server_outputs_match_oracle(ctx, mode):
     reqs = build_requests(160, seed=1)
-    kw = dict(graph=dict(max_batch_requests=64, use_graph=True),
-              batch=dict(max_batch_requests=64, use_graph=False),
+    kw = dict(graph=dict(max_batch_requests=64, use_graph=True, batch_max_kib=1 << 20),
+              batch=dict(max_batch_requests=64, use_graph=False, batch_max_kib=256),
               **{"per-request": dict(max_batch_requests=1, use_graph=False)})[mode]
     server = dpg.Server(ctx, 1 << 30, max_inflight=3, **kw)
     try:
