@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: autotuned)")
     ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "counters.json"),
                     help="HBM byte counts per launch measured with rocprofv3 --pmc (optional)")
     return ap.parse_args()
@@ -141,6 +143,13 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         rids = synth.rids_blocked(n, R, seed, backend="torch", device=dev)
     m = rids.numel()
     dst = torch.empty((m, R), dtype=torch.uint8, device=dev)
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     tuned_ms = None
     if args.log2_run or args.probe or args.dist:
         ctx.set_option(dpg.OPT_LOG2_RUN, args.log2_run)
@@ -185,7 +194,8 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     if not np.array_equal(got, synth.records_at(rids_np[sample], R, seed)):
         raise SystemExit("bench: DPG output differs from the generator's records")
     delivered = m * R
-    wkey = f"{n}x{R}:{args.pattern}"
+    # counter data apply only to the same shape and DPG plan
+    wkey = f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}"
     dpg_kernels = ["k_part_hist", "k_part_scatter", "k_dist_hist", "k_dist_scatter", "k_probe_cached",
                    "k_probe_lds", "k_gather_phase"]
     out = {
