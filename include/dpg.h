@@ -128,7 +128,8 @@ size_t dpg_retrieve_workspace_bytes(const dpg_ctx *ctx, int64_t n_src, int32_t r
  *     rids plus one stream synchronization); an out-of-range rid returns
  *     DPG_ERR_RID_OUT_OF_RANGE with dst untouched.
  *   check_rids = 0: an out-of-range rid is undefined behaviour.
- * src and dst must not overlap.  n_rids == 0 returns DPG_OK, enqueuing nothing. */
+ * dst must not overlap src, rids or the workspace, and the workspace must not
+ * overlap src or rids.  n_rids == 0 returns DPG_OK, enqueuing nothing. */
 dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t rec_bytes,
                         const int32_t *rids, int64_t n_rids, void *dst,
                         void *workspace, size_t workspace_bytes, dpg_algo algo,
@@ -311,7 +312,9 @@ typedef struct {
 typedef struct dpg_server dpg_server;
 dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_server **out);
 /* Queue a request (its dst is ignored: the output is allocated in the arena at
- * admission).  Invalid requests are accepted as FAILED tickets. */
+ * admission).  Invalid requests are accepted as FAILED tickets: INVALID_ARG
+ * for a malformed request or one whose inputs overlap the arena, BUSY for one
+ * whose output and workspace can never fit the arena. */
 dpg_status dpg_server_submit(dpg_server *server, const dpg_request *req, uint64_t *ticket);
 /* *dst: device address of the output once DONE (valid until released). */
 dpg_status dpg_server_poll(dpg_server *server, uint64_t ticket, int32_t *state, dpg_status *status,

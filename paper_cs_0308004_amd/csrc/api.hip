@@ -175,7 +175,9 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
     if (n_rids > 0 && (!rids || !dst)) return DPG_ERR_INVALID_ARG;
     if (((uintptr_t)rids) % 4 != 0 || ((uintptr_t)dst) % 4 != 0) return DPG_ERR_INVALID_ARG;
     if (check_rids != 0 && check_rids != 1) return DPG_ERR_INVALID_ARG;
-    if (ranges_overlap(src, (size_t)n_src * rec_bytes, dst, (size_t)n_rids * rec_bytes)) return DPG_ERR_INVALID_ARG;
+    if (ranges_overlap(src, (size_t)n_src * rec_bytes, dst, (size_t)n_rids * rec_bytes) ||
+        ranges_overlap(rids, (size_t)n_rids * 4, dst, (size_t)n_rids * rec_bytes))
+        return DPG_ERR_INVALID_ARG;
     RetrievePlan plan;
     st = make_retrieve_plan(ctx, n_src, rec_bytes, n_rids, algo, &plan);
     if (st != DPG_OK) return st;
@@ -184,6 +186,7 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
         if (workspace_bytes < plan.workspace) return DPG_ERR_WORKSPACE_TOO_SMALL;
         if (!workspace || ((uintptr_t)workspace) % kAlign != 0) return DPG_ERR_INVALID_ARG;
         if (ranges_overlap(workspace, plan.workspace, dst, (size_t)n_rids * rec_bytes) ||
+            ranges_overlap(workspace, plan.workspace, rids, (size_t)n_rids * 4) ||
             ranges_overlap(workspace, plan.workspace, src, (size_t)n_src * rec_bytes))
             return DPG_ERR_INVALID_ARG;
     }

@@ -56,28 +56,44 @@ constexpr int kBatchItemWords = 16384;  // ~64 KiB of output per work item
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// Descriptor pointers are read from memory, so the compiler sees them as
+// generic (flat) addresses; flat loads also wait on the LDS counter and were
+// issued one at a time.  All of them point at device memory.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p) {
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 // Copy the item's rows: element e of the flattened (row, element) space with
-// VEC dwords per element.
+// VEC dwords per element.  Loads carry no branches (lanes past the item repeat
+// its last element), so all kBatchPer of a lane are in flight together.
 template <typename E, bool NT>
 __device__ __forceinline__ void batch_copy(const BatchDesc &d, const int32_t *s_ia, const int32_t *s_ib, int rows,
                                            int64_t row0) {
     constexpr int VEC = sizeof(E) / 4;
     const int wa = d.wa / VEC, wb = d.wb / VEC, W = wa + wb;
-    const E *A = (const E *)d.a;
-    const E *B = (const E *)d.b;
-    E *o = (E *)d.out + row0 * W;
+    const auto *A = as_global((const E *)d.a);
+    const auto *B = as_global((const E *)(d.b ? d.b : d.a));
+    auto *o = as_global((E *)d.out + row0 * W);
     const int total = rows * W;
     for (int e0 = 0; e0 < total; e0 += kBatchThreads * kBatchPer) {
-        E v[kBatchPer];
+        int64_t off[kBatchPer];
+        bool in_a[kBatchPer];
 #pragma unroll
         for (int k = 0; k < kBatchPer; ++k) {
-            const int e = e0 + threadIdx.x + k * kBatchThreads;
-            if (e < total) {
-                const int j = W == 1 ? e : (int)__umulhi((uint32_t)e, d.magic);
-                const int w = e - j * W;
-                v[k] = w < wa ? A[(int64_t)s_ia[j] * wa + w] : B[(int64_t)s_ib[j] * wb + (w - wa)];
-            }
+            const int e = min(e0 + (int)threadIdx.x + k * kBatchThreads, total - 1);
+            const int j = W == 1 ? e : (int)__umulhi((uint32_t)e, d.magic);
+            const int w = e - j * W;
+            in_a[k] = w < wa;
+            off[k] = in_a[k] ? (int64_t)s_ia[j] * wa + w : (int64_t)s_ib[j] * wb + (w - wa);
         }
+        E v[kBatchPer];
+#pragma unroll
+        for (int k = 0; k < kBatchPer; ++k) v[k] = (in_a[k] ? A : B)[off[k]];
 #pragma unroll
         for (int k = 0; k < kBatchPer; ++k) {
             const int e = e0 + threadIdx.x + k * kBatchThreads;
@@ -122,16 +138,22 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__re
         const BatchDesc d = descs[r];
         const int64_t row0 = (item - d.item_start) * d.tile_rows;
         const int rows = (int)min((int64_t)d.tile_rows, d.n_rows - row0);
-        for (int j = threadIdx.x; j < rows; j += kBatchThreads) {
-            int64_t ia = d.idx_a ? (int64_t)d.idx_a[row0 + j] : row0 + j;
-            ia = (ia >= 0 && ia < d.lim_a) ? ia : 0;
-            int64_t ib = 0;
+        {
+            const auto *ga = as_global(d.a);
+            const auto *gi = as_global(d.idx_a);
+            const int64_t lim_a = d.lim_a, lim_b = d.lim_b;
+            const int wa = d.wa, fk_word = d.fk_word;
+            auto clamp_a = [=](int64_t ia) -> int64_t { return (ia >= 0 && ia < lim_a) ? ia : 0; };
+            if (d.idx_a) stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(gi[row0 + j]); });
+            else stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(row0 + j); });
             if (d.wb > 0) {
-                ib = (int64_t)d.a[ia * d.wa + d.fk_word];
-                ib = (ib >= 0 && ib < d.lim_b) ? ib : 0;
+                auto fk = [=](int64_t ia) -> int32_t {
+                    const int64_t ib = ga[ia * wa + fk_word];
+                    return ib < lim_b ? (int32_t)ib : 0;
+                };
+                if (d.idx_a) stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(gi[row0 + j])); });
+                else stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(row0 + j)); });
             }
-            s_ia[j] = (int32_t)ia;
-            s_ib[j] = (int32_t)ib;
         }
         __syncthreads();
         if (d.vec == 4) {
@@ -155,15 +177,21 @@ struct BatchRequestPlan {
     size_t ws_bytes = 0;    // ... or workspace of its own phase sequence
 };
 
-static dpg_status validate_request(const dpg_request &q) {
+// With `arena` non-null the output is not placed yet: it will live somewhere in
+// [arena, arena + arena_bytes), so the inputs are checked against that whole
+// range instead of against q.dst.
+static dpg_status validate_request(const dpg_request &q, const void *arena = nullptr, size_t arena_bytes = 0) {
+    const void *out = arena ? arena : q.dst;
     if (q.kind == DPG_REQ_RETRIEVE) {
         dpg_status st = validate_records(q.n_src, q.rec_bytes, q.src, q.n > 0);
         if (st != DPG_OK) return st;
         if (q.n < 0 || q.n > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
-        if (q.n > 0 && (!q.rids || !q.dst)) return DPG_ERR_INVALID_ARG;
-        if (((uintptr_t)q.rids | (uintptr_t)q.dst) % 4) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && (!q.rids || !out)) return DPG_ERR_INVALID_ARG;
+        if (((uintptr_t)q.rids | (uintptr_t)out) % 4) return DPG_ERR_INVALID_ARG;
         if (q.n > 0 && q.n_src == 0) return DPG_ERR_RID_OUT_OF_RANGE;
-        if (ranges_overlap(q.src, (size_t)q.n_src * q.rec_bytes, q.dst, (size_t)q.n * q.rec_bytes))
+        const size_t ob = arena ? arena_bytes : (size_t)q.n * q.rec_bytes;
+        if (ranges_overlap(q.src, (size_t)q.n_src * q.rec_bytes, out, ob) ||
+            ranges_overlap(q.rids, (size_t)q.n * 4, out, ob))
             return DPG_ERR_INVALID_ARG;
         return DPG_OK;
     }
@@ -173,23 +201,34 @@ static dpg_status validate_request(const dpg_request &q) {
         if (q.rec_bytes < 4 || q.rec_bytes > kMaxRecBytes || q.rec_bytes % 4) return DPG_ERR_INVALID_ARG;
         if (q.fk_offset < 0 || q.fk_offset % 4 || q.fk_offset + 4 > q.fact_bytes) return DPG_ERR_INVALID_ARG;
         if (q.order != DPG_JOIN_FACT_ORDER && q.order != DPG_JOIN_DIM_ORDER) return DPG_ERR_INVALID_ARG;
-        if (q.n > 0 && (!q.fact || !q.dst)) return DPG_ERR_INVALID_ARG;
+        if (q.n > 0 && (!q.fact || !out)) return DPG_ERR_INVALID_ARG;
         if (q.n_src > 0 && !q.src) return DPG_ERR_INVALID_ARG;
-        if (((uintptr_t)q.fact | (uintptr_t)q.src | (uintptr_t)q.dst) % 4) return DPG_ERR_INVALID_ARG;
+        if (((uintptr_t)q.fact | (uintptr_t)q.src | (uintptr_t)out) % 4) return DPG_ERR_INVALID_ARG;
         if (q.n > 0 && q.n_src == 0) return DPG_ERR_FK_OUT_OF_RANGE;
-        const size_t ob = (size_t)q.n * (q.fact_bytes + q.rec_bytes);
-        if (ranges_overlap(q.dst, ob, q.fact, (size_t)q.n * q.fact_bytes) ||
-            ranges_overlap(q.dst, ob, q.src, (size_t)q.n_src * q.rec_bytes))
+        const size_t ob = arena ? arena_bytes : (size_t)q.n * (q.fact_bytes + q.rec_bytes);
+        if (ranges_overlap(out, ob, q.fact, (size_t)q.n * q.fact_bytes) ||
+            ranges_overlap(out, ob, q.src, (size_t)q.n_src * q.rec_bytes))
             return DPG_ERR_INVALID_ARG;
         return DPG_OK;
     }
     return DPG_ERR_INVALID_ARG;
 }
 
+// Output rows per work item: about kBatchItemWords dwords, and a multiple of
+// 256 / gcd(row bytes, 256) rows so that every item's output starts on a
+// 256-byte boundary of the (256-byte aligned) output.
 static int tile_rows_for(int words) {
     int rows = kBatchItemWords / words;
     if (rows < 1) rows = 1;
     if (rows > kBatchMaxTileRows) rows = kBatchMaxTileRows;
+    int a = words * 4, b = 256;
+    while (b) {
+        const int t = a % b;
+        a = b;
+        b = t;
+    }
+    const int step = 256 / a;
+    if (rows >= step) rows = rows / step * step;
     return rows;
 }
 
@@ -351,8 +390,9 @@ static dpg_status run_own_sequences(dpg_ctx *ctx, const dpg_request *reqs, int32
     return DPG_OK;
 }
 
-dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, bool *direct, size_t *own_ws) {
-    dpg_status st = validate_request(q);
+dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const void *arena, size_t arena_bytes,
+                              bool *direct, size_t *own_ws) {
+    dpg_status st = validate_request(q, arena, arena_bytes);
     if (st != DPG_OK) return st;
     BatchRequestPlan bp;
     st = plan_request(ctx, q, &bp);

@@ -22,12 +22,30 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr double kStreamingStoreBytes = 256.0 * 1024 * 1024;
 
+__host__ __device__ constexpr int gcd_int(int a, int b) {
+    while (b) {
+        const int t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// Records per tile: at most `raw`, and a multiple of 256 / gcd(R, 256) so that
+// every tile's output starts on a 256-byte boundary.  Streaming stores of
+// partial 128-byte lines are several times slower than whole lines on MI355X.
+__host__ __device__ constexpr int aligned_tile(int raw, int rec_bytes) {
+    const int step = 256 / gcd_int(rec_bytes, 256);
+    const int t = raw / step * step;
+    return t > 0 ? t : raw;
+}
+
 template <typename E, int WE>
 struct GatherShape {
     static constexpr int kEDw = sizeof(E) / 4;
     static constexpr int kInRange = (WE > 0 && WE * kEDw >= 16 && WE * kEDw <= 64);
     static constexpr int PER = kInRange ? WE : 32 / kEDw;        // elements per thread
-    static constexpr int TILE = WE > 0 ? (256 * PER) / WE : 0;   // records per workgroup
+    static constexpr int TILE = WE > 0 ? aligned_tile((256 * PER) / WE, WE * (int)sizeof(E)) : 0;
 };
 
 template <typename E, int WE, bool NT>
@@ -51,18 +69,20 @@ __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int
     }
     __syncthreads();
     const int total = cnt * we;
-    E v[PER];
+    // Every lane loads unconditionally (lanes past the tile repeat its last
+    // element), so the loads carry no branches and all PER stay in flight.
+    int64_t off[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        if (e < total) {
-            int j;
-            if constexpr (WE > 0) j = e / WE;
-            else j = (int)__umulhi((uint32_t)e, magic);
-            const int w = e - j * we;
-            v[k] = src[(int64_t)s_idx[j] * we + w];
-        }
+        const int e = min(threadIdx.x + k * 256, total - 1);
+        int j;
+        if constexpr (WE > 0) j = e / WE;
+        else j = (int)__umulhi((uint32_t)e, magic);
+        off[k] = (int64_t)s_idx[j] * we + (e - j * we);
     }
+    E v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = src[off[k]];
     E *out = dst + base * we;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
@@ -96,7 +116,7 @@ static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx,
     if constexpr (WE > 0) {
         tile = S::TILE;
     } else {
-        tile = (256 * S::PER) / we;
+        tile = aligned_tile((256 * S::PER) / we, we * (int)sizeof(E));
         if (tile < 1 || we < 2) return DPG_ERR_UNSUPPORTED;
         magic = (uint32_t)((0x100000000ull + (uint64_t)we - 1) / (uint64_t)we);
     }

@@ -32,6 +32,24 @@ __device__ __forceinline__ uint64_t match_lanes(uint32_t key, int nbits, uint64_
     return m;
 }
 
+// s[j] = f(j) for j in [0, cnt), spread over the workgroup's 256 lanes.  Each
+// lane evaluates f four rows at a time without branches (rows past cnt repeat
+// row cnt - 1) and then stores the rows that exist, so the global loads inside
+// f are issued back to back instead of one per loop trip.
+template <typename F>
+__device__ __forceinline__ void stage_rows(int32_t *s, int cnt, F f) {
+    for (int j0 = 0; j0 < cnt; j0 += 4 * 256) {
+        int32_t v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) v[k] = f(min(j0 + (int)threadIdx.x + k * 256, cnt - 1));
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int j = j0 + (int)threadIdx.x + k * 256;
+            if (j < cnt) s[j] = v[k];
+        }
+    }
+}
+
 // Read `v` from lane `src_lane` of the wave.
 __device__ __forceinline__ int32_t lane_read(int32_t v, int src_lane) {
     return __shfl(v, src_lane, 64);

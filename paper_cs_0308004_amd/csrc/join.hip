@@ -35,49 +35,58 @@ __global__ __launch_bounds__(256) void k_join_extract(const uint32_t *__restrict
     if (idx) idx[i] = (uint32_t)i;
 }
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 // out row i = A[ia] (wa dwords) || B[ib] (wb dwords), ia = idx_a ? idx_a[i] : i,
 // ib = idx_b ? idx_b[i] : word fk_word of A row ia.  Indices outside their
 // table are replaced by 0 (undefined result, never an out-of-bounds access).
-template <int WA, int WB, bool NT>
+// E is the access width: 16 bytes when both row sizes and all three base
+// addresses are multiples of 16, else 4.  A tile of output rows is staged as
+// (ia, ib) pairs in LDS, then its (row, element) pairs are flattened over the
+// workgroup's lanes; every lane issues its PER loads without branches (lanes
+// past the tile repeat its last element) before storing.
+template <typename E, bool NT>
 __global__ __launch_bounds__(256) void k_join_assemble(const uint32_t *__restrict__ A, int64_t lim_a,
                                                        const int32_t *__restrict__ idx_a,
                                                        const uint32_t *__restrict__ B, int64_t lim_b,
                                                        const int32_t *__restrict__ idx_b, int fk_word,
-                                                       uint32_t *__restrict__ out, int64_t n, int wa_rt, int wb_rt,
-                                                       uint32_t magic, int tile_rt, int remap) {
-    constexpr bool kFixed = WA > 0 && WB > 0;
-    constexpr int PER = 32;
+                                                       uint32_t *__restrict__ out, int64_t n, int wa_dw, int wb_dw,
+                                                       uint32_t magic, int tile, int remap) {
+    constexpr int VEC = sizeof(E) / 4;
+    constexpr int PER = 32 / VEC;
     extern __shared__ int32_t s_ab[];
-    const int wa = kFixed ? WA : wa_rt, wb = kFixed ? WB : wb_rt, W = wa + wb;
-    const int tile = kFixed ? (256 * PER) / (WA + WB) : tile_rt;
     int32_t *s_a = s_ab, *s_b = s_ab + tile;
     const int64_t t = xcd_tile(blockIdx.x, gridDim.x, remap);
     const int64_t base = t * tile;
     const int cnt = (int)min((int64_t)tile, n - base);
-#pragma unroll 4
-    for (int j = threadIdx.x; j < cnt; j += 256) {
-        int64_t ia = idx_a ? (int64_t)idx_a[base + j] : base + j;
-        ia = (ia >= 0 && ia < lim_a) ? ia : 0;
-        int64_t ib = idx_b ? (int64_t)idx_b[base + j] : (int64_t)A[ia * wa + fk_word];
-        ib = (ib >= 0 && ib < lim_b) ? ib : 0;
-        s_a[j] = (int32_t)ia;
-        s_b[j] = (int32_t)ib;
-    }
+    // Stage (ia, ib) per row.  The branches on idx_a / idx_b are uniform and
+    // sit outside the row loops.
+    auto clamp_a = [=](int64_t ia) -> int64_t { return (ia >= 0 && ia < lim_a) ? ia : 0; };
+    auto clamp_b = [=](int64_t ib) -> int32_t { return (ib >= 0 && ib < lim_b) ? (int32_t)ib : 0; };
+    if (idx_a) stage_rows(s_a, cnt, [&](int j) { return (int32_t)clamp_a(idx_a[base + j]); });
+    else stage_rows(s_a, cnt, [&](int j) { return (int32_t)clamp_a(base + j); });
+    if (idx_b)
+        stage_rows(s_b, cnt, [&](int j) { return clamp_b(idx_b[base + j]); });
+    else if (idx_a)
+        stage_rows(s_b, cnt, [&](int j) { return clamp_b(A[clamp_a(idx_a[base + j]) * wa_dw + fk_word]); });
+    else
+        stage_rows(s_b, cnt, [&](int j) { return clamp_b(A[clamp_a(base + j) * wa_dw + fk_word]); });
     __syncthreads();
+    const int wa = wa_dw / VEC, wb = wb_dw / VEC, W = wa + wb;
     const int total = cnt * W;
-    uint32_t v[PER];
+    const E *Ae = (const E *)A, *Be = (const E *)B;
+    const E *ptr[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = threadIdx.x + k * 256;
-        if (e < total) {
-            int j;
-            if constexpr (kFixed) j = e / (WA + WB);
-            else j = (int)__umulhi((uint32_t)e, magic);
-            const int w = e - j * W;
-            v[k] = w < wa ? A[(int64_t)s_a[j] * wa + w] : B[(int64_t)s_b[j] * wb + (w - wa)];
-        }
+        const int e = min(threadIdx.x + k * 256, total - 1);
+        const int j = (int)__umulhi((uint32_t)e, magic);
+        const int w = e - j * W;
+        ptr[k] = w < wa ? Ae + ((int64_t)s_a[j] * wa + w) : Be + ((int64_t)s_b[j] * wb + (w - wa));
     }
-    uint32_t *o = out + base * W;
+    E v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = *ptr[k];
+    E *o = (E *)out + base * W;
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = threadIdx.x + k * 256;
@@ -88,23 +97,39 @@ __global__ __launch_bounds__(256) void k_join_assemble(const uint32_t *__restric
     }
 }
 
-template <int WA, int WB>
+// Output rows per tile: a multiple of 256 / gcd(row bytes, 256), so that every
+// tile's output starts on a 256-byte boundary (whole-line streaming stores).
+static int join_tile_rows(int raw, int row_bytes) {
+    int a = row_bytes, b = 256;
+    while (b) {
+        const int t = a % b;
+        a = b;
+        b = t;
+    }
+    const int step = 256 / a;
+    const int rows = raw / step * step;
+    return rows > 0 ? rows : raw;
+}
+
+template <typename E>
 static dpg_status launch_assemble_t(const uint32_t *A, int64_t lim_a, const int32_t *idx_a, const uint32_t *B,
                                     int64_t lim_b, const int32_t *idx_b, int fk_word, uint32_t *out, int64_t n,
                                     int wa, int wb, int remap, hipStream_t stream) {
-    const int W = wa + wb;
-    const int tile = (256 * 32) / W;
-    if (tile < 1) return DPG_ERR_UNSUPPORTED;
+    constexpr int VEC = sizeof(E) / 4;
+    const int W = (wa + wb) / VEC;  // elements per output row (>= 2)
+    const int tile = join_tile_rows((256 * (32 / VEC)) / W, (wa + wb) * 4);
+    if (tile < 1 || W < 2) return DPG_ERR_UNSUPPORTED;
     const uint32_t magic = (uint32_t)((0x100000000ull + (uint64_t)W - 1) / (uint64_t)W);
     const int64_t grid = (n + tile - 1) / tile;
+    if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
     const size_t lds = 2 * (size_t)tile * sizeof(int32_t);
-    const bool nt = (double)n * W * 4 > kJoinStreamingBytes;
+    const bool nt = (double)n * (wa + wb) * 4 > kJoinStreamingBytes;
     if (nt)
-        hipLaunchKernelGGL((k_join_assemble<WA, WB, true>), dim3((unsigned)grid), dim3(256), lds, stream, A, lim_a,
-                           idx_a, B, lim_b, idx_b, fk_word, out, n, wa, wb, magic, tile, remap);
+        hipLaunchKernelGGL((k_join_assemble<E, true>), dim3((unsigned)grid), dim3(256), lds, stream, A, lim_a, idx_a,
+                           B, lim_b, idx_b, fk_word, out, n, wa, wb, magic, tile, remap);
     else
-        hipLaunchKernelGGL((k_join_assemble<WA, WB, false>), dim3((unsigned)grid), dim3(256), lds, stream, A, lim_a,
-                           idx_a, B, lim_b, idx_b, fk_word, out, n, wa, wb, magic, tile, remap);
+        hipLaunchKernelGGL((k_join_assemble<E, false>), dim3((unsigned)grid), dim3(256), lds, stream, A, lim_a, idx_a,
+                           B, lim_b, idx_b, fk_word, out, n, wa, wb, magic, tile, remap);
     DPG_HIP(hipGetLastError());
     return DPG_OK;
 }
@@ -116,11 +141,12 @@ static dpg_status launch_assemble(dpg_ctx *ctx, const void *A, int64_t lim_a, co
     const double bytes = (double)n * (2.0 * (a_bytes + b_bytes) + (idx_a ? 4 : 0) + (idx_b ? 4 : 0));
     ProfScope prof(ctx, K_JOIN_ASSEMBLE, bytes, stream);
     const int wa = a_bytes / 4, wb = b_bytes / 4, remap = xcd_remap_flag(ctx);
-    if (wa == 4 && wb == 16)
-        return launch_assemble_t<4, 16>((const uint32_t *)A, lim_a, idx_a, (const uint32_t *)B, lim_b, idx_b, fk_word,
+    const uintptr_t al = (uintptr_t)A | (uintptr_t)B | (uintptr_t)out;
+    if (a_bytes % 16 == 0 && b_bytes % 16 == 0 && al % 16 == 0)
+        return launch_assemble_t<u32x4>((const uint32_t *)A, lim_a, idx_a, (const uint32_t *)B, lim_b, idx_b, fk_word,
                                         (uint32_t *)out, n, wa, wb, remap, stream);
-    return launch_assemble_t<0, 0>((const uint32_t *)A, lim_a, idx_a, (const uint32_t *)B, lim_b, idx_b, fk_word,
-                                   (uint32_t *)out, n, wa, wb, remap, stream);
+    return launch_assemble_t<uint32_t>((const uint32_t *)A, lim_a, idx_a, (const uint32_t *)B, lim_b, idx_b, fk_word,
+                                       (uint32_t *)out, n, wa, wb, remap, stream);
 }
 
 struct JoinPlan {

@@ -435,10 +435,8 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
     tk.submit = Clock::now();
     bool direct = false;
     size_t own_ws = 0;
-    // the output will live in the arena: validate against the arena's address
-    tk.req.dst = s->base;
-    tk.status = plan_batch_request(s->ctx, tk.req, &direct, &own_ws);
-    tk.req.dst = nullptr;
+    // the output will live somewhere in the arena: inputs must lie outside it
+    tk.status = plan_batch_request(s->ctx, tk.req, s->base, s->cfg.arena_bytes, &direct, &own_ws);
     if (tk.status == DPG_OK) {
         const size_t max_batched = (size_t)(s->cfg.batch_max_kib > 0 ? s->cfg.batch_max_kib : 4096) << 10;
         tk.batched = direct && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;

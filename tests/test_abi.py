@@ -91,8 +91,9 @@ def test_retrieve_argument_validation():
     assert call(src=SRC + 2) == E.ERR_INVALID_ARG
     assert call(algo=7) == E.ERR_INVALID_ARG
     assert call(check=2) == E.ERR_INVALID_ARG
-    # overlapping src and dst
+    # overlapping src and dst, rids and dst, rids and workspace
     assert call(dst=SRC + 400) == E.ERR_INVALID_ARG
+    assert call(dst=RIDS + 8) == E.ERR_INVALID_ARG
     # no source records but rids to retrieve: every rid is out of range
     assert call(n_src=0, src=0) == E.ERR_RID_OUT_OF_RANGE
     # workspace: too small, missing, misaligned, overlapping
@@ -101,6 +102,7 @@ def test_retrieve_argument_validation():
     assert call(algo=dpg.ALGO_DPG, ws=0, ws_bytes=need) == E.ERR_INVALID_ARG
     assert call(algo=dpg.ALGO_DPG, ws=WS + 16, ws_bytes=need) == E.ERR_INVALID_ARG
     assert call(algo=dpg.ALGO_DPG, ws=DST, ws_bytes=need) == E.ERR_INVALID_ARG
+    assert call(algo=dpg.ALGO_DPG, ws=RIDS - 256, ws_bytes=need) == E.ERR_INVALID_ARG
     # empty rid list with valid arguments passes validation (then needs a context)
     assert call(n=0, rids=0, dst=0, ws=0, ws_bytes=0) == E.ERR_INVALID_ARG
 
@@ -134,5 +136,9 @@ def test_batch_validation_without_device():
     bad.kind = 5
     arr4 = (dpg.Request * 1)(bad)
     assert lib.dpg_batch_run(None, arr4, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
+    bad = dpg.Request.from_buffer_copy(good)
+    bad.dst = RIDS + 4  # output over the rid list
+    arr5 = (dpg.Request * 1)(bad)
+    assert lib.dpg_batch_run(None, arr5, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
     assert lib.dpg_batch_graph_workspace_bytes(None, 0) == 0
     assert lib.dpg_batch_graph_workspace_bytes(None, 16) > 0
