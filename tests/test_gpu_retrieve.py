@@ -75,6 +75,10 @@ CASES = [
     (4000, 4000, 128, "identity"),
     (2500, 6000, 256, "uniform"),
     (300, 700, 4096, "uniform"),
+    (9001, 9001, 120, "perm"),
+    (5003, 7001, 96, "uniform"),
+    (2000, 3000, 1000, "perm"),
+    (6007, 6007, 32, "reverse"),
     (1, 5, 100, "same"),
     (3, 1, 24, "uniform"),
 ]
