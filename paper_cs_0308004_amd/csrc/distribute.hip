@@ -8,9 +8,12 @@
 //                      bucket sort of Section 5.3, also giving run_off[b]
 //   3. k_dist_scatter  one wave per tile walks its rids in list order and
 //                      appends each to its run: run[pos] = r, inv[i] = pos.
-// Appending in list order keeps every run in RID order (the stability the
-// gather of Phase III relies on); inv[i] names the INTERNAL slot that will hold
-// the record of the i-th rid, so the gather needs no search.
+// Appending in list order keeps every run in RID order, as Figure 1 does;
+// inv[i] names the INTERNAL slot that will hold the record of the i-th rid, so
+// the gather needs no search and does not depend on the order inside a run.
+// When B fits one 8-bit digit the distribute is instead one partition pass
+// (partition.hip) whose order inside a run is unspecified; inv keeps the
+// result exact.
 //
 // A rid outside [0, n_src) is skipped (its inv is 0), so no kernel of the
 // pipeline can address memory outside its buffers even on invalid input.
@@ -108,7 +111,7 @@ dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t 
         int32_t *item_off = p.probe == DPG_PROBE_LDS ? (int32_t *)(w + p.off_items) : nullptr;
         return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv),
                                 p.log2_run, (uint64_t)p.n_src, w + p.off_part, stream, nullptr, item_off,
-                                p.probe == DPG_PROBE_LDS ? p.probe_chunk : 0);
+                                p.probe == DPG_PROBE_LDS ? p.probe_chunk : 0, /*stable=*/false);
     }
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);

@@ -5,6 +5,7 @@
 // foreign-key sort of the DPG-Sort join (Section 4.2.1).
 //
 //   k_part_hist     per tile of T elements: digit counts -> cnt[t][d]
+//                   (LDS atomics into one histogram per wave)
 //   column scan     (scan.hip) -> off[t][d], bucket_off[d]
 //   k_part_scatter  per tile: stable rank of every element within its digit
 //                   (one ballot per digit bit inside a wave; each wave owns a
@@ -13,6 +14,10 @@
 //                   out as one contiguous segment per digit -- coalesced,
 //                   unlike a per-element scatter.  Optionally inv[i] = output
 //                   position of input element i, written in input order.
+//
+//   k_part_scatter_unstable  the DPG distribute's variant: the same tile
+//                   layout and offsets, ranks from LDS atomics, so the order
+//                   inside a bucket is unspecified (the gather follows inv).
 //
 // Keys are uint32 or uint64; an optional uint32 value travels with each key.
 // A key >= `limit` is invalid: counted nowhere, not moved, its inv entry 0
@@ -30,6 +35,25 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
     return (uint32_t)(key >> shift) & mask;
 }
 
+// Rank of each lane's element among the active lanes of its wave that hold
+// the same digit and sit below it, plus the running count of that digit in
+// `ctr` (LDS), which is advanced by the number of such lanes.  Order among
+// equal digits inside one row is lane order only when the row is uniform
+// (one atomic for the whole row); otherwise it is the order in which the LDS
+// serves the atomics.  Used where stability is not required.
+__device__ __forceinline__ int32_t rank_by_atomic(int32_t *ctr, uint32_t d, bool valid) {
+    const uint64_t act = __ballot(valid);
+    const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);
+    const uint64_t same = __ballot(valid && d == d0);
+    if (same == act) {  // uniform row (every row when keys are heavily skewed)
+        int32_t h = 0;
+        if (__lane_id() == 0) h = atomicAdd(&ctr[d0], (int32_t)__popcll(act));
+        h = __shfl(h, 0, 64);
+        return valid ? h + (int32_t)__popcll(act & lanemask_lt()) : -1;
+    }
+    return valid ? atomicAdd(&ctr[d], 1) : -1;
+}
+
 template <typename K>
 __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                             int nbits, uint64_t limit, int T,
@@ -42,7 +66,9 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * T;
     const int64_t end = min(base + T, n);
-    // all loads of a batch in flight before the first is used
+    // all loads of a batch in flight before the first is used; counts go to
+    // the wave's own LDS histogram with one atomic per element (one per row
+    // when the row holds a single digit)
     constexpr int kBatch = 8;
     for (int64_t i0 = base + wave * 64; i0 < end; i0 += kPartThreads * kBatch) {
         K kv[kBatch];
@@ -55,10 +81,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
             const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
-            const uint32_t d = digit_of(kv[u], shift, mask);
-            const uint64_t act = __ballot(valid);
-            const uint64_t peers = match_lanes(d, nbits, act);
-            if (valid && (peers & lanemask_lt()) == 0) h[wave][d] += __popcll(peers);
+            (void)rank_by_atomic(h[wave], digit_of(kv[u], shift, mask), valid);
         }
     }
     __syncthreads();
@@ -171,6 +194,83 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     }
 }
 
+// The same pass for uint32 keys without values when the order inside a bucket
+// does not matter (the DPG distribute, whose gather follows inv): ranks come
+// from LDS atomics instead of ballot matching, which costs one LDS atomic per
+// element rather than a ballot per digit bit.  Counts per (tile, digit) are
+// those of k_part_hist, so the column-scan offsets still apply.
+template <int PER>
+__global__ __launch_bounds__(kPartThreads) void k_part_scatter_unstable(
+    const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
+    const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int remap) {
+    constexpr int T = kPartThreads * PER;
+    __shared__ uint32_t s_key[T];
+    __shared__ int32_t s_cnt[kMaxDigitBuckets];    // count, then tile-local start
+    __shared__ int32_t s_glob[kMaxDigitBuckets];   // output start of each digit for this tile
+    __shared__ int32_t s_nvalid;
+    const int nb = 1 << nbits;
+    const uint32_t mask = (uint32_t)nb - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t t = xcd_tile(blockIdx.x, nT, remap);
+    const int64_t base = t * T;
+    const int cnt = (int)min((int64_t)T, n - base);
+    for (int d = threadIdx.x; d < nb; d += kPartThreads) {
+        s_cnt[d] = 0;
+        s_glob[d] = off[t * nb + d];
+    }
+    uint32_t key[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = k * kPartThreads + threadIdx.x;
+        key[k] = keys[base + min(e, cnt - 1)];
+    }
+    __syncthreads();
+    int32_t rank[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = k * kPartThreads + threadIdx.x;
+        const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
+        rank[k] = rank_by_atomic(s_cnt, digit_of(key[k], shift, mask), valid);
+    }
+    __syncthreads();
+    // exclusive prefix of the digit counts (one wave)
+    if (threadIdx.x < 64) {
+        int32_t carry = 0;
+        for (int d0 = 0; d0 < nb; d0 += 64) {
+            const int d = d0 + lane;
+            const int32_t c = d < nb ? s_cnt[d] : 0;
+            int32_t inc = c;
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int32_t y = __shfl_up(inc, s, 64);
+                if (lane >= s) inc += y;
+            }
+            if (d < nb) s_cnt[d] = carry + inc - c;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) s_nvalid = carry;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = k * kPartThreads + threadIdx.x;
+        if (rank[k] >= 0) {
+            const uint32_t d = digit_of(key[k], shift, mask);
+            s_key[s_cnt[d] + rank[k]] = key[k];
+            if (inv) inv[base + e] = s_glob[d] + rank[k];
+        } else if (inv && e < cnt) {
+            inv[base + e] = 0;
+        }
+    }
+    __syncthreads();
+    const int nvalid = s_nvalid;
+    for (int j = threadIdx.x; j < nvalid; j += kPartThreads) {
+        const uint32_t k = s_key[j];
+        const uint32_t d = digit_of(k, shift, mask);
+        keys_out[(int64_t)s_glob[d] + (j - s_cnt[d])] = k;
+    }
+}
+
 static int part_per(int key_bytes, bool has_val) {
     if (key_bytes == 4 && !has_val) return 32;
     return 16;
@@ -217,7 +317,7 @@ static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
-                            int item_chunk) {
+                            int item_chunk, bool stable) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -253,6 +353,15 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (p.has_val)
         return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
                                                     remap, stream);
+    if (!stable) {
+        static_assert(kPartThreads * 32 * 4 <= 48 * 1024, "static LDS of the unstable scatter");
+        if (p.per != 32) return DPG_ERR_UNSUPPORTED;
+        hipLaunchKernelGGL((k_part_scatter_unstable<32>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
+                           (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
+                           (uint32_t *)keys_out, inv, remap);
+        DPG_HIP(hipGetLastError());
+        return DPG_OK;
+    }
     return launch_scatter_t<uint32_t, false, 32>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
                                                  remap, stream);
 }
