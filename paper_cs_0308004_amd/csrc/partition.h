@@ -6,14 +6,17 @@
 
 namespace dpg {
 
-constexpr int kMaxDigitBits = 8;
+constexpr int kMaxDigitBits = 8;                    // stable passes
 constexpr int kMaxDigitBuckets = 1 << kMaxDigitBits;
+constexpr int kMaxWideBits = 12;                    // unstable uint32 passes (the DPG distribute)
+constexpr int kMaxWideBuckets = 1 << kMaxWideBits;
 
 struct PartPlan {
     int64_t n = 0;
     int nbits = 0;       // digit width; 2^nbits buckets
     int key_bytes = 4;   // 4 or 8
     bool has_val = false;
+    int threads = 256;   // workgroup size
     int per = 0;         // elements per thread
     int tile = 0;        // elements per workgroup
     int64_t n_tiles = 0, n_chunks = 0;
@@ -22,6 +25,8 @@ struct PartPlan {
 };
 
 // Layout of the scratch one pass needs (count matrix and bucket offsets).
+// nbits up to kMaxDigitBits for any pass; up to kMaxWideBits only for uint32
+// keys without values, which are then partitioned without stability.
 PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 
 // One pass: elements whose key is < limit (any key if limit is 0) move to the

@@ -94,6 +94,38 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
     }
 }
 
+// The histogram for more than 256 buckets: one table per workgroup.
+template <int THREADS>
+__global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__restrict__ keys, int64_t n,
+                                                            int shift, int nbits, uint64_t limit, int T,
+                                                            int32_t *__restrict__ cnt) {
+    extern __shared__ int32_t hw[];
+    const int nb = 1 << nbits;
+    const uint32_t mask = (uint32_t)nb - 1;
+    for (int d = threadIdx.x; d < nb; d += THREADS) hw[d] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * T;
+    const int64_t end = min(base + T, n);
+    constexpr int kBatch = 8;
+    for (int64_t i0 = base + threadIdx.x; i0 < end; i0 += (int64_t)THREADS * kBatch) {
+        uint32_t kv[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = i0 + (int64_t)u * THREADS;
+            kv[u] = keys[min(i, end - 1)];
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int64_t i = i0 + (int64_t)u * THREADS;
+            const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
+            (void)rank_by_atomic(hw, digit_of(kv[u], shift, mask), valid);
+        }
+    }
+    __syncthreads();
+    int32_t *row = cnt + (int64_t)blockIdx.x * nb;
+    for (int d = threadIdx.x; d < nb; d += THREADS) row[d] = hw[d];
+}
+
 // PER elements per thread; a tile is kPartThreads * PER elements; wave w owns
 // elements [w*64*PER, (w+1)*64*PER) of the tile, its row k being the 64
 // consecutive elements starting at w*64*PER + 64*k.
@@ -197,63 +229,81 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
 // The same pass for uint32 keys without values when the order inside a bucket
 // does not matter (the DPG distribute, whose gather follows inv): ranks come
 // from LDS atomics instead of ballot matching, which costs one LDS atomic per
-// element rather than a ballot per digit bit.  Counts per (tile, digit) are
-// those of k_part_hist, so the column-scan offsets still apply.
-template <int PER>
-__global__ __launch_bounds__(kPartThreads) void k_part_scatter_unstable(
+// element rather than a ballot per digit bit, and up to 2^13 buckets fit.
+// Counts per (tile, digit) are those of the histogram pass, so the column-scan
+// offsets still apply.  LDS: keys of the tile, then the count / start and the
+// output start of every digit.
+template <int THREADS, int PER>
+__global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
     const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int remap) {
-    constexpr int T = kPartThreads * PER;
-    __shared__ uint32_t s_key[T];
-    __shared__ int32_t s_cnt[kMaxDigitBuckets];    // count, then tile-local start
-    __shared__ int32_t s_glob[kMaxDigitBuckets];   // output start of each digit for this tile
-    __shared__ int32_t s_nvalid;
+    constexpr int T = THREADS * PER;
+    constexpr int W = THREADS / 64;
+    extern __shared__ __align__(16) char smem[];
+    uint32_t *s_key = (uint32_t *)smem;
     const int nb = 1 << nbits;
+    int32_t *s_cnt = (int32_t *)(smem + sizeof(uint32_t) * T);  // count, then tile-local start
+    int32_t *s_glob = s_cnt + nb;                               // output start of each digit for this tile
+    __shared__ int32_t s_wsum[W];
+    __shared__ int32_t s_nvalid;
     const uint32_t mask = (uint32_t)nb - 1;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t t = xcd_tile(blockIdx.x, nT, remap);
     const int64_t base = t * T;
     const int cnt = (int)min((int64_t)T, n - base);
-    for (int d = threadIdx.x; d < nb; d += kPartThreads) {
+    for (int d = threadIdx.x; d < nb; d += THREADS) {
         s_cnt[d] = 0;
         s_glob[d] = off[t * nb + d];
     }
     uint32_t key[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = k * kPartThreads + threadIdx.x;
+        const int e = k * THREADS + threadIdx.x;
         key[k] = keys[base + min(e, cnt - 1)];
     }
     __syncthreads();
     int32_t rank[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = k * kPartThreads + threadIdx.x;
+        const int e = k * THREADS + threadIdx.x;
         const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
         rank[k] = rank_by_atomic(s_cnt, digit_of(key[k], shift, mask), valid);
     }
     __syncthreads();
-    // exclusive prefix of the digit counts (one wave)
-    if (threadIdx.x < 64) {
+    // exclusive prefix of the digit counts: wave w scans the w-th slice of
+    // the digits, then the slices are offset by the totals of the slices
+    // before them
+    {
+        const int per_w = (nb + W - 1) / W;
+        const int d_lo = min(wave * per_w, nb), d_hi = min(d_lo + per_w, nb);
         int32_t carry = 0;
-        for (int d0 = 0; d0 < nb; d0 += 64) {
+        for (int d0 = d_lo; d0 < d_hi; d0 += 64) {
             const int d = d0 + lane;
-            const int32_t c = d < nb ? s_cnt[d] : 0;
+            const int32_t c = d < d_hi ? s_cnt[d] : 0;
             int32_t inc = c;
 #pragma unroll
             for (int s = 1; s < 64; s <<= 1) {
                 const int32_t y = __shfl_up(inc, s, 64);
                 if (lane >= s) inc += y;
             }
-            if (d < nb) s_cnt[d] = carry + inc - c;
+            if (d < d_hi) s_cnt[d] = carry + inc - c;
             carry += __shfl(inc, 63, 64);
         }
-        if (lane == 0) s_nvalid = carry;
+        if (lane == 0) s_wsum[wave] = carry;
+        __syncthreads();
+        int32_t before = 0, all = 0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            before += v < wave ? s_wsum[v] : 0;
+            all += s_wsum[v];
+        }
+        for (int d = d_lo + lane; d < d_hi; d += 64) s_cnt[d] += before;
+        if (threadIdx.x == 0) s_nvalid = all;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-        const int e = k * kPartThreads + threadIdx.x;
+        const int e = k * THREADS + threadIdx.x;
         if (rank[k] >= 0) {
             const uint32_t d = digit_of(key[k], shift, mask);
             s_key[s_cnt[d] + rank[k]] = key[k];
@@ -264,7 +314,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter_unstable(
     }
     __syncthreads();
     const int nvalid = s_nvalid;
-    for (int j = threadIdx.x; j < nvalid; j += kPartThreads) {
+    for (int j = threadIdx.x; j < nvalid; j += THREADS) {
         const uint32_t k = s_key[j];
         const uint32_t d = digit_of(k, shift, mask);
         keys_out[(int64_t)s_glob[d] + (j - s_cnt[d])] = k;
@@ -283,7 +333,11 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val) {
     p.key_bytes = key_bytes;
     p.has_val = has_val;
     p.per = part_per(key_bytes, has_val);
-    p.tile = kPartThreads * p.per;
+    if (nbits > kMaxDigitBits) {  // wide unstable pass: 1024 threads x 16 keys
+        p.threads = 1024;
+        p.per = 16;
+    }
+    p.tile = p.threads * p.per;
     p.n_tiles = n > 0 ? (n + p.tile - 1) / p.tile : 0;
     p.n_chunks = (p.n_tiles + 31) / 32;
     const int64_t nb = (int64_t)1 << nbits;
@@ -325,12 +379,19 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     int32_t *bucket_off = (int32_t *)(w + p.off_bucket);
     if (bucket_off_dev) *bucket_off_dev = bucket_off;
     if (p.n <= 0) return DPG_OK;
-    if (p.nbits < 1 || p.nbits > kMaxDigitBits) return DPG_ERR_UNSUPPORTED;
+    const bool wide = p.nbits > kMaxDigitBits;
+    if (p.nbits < 1 || p.nbits > kMaxWideBits) return DPG_ERR_UNSUPPORTED;
+    if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || p.per != 16))
+        return DPG_ERR_UNSUPPORTED;
     const int nb = 1 << p.nbits;
     const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
     {
         ProfScope prof(ctx, K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb, stream);
-        if (p.key_bytes == 8)
+        if (wide)
+            hipLaunchKernelGGL((k_part_hist_wide<1024>), dim3((unsigned)p.n_tiles), dim3(1024),
+                               (size_t)nb * sizeof(int32_t), stream, (const uint32_t *)keys_in, p.n, shift, p.nbits,
+                               limit, p.tile, cnt);
+        else if (p.key_bytes == 8)
             hipLaunchKernelGGL((k_part_hist<uint64_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
                                (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, cnt);
         else
@@ -354,11 +415,20 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
                                                     remap, stream);
     if (!stable) {
-        static_assert(kPartThreads * 32 * 4 <= 48 * 1024, "static LDS of the unstable scatter");
-        if (p.per != 32) return DPG_ERR_UNSUPPORTED;
-        hipLaunchKernelGGL((k_part_scatter_unstable<32>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
-                           (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
-                           (uint32_t *)keys_out, inv, remap);
+        const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb;
+        if (wide) {
+            if (lds > 64 * 1024)
+                DPG_HIP(hipFuncSetAttribute((const void *)k_part_scatter_unstable<1024, 16>,
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((k_part_scatter_unstable<1024, 16>), dim3((unsigned)p.n_tiles), dim3(1024), lds,
+                               stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
+                               (uint32_t *)keys_out, inv, remap);
+        } else {
+            if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
+            hipLaunchKernelGGL((k_part_scatter_unstable<kPartThreads, 32>), dim3((unsigned)p.n_tiles),
+                               dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit,
+                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, remap);
+        }
         DPG_HIP(hipGetLastError());
         return DPG_OK;
     }

@@ -4,14 +4,17 @@
 // The two constraints of Section 2.1 ("Constraints") become:
 //   * Phase II: one source run must fit the store that absorbs the probe's
 //     random reads.  With the LDS probe that store is the workgroup's LDS
-//     (L*R <= 64 KiB); with the cached probe it is the XCD's 4 MiB L2, shared
-//     by the runs its in-flight workgroups touch, so L*R is kept near 2 MiB,
-//     or up to 64 MiB (Infinity Cache) when that lets Phase I run as one
-//     coalesced 8-bit partition pass.
+//     (L*R <= 64 KiB); with the cached probe it is the XCD's 4 MiB L2 backed
+//     by the 256 MiB Infinity Cache, so L*R is kept at 2-4 MiB.  Measured on
+//     MI355X at 2^26 rids, runs of 2-8 MiB are within 3% of each other and of
+//     the best; the autotuner tries 256 KiB to 64 MiB.
 //   * Phases I and III: one buffer per run must fit the cache.  Here that is
-//     the LDS table of B running positions in the distribute (B <= 8192) and
-//     the B INTERNAL streams the gather reads, which the L2 and Infinity Cache
-//     hold comfortably at B <= 8192.
+//     the LDS table of B counters in the distribute (B <= 8192) and the B
+//     INTERNAL streams the gather reads, which the L2 and Infinity Cache hold
+//     comfortably at B <= 8192.
+// Phase I is one partition pass over B <= 4096 runs (an 8-bit pass up to 256
+// runs, a 12-bit one above); the append form (B <= 8192) serves as the
+// alternative the autotuner and tests can select.
 // L is a power of two so the run of rid r is r >> log2(L) (Section 2.1).
 #include <cstring>
 
@@ -22,8 +25,7 @@ namespace dpg {
 
 constexpr int64_t kMaxRuns = 8192;
 constexpr size_t kLdsRegionBytes = 64 * 1024;
-constexpr size_t kCachedRegionBytes = 2 << 20;
-constexpr size_t kMaxPartitionRegionBytes = 64 << 20;
+constexpr size_t kCachedRegionBytes = 4 << 20;
 
 dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool need_ptr) {
     if (n < 0 || n > INT32_MAX) return DPG_ERR_INVALID_ARG;
@@ -89,21 +91,18 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     } else {
         lg = floor_log2(kCachedRegionBytes / (size_t)R);
         if (lg < 0) lg = 0;
-        // Prefer runs long enough for the coalesced one-digit Phase I as long
-        // as one run stays well inside the Infinity Cache: measured on MI355X
-        // this beats more, L2-sized runs with the one-wave append.
-        const int lg_part = ilog2_ceil((N + kMaxDigitBuckets - 1) / kMaxDigitBuckets);
-        if (dist_mode != 1 && lg_part > lg && ((int64_t)R << lg_part) <= (int64_t)kMaxPartitionRegionBytes)
-            lg = lg_part;
     }
     if (lg > lg_n) lg = lg_n;
-    // B <= kMaxRuns: lengthen the runs if needed
-    while (((N + ((int64_t)1 << lg) - 1) >> lg) > kMaxRuns) ++lg;
+    // B <= kMaxRuns, and B <= kMaxWideBuckets for the one-pass partition
+    // distribute (its count matrix then stays at a quarter of the rid list):
+    // lengthen the runs if needed
+    const int64_t max_runs = (dist_mode == 1 || log2_run > 0) ? kMaxRuns : kMaxWideBuckets;
+    while (((N + ((int64_t)1 << lg) - 1) >> lg) > max_runs) ++lg;
     if (probe == DPG_PROBE_LDS && lg > lg_lds) probe = DPG_PROBE_CACHED;
     p->probe = probe;
     p->log2_run = lg;
     p->n_runs = (N + ((int64_t)1 << lg) - 1) >> lg;
-    if (p->n_runs <= kMaxDigitBuckets && dist_mode != 1) {
+    if (p->n_runs <= kMaxWideBuckets && dist_mode != 1) {
         // one coalesced partition pass (its own tile size)
         p->dist_mode = DIST_PARTITION;
         p->part_nbits = bit_length((uint64_t)(p->n_runs - 1));

@@ -1,27 +1,32 @@
 // Three-phase key-pointer sort (Section 3) with DPG as the copy phase:
-//   1. extraction of key-pointer pairs: k_sort_extract packs key bytes
-//      big-endian into a uint64 (so integer order is byte-lexicographic order)
-//      next to the record index;
+//   1. extraction of key-pointer pairs: k_sort_extract packs the first four
+//      key bytes big-endian into a uint32 (so integer order is byte-
+//      lexicographic order) next to the record index;
 //   2. sorting of the pairs: LSD radix sort, one stable 8-bit partition pass
-//      per key byte (the count bucket sort of Section 5.3, once per digit);
+//      per key byte (the count bucket sort of Section 5.3, once per digit),
+//      then k_tie_fix puts every group of equal 4-byte prefixes in final
+//      order by the remaining key bytes and the record index;
 //   3. copying of the records in the sorted order: dpg_retrieve with the
 //      sorted indices as rids (Section 2).
-// Keys longer than 8 bytes: the pairs are first sorted on bytes 0-7 only; if a
-// device check finds two equal 8-byte prefixes (k_tie_check), the pairs are
-// sorted again over the whole key, 8 bytes at a time from the last chunk to
-// the first.  Either way equal keys keep record-index order, so the result is
-// unique: lexicographic by key bytes, then by index.
+// Uniform 10-byte keys give groups of two or three at most, so the fix-up is
+// cheap.  If some group is longer than kMaxTieGroup (low-entropy keys), the
+// pairs are instead sorted over the whole key, 8 bytes at a time from the
+// last chunk to the first, each chunk by stable passes.  Either way equal
+// keys keep record-index order, so the result is unique: lexicographic by key
+// bytes, then by index.
 #include "dev_common.h"
 #include "dpg_internal.h"
 #include "partition.h"
 
 namespace dpg {
 
-// keys[j] = big-endian packing of nbytes (1..8) key bytes starting at byte
-// koff of record r = order ? order[j] : j (zero-padded low bytes); idx[j] = r.
+// keys[j] = big-endian packing of nbytes (1..sizeof(K)) key bytes starting at
+// byte koff of record r = order ? order[j] : j (zero-padded low bytes);
+// idx[j] = r.
+template <typename K>
 __global__ __launch_bounds__(256) void k_sort_extract(const uint8_t *__restrict__ src, int rec_bytes, int64_t n,
                                                       const uint32_t *__restrict__ order, int koff, int nbytes,
-                                                      uint64_t *__restrict__ keys, uint32_t *__restrict__ idx) {
+                                                      K *__restrict__ keys, uint32_t *__restrict__ idx) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= n) return;
     const uint32_t r = order ? order[j] : (uint32_t)j;
@@ -35,22 +40,66 @@ __global__ __launch_bounds__(256) void k_sort_extract(const uint8_t *__restrict_
     const uint64_t lo = (uint64_t)d0 | ((uint64_t)d1 << 32);
     uint64_t x = s ? ((lo >> (8 * s)) | ((uint64_t)d2 << (64 - 8 * s))) : lo;  // little-endian key bytes
     if (nbytes < 8) x &= (uint64_t(1) << (8 * nbytes)) - 1;
-    keys[j] = __builtin_bswap64(x);
+    if constexpr (sizeof(K) == 8) keys[j] = __builtin_bswap64(x);
+    else keys[j] = __builtin_bswap32((uint32_t)x);
     idx[j] = r;
 }
 
-// flag |= 1 if two neighbouring keys are equal.
-__global__ __launch_bounds__(256) void k_tie_check(const uint64_t *__restrict__ keys, int64_t n, int32_t *flag) {
-    int tie = 0;
-    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x + 1; j < n; j += (int64_t)gridDim.x * 256)
-        tie |= keys[j] == keys[j - 1];
-    if (__any(tie) && __lane_id() == 0) atomicOr(flag, 1);
+constexpr int kMaxTieGroup = 64;
+
+// Memcmp order of kbytes key bytes at koff of records x and y, then index.
+// Bytes are compared eight at a time, all sixteen loads issued together.
+__device__ __forceinline__ bool key_less(const uint8_t *__restrict__ src, int rec_bytes, int koff, int kbytes,
+                                         uint32_t x, uint32_t y) {
+    const uint8_t *a = src + (int64_t)x * rec_bytes + koff;
+    const uint8_t *b = src + (int64_t)y * rec_bytes + koff;
+    for (int t0 = 0; t0 < kbytes; t0 += 8) {
+        uint8_t ca[8], cb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = min(t0 + u, kbytes - 1);
+            ca[u] = a[t];
+            cb[u] = b[t];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (t0 + u < kbytes && ca[u] != cb[u]) return ca[u] < cb[u];
+    }
+    return x < y;
+}
+
+// Final order inside every group of equal prefixes of the sorted pairs: by
+// the key bytes after the prefix (koff, kbytes), then by index.  The thread at
+// a group's first element sorts it by insertion; a group longer than
+// kMaxTieGroup sets *overflow instead and is left alone.
+__global__ __launch_bounds__(256) void k_tie_fix(const uint32_t *__restrict__ keys, uint32_t *__restrict__ idx,
+                                                 int64_t n, const uint8_t *__restrict__ src, int rec_bytes,
+                                                 int koff, int kbytes, int32_t *overflow) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j + 1 >= n) return;
+    const uint32_t k = keys[j];
+    if (keys[j + 1] != k || (j > 0 && keys[j - 1] == k)) return;
+    int64_t e = j + 2;
+    while (e < n && e - j <= kMaxTieGroup && keys[e] == k) ++e;
+    if (e - j > kMaxTieGroup) {
+        atomicOr(overflow, 1);
+        return;
+    }
+    for (int64_t a = j + 1; a < e; ++a) {
+        const uint32_t x = idx[a];
+        int64_t b = a - 1;
+        while (b >= j && key_less(src, rec_bytes, koff, kbytes, x, idx[b])) {
+            idx[b + 1] = idx[b];
+            --b;
+        }
+        idx[b + 1] = x;
+    }
 }
 
 struct SortPlan {
     int64_t n = 0;
     int rec_bytes = 0, key_offset = 0, key_bytes = 0;
-    PartPlan part;
+    PartPlan part32, part64;  // passes over uint32 prefixes / over uint64 key chunks
     RetrievePlan ret;
     size_t off_keys[2] = {0, 0}, off_idx[2] = {0, 0}, off_part = 0, off_ret = 0, off_flag = 0;
     size_t workspace = 0;
@@ -69,7 +118,8 @@ static dpg_status make_sort_plan(const dpg_ctx *ctx, int64_t n, int32_t rec_byte
     p->key_bytes = key_bytes;
     const dpg_status st = make_retrieve_plan(ctx, n, rec_bytes, n, algo, &p->ret);
     if (st != DPG_OK) return st;
-    p->part = plan_partition(n, 8, 8, true);
+    p->part32 = plan_partition(n, 8, 4, true);
+    p->part64 = plan_partition(n, 8, 8, true);
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t at = off;
@@ -81,7 +131,7 @@ static dpg_status make_sort_plan(const dpg_ctx *ctx, int64_t n, int32_t rec_byte
     p->off_keys[1] = take((size_t)n * 8);
     p->off_idx[0] = take((size_t)n * 4);
     p->off_idx[1] = take((size_t)n * 4);
-    p->off_part = take(p->part.workspace);
+    p->off_part = take(p->part32.workspace > p->part64.workspace ? p->part32.workspace : p->part64.workspace);
     p->off_ret = take(p->ret.workspace);
     p->workspace = off;
     return DPG_OK;
@@ -96,7 +146,7 @@ static dpg_status sort_chunk(dpg_ctx *ctx, const SortPlan &p, const void *src, c
     const int dst_buf = order && (const char *)order == w + p.off_idx[*cur] ? 1 - *cur : *cur;
     {
         ProfScope prof(ctx, K_SORT_EXTRACT, (double)p.n * (64.0 + 12.0 + (order ? 4.0 : 0.0)), stream);
-        hipLaunchKernelGGL(k_sort_extract, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_sort_extract<uint64_t>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
                            (const uint8_t *)src, p.rec_bytes, p.n, order, p.key_offset + 8 * c, nbytes,
                            (uint64_t *)(w + p.off_keys[dst_buf]), (uint32_t *)(w + p.off_idx[dst_buf]));
         DPG_HIP(hipGetLastError());
@@ -104,9 +154,35 @@ static dpg_status sort_chunk(dpg_ctx *ctx, const SortPlan &p, const void *src, c
     *cur = dst_buf;
     for (int byte = nbytes - 1; byte >= 0; --byte) {
         const int other = 1 - *cur;
-        const dpg_status st = launch_partition(ctx, p.part, w + p.off_keys[*cur], (const uint32_t *)(w + p.off_idx[*cur]),
+        const dpg_status st = launch_partition(ctx, p.part64, w + p.off_keys[*cur], (const uint32_t *)(w + p.off_idx[*cur]),
                                                w + p.off_keys[other], (uint32_t *)(w + p.off_idx[other]), nullptr,
                                                56 - 8 * byte, 0, w + p.off_part, stream, nullptr);
+        if (st != DPG_OK) return st;
+        *cur = other;
+    }
+    return DPG_OK;
+}
+
+// Sort the pairs on the first four key bytes (stable passes, so equal
+// prefixes stay in index order); returns the buffer holding the result.
+static dpg_status sort_prefix(dpg_ctx *ctx, const SortPlan &p, const void *src, char *w, int *cur,
+                              hipStream_t stream) {
+    const int nbytes = p.key_bytes < 4 ? p.key_bytes : 4;
+    {
+        ProfScope prof(ctx, K_SORT_EXTRACT, (double)p.n * (64.0 + 8.0), stream);
+        hipLaunchKernelGGL(k_sort_extract<uint32_t>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
+                           (const uint8_t *)src, p.rec_bytes, p.n, nullptr, p.key_offset, nbytes,
+                           (uint32_t *)(w + p.off_keys[0]), (uint32_t *)(w + p.off_idx[0]));
+        DPG_HIP(hipGetLastError());
+    }
+    *cur = 0;
+    // key byte b (0 = most significant) sits at bits 24 - 8b; padding bytes
+    // past the key are zero and need no pass
+    for (int byte = nbytes - 1; byte >= 0; --byte) {
+        const int other = 1 - *cur;
+        const dpg_status st = launch_partition(ctx, p.part32, w + p.off_keys[*cur], (const uint32_t *)(w + p.off_idx[*cur]),
+                                               w + p.off_keys[other], (uint32_t *)(w + p.off_idx[other]), nullptr,
+                                               24 - 8 * byte, 0, w + p.off_part, stream, nullptr);
         if (st != DPG_OK) return st;
         *cur = other;
     }
@@ -118,25 +194,24 @@ static dpg_status run_sort(dpg_ctx *ctx, const SortPlan &p, const void *src, voi
     if (p.n == 0) return DPG_OK;
     char *w = (char *)ws;
     int cur = 0;
-    dpg_status st = sort_chunk(ctx, p, src, w, 0, nullptr, &cur, stream);
+    dpg_status st = sort_prefix(ctx, p, src, w, &cur, stream);
     if (st != DPG_OK) return st;
-    const int chunks = (p.key_bytes + 7) / 8;
-    if (chunks > 1 && p.n > 1) {
+    if (p.key_bytes > 4 && p.n > 1) {
         int32_t *flag = (int32_t *)(w + p.off_flag);
         st = launch_fill_i32(ctx, flag, 1, 0, stream);
         if (st != DPG_OK) return st;
         {
-            ProfScope prof(ctx, K_TIE_MARK, 8.0 * p.n, stream);
-            int64_t grid = (p.n + 255) / 256;
-            if (grid > (int64_t)ctx->n_cu * 16) grid = (int64_t)ctx->n_cu * 16;
-            hipLaunchKernelGGL(k_tie_check, dim3((unsigned)grid), dim3(256), 0, stream,
-                               (const uint64_t *)(w + p.off_keys[cur]), p.n, flag);
+            ProfScope prof(ctx, K_TIE_FIX, 8.0 * p.n, stream);
+            hipLaunchKernelGGL(k_tie_fix, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
+                               (const uint32_t *)(w + p.off_keys[cur]), (uint32_t *)(w + p.off_idx[cur]), p.n,
+                               (const uint8_t *)src, p.rec_bytes, p.key_offset + 4, p.key_bytes - 4, flag);
             DPG_HIP(hipGetLastError());
         }
         DPG_HIP(hipMemcpyAsync(ctx->host_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
         DPG_HIP(hipStreamSynchronize(stream));
         if (*ctx->host_flag) {
-            // full LSD over the key, last 8-byte chunk first
+            // long runs of equal prefixes: full LSD over the key, last 8-byte chunk first
+            const int chunks = (p.key_bytes + 7) / 8;
             cur = 0;
             for (int c = chunks - 1; c >= 0; --c) {
                 const uint32_t *order = c == chunks - 1 ? nullptr : (const uint32_t *)(w + p.off_idx[cur]);

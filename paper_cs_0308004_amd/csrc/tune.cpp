@@ -4,7 +4,8 @@
 // every candidate plan on the caller's buffers -- direct retrieval, and DPG
 // with each run length L whose runs span 256 KiB .. 64 MiB of source (the
 // region-size constraint of Section 2.1, "Constraints"), with both probe
-// flavours and both Phase I flavours where they apply -- and records the
+// flavours and both Phase I flavours (partition up to 4096 runs, append up
+// to 8192) where they apply -- and records the
 // fastest in the context's table.  DPG_ALGO_AUTO consults that table for
 // shapes in the same power-of-two size class.  The table can be saved to and
 // loaded from a text file (one line per shape).
@@ -31,7 +32,7 @@ static std::vector<Candidate> candidates(int64_t n_src, int32_t rec_bytes) {
         if (runs > 8192) continue;
         if (region > (64ll << 20)) break;
         if (region < (256 << 10) && lg < lg_n) continue;
-        if (runs <= kMaxDigitBuckets) c.push_back({DPG_ALGO_DPG, DPG_PROBE_CACHED, lg, 2});
+        if (runs <= kMaxWideBuckets) c.push_back({DPG_ALGO_DPG, DPG_PROBE_CACHED, lg, 2});
         if (runs > 16) c.push_back({DPG_ALGO_DPG, DPG_PROBE_CACHED, lg, 1});
     }
     // the LDS probe with its natural run length (64 KiB of source per run)
@@ -41,8 +42,8 @@ static std::vector<Candidate> candidates(int64_t n_src, int32_t rec_bytes) {
         if (lg_lds > lg_n) lg_lds = lg_n;
         const int64_t runs = (N + ((int64_t)1 << lg_lds) - 1) >> lg_lds;
         if (runs <= 8192) {
-            c.push_back({DPG_ALGO_DPG, DPG_PROBE_LDS, lg_lds, runs <= kMaxDigitBuckets ? 2 : 1});
-            if (runs <= kMaxDigitBuckets && runs > 16) c.push_back({DPG_ALGO_DPG, DPG_PROBE_LDS, lg_lds, 1});
+            if (runs <= kMaxWideBuckets) c.push_back({DPG_ALGO_DPG, DPG_PROBE_LDS, lg_lds, 2});
+            if (runs > 16) c.push_back({DPG_ALGO_DPG, DPG_PROBE_LDS, lg_lds, 1});
         }
     }
     return c;

@@ -55,6 +55,8 @@ VARIANTS = {
     "dpg-append": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_APPEND)),
     "dpg-lds-append": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_LDS, dist=dpg.DIST_APPEND)),
     "dpg-partition-long-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=12, dist=dpg.DIST_PARTITION)),
+    # 257..4096 runs: the 12-bit partition pass
+    "dpg-wide-partition": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=4, dist=dpg.DIST_PARTITION)),
     "auto": (dpg.ALGO_AUTO, {}),
 }
 
@@ -139,7 +141,10 @@ def test_phase_products_match_figure1(ctx):
                                                (3000, 9000, 16, "uniform", dpg.PROBE_LDS, 0, 1),
                                                (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0, 0),
                                                (70000, 70000, 64, "perm", dpg.PROBE_CACHED, 0, 1),
-                                               (4096, 4096, 8, "same", dpg.PROBE_LDS, 5, 0)]:
+                                               (4096, 4096, 8, "same", dpg.PROBE_LDS, 5, 0),
+                                               (20000, 20000, 32, "perm", dpg.PROBE_CACHED, 4, 2),
+                                               (3000, 9000, 16, "uniform", dpg.PROBE_CACHED, 2, 2),
+                                               (50000, 50000, 8, "same", dpg.PROBE_CACHED, 4, 2)]:
         src = synth.record_bytes(n, rec, seed=n)
         rids = make_rids(kind, n, m, rec, seed=n)
         configure(ctx, probe=probe, log2_run=lg, dist=dist)
