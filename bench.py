@@ -3,15 +3,15 @@
 Headline workload (the metric's configuration): 2^26 source records of 100 B
 (10-byte uniform key + 90-byte payload), rids a pseudo-random permutation of
 [0, 2^26), 2^26 outputs.  One step is one full DPG retrieval (distribute,
-probe, gather) in the best DPG configuration the autotuner finds; the direct
-gather is timed beside it on the same inputs.  Inputs are resident in HBM
-before timing starts.
+probe, gather) with the planner's DPG plan; the autotuner's best plan and
+its time are reported beside it, and the direct gather is timed on the same
+inputs.  Inputs are resident in HBM before timing starts.
 
 Secondary measurements reported in the same JSON line (each on its own
 synthetic inputs): the key-pointer sort of 10^8 x 100 B records, the DPG-Move
 and DPG-Sort joins of 2^28 x 16 B fact rows with 2^24 x 64 B dimension rows
 under Zipf(0 / 0.8 / 1.2) keys, and the serving workload (4096 retrieval /
-join requests, log-uniform sizes, Poisson arrivals, 64 GB HBM budget):
+join requests, log-uniform sizes, Poisson arrivals, 64 GiB HBM budget):
 batched server vs per-request launches, p50 / p99 latency.
 """
 from __future__ import annotations
@@ -46,9 +46,11 @@ def parse():
     ap.add_argument("--pattern", default="perm", choices=["perm", "uniform", "blocked"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--log2-run", type=int, default=0, help="force L = 2^v records per run (0: autotuned)")
-    ap.add_argument("--probe", type=int, default=0, help="1 cached, 2 LDS (0: autotuned)")
-    ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: autotuned)")
+    ap.add_argument("--log2-run", type=int, default=0, help="force L = 2^v records per run (0: planner's choice)")
+    ap.add_argument("--probe", type=int, default=0, help="1 cached, 2 LDS (0: planner's choice)")
+    ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: also run the autotuner over the DPG plans and report its pick")
     ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
@@ -150,17 +152,20 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         b.copy_(a)  # reads and writes exactly 1 GiB
         torch.cuda.synchronize()
         del a, b
-    tuned_ms = None
+    tuned = None
     if args.log2_run or args.probe or args.dist:
         ctx.set_option(dpg.OPT_LOG2_RUN, args.log2_run)
         ctx.set_option(dpg.OPT_PROBE, args.probe)
         ctx.set_option(dpg.OPT_DISTRIBUTE, args.dist)
-    else:
+    elif args.autotune:
+        # the autotuner's pick is reported next to the planner's default plan,
+        # which is what is timed (a fixed plan keeps profiles comparable)
         log("bench: autotuning the DPG configuration")
         best, tuned_ms = ctx.autotune_retrieve(src, rids, dst, reps=2, dpg_only=True)
-        ctx.set_option(dpg.OPT_LOG2_RUN, best.log2_run)
-        ctx.set_option(dpg.OPT_PROBE, best.probe)
-        ctx.set_option(dpg.OPT_DISTRIBUTE, 2 if best.n_runs <= 256 else 1)
+        tuned = {"ms": round(tuned_ms, 4), "log2_run": best.log2_run, "n_runs": best.n_runs,
+                 "probe": {1: "cached", 2: "lds"}.get(best.probe, "?"),
+                 "distribute": {1: "append", 2: "partition"}.get(best.distribute, "?")}
+        ctx.tune_clear()
     plan = ctx.plan_retrieve(n, R, m, dpg.ALGO_DPG)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
     ws_direct = torch.empty(256, dtype=torch.uint8, device=dev)
@@ -195,9 +200,9 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         raise SystemExit("bench: DPG output differs from the generator's records")
     delivered = m * R
     # counter data apply only to the same shape and DPG plan
-    wkey = f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}"
-    dpg_kernels = ["k_part_hist", "k_part_scatter", "k_dist_hist", "k_dist_scatter", "k_probe_cached",
-                   "k_probe_lds", "k_gather_phase"]
+    wkey = f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}:dist{plan.distribute}"
+    dpg_kernels = ["k_part_hist", "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable", "k_dist_hist",
+                   "k_dist_scatter", "k_probe_cached", "k_probe_lds", "k_gather_phase"]
     out = {
         "value": round(delivered / (ms_dpg * 1e-3) / 1e9, 2),
         "ms_per_step": round(ms_dpg, 4),
@@ -205,8 +210,9 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
             "workload": f"DPG record retrieval, N=M=2^{args.log2n}, {R}-byte records, rids {args.pattern}",
             "n_src": n, "n_rids": m, "rec_bytes": R, "rid_pattern": args.pattern,
             "algo": "dpg", "log2_run": plan.log2_run, "n_runs": plan.n_runs, "dist_tile": plan.dist_tile,
+            "distribute": {1: "append", 2: "partition"}.get(plan.distribute, "?"),
             "probe": {1: "cached", 2: "lds"}.get(plan.probe, "?"),
-            "autotuned_ms": None if tuned_ms is None else round(tuned_ms, 4),
+            "autotuned": tuned,
         },
         "roofline": roofline_entry(prof_dpg, dpg_kernels, counters, wkey),
         "direct": {
@@ -297,7 +303,7 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
     """4096 requests (75 % retrievals, 25 % fact-order or dimension-order
     joins), N log-uniform in [2^10, 2^max_log2], record size uniform over
     {16, 64, 100, 256} B, rids a random permutation of [0, N); tables resident;
-    Poisson arrivals; admission under a 64 GB arena."""
+    Poisson arrivals; admission under a 64 GiB arena."""
     dev = "cuda:0"
     n_req = args.serve_requests
     seed = synth.SEED_BASE + 4 + seed_off
@@ -365,7 +371,7 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
 
     res = {"workload": f"{n_req} requests: 75% retrieval, 25% FK join (either order); N log-uniform "
                        f"[2^10, 2^{max_log2}]; record size uniform over {{16,64,100,256}} B; random-permutation rids; "
-                       f"resident tables; Poisson arrivals; 64 GB HBM budget",
+                       f"resident tables; Poisson arrivals; 64 GiB HBM budget",
            "output_GB_total": round(out_bytes / 1e9, 2)}
     budget = 64 << 30
     modes = {"batched_graph": dict(max_inflight=4, max_batch_requests=256, use_graph=True),

@@ -98,14 +98,19 @@ typedef struct {
     int32_t probe;         /* DPG_PROBE_CACHED or DPG_PROBE_LDS (DPG only) */
     int32_t log2_run;      /* L = 2^log2_run source records per run */
     int32_t dist_tile;     /* rids per distribute tile */
+    int32_t distribute;    /* Phase I form: 1 append, 2 partition (DPG only; the
+                              values of DPG_OPT_DISTRIBUTE) */
+    int32_t reserved;      /* 0 */
     int64_t n_runs;        /* B = ceil(n_src / L), the paper's NUM_RUNS */
     int64_t n_tiles;       /* ceil(n_rids / dist_tile) */
     size_t workspace_bytes;
     /* After a DPG retrieval the workspace holds the phase products at these
      * byte offsets (0 when algo is direct), for inspection or pipelining:
      *   run_off  int32[n_runs + 1]  start of RID run b in rid_run (Phase I)
-     *   rid_run  int32[n_rids]      the RID runs, one after another, each in
-     *                               rid-list order (Phase I)
+     *   rid_run  int32[n_rids]      the RID runs, one after another (Phase
+     *                               I); each run in rid-list order with the
+     *                               append distribute, in unspecified order
+     *                               with the partition distribute
      *   internal n_rids records     the INTERNAL runs (Phase II)          */
     size_t ws_run_off;
     size_t ws_rid_run;

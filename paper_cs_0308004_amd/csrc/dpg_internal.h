@@ -60,6 +60,8 @@ enum KernelId {
     K_BATCH,
     K_PART_HIST,
     K_PART_SCATTER,
+    K_PART_HIST_WIDE,
+    K_PART_SCATTER_UNSTABLE,
     K_COUNT
 };
 const char *kernel_name(int id);

@@ -386,7 +386,8 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     const int nb = 1 << p.nbits;
     const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
     {
-        ProfScope prof(ctx, K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb, stream);
+        ProfScope prof(ctx, wide ? K_PART_HIST_WIDE : K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb,
+                       stream);
         if (wide)
             hipLaunchKernelGGL((k_part_hist_wide<1024>), dim3((unsigned)p.n_tiles), dim3(1024),
                                (size_t)nb * sizeof(int32_t), stream, (const uint32_t *)keys_in, p.n, shift, p.nbits,
@@ -402,7 +403,8 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     dpg_status st = launch_column_scan(ctx, cnt, p.n_tiles, nb, csum, p.n_chunks, total, bucket_off, item_off,
                                        item_chunk, stream);
     if (st != DPG_OK) return st;
-    ProfScope prof(ctx, K_PART_SCATTER, 2.0 * elem * p.n + (inv ? 4.0 * p.n : 0.0) + 4.0 * p.n_tiles * nb, stream);
+    ProfScope prof(ctx, stable ? K_PART_SCATTER : K_PART_SCATTER_UNSTABLE,
+                   2.0 * elem * p.n + (inv ? 4.0 * p.n : 0.0) + 4.0 * p.n_tiles * nb, stream);
     const int remap = xcd_remap_flag(ctx);
     if (p.key_bytes == 8) {
         if (p.has_val)

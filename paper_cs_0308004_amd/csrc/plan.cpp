@@ -190,6 +190,7 @@ extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32
     out->probe = p.algo == DPG_ALGO_DPG ? p.probe : 0;
     out->log2_run = p.log2_run;
     out->dist_tile = p.dist_tile;
+    out->distribute = p.algo == DPG_ALGO_DPG ? (p.dist_mode == dpg::DIST_PARTITION ? 2 : 1) : 0;
     out->n_runs = p.n_runs;
     out->n_tiles = p.n_tiles;
     out->workspace_bytes = p.workspace;

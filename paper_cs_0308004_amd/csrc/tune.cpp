@@ -127,6 +127,7 @@ dpg_status dpg_autotune_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, i
         best->probe = e.probe;
         best->log2_run = best_p.log2_run;
         best->dist_tile = best_p.dist_tile;
+        best->distribute = e.dist_mode;
         best->n_runs = best_p.n_runs;
         best->n_tiles = best_p.n_tiles;
         best->workspace_bytes = best_p.workspace;

@@ -34,7 +34,7 @@ class DPGError(RuntimeError):
 
 class Plan(ctypes.Structure):
     _fields_ = [("algo", _I32), ("probe", _I32), ("log2_run", _I32), ("dist_tile", _I32),
-                ("n_runs", _I64), ("n_tiles", _I64), ("workspace_bytes", _SZ),
+                ("distribute", _I32), ("reserved", _I32), ("n_runs", _I64), ("n_tiles", _I64), ("workspace_bytes", _SZ),
                 ("ws_run_off", _SZ), ("ws_rid_run", _SZ), ("ws_internal", _SZ)]
 
 
