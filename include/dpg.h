@@ -72,8 +72,11 @@ typedef enum {
     DPG_OPT_DIST_TILE = 3,  /* rids per distribute tile (multiple of 64) */
     DPG_OPT_XCD_REMAP = 4,  /* 1 (default): tiles of one XCD are contiguous; 2: off */
     DPG_OPT_USE_TUNED = 5,  /* 1 (default): consult the autotune table; 2: ignore it */
-    DPG_OPT_DISTRIBUTE = 6  /* Phase I: 1 one-wave append (any run count up to 8192),
-                               2 coalesced partition pass (used only when runs <= 256) */
+    DPG_OPT_DISTRIBUTE = 6, /* Phase I: 1 append (any run count up to 8192),
+                               2 coalesced partition pass (used only when runs <= 4096) */
+    DPG_OPT_GATHER = 7      /* Phase III: 1 INTERNAL read through the caches, 2 a
+                               distribute tile's records staged in LDS (used only
+                               with the partition distribute when they fit) */
 } dpg_option;
 
 typedef struct dpg_ctx dpg_ctx;
@@ -100,7 +103,8 @@ typedef struct {
     int32_t dist_tile;     /* rids per distribute tile */
     int32_t distribute;    /* Phase I form: 1 append, 2 partition (DPG only; the
                               values of DPG_OPT_DISTRIBUTE) */
-    int32_t reserved;      /* 0 */
+    int32_t gather;        /* Phase III form: 1 cached, 2 LDS-staged (DPG only;
+                              the values of DPG_OPT_GATHER) */
     int64_t n_runs;        /* B = ceil(n_src / L), the paper's NUM_RUNS */
     int64_t n_tiles;       /* ceil(n_rids / dist_tile) */
     size_t workspace_bytes;

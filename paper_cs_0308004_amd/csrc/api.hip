@@ -10,7 +10,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_scan_apply",   "k_dist_scatter", "k_probe_cached", "k_probe_lds",     "k_gather_phase",
     "k_check_ids",    "k_fill_i32",     "k_sort_extract", "k_radix_hist",    "k_radix_scatter",
     "k_tie_check",    "k_tie_fix",      "k_join_extract", "k_join_assemble", "k_join_stream",
-    "k_batch",        "k_part_hist",    "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable"};
+    "k_batch",        "k_part_hist",    "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable", "k_gather_lds"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 
@@ -41,10 +41,11 @@ ProfScope::~ProfScope() {
 }
 
 dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
-                                void *ws, hipStream_t stream) {
+                                void *ws, hipStream_t stream, bool local_inv) {
     const double R = p.rec_bytes, M = (double)p.n_rids;
     char *w = (char *)ws;
-    dpg_status st = launch_distribute(ctx, p, rids, ws, stream);
+    if (local_inv && !p.gather_lds) return DPG_ERR_UNSUPPORTED;
+    dpg_status st = launch_distribute(ctx, p, rids, ws, stream, local_inv);
     if (st != DPG_OK) return st;
     if (p.probe == DPG_PROBE_LDS) return launch_probe_lds(ctx, p, src, ws, stream);
     const double touched = (double)(p.n_src < p.n_rids ? p.n_src : p.n_rids);
@@ -60,8 +61,9 @@ dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, co
         return launch_gather(ctx, K_DIRECT_GATHER, src, p.n_src, rids, dst, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M,
                              stream);
     char *w = (char *)ws;
-    const dpg_status st = run_distribute_probe(ctx, p, src, rids, ws, stream);
+    const dpg_status st = run_distribute_probe(ctx, p, src, rids, ws, stream, p.gather_lds);
     if (st != DPG_OK) return st;
+    if (p.gather_lds) return launch_gather_lds(ctx, p, ws, dst, stream);
     return launch_gather(ctx, K_GATHER_PHASE, w + p.off_internal, p.n_rids, (const int32_t *)(w + p.off_inv), dst,
                          p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
 }
@@ -148,6 +150,10 @@ dpg_status dpg_set_option(dpg_ctx *ctx, dpg_option option, int64_t value) {
             if (value > 2) return DPG_ERR_INVALID_ARG;
             ctx->opt_distribute = value;
             return DPG_OK;
+        case DPG_OPT_GATHER:
+            if (value > 2) return DPG_ERR_INVALID_ARG;
+            ctx->opt_gather = value;
+            return DPG_OK;
     }
     return DPG_ERR_INVALID_ARG;
 }
@@ -161,6 +167,7 @@ dpg_status dpg_get_option(const dpg_ctx *ctx, dpg_option option, int64_t *value)
         case DPG_OPT_XCD_REMAP: *value = ctx->opt_xcd; return DPG_OK;
         case DPG_OPT_USE_TUNED: *value = ctx->opt_use_tuned; return DPG_OK;
         case DPG_OPT_DISTRIBUTE: *value = ctx->opt_distribute; return DPG_OK;
+        case DPG_OPT_GATHER: *value = ctx->opt_gather; return DPG_OK;
     }
     return DPG_ERR_INVALID_ARG;
 }

@@ -104,14 +104,15 @@ __global__ __launch_bounds__(64) void k_dist_scatter(const int32_t *__restrict__
 }
 
 dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,
-                             hipStream_t stream) {
+                             hipStream_t stream, bool local_inv) {
     char *w = (char *)ws;
+    if (local_inv && p.dist_mode != DIST_PARTITION) return DPG_ERR_UNSUPPORTED;
     if (p.dist_mode == DIST_PARTITION) {
         const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
         int32_t *item_off = p.probe == DPG_PROBE_LDS ? (int32_t *)(w + p.off_items) : nullptr;
         return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv),
                                 p.log2_run, (uint64_t)p.n_src, w + p.off_part, stream, nullptr, item_off,
-                                p.probe == DPG_PROBE_LDS ? p.probe_chunk : 0, /*stable=*/false);
+                                p.probe == DPG_PROBE_LDS ? p.probe_chunk : 0, /*stable=*/false, local_inv);
     }
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);

@@ -62,6 +62,7 @@ enum KernelId {
     K_PART_SCATTER,
     K_PART_HIST_WIDE,
     K_PART_SCATTER_UNSTABLE,
+    K_GATHER_LDS,        // Phase III, distribute tile staged in LDS
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -102,7 +103,7 @@ struct dpg_ctx {
     size_t l2_bytes = 4u << 20;
     // options
     int64_t opt_log2_run = 0, opt_probe = 0, opt_dist_tile = 0, opt_xcd = 1, opt_use_tuned = 1;
-    int64_t opt_distribute = 0;
+    int64_t opt_distribute = 0, opt_gather = 0;
     // profiling
     bool profiling = false;
     std::vector<dpg::ProfRecord> pending;
@@ -128,8 +129,8 @@ struct ProfScope {
     ~ProfScope();
 };
 
-// Phase I flavours: one-wave append into up to 8192 runs, or one coalesced
-// partition pass when the runs fit one 8-bit digit.
+// Phase I flavours: append into up to 8192 runs, or one coalesced partition
+// pass into up to 4096 runs.
 enum { DIST_APPEND = 0, DIST_PARTITION = 1 };
 
 // Retrieval plan (resolved), shared by retrieve, sort, join and batch.
@@ -149,6 +150,8 @@ struct RetrievePlan {
     int part_nbits = 0;        // digit width of the partition pass
     size_t off_part = 0;       // partition scratch (count matrix, bucket offsets)
     int32_t probe_chunk = 0;   // run entries per LDS-probe work item
+    bool gather_lds = false;   // Phase III stages each distribute tile in LDS
+    int part_tile = 0;         // rids per partition tile (gather_lds)
     size_t workspace = 0;
 };
 
@@ -159,14 +162,20 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
 // The same with every choice explicit (0 = automatic), ignoring options and
 // the tuning table; algo must be DIRECT or DPG.
 dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo, int probe,
-                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan);
+                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan,
+                                       int gather = 0);
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
 
 // Phases I and II of a planned DPG retrieval: afterwards the workspace holds
 // INTERNAL (at off_internal) and inv (at off_inv), so a caller can fuse Phase
-// III into its own kernel.
+// III into its own kernel.  With local_inv (only for plans with gather_lds)
+// inv holds each rid's slot within its distribute tile's segments instead of
+// its INTERNAL index.
 dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
-                                void *ws, hipStream_t stream);
+                                void *ws, hipStream_t stream, bool local_inv = false);
+// Phase III staged through LDS (plans with gather_lds, after
+// run_distribute_probe with local_inv).
+dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void *dst, hipStream_t stream);
 // Enqueue a planned retrieval (arguments already validated).
 dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
                         void *dst, void *ws, hipStream_t stream);
@@ -183,7 +192,7 @@ dpg_status launch_fill_i32(dpg_ctx *ctx, int32_t *p, int64_t n, int32_t value, h
 
 // ---- distribute (distribute.hip) ----
 dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,
-                             hipStream_t stream);
+                             hipStream_t stream, bool local_inv = false);
 // ---- probe (probe.hip) ----
 dpg_status launch_probe_lds(dpg_ctx *ctx, const RetrievePlan &p, const void *src, void *ws,
                             hipStream_t stream);

@@ -1,0 +1,187 @@
+// DPG Phase III (Section 2.1, Figure 1's gather) staged through LDS.
+//
+// The partition distribute cuts the rid list into tiles of T rids and leaves
+// the records of tile t in INTERNAL as one contiguous segment per run: run b's
+// share starts at off[t][b] (the column-scanned count matrix) and ends where
+// tile t + 1's share of run b starts (or at the end of run b for the last
+// tile).  With local slots, the distribute also wrote for every rid its slot
+// in the tile's segments laid end to end in run order.
+//
+// One workgroup per tile copies the tile's segments into LDS with coalesced
+// loads (each LDS slot finds its segment by a binary search over the
+// segments' starts), then writes the tile's output rows in rid-list order,
+// each read from its slot in LDS.  Every global access is then coalesced,
+// where the cached gather spends one cache-line request per small record.
+// Used for records of 4, 8 and 16 bytes, where a tile fits the LDS.
+#include "dev_common.h"
+#include "dpg_internal.h"
+#include "partition.h"
+
+namespace dpg {
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kGatherThreads = 1024;
+constexpr int kGatherPer = 8;  // elements per thread per round, all loads in flight together
+
+template <typename E, int WE, bool NT>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restrict__ internal,
+                                                               const int32_t *__restrict__ slot, E *__restrict__ dst,
+                                                               int64_t n, int T, int nbits, int64_t nT,
+                                                               const int32_t *__restrict__ off,
+                                                               const int32_t *__restrict__ bucket_off, int remap) {
+    constexpr int W = kGatherThreads / 64;
+    extern __shared__ __align__(16) char smem[];
+    const int nb = 1 << nbits;
+    E *s_rec = (E *)smem;                                         // T * WE elements
+    int32_t *s_off = (int32_t *)(smem + sizeof(E) * (size_t)T * WE);  // INTERNAL start of each run's segment
+    int32_t *s_start = s_off + nb;                                // segment length, then start in s_rec
+    __shared__ int32_t s_wsum[W];
+    __shared__ int32_t s_total;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t t = xcd_tile(blockIdx.x, nT, remap);
+    const int64_t base = t * T;
+    const int cnt = (int)min((int64_t)T, n - base);
+    for (int d = threadIdx.x; d < nb; d += kGatherThreads) {
+        const int32_t o = off[t * nb + d];
+        const int32_t next = t + 1 < nT ? off[(t + 1) * nb + d] : bucket_off[d + 1];
+        s_off[d] = o;
+        s_start[d] = next - o;
+    }
+    __syncthreads();
+    // exclusive prefix of the segment lengths: wave w scans the w-th slice,
+    // then every slice is offset by the totals before it
+    {
+        const int per_w = (nb + W - 1) / W;
+        const int d_lo = min(wave * per_w, nb), d_hi = min(d_lo + per_w, nb);
+        int32_t carry = 0;
+        for (int d0 = d_lo; d0 < d_hi; d0 += 64) {
+            const int d = d0 + lane;
+            const int32_t c = d < d_hi ? s_start[d] : 0;
+            int32_t inc = c;
+#pragma unroll
+            for (int s = 1; s < 64; s <<= 1) {
+                const int32_t y = __shfl_up(inc, s, 64);
+                if (lane >= s) inc += y;
+            }
+            if (d < d_hi) s_start[d] = carry + inc - c;
+            carry += __shfl(inc, 63, 64);
+        }
+        if (lane == 0) s_wsum[wave] = carry;
+        __syncthreads();
+        int32_t before = 0, all = 0;
+#pragma unroll
+        for (int v = 0; v < W; ++v) {
+            before += v < wave ? s_wsum[v] : 0;
+            all += s_wsum[v];
+        }
+        for (int d = d_lo + lane; d < d_hi; d += 64) s_start[d] += before;
+        if (threadIdx.x == 0) s_total = all;
+    }
+    __syncthreads();
+    const int V = s_total;  // records of valid rids in this tile (<= cnt)
+    // segments -> LDS
+    const int total_in = V * WE;
+    for (int x0 = 0; x0 < total_in; x0 += kGatherThreads * kGatherPer) {
+        int q[kGatherPer], d[kGatherPer];
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            q[k] = min(x0 + (int)threadIdx.x + k * kGatherThreads, total_in - 1);
+            d[k] = 0;
+        }
+        // largest d with s_start[d] <= slot: that segment is non-empty and
+        // holds the slot (binary lifting, the lanes' searches interleaved)
+        for (int step = nb >> 1; step > 0; step >>= 1) {
+#pragma unroll
+            for (int k = 0; k < kGatherPer; ++k)
+                if (s_start[d[k] + step] <= q[k] / WE) d[k] += step;
+        }
+        E v[kGatherPer];
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            const int qr = q[k] / WE, w = q[k] - qr * WE;
+            v[k] = internal[(int64_t)(s_off[d[k]] + (qr - s_start[d[k]])) * WE + w];
+        }
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            const int x = x0 + (int)threadIdx.x + k * kGatherThreads;
+            if (x < total_in) s_rec[x] = v[k];
+        }
+    }
+    __syncthreads();
+    // LDS -> output rows in rid-list order (invalid rids: slot 0, undefined row)
+    const int total_out = cnt * WE;
+    E *out = dst + base * WE;
+    for (int y0 = 0; y0 < total_out; y0 += kGatherThreads * kGatherPer) {
+        int32_t q[kGatherPer];
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            const int y = min(y0 + (int)threadIdx.x + k * kGatherThreads, total_out - 1);
+            q[k] = slot[base + y / WE];
+        }
+#pragma unroll
+        for (int k = 0; k < kGatherPer; ++k) {
+            const int y = y0 + (int)threadIdx.x + k * kGatherThreads;
+            if (y < total_out) {
+                const int e = y / WE, w = y - e * WE;
+                const int qq = min(max(q[k], 0), max(V - 1, 0));
+                const E val = V > 0 ? s_rec[qq * WE + w] : E{};
+                if constexpr (NT) __builtin_nontemporal_store(val, out + y);
+                else out[y] = val;
+            }
+        }
+    }
+}
+
+template <typename E, int WE>
+static dpg_status launch_gather_lds_t(const RetrievePlan &p, const void *internal, const int32_t *slot, void *dst,
+                                      const int32_t *off, const int32_t *bucket_off, int remap, hipStream_t stream) {
+    const int nb = 1 << p.part_nbits;
+    const size_t lds = sizeof(E) * (size_t)p.part_tile * WE + 2 * sizeof(int32_t) * nb;
+    const bool nt = (double)p.n_rids * p.rec_bytes > 256.0 * 1024 * 1024;
+    const int64_t nT = (p.n_rids + p.part_tile - 1) / p.part_tile;
+    if (nT > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
+#define DPG_LAUNCH_GLDS(NTV)                                                                                      \
+    do {                                                                                                          \
+        if (lds > 64 * 1024)                                                                                      \
+            DPG_HIP(hipFuncSetAttribute((const void *)k_gather_lds<E, WE, NTV>,                                  \
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                   \
+        hipLaunchKernelGGL((k_gather_lds<E, WE, NTV>), dim3((unsigned)nT), dim3(kGatherThreads), lds, stream,      \
+                           (const E *)internal, slot, (E *)dst, p.n_rids, p.part_tile, p.part_nbits, nT, off,     \
+                           bucket_off, remap);                                                                    \
+    } while (0)
+    if (nt) DPG_LAUNCH_GLDS(true);
+    else DPG_LAUNCH_GLDS(false);
+#undef DPG_LAUNCH_GLDS
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void *dst, hipStream_t stream) {
+    if (!p.gather_lds || p.dist_mode != DIST_PARTITION || p.part_tile <= 0) return DPG_ERR_UNSUPPORTED;
+    if (p.n_rids <= 0) return DPG_OK;
+    char *w = (char *)ws;
+    const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+    if (pp.tile != p.part_tile) return DPG_ERR_UNSUPPORTED;
+    const int32_t *off = (const int32_t *)(w + p.off_part + pp.off_cnt);
+    const int32_t *bucket_off = (const int32_t *)(w + p.off_part + pp.off_bucket);
+    const int32_t *slot = (const int32_t *)(w + p.off_inv);
+    const void *internal = w + p.off_internal;
+    const double M = (double)p.n_rids, R = p.rec_bytes;
+    ProfScope prof(ctx, K_GATHER_LDS, 4.0 * M + 2.0 * R * M, stream);
+    const int remap = xcd_remap_flag(ctx);
+    const bool a16 = ((uintptr_t)dst % 16) == 0, a8 = ((uintptr_t)dst % 8) == 0;
+    switch (p.rec_bytes) {
+        case 4: return launch_gather_lds_t<uint32_t, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
+        case 8:
+            if (a8) return launch_gather_lds_t<u32x2, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            return launch_gather_lds_t<uint32_t, 2>(p, internal, slot, dst, off, bucket_off, remap, stream);
+        case 16:
+            if (a16) return launch_gather_lds_t<u32x4, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            return launch_gather_lds_t<uint32_t, 4>(p, internal, slot, dst, off, bucket_off, remap, stream);
+    }
+    return DPG_ERR_UNSUPPORTED;
+}
+
+}  // namespace dpg

@@ -32,7 +32,9 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 // One pass: elements whose key is < limit (any key if limit is 0) move to the
 // bucket of digit (key >> shift) & (2^nbits - 1), in input order within a
 // bucket.  With stable = false (uint32 keys without values only) the order
-// inside a bucket is unspecified; inv stays exact.  inv (may be
+// inside a bucket is unspecified; inv stays exact.  local_inv (unstable passes
+// only): inv[i] is instead the slot of element i within its tile's output
+// segments laid end to end (digit order), i.e. relative to the tile.  inv (may be
 // null) receives the output position of every input element (0 if invalid).
 // bucket_off (in the scratch, also returned through *bucket_off_dev when
 // non-null) holds the 2^nbits + 1 bucket boundaries.
@@ -41,7 +43,8 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
-                            int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true);
+                            int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true,
+                            bool local_inv = false);
 
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,

@@ -236,7 +236,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
 template <int THREADS, int PER>
 __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
-    const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int remap) {
+    const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int local_inv,
+    int remap) {
     constexpr int T = THREADS * PER;
     constexpr int W = THREADS / 64;
     extern __shared__ __align__(16) char smem[];
@@ -307,7 +308,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
         if (rank[k] >= 0) {
             const uint32_t d = digit_of(key[k], shift, mask);
             s_key[s_cnt[d] + rank[k]] = key[k];
-            if (inv) inv[base + e] = s_glob[d] + rank[k];
+            if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rank[k];
         } else if (inv && e < cnt) {
             inv[base + e] = 0;
         }
@@ -371,7 +372,7 @@ static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
-                            int item_chunk, bool stable) {
+                            int item_chunk, bool stable, bool local_inv) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -383,6 +384,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (p.nbits < 1 || p.nbits > kMaxWideBits) return DPG_ERR_UNSUPPORTED;
     if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || p.per != 16))
         return DPG_ERR_UNSUPPORTED;
+    if (local_inv && stable) return DPG_ERR_UNSUPPORTED;
     const int nb = 1 << p.nbits;
     const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
     {
@@ -424,12 +426,12 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL((k_part_scatter_unstable<1024, 16>), dim3((unsigned)p.n_tiles), dim3(1024), lds,
                                stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
-                               (uint32_t *)keys_out, inv, remap);
+                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, remap);
         } else {
             if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
             hipLaunchKernelGGL((k_part_scatter_unstable<kPartThreads, 32>), dim3((unsigned)p.n_tiles),
                                dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit,
-                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, remap);
+                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, remap);
         }
         DPG_HIP(hipGetLastError());
         return DPG_OK;

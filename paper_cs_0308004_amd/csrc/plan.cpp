@@ -76,7 +76,11 @@ static void layout_workspace(RetrievePlan *p) {
     p->workspace = off;
 }
 
-static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, int dist_mode) {
+// LDS a workgroup of the LDS-staged gather may use: the tile's records plus
+// two int32 tables over the runs.
+constexpr size_t kGatherLdsBytes = 150 * 1024;
+
+static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, int dist_mode, int gather) {
     const int64_t N = p->n_src > 0 ? p->n_src : 1, M = p->n_rids;
     const int R = p->rec_bytes;
     const int lg_n = ilog2_ceil(N);
@@ -89,7 +93,9 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     } else if (probe == DPG_PROBE_LDS) {
         lg = lg_lds;
     } else {
-        lg = floor_log2(kCachedRegionBytes / (size_t)R);
+        // records under 16 bytes: 2 MiB regions (the probe's random reads then
+        // hit L2 most); larger records: 4 MiB (measured at 2^26 rids)
+        lg = floor_log2((R < 16 ? kCachedRegionBytes / 2 : kCachedRegionBytes) / (size_t)R);
         if (lg < 0) lg = 0;
     }
     if (lg > lg_n) lg = lg_n;
@@ -122,6 +128,14 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
         p->n_tiles = M > 0 ? (M + T - 1) / T : 0;
         p->n_chunks = (p->n_tiles + 31) / 32;
     }
+    // Phase III through LDS when a partition tile's records fit (records of
+    // 4, 8 or 16 bytes, one LDS element each): every global access of the
+    // gather is then coalesced.
+    if (p->dist_mode == DIST_PARTITION && gather != 1 && (R == 4 || R == 8 || R == 16)) {
+        const size_t lds = (size_t)p->dist_tile * R + 8u * ((size_t)1 << p->part_nbits);
+        p->gather_lds = lds <= kGatherLdsBytes;
+        p->part_tile = p->dist_tile;
+    }
     if (probe == DPG_PROBE_LDS) {
         int64_t P = (int64_t)1 << lg;
         if (P < 256) P = 256;
@@ -137,7 +151,7 @@ TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids) {
 }
 
 dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo, int probe,
-                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *p) {
+                                       int log2_run, int dist_tile, int dist_mode, RetrievePlan *p, int gather) {
     if (n_src < 0 || n_src > INT32_MAX || n_rids < 0 || n_rids > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
     if (rec_bytes < 4 || rec_bytes > kMaxRecBytes || rec_bytes % 4 != 0) return DPG_ERR_INVALID_ARG;
     if (algo != DPG_ALGO_DIRECT && algo != DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
@@ -146,7 +160,7 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
     p->n_rids = n_rids;
     p->rec_bytes = rec_bytes;
     p->algo = algo;
-    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile, dist_mode);
+    if (algo == DPG_ALGO_DPG && n_rids > 0) plan_dpg(p, probe, log2_run, dist_tile, dist_mode, gather);
     layout_workspace(p);
     return DPG_OK;
 }
@@ -158,6 +172,7 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
     int log2_run = ctx ? (int)ctx->opt_log2_run : 0;
     int dist_tile = ctx ? (int)ctx->opt_dist_tile : 0;
     int dist_mode = ctx ? (int)ctx->opt_distribute : 0;
+    const int gather = ctx ? (int)ctx->opt_gather : 0;
     if (algo == DPG_ALGO_AUTO) {
         // Measured on MI355X (2^26 records): direct retrieval is faster at every
         // record size from 8 to 256 bytes, so it is the default unless the
@@ -174,7 +189,8 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
             }
         }
     }
-    return make_retrieve_plan_explicit(n_src, rec_bytes, n_rids, algo, probe, log2_run, dist_tile, dist_mode, p);
+    return make_retrieve_plan_explicit(n_src, rec_bytes, n_rids, algo, probe, log2_run, dist_tile, dist_mode, p,
+                                       gather);
 }
 
 }  // namespace dpg
@@ -191,6 +207,7 @@ extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32
     out->log2_run = p.log2_run;
     out->dist_tile = p.dist_tile;
     out->distribute = p.algo == DPG_ALGO_DPG ? (p.dist_mode == dpg::DIST_PARTITION ? 2 : 1) : 0;
+    out->gather = p.algo == DPG_ALGO_DPG ? (p.gather_lds ? 2 : 1) : 0;
     out->n_runs = p.n_runs;
     out->n_tiles = p.n_tiles;
     out->workspace_bytes = p.workspace;

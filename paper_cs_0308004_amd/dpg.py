@@ -19,8 +19,9 @@ ERR_WORKSPACE_TOO_SMALL, ERR_UNSUPPORTED, ERR_HIP, ERR_BUSY = 4, 5, 6, 7
 ALGO_AUTO, ALGO_DIRECT, ALGO_DPG = 0, 1, 2
 JOIN_FACT_ORDER, JOIN_DIM_ORDER = 0, 1
 PROBE_AUTO, PROBE_CACHED, PROBE_LDS = 0, 1, 2
-OPT_LOG2_RUN, OPT_PROBE, OPT_DIST_TILE, OPT_XCD_REMAP, OPT_USE_TUNED, OPT_DISTRIBUTE = 1, 2, 3, 4, 5, 6
+OPT_LOG2_RUN, OPT_PROBE, OPT_DIST_TILE, OPT_XCD_REMAP, OPT_USE_TUNED, OPT_DISTRIBUTE, OPT_GATHER = 1, 2, 3, 4, 5, 6, 7
 DIST_AUTO, DIST_APPEND, DIST_PARTITION = 0, 1, 2
+GATHER_AUTO, GATHER_CACHED, GATHER_LDS = 0, 1, 2
 
 _VP, _I32, _I64, _SZ, _DBL = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
 
@@ -34,7 +35,7 @@ class DPGError(RuntimeError):
 
 class Plan(ctypes.Structure):
     _fields_ = [("algo", _I32), ("probe", _I32), ("log2_run", _I32), ("dist_tile", _I32),
-                ("distribute", _I32), ("reserved", _I32), ("n_runs", _I64), ("n_tiles", _I64), ("workspace_bytes", _SZ),
+                ("distribute", _I32), ("gather", _I32), ("n_runs", _I64), ("n_tiles", _I64), ("workspace_bytes", _SZ),
                 ("ws_run_off", _SZ), ("ws_rid_run", _SZ), ("ws_internal", _SZ)]
 
 

@@ -142,3 +142,17 @@ def test_batch_validation_without_device():
     assert lib.dpg_batch_run(None, arr5, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
     assert lib.dpg_batch_graph_workspace_bytes(None, 0) == 0
     assert lib.dpg_batch_graph_workspace_bytes(None, 16) > 0
+
+
+def test_plan_phase_forms():
+    """The planner's Phase I / Phase III forms: one partition pass for up to
+    4096 runs; Phase III staged in LDS for 4-, 8- and 16-byte records."""
+    for rec in (4, 8, 16):
+        p = dpg.plan_retrieve(1 << 26, rec, 1 << 26, dpg.ALGO_DPG)
+        assert p.distribute == dpg.DIST_PARTITION and p.gather == dpg.GATHER_LDS, rec
+    for rec in (12, 32, 100, 256):
+        p = dpg.plan_retrieve(1 << 26, rec, 1 << 26, dpg.ALGO_DPG)
+        assert p.distribute == dpg.DIST_PARTITION and p.gather == dpg.GATHER_CACHED, rec
+        assert p.n_runs <= 4096
+    p = dpg.plan_retrieve(1 << 26, 8, 1 << 26, dpg.ALGO_DIRECT)
+    assert p.distribute == 0 and p.gather == 0

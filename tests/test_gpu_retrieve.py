@@ -19,12 +19,13 @@ def ctx():
     c.close()
 
 
-def configure(ctx, probe=0, log2_run=0, dist_tile=0, xcd=1, dist=0):
+def configure(ctx, probe=0, log2_run=0, dist_tile=0, xcd=1, dist=0, gather=0):
     ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
     ctx.set_option(dpg.OPT_PROBE, probe)
     ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
     ctx.set_option(dpg.OPT_DIST_TILE, dist_tile)
     ctx.set_option(dpg.OPT_XCD_REMAP, xcd)
+    ctx.set_option(dpg.OPT_GATHER, gather)
 
 
 def make_rids(kind, n_src, n_rids, rec_bytes, seed):
@@ -57,6 +58,12 @@ VARIANTS = {
     "dpg-partition-long-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=12, dist=dpg.DIST_PARTITION)),
     # 257..4096 runs: the 12-bit partition pass
     "dpg-wide-partition": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=4, dist=dpg.DIST_PARTITION)),
+    # Phase III forms: through the caches, or a distribute tile staged in LDS
+    # (the latter applies to 4..16-byte records with the partition distribute)
+    "dpg-cached-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_PARTITION, gather=1)),
+    "dpg-lds-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_PARTITION, gather=2)),
+    "dpg-lds-gather-wide": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=3, dist=dpg.DIST_PARTITION,
+                                               gather=2)),
     "auto": (dpg.ALGO_AUTO, {}),
 }
 
