@@ -392,19 +392,24 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
                                          "span_s": round(st["span_s"], 4)}
             servers[name].close()
             del servers[name]
-        # a common arrival rate: 80 % of what per-request launches sustain
-        rate = 0.8 * sat["per_request"]
-        res["arrival_rate_req_per_s"] = round(rate, 1)
-        for name, kw in modes.items():
-            servers[name] = dpg.Server(ctx, budget, **kw)
-            log(f"bench: serving at {rate:.0f} req/s, {name}")
-            st = run(servers[name], rate)
-            res[name] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
-                         "max_ms": round(st["max_ms"], 3), "req_per_s": round(n_req / st["span_s"], 1),
-                         "GB_per_s": round(st["bytes_delivered"] / st["span_s"] / 1e9, 2),
-                         "batches": st["batches"], "arena_high_water_GB": round(st["arena_high_water"] / 1e9, 2)}
-            servers[name].close()
-            del servers[name]
+        # common arrival rates: 50, 80 and 95 % of what per-request launches
+        # sustain; every mode sees the same arrival times at each rate
+        res["load_points"] = []
+        for frac in (0.5, 0.8, 0.95):
+            rate = frac * sat["per_request"]
+            point = {"fraction_of_per_request_saturation": frac, "arrival_rate_req_per_s": round(rate, 1)}
+            for name, kw in modes.items():
+                servers[name] = dpg.Server(ctx, budget, **kw)
+                log(f"bench: serving at {rate:.0f} req/s, {name}")
+                st = run(servers[name], rate)
+                point[name] = {"p50_ms": round(st["p50_ms"], 3), "p99_ms": round(st["p99_ms"], 3),
+                               "max_ms": round(st["max_ms"], 3), "req_per_s": round(n_req / st["span_s"], 1),
+                               "GB_per_s": round(st["bytes_delivered"] / st["span_s"] / 1e9, 2),
+                               "batches": st["batches"],
+                               "arena_high_water_GB": round(st["arena_high_water"] / 1e9, 2)}
+                servers[name].close()
+                del servers[name]
+            res["load_points"].append(point)
     finally:
         for srv in servers.values():
             srv.close()
@@ -417,7 +422,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is described in DESIGN.md but not built)", file=sys.stderr)
+              "(the multi-GPU sharding is not built)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch

@@ -43,7 +43,7 @@ typedef enum {
     DPG_ERR_RID_OUT_OF_RANGE = 2,    /* a rid outside [0, n_src) (only detected when asked) */
     DPG_ERR_FK_OUT_OF_RANGE = 3,     /* a foreign key outside [0, n_dim) (only when asked) */
     DPG_ERR_WORKSPACE_TOO_SMALL = 4, /* workspace_bytes below the *_workspace_bytes query */
-    DPG_ERR_UNSUPPORTED = 5,         /* valid request this build cannot serve */
+    DPG_ERR_UNSUPPORTED = 5,         /* valid request the library cannot serve */
     DPG_ERR_HIP = 6,                 /* a HIP runtime call failed */
     DPG_ERR_BUSY = 7                 /* serving: no capacity for the request right now */
 } dpg_status;
