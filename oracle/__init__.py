@@ -14,6 +14,9 @@ Cache-Efficient Accelerator for Sorting and for Join Operators":
 * :func:`sort_records` -- the three-phase key-pointer sort of Section 3.
 * :func:`fk_join_fact_order` / :func:`fk_join_dim_order` -- the DPG-Move and
   DPG-Sort goals of Section 4.2.1.
+* :func:`hash_build` / :func:`hash_lookup` -- the hash index of Section 4.2.3
+  (one key-rid pair per slot, collisions in an overflow array) and the result
+  of a batch lookup (smallest rid holding each query key, or -1).
 """
 from __future__ import annotations
 
@@ -59,8 +62,11 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     join = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP]
     lib.oracle_fk_join_fact_order.argtypes = join
     lib.oracle_fk_join_dim_order.argtypes = join
+    lib.oracle_hash_build.argtypes = [_VP, _I64, _I32, _VP, _VP, _VP, _VP]
+    lib.oracle_hash_lookup.argtypes = [_VP, _I64, _VP, _I64, _VP]
     for f in (lib.oracle_retrieve, lib.oracle_dpg_phases, lib.oracle_sort_records,
-              lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order):
+              lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order, lib.oracle_hash_build,
+              lib.oracle_hash_lookup):
         f.restype = ctypes.c_int
     return lib
 
@@ -156,3 +162,39 @@ def fk_join_fact_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, li
 def fk_join_dim_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, lib=None) -> np.ndarray:
     """DPG-Sort goal (Section 4.2.1): joined rows in foreign-key order, ties in fact order."""
     return _join("oracle_fk_join_dim_order", fact, dim, fk_offset, lib)
+
+
+HASH_EMPTY = 0xFFFFFFFF
+
+
+def hash_build(keys: np.ndarray, log2_slots: int, lib=None):
+    """The hash index of Section 4.2.3 over uint32 keys (rid = position).
+
+    Returns (slots, ov_off, ov): slots is (S, 2) uint32 of (key, rid) with
+    empty slots (0, 0xFFFFFFFF); ov_off is int64[S + 1]; ov is (n_ov, 2) uint32
+    of the overflow (key, rid) pairs in (home slot, rid) order."""
+    lib = lib or load()
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    S = 1 << log2_slots
+    slots = np.empty((S, 2), dtype=np.uint32)
+    ov_off = np.empty(S + 1, dtype=np.int64)
+    ov = np.empty((max(k.size, 1), 2), dtype=np.uint32)
+    n_ov = ctypes.c_int64()
+    rc = lib.oracle_hash_build(_ptr(k), k.size, log2_slots, _ptr(slots), _ptr(ov_off), _ptr(ov),
+                               ctypes.byref(n_ov))
+    if rc:
+        raise OracleError(rc, "hash_build")
+    return slots, ov_off, ov[:n_ov.value].copy()
+
+
+def hash_lookup(keys: np.ndarray, queries: np.ndarray, lib=None) -> np.ndarray:
+    """Batch lookup (Section 4.2.3): for each query, the smallest rid whose key
+    equals it, or -1."""
+    lib = lib or load()
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    q = np.ascontiguousarray(queries, dtype=np.uint32)
+    out = np.empty(q.size, dtype=np.int32)
+    rc = lib.oracle_hash_lookup(_ptr(k), k.size, _ptr(q), q.size, _ptr(out))
+    if rc:
+        raise OracleError(rc, "hash_lookup")
+    return out

@@ -9,6 +9,9 @@
  * shares no code, header, table or helper with the HIP library, and nothing in
  * the library may call it.
  *
+ * It also states the hash index of Section 4.2.3 (batch lookup in hash
+ * indexes) and the result of a batch lookup in it.
+ *
  * Conventions (readings of the paper, listed again in the design notes):
  *   - rids are 0-based and must lie in [0, n_src) (Section 2.1 says rid values
  *     lie between 0 and N; Figure 1 is written 1-based, the text and the worked
@@ -26,6 +29,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifndef INT32_MAX
+#define INT32_MAX 2147483647
+#endif
 
 #define ORACLE_OK 0
 #define ORACLE_EINVAL 1
@@ -277,6 +283,132 @@ int oracle_fk_join_dim_order(const uint8_t *fact, int64_t n_fact, int32_t fact_b
         const uint8_t *f = fact + pairs[j].rid * (int64_t)fact_bytes;
         emit_joined_row(out + j * out_bytes, f, fact_bytes,
                         dim + (int64_t)pairs[j].fk * dim_bytes, dim_bytes);
+    }
+    free(pairs);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Hash index and batch lookup (Section 4.2.3, batch lookup in hash indexes). */
+/*                                                                           */
+/* The paper's hash index holds one key-rid pair per hash slot and keeps the */
+/* pairs that collide with an occupied slot in a second, overflow array.    */
+/* This oracle fixes the layout so that two builds can be compared byte for  */
+/* byte:                                                                     */
+/*   - S = 2^log2_slots slots; the home slot of key k is the top log2_slots  */
+/*     bits of the 32-bit product k * 0x9E3779B1 (Knuth's multiplicative     */
+/*     hashing with the golden-ratio constant);                              */
+/*   - slots[2h], slots[2h+1] = key, rid of the smallest rid whose key has   */
+/*     home h; an empty slot holds key 0, rid 0xFFFFFFFF;                    */
+/*   - every other key-rid pair sits in ov (pairs of uint32), ordered by     */
+/*     (home slot, rid); ov_off[h] = number of overflow pairs whose home is  */
+/*     below h, ov_off[S] = all of them.                                     */
+/* The lookup result is defined without the index: for each query, the      */
+/* smallest rid whose key equals it, or -1.                                  */
+/* ------------------------------------------------------------------------- */
+#define ORACLE_HASH_MUL 0x9E3779B1u
+#define ORACLE_HASH_EMPTY 0xFFFFFFFFu
+
+static uint32_t hash_home(uint32_t key, int32_t log2_slots)
+{
+    return (uint32_t)(key * ORACLE_HASH_MUL) >> (32 - log2_slots);
+}
+
+int oracle_hash_build(const uint32_t *keys, int64_t n, int32_t log2_slots,
+                      uint32_t *slots, int64_t *ov_off, uint32_t *ov, int64_t *n_ov)
+{
+    if (n < 0 || n > INT32_MAX - 1 || log2_slots < 1 || log2_slots > 30)
+        return ORACLE_EINVAL;
+    int64_t S = (int64_t)1 << log2_slots;
+    int64_t *count = calloc((size_t)S, sizeof(int64_t));
+    int64_t *cursor = malloc((size_t)S * sizeof(int64_t));
+    if (!count || !cursor) {
+        free(count);
+        free(cursor);
+        return ORACLE_EINVAL;
+    }
+    for (int64_t h = 0; h < S; ++h) {
+        slots[2 * h] = 0;
+        slots[2 * h + 1] = ORACLE_HASH_EMPTY;
+    }
+    /* the first key of each slot (in rid order) takes the slot */
+    for (int64_t j = 0; j < n; ++j) {
+        uint32_t h = hash_home(keys[j], log2_slots);
+#ifdef ORACLE_MUTANT_HASH_LAST
+        if (count[h] >= 0) {
+#else
+        if (count[h] == 0) {
+#endif
+            slots[2 * h] = keys[j];
+            slots[2 * h + 1] = (uint32_t)j;
+        }
+        count[h] += 1;
+    }
+    /* overflow offsets: one fewer pair per occupied slot */
+    int64_t total = 0;
+    for (int64_t h = 0; h < S; ++h) {
+        ov_off[h] = total;
+        cursor[h] = total;
+        if (count[h] > 1)
+            total += count[h] - 1;
+    }
+    ov_off[S] = total;
+    /* the other keys, in (home, rid) order */
+    for (int64_t j = 0; j < n; ++j) {
+        uint32_t h = hash_home(keys[j], log2_slots);
+        if (slots[2 * h + 1] == (uint32_t)j)
+            continue;
+        ov[2 * cursor[h]] = keys[j];
+        ov[2 * cursor[h] + 1] = (uint32_t)j;
+        cursor[h] += 1;
+    }
+    *n_ov = total;
+    free(count);
+    free(cursor);
+    return ORACLE_OK;
+}
+
+typedef struct {
+    uint32_t key;
+    int64_t rid;
+} key_rid;
+
+static int compare_key_rid(const void *pa, const void *pb)
+{
+    const key_rid *a = pa, *b = pb;
+    if (a->key != b->key)
+        return a->key < b->key ? -1 : 1;
+    return (a->rid > b->rid) - (a->rid < b->rid);
+}
+
+int oracle_hash_lookup(const uint32_t *keys, int64_t n, const uint32_t *queries, int64_t m,
+                       int32_t *out)
+{
+    if (n < 0 || n > INT32_MAX - 1 || m < 0)
+        return ORACLE_EINVAL;
+    key_rid *pairs = malloc((size_t)(n > 0 ? n : 1) * sizeof(key_rid));
+    if (!pairs)
+        return ORACLE_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        pairs[j].key = keys[j];
+        pairs[j].rid = j;
+    }
+    qsort(pairs, (size_t)n, sizeof(key_rid), compare_key_rid);
+    for (int64_t i = 0; i < m; ++i) {
+        /* first pair whose key is >= the query */
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            int64_t mid = lo + (hi - lo) / 2;
+            if (pairs[mid].key < queries[i])
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+#ifdef ORACLE_MUTANT_LOOKUP_LAST
+        while (lo + 1 < n && pairs[lo + 1].key == queries[i])
+            ++lo;
+#endif
+        out[i] = (lo < n && pairs[lo].key == queries[i]) ? (int32_t)pairs[lo].rid : -1;
     }
     free(pairs);
     return ORACLE_OK;

@@ -266,8 +266,103 @@ def pin_join_errors(lib):
             raise AssertionError("foreign key out of range accepted")
 
 
+# ---------------------------------------------------------------------------
+# hash index and batch lookup (Section 4.2.3)
+# ---------------------------------------------------------------------------
+def stated_home(keys: np.ndarray, log2_slots: int) -> np.ndarray:
+    """The index's stated slot function: top log2_slots bits of k * 0x9E3779B1 (mod 2^32)."""
+    prod = (keys.astype(np.uint64) * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)
+    return (prod >> np.uint64(32 - log2_slots)).astype(np.int64)
+
+
+def pin_hash_lookup_brute_force(lib):
+    """Every key list of length <= 4 over a 3-letter alphabet, every query of
+    the alphabet plus one absent value: the answer is the first position
+    holding the query (linear scan), or -1."""
+    alphabet = [0, 7, 0xFFFFFFFF]
+    queries = np.array(alphabet + [12345], dtype=np.uint32)
+    for n in range(0, 5):
+        for seq in itertools.product(alphabet, repeat=n):
+            keys = np.array(seq, dtype=np.uint32)
+            got = oracle.hash_lookup(keys, queries, lib=lib)
+            want = [next((j for j in range(n) if seq[j] == q), -1) for q in queries.tolist()]
+            assert got.tolist() == want, (seq, got, want)
+
+
+def pin_hash_lookup_closed_forms(lib):
+    """Distinct keys: looking up the keys themselves returns 0..n-1, a shuffled
+    subset returns its positions, and values never stored return -1."""
+    n = 5000
+    keys = (2 * synth.rids_permutation(1 << 16, seed=5)[:n].astype(np.uint32) + 1)  # odd, distinct
+    assert np.array_equal(oracle.hash_lookup(keys, keys, lib=lib), np.arange(n, dtype=np.int32))
+    pick = synth.rids_permutation(n, seed=6)[:700]
+    assert np.array_equal(oracle.hash_lookup(keys, keys[pick], lib=lib), pick.astype(np.int32))
+    even = np.arange(0, 4000, 2, dtype=np.uint32)
+    assert np.all(oracle.hash_lookup(keys, even, lib=lib) == -1)
+    assert oracle.hash_lookup(keys, np.zeros(0, dtype=np.uint32), lib=lib).size == 0
+
+
+def pin_hash_build_invariants(lib):
+    """The stated layout: every rid stored exactly once; a slot holds the
+    smallest rid of its home; the overflow pairs of home h sit in
+    [ov_off[h], ov_off[h+1]) in rid order; and a lookup through the index
+    (slot, then its overflow range) gives the batch-lookup result."""
+    rng = np.random.default_rng(8)
+    for n, log2_slots, span in ((5000, 10, 1 << 32), (5000, 12, 3000), (3000, 14, 1 << 32), (1, 3, 10), (0, 4, 10)):
+        keys = rng.integers(0, span, n, dtype=np.uint64).astype(np.uint32)
+        slots, ov_off, ov = oracle.hash_build(keys, log2_slots, lib=lib)
+        S = 1 << log2_slots
+        home = stated_home(keys, log2_slots)
+        occupied = slots[:, 1] != oracle.HASH_EMPTY
+        # every rid once
+        rids = np.concatenate([slots[occupied, 1], ov[:, 1]]).astype(np.int64)
+        assert np.array_equal(np.sort(rids), np.arange(n))
+        # slots: the smallest rid of each home
+        first = np.full(S, -1, dtype=np.int64)
+        for j in range(n - 1, -1, -1):
+            first[home[j]] = j
+        assert np.array_equal(occupied, first >= 0)
+        assert np.array_equal(slots[occupied, 1].astype(np.int64), first[occupied])
+        assert np.array_equal(slots[occupied, 0], keys[first[occupied]])
+        assert np.all(slots[~occupied, 0] == 0)
+        # overflow: grouped by home in slot order, rids ascending within a home
+        assert ov_off[0] == 0 and ov_off[S] == len(ov) == n - occupied.sum()
+        assert np.all(np.diff(ov_off) >= 0)
+        ov_home = np.repeat(np.arange(S), np.diff(ov_off))
+        assert np.array_equal(home[ov[:, 1].astype(np.int64)], ov_home)
+        assert np.array_equal(keys[ov[:, 1].astype(np.int64)], ov[:, 0])
+        order = np.lexsort((ov[:, 1].astype(np.int64), ov_home))
+        assert np.array_equal(order, np.arange(len(ov)))
+        # a lookup through the index
+        queries = np.concatenate([keys[: min(n, 500)], rng.integers(0, 1 << 32, 300, dtype=np.uint64).astype(np.uint32)])
+        want = oracle.hash_lookup(keys, queries, lib=lib)
+        qh = stated_home(queries, log2_slots)
+        for i, q in enumerate(queries.tolist()):
+            h = int(qh[i])
+            got = -1
+            if slots[h, 1] != oracle.HASH_EMPTY and int(slots[h, 0]) == q:
+                got = int(slots[h, 1])
+            else:
+                for a in range(int(ov_off[h]), int(ov_off[h + 1])):
+                    if int(ov[a, 0]) == q:
+                        got = int(ov[a, 1])
+                        break
+            assert got == want[i], (i, q, got, want[i])
+
+
+def pin_hash_errors(lib):
+    for log2_slots in (0, 31):
+        try:
+            oracle.hash_build(np.zeros(4, dtype=np.uint32), log2_slots, lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == oracle.EINVAL
+        else:
+            raise AssertionError("bad slot count accepted")
+
+
 ALL_PINS = [
     pin_retrieve_brute_force, pin_retrieve_closed_forms, pin_retrieve_multiset, pin_retrieve_errors,
     pin_fig2_example, pin_phase_invariants, pin_sort_random, pin_sort_ties,
     pin_join_fact_order, pin_join_dim_order, pin_join_errors,
+    pin_hash_lookup_brute_force, pin_hash_lookup_closed_forms, pin_hash_build_invariants, pin_hash_errors,
 ]

@@ -14,6 +14,8 @@ MUTANTS = {
     "ORACLE_MUTANT_NEIGHBOUR": [pins_oracle.pin_retrieve_brute_force, pins_oracle.pin_retrieve_closed_forms],
     "ORACLE_MUTANT_TIES_DESCENDING": [pins_oracle.pin_sort_ties],
     "ORACLE_MUTANT_UNSTABLE_JOIN": [pins_oracle.pin_join_dim_order],
+    "ORACLE_MUTANT_HASH_LAST": [pins_oracle.pin_hash_build_invariants],
+    "ORACLE_MUTANT_LOOKUP_LAST": [pins_oracle.pin_hash_lookup_brute_force],
 }
 
 
