@@ -10,7 +10,8 @@ inputs.  Inputs are resident in HBM before timing starts.
 Secondary measurements reported in the same JSON line (each on its own
 synthetic inputs): the key-pointer sort of 10^8 x 100 B records, the DPG-Move
 and DPG-Sort joins of 2^28 x 16 B fact rows with 2^24 x 64 B dimension rows
-under Zipf(0 / 0.8 / 1.2) keys, and the serving workload (4096 retrieval /
+under Zipf(0 / 0.8 / 1.2) keys, the batch lookup of 2^26 keys in a hash index
+of 2^24 keys, and the serving workload (4096 retrieval /
 join requests, log-uniform sizes, Poisson arrivals, 64 GiB HBM budget):
 batched server vs per-request launches, p50 / p99 latency.
 """
@@ -51,7 +52,7 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
-    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,serve (default all)")
+    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,hash,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
@@ -299,6 +300,51 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                         "output 2^28 x 80 B rows", **res}
 
 
+def bench_hash(args, ctx, dpg, synth, torch, np):
+    """Batch lookup in a hash index (Section 4.2.3): 2^24 distinct uint32 keys
+    in 2^25 slots, 2^26 query keys of which 80 % are stored; DPG (distribute
+    by index partition, probe, gather) vs one direct probe per query."""
+    dev = "cuda:0"
+    n, s, m = 1 << 24, 25, 1 << 26
+    seed = synth.SEED_BASE + 6
+    log(f"bench: hash index of {n} keys in 2^{s} slots, {m} lookups")
+    keys = 2 * synth.rids_permutation(1 << 25, seed, backend="torch", device=dev)[:n].to(torch.int64) + 1
+    keys = keys.to(torch.int32)  # odd, distinct (bit patterns of uint32)
+    t0 = time.perf_counter()
+    index = ctx.hash_build(keys, s)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    pick = synth.uniform_at(n, torch.arange(m, device=dev), seed, synth.STREAM_RIDS, backend="torch", device=dev)
+    queries = keys[pick.to(torch.int64)].clone()
+    hit = synth.uniform_at(10, torch.arange(m, device=dev), seed, synth.STREAM_MIX, backend="torch", device=dev) < 8
+    queries[~hit] = 2 * (pick[~hit].to(torch.int32) + 1)  # even: never stored
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = torch.empty(ctx.hash_lookup_workspace_bytes(n, s, m, dpg.ALGO_DPG), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {"workload": f"batch lookup of 2^26 uint32 keys (80% stored) in a hash index of 2^24 distinct keys, "
+                       f"2^{s} slots + overflow array", "build_s": round(build_s, 4)}
+    for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
+        ctx.profile_enable(True)
+        ctx.hash_lookup(index, n, s, queries, out, algo=algo, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        ctx.profile_reset()
+        ms, _ = time_steps(lambda: ctx.hash_lookup(index, n, s, queries, out, algo=algo, workspace=ws,
+                                                   stream=stream), args.steps, args.warmup, torch)
+        prof = ctx.profile_collect()
+        ctx.profile_enable(False)
+        ctx.profile_reset()
+        got = out.cpu().numpy()
+        want = np.where(hit.cpu().numpy(), pick.cpu().numpy(), -1)
+        if not np.array_equal(got, want):
+            raise SystemExit(f"bench: {name} hash lookup differs from the stored rids")
+        res[name] = {"ms": round(ms, 4), "lookups_per_s": round(m / (ms * 1e-3), 1),
+                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()}}
+    res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
+    del keys, index, queries, out, ws
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
     """4096 requests (75 % retrievals, 25 % fact-order or dimension-order
     joins), N log-uniform in [2^10, 2^max_log2], record size uniform over
@@ -429,7 +475,7 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "hash", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -446,6 +492,8 @@ def main():
         out["sort"] = bench_sort(args, ctx, dpg, synth, torch, np)
     if "join" in only:
         out["join"] = bench_join(args, ctx, dpg, synth, torch, np)
+    if "hash" in only:
+        out["hash_lookup"] = bench_hash(args, ctx, dpg, synth, torch, np)
     if "serve" in only:
         out["serving"] = bench_serve(args, ctx, dpg, synth, torch, np)
         # the same mix restricted to small requests (N up to 2^14), where

@@ -180,10 +180,12 @@ size_t dpg_sort_workspace_bytes(const dpg_ctx *ctx, int64_t n, int32_t rec_bytes
 
 /* dst[j] = src[perm[j]] where perm sorts the records by key.  perm_out
  * (nullable, uint32[n]) receives perm.  key_bytes in [1, 64].  copy_algo picks
- * the retrieval used for the copy phase (DPG, direct, or AUTO).  For keys
- * longer than 8 bytes the call synchronizes the stream once, to learn whether
- * two records share their first 8 key bytes (then the pairs are sorted over
- * the whole key).  src, dst, perm_out and workspace must not overlap. */
+ * the retrieval used for the copy phase (DPG, direct, or AUTO).  The pairs
+ * are sorted on the first 4 key bytes, then every group of equal prefixes is
+ * put in order by the remaining bytes and the index.  For keys longer than 4
+ * bytes the call synchronizes the stream once, to learn whether some group is
+ * longer than 64 records (then the pairs are sorted over the whole key
+ * instead).  src, dst, perm_out and workspace must not overlap. */
 dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes,
                             int32_t key_offset, int32_t key_bytes, void *dst, uint32_t *perm_out,
                             void *workspace, size_t workspace_bytes, dpg_algo copy_algo,
@@ -213,6 +215,54 @@ dpg_status dpg_fk_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t f
                        int32_t fk_offset, const void *dim, int64_t n_dim, int32_t dim_bytes,
                        void *out, dpg_join_order order, void *workspace, size_t workspace_bytes,
                        dpg_algo algo, int check_fk, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
+/* Hash index and batch lookup (Section 4.2.3, batch lookup in hash indexes): */
+/* a hash index over uint32 keys (rid = position in the key array) holds one  */
+/* key-rid pair per slot and keeps the pairs that collide with an occupied    */
+/* slot in an overflow array.  A batch lookup returns, for each query key,    */
+/* the smallest rid holding it, or -1.  With DPG the queries are distributed  */
+/* by the index partition of their slot, each partition is probed while it    */
+/* is cache resident, and the rids are gathered back into query order.        */
+/*                                                                           */
+/* Index layout (one buffer of dpg_hash_index_bytes, 256-byte aligned):      */
+/*   S = 2^log2_slots slots; the home slot of key k is the top log2_slots     */
+/*   bits of the 32-bit product k * 0x9E3779B1 (multiplicative hashing).      */
+/*   slots  uint32[2S] at byte 0: key, rid of the smallest rid whose key has  */
+/*          this home; an empty slot holds key 0, rid 0xFFFFFFFF              */
+/*   ov_off int32[S+1] at dpg_hash_ov_off_offset: overflow pairs whose home   */
+/*          is below h; ov_off[S] = all of them                               */
+/*   ov     uint32[2n] at dpg_hash_ov_offset: the other key-rid pairs in      */
+/*          (home, rid) order                                                 */
+/* ------------------------------------------------------------------------- */
+#define DPG_HASH_EMPTY 0xFFFFFFFFu
+
+/* Bytes of an index over n_keys keys with 2^log2_slots slots (0 if invalid:
+ * log2_slots in [4, 30], n_keys in [0, 2^31 - 2]), and the byte offsets of
+ * its ov_off and ov arrays. */
+size_t dpg_hash_index_bytes(int64_t n_keys, int32_t log2_slots);
+size_t dpg_hash_ov_off_offset(int32_t log2_slots);
+size_t dpg_hash_ov_offset(int32_t log2_slots);
+
+/* Build the index of `keys` (device, uint32[n_keys]) into `index`.  The
+ * contents of slots, ov_off and ov[0, ov_off[S]) are fully determined by the
+ * keys (padding bytes between and after them are left as they were). */
+size_t dpg_hash_build_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys, int32_t log2_slots);
+dpg_status dpg_hash_build(dpg_ctx *ctx, const uint32_t *keys, int64_t n_keys, int32_t log2_slots,
+                          void *index, size_t index_bytes, void *workspace, size_t workspace_bytes,
+                          hipStream_t stream);
+
+/* rids[i] = smallest rid whose key equals queries[i], or -1 (device arrays of
+ * n_queries).  index must have been built for (n_keys, log2_slots).  algo:
+ * DPG_ALGO_DIRECT probes the index once per query in query order; DPG_ALGO_DPG
+ * distributes the queries by index partition (2^DPG_OPT_LOG2_RUN slots per
+ * partition, default 2^18), probes each partition, and gathers the rids;
+ * DPG_ALGO_AUTO picks DPG.  rids must not overlap queries, index or workspace. */
+size_t dpg_hash_lookup_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys, int32_t log2_slots,
+                                       int64_t n_queries, dpg_algo algo);
+dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int32_t log2_slots,
+                           const uint32_t *queries, int64_t n_queries, int32_t *rids,
+                           void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Batches: many retrieval / join requests of uneven size in one call.  All   */

@@ -6,11 +6,12 @@
 namespace dpg {
 
 static const char *const kKernelNames[K_COUNT] = {
-    "k_direct_gather", "k_dist_hist",    "k_scan_chunks",  "k_scan_cols",     "k_scan_base",
-    "k_scan_apply",   "k_dist_scatter", "k_probe_cached", "k_probe_lds",     "k_gather_phase",
-    "k_check_ids",    "k_fill_i32",     "k_sort_extract", "k_radix_hist",    "k_radix_scatter",
-    "k_tie_check",    "k_tie_fix",      "k_join_extract", "k_join_assemble", "k_join_stream",
-    "k_batch",        "k_part_hist",    "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable", "k_gather_lds"};
+    "k_direct_gather", "k_dist_hist",       "k_scan_chunks",   "k_scan_cols",      "k_scan_base",
+    "k_scan_apply",    "k_dist_scatter",    "k_probe_cached",  "k_probe_lds",      "k_gather_phase",
+    "k_check_ids",     "k_fill_i32",        "k_sort_extract",  "k_tie_fix",        "k_join_extract",
+    "k_join_assemble", "k_batch",           "k_part_hist",     "k_part_scatter",   "k_part_hist_wide",
+    "k_part_scatter_unstable", "k_gather_lds", "k_hash_home", "k_hash_mark", "k_hash_place",
+    "k_hash_ov_off", "k_hash_direct", "k_hash_probe"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 

@@ -50,19 +50,21 @@ enum KernelId {
     K_CHECK_IDS,
     K_FILL,
     K_SORT_EXTRACT,
-    K_RADIX_HIST,
-    K_RADIX_SCATTER,
-    K_TIE_MARK,
     K_TIE_FIX,
     K_JOIN_EXTRACT,
     K_JOIN_ASSEMBLE,
-    K_JOIN_STREAM,
     K_BATCH,
     K_PART_HIST,
     K_PART_SCATTER,
     K_PART_HIST_WIDE,
     K_PART_SCATTER_UNSTABLE,
     K_GATHER_LDS,        // Phase III, distribute tile staged in LDS
+    K_HASH_HOME,         // hash index build
+    K_HASH_MARK,
+    K_HASH_PLACE,
+    K_HASH_OVOFF,
+    K_HASH_DIRECT,       // batch lookup, one probe per query in query order
+    K_HASH_PROBE,        // batch lookup, DPG Phase II over one index partition at a time
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -165,6 +167,12 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
                                        int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan,
                                        int gather = 0);
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
+// The DPG plan of a hash-index batch lookup: queries distributed into 2^bits
+// runs of index slots by the top bits of key * kHashMul (their home slot's
+// partition); INTERNAL holds one int32 rid per query.  log2_run_slots 0 means
+// 2^18 slots (2 MiB of slots) per run.
+dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather,
+                                 RetrievePlan *plan);
 
 // Phases I and II of a planned DPG retrieval: afterwards the workspace holds
 // INTERNAL (at off_internal) and inv (at off_inv), so a caller can fuse Phase

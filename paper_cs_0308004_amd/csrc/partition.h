@@ -34,7 +34,9 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 // bucket.  With stable = false (uint32 keys without values only) the order
 // inside a bucket is unspecified; inv stays exact.  local_inv (unstable passes
 // only): inv[i] is instead the slot of element i within its tile's output
-// segments laid end to end (digit order), i.e. relative to the tile.  inv (may be
+// segments laid end to end (digit order), i.e. relative to the tile.
+// key_mul (unstable uint32 passes only): every key is first multiplied by it
+// (mod 2^32), and the products are what is partitioned and written out.  inv (may be
 // null) receives the output position of every input element (0 if invalid).
 // bucket_off (in the scratch, also returned through *bucket_off_dev when
 // non-null) holds the 2^nbits + 1 bucket boundaries.
@@ -44,7 +46,13 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
                             int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true,
-                            bool local_inv = false);
+                            bool local_inv = false, uint32_t key_mul = 1);
+
+// Exclusive scan of a[0..n) in place; *total = the sum (device).  scratch:
+// scan_1d_scratch_bytes(n).
+size_t scan_1d_scratch_bytes(int64_t n);
+dpg_status launch_scan_1d(dpg_ctx *ctx, int32_t *a, int64_t n, int32_t *scratch, int32_t *total,
+                          hipStream_t stream);
 
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,

@@ -56,7 +56,7 @@ __device__ __forceinline__ int32_t rank_by_atomic(int32_t *ctr, uint32_t d, bool
 
 template <typename K>
 __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict__ keys, int64_t n, int shift,
-                                                            int nbits, uint64_t limit, int T,
+                                                            int nbits, uint64_t limit, int T, uint32_t key_mul,
                                                             int32_t *__restrict__ cnt) {
     __shared__ int32_t h[kPartWaves][kMaxDigitBuckets];
     const int nb = 1 << nbits;
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
-            kv[u] = i < end ? keys[i] : K(0);
+            kv[u] = i < end ? (K)(keys[i] * (K)key_mul) : K(0);
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__restrict__ keys, int64_t n,
                                                             int shift, int nbits, uint64_t limit, int T,
-                                                            int32_t *__restrict__ cnt) {
+                                                            uint32_t key_mul, int32_t *__restrict__ cnt) {
     extern __shared__ int32_t hw[];
     const int nb = 1 << nbits;
     const uint32_t mask = (uint32_t)nb - 1;
@@ -112,7 +112,7 @@ __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__re
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * THREADS;
-            kv[u] = keys[min(i, end - 1)];
+            kv[u] = keys[min(i, end - 1)] * key_mul;
         }
 #pragma unroll
         for (int u = 0; u < kBatch; ++u) {
@@ -237,7 +237,7 @@ template <int THREADS, int PER>
 __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
     const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int local_inv,
-    int remap) {
+    uint32_t key_mul, int remap) {
     constexpr int T = THREADS * PER;
     constexpr int W = THREADS / 64;
     extern __shared__ __align__(16) char smem[];
@@ -260,7 +260,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
-        key[k] = keys[base + min(e, cnt - 1)];
+        key[k] = keys[base + min(e, cnt - 1)] * key_mul;
     }
     __syncthreads();
     int32_t rank[PER];
@@ -372,7 +372,7 @@ static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
-                            int item_chunk, bool stable, bool local_inv) {
+                            int item_chunk, bool stable, bool local_inv, uint32_t key_mul) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -385,6 +385,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || p.per != 16))
         return DPG_ERR_UNSUPPORTED;
     if (local_inv && stable) return DPG_ERR_UNSUPPORTED;
+    if (key_mul != 1 && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
     const int nb = 1 << p.nbits;
     const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
     {
@@ -393,13 +394,13 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         if (wide)
             hipLaunchKernelGGL((k_part_hist_wide<1024>), dim3((unsigned)p.n_tiles), dim3(1024),
                                (size_t)nb * sizeof(int32_t), stream, (const uint32_t *)keys_in, p.n, shift, p.nbits,
-                               limit, p.tile, cnt);
+                               limit, p.tile, key_mul, cnt);
         else if (p.key_bytes == 8)
             hipLaunchKernelGGL((k_part_hist<uint64_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
-                               (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, cnt);
+                               (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, 1u, cnt);
         else
             hipLaunchKernelGGL((k_part_hist<uint32_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
-                               (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, cnt);
+                               (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt);
         DPG_HIP(hipGetLastError());
     }
     dpg_status st = launch_column_scan(ctx, cnt, p.n_tiles, nb, csum, p.n_chunks, total, bucket_off, item_off,
@@ -426,12 +427,12 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL((k_part_scatter_unstable<1024, 16>), dim3((unsigned)p.n_tiles), dim3(1024), lds,
                                stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
-                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, remap);
+                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap);
         } else {
             if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
             hipLaunchKernelGGL((k_part_scatter_unstable<kPartThreads, 32>), dim3((unsigned)p.n_tiles),
                                dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit,
-                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, remap);
+                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap);
         }
         DPG_HIP(hipGetLastError());
         return DPG_OK;

@@ -146,6 +146,38 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     }
 }
 
+dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather,
+                                 RetrievePlan *p) {
+    if (n_queries < 0 || n_queries > INT32_MAX - 1 || log2_slots < 4 || log2_slots > 30) return DPG_ERR_INVALID_ARG;
+    *p = RetrievePlan();
+    p->algo = DPG_ALGO_DPG;
+    p->n_src = 0;  // partition limit 0: every key is valid
+    p->n_rids = n_queries;
+    p->rec_bytes = 4;  // INTERNAL holds an int32 rid per query
+    p->probe = DPG_PROBE_CACHED;
+    if (n_queries > 0) {
+        const int l = log2_run_slots > 0 ? log2_run_slots : 18;
+        int bits = log2_slots - l;
+        if (bits < 1) bits = 1;
+        if (bits > kMaxWideBits) bits = kMaxWideBits;
+        p->log2_run = 32 - bits;  // run of a query = (key * kHashMul) >> (32 - bits)
+        p->n_runs = (int64_t)1 << bits;
+        p->dist_mode = DIST_PARTITION;
+        p->part_nbits = bits;
+        const PartPlan pp = plan_partition(n_queries, bits, 4, false);
+        p->dist_tile = pp.tile;
+        p->n_tiles = pp.n_tiles;
+        p->n_chunks = pp.n_chunks;
+        if (gather != 1) {
+            const size_t lds = (size_t)pp.tile * 4 + 8u * ((size_t)1 << bits);
+            p->gather_lds = lds <= kGatherLdsBytes;
+            p->part_tile = pp.tile;
+        }
+    }
+    layout_workspace(p);
+    return DPG_OK;
+}
+
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids) {
     return TuneKey{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
 }

@@ -108,6 +108,99 @@ __global__ __launch_bounds__(256) void k_scan_apply(int32_t *__restrict__ cnt, i
     }
 }
 
+// ---------------------------------------------------------------------------
+// Exclusive scan of one int32 array in place: per-block sums, one workgroup
+// scanning the block sums, then each block rescans its chunk with its offset.
+// ---------------------------------------------------------------------------
+constexpr int kScan1dThreads = 1024;
+constexpr int kScan1dPer = 16;
+constexpr int64_t kScan1dChunk = (int64_t)kScan1dThreads * kScan1dPer;
+
+__device__ __forceinline__ int32_t block_exclusive_scan(int32_t v, int32_t *s_w, int32_t *total) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int32_t inc = wave_inclusive_scan(v);
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int32_t w = lane < kScan1dThreads / 64 ? s_w[lane] : 0;
+        const int32_t sw = wave_inclusive_scan(w);
+        if (lane < kScan1dThreads / 64) s_w[lane] = sw - w;
+        if (lane == 63) *total = sw;
+    }
+    __syncthreads();
+    const int32_t r = s_w[wave] + inc - v;
+    __syncthreads();
+    return r;
+}
+
+// block_sums[b] = sum of chunk b (kScan1dChunk elements; each thread sums kScan1dPer consecutive ones)
+__global__ __launch_bounds__(kScan1dThreads) void k_scan1d_reduce(const int32_t *__restrict__ a, int64_t n,
+                                                                  int32_t *__restrict__ block_sums) {
+    __shared__ int32_t s_w[kScan1dThreads / 64];
+    __shared__ int32_t s_tot;
+    const int64_t base = (int64_t)blockIdx.x * kScan1dChunk + (int64_t)threadIdx.x * kScan1dPer;
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScan1dPer; ++k) sum += base + k < n ? a[base + k] : 0;
+    (void)block_exclusive_scan(sum, s_w, &s_tot);
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = s_tot;
+}
+
+// One workgroup: exclusive scan of block_sums in place; *total = sum.
+__global__ __launch_bounds__(kScan1dThreads) void k_scan1d_blocks(int32_t *__restrict__ block_sums, int64_t nb,
+                                                                  int32_t *__restrict__ total) {
+    __shared__ int32_t s_w[kScan1dThreads / 64];
+    __shared__ int32_t s_tot;
+    int32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScan1dThreads) {
+        const int64_t b = b0 + threadIdx.x;
+        const int32_t v = b < nb ? block_sums[b] : 0;
+        const int32_t ex = block_exclusive_scan(v, s_w, &s_tot);
+        if (b < nb) block_sums[b] = carry + ex;
+        carry += s_tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(kScan1dThreads) void k_scan1d_apply(int32_t *__restrict__ a, int64_t n,
+                                                                 const int32_t *__restrict__ block_sums) {
+    __shared__ int32_t s_w[kScan1dThreads / 64];
+    __shared__ int32_t s_tot;
+    const int64_t base = (int64_t)blockIdx.x * kScan1dChunk + (int64_t)threadIdx.x * kScan1dPer;
+    int32_t v[kScan1dPer];
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScan1dPer; ++k) {
+        v[k] = base + k < n ? a[base + k] : 0;
+        sum += v[k];
+    }
+    int32_t run = block_sums[blockIdx.x] + block_exclusive_scan(sum, s_w, &s_tot);
+#pragma unroll
+    for (int k = 0; k < kScan1dPer; ++k) {
+        if (base + k < n) a[base + k] = run;
+        run += v[k];
+    }
+}
+
+size_t scan_1d_scratch_bytes(int64_t n) {
+    return (size_t)((n + kScan1dChunk - 1) / kScan1dChunk + 1) * sizeof(int32_t);
+}
+
+dpg_status launch_scan_1d(dpg_ctx *ctx, int32_t *a, int64_t n, int32_t *scratch, int32_t *total,
+                          hipStream_t stream) {
+    if (n <= 0) return launch_fill_i32(ctx, total, 1, 0, stream);
+    const int64_t nb = (n + kScan1dChunk - 1) / kScan1dChunk;
+    ProfScope prof(ctx, K_SCAN_CHUNKS, 12.0 * n, stream);
+    hipLaunchKernelGGL(k_scan1d_reduce, dim3((unsigned)nb), dim3(kScan1dThreads), 0, stream, a, n, scratch);
+    DPG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan1d_blocks, dim3(1), dim3(kScan1dThreads), 0, stream, scratch, nb, total);
+    DPG_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_scan1d_apply, dim3((unsigned)nb), dim3(kScan1dThreads), 0, stream, a, n, scratch);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
                               hipStream_t stream) {

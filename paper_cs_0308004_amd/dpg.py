@@ -91,6 +91,13 @@ SIGNATURES = {
     "dpg_sort_records": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_fk_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32]),
     "dpg_fk_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_hash_index_bytes": (_SZ, [_I64, _I32]),
+    "dpg_hash_ov_off_offset": (_SZ, [_I32]),
+    "dpg_hash_ov_offset": (_SZ, [_I32]),
+    "dpg_hash_build_workspace_bytes": (_SZ, [_VP, _I64, _I32]),
+    "dpg_hash_build": (_I32, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _SZ, _VP]),
+    "dpg_hash_lookup_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
+    "dpg_hash_lookup": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_batch_workspace_bytes": (_SZ, [_VP, ctypes.POINTER(Request), _I32]),
     "dpg_batch_run": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP, _SZ, _VP]),
     "dpg_batch_graph_workspace_bytes": (_SZ, [_VP, _I32]),
@@ -305,6 +312,41 @@ class Context:
                                order, _addr(workspace), workspace.numel(), algo, int(check_fk), _stream(stream))
         _check(st, "dpg_fk_join")
         return out
+
+    # ---- hash index and batch lookup (Section 4.2.3) --------------------
+    def hash_build(self, keys, log2_slots: int, stream=None):
+        """Build the hash index of a uint32 key tensor (rid = position); returns
+        the index as a uint8 device tensor."""
+        import torch
+
+        n = keys.numel()
+        nbytes = lib().dpg_hash_index_bytes(n, log2_slots)
+        if nbytes == 0:
+            raise DPGError(ERR_INVALID_ARG, "dpg_hash_index_bytes")
+        index = torch.empty(nbytes, dtype=torch.uint8, device=keys.device)
+        need = lib().dpg_hash_build_workspace_bytes(self.handle, n, log2_slots)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+        _check(lib().dpg_hash_build(self.handle, _addr(keys), n, log2_slots, _addr(index), index.numel(), _addr(ws),
+                                    ws.numel(), _stream(stream)), "dpg_hash_build")
+        return index
+
+    def hash_lookup_workspace_bytes(self, n_keys: int, log2_slots: int, n_queries: int, algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_hash_lookup_workspace_bytes(self.handle, n_keys, log2_slots, n_queries, algo)
+
+    def hash_lookup(self, index, n_keys: int, log2_slots: int, queries, rids=None, algo: int = ALGO_AUTO,
+                    workspace=None, stream=None):
+        """rids[i] = smallest rid whose key equals queries[i], or -1."""
+        import torch
+
+        m = queries.numel()
+        if rids is None:
+            rids = torch.empty(m, dtype=torch.int32, device=queries.device)
+        if workspace is None:
+            need = self.hash_lookup_workspace_bytes(n_keys, log2_slots, m, algo)
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=queries.device)
+        _check(lib().dpg_hash_lookup(self.handle, _addr(index), n_keys, log2_slots, _addr(queries), m, _addr(rids),
+                                     _addr(workspace), workspace.numel(), algo, _stream(stream)), "dpg_hash_lookup")
+        return rids
 
     # ---- batches -------------------------------------------------------
     def batch_workspace_bytes(self, reqs) -> int:

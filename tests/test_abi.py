@@ -156,3 +156,35 @@ def test_plan_phase_forms():
         assert p.n_runs <= 4096
     p = dpg.plan_retrieve(1 << 26, 8, 1 << 26, dpg.ALGO_DIRECT)
     assert p.distribute == 0 and p.gather == 0
+
+
+def test_hash_index_layout_and_validation():
+    lib = dpg.lib()
+    s = 10
+    assert lib.dpg_hash_ov_off_offset(s) == 8 << s
+    assert lib.dpg_hash_ov_offset(s) == (8 << s) + (((4 * ((1 << s) + 1)) + 255) // 256) * 256
+    assert lib.dpg_hash_index_bytes(1000, s) == lib.dpg_hash_ov_offset(s) + 8192
+    for bad in ((1000, 3), (1000, 31), (-1, 10), (1 << 31, 10)):
+        assert lib.dpg_hash_index_bytes(*bad) == 0
+    assert lib.dpg_hash_build_workspace_bytes(None, 1000, 3) == 0
+    need_ix = lib.dpg_hash_index_bytes(1000, s)
+    need_ws = lib.dpg_hash_build_workspace_bytes(None, 1000, s)
+    assert need_ws > 0
+    IX = 0x50000000
+    E = dpg
+    # valid arguments, but no context
+    assert lib.dpg_hash_build(None, SRC, 1000, s, IX, need_ix, WS, need_ws, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_hash_build(None, SRC, 1000, s, IX, need_ix - 1, WS, need_ws, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_hash_build(None, SRC, 1000, s, IX + 16, need_ix, WS, need_ws, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_hash_build(None, SRC, 1000, s, IX, need_ix, WS, need_ws - 1, None) == E.ERR_WORKSPACE_TOO_SMALL
+    assert lib.dpg_hash_build(None, SRC, 1000, s, IX, need_ix, IX + 256, need_ws, None) == E.ERR_INVALID_ARG
+    need_q = lib.dpg_hash_lookup_workspace_bytes(None, 1000, s, 5000, dpg.ALGO_DPG)
+    assert need_q > 0
+    assert lib.dpg_hash_lookup_workspace_bytes(None, 1000, s, 5000, dpg.ALGO_DIRECT) == 256
+    assert lib.dpg_hash_lookup_workspace_bytes(None, 1000, s, 5000, 7) == 0
+    assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, DST, WS, need_q, dpg.ALGO_DPG, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, DST, WS, need_q - 1, dpg.ALGO_DPG,
+                               None) == E.ERR_WORKSPACE_TOO_SMALL
+    assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, RIDS + 4, WS, need_q, dpg.ALGO_DPG,
+                               None) == E.ERR_INVALID_ARG  # output over the queries
+    assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, DST, WS, need_q, 9, None) == E.ERR_INVALID_ARG
