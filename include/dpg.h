@@ -256,7 +256,9 @@ dpg_status dpg_hash_build(dpg_ctx *ctx, const uint32_t *keys, int64_t n_keys, in
  * n_queries).  index must have been built for (n_keys, log2_slots).  algo:
  * DPG_ALGO_DIRECT probes the index once per query in query order; DPG_ALGO_DPG
  * distributes the queries by index partition (2^DPG_OPT_LOG2_RUN slots per
- * partition, default 2^18), probes each partition, and gathers the rids;
+ * partition), probes each partition -- staged in LDS (default and at most
+ * 2^14 slots per partition) or through the caches (DPG_OPT_PROBE =
+ * DPG_PROBE_CACHED, default 2^18 slots) -- and gathers the rids;
  * DPG_ALGO_AUTO picks DPG.  rids must not overlap queries, index or workspace. */
 size_t dpg_hash_lookup_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys, int32_t log2_slots,
                                        int64_t n_queries, dpg_algo algo);

@@ -65,6 +65,7 @@ enum KernelId {
     K_HASH_OVOFF,
     K_HASH_DIRECT,       // batch lookup, one probe per query in query order
     K_HASH_PROBE,        // batch lookup, DPG Phase II over one index partition at a time
+    K_HASH_PROBE_LDS,    // the same with the partition's slots staged in LDS
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -169,9 +170,10 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
 // The DPG plan of a hash-index batch lookup: queries distributed into 2^bits
 // runs of index slots by the top bits of key * kHashMul (their home slot's
-// partition); INTERNAL holds one int32 rid per query.  log2_run_slots 0 means
-// 2^18 slots (2 MiB of slots) per run.
-dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather,
+// partition); INTERNAL holds one int32 rid per query.  probe: DPG_PROBE_CACHED
+// reads each run's slots through the caches (2^18 slots per run by default),
+// otherwise they are staged in LDS when a run's slots fit (2^14 by default).
+dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather, int probe,
                                  RetrievePlan *plan);
 
 // Phases I and II of a planned DPG retrieval: afterwards the workspace holds

@@ -129,6 +129,82 @@ __global__ __launch_bounds__(256) void k_hash_probe(const uint32_t *__restrict__
     internal[p] = probe_key(slots, ov_off, ov, n_keys, z * kHashMulInv, slot_of(z, s));
 }
 
+// Phase II with the run's slots staged in LDS.  Work item = (run b, chunk of
+// at most P queries of run b); the workgroup loads slots [b*L, (b+1)*L) with
+// 16-byte loads, then probes its queries there (an overflow range, needed only
+// when the slot holds another key, is read through the caches).
+constexpr int kHashProbeThreads = 1024;
+constexpr int kHashProbeBatch = 16;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kHashProbeThreads) void k_hash_probe_lds(
+    const uint32_t *__restrict__ zrun, const int32_t *__restrict__ run_off, const int32_t *__restrict__ item_off,
+    int B, int lg_l, int P, const uint2 *__restrict__ slots, const int32_t *__restrict__ ov_off,
+    const uint2 *__restrict__ ov, int64_t n_keys, int s, int32_t *__restrict__ internal) {
+    extern __shared__ __align__(16) char smem[];
+    uint2 *s_slots = (uint2 *)smem;
+    __shared__ int s_bucket;
+    const int32_t item = (int32_t)blockIdx.x;
+    if (item >= item_off[B]) return;
+    if (threadIdx.x == 0) {
+        int lo = 0, hi = B - 1;  // largest b with item_off[b] <= item
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (item_off[mid] <= item) lo = mid;
+            else hi = mid - 1;
+        }
+        s_bucket = lo;
+    }
+    __syncthreads();
+    const int b = s_bucket;
+    const int64_t k0 = (int64_t)run_off[b] + (int64_t)(item - item_off[b]) * P;
+    const int64_t k1 = min(k0 + P, (int64_t)run_off[b + 1]);
+    const int cnt = (int)(k1 - k0);
+    const int L = 1 << lg_l;
+    const int64_t base = (int64_t)b << lg_l;
+    const u32x4 *src4 = (const u32x4 *)(slots + base);
+    u32x4 *dst4 = (u32x4 *)s_slots;
+#pragma unroll 4
+    for (int e = threadIdx.x; e < L / 2; e += kHashProbeThreads) dst4[e] = src4[e];
+    __syncthreads();
+    // the chunk's keys are loaded kHashProbeBatch per thread at a time, all in
+    // flight together, before any is probed
+    for (int j0 = 0; j0 < cnt; j0 += kHashProbeThreads * kHashProbeBatch) {
+        uint32_t zz[kHashProbeBatch];
+#pragma unroll
+        for (int k = 0; k < kHashProbeBatch; ++k)
+            zz[k] = zrun[k0 + min(j0 + (int)threadIdx.x + k * kHashProbeThreads, cnt - 1)];
+#pragma unroll
+        for (int k = 0; k < kHashProbeBatch; ++k) {
+            const int j = j0 + (int)threadIdx.x + k * kHashProbeThreads;
+            if (j >= cnt) break;
+            const uint32_t z = zz[k];
+            const uint32_t q = z * kHashMulInv, h = slot_of(z, s);
+            const int64_t local = (int64_t)h - base;
+            int32_t r = -1;
+            if (local >= 0 && local < L) {
+                const uint2 sl = s_slots[local];
+                if (sl.y != DPG_HASH_EMPTY) {
+                    if (sl.x == q) {
+                        r = (int32_t)sl.y;
+                    } else {
+                        const int64_t a = max((int64_t)ov_off[h], (int64_t)0);
+                        const int64_t e = min((int64_t)ov_off[h + 1], n_keys);
+                        for (int64_t x = a; x < e; ++x) {
+                            const uint2 o = ov[x];
+                            if (o.x == q) {
+                                r = (int32_t)o.y;
+                                break;
+                            }
+                        }
+                    }
+                }
+            }
+            internal[k0 + j] = r;
+        }
+    }
+}
+
 // ---- workspace layout --------------------------------------------------------
 struct HashBuildPlan {
     int64_t n = 0;
@@ -264,7 +340,7 @@ size_t dpg_hash_lookup_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys, int32
     if (algo != DPG_ALGO_AUTO && algo != DPG_ALGO_DPG) return 0;
     RetrievePlan p;
     if (make_hash_lookup_plan(n_queries, log2_slots, ctx ? (int)ctx->opt_log2_run : 0,
-                              ctx ? (int)ctx->opt_gather : 0, &p) != DPG_OK)
+                              ctx ? (int)ctx->opt_gather : 0, ctx ? (int)ctx->opt_probe : 0, &p) != DPG_OK)
         return 0;
     return p.workspace;
 }
@@ -285,7 +361,8 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
     RetrievePlan p;
     if (a == DPG_ALGO_DPG) {
         const dpg_status st = make_hash_lookup_plan(n_queries, log2_slots, ctx ? (int)ctx->opt_log2_run : 0,
-                                                    ctx ? (int)ctx->opt_gather : 0, &p);
+                                                    ctx ? (int)ctx->opt_gather : 0, ctx ? (int)ctx->opt_probe : 0,
+                                                    &p);
         if (st != DPG_OK) return st;
         if (n_queries > 0) {
             if (workspace_bytes < p.workspace) return DPG_ERR_WORKSPACE_TOO_SMALL;
@@ -313,12 +390,27 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
     // Phase I: distribute z = key * kHashMul by its top bits (the index partition)
     char *w = (char *)workspace;
     const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+    const bool lds_probe = p.probe == DPG_PROBE_LDS;
+    int32_t *item_off = lds_probe ? (int32_t *)(w + p.off_items) : nullptr;
+    int32_t *run_off = nullptr;
     dpg_status st = launch_partition(ctx, pp, queries, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv),
-                                     p.log2_run, 0, w + p.off_part, stream, nullptr, nullptr, 0, /*stable=*/false,
-                                     p.gather_lds, kHashMul);
+                                     p.log2_run, 0, w + p.off_part, stream, &run_off, item_off,
+                                     lds_probe ? p.probe_chunk : 0, /*stable=*/false, p.gather_lds, kHashMul);
     if (st != DPG_OK) return st;
     // Phase II: probe one partition of the index at a time
-    {
+    if (lds_probe) {
+        const int B = (int)p.n_runs, lg_l = log2_slots - p.part_nbits, P = p.probe_chunk;
+        const size_t lds = (size_t)8 << lg_l;
+        const int64_t grid = (int64_t)B + (n_queries + P - 1) / P;
+        ProfScope prof(ctx, K_HASH_PROBE_LDS, 8.0 * M + 8.0 * ((double)((int64_t)1 << log2_slots)), stream);
+        if (lds > 64 * 1024)
+            DPG_HIP(hipFuncSetAttribute((const void *)k_hash_probe_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds));
+        hipLaunchKernelGGL(k_hash_probe_lds, dim3((unsigned)grid), dim3(kHashProbeThreads), lds, stream,
+                           (const uint32_t *)(w + p.off_run), run_off, item_off, B, lg_l, P, slots, ov_off, ov,
+                           n_keys, log2_slots, (int32_t *)(w + p.off_internal));
+        DPG_HIP(hipGetLastError());
+    } else {
         ProfScope prof(ctx, K_HASH_PROBE, 8.0 * M + 8.0 * ((double)((int64_t)1 << log2_slots)), stream);
         hipLaunchKernelGGL(k_hash_probe, dim3(grid_of(n_queries)), dim3(256), 0, stream,
                            (const uint32_t *)(w + p.off_run), n_queries, slots, ov_off, ov, n_keys, log2_slots,

@@ -146,7 +146,7 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     }
 }
 
-dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather,
+dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2_run_slots, int gather, int probe,
                                  RetrievePlan *p) {
     if (n_queries < 0 || n_queries > INT32_MAX - 1 || log2_slots < 4 || log2_slots > 30) return DPG_ERR_INVALID_ARG;
     *p = RetrievePlan();
@@ -156,10 +156,18 @@ dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2
     p->rec_bytes = 4;  // INTERNAL holds an int32 rid per query
     p->probe = DPG_PROBE_CACHED;
     if (n_queries > 0) {
-        const int l = log2_run_slots > 0 ? log2_run_slots : 18;
+        // LDS probe: 2^14 slots (128 KiB) per run unless set otherwise, at
+        // most 2^14; the cached probe: 2^18 slots (2 MiB).  Measured at 2^26
+        // queries: 2^14-slot runs beat 2^13 (fewer runs for Phases I and III).
+        const bool lds = probe != DPG_PROBE_CACHED;
+        const int l = log2_run_slots > 0 ? log2_run_slots : (lds ? 14 : 18);
         int bits = log2_slots - l;
         if (bits < 1) bits = 1;
         if (bits > kMaxWideBits) bits = kMaxWideBits;
+        if (lds && log2_slots - bits <= 14) {
+            p->probe = DPG_PROBE_LDS;
+            p->probe_chunk = 16384;
+        }
         p->log2_run = 32 - bits;  // run of a query = (key * kHashMul) >> (32 - bits)
         p->n_runs = (int64_t)1 << bits;
         p->dist_mode = DIST_PARTITION;

@@ -94,6 +94,8 @@ LOOKUP_VARIANTS = {
     "direct": (dpg.ALGO_DIRECT, {}),
     "dpg": (dpg.ALGO_DPG, {}),
     "dpg-cached-gather": (dpg.ALGO_DPG, dict(gather=dpg.GATHER_CACHED)),
+    "dpg-cached-probe": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED)),
+    "dpg-cached-probe-and-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, gather=dpg.GATHER_CACHED)),
     "dpg-small-partitions": (dpg.ALGO_DPG, dict(log2_run=6)),     # many (wide-partition) runs
     "dpg-one-partition": (dpg.ALGO_DPG, dict(log2_run=30)),        # the minimum of two runs
     "auto": (dpg.ALGO_AUTO, {}),
@@ -122,12 +124,14 @@ def test_lookup_matches_oracle(ctx, case, variant):
     index = ctx.hash_build(dev(keys), s)
     ctx.set_option(dpg.OPT_LOG2_RUN, opts.get("log2_run", 0))
     ctx.set_option(dpg.OPT_GATHER, opts.get("gather", 0))
+    ctx.set_option(dpg.OPT_PROBE, opts.get("probe", 0))
     try:
         got = ctx.hash_lookup(index, n, s, dev(queries), algo=algo)
         torch.cuda.synchronize()
     finally:
         ctx.set_option(dpg.OPT_LOG2_RUN, 0)
         ctx.set_option(dpg.OPT_GATHER, 0)
+        ctx.set_option(dpg.OPT_PROBE, 0)
     want = oracle.hash_lookup(keys, queries)
     assert np.array_equal(got.cpu().numpy(), want)
 
@@ -146,9 +150,13 @@ def test_lookup_full_size_sampled(ctx):
     queries = keys_d[pick].clone()
     miss = torch.rand(m, device=DEV, generator=g) >= 0.8
     queries[miss] = 2 * torch.randint(0, 1 << 30, (int(miss.sum()),), device=DEV, generator=g).to(torch.int32)
-    for algo in (dpg.ALGO_DIRECT, dpg.ALGO_DPG):
-        got = ctx.hash_lookup(index, n, s, queries, algo=algo)
-        torch.cuda.synchronize()
+    for algo, probe in ((dpg.ALGO_DIRECT, 0), (dpg.ALGO_DPG, dpg.PROBE_CACHED), (dpg.ALGO_DPG, 0)):
+        ctx.set_option(dpg.OPT_PROBE, probe)
+        try:
+            got = ctx.hash_lookup(index, n, s, queries, algo=algo)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_option(dpg.OPT_PROBE, 0)
         assert torch.equal(got[miss], torch.full_like(got[miss], -1))
         hit = ~miss
         assert torch.equal(got[hit].to(torch.int64), pick[hit])
