@@ -430,7 +430,8 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
         for name, kw in modes.items():
             servers[name] = dpg.Server(ctx, budget, **kw)
             log(f"bench: serving saturation run, {name}")
-            st = run(servers[name], None)
+            # the better of two runs: a single one varies by about 10 %
+            st = min((run(servers[name], None) for _ in range(2)), key=lambda t: t["span_s"])
             sat[name] = n_req / st["span_s"]
             res[f"{name}_saturation"] = {"req_per_s": round(sat[name], 1),
                                          "GB_per_s": round(st["bytes_delivered"] / st["span_s"] / 1e9, 2),
@@ -438,10 +439,10 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
                                          "span_s": round(st["span_s"], 4)}
             servers[name].close()
             del servers[name]
-        # common arrival rates: 50, 80 and 95 % of what per-request launches
-        # sustain; every mode sees the same arrival times at each rate
+        # common arrival rates: 50, 80, 95 and 110 % of what per-request
+        # launches sustain; every mode sees the same arrival times at each rate
         res["load_points"] = []
-        for frac in (0.5, 0.8, 0.95):
+        for frac in (0.5, 0.8, 0.95, 1.1):
             rate = frac * sat["per_request"]
             point = {"fraction_of_per_request_saturation": frac, "arrival_rate_req_per_s": round(rate, 1)}
             for name, kw in modes.items():
