@@ -16,10 +16,11 @@
 //     there as one persistent batch -- a replay of the slot's captured graph,
 //     or the same two kernels launched directly -- after waiting up to
 //     batch_window_us for a partial batch to fill; any other request runs
-//     alone through its
-//     single-request entry point, whose dedicated kernels are faster for
-//     large outputs and need no batching to hide launch cost.  With batches
-//     of one, every request takes that path (the per-request baseline).
+//     alone through its single-request entry point, whose dedicated kernels
+//     are faster for large outputs and need no batching to hide launch cost.
+//     A batch that would hold a single request also takes that path, so
+//     batching costs nothing at low load.  With max_batch_requests = 1 every
+//     request takes it (the per-request baseline).
 //     Requests arriving while batches run are admitted and launched on the
 //     next free slot, so their work overlaps on the device.
 //   * Completion: a batch's event marks all its requests done; their latency
@@ -122,6 +123,7 @@ struct Ticket {
     int state = T_QUEUED;
     dpg_status status = DPG_OK;
     bool batched = false;          // runs inside a slot's persistent batch launch
+    size_t own_ws = 0;             // workspace of its single-request entry point
     size_t out_off = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0;
     bool has_out = false, has_ws = false;
     Clock::time_point submit, admit, done;
@@ -203,14 +205,18 @@ static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> 
     dpg_ctx *ctx = s->ctx;
     dpg_status st = DPG_OK;
     const Ticket &first = s->tickets[batch[0]];
-    if (!first.batched) {
+    // A batch of one runs through the single-request entry point (no
+    // descriptor upload), borrowing the idle slot's descriptor workspace.
+    const bool alone = first.batched && batch.size() == 1 && first.own_ws <= sl.batch_ws_bytes;
+    if (!first.batched || alone) {
         const dpg_request &q = first.req;
-        char *w = first.has_ws ? s->base + first.ws_off : nullptr;
+        char *w = alone ? s->base + sl.batch_ws_off : (first.has_ws ? s->base + first.ws_off : nullptr);
+        const size_t wb = alone ? sl.batch_ws_bytes : first.ws_bytes;
         st = q.kind == DPG_REQ_RETRIEVE
-                 ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w, first.ws_bytes,
-                                (dpg_algo)q.algo, 0, sl.stream)
+                 ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w, wb, (dpg_algo)q.algo, 0,
+                                sl.stream)
                  : dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
-                               (dpg_join_order)q.order, w, first.ws_bytes, (dpg_algo)q.algo, 0, sl.stream);
+                               (dpg_join_order)q.order, w, wb, (dpg_algo)q.algo, 0, sl.stream);
     } else {
         std::vector<dpg_request> reqs;
         reqs.reserve(batch.size());
@@ -441,6 +447,7 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
         const size_t max_batched = (size_t)(s->cfg.batch_max_kib > 0 ? s->cfg.batch_max_kib : 4096) << 10;
         tk.batched = direct && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
         tk.ws_bytes = tk.batched ? 0 : own_ws;
+        tk.own_ws = own_ws;
     } else {
         tk.state = T_FAILED;
     }
