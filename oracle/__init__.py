@@ -14,6 +14,8 @@ Cache-Efficient Accelerator for Sorting and for Join Operators":
 * :func:`sort_records` -- the three-phase key-pointer sort of Section 3.
 * :func:`fk_join_fact_order` / :func:`fk_join_dim_order` -- the DPG-Move and
   DPG-Sort goals of Section 4.2.1.
+* :func:`sort_merge_join` -- the sort-merge join of Section 4.1 (all pairs of
+  equal join keys, ordered by key, then R index, then S index).
 * :func:`hash_build` / :func:`hash_lookup` -- the hash index of Section 4.2.3
   (one key-rid pair per slot, collisions in an overflow array) and the result
   of a batch lookup (smallest rid holding each query key, or -1).
@@ -64,9 +66,10 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_fk_join_dim_order.argtypes = join
     lib.oracle_hash_build.argtypes = [_VP, _I64, _I32, _VP, _VP, _VP, _VP]
     lib.oracle_hash_lookup.argtypes = [_VP, _I64, _VP, _I64, _VP]
+    lib.oracle_sort_merge_join.argtypes = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64, _VP]
     for f in (lib.oracle_retrieve, lib.oracle_dpg_phases, lib.oracle_sort_records,
               lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order, lib.oracle_hash_build,
-              lib.oracle_hash_lookup):
+              lib.oracle_hash_lookup, lib.oracle_sort_merge_join):
         f.restype = ctypes.c_int
     return lib
 
@@ -197,4 +200,24 @@ def hash_lookup(keys: np.ndarray, queries: np.ndarray, lib=None) -> np.ndarray:
     rc = lib.oracle_hash_lookup(_ptr(k), k.size, _ptr(q), q.size, _ptr(out))
     if rc:
         raise OracleError(rc, "hash_lookup")
+    return out
+
+
+def sort_merge_join(r: np.ndarray, s: np.ndarray, key_off_r: int, key_off_s: int, key_bytes: int, lib=None):
+    """Sort-merge join (Section 4.1): rows R[i] || S[j] for every pair of equal
+    join keys, ordered by key (memcmp), then i, then j."""
+    lib = lib or load()
+    a = _records(r, r.shape[1])
+    b = _records(s, s.shape[1])
+    n = ctypes.c_int64()
+    rc = lib.oracle_sort_merge_join(_ptr(a), a.shape[0], a.shape[1], key_off_r, _ptr(b), b.shape[0], b.shape[1],
+                                    key_off_s, key_bytes, ctypes.c_void_p(0), 0, ctypes.byref(n))
+    if rc not in (OK, ERANGE):
+        raise OracleError(rc, "sort_merge_join")
+    out = np.empty((n.value, a.shape[1] + b.shape[1]), dtype=np.uint8)
+    if n.value:
+        rc = lib.oracle_sort_merge_join(_ptr(a), a.shape[0], a.shape[1], key_off_r, _ptr(b), b.shape[0],
+                                        b.shape[1], key_off_s, key_bytes, _ptr(out), n.value, ctypes.byref(n))
+        if rc:
+            raise OracleError(rc, "sort_merge_join")
     return out

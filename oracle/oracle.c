@@ -413,3 +413,103 @@ int oracle_hash_lookup(const uint32_t *keys, int64_t n, const uint32_t *queries,
     free(pairs);
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Sort-merge join (Section 4.1): both relations sorted on the join key, then */
+/* merged.  The result is every pair (i, j) whose join keys are equal (the    */
+/* key_bytes bytes at key_off_r of R row i and at key_off_s of S row j), each */
+/* written as R row i followed by S row j, ordered by key (unsigned bytes,    */
+/* memcmp order), then i, then j.                                            */
+/* Returns ERANGE with *n_out = the number of result rows when out_capacity  */
+/* rows do not hold them (nothing is written then).                          */
+/* ------------------------------------------------------------------------- */
+typedef struct {
+    const uint8_t *key;
+    int64_t idx;
+} keyed_row;
+
+static int32_t g_smj_key_bytes;
+
+static int compare_keyed_row(const void *pa, const void *pb)
+{
+    const keyed_row *a = pa, *b = pb;
+    int c = memcmp(a->key, b->key, (size_t)g_smj_key_bytes);
+    if (c)
+        return c;
+    return (a->idx > b->idx) - (a->idx < b->idx);
+}
+
+static keyed_row *sorted_rows(const uint8_t *rows, int64_t n, int32_t rec_bytes, int32_t key_off)
+{
+    keyed_row *k = malloc((size_t)(n > 0 ? n : 1) * sizeof(keyed_row));
+    if (!k)
+        return NULL;
+    for (int64_t i = 0; i < n; ++i) {
+        k[i].key = rows + i * (int64_t)rec_bytes + key_off;
+        k[i].idx = i;
+    }
+    qsort(k, (size_t)n, sizeof(keyed_row), compare_keyed_row);
+    return k;
+}
+
+int oracle_sort_merge_join(const uint8_t *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                           const uint8_t *s, int64_t n_s, int32_t rec_s, int32_t key_off_s,
+                           int32_t key_bytes, uint8_t *out, int64_t out_capacity, int64_t *n_out)
+{
+    if (n_r < 0 || n_s < 0 || rec_r < 1 || rec_s < 1 || key_bytes < 1 || key_off_r < 0 || key_off_s < 0 ||
+        key_off_r + key_bytes > rec_r || key_off_s + key_bytes > rec_s)
+        return ORACLE_EINVAL;
+    g_smj_key_bytes = key_bytes;
+    keyed_row *kr = sorted_rows(r, n_r, rec_r, key_off_r);
+    keyed_row *ks = sorted_rows(s, n_s, rec_s, key_off_s);
+    if (!kr || !ks) {
+        free(kr);
+        free(ks);
+        return ORACLE_EINVAL;
+    }
+    int64_t out_bytes = (int64_t)rec_r + rec_s;
+    for (int pass = 0; pass < 2; ++pass) {  /* count, then write */
+        int64_t a = 0, b = 0, n = 0;
+        while (a < n_r && b < n_s) {
+            int c = memcmp(kr[a].key, ks[b].key, (size_t)key_bytes);
+            if (c < 0) {
+                ++a;
+            } else if (c > 0) {
+                ++b;
+            } else {
+                int64_t a2 = a, b2 = b;
+                while (a2 < n_r && memcmp(kr[a2].key, kr[a].key, (size_t)key_bytes) == 0)
+                    ++a2;
+                while (b2 < n_s && memcmp(ks[b2].key, ks[b].key, (size_t)key_bytes) == 0)
+                    ++b2;
+                /* the pairs of one key, R index major */
+                for (int64_t u = 0; u < (a2 - a) * (b2 - b); ++u) {
+#ifdef ORACLE_MUTANT_SMJ_J_MAJOR
+                    int64_t x = a + u % (a2 - a), y = b + u / (a2 - a);
+#else
+                    int64_t x = a + u / (b2 - b), y = b + u % (b2 - b);
+#endif
+                    if (pass == 1) {
+                        uint8_t *row = out + n * out_bytes;
+                        memcpy(row, r + kr[x].idx * (int64_t)rec_r, (size_t)rec_r);
+                        memcpy(row + rec_r, s + ks[y].idx * (int64_t)rec_s, (size_t)rec_s);
+                    }
+                    ++n;
+                }
+                a = a2;
+                b = b2;
+            }
+        }
+        if (pass == 0) {
+            *n_out = n;
+            if (n > out_capacity) {
+                free(kr);
+                free(ks);
+                return ORACLE_ERANGE;
+            }
+        }
+    }
+    free(kr);
+    free(ks);
+    return ORACLE_OK;
+}

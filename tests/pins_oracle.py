@@ -360,9 +360,83 @@ def pin_hash_errors(lib):
             raise AssertionError("bad slot count accepted")
 
 
+# ---------------------------------------------------------------------------
+# sort-merge join (Section 4.1)
+# ---------------------------------------------------------------------------
+def _smj_brute(r, s, kr, ks, kb):
+    """Every pair of equal keys by nested loops, ordered by (key bytes, i, j)."""
+    pairs = [(bytes(r[i, kr:kr + kb]), i, j) for i in range(r.shape[0]) for j in range(s.shape[0])
+             if bytes(r[i, kr:kr + kb]) == bytes(s[j, ks:ks + kb])]
+    pairs.sort()
+    w = r.shape[1] + s.shape[1]
+    if not pairs:
+        return np.zeros((0, w), dtype=np.uint8)
+    return np.stack([np.concatenate([r[i], s[j]]) for _, i, j in pairs])
+
+
+def pin_smj_brute_force(lib):
+    """Small relations over a tiny key alphabet (many duplicates on both
+    sides): the join equals the nested-loop pairs in (key, i, j) order."""
+    rng = np.random.default_rng(12)
+    for trial in range(60):
+        kb = int(rng.integers(1, 4))
+        nr, ns = int(rng.integers(0, 13)), int(rng.integers(0, 13))
+        wr, ws = kb + int(rng.integers(0, 6)), kb + int(rng.integers(0, 6))
+        kr, ks = int(rng.integers(0, wr - kb + 1)), int(rng.integers(0, ws - kb + 1))
+        r = rng.integers(0, 256, (nr, wr), dtype=np.uint8)
+        s = rng.integers(0, 256, (ns, ws), dtype=np.uint8)
+        alphabet = rng.integers(0, 256, (3, kb), dtype=np.uint8)
+        if nr:
+            r[:, kr:kr + kb] = alphabet[rng.integers(0, 3, nr)]
+        if ns:
+            s[:, ks:ks + kb] = alphabet[rng.integers(0, 3, ns)]
+        got = oracle.sort_merge_join(r, s, kr, ks, kb, lib=lib)
+        want = _smj_brute(r, s, kr, ks, kb)
+        assert got.shape == want.shape and np.array_equal(got, want), (trial, got.shape, want.shape)
+
+
+def pin_smj_closed_forms(lib):
+    """Distinct keys: the join is the matching rows in key order; disjoint key
+    sets give nothing; one shared key gives the full cross product, R major."""
+    n = 300
+    r = distinct_records(n, 8, seed=1)
+    s = distinct_records(2 * n, 12, seed=2)
+    keys = synth.rids_permutation(2 * n, seed=9).astype(">u4")  # big-endian: memcmp order = integer order
+    s[:, 4:8] = keys.view(np.uint8).reshape(-1, 4)
+    r[:, 0:4] = (np.arange(n, dtype=np.uint32) * 2).astype(">u4").view(np.uint8).reshape(-1, 4)  # even keys
+    out = oracle.sort_merge_join(r, s, 0, 4, 4, lib=lib)
+    ks = keys.astype(np.int64)
+    match = [(k, i, int(np.nonzero(ks == k)[0][0])) for i, k in enumerate(range(0, 2 * n, 2)) if k < 2 * n]
+    assert out.shape[0] == len(match)
+    for row, (k, i, j) in zip(out, match):
+        assert np.array_equal(row[:8], r[i]) and np.array_equal(row[8:], s[j])
+    s2 = s.copy()
+    s2[:, 4:8] = np.frombuffer((np.arange(2 * n, dtype=np.uint32) * 2 + 1).astype(">u4").tobytes(),
+                               dtype=np.uint8).reshape(-1, 4)  # odd keys
+    assert oracle.sort_merge_join(r, s2, 0, 4, 4, lib=lib).shape == (0, 20)
+    r3, s3 = r[:7].copy(), s[:5].copy()
+    r3[:, 0:4] = 77
+    s3[:, 4:8] = 77
+    out3 = oracle.sort_merge_join(r3, s3, 0, 4, 4, lib=lib)
+    want = np.stack([np.concatenate([r3[i], s3[j]]) for i in range(7) for j in range(5)])
+    assert np.array_equal(out3, want)
+
+
+def pin_smj_errors(lib):
+    r = np.zeros((4, 8), dtype=np.uint8)
+    for kr, kb in ((5, 4), (0, 0), (-1, 2)):
+        try:
+            oracle.sort_merge_join(r, r, kr, 0, kb, lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == oracle.EINVAL
+        else:
+            raise AssertionError("bad key accepted")
+
+
 ALL_PINS = [
     pin_retrieve_brute_force, pin_retrieve_closed_forms, pin_retrieve_multiset, pin_retrieve_errors,
     pin_fig2_example, pin_phase_invariants, pin_sort_random, pin_sort_ties,
     pin_join_fact_order, pin_join_dim_order, pin_join_errors,
     pin_hash_lookup_brute_force, pin_hash_lookup_closed_forms, pin_hash_build_invariants, pin_hash_errors,
+    pin_smj_brute_force, pin_smj_closed_forms, pin_smj_errors,
 ]

@@ -16,6 +16,7 @@ MUTANTS = {
     "ORACLE_MUTANT_UNSTABLE_JOIN": [pins_oracle.pin_join_dim_order],
     "ORACLE_MUTANT_HASH_LAST": [pins_oracle.pin_hash_build_invariants],
     "ORACLE_MUTANT_LOOKUP_LAST": [pins_oracle.pin_hash_lookup_brute_force],
+    "ORACLE_MUTANT_SMJ_J_MAJOR": [pins_oracle.pin_smj_brute_force, pins_oracle.pin_smj_closed_forms],
 }
 
 
