@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
-    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,hash,serve (default all)")
+    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
@@ -300,6 +300,56 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                         "output 2^28 x 80 B rows", **res}
 
 
+def bench_smj(args, ctx, dpg, synth, torch, np):
+    """Sort-merge join with DPG sort (Section 4.1): two relations of 2^24 x
+    100 B rows, joined on a 4-byte key uniform over 2^24 values; both sorted by
+    the key-pointer sort (copy phase DPG or direct), then merged."""
+    dev = "cuda:0"
+    n, R, n_keys = 1 << 24, 100, 1 << 24
+    seed = synth.SEED_BASE + 7
+    log("bench: sort-merge join of 2^24 x 100 B with 2^24 x 100 B rows")
+    rel, counts = [], []
+    for side in range(2):
+        rows = synth.record_bytes(n, R, seed + side, backend="torch", device=dev)
+        k = synth.uniform_at(n_keys, torch.arange(n, device=dev), seed + side, synth.STREAM_FK, backend="torch",
+                             device=dev).to(torch.int32)
+        rows[:, 0:4] = k.view(torch.uint8).reshape(-1, 4)
+        rel.append(rows)
+        counts.append(torch.bincount(k.to(torch.int64), minlength=n_keys))
+    want_rows = int((counts[0] * counts[1]).sum())
+    del counts
+    cap = want_rows + 1024
+    out = torch.empty((cap, 2 * R), dtype=torch.uint8, device=dev)
+    res = {"workload": "R, S: 2^24 x 100 B rows each, 4-byte join key uniform over 2^24 values; "
+                       f"{want_rows} result rows of 200 B", "result_rows": want_rows}
+    steps = max(2, args.steps // 3)
+    for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
+        ws = torch.empty(ctx.sort_merge_join_workspace_bytes(n, R, 0, n, R, 0, 4, algo), dtype=torch.uint8,
+                         device=dev)
+        ctx.profile_enable(True)
+        ctx.profile_reset()
+        got = []
+        ms, _ = time_steps(lambda: got.append(ctx.sort_merge_join(rel[0], rel[1], 0, 0, 4, algo=algo, out=out,
+                                                                   workspace=ws)), steps, 1, torch)
+        prof = ctx.profile_collect()
+        ctx.profile_enable(False)
+        ctx.profile_reset()
+        rows = got[-1]
+        if rows.shape[0] != want_rows or not torch.equal(rows[:, 0:4], rows[:, R:R + 4]):
+            raise SystemExit(f"bench: {name} sort-merge join result is wrong")
+        kk = rows[:, 0:4].flip(1).contiguous().view(torch.int32).view(-1).to(torch.int64) & 0xFFFFFFFF
+        if not bool((kk[1:] >= kk[:-1]).all()):
+            raise SystemExit(f"bench: {name} sort-merge join result is not in key order")
+        calls = steps + 1
+        res[name] = {"ms": round(ms, 3), "input_rows_per_s": round(2 * n / (ms * 1e-3), 1),
+                     "kernels_ms_per_join": {k: round(v["ms"] / calls, 4) for k, v in prof.items()}}
+        del ws, got, rows, kk
+    res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
+    del rel, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_hash(args, ctx, dpg, synth, torch, np):
     """Batch lookup in a hash index (Section 4.2.3): 2^24 distinct uint32 keys
     in 2^25 slots, 2^26 query keys of which 80 % are stored; DPG (distribute
@@ -476,7 +526,7 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "hash", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -493,6 +543,8 @@ def main():
         out["sort"] = bench_sort(args, ctx, dpg, synth, torch, np)
     if "join" in only:
         out["join"] = bench_join(args, ctx, dpg, synth, torch, np)
+    if "smj" in only:
+        out["sort_merge_join"] = bench_smj(args, ctx, dpg, synth, torch, np)
     if "hash" in only:
         out["hash_lookup"] = bench_hash(args, ctx, dpg, synth, torch, np)
     if "serve" in only:

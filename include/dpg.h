@@ -217,6 +217,29 @@ dpg_status dpg_fk_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t f
                        dpg_algo algo, int check_fk, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Sort-merge join with DPG sort (Section 4.1): both relations are sorted on   */
+/* the join key with dpg_sort_records (copy phase: DPG, direct or AUTO), then  */
+/* merged.  The result holds one row per pair of rows with equal keys -- the  */
+/* R row followed by the S row (rec_r + rec_s bytes) -- ordered by key        */
+/* (unsigned bytes, memcmp order), then R index, then S index.  The join key  */
+/* is key_bytes (1..8) bytes at key_off_r of an R row and key_off_s of an S   */
+/* row.                                                                       */
+/* ------------------------------------------------------------------------- */
+size_t dpg_sort_merge_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                                           int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                                           dpg_algo sort_copy_algo);
+
+/* out holds out_capacity rows.  The call synchronizes the stream once to learn
+ * the number of result rows, stored in *out_rows (host).  If they do not fit,
+ * it returns DPG_ERR_WORKSPACE_TOO_SMALL and writes no row; 2^31 or more
+ * result rows return DPG_ERR_UNSUPPORTED.  out must not overlap r, s or the
+ * workspace. */
+dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                               const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                               void *out, int64_t out_capacity, int64_t *out_rows, void *workspace,
+                               size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Hash index and batch lookup (Section 4.2.3, batch lookup in hash indexes): */
 /* a hash index over uint32 keys (rid = position in the key array) holds one  */
 /* key-rid pair per slot and keeps the pairs that collide with an occupied    */

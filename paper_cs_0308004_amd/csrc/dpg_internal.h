@@ -66,6 +66,9 @@ enum KernelId {
     K_HASH_DIRECT,       // batch lookup, one probe per query in query order
     K_HASH_PROBE,        // batch lookup, DPG Phase II over one index partition at a time
     K_HASH_PROBE_LDS,    // the same with the partition's slots staged in LDS
+    K_SMJ_KEYS,          // sort-merge join: packed keys of the sorted relations
+    K_SMJ_RANGES,        //   matching S range of every R row
+    K_SMJ_EMIT,          //   result rows
     K_COUNT
 };
 const char *kernel_name(int id);

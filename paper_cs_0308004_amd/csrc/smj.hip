@@ -1,0 +1,267 @@
+// Sort-merge join with DPG sort (Section 4.1): both relations are sorted on
+// the join key by the key-pointer sort of Section 3 (dpg_sort_records, whose
+// copy phase is DPG or the direct gather), then merged.
+//
+// Merge: every sorted R row a finds the range [lo_a, lo_a + cnt_a) of sorted S
+// rows with its key by binary search over the S keys (packed big-endian into
+// uint64, so integer order is memcmp order); an exclusive scan of cnt gives
+// each R row its first output row; each output row o then finds its R row a
+// (binary search over the scanned offsets) and its S row lo_a + o - off_a.
+// Output rows are written in order, so the writes are coalesced, and the
+// sorted rows are read nearly in order.  The result order is (key, R index,
+// S index) because both sorts are stable.
+#include "dev_common.h"
+#include "dpg_internal.h"
+#include "partition.h"
+
+namespace dpg {
+
+constexpr int kSmjMaxKeyBytes = 8;
+
+// keys[i] = big-endian value of the kb key bytes at koff of row i.
+__global__ __launch_bounds__(256) void k_smj_keys(const uint8_t *__restrict__ rows, int64_t n, int rec, int koff,
+                                                  int kb, uint64_t *__restrict__ keys) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const uint8_t *p = rows + i * rec + koff;
+    uint64_t x = 0;
+    for (int t = 0; t < kb; ++t) x = (x << 8) | p[t];
+    keys[i] = x;
+}
+
+// lo[a], cnt[a]: the S rows whose key equals R row a's; total += cnt (int64).
+__global__ __launch_bounds__(256) void k_smj_ranges(const uint64_t *__restrict__ kr, int64_t nr,
+                                                    const uint64_t *__restrict__ ks, int64_t ns,
+                                                    int32_t *__restrict__ lo, int32_t *__restrict__ cnt,
+                                                    unsigned long long *__restrict__ total) {
+    __shared__ unsigned long long s_sum[4];
+    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t c = 0;
+    if (a < nr) {
+        const uint64_t k = kr[a];
+        int64_t l = 0, h = ns;  // first S key >= k
+        while (l < h) {
+            const int64_t m = (l + h) >> 1;
+            if (ks[m] < k) l = m + 1;
+            else h = m;
+        }
+        int64_t u = l, hu = ns;  // first S key > k
+        while (u < hu) {
+            const int64_t m = (u + hu) >> 1;
+            if (ks[m] <= k) u = m + 1;
+            else hu = m;
+        }
+        lo[a] = (int32_t)l;
+        c = u - l;
+        cnt[a] = (int32_t)c;
+    }
+    // block sum, one atomic per block
+    unsigned long long v = (unsigned long long)c;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long b = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
+        if (b) atomicAdd(total, b);
+    }
+}
+
+// Output rows [t*tile, ...): row o = R[a] || S[lo[a] + o - off[a]], a the last R
+// row with off[a] <= o (and cnt[a] > 0).  Rows are copied as dwords flattened
+// over the workgroup, every load issued before the stores.
+constexpr int kSmjPer = 32;
+
+__global__ __launch_bounds__(256) void k_smj_emit(const uint32_t *__restrict__ R, int wr, int64_t nr,
+                                                  const uint32_t *__restrict__ S, int ws, int64_t ns,
+                                                  const int32_t *__restrict__ off, const int32_t *__restrict__ lo,
+                                                  uint32_t *__restrict__ out, int64_t n_out, int tile,
+                                                  uint32_t magic) {
+    extern __shared__ int32_t s_ab[];
+    int32_t *s_a = s_ab, *s_b = s_ab + tile;
+    const int64_t base = (int64_t)blockIdx.x * tile;
+    const int cnt = (int)min((int64_t)tile, n_out - base);
+    for (int j = threadIdx.x; j < cnt; j += 256) {
+        const int64_t o = base + j;
+        int64_t l = 0, h = nr;  // first R row with off > o
+        while (l < h) {
+            const int64_t m = (l + h) >> 1;
+            if ((int64_t)off[m] <= o) l = m + 1;
+            else h = m;
+        }
+        const int64_t a = l > 0 ? l - 1 : 0;
+        int64_t b = (int64_t)lo[a] + (o - (int64_t)off[a]);
+        b = (b >= 0 && b < ns) ? b : 0;
+        s_a[j] = (int32_t)a;
+        s_b[j] = (int32_t)b;
+    }
+    __syncthreads();
+    const int W = wr + ws;
+    const int total = cnt * W;
+    int64_t src[kSmjPer];
+    bool from_r[kSmjPer];
+#pragma unroll
+    for (int k = 0; k < kSmjPer; ++k) {
+        const int e = min((int)threadIdx.x + k * 256, total - 1);
+        const int j = (int)__umulhi((uint32_t)e, magic);
+        const int w = e - j * W;
+        from_r[k] = w < wr;
+        src[k] = from_r[k] ? (int64_t)s_a[j] * wr + w : (int64_t)s_b[j] * ws + (w - wr);
+    }
+    uint32_t v[kSmjPer];
+#pragma unroll
+    for (int k = 0; k < kSmjPer; ++k) v[k] = from_r[k] ? R[src[k]] : S[src[k]];
+    uint32_t *o = out + base * W;
+#pragma unroll
+    for (int k = 0; k < kSmjPer; ++k) {
+        const int e = threadIdx.x + k * 256;
+        if (e < total) __builtin_nontemporal_store(v[k], o + e);
+    }
+}
+
+struct SmjPlan {
+    int64_t nr = 0, ns = 0;
+    int rec_r = 0, rec_s = 0, koff_r = 0, koff_s = 0, kb = 0, algo = 0;
+    size_t sort_ws = 0;
+    size_t off_r = 0, off_s = 0, off_sort = 0, off_kr = 0, off_ks = 0, off_lo = 0, off_cnt = 0, off_scan = 0,
+           off_total = 0, workspace = 0;
+};
+
+static dpg_status make_smj_plan(const dpg_ctx *ctx, int64_t nr, int32_t rec_r, int32_t koff_r, int64_t ns,
+                                int32_t rec_s, int32_t koff_s, int32_t kb, int algo, SmjPlan *p) {
+    if (nr < 0 || nr > INT32_MAX - 1 || ns < 0 || ns > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
+    if (rec_r < 4 || rec_r > kMaxRecBytes || rec_r % 4 || rec_s < 4 || rec_s > kMaxRecBytes || rec_s % 4)
+        return DPG_ERR_INVALID_ARG;
+    if (kb < 1 || kb > kSmjMaxKeyBytes || koff_r < 0 || koff_s < 0 || koff_r + kb > rec_r || koff_s + kb > rec_s)
+        return DPG_ERR_INVALID_ARG;
+    if (algo < DPG_ALGO_AUTO || algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
+    *p = SmjPlan();
+    p->nr = nr;
+    p->ns = ns;
+    p->rec_r = rec_r;
+    p->rec_s = rec_s;
+    p->koff_r = koff_r;
+    p->koff_s = koff_s;
+    p->kb = kb;
+    p->algo = algo;
+    const size_t wr = nr > 0 ? dpg_sort_workspace_bytes(ctx, nr, rec_r, koff_r, kb, (dpg_algo)algo) : 0;
+    const size_t wsz = ns > 0 ? dpg_sort_workspace_bytes(ctx, ns, rec_s, koff_s, kb, (dpg_algo)algo) : 0;
+    if ((nr > 0 && wr == 0) || (ns > 0 && wsz == 0)) return DPG_ERR_INVALID_ARG;
+    p->sort_ws = wr > wsz ? wr : wsz;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + (bytes > 0 ? bytes : 1));
+        return at;
+    };
+    p->off_r = take((size_t)nr * rec_r);
+    p->off_s = take((size_t)ns * rec_s);
+    p->off_sort = take(p->sort_ws);
+    p->off_kr = take((size_t)nr * 8);
+    p->off_ks = take((size_t)ns * 8);
+    p->off_lo = take((size_t)nr * 4);
+    p->off_cnt = take((size_t)nr * 4);
+    p->off_scan = take(scan_1d_scratch_bytes(nr));
+    p->off_total = take(8);
+    p->workspace = off;
+    return DPG_OK;
+}
+
+}  // namespace dpg
+
+using namespace dpg;
+
+extern "C" {
+
+size_t dpg_sort_merge_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                                           int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                                           dpg_algo sort_copy_algo) {
+    SmjPlan p;
+    if (make_smj_plan(ctx, n_r, rec_r, key_off_r, n_s, rec_s, key_off_s, key_bytes, sort_copy_algo, &p) != DPG_OK)
+        return 0;
+    return p.workspace;
+}
+
+dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                               const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                               void *out, int64_t out_capacity, int64_t *out_rows, void *workspace,
+                               size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream) {
+    SmjPlan p;
+    dpg_status st = make_smj_plan(ctx, n_r, rec_r, key_off_r, n_s, rec_s, key_off_s, key_bytes, sort_copy_algo, &p);
+    if (st != DPG_OK) return st;
+    if (!out_rows || out_capacity < 0) return DPG_ERR_INVALID_ARG;
+    if ((n_r > 0 && (!r || ((uintptr_t)r) % 4)) || (n_s > 0 && (!s || ((uintptr_t)s) % 4))) return DPG_ERR_INVALID_ARG;
+    if (out_capacity > 0 && (!out || ((uintptr_t)out) % 4)) return DPG_ERR_INVALID_ARG;
+    if (workspace_bytes < p.workspace) return DPG_ERR_WORKSPACE_TOO_SMALL;
+    if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
+    const size_t rb = (size_t)n_r * rec_r, sb = (size_t)n_s * rec_s;
+    const size_t ob = (size_t)out_capacity * (size_t)(rec_r + rec_s);
+    if (ranges_overlap(out, ob, r, rb) || ranges_overlap(out, ob, s, sb) ||
+        ranges_overlap(out, ob, workspace, p.workspace) || ranges_overlap(workspace, p.workspace, r, rb) ||
+        ranges_overlap(workspace, p.workspace, s, sb))
+        return DPG_ERR_INVALID_ARG;
+    if (!ctx) return DPG_ERR_INVALID_ARG;
+    *out_rows = 0;
+    if (n_r == 0 || n_s == 0) return DPG_OK;
+    char *w = (char *)workspace;
+    // 1. sort both relations on the join key (Section 3, DPG copy phase)
+    st = dpg_sort_records(ctx, r, n_r, rec_r, key_off_r, key_bytes, w + p.off_r, nullptr, w + p.off_sort, p.sort_ws,
+                          sort_copy_algo, stream);
+    if (st != DPG_OK) return st;
+    st = dpg_sort_records(ctx, s, n_s, rec_s, key_off_s, key_bytes, w + p.off_s, nullptr, w + p.off_sort, p.sort_ws,
+                          sort_copy_algo, stream);
+    if (st != DPG_OK) return st;
+    // 2. merge: key ranges and the number of result rows
+    uint64_t *kr = (uint64_t *)(w + p.off_kr), *ks = (uint64_t *)(w + p.off_ks);
+    int32_t *lo = (int32_t *)(w + p.off_lo), *cnt = (int32_t *)(w + p.off_cnt);
+    unsigned long long *total = (unsigned long long *)(w + p.off_total);
+    {
+        ProfScope prof(ctx, K_SMJ_KEYS, (double)n_r * (64 + 8) + (double)n_s * (64 + 8), stream);
+        hipLaunchKernelGGL(k_smj_keys, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, stream,
+                           (const uint8_t *)(w + p.off_r), n_r, rec_r, key_off_r, key_bytes, kr);
+        DPG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_smj_keys, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, stream,
+                           (const uint8_t *)(w + p.off_s), n_s, rec_s, key_off_s, key_bytes, ks);
+        DPG_HIP(hipGetLastError());
+    }
+    st = launch_fill_i32(ctx, (int32_t *)total, 2, 0, stream);
+    if (st != DPG_OK) return st;
+    {
+        ProfScope prof(ctx, K_SMJ_RANGES, 16.0 * n_r, stream);
+        hipLaunchKernelGGL(k_smj_ranges, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, stream, kr, n_r, ks,
+                           n_s, lo, cnt, total);
+        DPG_HIP(hipGetLastError());
+    }
+    unsigned long long n_out = 0;
+    DPG_HIP(hipMemcpyAsync(&n_out, total, sizeof(n_out), hipMemcpyDeviceToHost, stream));
+    DPG_HIP(hipStreamSynchronize(stream));
+    *out_rows = (int64_t)n_out;
+    if ((int64_t)n_out > out_capacity) return DPG_ERR_WORKSPACE_TOO_SMALL;
+    if (n_out >= (unsigned long long)INT32_MAX) return DPG_ERR_UNSUPPORTED;
+    if (n_out == 0) return DPG_OK;
+    // 3. first result row of every R row, then the rows themselves
+    st = launch_scan_1d(ctx, cnt, n_r, (int32_t *)(w + p.off_scan), (int32_t *)total, stream);
+    if (st != DPG_OK) return st;
+    const int wr = rec_r / 4, wsd = rec_s / 4, W = wr + wsd;
+    // a multiple of 256 / gcd(row bytes, 256) rows per tile: every tile's
+    // output starts on a 256-byte boundary (whole-line streaming stores)
+    int g = 4 * W, b = 256;
+    while (b) {
+        const int t = g % b;
+        g = b;
+        b = t;
+    }
+    const int step = 256 / g;
+    int tile = (256 * kSmjPer) / W;
+    if (tile >= step) tile = tile / step * step;
+    if (tile < 1) return DPG_ERR_UNSUPPORTED;
+    const uint32_t magic = (uint32_t)((0x100000000ull + (uint64_t)W - 1) / (uint64_t)W);
+    const int64_t grid = ((int64_t)n_out + tile - 1) / tile;
+    ProfScope prof(ctx, K_SMJ_EMIT, (double)n_out * (2.0 * (rec_r + rec_s) + 8.0), stream);
+    hipLaunchKernelGGL(k_smj_emit, dim3((unsigned)grid), dim3(256), 2 * (size_t)tile * sizeof(int32_t), stream,
+                       (const uint32_t *)(w + p.off_r), wr, n_r, (const uint32_t *)(w + p.off_s), wsd, n_s, cnt, lo,
+                       (uint32_t *)out, (int64_t)n_out, tile, magic);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+}  // extern "C"

@@ -91,6 +91,9 @@ SIGNATURES = {
     "dpg_sort_records": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_fk_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32]),
     "dpg_fk_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_sort_merge_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32, _I32]),
+    "dpg_sort_merge_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64,
+                                   ctypes.POINTER(_I64), _VP, _SZ, _I32, _VP]),
     "dpg_hash_index_bytes": (_SZ, [_I64, _I32]),
     "dpg_hash_ov_off_offset": (_SZ, [_I32]),
     "dpg_hash_ov_offset": (_SZ, [_I32]),
@@ -312,6 +315,43 @@ class Context:
                                order, _addr(workspace), workspace.numel(), algo, int(check_fk), _stream(stream))
         _check(st, "dpg_fk_join")
         return out
+
+    # ---- sort-merge join (Section 4.1) ------------------------------------
+    def sort_merge_join_workspace_bytes(self, n_r: int, rec_r: int, key_off_r: int, n_s: int, rec_s: int,
+                                        key_off_s: int, key_bytes: int, algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_sort_merge_join_workspace_bytes(self.handle, n_r, rec_r, key_off_r, n_s, rec_s, key_off_s,
+                                                         key_bytes, algo)
+
+    def sort_merge_join(self, r, s, key_off_r: int, key_off_s: int, key_bytes: int, algo: int = ALGO_AUTO,
+                        out=None, workspace=None, stream=None):
+        """Rows R[i] || S[j] for every pair of equal join keys, ordered by key,
+        then i, then j.  r, s: (n, rec) uint8 device tensors.  Returns a view
+        of the first result rows of `out` ((capacity, rec_r + rec_s) uint8;
+        default: as many rows as the larger relation).  When the result does
+        not fit, a new output of the exact size is allocated and the call
+        repeated."""
+        import torch
+
+        nr, ns = r.shape[0], s.shape[0]
+        rec_r, rec_s = _rec_bytes(r), _rec_bytes(s)
+        need = self.sort_merge_join_workspace_bytes(nr, rec_r, key_off_r, ns, rec_s, key_off_s, key_bytes, algo)
+        if need == 0:
+            raise DPGError(ERR_INVALID_ARG, "dpg_sort_merge_join_workspace_bytes")
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=r.device)
+        if out is None:
+            out = torch.empty((max(nr, ns, 1), rec_r + rec_s), dtype=torch.uint8, device=r.device)
+        for _ in range(2):
+            n_out = _I64()
+            st = lib().dpg_sort_merge_join(self.handle, _addr(r), nr, rec_r, key_off_r, _addr(s), ns, rec_s,
+                                           key_off_s, key_bytes, _addr(out), out.shape[0], ctypes.byref(n_out),
+                                           _addr(workspace), workspace.numel(), algo, _stream(stream))
+            if st == ERR_WORKSPACE_TOO_SMALL and n_out.value > out.shape[0]:
+                out = torch.empty((n_out.value, rec_r + rec_s), dtype=torch.uint8, device=r.device)
+                continue
+            _check(st, "dpg_sort_merge_join")
+            return out[: n_out.value]
+        raise DPGError(ERR_WORKSPACE_TOO_SMALL, "dpg_sort_merge_join")
 
     # ---- hash index and batch lookup (Section 4.2.3) --------------------
     def hash_build(self, keys, log2_slots: int, stream=None):

@@ -188,3 +188,28 @@ def test_hash_index_layout_and_validation():
     assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, RIDS + 4, WS, need_q, dpg.ALGO_DPG,
                                None) == E.ERR_INVALID_ARG  # output over the queries
     assert lib.dpg_hash_lookup(None, IX, 1000, s, RIDS, 5000, DST, WS, need_q, 9, None) == E.ERR_INVALID_ARG
+
+
+def test_sort_merge_join_validation():
+    lib = dpg.lib()
+    E = dpg
+    args = (1000, 16, 0, 2000, 32, 4, 4)
+    need = lib.dpg_sort_merge_join_workspace_bytes(None, *args, dpg.ALGO_DPG)
+    assert need >= 1000 * 16 + 2000 * 32 + 8 * 3000
+    for bad in ((1000, 16, 0, 2000, 32, 4, 0), (1000, 16, 0, 2000, 32, 4, 9), (1000, 16, 13, 2000, 32, 4, 4),
+                (1000, 18, 0, 2000, 32, 4, 4), (-1, 16, 0, 2000, 32, 4, 4), (1000, 16, 0, 2000, 32, 29, 4)):
+        assert lib.dpg_sort_merge_join_workspace_bytes(None, *bad, dpg.ALGO_DPG) == 0
+    assert lib.dpg_sort_merge_join_workspace_bytes(None, *args, 7) == 0
+    n = ctypes.c_int64(-5)
+    OUT = 0x50000000
+    call = lambda out, cap, ws, wsb, rows=ctypes.byref(n): lib.dpg_sort_merge_join(
+        None, SRC, 1000, 16, 0, DST, 2000, 32, 4, 4, out, cap, rows, ws, wsb, dpg.ALGO_DPG, None)
+    assert call(OUT, 100, WS, need) == E.ERR_INVALID_ARG                 # valid, but no context
+    assert call(OUT, 100, WS, need - 1) == E.ERR_WORKSPACE_TOO_SMALL
+    assert call(OUT, 100, WS, need, None) == E.ERR_INVALID_ARG          # no row count
+    assert call(OUT, -1, WS, need) == E.ERR_INVALID_ARG
+    assert call(OUT + 2, 100, WS, need) == E.ERR_INVALID_ARG            # misaligned output
+    assert call(SRC + 64, 100, WS, need) == E.ERR_INVALID_ARG           # output over R
+    assert call(OUT, 100, WS + 16, need) == E.ERR_INVALID_ARG           # misaligned workspace
+    assert call(OUT, 100, DST, need) == E.ERR_INVALID_ARG               # workspace over S
+    assert n.value == -5                                                # nothing written on a rejected call
