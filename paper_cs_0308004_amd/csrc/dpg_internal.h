@@ -189,6 +189,12 @@ dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void 
 // Phase III staged through LDS (plans with gather_lds, after
 // run_distribute_probe with local_inv).
 dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void *dst, hipStream_t stream);
+// dpg_sort_records; with key_bytes <= 4, *sorted_keys (when given) receives the
+// address inside the workspace of the n sorted keys as big-endian uint32 (key
+// bytes first, zero padding), valid until the workspace is used again, else null.
+dpg_status sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes, int32_t key_offset,
+                        int32_t key_bytes, void *dst, uint32_t *perm_out, void *workspace, size_t workspace_bytes,
+                        int algo, hipStream_t stream, const uint32_t **sorted_keys);
 // Enqueue a planned retrieval (arguments already validated).
 dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
                         void *dst, void *ws, hipStream_t stream);

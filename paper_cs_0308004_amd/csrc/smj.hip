@@ -29,36 +29,64 @@ __global__ __launch_bounds__(256) void k_smj_keys(const uint8_t *__restrict__ ro
     keys[i] = x;
 }
 
-// lo[a], cnt[a]: the S rows whose key equals R row a's; total += cnt (int64).
-__global__ __launch_bounds__(256) void k_smj_ranges(const uint64_t *__restrict__ kr, int64_t nr,
-                                                    const uint64_t *__restrict__ ks, int64_t ns,
-                                                    int32_t *__restrict__ lo, int32_t *__restrict__ cnt,
+// Rows per workgroup of k_smj_ranges, and the S keys it can stage in LDS.
+constexpr int kSmjRangeRows = 1024;
+constexpr int kSmjRangeCap = 4096;
+
+// First index in [l, h) whose key is > k (upper) or >= k (lower), keys sorted.
+template <typename K, bool UPPER>
+__device__ __forceinline__ int64_t smj_bound(const K *keys, int64_t l, int64_t h, K k) {
+    while (l < h) {
+        const int64_t m = (l + h) >> 1;
+        const K v = keys[m];
+        if (UPPER ? v <= k : v < k) l = m + 1;
+        else h = m;
+    }
+    return l;
+}
+
+// lo[a], cnt[a]: the S rows whose key equals R row a's; total += sum of cnt.
+// R rows [a0, a1) of one workgroup have keys in [kr[a0], kr[a1-1]], so their
+// S ranges lie inside [lower(kr[a0]), upper(kr[a1-1])): two global searches
+// per workgroup bound them, and when that span is short it is staged in LDS
+// and every row searches there.
+template <typename K>
+__global__ __launch_bounds__(256) void k_smj_ranges(const K *__restrict__ kr, int64_t nr, const K *__restrict__ ks,
+                                                    int64_t ns, int32_t *__restrict__ lo, int32_t *__restrict__ cnt,
                                                     unsigned long long *__restrict__ total) {
+    __shared__ K s_key[kSmjRangeCap];
+    __shared__ int64_t s_lim[2];
     __shared__ unsigned long long s_sum[4];
-    const int64_t a = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t c = 0;
-    if (a < nr) {
-        const uint64_t k = kr[a];
-        int64_t l = 0, h = ns;  // first S key >= k
-        while (l < h) {
-            const int64_t m = (l + h) >> 1;
-            if (ks[m] < k) l = m + 1;
-            else h = m;
-        }
-        int64_t u = l, hu = ns;  // first S key > k
-        while (u < hu) {
-            const int64_t m = (u + hu) >> 1;
-            if (ks[m] <= k) u = m + 1;
-            else hu = m;
+    const int64_t a0 = (int64_t)blockIdx.x * kSmjRangeRows;
+    const int64_t a1 = min(a0 + (int64_t)kSmjRangeRows, nr);
+    if (threadIdx.x == 0) s_lim[0] = smj_bound<K, false>(ks, 0, ns, kr[a0]);
+    if (threadIdx.x == 64) s_lim[1] = smj_bound<K, true>(ks, 0, ns, kr[a1 - 1]);
+    __syncthreads();
+    const int64_t s0 = s_lim[0], s1 = s_lim[1];
+    const bool staged = s1 - s0 <= kSmjRangeCap;
+    if (staged)
+        for (int i = threadIdx.x; i < (int)(s1 - s0); i += 256) s_key[i] = ks[s0 + i];
+    __syncthreads();
+    unsigned long long sum = 0;
+    for (int r = 0; r < kSmjRangeRows / 256; ++r) {
+        const int64_t a = a0 + threadIdx.x + r * 256;
+        if (a >= a1) break;
+        const K k = kr[a];
+        int64_t l, u;
+        if (staged) {
+            l = s0 + smj_bound<K, false>(s_key, 0, s1 - s0, k);
+            u = s0 + smj_bound<K, true>(s_key, l - s0, s1 - s0, k);
+        } else {
+            l = smj_bound<K, false>(ks, s0, s1, k);
+            u = smj_bound<K, true>(ks, l, s1, k);
         }
         lo[a] = (int32_t)l;
-        c = u - l;
-        cnt[a] = (int32_t)c;
+        cnt[a] = (int32_t)(u - l);
+        sum += (unsigned long long)(u - l);
     }
     // block sum, one atomic per block
-    unsigned long long v = (unsigned long long)c;
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = v;
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+    if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = sum;
     __syncthreads();
     if (threadIdx.x == 0) {
         const unsigned long long b = s_sum[0] + s_sum[1] + s_sum[2] + s_sum[3];
@@ -66,10 +94,23 @@ __global__ __launch_bounds__(256) void k_smj_ranges(const uint64_t *__restrict__
     }
 }
 
+// Last index in [l, h) with off[i] <= o (off nondecreasing, off[l] <= o).
+__device__ __forceinline__ int64_t smj_row_of(const int32_t *off, int64_t l, int64_t h, int64_t o) {
+    while (h - l > 1) {
+        const int64_t m = (l + h) >> 1;
+        if ((int64_t)off[m] <= o) l = m;
+        else h = m;
+    }
+    return l;
+}
+
 // Output rows [t*tile, ...): row o = R[a] || S[lo[a] + o - off[a]], a the last R
-// row with off[a] <= o (and cnt[a] > 0).  Rows are copied as dwords flattened
-// over the workgroup, every load issued before the stores.
+// row with off[a] <= o (it has cnt[a] > 0).  The R rows of one tile lie
+// between those of its first and last output rows; when that span is short,
+// its offsets and range starts are staged in LDS.  Rows are copied as dwords
+// flattened over the workgroup, every load issued before the stores.
 constexpr int kSmjPer = 32;
+constexpr int kSmjEmitCap = 2048;
 
 __global__ __launch_bounds__(256) void k_smj_emit(const uint32_t *__restrict__ R, int wr, int64_t nr,
                                                   const uint32_t *__restrict__ S, int ws, int64_t ns,
@@ -77,19 +118,36 @@ __global__ __launch_bounds__(256) void k_smj_emit(const uint32_t *__restrict__ R
                                                   uint32_t *__restrict__ out, int64_t n_out, int tile,
                                                   uint32_t magic) {
     extern __shared__ int32_t s_ab[];
+    __shared__ int32_t s_off[kSmjEmitCap], s_lo[kSmjEmitCap];
+    __shared__ int64_t s_span[2];
     int32_t *s_a = s_ab, *s_b = s_ab + tile;
     const int64_t base = (int64_t)blockIdx.x * tile;
     const int cnt = (int)min((int64_t)tile, n_out - base);
+    if (threadIdx.x == 0) s_span[0] = smj_row_of(off, 0, nr, base);
+    if (threadIdx.x == 64) s_span[1] = smj_row_of(off, 0, nr, base + cnt - 1);
+    __syncthreads();
+    const int64_t af = s_span[0], span = s_span[1] - af + 1;
+    const bool staged = span <= kSmjEmitCap;
+    if (staged)
+        for (int i = threadIdx.x; i < (int)span; i += 256) {
+            s_off[i] = off[af + i];
+            s_lo[i] = lo[af + i];
+        }
+    __syncthreads();
     for (int j = threadIdx.x; j < cnt; j += 256) {
         const int64_t o = base + j;
-        int64_t l = 0, h = nr;  // first R row with off > o
-        while (l < h) {
-            const int64_t m = (l + h) >> 1;
-            if ((int64_t)off[m] <= o) l = m + 1;
-            else h = m;
+        int64_t a, first, start;
+        if (staged) {
+            const int i = (int)smj_row_of(s_off, 0, span, o);
+            a = af + i;
+            first = s_off[i];
+            start = s_lo[i];
+        } else {
+            a = smj_row_of(off, af, af + span, o);
+            first = off[a];
+            start = lo[a];
         }
-        const int64_t a = l > 0 ? l - 1 : 0;
-        int64_t b = (int64_t)lo[a] + (o - (int64_t)off[a]);
+        int64_t b = start + (o - first);
         b = (b >= 0 && b < ns) ? b : 0;
         s_a[j] = (int32_t)a;
         s_b[j] = (int32_t)b;
@@ -203,32 +261,48 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
     *out_rows = 0;
     if (n_r == 0 || n_s == 0) return DPG_OK;
     char *w = (char *)workspace;
-    // 1. sort both relations on the join key (Section 3, DPG copy phase)
-    st = dpg_sort_records(ctx, r, n_r, rec_r, key_off_r, key_bytes, w + p.off_r, nullptr, w + p.off_sort, p.sort_ws,
-                          sort_copy_algo, stream);
+    // 1. sort both relations on the join key (Section 3, DPG copy phase); a
+    //    key of at most 4 bytes comes out of the sort as sorted uint32 values
+    const bool key32 = key_bytes <= 4;
+    void *kr = w + p.off_kr, *ks = w + p.off_ks;
+    const uint32_t *sorted_keys = nullptr;
+    st = sort_records(ctx, r, n_r, rec_r, key_off_r, key_bytes, w + p.off_r, nullptr, w + p.off_sort, p.sort_ws,
+                      sort_copy_algo, stream, &sorted_keys);
     if (st != DPG_OK) return st;
-    st = dpg_sort_records(ctx, s, n_s, rec_s, key_off_s, key_bytes, w + p.off_s, nullptr, w + p.off_sort, p.sort_ws,
-                          sort_copy_algo, stream);
+    if (key32) {  // the S sort reuses the workspace: keep R's keys
+        if (!sorted_keys) return DPG_ERR_UNSUPPORTED;
+        DPG_HIP(hipMemcpyAsync(kr, sorted_keys, (size_t)n_r * 4, hipMemcpyDeviceToDevice, stream));
+    }
+    st = sort_records(ctx, s, n_s, rec_s, key_off_s, key_bytes, w + p.off_s, nullptr, w + p.off_sort, p.sort_ws,
+                      sort_copy_algo, stream, &sorted_keys);
     if (st != DPG_OK) return st;
-    // 2. merge: key ranges and the number of result rows
-    uint64_t *kr = (uint64_t *)(w + p.off_kr), *ks = (uint64_t *)(w + p.off_ks);
-    int32_t *lo = (int32_t *)(w + p.off_lo), *cnt = (int32_t *)(w + p.off_cnt);
-    unsigned long long *total = (unsigned long long *)(w + p.off_total);
-    {
+    if (key32) {
+        if (!sorted_keys) return DPG_ERR_UNSUPPORTED;
+        ks = (void *)sorted_keys;
+    } else {
         ProfScope prof(ctx, K_SMJ_KEYS, (double)n_r * (64 + 8) + (double)n_s * (64 + 8), stream);
         hipLaunchKernelGGL(k_smj_keys, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, stream,
-                           (const uint8_t *)(w + p.off_r), n_r, rec_r, key_off_r, key_bytes, kr);
+                           (const uint8_t *)(w + p.off_r), n_r, rec_r, key_off_r, key_bytes, (uint64_t *)kr);
         DPG_HIP(hipGetLastError());
         hipLaunchKernelGGL(k_smj_keys, dim3((unsigned)((n_s + 255) / 256)), dim3(256), 0, stream,
-                           (const uint8_t *)(w + p.off_s), n_s, rec_s, key_off_s, key_bytes, ks);
+                           (const uint8_t *)(w + p.off_s), n_s, rec_s, key_off_s, key_bytes, (uint64_t *)ks);
         DPG_HIP(hipGetLastError());
     }
+    // 2. merge: key ranges and the number of result rows
+    int32_t *lo = (int32_t *)(w + p.off_lo), *cnt = (int32_t *)(w + p.off_cnt);
+    unsigned long long *total = (unsigned long long *)(w + p.off_total);
     st = launch_fill_i32(ctx, (int32_t *)total, 2, 0, stream);
     if (st != DPG_OK) return st;
     {
-        ProfScope prof(ctx, K_SMJ_RANGES, 16.0 * n_r, stream);
-        hipLaunchKernelGGL(k_smj_ranges, dim3((unsigned)((n_r + 255) / 256)), dim3(256), 0, stream, kr, n_r, ks,
-                           n_s, lo, cnt, total);
+        const unsigned grid = (unsigned)((n_r + kSmjRangeRows - 1) / kSmjRangeRows);
+        const double kbytes = key32 ? 4.0 : 8.0;
+        ProfScope prof(ctx, K_SMJ_RANGES, kbytes * (n_r + n_s) + 8.0 * n_r, stream);
+        if (key32)
+            hipLaunchKernelGGL(k_smj_ranges<uint32_t>, dim3(grid), dim3(256), 0, stream, (const uint32_t *)kr, n_r,
+                               (const uint32_t *)ks, n_s, lo, cnt, total);
+        else
+            hipLaunchKernelGGL(k_smj_ranges<uint64_t>, dim3(grid), dim3(256), 0, stream, (const uint64_t *)kr, n_r,
+                               (const uint64_t *)ks, n_s, lo, cnt, total);
         DPG_HIP(hipGetLastError());
     }
     unsigned long long n_out = 0;

@@ -190,12 +190,14 @@ static dpg_status sort_prefix(dpg_ctx *ctx, const SortPlan &p, const void *src, 
 }
 
 static dpg_status run_sort(dpg_ctx *ctx, const SortPlan &p, const void *src, void *dst, uint32_t *perm_out,
-                           void *ws, hipStream_t stream) {
+                           void *ws, hipStream_t stream, const uint32_t **sorted_keys) {
     if (p.n == 0) return DPG_OK;
     char *w = (char *)ws;
     int cur = 0;
     dpg_status st = sort_prefix(ctx, p, src, w, &cur, stream);
     if (st != DPG_OK) return st;
+    // a key of at most 4 bytes is its whole prefix: the sorted prefixes are the sorted keys
+    if (sorted_keys) *sorted_keys = p.key_bytes <= 4 ? (const uint32_t *)(w + p.off_keys[cur]) : nullptr;
     if (p.key_bytes > 4 && p.n > 1) {
         int32_t *flag = (int32_t *)(w + p.off_flag);
         st = launch_fill_i32(ctx, flag, 1, 0, stream);
@@ -237,9 +239,12 @@ extern "C" size_t dpg_sort_workspace_bytes(const dpg_ctx *ctx, int64_t n, int32_
     return p.workspace;
 }
 
-extern "C" dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes,
-                                       int32_t key_offset, int32_t key_bytes, void *dst, uint32_t *perm_out,
-                                       void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream) {
+namespace dpg {
+
+dpg_status sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes, int32_t key_offset,
+                        int32_t key_bytes, void *dst, uint32_t *perm_out, void *workspace, size_t workspace_bytes,
+                        int algo, hipStream_t stream, const uint32_t **sorted_keys) {
+    if (sorted_keys) *sorted_keys = nullptr;
     SortPlan p;
     dpg_status st = make_sort_plan(ctx, n, rec_bytes, key_offset, key_bytes, algo, &p);
     if (st != DPG_OK) return st;
@@ -259,5 +264,14 @@ extern "C" dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n,
             return DPG_ERR_INVALID_ARG;
     }
     if (!ctx) return DPG_ERR_INVALID_ARG;
-    return run_sort(ctx, p, src, dst, perm_out, workspace, stream);
+    return run_sort(ctx, p, src, dst, perm_out, workspace, stream, sorted_keys);
+}
+
+}  // namespace dpg
+
+extern "C" dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes,
+                                       int32_t key_offset, int32_t key_bytes, void *dst, uint32_t *perm_out,
+                                       void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream) {
+    return sort_records(ctx, src, n, rec_bytes, key_offset, key_bytes, dst, perm_out, workspace, workspace_bytes,
+                        algo, stream, nullptr);
 }

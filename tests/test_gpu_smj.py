@@ -41,6 +41,10 @@ CASES = [
     (0, 16, 0, 100, 16, 0, 4, 10),               # empty R
     (300, 100, 90, 400, 20, 13, 7, 3),           # three keys: large cross products
     (70001, 32, 0, 65537, 16, 4, 4, 50000),      # many tiles, ragged
+    (70001, 4, 0, 65537, 4, 0, 4, 50000),        # 4-byte rows: a tile spans more R rows than LDS holds
+    (40000, 4, 0, 3000, 4, 0, 4, 1 << 20),       # mostly unmatched R rows
+    (3000, 8, 0, 9000, 8, 4, 2, 5),              # an R block's S span exceeds LDS: global search
+    (2000, 12, 4, 2500, 8, 0, 8, 40),            # 8-byte keys (packed keys path), heavy duplicates
 ]
 
 
