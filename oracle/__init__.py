@@ -67,9 +67,13 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_hash_build.argtypes = [_VP, _I64, _I32, _VP, _VP, _VP, _VP]
     lib.oracle_hash_lookup.argtypes = [_VP, _I64, _VP, _I64, _VP]
     lib.oracle_sort_merge_join.argtypes = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64, _VP]
+    lib.oracle_btree_shape.argtypes = [_I64, _VP, _I32]
+    lib.oracle_btree_build.argtypes = [_VP, _I64, _VP, _VP, _VP]
+    lib.oracle_btree_lookup.argtypes = [_VP, _VP, _VP, _I64, _VP, _I64, _VP]
     for f in (lib.oracle_retrieve, lib.oracle_dpg_phases, lib.oracle_sort_records,
               lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order, lib.oracle_hash_build,
-              lib.oracle_hash_lookup, lib.oracle_sort_merge_join):
+              lib.oracle_hash_lookup, lib.oracle_sort_merge_join, lib.oracle_btree_shape,
+              lib.oracle_btree_build, lib.oracle_btree_lookup):
         f.restype = ctypes.c_int
     return lib
 
@@ -220,4 +224,55 @@ def sort_merge_join(r: np.ndarray, s: np.ndarray, key_off_r: int, key_off_s: int
                                         b.shape[1], key_off_s, key_bytes, _ptr(out), n.value, ctypes.byref(n))
         if rc:
             raise OracleError(rc, "sort_merge_join")
+    return out
+
+
+BTREE_FANOUT = 32
+
+
+def btree_shape(n: int, lib=None) -> list:
+    """Nodes per level of the enhanced B+ tree over n entries, leaf level first."""
+    lib = lib or load()
+    nodes = np.zeros(16, dtype=np.int64)
+    levels = lib.oracle_btree_shape(n, _ptr(nodes), 16)
+    if levels < 1:
+        raise OracleError(EINVAL, "btree_shape")
+    return [int(x) for x in nodes[:levels]]
+
+
+def btree_build(keys: np.ndarray, lib=None):
+    """The enhanced B+ tree of Section 4.2.3 over uint32 keys (rid = position).
+
+    Returns (leaf_keys uint32, leaf_rids int32, [level 1, level 2, ...]) where
+    level l is a (nodes, 32) uint32 array of the largest key under each child."""
+    lib = lib or load()
+    k = np.ascontiguousarray(keys, dtype=np.uint32)
+    shape = btree_shape(k.size, lib)
+    leaf_keys = np.empty(shape[0] * BTREE_FANOUT, dtype=np.uint32)
+    leaf_rids = np.empty(shape[0] * BTREE_FANOUT, dtype=np.int32)
+    inner = np.empty(max(1, sum(shape[1:])) * BTREE_FANOUT, dtype=np.uint32)
+    rc = lib.oracle_btree_build(_ptr(k), k.size, _ptr(leaf_keys), _ptr(leaf_rids), _ptr(inner))
+    if rc:
+        raise OracleError(rc, "btree_build")
+    levels, at = [], 0
+    for c in shape[1:]:
+        levels.append(inner[at:at + c * BTREE_FANOUT].reshape(c, BTREE_FANOUT).copy())
+        at += c * BTREE_FANOUT
+    return leaf_keys, leaf_rids, levels
+
+
+def btree_lookup(tree, n: int, queries: np.ndarray, lib=None) -> np.ndarray:
+    """Batch lookup by walking the tree from the root (Section 4.2.3): the rid
+    of the first entry whose key equals the query, or -1."""
+    lib = lib or load()
+    leaf_keys, leaf_rids, levels = tree
+    inner = np.concatenate([lv.reshape(-1) for lv in levels]) if levels else np.zeros(1, dtype=np.uint32)
+    inner = np.ascontiguousarray(inner, dtype=np.uint32)
+    q = np.ascontiguousarray(queries, dtype=np.uint32)
+    out = np.empty(q.size, dtype=np.int32)
+    rc = lib.oracle_btree_lookup(_ptr(np.ascontiguousarray(leaf_keys, dtype=np.uint32)),
+                                 _ptr(np.ascontiguousarray(leaf_rids, dtype=np.int32)), _ptr(inner), n, _ptr(q),
+                                 q.size, _ptr(out))
+    if rc:
+        raise OracleError(rc, "btree_lookup")
     return out

@@ -9,8 +9,9 @@
  * shares no code, header, table or helper with the HIP library, and nothing in
  * the library may call it.
  *
- * It also states the hash index of Section 4.2.3 (batch lookup in hash
- * indexes) and the result of a batch lookup in it.
+ * It also states the hash index and the enhanced B+ tree of Section 4.2.3
+ * (batch lookup in indexes), the result of a batch lookup in either, and the
+ * sort-merge join of Section 4.1.
  *
  * Conventions (readings of the paper, listed again in the design notes):
  *   - rids are 0-based and must lie in [0, n_src) (Section 2.1 says rid values
@@ -511,5 +512,145 @@ int oracle_sort_merge_join(const uint8_t *r, int64_t n_r, int32_t rec_r, int32_t
     }
     free(kr);
     free(ks);
+    return ORACLE_OK;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Enhanced B+ tree and batch lookup in it (Section 4.2.3, batch lookup in
+ * B+ tree indexes).
+ *
+ * "Enhanced" means every slot of every node is used, so the tree is fixed by
+ * its entries and the fanout (32 here).  Level 0 holds the (key, rid) entries
+ * sorted by key, then rid, in blocks of 32; the last block is padded with key
+ * 0xFFFFFFFF and rid -1, and there is always at least one block.  Level l >= 1
+ * has ceil(nodes of level l-1 / 32) nodes of 32 keys: entry i of node j is the
+ * largest key under child c = 32 j + i of level l-1 (the child's last entry),
+ * or 0xFFFFFFFF when there is no such child.  The top level has one node.
+ *
+ * A lookup walks down from the root: in each node it takes the first entry not
+ * less than the query (the children before it hold only smaller keys), and in
+ * the leaf block the first key not less than the query; the result is that
+ * entry's rid when its key equals the query, else -1.  So a key held by
+ * several entries returns its smallest rid, as the hash lookup does.
+ * ------------------------------------------------------------------------- */
+#define ORACLE_BTREE_FANOUT 32
+#define ORACLE_BTREE_PAD 0xFFFFFFFFu
+
+/* Number of levels (leaf level included); nodes[l] = nodes of level l. */
+int oracle_btree_shape(int64_t n, int64_t *nodes, int32_t max_levels)
+{
+    if (n < 0 || n > INT32_MAX - 1)
+        return -1;
+    int64_t c = (n + ORACLE_BTREE_FANOUT - 1) / ORACLE_BTREE_FANOUT;
+    if (c < 1)
+        c = 1;
+    int32_t levels = 0;
+    for (;;) {
+        if (levels >= max_levels)
+            return -1;
+        nodes[levels++] = c;
+        if (c == 1)
+            break;
+        c = (c + ORACLE_BTREE_FANOUT - 1) / ORACLE_BTREE_FANOUT;
+    }
+    return levels;
+}
+
+/* leaf_keys, leaf_rids: nodes[0] * 32 entries; inner: the levels 1, 2, ...
+ * laid end to end, nodes[l] * 32 keys each. */
+int oracle_btree_build(const uint32_t *keys, int64_t n, uint32_t *leaf_keys, int32_t *leaf_rids,
+                       uint32_t *inner)
+{
+    int64_t nodes[16];
+    int32_t levels = oracle_btree_shape(n, nodes, 16);
+    if (levels < 1)
+        return ORACLE_EINVAL;
+    key_rid *pairs = malloc((size_t)(n > 0 ? n : 1) * sizeof(key_rid));
+    if (!pairs)
+        return ORACLE_EINVAL;
+    for (int64_t j = 0; j < n; ++j) {
+        pairs[j].key = keys[j];
+        pairs[j].rid = j;
+    }
+    qsort(pairs, (size_t)n, sizeof(key_rid), compare_key_rid);
+    int64_t slots = nodes[0] * ORACLE_BTREE_FANOUT;
+    for (int64_t e = 0; e < slots; ++e) {
+        leaf_keys[e] = e < n ? pairs[e].key : ORACLE_BTREE_PAD;
+        leaf_rids[e] = e < n ? (int32_t)pairs[e].rid : -1;
+    }
+    free(pairs);
+    const uint32_t *below = leaf_keys;
+    uint32_t *level = inner;
+    for (int32_t l = 1; l < levels; ++l) {
+        for (int64_t j = 0; j < nodes[l]; ++j) {
+            for (int i = 0; i < ORACLE_BTREE_FANOUT; ++i) {
+                int64_t c = j * ORACLE_BTREE_FANOUT + i;
+#ifdef ORACLE_MUTANT_BTREE_FIRST_ENTRY
+                uint32_t v = c < nodes[l - 1] ? below[c * ORACLE_BTREE_FANOUT] : ORACLE_BTREE_PAD;
+#else
+                uint32_t v = c < nodes[l - 1] ? below[c * ORACLE_BTREE_FANOUT + ORACLE_BTREE_FANOUT - 1]
+                                              : ORACLE_BTREE_PAD;
+#endif
+                level[j * ORACLE_BTREE_FANOUT + i] = v;
+            }
+        }
+        below = level;
+        level += nodes[l] * ORACLE_BTREE_FANOUT;
+    }
+    return ORACLE_OK;
+}
+
+/* Position of the first of the 32 keys of a node that is not less than q
+ * (32 when every key is less). */
+static int btree_first_not_less(const uint32_t *node, uint32_t q)
+{
+    int i = 0;
+#ifdef ORACLE_MUTANT_BTREE_STRICT
+    while (i < ORACLE_BTREE_FANOUT && node[i] <= q)
+#else
+    while (i < ORACLE_BTREE_FANOUT && node[i] < q)
+#endif
+        ++i;
+    return i;
+}
+
+int oracle_btree_lookup(const uint32_t *leaf_keys, const int32_t *leaf_rids, const uint32_t *inner,
+                        int64_t n, const uint32_t *queries, int64_t m, int32_t *out)
+{
+    int64_t nodes[16];
+    int32_t levels = oracle_btree_shape(n, nodes, 16);
+    if (levels < 1 || m < 0)
+        return ORACLE_EINVAL;
+    const uint32_t *level_at[16];
+    level_at[0] = leaf_keys;
+    const uint32_t *p = inner;
+    for (int32_t l = 1; l < levels; ++l) {
+        level_at[l] = p;
+        p += nodes[l] * ORACLE_BTREE_FANOUT;
+    }
+    for (int64_t k = 0; k < m; ++k) {
+        uint32_t q = queries[k];
+        int64_t node = 0;
+        int32_t result = -1;
+        int found_path = 1;
+        for (int32_t l = levels - 1; l >= 1; --l) {
+            int i = btree_first_not_less(level_at[l] + node * ORACLE_BTREE_FANOUT, q);
+            int64_t c = node * ORACLE_BTREE_FANOUT + i;
+            if (i == ORACLE_BTREE_FANOUT || c >= nodes[l - 1]) {
+                found_path = 0; /* larger than every key */
+                break;
+            }
+            node = c;
+        }
+        if (found_path) {
+            int i = btree_first_not_less(leaf_keys + node * ORACLE_BTREE_FANOUT, q);
+            if (i < ORACLE_BTREE_FANOUT) {
+                int64_t e = node * ORACLE_BTREE_FANOUT + i;
+                if (leaf_keys[e] == q && leaf_rids[e] >= 0)
+                    result = leaf_rids[e];
+            }
+        }
+        out[k] = result;
+    }
     return ORACLE_OK;
 }

@@ -433,10 +433,113 @@ def pin_smj_errors(lib):
             raise AssertionError("bad key accepted")
 
 
+# ---------------------------------------------------------------------------
+# enhanced B+ tree and batch lookup in it (Section 4.2.3)
+# ---------------------------------------------------------------------------
+BT_PAD = 0xFFFFFFFF
+
+
+def _first_position(keys, q):
+    """The batch-lookup answer by linear scan: first position holding q, or -1."""
+    hit = np.nonzero(keys == np.uint32(q))[0]
+    return int(hit[0]) if hit.size else -1
+
+
+def pin_btree_lookup_brute_force(lib):
+    """Walking the tree gives the first position holding the query (linear
+    scan), or -1: every key list of length <= 5 on a 3-letter alphabet (with
+    0xFFFFFFFF, the padding key, as a real key), then trees of 1 to 4 levels
+    whose queries include every separator of the inner levels and its
+    neighbours."""
+    alphabet = [0, 7, BT_PAD]
+    queries = np.array(alphabet + [3, 8, 12345], dtype=np.uint32)
+    for n in range(0, 6):
+        for seq in itertools.product(alphabet, repeat=n):
+            keys = np.array(seq, dtype=np.uint32)
+            got = oracle.btree_lookup(oracle.btree_build(keys, lib=lib), n, queries, lib=lib)
+            want = [_first_position(keys, q) for q in queries.tolist()]
+            assert got.tolist() == want, (seq, got, want)
+    rng = np.random.default_rng(21)
+    for n, span in ((33, 1 << 32), (1024, 50), (1025, 1 << 32), (2000, 700), (32 * 32 * 32 + 5, 1 << 32),
+                    (33000, 20000)):
+        keys = rng.integers(0, span, n, dtype=np.uint64).astype(np.uint32)
+        tree = oracle.btree_build(keys, lib=lib)
+        seps = np.concatenate([lv.reshape(-1) for lv in tree[2]]) if tree[2] else np.zeros(0, np.uint32)
+        seps = seps[seps != BT_PAD].astype(np.int64)
+        near = np.concatenate([seps - 1, seps, seps + 1]) % (1 << 32)
+        q = np.concatenate([keys[rng.integers(0, n, 400)], rng.integers(0, 1 << 32, 200, dtype=np.uint64),
+                            rng.choice(near, min(near.size, 600), replace=False) if near.size else [],
+                            [0, BT_PAD, int(keys.max()), int(keys.max()) + 1, int(keys.min())]])
+        q = (np.asarray(q, dtype=np.int64) % (1 << 32)).astype(np.uint32)
+        got = oracle.btree_lookup(tree, n, q, lib=lib)
+        want = np.array([_first_position(keys, x) for x in q.tolist()], dtype=np.int32)
+        assert np.array_equal(got, want), (n, span)
+
+
+def pin_btree_structure(lib):
+    """The stated layout: leaf entries are the (key, rid) pairs sorted by key
+    then rid, padded with (0xFFFFFFFF, -1) to whole blocks of 32; each level
+    has ceil(nodes below / 32) nodes; an inner entry is the last entry of its
+    child, or 0xFFFFFFFF past the last child; the top level is one node."""
+    rng = np.random.default_rng(22)
+    for n, span in ((0, 10), (1, 10), (31, 5), (32, 1 << 32), (33, 1 << 32), (1025, 300), (40000, 1 << 32)):
+        keys = rng.integers(0, span, n, dtype=np.uint64).astype(np.uint32)
+        leaf_keys, leaf_rids, levels = oracle.btree_build(keys, lib=lib)
+        shape = oracle.btree_shape(n, lib=lib)
+        blocks = max(1, -(-n // 32))
+        assert shape[0] == blocks and leaf_keys.size == 32 * blocks
+        for a, b in zip(shape, shape[1:]):
+            assert b == -(-a // 32)
+        assert shape[-1] == 1 and len(levels) == len(shape) - 1
+        order = np.lexsort((np.arange(n), keys))
+        assert np.array_equal(leaf_rids[:n], order.astype(np.int32))
+        assert np.array_equal(leaf_keys[:n], keys[order])
+        assert np.all(leaf_keys[n:] == BT_PAD) and np.all(leaf_rids[n:] == -1)
+        below = leaf_keys.reshape(-1, 32)
+        for lv, c in zip(levels, shape[1:]):
+            assert lv.shape == (c, 32)
+            flat = lv.reshape(-1)
+            kids = below.shape[0]
+            assert np.array_equal(flat[:kids], below[:, 31])
+            assert np.all(flat[kids:] == BT_PAD)
+            below = lv
+
+
+def pin_btree_closed_forms(lib):
+    """Distinct keys 3e in shuffled order: the leaves hold 3e in order with the
+    position of 3e as rid; the level-1 entry of block c is 3 (32 c + 31); the
+    lookup of 3e returns that position and of 3e + 1 returns -1."""
+    n = 32 * 32 * 3 + 17
+    perm = synth.rids_permutation(n, seed=23)
+    keys = (3 * perm).astype(np.uint32)
+    leaf_keys, leaf_rids, levels = oracle.btree_build(keys, lib=lib)
+    inv = np.empty(n, dtype=np.int64)
+    inv[perm] = np.arange(n)
+    assert np.array_equal(leaf_keys[:n], 3 * np.arange(n, dtype=np.uint32))
+    assert np.array_equal(leaf_rids[:n], inv.astype(np.int32))
+    full = n // 32
+    assert np.array_equal(levels[0].reshape(-1)[:full], 3 * (32 * np.arange(full) + 31).astype(np.uint32))
+    tree = (leaf_keys, leaf_rids, levels)
+    e = np.arange(n, dtype=np.uint32)
+    assert np.array_equal(oracle.btree_lookup(tree, n, 3 * e, lib=lib), inv.astype(np.int32))
+    assert np.all(oracle.btree_lookup(tree, n, 3 * e + 1, lib=lib) == -1)
+
+
+def pin_btree_errors(lib):
+    for n in (-1, 1 << 31):
+        try:
+            oracle.btree_shape(n, lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == oracle.EINVAL
+        else:
+            raise AssertionError("bad entry count accepted")
+
+
 ALL_PINS = [
     pin_retrieve_brute_force, pin_retrieve_closed_forms, pin_retrieve_multiset, pin_retrieve_errors,
     pin_fig2_example, pin_phase_invariants, pin_sort_random, pin_sort_ties,
     pin_join_fact_order, pin_join_dim_order, pin_join_errors,
     pin_hash_lookup_brute_force, pin_hash_lookup_closed_forms, pin_hash_build_invariants, pin_hash_errors,
     pin_smj_brute_force, pin_smj_closed_forms, pin_smj_errors,
+    pin_btree_lookup_brute_force, pin_btree_structure, pin_btree_closed_forms, pin_btree_errors,
 ]

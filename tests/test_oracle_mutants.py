@@ -17,6 +17,8 @@ MUTANTS = {
     "ORACLE_MUTANT_HASH_LAST": [pins_oracle.pin_hash_build_invariants],
     "ORACLE_MUTANT_LOOKUP_LAST": [pins_oracle.pin_hash_lookup_brute_force],
     "ORACLE_MUTANT_SMJ_J_MAJOR": [pins_oracle.pin_smj_brute_force, pins_oracle.pin_smj_closed_forms],
+    "ORACLE_MUTANT_BTREE_FIRST_ENTRY": [pins_oracle.pin_btree_structure, pins_oracle.pin_btree_lookup_brute_force],
+    "ORACLE_MUTANT_BTREE_STRICT": [pins_oracle.pin_btree_lookup_brute_force],
 }
 
 
