@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
-    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,serve (default all)")
+    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,btree,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
@@ -395,6 +395,52 @@ def bench_hash(args, ctx, dpg, synth, torch, np):
     return res
 
 
+def bench_btree(args, ctx, dpg, synth, torch, np):
+    """Batch lookup in an enhanced B+ tree (Section 4.2.3): 2^26 distinct
+    uint32 keys (a 516 MiB tree, twice the Infinity Cache), 2^26 query keys of
+    which 80 % are stored; DPG (top-of-tree partition, walks finished with
+    each run's leaves in LDS, gather) vs one root-to-leaf walk per query."""
+    dev = "cuda:0"
+    n, m = 1 << 26, 1 << 26
+    seed = synth.SEED_BASE + 8
+    log(f"bench: B+ tree of {n} keys, {m} lookups")
+    keys = 2 * synth.rids_permutation(1 << 27, seed, backend="torch", device=dev)[:n].to(torch.int64) + 1
+    keys = keys.to(torch.int32)  # odd, distinct (bit patterns of uint32)
+    t0 = time.perf_counter()
+    tree = ctx.btree_build(keys)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    pick = synth.uniform_at(n, torch.arange(m, device=dev), seed, synth.STREAM_RIDS, backend="torch", device=dev)
+    queries = keys[pick.to(torch.int64)].clone()
+    hit = synth.uniform_at(10, torch.arange(m, device=dev), seed, synth.STREAM_MIX, backend="torch", device=dev) < 8
+    queries[~hit] = 2 * (pick[~hit].to(torch.int32) + 1)  # even: never stored
+    out = torch.empty(m, dtype=torch.int32, device=dev)
+    ws = torch.empty(ctx.btree_lookup_workspace_bytes(n, m, dpg.ALGO_DPG), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    res = {"workload": "batch lookup of 2^26 uint32 keys (80% stored) in an enhanced B+ tree (fanout 32) of "
+                       "2^26 distinct keys", "tree_MiB": round(tree.numel() / 2 ** 20, 1),
+           "build_s": round(build_s, 4)}
+    want = np.where(hit.cpu().numpy(), pick.cpu().numpy(), -1)
+    for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
+        ctx.profile_enable(True)
+        ctx.btree_lookup(tree, n, queries, out, algo=algo, workspace=ws, stream=stream)
+        torch.cuda.synchronize()
+        ctx.profile_reset()
+        ms, _ = time_steps(lambda: ctx.btree_lookup(tree, n, queries, out, algo=algo, workspace=ws,
+                                                    stream=stream), args.steps, args.warmup, torch)
+        prof = ctx.profile_collect()
+        ctx.profile_enable(False)
+        ctx.profile_reset()
+        if not np.array_equal(out.cpu().numpy(), want):
+            raise SystemExit(f"bench: {name} B+ tree lookup differs from the stored rids")
+        res[name] = {"ms": round(ms, 4), "lookups_per_s": round(m / (ms * 1e-3), 1),
+                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()}}
+    res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
+    del keys, tree, queries, out, ws, pick, hit
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
     """4096 requests (75 % retrievals, 25 % fact-order or dimension-order
     joins), N log-uniform in [2^10, 2^max_log2], record size uniform over
@@ -526,7 +572,7 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "btree", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -547,6 +593,8 @@ def main():
         out["sort_merge_join"] = bench_smj(args, ctx, dpg, synth, torch, np)
     if "hash" in only:
         out["hash_lookup"] = bench_hash(args, ctx, dpg, synth, torch, np)
+    if "btree" in only:
+        out["btree_lookup"] = bench_btree(args, ctx, dpg, synth, torch, np)
     if "serve" in only:
         out["serving"] = bench_serve(args, ctx, dpg, synth, torch, np)
         # the same mix restricted to small requests (N up to 2^14), where

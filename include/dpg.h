@@ -290,6 +290,57 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
                            void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
+/* Enhanced B+ tree and batch lookup (Section 4.2.3, batch lookup in B+ tree  */
+/* indexes).  The tree indexes uint32 keys (rid = position in the key array); */
+/* "enhanced" means every slot of every node is used, so the tree is fixed by */
+/* its keys.  A batch lookup returns, for each query key, the smallest rid    */
+/* holding it, or -1 (the same result as the hash lookup).  With DPG the      */
+/* queries are distributed into runs of consecutive lower subtrees by a       */
+/* search of the tree's top (the first pass of the paper's two-pass lookup),  */
+/* each run's subtrees are staged in LDS and its queries finish their walk    */
+/* there (the second pass), and the rids are gathered back into query order.  */
+/*                                                                           */
+/* Tree layout (one buffer of dpg_btree_bytes, 256-byte aligned), fanout 32:  */
+/*   level 0 keys uint32[32 B0] at byte 0, rids int32[32 B0] at               */
+/*          dpg_btree_rids_offset: the (key, rid) entries sorted by key, then */
+/*          rid, in B0 = max(1, ceil(n_keys / 32)) blocks; the tail of the    */
+/*          last block is (0xFFFFFFFF, -1)                                    */
+/*   level l >= 1 at dpg_btree_level_offset(l): ceil(nodes(l-1) / 32) nodes  */
+/*          of 32 uint32; entry i of node j = last key of node 32 j + i of    */
+/*          level l-1, or 0xFFFFFFFF past its last node; the top level is one */
+/*          node (dpg_btree_levels counts the levels, leaves included)        */
+/* ------------------------------------------------------------------------- */
+#define DPG_BTREE_FANOUT 32
+
+/* Bytes of a tree over n_keys keys, its level count, and the byte offsets of
+ * the keys of one level (0 = the leaf keys) and of the leaf rids.  All return
+ * 0 when n_keys is outside [0, 2^31 - 2] or level is not a level of the tree. */
+size_t dpg_btree_bytes(int64_t n_keys);
+int32_t dpg_btree_levels(int64_t n_keys);
+size_t dpg_btree_level_offset(int64_t n_keys, int32_t level);
+size_t dpg_btree_rids_offset(int64_t n_keys);
+
+/* Build the tree of `keys` (device, uint32[n_keys]) into `tree` (at least
+ * dpg_btree_bytes; padding bytes between the arrays are left as they were). */
+size_t dpg_btree_build_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys);
+dpg_status dpg_btree_build(dpg_ctx *ctx, const uint32_t *keys, int64_t n_keys, void *tree, size_t tree_bytes,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* rids[i] = smallest rid whose key equals queries[i], or -1 (device arrays of
+ * n_queries).  tree must have been built for n_keys.  algo: DPG_ALGO_DIRECT
+ * walks from the root once per query in query order; DPG_ALGO_DPG (and AUTO)
+ * distributes the queries into runs of consecutive leaf blocks (2^DPG_OPT_LOG2_RUN
+ * entries per run, at least 1024; by default the fewest that keep the runs
+ * within 4096), finishes each run's walks with its leaves staged in LDS (runs
+ * of at most 16384 entries) or, with DPG_OPT_PROBE = DPG_PROBE_CACHED or
+ * larger runs, through the caches, and gathers the rids.  rids must not
+ * overlap queries, tree or workspace. */
+size_t dpg_btree_lookup_workspace_bytes(const dpg_ctx *ctx, int64_t n_keys, int64_t n_queries, dpg_algo algo);
+dpg_status dpg_btree_lookup(dpg_ctx *ctx, const void *tree, int64_t n_keys, const uint32_t *queries,
+                            int64_t n_queries, int32_t *rids, void *workspace, size_t workspace_bytes,
+                            dpg_algo algo, hipStream_t stream);
+
+/* ------------------------------------------------------------------------- */
 /* Batches: many retrieval / join requests of uneven size in one call.  All   */
 /* direct-algorithm work of the batch (direct retrievals, direct fact-order   */
 /* joins) runs in ONE launch of a persistent, queue-driven kernel; requests   */

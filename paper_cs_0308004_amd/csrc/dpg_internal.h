@@ -69,6 +69,10 @@ enum KernelId {
     K_SMJ_KEYS,          // sort-merge join: packed keys of the sorted relations
     K_SMJ_RANGES,        //   matching S range of every R row
     K_SMJ_EMIT,          //   result rows
+    K_BT_LEVEL,          // B+ tree build: one inner level
+    K_BT_DIRECT,         // B+ tree batch lookup, one root-to-leaf walk per query
+    K_BT_PROBE,          //   DPG Phase II, walks over one run's subtrees through the caches
+    K_BT_PROBE_LDS,      //   the same with the run's leaves staged in LDS
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -171,6 +175,10 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
                                        int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan,
                                        int gather = 0);
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
+// Plan of a batch lookup whose queries are partitioned into n_runs <= 4096
+// runs by splitters (one unstable pass); INTERNAL holds an int32 rid per
+// query; lds_probe: work items of at most 16384 queries per run.
+dpg_status make_split_lookup_plan(int64_t n_queries, int64_t n_runs, int gather, bool lds_probe, RetrievePlan *p);
 // The DPG plan of a hash-index batch lookup: queries distributed into 2^bits
 // runs of index slots by the top bits of key * kHashMul (their home slot's
 // partition); INTERNAL holds one int32 rid per query.  probe: DPG_PROBE_CACHED

@@ -20,7 +20,7 @@ struct PartPlan {
     int per = 0;         // elements per thread
     int tile = 0;        // elements per workgroup
     int64_t n_tiles = 0, n_chunks = 0;
-    size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0;
+    size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0, off_cells = 0;
     size_t workspace = 0;
 };
 
@@ -35,6 +35,10 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 // inside a bucket is unspecified; inv stays exact.  local_inv (unstable passes
 // only): inv[i] is instead the slot of element i within its tile's output
 // segments laid end to end (digit order), i.e. relative to the tile.
+// split / n_split (unstable uint32 passes only): the bucket of a key is
+// instead the number of the n_split ascending splitters below it (device
+// array, n_split < 2^nbits), i.e. bucket b holds the keys in
+// (split[b-1], split[b]].
 // key_mul (unstable uint32 passes only): every key is first multiplied by it
 // (mod 2^32), and the products are what is partitioned and written out.  inv (may be
 // null) receives the output position of every input element (0 if invalid).
@@ -46,7 +50,8 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
                             int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true,
-                            bool local_inv = false, uint32_t key_mul = 1);
+                            bool local_inv = false, uint32_t key_mul = 1, const uint32_t *split = nullptr,
+                            int n_split = 0);
 
 // Exclusive scan of a[0..n) in place; *total = the sum (device).  scratch:
 // scan_1d_scratch_bytes(n).

@@ -35,6 +35,69 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
     return (uint32_t)(key >> shift) & mask;
 }
 
+// Splitter buckets.  With ascending splitters s[0..ns), the bucket of a key
+// is the number of splitters below it.  A table over the top kSplitCellBits
+// bits of the key narrows the search: cell_lo[h] = number of splitters whose
+// top bits are below h, so the splitters below a key with top bits h are the
+// first cell_lo[h] plus those of [cell_lo[h], cell_lo[h+1]) below it.
+constexpr int kSplitCellBits = 12;
+constexpr int kSplitCells = 1 << kSplitCellBits;
+
+struct SplitLds {
+    const uint32_t *s = nullptr;  // splitters in LDS (null: digits)
+    const int32_t *cell_lo = nullptr;
+};
+
+__device__ __forceinline__ uint32_t split_bucket(const SplitLds &sp, uint32_t key) {
+    const uint32_t h = key >> (32 - kSplitCellBits);
+    int l = sp.cell_lo[h], r = sp.cell_lo[h + 1];
+    while (l < r) {
+        const int m = (l + r) >> 1;
+        if (sp.s[m] < key) l = m + 1;
+        else r = m;
+    }
+    return (uint32_t)l;
+}
+
+// The bucket of a uint32 key: its digit, or with splitters its splitter bucket.
+__device__ __forceinline__ uint32_t bucket_of(uint32_t key, int shift, uint32_t mask, const SplitLds &sp) {
+    return sp.s ? split_bucket(sp, key) : digit_of(key, shift, mask);
+}
+
+// Stage the splitters and their cell table (if any) in LDS at `lds`.
+__device__ __forceinline__ SplitLds stage_splitters(uint32_t *lds, const uint32_t *split, const int32_t *cell_lo,
+                                                    int ns) {
+    SplitLds sp;
+    if (!split) return sp;
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) lds[i] = split[i];
+    int32_t *lo = (int32_t *)(lds + ns);
+    for (int i = threadIdx.x; i <= kSplitCells; i += blockDim.x) lo[i] = cell_lo[i];
+    sp.s = lds;
+    sp.cell_lo = lo;
+    return sp;
+}
+
+static size_t split_lds_bytes(int ns, bool on) { return on ? 4 * ((size_t)ns + kSplitCells + 1) : 0; }
+
+// cell_lo[h] for h in [0, kSplitCells]: splitters below h << (32 - bits).
+__global__ __launch_bounds__(256) void k_split_cells(const uint32_t *__restrict__ split, int ns,
+                                                     int32_t *__restrict__ cell_lo) {
+    const int h = blockIdx.x * 256 + threadIdx.x;
+    if (h > kSplitCells) return;
+    if (h == kSplitCells) {
+        cell_lo[h] = ns;
+        return;
+    }
+    const uint32_t bound = (uint32_t)h << (32 - kSplitCellBits);
+    int l = 0, r = ns;
+    while (l < r) {
+        const int m = (l + r) >> 1;
+        if (split[m] < bound) l = m + 1;
+        else r = m;
+    }
+    cell_lo[h] = l;
+}
+
 // Rank of each lane's element among the active lanes of its wave that hold
 // the same digit and sit below it, plus the running count of that digit in
 // `ctr` (LDS), which is advanced by the number of such lanes.  Order among
@@ -57,12 +120,16 @@ __device__ __forceinline__ int32_t rank_by_atomic(int32_t *ctr, uint32_t d, bool
 template <typename K>
 __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                             int nbits, uint64_t limit, int T, uint32_t key_mul,
-                                                            int32_t *__restrict__ cnt) {
+                                                            int32_t *__restrict__ cnt,
+                                                            const uint32_t *__restrict__ split,
+                                                            const int32_t *__restrict__ cell_lo, int n_split) {
     __shared__ int32_t h[kPartWaves][kMaxDigitBuckets];
+    extern __shared__ uint32_t s_split_h[];
     const int nb = 1 << nbits;
     const uint32_t mask = (uint32_t)nb - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = lane; d < nb; d += 64) h[wave][d] = 0;
+    const SplitLds sp = stage_splitters(s_split_h, split, cell_lo, n_split);
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * T;
     const int64_t end = min(base + T, n);
@@ -81,7 +148,10 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
             const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
-            (void)rank_by_atomic(h[wave], digit_of(kv[u], shift, mask), valid);
+            uint32_t d;
+            if constexpr (sizeof(K) == 4) d = bucket_of(kv[u], shift, mask, sp);
+            else d = digit_of(kv[u], shift, mask);
+            (void)rank_by_atomic(h[wave], d, valid);
         }
     }
     __syncthreads();
@@ -98,11 +168,14 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
 template <int THREADS>
 __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__restrict__ keys, int64_t n,
                                                             int shift, int nbits, uint64_t limit, int T,
-                                                            uint32_t key_mul, int32_t *__restrict__ cnt) {
+                                                            uint32_t key_mul, int32_t *__restrict__ cnt,
+                                                            const uint32_t *__restrict__ split,
+                                                            const int32_t *__restrict__ cell_lo, int n_split) {
     extern __shared__ int32_t hw[];
     const int nb = 1 << nbits;
     const uint32_t mask = (uint32_t)nb - 1;
     for (int d = threadIdx.x; d < nb; d += THREADS) hw[d] = 0;
+    const SplitLds sp = stage_splitters((uint32_t *)(hw + nb), split, cell_lo, n_split);
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * T;
     const int64_t end = min(base + T, n);
@@ -118,7 +191,7 @@ __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__re
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * THREADS;
             const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
-            (void)rank_by_atomic(hw, digit_of(kv[u], shift, mask), valid);
+            (void)rank_by_atomic(hw, bucket_of(kv[u], shift, mask, sp), valid);
         }
     }
     __syncthreads();
@@ -237,7 +310,8 @@ template <int THREADS, int PER>
 __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
     const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int local_inv,
-    uint32_t key_mul, int remap) {
+    uint32_t key_mul, int remap, const uint32_t *__restrict__ split, const int32_t *__restrict__ cell_lo,
+    int n_split) {
     constexpr int T = THREADS * PER;
     constexpr int W = THREADS / 64;
     extern __shared__ __align__(16) char smem[];
@@ -245,6 +319,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const int nb = 1 << nbits;
     int32_t *s_cnt = (int32_t *)(smem + sizeof(uint32_t) * T);  // count, then tile-local start
     int32_t *s_glob = s_cnt + nb;                               // output start of each digit for this tile
+    const SplitLds sp = stage_splitters((uint32_t *)(s_glob + nb), split, cell_lo, n_split);  // splitters, if any
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_nvalid;
     const uint32_t mask = (uint32_t)nb - 1;
@@ -264,11 +339,13 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     }
     __syncthreads();
     int32_t rank[PER];
+    uint32_t bkt[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
         const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
-        rank[k] = rank_by_atomic(s_cnt, digit_of(key[k], shift, mask), valid);
+        bkt[k] = bucket_of(key[k], shift, mask, sp);
+        rank[k] = rank_by_atomic(s_cnt, bkt[k], valid);
     }
     __syncthreads();
     // exclusive prefix of the digit counts: wave w scans the w-th slice of
@@ -306,7 +383,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
         if (rank[k] >= 0) {
-            const uint32_t d = digit_of(key[k], shift, mask);
+            const uint32_t d = bkt[k];
             s_key[s_cnt[d] + rank[k]] = key[k];
             if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rank[k];
         } else if (inv && e < cnt) {
@@ -317,7 +394,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const int nvalid = s_nvalid;
     for (int j = threadIdx.x; j < nvalid; j += THREADS) {
         const uint32_t k = s_key[j];
-        const uint32_t d = digit_of(k, shift, mask);
+        const uint32_t d = bucket_of(k, shift, mask, sp);
         keys_out[(int64_t)s_glob[d] + (j - s_cnt[d])] = k;
     }
 }
@@ -352,6 +429,7 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val) {
     p.off_csum = take((size_t)p.n_chunks * nb * 4);
     p.off_total = take((size_t)nb * 4);
     p.off_bucket = take((size_t)(nb + 1) * 4);
+    p.off_cells = take((size_t)(kSplitCells + 1) * 4);
     p.workspace = off;
     return p;
 }
@@ -372,7 +450,8 @@ static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
-                            int item_chunk, bool stable, bool local_inv, uint32_t key_mul) {
+                            int item_chunk, bool stable, bool local_inv, uint32_t key_mul, const uint32_t *split,
+                            int n_split) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -387,20 +466,31 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (local_inv && stable) return DPG_ERR_UNSUPPORTED;
     if (key_mul != 1 && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
     const int nb = 1 << p.nbits;
+    if (!split) n_split = 0;
+    if (split && (stable || p.key_bytes != 4 || p.has_val || n_split < 0 || n_split >= nb)) return DPG_ERR_UNSUPPORTED;
+    const size_t split_lds = split_lds_bytes(n_split, split != nullptr);
+    const int32_t *cells = (const int32_t *)(w + p.off_cells);
+    if (split) {
+        hipLaunchKernelGGL(k_split_cells, dim3((kSplitCells + 1 + 255) / 256), dim3(256), 0, stream, split, n_split,
+                           (int32_t *)(w + p.off_cells));
+        DPG_HIP(hipGetLastError());
+    }
     const double elem = p.key_bytes + (p.has_val ? 4.0 : 0.0);
     {
         ProfScope prof(ctx, wide ? K_PART_HIST_WIDE : K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb,
                        stream);
         if (wide)
             hipLaunchKernelGGL((k_part_hist_wide<1024>), dim3((unsigned)p.n_tiles), dim3(1024),
-                               (size_t)nb * sizeof(int32_t), stream, (const uint32_t *)keys_in, p.n, shift, p.nbits,
-                               limit, p.tile, key_mul, cnt);
+                               (size_t)nb * sizeof(int32_t) + split_lds, stream, (const uint32_t *)keys_in, p.n,
+                               shift, p.nbits, limit, p.tile, key_mul, cnt, split, cells, n_split);
         else if (p.key_bytes == 8)
             hipLaunchKernelGGL((k_part_hist<uint64_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
-                               (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, 1u, cnt);
+                               (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, 1u, cnt, nullptr,
+                               nullptr, 0);
         else
-            hipLaunchKernelGGL((k_part_hist<uint32_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
-                               (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt);
+            hipLaunchKernelGGL((k_part_hist<uint32_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), split_lds,
+                               stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt,
+                               split, cells, n_split);
         DPG_HIP(hipGetLastError());
     }
     dpg_status st = launch_column_scan(ctx, cnt, p.n_tiles, nb, csum, p.n_chunks, total, bucket_off, item_off,
@@ -420,19 +510,20 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
                                                     remap, stream);
     if (!stable) {
-        const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb;
+        const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb + split_lds;
         if (wide) {
             if (lds > 64 * 1024)
                 DPG_HIP(hipFuncSetAttribute((const void *)k_part_scatter_unstable<1024, 16>,
                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL((k_part_scatter_unstable<1024, 16>), dim3((unsigned)p.n_tiles), dim3(1024), lds,
                                stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
-                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap);
+                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap, split, cells, n_split);
         } else {
             if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
             hipLaunchKernelGGL((k_part_scatter_unstable<kPartThreads, 32>), dim3((unsigned)p.n_tiles),
                                dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit,
-                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap);
+                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap, split,
+                               cells, n_split);
         }
         DPG_HIP(hipGetLastError());
         return DPG_OK;

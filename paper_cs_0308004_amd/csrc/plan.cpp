@@ -186,6 +186,35 @@ dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2
     return DPG_OK;
 }
 
+dpg_status make_split_lookup_plan(int64_t n_queries, int64_t n_runs, int gather, bool lds_probe, RetrievePlan *p) {
+    if (n_queries < 0 || n_queries > INT32_MAX - 1 || n_runs < 1 || n_runs > kMaxWideBuckets)
+        return DPG_ERR_INVALID_ARG;
+    *p = RetrievePlan();
+    p->algo = DPG_ALGO_DPG;
+    p->n_src = 0;  // every query is valid
+    p->n_rids = n_queries;
+    p->rec_bytes = 4;  // INTERNAL holds an int32 rid per query
+    p->probe = lds_probe ? DPG_PROBE_LDS : DPG_PROBE_CACHED;
+    if (n_queries > 0) {
+        int bits = n_runs > 1 ? floor_log2((uint64_t)(n_runs - 1)) + 1 : 1;
+        p->n_runs = n_runs;
+        p->dist_mode = DIST_PARTITION;
+        p->part_nbits = bits;
+        if (lds_probe) p->probe_chunk = 16384;
+        const PartPlan pp = plan_partition(n_queries, bits, 4, false);
+        p->dist_tile = pp.tile;
+        p->n_tiles = pp.n_tiles;
+        p->n_chunks = pp.n_chunks;
+        if (gather != 1) {
+            const size_t lds = (size_t)pp.tile * 4 + 8u * ((size_t)1 << bits);
+            p->gather_lds = lds <= kGatherLdsBytes;
+            p->part_tile = pp.tile;
+        }
+    }
+    layout_workspace(p);
+    return DPG_OK;
+}
+
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids) {
     return TuneKey{rec_bytes, ilog2_ceil(n_src > 0 ? n_src : 1), ilog2_ceil(n_rids > 0 ? n_rids : 1)};
 }

@@ -101,6 +101,14 @@ SIGNATURES = {
     "dpg_hash_build": (_I32, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _SZ, _VP]),
     "dpg_hash_lookup_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
     "dpg_hash_lookup": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
+    "dpg_btree_bytes": (_SZ, [_I64]),
+    "dpg_btree_levels": (_I32, [_I64]),
+    "dpg_btree_level_offset": (_SZ, [_I64, _I32]),
+    "dpg_btree_rids_offset": (_SZ, [_I64]),
+    "dpg_btree_build_workspace_bytes": (_SZ, [_VP, _I64]),
+    "dpg_btree_build": (_I32, [_VP, _VP, _I64, _VP, _SZ, _VP, _SZ, _VP]),
+    "dpg_btree_lookup_workspace_bytes": (_SZ, [_VP, _I64, _I64, _I32]),
+    "dpg_btree_lookup": (_I32, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_batch_workspace_bytes": (_SZ, [_VP, ctypes.POINTER(Request), _I32]),
     "dpg_batch_run": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP, _SZ, _VP]),
     "dpg_batch_graph_workspace_bytes": (_SZ, [_VP, _I32]),
@@ -386,6 +394,41 @@ class Context:
             workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=queries.device)
         _check(lib().dpg_hash_lookup(self.handle, _addr(index), n_keys, log2_slots, _addr(queries), m, _addr(rids),
                                      _addr(workspace), workspace.numel(), algo, _stream(stream)), "dpg_hash_lookup")
+        return rids
+
+    # ---- enhanced B+ tree and batch lookup (Section 4.2.3) -------------
+    def btree_build(self, keys, stream=None):
+        """Build the enhanced B+ tree of a uint32 key tensor (rid = position);
+        returns the tree as a uint8 device tensor."""
+        import torch
+
+        n = keys.numel()
+        nbytes = lib().dpg_btree_bytes(n)
+        if nbytes == 0:
+            raise DPGError(ERR_INVALID_ARG, "dpg_btree_bytes")
+        tree = torch.empty(nbytes, dtype=torch.uint8, device=keys.device)
+        need = lib().dpg_btree_build_workspace_bytes(self.handle, n)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=keys.device)
+        _check(lib().dpg_btree_build(self.handle, _addr(keys), n, _addr(tree), tree.numel(), _addr(ws), ws.numel(),
+                                     _stream(stream)), "dpg_btree_build")
+        return tree
+
+    def btree_lookup_workspace_bytes(self, n_keys: int, n_queries: int, algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_btree_lookup_workspace_bytes(self.handle, n_keys, n_queries, algo)
+
+    def btree_lookup(self, tree, n_keys: int, queries, rids=None, algo: int = ALGO_AUTO, workspace=None,
+                     stream=None):
+        """rids[i] = smallest rid whose key equals queries[i], or -1."""
+        import torch
+
+        m = queries.numel()
+        if rids is None:
+            rids = torch.empty(m, dtype=torch.int32, device=queries.device)
+        if workspace is None:
+            need = self.btree_lookup_workspace_bytes(n_keys, m, algo)
+            workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=queries.device)
+        _check(lib().dpg_btree_lookup(self.handle, _addr(tree), n_keys, _addr(queries), m, _addr(rids),
+                                      _addr(workspace), workspace.numel(), algo, _stream(stream)), "dpg_btree_lookup")
         return rids
 
     # ---- batches -------------------------------------------------------

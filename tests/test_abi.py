@@ -213,3 +213,44 @@ def test_sort_merge_join_validation():
     assert call(OUT, 100, WS + 16, need) == E.ERR_INVALID_ARG           # misaligned workspace
     assert call(OUT, 100, DST, need) == E.ERR_INVALID_ARG               # workspace over S
     assert n.value == -5                                                # nothing written on a rejected call
+
+
+def test_btree_layout_and_validation():
+    lib = dpg.lib()
+    E = dpg
+    # 1000 keys: 32 leaf blocks, one inner node
+    assert lib.dpg_btree_levels(1000) == 2
+    assert lib.dpg_btree_rids_offset(1000) == 4096
+    assert lib.dpg_btree_level_offset(1000, 0) == 0
+    assert lib.dpg_btree_level_offset(1000, 1) == 8192
+    assert lib.dpg_btree_bytes(1000) == 8192 + 256
+    # 0 keys: one (padding) leaf block; 2^15 + 1 keys: 1025 blocks -> 33 -> 2 -> 1
+    assert lib.dpg_btree_levels(0) == 1 and lib.dpg_btree_bytes(0) == 512  # keys, then rids at 256
+    assert lib.dpg_btree_levels((1 << 15) + 1) == 4
+    for bad in ((-1, 0), (1 << 31, 0), (1000, 2), (1000, -1)):
+        assert lib.dpg_btree_level_offset(*bad) == 0
+    assert lib.dpg_btree_bytes(-1) == 0 and lib.dpg_btree_levels(-1) == 0
+    n = 5000
+    tb = lib.dpg_btree_bytes(n)
+    need = lib.dpg_btree_build_workspace_bytes(None, n)
+    assert need >= 16 * n
+    T = 0x50000000
+    assert lib.dpg_btree_build(None, SRC, n, T, tb, WS, need, None) == E.ERR_INVALID_ARG  # no context
+    assert lib.dpg_btree_build(None, SRC, n, T, tb - 1, WS, need, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_btree_build(None, SRC, n, T + 16, tb, WS, need, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_btree_build(None, SRC, n, T, tb, WS, need - 1, None) == E.ERR_WORKSPACE_TOO_SMALL
+    assert lib.dpg_btree_build(None, SRC, n, T, tb, T + 256, need, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_btree_build(None, SRC, n, SRC + 256, tb, WS, need, None) == E.ERR_INVALID_ARG  # tree over keys
+    need_q = lib.dpg_btree_lookup_workspace_bytes(None, n, 7000, dpg.ALGO_DPG)
+    assert need_q > 7000 * 12
+    assert lib.dpg_btree_lookup_workspace_bytes(None, n, 7000, dpg.ALGO_DIRECT) == 256
+    assert lib.dpg_btree_lookup_workspace_bytes(None, n, 7000, 7) == 0
+    assert lib.dpg_btree_lookup_workspace_bytes(None, -1, 7000, dpg.ALGO_DPG) == 0
+    assert lib.dpg_btree_lookup(None, T, n, RIDS, 7000, DST, WS, need_q, dpg.ALGO_DPG, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_btree_lookup(None, T, n, RIDS, 7000, DST, WS, need_q - 1, dpg.ALGO_DPG,
+                                None) == E.ERR_WORKSPACE_TOO_SMALL
+    assert lib.dpg_btree_lookup(None, T, n, RIDS, 7000, RIDS + 4, WS, need_q, dpg.ALGO_DPG,
+                                None) == E.ERR_INVALID_ARG  # output over the queries
+    assert lib.dpg_btree_lookup(None, T, n, RIDS, 7000, DST, WS, need_q, 9, None) == E.ERR_INVALID_ARG
+    assert lib.dpg_btree_lookup(None, T + 64, n, RIDS, 7000, DST, WS, need_q, dpg.ALGO_DPG,
+                                None) == E.ERR_INVALID_ARG  # misaligned tree
