@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
-    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,btree,serve (default all)")
+    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,btree,skew,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
@@ -441,6 +441,60 @@ def bench_btree(args, ctx, dpg, synth, torch, np):
     return res
 
 
+def bench_skew_multipass(args, ctx, dpg, synth, torch, np):
+    """The two Phase I forms for extreme cases (Sections 2.3 and 7):
+    skew-balanced runs from a sorted sample, on 2^26 Zipf(1.2) rids over
+    2^26 x 100 B records whose hot records sit together; and two-pass DPG on a
+    64 GiB source (2^30 x 64 B, 2^27 uniform rids), against the one-pass
+    partition with longer runs and the direct gather."""
+    dev = "cuda:0"
+    steps = max(2, args.steps // 3)
+    res = {}
+
+    def timed(name, src, rids, algo, dist=0, lg=0):
+        ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
+        ctx.set_option(dpg.OPT_LOG2_RUN, lg)
+        try:
+            plan = ctx.plan_retrieve(src.shape[0], src.shape[1], rids.numel(), algo)
+            ws = torch.empty(max(1, plan.workspace_bytes), dtype=torch.uint8, device=dev)
+            dst = torch.empty((rids.numel(), src.shape[1]), dtype=torch.uint8, device=dev)
+            ms, _ = time_steps(lambda: ctx.retrieve(src, rids, dst=dst, algo=algo, workspace=ws), steps, 1, torch)
+            pick = torch.arange(0, rids.numel(), 997, device=dev)
+            if not torch.equal(dst[pick], src[rids[pick].to(torch.int64)]):
+                raise SystemExit(f"bench: {name} retrieval differs from src[rids]")
+            res[name] = {"ms": round(ms, 3), "log2_run": plan.log2_run, "runs": plan.n_runs,
+                         "distribute": plan.distribute}
+            del ws, dst
+        finally:
+            ctx.set_option(dpg.OPT_DISTRIBUTE, 0)
+            ctx.set_option(dpg.OPT_LOG2_RUN, 0)
+
+    n, R = 1 << 26, 100
+    log("bench: skewed rids (Zipf 1.2, hot records together), 2^26 x 100 B")
+    src = synth.record_bytes(n, R, synth.SEED_BASE + 9, backend="torch", device=dev)
+    rids = synth.zipf_fk_at(n, 1.2, torch.arange(n, device=dev), synth.SEED_BASE + 9, permute_ids=False,
+                            backend="torch", device=dev).to(torch.int32)
+    timed("zipf1.2_direct", src, rids, dpg.ALGO_DIRECT)
+    timed("zipf1.2_dpg_partition", src, rids, dpg.ALGO_DPG, dpg.DIST_PARTITION)
+    timed("zipf1.2_dpg_sampled", src, rids, dpg.ALGO_DPG, dpg.DIST_SAMPLED)
+    del src, rids
+    torch.cuda.empty_cache()
+    n, R, m = 1 << 30, 64, 1 << 27
+    log("bench: 64 GiB source (2^30 x 64 B), 2^27 uniform rids")
+    src = torch.empty((n, R), dtype=torch.uint8, device=dev)
+    synth.record_bytes(n, R, synth.SEED_BASE + 10, backend="torch", device=dev, out=src)
+    rids = synth.uniform_at(n, torch.arange(m, device=dev), synth.SEED_BASE + 10, synth.STREAM_RIDS,
+                            backend="torch", device=dev).to(torch.int32)
+    timed("big_direct", src, rids, dpg.ALGO_DIRECT)
+    timed("big_dpg_one_pass", src, rids, dpg.ALGO_DPG)
+    timed("big_dpg_two_pass", src, rids, dpg.ALGO_DPG, dpg.DIST_TWO_PASS, 16)
+    del src, rids
+    torch.cuda.empty_cache()
+    res["workload"] = ("zipf: 2^26 Zipf(1.2) rank-ordered rids over 2^26 x 100 B; big: 2^27 uniform rids over "
+                       "2^30 x 64 B (64 GiB)")
+    return res
+
+
 def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
     """4096 requests (75 % retrievals, 25 % fact-order or dimension-order
     joins), N log-uniform in [2^10, 2^max_log2], record size uniform over
@@ -572,7 +626,7 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "btree", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "btree", "skew", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -595,6 +649,8 @@ def main():
         out["hash_lookup"] = bench_hash(args, ctx, dpg, synth, torch, np)
     if "btree" in only:
         out["btree_lookup"] = bench_btree(args, ctx, dpg, synth, torch, np)
+    if "skew" in only:
+        out["skew_multipass"] = bench_skew_multipass(args, ctx, dpg, synth, torch, np)
     if "serve" in only:
         out["serving"] = bench_serve(args, ctx, dpg, synth, torch, np)
         # the same mix restricted to small requests (N up to 2^14), where

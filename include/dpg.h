@@ -73,7 +73,14 @@ typedef enum {
     DPG_OPT_XCD_REMAP = 4,  /* 1 (default): tiles of one XCD are contiguous; 2: off */
     DPG_OPT_USE_TUNED = 5,  /* 1 (default): consult the autotune table; 2: ignore it */
     DPG_OPT_DISTRIBUTE = 6, /* Phase I: 1 append (any run count up to 8192),
-                               2 coalesced partition pass (used only when runs <= 4096) */
+                               2 coalesced partition pass (used only when runs <= 4096),
+                               3 the partition pass into up to 4096 runs of equal
+                               rid share, bounded by splitters from a sorted
+                               sample of 64 rids per run (data skew, Section 2.3;
+                               runs are then probed through the caches),
+                               4 two partition passes, fine then coarse run bits,
+                               into up to 2^20 runs, and Phase III in two passes
+                               (multi-pass DPG, Section 7; probed through the caches) */
     DPG_OPT_GATHER = 7      /* Phase III: 1 INTERNAL read through the caches, 2 a
                                distribute tile's records staged in LDS (used only
                                with the partition distribute when they fit) */
@@ -101,8 +108,8 @@ typedef struct {
     int32_t probe;         /* DPG_PROBE_CACHED or DPG_PROBE_LDS (DPG only) */
     int32_t log2_run;      /* L = 2^log2_run source records per run */
     int32_t dist_tile;     /* rids per distribute tile */
-    int32_t distribute;    /* Phase I form: 1 append, 2 partition (DPG only; the
-                              values of DPG_OPT_DISTRIBUTE) */
+    int32_t distribute;    /* Phase I form: 1 append, 2 partition, 3 sampled, 4
+                              two-pass (DPG only; the values of DPG_OPT_DISTRIBUTE) */
     int32_t gather;        /* Phase III form: 1 cached, 2 LDS-staged (DPG only;
                               the values of DPG_OPT_GATHER) */
     int64_t n_runs;        /* B = ceil(n_src / L), the paper's NUM_RUNS */
@@ -110,7 +117,8 @@ typedef struct {
     size_t workspace_bytes;
     /* After a DPG retrieval the workspace holds the phase products at these
      * byte offsets (0 when algo is direct), for inspection or pipelining:
-     *   run_off  int32[n_runs + 1]  start of RID run b in rid_run (Phase I)
+     *   run_off  int32[n_runs + 1]  start of RID run b in rid_run (Phase I;
+     *                               not kept by the two-pass form: offset 0)
      *   rid_run  int32[n_rids]      the RID runs, one after another (Phase
      *                               I); each run in rid-list order with the
      *                               append distribute, in unspecified order

@@ -42,8 +42,9 @@ ProfScope::~ProfScope() {
     ctx->pending.push_back(ProfRecord{kernel, bytes, ev0, ev1});
 }
 
-dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
-                                void *ws, hipStream_t stream, bool local_inv) {
+// Phases I and II; INTERNAL then holds the records in run order.
+static dpg_status distribute_and_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
+                                       void *ws, hipStream_t stream, bool local_inv) {
     const double R = p.rec_bytes, M = (double)p.n_rids;
     char *w = (char *)ws;
     if (local_inv && !p.gather_lds) return DPG_ERR_UNSUPPORTED;
@@ -55,6 +56,16 @@ dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void 
                          p.n_rids, p.rec_bytes, 4.0 * M + R * touched + R * M, stream);
 }
 
+dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
+                                void *ws, hipStream_t stream, bool local_inv) {
+    dpg_status st = distribute_and_probe(ctx, p, src, rids, ws, stream, local_inv);
+    if (st != DPG_OK || p.dist_mode != DIST_TWO_PASS) return st;
+    // callers that fuse Phase III need one slot per rid: inv = inv_c o inv_f
+    char *w = (char *)ws;
+    return launch_gather(ctx, K_GATHER_PHASE, w + p.off_inv_c, p.n_rids, (const int32_t *)(w + p.off_inv_f),
+                         w + p.off_inv, p.n_rids, 4, 12.0 * p.n_rids, stream);
+}
+
 dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids, void *dst,
                         void *ws, hipStream_t stream) {
     const double R = p.rec_bytes, M = (double)p.n_rids;
@@ -63,6 +74,18 @@ dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, co
         return launch_gather(ctx, K_DIRECT_GATHER, src, p.n_src, rids, dst, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M,
                              stream);
     char *w = (char *)ws;
+    if (p.dist_mode == DIST_TWO_PASS) {
+        // Phase III in two passes, coarse first: u[j] = INTERNAL[inv_c[j]] in
+        // the fine pass's order, then dst[i] = u[inv_f[i]]; each pass reads
+        // from at most 2^8 or 2^12 streams
+        dpg_status st = distribute_and_probe(ctx, p, src, rids, ws, stream, false);
+        if (st != DPG_OK) return st;
+        st = launch_gather(ctx, K_GATHER_PHASE, w + p.off_internal, p.n_rids, (const int32_t *)(w + p.off_inv_c),
+                           w + p.off_u, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
+        if (st != DPG_OK) return st;
+        return launch_gather(ctx, K_GATHER_PHASE, w + p.off_u, p.n_rids, (const int32_t *)(w + p.off_inv_f), dst,
+                             p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
+    }
     const dpg_status st = run_distribute_probe(ctx, p, src, rids, ws, stream, p.gather_lds);
     if (st != DPG_OK) return st;
     if (p.gather_lds) return launch_gather_lds(ctx, p, ws, dst, stream);
@@ -149,7 +172,7 @@ dpg_status dpg_set_option(dpg_ctx *ctx, dpg_option option, int64_t value) {
             ctx->opt_use_tuned = value ? value : 1;
             return DPG_OK;
         case DPG_OPT_DISTRIBUTE:
-            if (value > 2) return DPG_ERR_INVALID_ARG;
+            if (value > kDistOptionMax) return DPG_ERR_INVALID_ARG;
             ctx->opt_distribute = value;
             return DPG_OK;
         case DPG_OPT_GATHER:

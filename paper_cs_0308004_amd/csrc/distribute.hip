@@ -17,6 +17,8 @@
 //
 // A rid outside [0, n_src) is skipped (its inv is 0), so no kernel of the
 // pipeline can address memory outside its buffers even on invalid input.
+#include <algorithm>
+
 #include "dev_common.h"
 #include "dpg_internal.h"
 #include "partition.h"
@@ -103,10 +105,85 @@ __global__ __launch_bounds__(64) void k_dist_scatter(const int32_t *__restrict__
     }
 }
 
+// Sample for the splitters of the skew-balanced runs: n_sample rids at evenly
+// spaced list positions (an rid out of range is clamped into it: only the
+// balance of the runs depends on the sample).
+__global__ __launch_bounds__(256) void k_dist_sample(const int32_t *__restrict__ rids, int64_t m, int64_t n_src,
+                                                     int64_t s, uint32_t *__restrict__ out) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= s) return;
+    const int64_t r = rids[k * m / s];  // k < s and m below 2^31: no overflow
+    out[k] = (uint32_t)(r < 0 ? 0 : (r >= n_src ? n_src - 1 : r));
+}
+
+// split[b] = the last sampled rid of the b-th of B equal shares of the sorted
+// sample, b < B - 1: run b then holds the rids in (split[b-1], split[b]].
+__global__ __launch_bounds__(256) void k_dist_splitters(const uint32_t *__restrict__ sorted, int64_t s, int B,
+                                                        uint32_t *__restrict__ split) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= B - 1) return;
+    int64_t at = (int64_t)(b + 1) * s / B - 1;
+    if (at < 0) at = 0;
+    split[b] = sorted[at];
+}
+
+// Phase I with runs balanced by a sample (Section 2.3, data skew): sample the
+// rids, sort the sample (stable 8-bit passes over the bytes an rid can
+// occupy), take B - 1 splitters that cut it into equal shares, then one
+// partition pass of the rids by splitter.
+static dpg_status launch_distribute_sampled(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, char *w,
+                                            hipStream_t stream, bool local_inv) {
+    const int64_t s = p.n_sample, M = p.n_rids;
+    const int B = (int)p.n_runs;
+    uint32_t *a = (uint32_t *)(w + p.off_sample), *b = (uint32_t *)(w + p.off_sample2);
+    uint32_t *split = (uint32_t *)(w + p.off_split);
+    hipLaunchKernelGGL(k_dist_sample, dim3((unsigned)((s + 255) / 256)), dim3(256), 0, stream, rids, M, p.n_src, s,
+                       a);
+    DPG_HIP(hipGetLastError());
+    const PartPlan sp = plan_partition(s, 8, 4, false);
+    const int passes = std::max(1, (bit_length((uint64_t)(p.n_src > 1 ? p.n_src - 1 : 1)) + 7) / 8);
+    for (int k = 0; k < passes; ++k) {
+        const dpg_status st =
+            launch_partition(ctx, sp, a, nullptr, b, nullptr, nullptr, 8 * k, 0, w + p.off_spart, stream, nullptr);
+        if (st != DPG_OK) return st;
+        std::swap(a, b);
+    }
+    if (B > 1) {
+        hipLaunchKernelGGL(k_dist_splitters, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, a, s, B, split);
+        DPG_HIP(hipGetLastError());
+    }
+    const PartPlan pp = plan_partition(M, p.part_nbits, 4, false);
+    return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv), 0,
+                            (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0, /*stable=*/false,
+                            local_inv, 1u, split, B - 1);
+}
+
+// Phase I in two passes (the multi-pass DPG of Section 7): the rids are
+// partitioned by the fine bits of their run index (unstable), then that list
+// by the coarse bits (stable), so the final list is in run order; inv_f and
+// inv_c record both moves.  An rid out of range is dropped by the first pass;
+// the second pass treats the unwritten tail of the first pass's output the
+// same way, so every later index stays in its buffer.
+static dpg_status launch_distribute_two_pass(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, char *w,
+                                             hipStream_t stream) {
+    const int64_t M = p.n_rids;
+    const PartPlan pf = plan_partition(M, p.lg_fine, 4, false);
+    const PartPlan pc = plan_partition(M, p.lg_coarse, 4, false);
+    dpg_status st = launch_partition(ctx, pf, rids, nullptr, w + p.off_run_f, nullptr, (int32_t *)(w + p.off_inv_f),
+                                     p.log2_run, (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0,
+                                     /*stable=*/false);
+    if (st != DPG_OK) return st;
+    return launch_partition(ctx, pc, w + p.off_run_f, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv_c),
+                            p.log2_run + p.lg_fine, (uint64_t)p.n_src, w + p.off_part2, stream, nullptr, nullptr, 0,
+                            /*stable=*/true);
+}
+
 dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,
                              hipStream_t stream, bool local_inv) {
     char *w = (char *)ws;
-    if (local_inv && p.dist_mode != DIST_PARTITION) return DPG_ERR_UNSUPPORTED;
+    if (local_inv && p.dist_mode != DIST_PARTITION && p.dist_mode != DIST_SAMPLED) return DPG_ERR_UNSUPPORTED;
+    if (p.dist_mode == DIST_SAMPLED) return launch_distribute_sampled(ctx, p, rids, w, stream, local_inv);
+    if (p.dist_mode == DIST_TWO_PASS) return launch_distribute_two_pass(ctx, p, rids, w, stream);
     if (p.dist_mode == DIST_PARTITION) {
         const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
         int32_t *item_off = p.probe == DPG_PROBE_LDS ? (int32_t *)(w + p.off_items) : nullptr;

@@ -139,9 +139,17 @@ struct ProfScope {
     ~ProfScope();
 };
 
-// Phase I flavours: append into up to 8192 runs, or one coalesced partition
-// pass into up to 4096 runs.
-enum { DIST_APPEND = 0, DIST_PARTITION = 1 };
+// Phase I flavours: append into up to 8192 runs; one coalesced partition
+// pass into up to 4096 runs; the same pass into up to 4096 runs bounded by
+// splitters drawn from a sorted sample of the rids (skew, Section 2.3); two
+// partition passes (fine run bits, then coarse bits) into up to 2^20 runs,
+// gathered back in two passes (the multi-pass DPG of Section 7).
+enum { DIST_APPEND = 0, DIST_PARTITION = 1, DIST_SAMPLED = 2, DIST_TWO_PASS = 3 };
+// The DPG_OPT_DISTRIBUTE value of a Phase I flavour (1 append, 2 partition,
+// 3 sampled, 4 two-pass) and back (0 for an unknown value).
+inline int dist_option_value(int dist_mode) { return dist_mode + 1; }
+constexpr int kDistOptionMax = 4;
+constexpr int kSampleFactor = 64;  // sampled rids per run
 
 // Retrieval plan (resolved), shared by retrieve, sort, join and batch.
 struct RetrievePlan {
@@ -156,12 +164,19 @@ struct RetrievePlan {
     size_t off_cnt = 0, off_csum = 0, off_total = 0, off_bucket = 0, off_items = 0;
     size_t off_run = 0, off_inv = 0, off_internal = 0, off_flag = 0;
     int64_t n_chunks = 0;      // column-scan chunks of the count matrix
-    int dist_mode = 0;         // DIST_APPEND or DIST_PARTITION
+    int dist_mode = 0;         // DIST_APPEND, DIST_PARTITION, DIST_SAMPLED or DIST_TWO_PASS
     int part_nbits = 0;        // digit width of the partition pass
     size_t off_part = 0;       // partition scratch (count matrix, bucket offsets)
     int32_t probe_chunk = 0;   // run entries per LDS-probe work item
     bool gather_lds = false;   // Phase III stages each distribute tile in LDS
     int part_tile = 0;         // rids per partition tile (gather_lds)
+    // DIST_SAMPLED: the sample, its sorted copy, its sort scratch, the splitters
+    int64_t n_sample = 0;
+    size_t off_sample = 0, off_sample2 = 0, off_spart = 0, off_split = 0;
+    // DIST_TWO_PASS: digit widths, the fine pass's runs and slots, the coarse
+    // pass's slots and scratch, and the intermediate record array of Phase III
+    int lg_fine = 0, lg_coarse = 0;
+    size_t off_run_f = 0, off_inv_f = 0, off_inv_c = 0, off_part2 = 0, off_u = 0;
     size_t workspace = 0;
 };
 

@@ -159,7 +159,8 @@ static dpg_status launch_gather_lds_t(const RetrievePlan &p, const void *interna
 }
 
 dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void *dst, hipStream_t stream) {
-    if (!p.gather_lds || p.dist_mode != DIST_PARTITION || p.part_tile <= 0) return DPG_ERR_UNSUPPORTED;
+    if (!p.gather_lds || (p.dist_mode != DIST_PARTITION && p.dist_mode != DIST_SAMPLED) || p.part_tile <= 0)
+        return DPG_ERR_UNSUPPORTED;
     if (p.n_rids <= 0) return DPG_OK;
     char *w = (char *)ws;
     const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);

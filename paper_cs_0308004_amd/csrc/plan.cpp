@@ -16,6 +16,7 @@
 // runs, a 12-bit one above); the append form (B <= 8192) serves as the
 // alternative the autotuner and tests can select.
 // L is a power of two so the run of rid r is r >> log2(L) (Section 2.1).
+#include <algorithm>
 #include <cstring>
 
 #include "dpg_internal.h"
@@ -24,6 +25,7 @@
 namespace dpg {
 
 constexpr int64_t kMaxRuns = 8192;
+constexpr int64_t kMaxTwoPassRuns = (int64_t)1 << 20;  // 12 fine bits x 8 coarse bits
 constexpr size_t kLdsRegionBytes = 64 * 1024;
 constexpr size_t kCachedRegionBytes = 4 << 20;
 
@@ -57,11 +59,28 @@ static void layout_workspace(RetrievePlan *p) {
     p->off_flag = take(sizeof(int32_t));
     if (p->algo == DPG_ALGO_DPG) {
         const int64_t B = p->n_runs, M = p->n_rids;
-        if (p->dist_mode == DIST_PARTITION) {
+        if (p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) {
             const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
             p->off_part = take(pp.workspace);
             p->off_bucket = p->off_part + pp.off_bucket;
             p->off_items = take((size_t)((1 << p->part_nbits) + 1) * 4);
+            if (p->dist_mode == DIST_SAMPLED) {
+                const PartPlan sp = plan_partition(p->n_sample, 8, 4, false);
+                p->off_sample = take((size_t)p->n_sample * 4);
+                p->off_sample2 = take((size_t)p->n_sample * 4);
+                p->off_spart = take(sp.workspace);
+                p->off_split = take((size_t)B * 4);
+            }
+        } else if (p->dist_mode == DIST_TWO_PASS) {
+            const PartPlan pf = plan_partition(M, p->lg_fine, 4, false);
+            const PartPlan pc = plan_partition(M, p->lg_coarse, 4, false);
+            p->off_part = take(pf.workspace);
+            p->off_part2 = take(pc.workspace);
+            p->off_bucket = p->off_part2 + pc.off_bucket;  // coarse run boundaries
+            p->off_run_f = take((size_t)M * 4);
+            p->off_inv_f = take((size_t)M * 4);
+            p->off_inv_c = take((size_t)M * 4);
+            p->off_u = take((size_t)M * p->rec_bytes);
         } else {
             p->off_cnt = take((size_t)p->n_tiles * B * 4);
             p->off_csum = take((size_t)p->n_chunks * B * 4);
@@ -85,6 +104,10 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     const int R = p->rec_bytes;
     const int lg_n = ilog2_ceil(N);
     const int lg_lds = floor_log2(kLdsRegionBytes / (size_t)R);
+    const bool sampled = dist_mode == DIST_SAMPLED + 1, two_pass = dist_mode == DIST_TWO_PASS + 1;
+    // runs of uneven width (sampled) or without per-run boundaries (two-pass)
+    // are probed through the caches
+    if (sampled || two_pass) probe = DPG_PROBE_CACHED;
     if (probe == DPG_PROBE_AUTO) probe = DPG_PROBE_CACHED;
     if (probe == DPG_PROBE_LDS && lg_lds < 0) probe = DPG_PROBE_CACHED;
     int lg;
@@ -102,13 +125,35 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     // B <= kMaxRuns, and B <= kMaxWideBuckets for the one-pass partition
     // distribute (its count matrix then stays at a quarter of the rid list):
     // lengthen the runs if needed
-    const int64_t max_runs = (dist_mode == 1 || log2_run > 0) ? kMaxRuns : kMaxWideBuckets;
+    const int64_t max_runs = two_pass ? kMaxTwoPassRuns
+                             : sampled ? kMaxWideBuckets
+                             : (dist_mode == 1 || log2_run > 0) ? kMaxRuns : kMaxWideBuckets;
     while (((N + ((int64_t)1 << lg) - 1) >> lg) > max_runs) ++lg;
     if (probe == DPG_PROBE_LDS && lg > lg_lds) probe = DPG_PROBE_CACHED;
     p->probe = probe;
     p->log2_run = lg;
     p->n_runs = (N + ((int64_t)1 << lg) - 1) >> lg;
-    if (p->n_runs <= kMaxWideBuckets && dist_mode != 1) {
+    if (two_pass) {
+        // fine bits first (unstable, up to 12), then the coarse bits (stable,
+        // up to 8): runs are ordered by (coarse, fine) = by run index
+        const int T = p->n_runs > 1 ? std::max(2, bit_length((uint64_t)(p->n_runs - 1))) : 2;
+        p->dist_mode = DIST_TWO_PASS;
+        p->lg_coarse = std::max(1, T - kMaxWideBits);
+        p->lg_fine = T - p->lg_coarse;
+        p->part_nbits = p->lg_fine;
+        const PartPlan pf = plan_partition(M, p->lg_fine, 4, false);
+        p->dist_tile = pf.tile;
+        p->n_tiles = pf.n_tiles;
+        p->n_chunks = pf.n_chunks;
+    } else if (sampled) {
+        p->dist_mode = DIST_SAMPLED;
+        p->part_nbits = std::max(1, bit_length((uint64_t)(p->n_runs - 1)));
+        p->n_sample = std::max<int64_t>(1, std::min<int64_t>(M, kSampleFactor * p->n_runs));
+        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+        p->dist_tile = pp.tile;
+        p->n_tiles = pp.n_tiles;
+        p->n_chunks = pp.n_chunks;
+    } else if (p->n_runs <= kMaxWideBuckets && dist_mode != 1) {
         // one coalesced partition pass (its own tile size)
         p->dist_mode = DIST_PARTITION;
         p->part_nbits = bit_length((uint64_t)(p->n_runs - 1));
@@ -131,7 +176,8 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     // Phase III through LDS when a partition tile's records fit (records of
     // 4, 8 or 16 bytes, one LDS element each): every global access of the
     // gather is then coalesced.
-    if (p->dist_mode == DIST_PARTITION && gather != 1 && (R == 4 || R == 8 || R == 16)) {
+    if ((p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) && gather != 1 &&
+        (R == 4 || R == 8 || R == 16)) {
         const size_t lds = (size_t)p->dist_tile * R + 8u * ((size_t)1 << p->part_nbits);
         p->gather_lds = lds <= kGatherLdsBytes;
         p->part_tile = p->dist_tile;
@@ -275,13 +321,13 @@ extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32
     out->probe = p.algo == DPG_ALGO_DPG ? p.probe : 0;
     out->log2_run = p.log2_run;
     out->dist_tile = p.dist_tile;
-    out->distribute = p.algo == DPG_ALGO_DPG ? (p.dist_mode == dpg::DIST_PARTITION ? 2 : 1) : 0;
+    out->distribute = p.algo == DPG_ALGO_DPG ? dpg::dist_option_value(p.dist_mode) : 0;
     out->gather = p.algo == DPG_ALGO_DPG ? (p.gather_lds ? 2 : 1) : 0;
     out->n_runs = p.n_runs;
     out->n_tiles = p.n_tiles;
     out->workspace_bytes = p.workspace;
     if (p.algo == DPG_ALGO_DPG && n_rids > 0) {
-        out->ws_run_off = p.off_bucket;
+        out->ws_run_off = p.dist_mode == dpg::DIST_TWO_PASS ? 0 : p.off_bucket;
         out->ws_rid_run = p.off_run;
         out->ws_internal = p.off_internal;
     }

@@ -18,7 +18,7 @@
 namespace dpg {
 
 struct Candidate {
-    int algo, probe, log2_run, dist_mode;  // dist_mode as the option value (1 append, 2 partition)
+    int algo, probe, log2_run, dist_mode;  // dist_mode as the option value (1 append, 2 partition, ...)
 };
 
 static std::vector<Candidate> candidates(int64_t n_src, int32_t rec_bytes) {
@@ -119,7 +119,7 @@ dpg_status dpg_autotune_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, i
     if (st != DPG_OK) return st;
     if (best_t >= 1e300) return DPG_ERR_UNSUPPORTED;
     TuneEntry e{best_c.algo, best_p.algo == DPG_ALGO_DPG ? best_p.probe : 0, best_p.log2_run, 0,
-                best_p.algo == DPG_ALGO_DPG ? (best_p.dist_mode == DIST_PARTITION ? 2 : 1) : 0, best_t};
+                best_p.algo == DPG_ALGO_DPG ? dist_option_value(best_p.dist_mode) : 0, best_t};
     ctx->tuned[tune_key(rec_bytes, n_src, n_rids)] = e;
     if (best) {
         *best = dpg_plan{};
@@ -169,7 +169,7 @@ dpg_status dpg_tune_load(dpg_ctx *ctx, const char *path) {
         if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &k.rec_bytes, &k.log2_n_src, &k.log2_n_rids, &e.algo,
                         &e.probe, &e.log2_run, &e.dist_mode, &e.ms) != 8 ||
             (e.algo != DPG_ALGO_DIRECT && e.algo != DPG_ALGO_DPG) || e.probe < 0 || e.probe > DPG_PROBE_LDS ||
-            e.log2_run < 0 || e.log2_run > 31 || e.dist_mode < 0 || e.dist_mode > 2) {
+            e.log2_run < 0 || e.log2_run > 31 || e.dist_mode < 0 || e.dist_mode > kDistOptionMax) {
             st = DPG_ERR_INVALID_ARG;
             break;
         }

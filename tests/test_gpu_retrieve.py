@@ -38,6 +38,8 @@ def make_rids(kind, n_src, n_rids, rec_bytes, seed):
         return synth.rids_blocked(n_src, rec_bytes, seed)
     if kind == "same":
         return np.full(n_rids, n_src // 2, dtype=np.int32)
+    if kind == "zipf":  # Zipf(1.2) ranks as ids: the hot records sit together at the start
+        return synth.zipf_fk_at(n_src, 1.2, np.arange(n_rids), seed, permute_ids=False).astype(np.int32)
     if kind == "identity":
         return np.arange(n_rids, dtype=np.int32) % n_src
     if kind == "reverse":
@@ -64,6 +66,12 @@ VARIANTS = {
     "dpg-lds-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_PARTITION, gather=2)),
     "dpg-lds-gather-wide": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=3, dist=dpg.DIST_PARTITION,
                                                gather=2)),
+    # skew-balanced runs from a sorted sample (Section 2.3)
+    "dpg-sampled": (dpg.ALGO_DPG, dict(dist=dpg.DIST_SAMPLED)),
+    "dpg-sampled-short-runs": (dpg.ALGO_DPG, dict(dist=dpg.DIST_SAMPLED, log2_run=3)),
+    # two partition passes and a two-pass gather (multi-pass DPG, Section 7)
+    "dpg-two-pass": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS)),
+    "dpg-two-pass-short-runs": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS, log2_run=1)),
     "auto": (dpg.ALGO_AUTO, {}),
 }
 
@@ -90,6 +98,8 @@ CASES = [
     (6007, 6007, 32, "reverse"),
     (1, 5, 100, "same"),
     (3, 1, 24, "uniform"),
+    (50000, 80000, 100, "zipf"),
+    (20000, 30000, 8, "zipf"),
 ]
 
 
@@ -253,3 +263,56 @@ def test_config1_full_oracle(ctx):
     for algo in (dpg.ALGO_DIRECT, dpg.ALGO_DPG):
         got = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=algo)
         assert np.array_equal(got.cpu().numpy(), expect)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "zipf"])
+def test_sampled_runs_are_ordered_ranges(ctx, kind):
+    """Runs bounded by splitters from a sorted sample (Section 2.3): run b's
+    rids all lie below run b+1's, the runs hold the rid multiset, and with
+    uniform rids no run holds more than twice its share."""
+    n, m, rec = 200003, 300000, 16
+    src = synth.record_bytes(n, rec, seed=4)
+    rids = make_rids(kind, n, m, rec, seed=4)
+    configure(ctx, dist=dpg.DIST_SAMPLED, log2_run=6)
+    try:
+        plan = ctx.plan_retrieve(n, rec, m, dpg.ALGO_DPG)
+        assert plan.distribute == dpg.DIST_SAMPLED and plan.n_runs > 1000
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV)
+        out = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=dpg.ALGO_DPG,
+                           workspace=ws)
+        torch.cuda.synchronize()
+    finally:
+        configure(ctx)
+    assert np.array_equal(out.cpu().numpy(), oracle.retrieve(src, rids))
+    w = ws.cpu().numpy()
+    off = w[plan.ws_run_off: plan.ws_run_off + 4 * (plan.n_runs + 1)].view(np.int32).astype(np.int64)
+    run = w[plan.ws_rid_run: plan.ws_rid_run + 4 * m].view(np.int32)
+    assert off[0] == 0 and off[-1] == m and np.all(np.diff(off) >= 0)
+    assert np.array_equal(np.sort(run), np.sort(rids))
+    runs = [run[off[b]:off[b + 1]] for b in range(plan.n_runs) if off[b + 1] > off[b]]
+    for a, b in zip(runs, runs[1:]):
+        assert a.max() < b.min()
+    if kind == "uniform":
+        assert np.diff(off).max() <= 2 * m / plan.n_runs
+
+
+def test_two_pass_runs_in_run_order(ctx):
+    """Two partition passes (fine run bits, then coarse bits, stable): the
+    final RID list is ordered by run index and holds the rid multiset."""
+    n, m, rec = 300007, 400000, 8
+    src = synth.record_bytes(n, rec, seed=5)
+    rids = make_rids("uniform", n, m, rec, seed=5)
+    configure(ctx, dist=dpg.DIST_TWO_PASS, log2_run=2)   # 75002 runs: 12 fine bits + 5 coarse bits
+    try:
+        plan = ctx.plan_retrieve(n, rec, m, dpg.ALGO_DPG)
+        assert plan.distribute == dpg.DIST_TWO_PASS and plan.n_runs > 4096 and plan.ws_run_off == 0
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV)
+        out = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=dpg.ALGO_DPG,
+                           workspace=ws)
+        torch.cuda.synchronize()
+    finally:
+        configure(ctx)
+    assert np.array_equal(out.cpu().numpy(), oracle.retrieve(src, rids))
+    run = ws.cpu().numpy()[plan.ws_rid_run: plan.ws_rid_run + 4 * m].view(np.int32)
+    assert np.all(np.diff(run.astype(np.int64) >> plan.log2_run) >= 0)
+    assert np.array_equal(np.sort(run), np.sort(rids))
