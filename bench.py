@@ -105,6 +105,15 @@ def cpu_baseline(src_dev, rids_np, rec_bytes, target_s):
     }
 
 
+def oracle_rate(fn, units: float, unit: str, sample: str):
+    """The oracle timed on a bounded sample of a section's workload (one core)."""
+    t0 = time.perf_counter()
+    fn()
+    dt = time.perf_counter() - t0
+    return {"value": round(units / dt, 1), "unit": unit, "cores": 1, "kind": "oracle",
+            "sample": f"{sample}; {dt:.2f} s single-threaded"}
+
+
 def roofline_entry(prof: dict, kernels: list[str], counters: dict | None, workload_key: str | None = None):
     """The dominant kernel: algorithmic bytes per launch over its average
     launch duration (HIP events on the kernel's own stream)."""
@@ -266,7 +275,12 @@ def bench_sort(args, ctx, dpg, synth, torch, np):
     keys = [bytes(r) for r in k8]
     if keys != sorted(keys):
         raise SystemExit("bench: sort output not sorted")
-    del src, dst, perm
+    import oracle
+
+    host = src[: 1 << 20].cpu().numpy()
+    res["cpu_oracle"] = oracle_rate(lambda: oracle.sort_records(host, 0, 10), 1 << 20, "records/s",
+                                    "the first 2^20 of the records")
+    del src, dst, perm, host
     torch.cuda.empty_cache()
     return {"workload": "10^8 records x 100 B, 10-byte uniform key; key-pointer LSD radix sort + copy",
             **res, "dpg_over_direct": round(res["direct"]["ms"] / res["dpg"]["ms"], 4)}
@@ -292,6 +306,13 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                 res[f"zipf{s}_{oname}_{aname}"] = {"ms": round(ms, 3),
                                                    "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
                 del ws
+        if s == 0.0:
+            import oracle
+
+            f_host, d_host = fact[: 1 << 22].cpu().numpy(), dim.cpu().numpy()
+            res["cpu_oracle"] = oracle_rate(lambda: oracle.fk_join_fact_order(f_host, d_host, 0), 1 << 22,
+                                            "fact rows/s", "the first 2^22 fact rows (Zipf 0) of the fact-order join")
+            del f_host, d_host
         del fact
         torch.cuda.empty_cache()
     del dim, out
@@ -342,10 +363,16 @@ def bench_smj(args, ctx, dpg, synth, torch, np):
             raise SystemExit(f"bench: {name} sort-merge join result is not in key order")
         calls = steps + 1
         res[name] = {"ms": round(ms, 3), "input_rows_per_s": round(2 * n / (ms * 1e-3), 1),
-                     "kernels_ms_per_join": {k: round(v["ms"] / calls, 4) for k, v in prof.items()}}
+                     "kernels_ms_per_join": {k: round(v["ms"] / calls, 4) for k, v in prof.items()},
+                     "roofline": roofline_entry(prof, list(prof), None)}
         del ws, got, rows, kk
     res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
-    del rel, out
+    import oracle
+
+    r_host, s_host = rel[0][: 1 << 20].cpu().numpy(), rel[1][: 1 << 20].cpu().numpy()
+    res["cpu_oracle"] = oracle_rate(lambda: oracle.sort_merge_join(r_host, s_host, 0, 0, 4), 2 << 20,
+                                    "input rows/s", "the first 2^20 rows of each relation")
+    del rel, out, r_host, s_host
     torch.cuda.empty_cache()
     return res
 
@@ -388,9 +415,16 @@ def bench_hash(args, ctx, dpg, synth, torch, np):
         if not np.array_equal(got, want):
             raise SystemExit(f"bench: {name} hash lookup differs from the stored rids")
         res[name] = {"ms": round(ms, 4), "lookups_per_s": round(m / (ms * 1e-3), 1),
-                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()}}
+                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()},
+                     "roofline": roofline_entry(prof, list(prof), None)}
     res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
-    del keys, index, queries, out, ws
+    import oracle
+
+    k_host = keys.cpu().numpy().view(np.uint32)
+    q_host = queries[: 1 << 22].cpu().numpy().view(np.uint32)
+    res["cpu_oracle"] = oracle_rate(lambda: oracle.hash_lookup(k_host, q_host), 1 << 22, "lookups/s",
+                                    "the first 2^22 queries against all 2^24 keys")
+    del keys, index, queries, out, ws, k_host, q_host
     torch.cuda.empty_cache()
     return res
 
@@ -434,9 +468,20 @@ def bench_btree(args, ctx, dpg, synth, torch, np):
         if not np.array_equal(out.cpu().numpy(), want):
             raise SystemExit(f"bench: {name} B+ tree lookup differs from the stored rids")
         res[name] = {"ms": round(ms, 4), "lookups_per_s": round(m / (ms * 1e-3), 1),
-                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()}}
+                     "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()},
+                     "roofline": roofline_entry(prof, list(prof), None)}
     res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
-    del keys, tree, queries, out, ws, pick, hit
+    import oracle
+
+    k_host = keys[: 1 << 22].cpu().numpy().view(np.uint32)
+    q_host = queries[: 1 << 22].cpu().numpy().view(np.uint32)
+
+    def walk():
+        oracle.btree_lookup(oracle.btree_build(k_host), k_host.size, q_host)
+
+    res["cpu_oracle"] = oracle_rate(walk, 1 << 22, "lookups/s",
+                                    "build over the first 2^22 keys, then 2^22 walks")
+    del keys, tree, queries, out, ws, pick, hit, k_host, q_host
     torch.cuda.empty_cache()
     return res
 

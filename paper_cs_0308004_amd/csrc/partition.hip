@@ -59,9 +59,12 @@ __device__ __forceinline__ uint32_t split_bucket(const SplitLds &sp, uint32_t ke
     return (uint32_t)l;
 }
 
-// The bucket of a uint32 key: its digit, or with splitters its splitter bucket.
+// The bucket of a uint32 key: its digit, or with splitters its splitter
+// bucket (SPLIT is a template flag, so the digit path carries no splitter code).
+template <bool SPLIT>
 __device__ __forceinline__ uint32_t bucket_of(uint32_t key, int shift, uint32_t mask, const SplitLds &sp) {
-    return sp.s ? split_bucket(sp, key) : digit_of(key, shift, mask);
+    if constexpr (SPLIT) return split_bucket(sp, key);
+    else return digit_of(key, shift, mask);
 }
 
 // Stage the splitters and their cell table (if any) in LDS at `lds`.
@@ -117,7 +120,7 @@ __device__ __forceinline__ int32_t rank_by_atomic(int32_t *ctr, uint32_t d, bool
     return valid ? atomicAdd(&ctr[d], 1) : -1;
 }
 
-template <typename K>
+template <typename K, bool SPLIT>
 __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict__ keys, int64_t n, int shift,
                                                             int nbits, uint64_t limit, int T, uint32_t key_mul,
                                                             int32_t *__restrict__ cnt,
@@ -129,7 +132,8 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
     const uint32_t mask = (uint32_t)nb - 1;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int d = lane; d < nb; d += 64) h[wave][d] = 0;
-    const SplitLds sp = stage_splitters(s_split_h, split, cell_lo, n_split);
+    SplitLds sp;
+    if constexpr (SPLIT) sp = stage_splitters(s_split_h, split, cell_lo, n_split);
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * T;
     const int64_t end = min(base + T, n);
@@ -149,7 +153,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
             const int64_t i = i0 + (int64_t)u * kPartThreads + lane;
             const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
             uint32_t d;
-            if constexpr (sizeof(K) == 4) d = bucket_of(kv[u], shift, mask, sp);
+            if constexpr (SPLIT) d = bucket_of<true>((uint32_t)kv[u], shift, mask, sp);
             else d = digit_of(kv[u], shift, mask);
             (void)rank_by_atomic(h[wave], d, valid);
         }
@@ -165,7 +169,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
 }
 
 // The histogram for more than 256 buckets: one table per workgroup.
-template <int THREADS>
+template <int THREADS, bool SPLIT>
 __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__restrict__ keys, int64_t n,
                                                             int shift, int nbits, uint64_t limit, int T,
                                                             uint32_t key_mul, int32_t *__restrict__ cnt,
@@ -175,7 +179,8 @@ __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__re
     const int nb = 1 << nbits;
     const uint32_t mask = (uint32_t)nb - 1;
     for (int d = threadIdx.x; d < nb; d += THREADS) hw[d] = 0;
-    const SplitLds sp = stage_splitters((uint32_t *)(hw + nb), split, cell_lo, n_split);
+    SplitLds sp;
+    if constexpr (SPLIT) sp = stage_splitters((uint32_t *)(hw + nb), split, cell_lo, n_split);
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * T;
     const int64_t end = min(base + T, n);
@@ -191,7 +196,7 @@ __global__ __launch_bounds__(THREADS) void k_part_hist_wide(const uint32_t *__re
         for (int u = 0; u < kBatch; ++u) {
             const int64_t i = i0 + (int64_t)u * THREADS;
             const bool valid = i < end && (limit == 0 || (uint64_t)kv[u] < limit);
-            (void)rank_by_atomic(hw, bucket_of(kv[u], shift, mask, sp), valid);
+            (void)rank_by_atomic(hw, bucket_of<SPLIT>(kv[u], shift, mask, sp), valid);
         }
     }
     __syncthreads();
@@ -306,7 +311,7 @@ __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
 // Counts per (tile, digit) are those of the histogram pass, so the column-scan
 // offsets still apply.  LDS: keys of the tile, then the count / start and the
 // output start of every digit.
-template <int THREADS, int PER>
+template <int THREADS, int PER, bool SPLIT>
 __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
     const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int local_inv,
@@ -319,7 +324,8 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const int nb = 1 << nbits;
     int32_t *s_cnt = (int32_t *)(smem + sizeof(uint32_t) * T);  // count, then tile-local start
     int32_t *s_glob = s_cnt + nb;                               // output start of each digit for this tile
-    const SplitLds sp = stage_splitters((uint32_t *)(s_glob + nb), split, cell_lo, n_split);  // splitters, if any
+    SplitLds sp;  // splitters, if any, after the digit tables
+    if constexpr (SPLIT) sp = stage_splitters((uint32_t *)(s_glob + nb), split, cell_lo, n_split);
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_nvalid;
     const uint32_t mask = (uint32_t)nb - 1;
@@ -344,8 +350,9 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
         const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
-        bkt[k] = bucket_of(key[k], shift, mask, sp);
-        rank[k] = rank_by_atomic(s_cnt, bkt[k], valid);
+        const uint32_t d = bucket_of<SPLIT>(key[k], shift, mask, sp);
+        if constexpr (SPLIT) bkt[k] = d;  // a splitter search is kept, a digit recomputed
+        rank[k] = rank_by_atomic(s_cnt, d, valid);
     }
     __syncthreads();
     // exclusive prefix of the digit counts: wave w scans the w-th slice of
@@ -383,7 +390,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
         if (rank[k] >= 0) {
-            const uint32_t d = bkt[k];
+            const uint32_t d = SPLIT ? bkt[k] : digit_of(key[k], shift, mask);
             s_key[s_cnt[d] + rank[k]] = key[k];
             if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rank[k];
         } else if (inv && e < cnt) {
@@ -394,7 +401,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const int nvalid = s_nvalid;
     for (int j = threadIdx.x; j < nvalid; j += THREADS) {
         const uint32_t k = s_key[j];
-        const uint32_t d = bucket_of(k, shift, mask, sp);
+        const uint32_t d = bucket_of<SPLIT>(k, shift, mask, sp);
         keys_out[(int64_t)s_glob[d] + (j - s_cnt[d])] = k;
     }
 }
@@ -480,15 +487,17 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         ProfScope prof(ctx, wide ? K_PART_HIST_WIDE : K_PART_HIST, (double)p.key_bytes * p.n + 4.0 * p.n_tiles * nb,
                        stream);
         if (wide)
-            hipLaunchKernelGGL((k_part_hist_wide<1024>), dim3((unsigned)p.n_tiles), dim3(1024),
-                               (size_t)nb * sizeof(int32_t) + split_lds, stream, (const uint32_t *)keys_in, p.n,
-                               shift, p.nbits, limit, p.tile, key_mul, cnt, split, cells, n_split);
+            hipLaunchKernelGGL((split ? k_part_hist_wide<1024, true> : k_part_hist_wide<1024, false>),
+                               dim3((unsigned)p.n_tiles), dim3(1024), (size_t)nb * sizeof(int32_t) + split_lds, stream,
+                               (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt, split, cells,
+                               n_split);
         else if (p.key_bytes == 8)
-            hipLaunchKernelGGL((k_part_hist<uint64_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
+            hipLaunchKernelGGL((k_part_hist<uint64_t, false>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
                                (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, 1u, cnt, nullptr,
                                nullptr, 0);
         else
-            hipLaunchKernelGGL((k_part_hist<uint32_t>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), split_lds,
+            hipLaunchKernelGGL((split ? k_part_hist<uint32_t, true> : k_part_hist<uint32_t, false>),
+                               dim3((unsigned)p.n_tiles), dim3(kPartThreads), split_lds,
                                stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt,
                                split, cells, n_split);
         DPG_HIP(hipGetLastError());
@@ -512,18 +521,21 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (!stable) {
         const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb + split_lds;
         if (wide) {
+            const void *fn = split ? (const void *)k_part_scatter_unstable<1024, 16, true>
+                                   : (const void *)k_part_scatter_unstable<1024, 16, false>;
             if (lds > 64 * 1024)
-                DPG_HIP(hipFuncSetAttribute((const void *)k_part_scatter_unstable<1024, 16>,
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((k_part_scatter_unstable<1024, 16>), dim3((unsigned)p.n_tiles), dim3(1024), lds,
-                               stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.n_tiles, cnt,
-                               (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap, split, cells, n_split);
+                DPG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL((split ? k_part_scatter_unstable<1024, 16, true> : k_part_scatter_unstable<1024, 16, false>),
+                               dim3((unsigned)p.n_tiles), dim3(1024), lds, stream, (const uint32_t *)keys_in, p.n,
+                               shift, p.nbits, limit, p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0,
+                               key_mul, remap, split, cells, n_split);
         } else {
             if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
-            hipLaunchKernelGGL((k_part_scatter_unstable<kPartThreads, 32>), dim3((unsigned)p.n_tiles),
-                               dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit,
-                               p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0, key_mul, remap, split,
-                               cells, n_split);
+            hipLaunchKernelGGL((split ? k_part_scatter_unstable<kPartThreads, 32, true>
+                                      : k_part_scatter_unstable<kPartThreads, 32, false>),
+                               dim3((unsigned)p.n_tiles), dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in,
+                               p.n, shift, p.nbits, limit, p.n_tiles, cnt, (uint32_t *)keys_out, inv,
+                               local_inv ? 1 : 0, key_mul, remap, split, cells, n_split);
         }
         DPG_HIP(hipGetLastError());
         return DPG_OK;
