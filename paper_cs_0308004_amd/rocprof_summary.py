@@ -34,6 +34,18 @@ def short_name(name: str) -> str:
     return name.split("(")[0][:80]
 
 
+def template_args(name: str) -> str:
+    """'void dpg::k_probe_cached<unsigned int __vector(4), 4, true>(...)' -> 'u32x4, 4, true'."""
+    m = re.search(r"dpg::k_[a-z0-9_]+<(.*?)>\(", name)
+    if not m:
+        return ""
+    s = m.group(1)
+    for a, b in (("unsigned int __vector(4)", "u32x4"), ("unsigned int __vector(2)", "u32x2"),
+                 ("unsigned long", "u64"), ("unsigned int", "u32")):
+        s = s.replace(a, b)
+    return s
+
+
 def read_csv(path: str) -> list[dict]:
     with open(path, newline="") as f:
         return list(csv.DictReader(f))
@@ -49,13 +61,15 @@ def find(dir_: str, suffix: str) -> str:
 def stats_report(stats_csv: str, out_md: str, command: str):
     rows = read_csv(stats_csv)
     lines = ["# Kernel durations (rocprofv3 --kernel-trace --stats)", "", f"Command: `{command}`", "",
-             "| kernel | calls | average (us) | total (ms) | % of GPU time |", "|---|---:|---:|---:|---:|"]
+             "| kernel | template arguments | calls | average (us) | total (ms) | % of GPU time |",
+             "|---|---|---:|---:|---:|---:|"]
     for r in rows:
         name = r.get("Name") or r.get("Kernel_Name") or ""
         if not short_name(name).startswith("k_"):
             continue
-        lines.append(f"| {short_name(name)} | {int(r['Calls'])} | {float(r['AverageNs']) / 1e3:.1f} | "
-                     f"{float(r['TotalDurationNs']) / 1e6:.3f} | {float(r['Percentage']):.2f} |")
+        lines.append(f"| {short_name(name)} | {template_args(name)} | {int(r['Calls'])} | "
+                     f"{float(r['AverageNs']) / 1e3:.1f} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                     f"{float(r['Percentage']):.2f} |")
     lines += ["", "Kernels of other libraries (input generation by torch, runtime copies) are omitted."]
     with open(out_md, "w") as f:
         f.write("\n".join(lines) + "\n")

@@ -83,3 +83,48 @@ def test_smj_capacity_and_errors(ctx):
     got = ctx.sort_merge_join(rd, sd, 0, 0, 4, out=torch.empty((1, 32), dtype=torch.uint8, device=DEV))
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), want)
+
+
+def test_smj_full_size(ctx):
+    """The benchmark's configuration: R and S of 2^24 x 100 B rows, a 4-byte
+    key uniform over 2^24 values.  The result is fixed by its definition:
+    for every key, a block of cR * cS rows, R index major, at the position the
+    counts of the smaller keys give.  Checked: the row count, that both halves
+    of every row hold the same key, that keys never decrease, and for 64
+    sampled keys the exact block."""
+    n, R = 1 << 24, 100
+    rel, keys, counts = [], [], []
+    for side in range(2):
+        rows = synth.record_bytes(n, R, 300 + side, backend="torch", device=DEV)
+        k = synth.uniform_at(n, torch.arange(n, device=DEV), 300 + side, synth.STREAM_FK, backend="torch",
+                             device=DEV).to(torch.int32)
+        rows[:, 0:4] = k.view(torch.uint8).reshape(-1, 4)
+        rel.append(rows)
+        keys.append(k.to(torch.int64))
+        counts.append(torch.bincount(k.to(torch.int64), minlength=n))
+    # the key compares as big-endian bytes: order the blocks by that value
+    be = lambda k: ((k & 0xFF) << 24) | (((k >> 8) & 0xFF) << 16) | (((k >> 16) & 0xFF) << 8) | ((k >> 24) & 0xFF)
+    per_key = counts[0] * counts[1]
+    total = int(per_key.sum())
+    ids = torch.arange(n, device=DEV)
+    order = torch.argsort(be(ids))
+    start = torch.zeros(n, dtype=torch.int64, device=DEV)
+    start[order] = torch.cumsum(per_key[order], 0) - per_key[order]
+    for algo in (dpg.ALGO_DPG, dpg.ALGO_DIRECT):
+        out = ctx.sort_merge_join(rel[0], rel[1], 0, 0, 4, algo=algo,
+                                  out=torch.empty((total + 16, 2 * R), dtype=torch.uint8, device=DEV))
+        torch.cuda.synchronize()
+        assert out.shape[0] == total
+        assert torch.equal(out[:, 0:4], out[:, R:R + 4])
+        kk = be(out[:, 0:4].contiguous().view(torch.int32).view(-1).to(torch.int64) & 0xFFFFFFFF)
+        assert bool((kk[1:] >= kk[:-1]).all())
+        hot = torch.nonzero(per_key > 0).view(-1)
+        pick = hot[torch.randperm(hot.numel(), device=DEV, generator=torch.Generator(device=DEV).manual_seed(3))[:64]]
+        for key in pick.tolist():
+            ri = torch.nonzero(keys[0] == key).view(-1)
+            si = torch.nonzero(keys[1] == key).view(-1)
+            want = torch.cat([rel[0][ri].repeat_interleave(si.numel(), 0), rel[1][si].repeat(ri.numel(), 1)], 1)
+            s0 = int(start[key])
+            assert torch.equal(out[s0:s0 + want.shape[0]], want), key
+        del out
+    torch.cuda.empty_cache()
