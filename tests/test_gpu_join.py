@@ -106,3 +106,26 @@ def test_join_full_size_sampled(ctx):
     assert torch.equal(a, b)
     del fact, dim, out, ofk, a, b
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("dist", [dpg.DIST_APPEND, dpg.DIST_SAMPLED, dpg.DIST_TWO_PASS],
+                         ids=["append", "sampled", "two-pass"])
+@pytest.mark.parametrize("order", [dpg.JOIN_FACT_ORDER, dpg.JOIN_DIM_ORDER], ids=["move", "sort"])
+def test_join_phase_i_forms(ctx, order, dist):
+    """Every Phase I form gives the same join (the fused assembly reads
+    INTERNAL through one slot per row, which the two-pass form composes)."""
+    n_fact, n_dim = 60001, 1 << 14
+    seed = synth.SEED_BASE + 77
+    fact = synth.fact_table(n_fact, n_dim, 1.2, seed, permute_ids=False)
+    dim = synth.dim_table(n_dim, seed)
+    fn = oracle.fk_join_fact_order if order == dpg.JOIN_FACT_ORDER else oracle.fk_join_dim_order
+    want = fn(fact, dim, 0)
+    ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
+    ctx.set_option(dpg.OPT_LOG2_RUN, 2)  # thousands of runs
+    try:
+        got = ctx.fk_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 0, order, algo=dpg.ALGO_DPG)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(dpg.OPT_DISTRIBUTE, 0)
+        ctx.set_option(dpg.OPT_LOG2_RUN, 0)
+    assert np.array_equal(got.cpu().numpy(), want)
