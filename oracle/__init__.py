@@ -67,13 +67,14 @@ def _bind(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_hash_build.argtypes = [_VP, _I64, _I32, _VP, _VP, _VP, _VP]
     lib.oracle_hash_lookup.argtypes = [_VP, _I64, _VP, _I64, _VP]
     lib.oracle_sort_merge_join.argtypes = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64, _VP]
+    lib.oracle_key_join.argtypes = [_VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP]
     lib.oracle_btree_shape.argtypes = [_I64, _VP, _I32]
     lib.oracle_btree_build.argtypes = [_VP, _I64, _VP, _VP, _VP]
     lib.oracle_btree_lookup.argtypes = [_VP, _VP, _VP, _I64, _VP, _I64, _VP]
     for f in (lib.oracle_retrieve, lib.oracle_dpg_phases, lib.oracle_sort_records,
               lib.oracle_fk_join_fact_order, lib.oracle_fk_join_dim_order, lib.oracle_hash_build,
               lib.oracle_hash_lookup, lib.oracle_sort_merge_join, lib.oracle_btree_shape,
-              lib.oracle_btree_build, lib.oracle_btree_lookup):
+              lib.oracle_btree_build, lib.oracle_btree_lookup, lib.oracle_key_join):
         f.restype = ctypes.c_int
     return lib
 
@@ -169,6 +170,21 @@ def fk_join_fact_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, li
 def fk_join_dim_order(fact: np.ndarray, dim: np.ndarray, fk_offset: int = 0, lib=None) -> np.ndarray:
     """DPG-Sort goal (Section 4.2.1): joined rows in foreign-key order, ties in fact order."""
     return _join("oracle_fk_join_dim_order", fact, dim, fk_offset, lib)
+
+
+def key_join(fact: np.ndarray, dim: np.ndarray, fk_offset: int, key_offset: int, order: int = 0, lib=None):
+    """Join over non-dense keys (Sections 4.2.2-4.2.3): fact row i joins the
+    first dimension row whose uint32 key at key_offset equals its fk; order 0
+    keeps fact order, order 1 orders by that dimension row (ties in fact order)."""
+    lib = lib or load()
+    f = _records(fact, fact.shape[1])
+    d = _records(dim, dim.shape[1])
+    out = np.empty((f.shape[0], f.shape[1] + d.shape[1]), dtype=np.uint8)
+    rc = lib.oracle_key_join(_ptr(f), f.shape[0], f.shape[1], fk_offset, _ptr(d), d.shape[0], d.shape[1],
+                             key_offset, order, _ptr(out))
+    if rc:
+        raise OracleError(rc, "key_join")
+    return out
 
 
 HASH_EMPTY = 0xFFFFFFFF

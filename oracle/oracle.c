@@ -654,3 +654,66 @@ int oracle_btree_lookup(const uint32_t *leaf_keys, const int32_t *leaf_rids, con
     }
     return ORACLE_OK;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Foreign-key join over non-dense keys (Sections 4.2.2 and 4.2.3): the      */
+/* dimension rows carry a uint32 key at key_offset, and the join triple of   */
+/* fact row i is (fk_i, i, j) with j the first dimension row whose key is    */
+/* fk_i -- the rid an index lookup of fk_i returns.  Every fk must have a    */
+/* dimension row (ORACLE_ERANGE otherwise).  order 0: out[i] = fact[i] ||    */
+/* dim[j_i] (fact order); order 1: the same rows ordered by j, ties in fact  */
+/* order (dimension order).                                                  */
+/* ------------------------------------------------------------------------- */
+int oracle_key_join(const uint8_t *fact, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
+                    const uint8_t *dim, int64_t n_dim, int32_t dim_bytes, int32_t key_offset, int32_t order,
+                    uint8_t *out)
+{
+    if (n_fact < 0 || n_dim < 0 || n_dim > INT32_MAX - 1 || fact_bytes < 1 || dim_bytes < 1 || fk_offset < 0 ||
+        fk_offset + 4 > fact_bytes || key_offset < 0 || key_offset + 4 > dim_bytes || (order != 0 && order != 1))
+        return ORACLE_EINVAL;
+    if (n_fact == 0)
+        return ORACLE_OK;
+    key_rid *keys = malloc((size_t)(n_dim > 0 ? n_dim : 1) * sizeof(key_rid));
+    rid_pair *pairs = malloc((size_t)n_fact * sizeof(rid_pair));
+    if (!keys || !pairs) {
+        free(keys);
+        free(pairs);
+        return ORACLE_EINVAL;
+    }
+    for (int64_t j = 0; j < n_dim; ++j) {
+        keys[j].key = read_le_u32(dim + j * (int64_t)dim_bytes + key_offset);
+        keys[j].rid = j;
+    }
+    qsort(keys, (size_t)n_dim, sizeof(key_rid), compare_key_rid);
+    for (int64_t i = 0; i < n_fact; ++i) {
+        uint32_t fk = read_le_u32(fact + i * (int64_t)fact_bytes + fk_offset);
+        int64_t lo = 0, hi = n_dim; /* first (key, rid) with key >= fk */
+        while (lo < hi) {
+            int64_t mid = (lo + hi) / 2;
+            if (keys[mid].key < fk)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        if (lo == n_dim || keys[lo].key != fk) {
+            free(keys);
+            free(pairs);
+            return ORACLE_ERANGE;
+        }
+#ifdef ORACLE_MUTANT_KEYJOIN_LAST_MATCH
+        while (lo + 1 < n_dim && keys[lo + 1].key == fk)
+            ++lo;
+#endif
+        pairs[i].fk = (uint32_t)keys[lo].rid;
+        pairs[i].rid = i;
+    }
+    if (order == 1)
+        qsort(pairs, (size_t)n_fact, sizeof(rid_pair), compare_rid_pair);
+    int64_t out_bytes = (int64_t)fact_bytes + dim_bytes;
+    for (int64_t k = 0; k < n_fact; ++k)
+        emit_joined_row(out + k * out_bytes, fact + pairs[k].rid * (int64_t)fact_bytes, fact_bytes,
+                        dim + (int64_t)pairs[k].fk * dim_bytes, dim_bytes);
+    free(keys);
+    free(pairs);
+    return ORACLE_OK;
+}

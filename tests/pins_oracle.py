@@ -535,6 +535,66 @@ def pin_btree_errors(lib):
             raise AssertionError("bad entry count accepted")
 
 
+# ---------------------------------------------------------------------------
+# foreign-key join over non-dense keys (Sections 4.2.2-4.2.3)
+# ---------------------------------------------------------------------------
+def _key_join_brute(fact, dim, fk_off, key_off, order):
+    fk = fact[:, fk_off:fk_off + 4].copy().view("<u4").reshape(-1)
+    dk = dim[:, key_off:key_off + 4].copy().view("<u4").reshape(-1)
+    j = [next(r for r in range(dim.shape[0]) if dk[r] == k) for k in fk.tolist()]
+    rows = list(range(fact.shape[0]))
+    if order == 1:
+        rows.sort(key=lambda i: (j[i], i))
+    return np.array([np.concatenate([fact[i], dim[j[i]]]) for i in rows], dtype=np.uint8).reshape(
+        fact.shape[0], fact.shape[1] + dim.shape[1])
+
+
+def pin_key_join_brute_force(lib):
+    """Each fact row joins the first dimension row holding its key: every
+    dimension key list of length <= 4 on a 3-letter alphabet (duplicates
+    included) and every fact key list of length <= 3 drawn from it, in both
+    orders, against nested loops."""
+    alphabet = [3, 9, 0xFFFFFFFF]
+    rng = np.random.default_rng(31)
+    for nd in range(1, 5):
+        for dkeys in itertools.product(alphabet, repeat=nd):
+            dim = rng.integers(0, 256, (nd, 12), dtype=np.uint8)
+            dim[:, 4:8] = np.array(dkeys, dtype="<u4").view(np.uint8).reshape(nd, 4)
+            present = sorted(set(dkeys))
+            for nf in range(0, 4):
+                for fkeys in itertools.product(present, repeat=nf):
+                    fact = rng.integers(0, 256, (nf, 8), dtype=np.uint8)
+                    if nf:
+                        fact[:, 0:4] = np.array(fkeys, dtype="<u4").view(np.uint8).reshape(nf, 4)
+                    for order in (0, 1):
+                        got = oracle.key_join(fact, dim, 0, 4, order, lib=lib)
+                        assert np.array_equal(got, _key_join_brute(fact, dim, 0, 4, order)), (dkeys, fkeys, order)
+
+
+def pin_key_join_dense_keys(lib):
+    """With dimension keys equal to the row numbers the join is the dense
+    foreign-key join of Section 4.2.1, in either order."""
+    n_fact, n_dim = 3000, 257
+    fact = synth.fact_table(n_fact, n_dim, 0.8, seed=32)
+    dim = synth.dim_table(n_dim, seed=33)  # key = row number at byte 0
+    assert np.array_equal(oracle.key_join(fact, dim, 0, 0, 0, lib=lib), oracle.fk_join_fact_order(fact, dim, 0))
+    assert np.array_equal(oracle.key_join(fact, dim, 0, 0, 1, lib=lib), oracle.fk_join_dim_order(fact, dim, 0))
+
+
+def pin_key_join_errors(lib):
+    fact = np.zeros((2, 8), dtype=np.uint8)
+    fact[1, 0] = 5
+    dim = np.zeros((3, 8), dtype=np.uint8)  # keys 0, 0, 0: key 5 is missing
+    for args, code in (((0, 0, 0), oracle.ERANGE), ((5, 0, 0), oracle.EINVAL), ((0, 6, 0), oracle.EINVAL),
+                       ((0, 0, 2), oracle.EINVAL)):
+        try:
+            oracle.key_join(fact, dim, *args, lib=lib)
+        except oracle.OracleError as e:
+            assert e.code == code
+        else:
+            raise AssertionError(f"accepted {args}")
+
+
 ALL_PINS = [
     pin_retrieve_brute_force, pin_retrieve_closed_forms, pin_retrieve_multiset, pin_retrieve_errors,
     pin_fig2_example, pin_phase_invariants, pin_sort_random, pin_sort_ties,
@@ -542,4 +602,5 @@ ALL_PINS = [
     pin_hash_lookup_brute_force, pin_hash_lookup_closed_forms, pin_hash_build_invariants, pin_hash_errors,
     pin_smj_brute_force, pin_smj_closed_forms, pin_smj_errors,
     pin_btree_lookup_brute_force, pin_btree_structure, pin_btree_closed_forms, pin_btree_errors,
+    pin_key_join_brute_force, pin_key_join_dense_keys, pin_key_join_errors,
 ]

@@ -19,6 +19,7 @@ MUTANTS = {
     "ORACLE_MUTANT_SMJ_J_MAJOR": [pins_oracle.pin_smj_brute_force, pins_oracle.pin_smj_closed_forms],
     "ORACLE_MUTANT_BTREE_FIRST_ENTRY": [pins_oracle.pin_btree_structure, pins_oracle.pin_btree_lookup_brute_force],
     "ORACLE_MUTANT_BTREE_STRICT": [pins_oracle.pin_btree_lookup_brute_force],
+    "ORACLE_MUTANT_KEYJOIN_LAST_MATCH": [pins_oracle.pin_key_join_brute_force],
 }
 
 
