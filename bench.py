@@ -307,6 +307,27 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                                                    "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
                 del ws
         if s == 0.0:
+            # the same join over non-dense keys: dimension keys are distinct
+            # odd uint32, and the fk column holds the key of the row it names
+            keys = (2 * synth.rids_permutation(1 << 30, seed, backend="torch", device=dev, count=n_dim).to(torch.int64)
+                    + 1).to(torch.int32)
+            dim_k = dim.clone()
+            dim_k[:, 4:8] = keys.view(torch.uint8).reshape(-1, 4)
+            fact_k = fact.clone()
+            fact_k[:, 0:4] = keys[fact[:, 0:4].contiguous().view(torch.int32).view(-1).to(torch.int64)].view(
+                torch.uint8).reshape(-1, 4)
+            lg_slots = 25
+            index = ctx.hash_build(keys, lg_slots)
+            for order, oname in ((dpg.JOIN_FACT_ORDER, "move"), (dpg.JOIN_DIM_ORDER, "sort")):
+                for algo, aname in ((dpg.ALGO_DPG, "dpg"), (dpg.ALGO_DIRECT, "direct"), (dpg.ALGO_AUTO, "auto")):
+                    ws = torch.empty(ctx.key_join_workspace_bytes(n_fact, 16, 0, n_dim, 64, lg_slots, order, algo),
+                                     dtype=torch.uint8, device=dev)
+                    ms, _ = time_steps(lambda: ctx.key_join(fact_k, dim_k, 0, index, lg_slots, order, out=out,
+                                                            algo=algo, workspace=ws), steps, 1, torch)
+                    res[f"keyed_{oname}_{aname}"] = {"ms": round(ms, 3),
+                                                     "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
+                    del ws
+            del dim_k, fact_k, keys, index
             import oracle
 
             f_host, d_host = fact[: 1 << 22].cpu().numpy(), dim.cpu().numpy()
@@ -318,6 +339,8 @@ def bench_join(args, ctx, dpg, synth, torch, np):
     del dim, out
     torch.cuda.empty_cache()
     return {"workload": "fact 2^28 x 16 B (uint32 fk, Zipf s over 2^24 ids) joined with dimension 2^24 x 64 B; "
+                        "keyed_*: the same join (s = 0) over distinct non-dense uint32 keys, through a hash index "
+                        "of 2^25 slots (auto: DPG lookup, planner's move); "
                         "output 2^28 x 80 B rows", **res}
 
 

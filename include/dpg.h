@@ -297,6 +297,25 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
                            const uint32_t *queries, int64_t n_queries, int32_t *rids,
                            void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream);
 
+/* Foreign-key join over non-dense keys (Sections 4.2.2 and 4.2.3): the
+ * dimension rows carry arbitrary uint32 keys, and `index` is the hash index of
+ * those keys (dpg_hash_build over the dimension's key column, uint32[n_dim],
+ * rid = dimension row, with 2^log2_slots slots).  The join triples come from
+ * a batch lookup of the fact rows' fk column in the index (with DPG unless
+ * algo is DPG_ALGO_DIRECT); fact row i then joins dimension row j_i, the
+ * smallest row holding its key, exactly as dpg_fk_join joins row fk_i (same
+ * output layout, both orders, same algo meaning for the move).  Every fk must
+ * be a key of the index: DPG_ERR_FK_OUT_OF_RANGE otherwise (checked on the
+ * device; the call synchronizes the stream once).  out must not overlap
+ * fact, dim, index or workspace. */
+size_t dpg_key_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
+                                    int64_t n_dim, int32_t dim_bytes, int32_t log2_slots, dpg_join_order order,
+                                    dpg_algo algo);
+dpg_status dpg_key_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
+                        const void *dim, int64_t n_dim, int32_t dim_bytes, const void *index, int32_t log2_slots,
+                        void *out, dpg_join_order order, void *workspace, size_t workspace_bytes, dpg_algo algo,
+                        hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Enhanced B+ tree and batch lookup (Section 4.2.3, batch lookup in B+ tree  */
 /* indexes).  The tree indexes uint32 keys (rid = position in the key array); */

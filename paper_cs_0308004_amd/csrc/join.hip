@@ -213,16 +213,19 @@ static dpg_status extract_fk(dpg_ctx *ctx, const JoinPlan &p, const void *fact, 
     return DPG_OK;
 }
 
+// ids_ready: the dense dimension rows of the fact rows are already in the
+// workspace (fact order: the fk array; dimension order: keys[0], with the
+// fact row numbers in vals[0]) and are not extracted from the fact rows.
 static dpg_status run_join(dpg_ctx *ctx, const JoinPlan &p, const void *fact, const void *dim, void *out,
-                           int check_fk, void *ws, hipStream_t stream) {
+                           int check_fk, void *ws, hipStream_t stream, bool ids_ready = false) {
     if (p.n_fact == 0) return DPG_OK;
     char *w = (char *)ws;
     int32_t *flag = (int32_t *)(w + p.off_flag);
     dpg_status st;
     if (p.order == DPG_JOIN_FACT_ORDER) {
         uint32_t *fk = (uint32_t *)(w + p.off_fk);
-        const bool need_fk = check_fk || p.algo == DPG_ALGO_DPG;
-        if (need_fk) {
+        const bool need_fk = ids_ready || check_fk || p.algo == DPG_ALGO_DPG;
+        if (need_fk && !ids_ready) {
             st = extract_fk(ctx, p, fact, fk, nullptr, stream);
             if (st != DPG_OK) return st;
         }
@@ -244,8 +247,10 @@ static dpg_status run_join(dpg_ctx *ctx, const JoinPlan &p, const void *fact, co
     }
     // DPG-Sort: (fk, i) pairs sorted by fk, stable
     int cur = 0;
-    st = extract_fk(ctx, p, fact, (uint32_t *)(w + p.off_keys[0]), (uint32_t *)(w + p.off_vals[0]), stream);
-    if (st != DPG_OK) return st;
+    if (!ids_ready) {
+        st = extract_fk(ctx, p, fact, (uint32_t *)(w + p.off_keys[0]), (uint32_t *)(w + p.off_vals[0]), stream);
+        if (st != DPG_OK) return st;
+    }
     if (check_fk) {
         bool bad = false;
         st = check_ids(ctx, (const int32_t *)(w + p.off_keys[0]), p.n_fact, p.n_dim, flag, stream, &bad);
@@ -308,4 +313,99 @@ extern "C" dpg_status dpg_fk_join(dpg_ctx *ctx, const void *fact, int64_t n_fact
     }
     if (!ctx) return DPG_ERR_INVALID_ARG;
     return run_join(ctx, p, fact, dim, out, check_fk, workspace, stream);
+}
+
+// ---- foreign-key join over non-dense keys (Sections 4.2.2 and 4.2.3) -------
+// The join triples (k, rid_R, rid_F) come from a batch lookup of the fk
+// column in a hash index over the dimension keys; the dense join above then
+// runs on rid_F.
+namespace dpg {
+
+__global__ __launch_bounds__(256) void k_join_iota(uint32_t *__restrict__ v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) v[i] = (uint32_t)i;
+}
+
+struct KeyJoinPlan {
+    JoinPlan join;
+    size_t off_raw = 0, off_lookup = 0, lookup_bytes = 0, workspace = 0;
+};
+
+static dpg_status make_key_join_plan(const dpg_ctx *ctx, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
+                                     int64_t n_dim, int32_t dim_bytes, int32_t log2_slots, int order, int algo,
+                                     KeyJoinPlan *p) {
+    *p = KeyJoinPlan();
+    if (n_dim > INT32_MAX - 1) return DPG_ERR_INVALID_ARG;
+    dpg_status st = make_join_plan(ctx, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes, order, algo, &p->join);
+    if (st != DPG_OK) return st;
+    p->lookup_bytes = dpg_hash_lookup_workspace_bytes(ctx, n_dim, log2_slots, n_fact, (dpg_algo)algo);
+    if (p->lookup_bytes == 0) return DPG_ERR_INVALID_ARG;
+    p->off_raw = align_up(p->join.workspace);
+    p->off_lookup = align_up(p->off_raw + (size_t)n_fact * 4 + 1);
+    p->workspace = align_up(p->off_lookup + p->lookup_bytes);
+    return DPG_OK;
+}
+
+}  // namespace dpg
+
+extern "C" size_t dpg_key_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_fact, int32_t fact_bytes,
+                                               int32_t fk_offset, int64_t n_dim, int32_t dim_bytes,
+                                               int32_t log2_slots, dpg_join_order order, dpg_algo algo) {
+    KeyJoinPlan p;
+    if (make_key_join_plan(ctx, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes, log2_slots, order, algo, &p) !=
+        DPG_OK)
+        return 0;
+    return p.workspace;
+}
+
+extern "C" dpg_status dpg_key_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t fact_bytes,
+                                   int32_t fk_offset, const void *dim, int64_t n_dim, int32_t dim_bytes,
+                                   const void *index, int32_t log2_slots, void *out, dpg_join_order order,
+                                   void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream) {
+    KeyJoinPlan p;
+    dpg_status st = make_key_join_plan(ctx, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes, log2_slots, order,
+                                       algo, &p);
+    if (st != DPG_OK) return st;
+    const JoinPlan &jp = p.join;
+    if (n_fact > 0 && (!fact || !out)) return DPG_ERR_INVALID_ARG;
+    if (n_dim > 0 && !dim) return DPG_ERR_INVALID_ARG;
+    if (!index || ((uintptr_t)index) % kAlign) return DPG_ERR_INVALID_ARG;
+    if (((uintptr_t)fact | (uintptr_t)dim | (uintptr_t)out) % 4) return DPG_ERR_INVALID_ARG;
+    const size_t fb = (size_t)n_fact * fact_bytes, db = (size_t)n_dim * dim_bytes;
+    const size_t ob = (size_t)n_fact * (fact_bytes + dim_bytes);
+    const size_t ib = dpg_hash_index_bytes(n_dim, log2_slots);
+    if (ranges_overlap(out, ob, fact, fb) || ranges_overlap(out, ob, dim, db) || ranges_overlap(out, ob, index, ib))
+        return DPG_ERR_INVALID_ARG;
+    if (n_fact > 0 && n_dim == 0) return DPG_ERR_FK_OUT_OF_RANGE;
+    if (n_fact > 0) {
+        if (workspace_bytes < p.workspace) return DPG_ERR_WORKSPACE_TOO_SMALL;
+        if (!workspace || ((uintptr_t)workspace) % kAlign != 0) return DPG_ERR_INVALID_ARG;
+        if (ranges_overlap(workspace, p.workspace, out, ob) || ranges_overlap(workspace, p.workspace, fact, fb) ||
+            ranges_overlap(workspace, p.workspace, dim, db) || ranges_overlap(workspace, p.workspace, index, ib))
+            return DPG_ERR_INVALID_ARG;
+    }
+    if (!ctx) return DPG_ERR_INVALID_ARG;
+    if (n_fact == 0) return DPG_OK;
+    char *w = (char *)workspace;
+    uint32_t *raw = (uint32_t *)(w + p.off_raw);
+    const bool fact_order = order == DPG_JOIN_FACT_ORDER;
+    int32_t *rid = (int32_t *)(w + (fact_order ? jp.off_fk : jp.off_keys[0]));
+    // 1. the fk column, then its batch lookup in the index: rid_F per fact row
+    st = extract_fk(ctx, jp, fact, raw, nullptr, stream);
+    if (st != DPG_OK) return st;
+    st = dpg_hash_lookup(ctx, index, n_dim, log2_slots, raw, n_fact, rid, w + p.off_lookup, p.lookup_bytes, algo,
+                         stream);
+    if (st != DPG_OK) return st;
+    // 2. every key must have a dimension row
+    bool bad = false;
+    st = check_ids(ctx, rid, n_fact, n_dim, (int32_t *)(w + jp.off_flag), stream, &bad);
+    if (st != DPG_OK) return st;
+    if (bad) return DPG_ERR_FK_OUT_OF_RANGE;
+    if (!fact_order) {
+        hipLaunchKernelGGL(k_join_iota, dim3((unsigned)((n_fact + 255) / 256)), dim3(256), 0, stream,
+                           (uint32_t *)(w + jp.off_vals[0]), n_fact);
+        DPG_HIP(hipGetLastError());
+    }
+    // 3. the dense join on rid_F
+    return run_join(ctx, jp, fact, dim, out, 0, workspace, stream, /*ids_ready=*/true);
 }

@@ -101,6 +101,9 @@ SIGNATURES = {
     "dpg_hash_build": (_I32, [_VP, _VP, _I64, _I32, _VP, _SZ, _VP, _SZ, _VP]),
     "dpg_hash_lookup_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
     "dpg_hash_lookup": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
+    "dpg_key_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32, _I32]),
+    "dpg_key_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _I32, _VP, _SZ, _I32,
+                            _VP]),
     "dpg_btree_bytes": (_SZ, [_I64]),
     "dpg_btree_levels": (_I32, [_I64]),
     "dpg_btree_level_offset": (_SZ, [_I64, _I32]),
@@ -395,6 +398,31 @@ class Context:
         _check(lib().dpg_hash_lookup(self.handle, _addr(index), n_keys, log2_slots, _addr(queries), m, _addr(rids),
                                      _addr(workspace), workspace.numel(), algo, _stream(stream)), "dpg_hash_lookup")
         return rids
+
+    def key_join_workspace_bytes(self, n_fact: int, fact_bytes: int, fk_offset: int, n_dim: int, dim_bytes: int,
+                                 log2_slots: int, order: int = 0, algo: int = ALGO_AUTO) -> int:
+        return lib().dpg_key_join_workspace_bytes(self.handle, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes,
+                                                  log2_slots, order, algo)
+
+    def key_join(self, fact, dim, fk_offset: int, index, log2_slots: int, order: int = 0, out=None,
+                 algo: int = ALGO_AUTO, workspace=None, stream=None):
+        """Join fact rows to the dimension row holding their fk as a key
+        (index: the hash index of the dimension keys, rid = dimension row)."""
+        import torch
+
+        nf, nd = fact.shape[0], dim.shape[0]
+        fb, db = _rec_bytes(fact), _rec_bytes(dim)
+        if out is None:
+            out = torch.empty((nf, fb + db), dtype=torch.uint8, device=fact.device)
+        if workspace is None:
+            need = self.key_join_workspace_bytes(nf, fb, fk_offset, nd, db, log2_slots, order, algo)
+            if need == 0:
+                raise DPGError(ERR_INVALID_ARG, "dpg_key_join_workspace_bytes")
+            workspace = torch.empty(need, dtype=torch.uint8, device=fact.device)
+        _check(lib().dpg_key_join(self.handle, _addr(fact), nf, fb, fk_offset, _addr(dim), nd, db, _addr(index),
+                                  log2_slots, _addr(out), order, _addr(workspace), workspace.numel(), algo,
+                                  _stream(stream)), "dpg_key_join")
+        return out
 
     # ---- enhanced B+ tree and batch lookup (Section 4.2.3) -------------
     def btree_build(self, keys, stream=None):

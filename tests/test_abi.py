@@ -254,3 +254,21 @@ def test_btree_layout_and_validation():
     assert lib.dpg_btree_lookup(None, T, n, RIDS, 7000, DST, WS, need_q, 9, None) == E.ERR_INVALID_ARG
     assert lib.dpg_btree_lookup(None, T + 64, n, RIDS, 7000, DST, WS, need_q, dpg.ALGO_DPG,
                                 None) == E.ERR_INVALID_ARG  # misaligned tree
+
+
+def test_key_join_validation():
+    lib = dpg.lib()
+    E = dpg
+    need = lib.dpg_key_join_workspace_bytes(None, 5000, 16, 0, 300, 64, 9, dpg.JOIN_FACT_ORDER, dpg.ALGO_DPG)
+    assert need > 5000 * 8
+    assert lib.dpg_key_join_workspace_bytes(None, 5000, 16, 0, 300, 64, 3, 0, dpg.ALGO_DPG) == 0  # slots
+    assert lib.dpg_key_join_workspace_bytes(None, 5000, 16, 2, 300, 64, 9, 0, dpg.ALGO_DPG) == 0  # fk offset
+    assert lib.dpg_key_join_workspace_bytes(None, 5000, 16, 0, 300, 64, 9, 5, dpg.ALGO_DPG) == 0  # order
+    IX, OUT = 0x50000000, 0x60000000
+    call = lambda ix, out, ws, wsb: lib.dpg_key_join(None, SRC, 5000, 16, 0, DST, 300, 64, ix, 9, out,
+                                                      dpg.JOIN_FACT_ORDER, ws, wsb, dpg.ALGO_DPG, None)
+    assert call(IX, OUT, WS, need) == E.ERR_INVALID_ARG            # valid, but no context
+    assert call(IX, OUT, WS, need - 1) == E.ERR_WORKSPACE_TOO_SMALL
+    assert call(IX + 16, OUT, WS, need) == E.ERR_INVALID_ARG       # misaligned index
+    assert call(IX, SRC + 64, WS, need) == E.ERR_INVALID_ARG       # output over the fact rows
+    assert call(IX, OUT, IX, need) == E.ERR_INVALID_ARG            # workspace over the index
