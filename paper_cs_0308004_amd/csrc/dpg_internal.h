@@ -20,6 +20,8 @@
 namespace dpg {
 
 constexpr int kMaxRecBytes = 4096;
+constexpr size_t kProbeWideRegionBytes = 128 * 1024;  // region of the wide LDS probe
+constexpr int kProbeWideChunk = 32768;                // rids per work item of the wide LDS probe
 constexpr size_t kAlign = 256;
 
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -169,6 +171,7 @@ struct RetrievePlan {
     size_t off_part = 0;       // partition scratch (count matrix, bucket offsets)
     int32_t probe_chunk = 0;   // run entries per LDS-probe work item
     bool gather_lds = false;   // Phase III stages each distribute tile in LDS
+    bool probe_wide = false;   // Phase II: the 1024-thread LDS probe for 4/8/16-byte records
     int part_tile = 0;         // rids per partition tile (gather_lds)
     // DIST_SAMPLED: the sample, its sorted copy, its sort scratch, the splitters
     int64_t n_sample = 0;

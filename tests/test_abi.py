@@ -50,8 +50,8 @@ def test_plan_constraints(rec_bytes):
         assert p.n_runs == -(-n // L) and 1 <= p.n_runs <= 8192
         assert p.dist_tile % 64 == 0 and p.n_tiles == -(-n // p.dist_tile)
         assert p.n_tiles * p.n_runs <= max(n, 1024 * 8192) // 4 + 8192
-        if p.probe == dpg.PROBE_LDS:
-            assert L * rec_bytes <= 64 * 1024
+        if p.probe == dpg.PROBE_LDS:  # 128 KiB regions for 4..16-byte records, else 64 KiB
+            assert L * rec_bytes <= (128 if rec_bytes in (4, 8, 16) else 64) * 1024
         # workspace holds the runs, inv and INTERNAL at least
         assert p.workspace_bytes >= n * (8 + rec_bytes)
         assert p.ws_internal + n * rec_bytes <= p.workspace_bytes
@@ -62,9 +62,12 @@ def test_plan_constraints(rec_bytes):
 
 def test_plan_lds_probe_fits():
     lib = dpg.lib()
-    # with a NULL context the default options apply: cached probe
+    # with a NULL context the default options apply: cached probe, except the
+    # wide LDS probe for 4-byte records
     p = dpg.plan_retrieve(1 << 20, 100, 1 << 20, dpg.ALGO_DPG)
     assert p.probe == dpg.PROBE_CACHED
+    p4 = dpg.plan_retrieve(1 << 26, 4, 1 << 26, dpg.ALGO_DPG)
+    assert p4.probe == dpg.PROBE_LDS and p4.log2_run == 15 and p4.distribute == dpg.DIST_PARTITION
     assert lib.dpg_retrieve_workspace_bytes(None, 100, 6, 10, 0) == 0  # rejected shape
 
 
