@@ -78,7 +78,7 @@ constexpr int kProbeWideBatch = 16;
 template <typename E, bool NT>
 __global__ __launch_bounds__(kProbeWideThreads) void k_probe_lds_wide(
     const E *__restrict__ src, int64_t n_src, const int32_t *__restrict__ run, const int32_t *__restrict__ run_off,
-    const int32_t *__restrict__ item_off, int B, int shift, int P, E *__restrict__ internal) {
+    const int32_t *__restrict__ item_off, int B, int shift, int P, E *__restrict__ internal, int src_a16) {
     extern __shared__ __align__(16) char smem[];
     E *region = (E *)smem;
     __shared__ int s_bucket;
@@ -100,12 +100,12 @@ __global__ __launch_bounds__(kProbeWideThreads) void k_probe_lds_wide(
     const int cnt = (int)(k1 - k0);
     const int64_t r0 = (int64_t)b << shift;
     const int rlen = (int)min((int64_t)1 << shift, n_src - r0);
-    // the region: 16-byte loads (the launcher checks src is 16-byte aligned),
-    // then the elements of a ragged tail
+    // the region: 16-byte loads when src_a16 (the source and every region
+    // start are 16-byte aligned), then the elements of a ragged tail
     {
+        const int n16 = src_a16 ? (int)(((int64_t)rlen * sizeof(E)) / 16) : 0;
         const u32x4 *s16 = (const u32x4 *)(src + r0);
         u32x4 *d16 = (u32x4 *)region;
-        const int n16 = (int)(((int64_t)rlen * sizeof(E)) / 16);
 #pragma unroll 4
         for (int e = threadIdx.x; e < n16; e += kProbeWideThreads) d16[e] = s16[e];
         for (int e = n16 * (int)(16 / sizeof(E)) + threadIdx.x; e < rlen; e += kProbeWideThreads)
@@ -139,7 +139,9 @@ static dpg_status launch_probe_wide_t(const RetrievePlan &p, const void *src, vo
     E *internal = (E *)(w + p.off_internal);
     const int P = p.probe_chunk;
     const size_t lds = ((size_t)1 << p.log2_run) * sizeof(E);
-    if (lds > kProbeWideRegionBytes || ((uintptr_t)src) % 16) return DPG_ERR_UNSUPPORTED;
+    if (lds > kProbeWideRegionBytes) return DPG_ERR_UNSUPPORTED;
+    // 16-byte staging when src and every region start are 16-byte aligned
+    const int a16 = ((uintptr_t)src) % 16 == 0 && (((size_t)1 << p.log2_run) * sizeof(E)) % 16 == 0;
     const int B = 1 << p.part_nbits;
     const int64_t grid = p.n_runs + (p.n_rids + P - 1) / P;
     if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
@@ -148,10 +150,10 @@ static dpg_status launch_probe_wide_t(const RetrievePlan &p, const void *src, vo
     if (lds > 64 * 1024) DPG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (nt)
         hipLaunchKernelGGL((k_probe_lds_wide<E, true>), dim3((unsigned)grid), dim3(kProbeWideThreads), lds, stream,
-                           (const E *)src, p.n_src, run, run_off, item_off, B, p.log2_run, P, internal);
+                           (const E *)src, p.n_src, run, run_off, item_off, B, p.log2_run, P, internal, a16);
     else
         hipLaunchKernelGGL((k_probe_lds_wide<E, false>), dim3((unsigned)grid), dim3(kProbeWideThreads), lds, stream,
-                           (const E *)src, p.n_src, run, run_off, item_off, B, p.log2_run, P, internal);
+                           (const E *)src, p.n_src, run, run_off, item_off, B, p.log2_run, P, internal, a16);
     DPG_HIP(hipGetLastError());
     return DPG_OK;
 }

@@ -175,6 +175,8 @@ def _addr(t) -> int:
         return 0
     if isinstance(t, int):
         return t
+    if not t.is_contiguous():
+        raise ValueError("tensors passed to libdpg must be contiguous")
     return t.data_ptr()
 
 

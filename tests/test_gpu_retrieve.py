@@ -316,3 +316,23 @@ def test_two_pass_runs_in_run_order(ctx):
     run = ws.cpu().numpy()[plan.ws_rid_run: plan.ws_rid_run + 4 * m].view(np.int32)
     assert np.all(np.diff(run.astype(np.int64) >> plan.log2_run) >= 0)
     assert np.array_equal(np.sort(run), np.sort(rids))
+
+
+@pytest.mark.parametrize("rec", [4, 8, 16])
+@pytest.mark.parametrize("log2_run", [0, 1, 3])
+def test_lds_probe_unaligned_source(ctx, rec, log2_run):
+    """The LDS probes stage a region with 16-byte loads only when the source
+    and every region start allow it: a source 4 bytes past an aligned address,
+    and runs of 2 or 8 records, take the element-wise path."""
+    n, m = 20001, 30000
+    base = torch.from_numpy(synth.record_bytes(n + 1, rec, seed=rec)).to(DEV)
+    src = base.view(-1)[4: 4 + n * rec].view(n, rec)  # 4 bytes past the allocation
+    rids = torch.from_numpy(synth.rids_uniform(n, m, seed=rec + 1)).to(DEV)
+    want = oracle.retrieve(src.cpu().numpy(), rids.cpu().numpy())
+    configure(ctx, probe=dpg.PROBE_LDS, log2_run=log2_run)
+    try:
+        got = ctx.retrieve(src, rids, algo=dpg.ALGO_DPG)
+        torch.cuda.synchronize()
+    finally:
+        configure(ctx)
+    assert np.array_equal(got.cpu().numpy(), want)
