@@ -83,7 +83,13 @@ typedef enum {
                                (multi-pass DPG, Section 7; probed through the caches) */
     DPG_OPT_GATHER = 7      /* Phase III: 1 INTERNAL read through the caches, 2 a
                                distribute tile's records staged in LDS (used only
-                               with the partition distribute when they fit) */
+                               with the partition distribute when they fit), 3 none:
+                               the distribute also records every rid's list position
+                               and the (cached) probe writes each record straight to
+                               its place in dst -- two-phase DPG, up to 2048 runs,
+                               no INTERNAL (used only with the one-pass partition;
+                               joins treat 3 as automatic).  Automatic picks 3 for
+                               records of whole 64-byte multiples, else 2 or 1 */
 } dpg_option;
 
 typedef struct dpg_ctx dpg_ctx;
@@ -110,8 +116,8 @@ typedef struct {
     int32_t dist_tile;     /* rids per distribute tile */
     int32_t distribute;    /* Phase I form: 1 append, 2 partition, 3 sampled, 4
                               two-pass (DPG only; the values of DPG_OPT_DISTRIBUTE) */
-    int32_t gather;        /* Phase III form: 1 cached, 2 LDS-staged (DPG only;
-                              the values of DPG_OPT_GATHER) */
+    int32_t gather;        /* Phase III form: 1 cached, 2 LDS-staged, 3 none (the
+                              probe scatters; DPG only; the values of DPG_OPT_GATHER) */
     int64_t n_runs;        /* B = ceil(n_src / L), the paper's NUM_RUNS */
     int64_t n_tiles;       /* ceil(n_rids / dist_tile) */
     size_t workspace_bytes;
@@ -123,7 +129,8 @@ typedef struct {
      *                               I); each run in rid-list order with the
      *                               append distribute, in unspecified order
      *                               with the partition distribute
-     *   internal n_rids records     the INTERNAL runs (Phase II)          */
+     *   internal n_rids records     the INTERNAL runs (Phase II; none when
+     *                               the probe scatters: offset 0)          */
     size_t ws_run_off;
     size_t ws_rid_run;
     size_t ws_internal;

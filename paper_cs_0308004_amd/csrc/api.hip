@@ -12,7 +12,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_join_assemble", "k_batch",           "k_part_hist",     "k_part_scatter",   "k_part_hist_wide",
     "k_part_scatter_unstable", "k_gather_lds", "k_hash_home", "k_hash_mark", "k_hash_place",
     "k_hash_ov_off", "k_hash_direct", "k_hash_probe", "k_hash_probe_lds", "k_smj_keys", "k_smj_ranges",
-    "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds"};
+    "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds", "k_probe_scatter"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 
@@ -58,6 +58,7 @@ static dpg_status distribute_and_probe(dpg_ctx *ctx, const RetrievePlan &p, cons
 
 dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void *src, const int32_t *rids,
                                 void *ws, hipStream_t stream, bool local_inv) {
+    if (p.scatter) return DPG_ERR_UNSUPPORTED;  // no INTERNAL to hand over
     dpg_status st = distribute_and_probe(ctx, p, src, rids, ws, stream, local_inv);
     if (st != DPG_OK || p.dist_mode != DIST_TWO_PASS) return st;
     // callers that fuse Phase III need one slot per rid: inv = inv_c o inv_f
@@ -74,6 +75,15 @@ dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, co
         return launch_gather(ctx, K_DIRECT_GATHER, src, p.n_src, rids, dst, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M,
                              stream);
     char *w = (char *)ws;
+    if (p.scatter) {
+        // two phases: distribute (runs and list positions), then the probe
+        // writes each record straight to dst[pos]
+        dpg_status st = launch_distribute(ctx, p, rids, ws, stream, false);
+        if (st != DPG_OK) return st;
+        const int32_t *n_valid = (const int32_t *)(w + p.off_bucket) + (1 << p.part_nbits);
+        return launch_probe_scatter(ctx, src, p.n_src, (const int32_t *)(w + p.off_run),
+                                    (const int32_t *)(w + p.off_inv), n_valid, dst, p.n_rids, p.rec_bytes, stream);
+    }
     if (p.dist_mode == DIST_TWO_PASS) {
         // Phase III in two passes, coarse first: u[j] = INTERNAL[inv_c[j]] in
         // the fine pass's order, then dst[i] = u[inv_f[i]]; each pass reads
@@ -176,7 +186,7 @@ dpg_status dpg_set_option(dpg_ctx *ctx, dpg_option option, int64_t value) {
             ctx->opt_distribute = value;
             return DPG_OK;
         case DPG_OPT_GATHER:
-            if (value > 2) return DPG_ERR_INVALID_ARG;
+            if (value > 3) return DPG_ERR_INVALID_ARG;
             ctx->opt_gather = value;
             return DPG_OK;
     }

@@ -107,6 +107,118 @@ DPG_GATHER_KERNEL(k_probe_cached)
 DPG_GATHER_KERNEL(k_gather_phase)
 #undef DPG_GATHER_KERNEL
 
+// Two-phase DPG (the probe scatters): dst[pos[k]] = src[run[k]] for k in run
+// order.  The same flattened tile as the gather, with the tile's positions
+// staged beside its indices; only the first *n_valid entries are live (the
+// distribute drops invalid rids), and a position outside [0, n_dst) is skipped.
+template <typename E, int WE, bool NT>
+__global__ __launch_bounds__(256) void k_probe_scatter(const E *__restrict__ src, const int32_t *__restrict__ run,
+                                                       const int32_t *__restrict__ pos,
+                                                       const int32_t *__restrict__ n_valid, E *__restrict__ dst,
+                                                       int64_t n_dst, int64_t limit, int we_rt, uint32_t magic,
+                                                       int tile_rt, int remap) {
+    extern __shared__ int32_t s_tab[];
+    using S = GatherShape<E, WE>;
+    constexpr int PER = S::PER;
+    const int we = WE > 0 ? WE : we_rt;
+    const int tile = WE > 0 ? S::TILE : tile_rt;
+    int32_t *s_run = s_tab, *s_pos = s_tab + tile;
+    const int64_t t = xcd_tile(blockIdx.x, gridDim.x, remap);
+    const int64_t base = t * tile;
+    const int64_t live = min((int64_t)*n_valid, n_dst);
+    const int cnt = (int)min((int64_t)tile, live - base);
+    if (cnt <= 0) return;
+#pragma unroll 8
+    for (int j = threadIdx.x; j < cnt; j += 256) {
+        const int32_t r = run[base + j];
+        const int32_t q = pos[base + j];
+        s_run[j] = (r >= 0 && (int64_t)r < limit) ? r : 0;
+        s_pos[j] = (q >= 0 && (int64_t)q < n_dst) ? q : -1;
+    }
+    __syncthreads();
+    const int total = cnt * we;
+    int64_t off[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = min(threadIdx.x + k * 256, total - 1);
+        int j;
+        if constexpr (WE > 0) j = e / WE;
+        else j = (int)__umulhi((uint32_t)e, magic);
+        off[k] = (int64_t)s_run[j] * we + (e - j * we);
+    }
+    E v[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) v[k] = src[off[k]];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * 256;
+        if (e < total) {
+            int j;
+            if constexpr (WE > 0) j = e / WE;
+            else j = (int)__umulhi((uint32_t)e, magic);
+            const int32_t q = s_pos[j];
+            if (q >= 0) {
+                E *o = dst + (int64_t)q * we + (e - j * we);
+                if constexpr (NT) __builtin_nontemporal_store(v[k], o);
+                else *o = v[k];
+            }
+        }
+    }
+}
+
+template <typename E, int WE>
+static dpg_status launch_scatter_t(const void *src, const int32_t *run, const int32_t *pos, const int32_t *n_valid,
+                                   void *dst, int64_t n, int64_t limit, int we, int remap, bool nt,
+                                   hipStream_t stream) {
+    using S = GatherShape<E, WE>;
+    int tile;
+    uint32_t magic = 0;
+    if constexpr (WE > 0) {
+        tile = S::TILE;
+    } else {
+        tile = aligned_tile((256 * S::PER) / we, we * (int)sizeof(E));
+        if (tile < 1 || we < 2) return DPG_ERR_UNSUPPORTED;
+        magic = (uint32_t)((0x100000000ull + (uint64_t)we - 1) / (uint64_t)we);
+    }
+    const int64_t grid = (n + tile - 1) / tile;
+    if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
+    const size_t lds = 2 * (size_t)tile * sizeof(int32_t);
+    if (nt)
+        hipLaunchKernelGGL((k_probe_scatter<E, WE, true>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src,
+                           run, pos, n_valid, (E *)dst, n, limit, we, magic, tile, remap);
+    else
+        hipLaunchKernelGGL((k_probe_scatter<E, WE, false>), dim3((unsigned)grid), dim3(256), lds, stream,
+                           (const E *)src, run, pos, n_valid, (E *)dst, n, limit, we, magic, tile, remap);
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
+dpg_status launch_probe_scatter(dpg_ctx *ctx, const void *src, int64_t limit, const int32_t *run, const int32_t *pos,
+                                const int32_t *n_valid, void *dst, int64_t n, int rec_bytes, hipStream_t stream) {
+    if (n <= 0) return DPG_OK;
+    const double M = (double)n, R = rec_bytes;
+    ProfScope prof(ctx, K_PROBE_SCATTER, 8.0 * M + 2.0 * R * M, stream);
+    const int remap = xcd_remap_flag(ctx);
+    // the same rule as the gather: streaming stores for outputs larger than
+    // the Infinity Cache
+    const bool nt = (double)n * rec_bytes > kStreamingStoreBytes;
+    const uintptr_t al = (uintptr_t)src | (uintptr_t)dst;
+    if (rec_bytes % 16 == 0 && al % 16 == 0) {
+        const int we = rec_bytes / 16;
+        if (we == 1) return launch_scatter_t<u32x4, 1>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+        return launch_scatter_t<u32x4, 0>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+    }
+    if (rec_bytes % 8 == 0 && al % 8 == 0) {
+        const int we = rec_bytes / 8;
+        if (we == 1) return launch_scatter_t<u32x2, 1>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+        return launch_scatter_t<u32x2, 0>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+    }
+    const int we = rec_bytes / 4;
+    if (we == 1) return launch_scatter_t<uint32_t, 1>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+    if (we == 25) return launch_scatter_t<uint32_t, 25>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+    return launch_scatter_t<uint32_t, 0>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
+}
+
 template <typename E, int WE>
 static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx, void *dst, int64_t n,
                                   int64_t limit, int we, int remap, hipStream_t stream) {

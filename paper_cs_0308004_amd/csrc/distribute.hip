@@ -184,6 +184,13 @@ dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t 
     if (local_inv && p.dist_mode != DIST_PARTITION && p.dist_mode != DIST_SAMPLED) return DPG_ERR_UNSUPPORTED;
     if (p.dist_mode == DIST_SAMPLED) return launch_distribute_sampled(ctx, p, rids, w, stream, local_inv);
     if (p.dist_mode == DIST_TWO_PASS) return launch_distribute_two_pass(ctx, p, rids, w, stream);
+    if (p.dist_mode == DIST_PARTITION && p.scatter) {
+        // two-phase DPG: the runs, and beside each rid its list position
+        const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+        return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, nullptr, p.log2_run,
+                                (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0, /*stable=*/false,
+                                false, 1u, nullptr, 0, (uint32_t *)(w + p.off_inv));
+    }
     if (p.dist_mode == DIST_PARTITION) {
         const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
         int32_t *item_off = p.probe == DPG_PROBE_LDS ? (int32_t *)(w + p.off_items) : nullptr;

@@ -75,6 +75,7 @@ enum KernelId {
     K_BT_DIRECT,         // B+ tree batch lookup, one root-to-leaf walk per query
     K_BT_PROBE,          //   DPG Phase II, walks over one run's subtrees through the caches
     K_BT_PROBE_LDS,      //   the same with the run's leaves staged in LDS
+    K_PROBE_SCATTER,     // two-phase DPG: Phase II writes each record to its place in dst
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -172,6 +173,7 @@ struct RetrievePlan {
     int32_t probe_chunk = 0;   // run entries per LDS-probe work item
     bool gather_lds = false;   // Phase III stages each distribute tile in LDS
     bool probe_wide = false;   // Phase II: the 1024-thread LDS probe for 4/8/16-byte records
+    bool scatter = false;      // two phases: the probe writes dst[pos] directly (no INTERNAL, no gather)
     int part_tile = 0;         // rids per partition tile (gather_lds)
     // DIST_SAMPLED: the sample, its sorted copy, its sort scratch, the splitters
     int64_t n_sample = 0;
@@ -185,8 +187,10 @@ struct RetrievePlan {
 
 dpg_status validate_records(int64_t n, int32_t rec_bytes, const void *ptr, bool need_ptr);
 bool ranges_overlap(const void *a, size_t an, const void *b, size_t bn);
+// allow_scatter = false (callers that need INTERNAL and the slots, such as
+// the joins): DPG_OPT_GATHER = 3 is treated as automatic.
 dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
-                              int64_t n_rids, int algo, RetrievePlan *plan);
+                              int64_t n_rids, int algo, RetrievePlan *plan, bool allow_scatter = true);
 // The same with every choice explicit (0 = automatic), ignoring options and
 // the tuning table; algo must be DIRECT or DPG.
 dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo, int probe,
@@ -231,6 +235,9 @@ dpg_status check_ids(dpg_ctx *ctx, const int32_t *ids, int64_t n, int64_t limit,
 // ---- kernel launchers (copy.hip) ----
 // dst[k] = src[idx[k]] (records of rec_bytes) for k in [0, n).
 // An index outside [0, limit) copies record 0 (never an out-of-bounds access).
+// dst[pos[k]] = src[run[k]] for k < min(*n_valid, n) (device count).
+dpg_status launch_probe_scatter(dpg_ctx *ctx, const void *src, int64_t limit, const int32_t *run, const int32_t *pos,
+                                const int32_t *n_valid, void *dst, int64_t n, int rec_bytes, hipStream_t stream);
 dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t limit, const int32_t *idx,
                          void *dst, int64_t n, int rec_bytes, double alg_bytes, hipStream_t stream);
 dpg_status launch_fill_i32(dpg_ctx *ctx, int32_t *p, int64_t n, int32_t value, hipStream_t stream);

@@ -177,7 +177,7 @@ static dpg_status make_join_plan(const dpg_ctx *ctx, int64_t n_fact, int32_t fac
     // the moved relation: dimension rows (DPG-Move) or fact rows (DPG-Sort)
     const int64_t n_src = order == DPG_JOIN_FACT_ORDER ? n_dim : n_fact;
     const int rec = order == DPG_JOIN_FACT_ORDER ? dim_bytes : fact_bytes;
-    dpg_status st = make_retrieve_plan(ctx, n_src, rec, n_fact, algo, &p->ret);
+    dpg_status st = make_retrieve_plan(ctx, n_src, rec, n_fact, algo, &p->ret, /*allow_scatter=*/false);
     if (st != DPG_OK) return st;
     p->algo = p->ret.algo;
     p->fk_bits = n_dim > 1 ? bit_length((uint64_t)(n_dim - 1)) : 1;

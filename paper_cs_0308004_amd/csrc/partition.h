@@ -10,6 +10,7 @@ constexpr int kMaxDigitBits = 8;                    // stable passes
 constexpr int kMaxDigitBuckets = 1 << kMaxDigitBits;
 constexpr int kMaxWideBits = 12;                    // unstable uint32 passes (the DPG distribute)
 constexpr int kMaxWideBuckets = 1 << kMaxWideBits;
+constexpr size_t kMaxPartitionLds = 160 * 1024;  // LDS of one workgroup
 
 struct PartPlan {
     int64_t n = 0;
@@ -39,6 +40,10 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val);
 // instead the number of the n_split ascending splitters below it (device
 // array, n_split < 2^nbits), i.e. bucket b holds the keys in
 // (split[b-1], split[b]].
+// idx_out (unstable passes only; may be null) receives, beside each output
+// key, the input position of its element; the tile is then staged in LDS
+// twice over, which needs the digit tables small enough (up to 2^11 digits
+// for the wide pass).
 // key_mul (unstable uint32 passes only): every key is first multiplied by it
 // (mod 2^32), and the products are what is partitioned and written out.  inv (may be
 // null) receives the output position of every input element (0 if invalid).
@@ -51,7 +56,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
                             int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true,
                             bool local_inv = false, uint32_t key_mul = 1, const uint32_t *split = nullptr,
-                            int n_split = 0);
+                            int n_split = 0, uint32_t *idx_out = nullptr);
 
 // Exclusive scan of a[0..n) in place; *total = the sum (device).  scratch:
 // scan_1d_scratch_bytes(n).

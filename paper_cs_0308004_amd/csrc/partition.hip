@@ -316,7 +316,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     const uint32_t *__restrict__ keys, int64_t n, int shift, int nbits, uint64_t limit, int64_t nT,
     const int32_t *__restrict__ off, uint32_t *__restrict__ keys_out, int32_t *__restrict__ inv, int local_inv,
     uint32_t key_mul, int remap, const uint32_t *__restrict__ split, const int32_t *__restrict__ cell_lo,
-    int n_split) {
+    int n_split, uint32_t *__restrict__ idx_out) {
     constexpr int T = THREADS * PER;
     constexpr int W = THREADS / 64;
     extern __shared__ __align__(16) char smem[];
@@ -326,6 +326,8 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     int32_t *s_glob = s_cnt + nb;                               // output start of each digit for this tile
     SplitLds sp;  // splitters, if any, after the digit tables
     if constexpr (SPLIT) sp = stage_splitters((uint32_t *)(s_glob + nb), split, cell_lo, n_split);
+    // the input position of every element of the tile, when idx_out is given
+    uint32_t *s_idx = (uint32_t *)(s_glob + nb) + (SPLIT ? n_split + kSplitCells + 1 : 0);
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_nvalid;
     const uint32_t mask = (uint32_t)nb - 1;
@@ -392,6 +394,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
         if (rank[k] >= 0) {
             const uint32_t d = SPLIT ? bkt[k] : digit_of(key[k], shift, mask);
             s_key[s_cnt[d] + rank[k]] = key[k];
+            if (idx_out) s_idx[s_cnt[d] + rank[k]] = (uint32_t)(base + e);
             if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rank[k];
         } else if (inv && e < cnt) {
             inv[base + e] = 0;
@@ -402,7 +405,9 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     for (int j = threadIdx.x; j < nvalid; j += THREADS) {
         const uint32_t k = s_key[j];
         const uint32_t d = bucket_of<SPLIT>(k, shift, mask, sp);
-        keys_out[(int64_t)s_glob[d] + (j - s_cnt[d])] = k;
+        const int64_t pos = (int64_t)s_glob[d] + (j - s_cnt[d]);
+        keys_out[pos] = k;
+        if (idx_out) idx_out[pos] = s_idx[j];
     }
 }
 
@@ -458,7 +463,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
                             int item_chunk, bool stable, bool local_inv, uint32_t key_mul, const uint32_t *split,
-                            int n_split) {
+                            int n_split, uint32_t *idx_out) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -475,6 +480,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     const int nb = 1 << p.nbits;
     if (!split) n_split = 0;
     if (split && (stable || p.key_bytes != 4 || p.has_val || n_split < 0 || n_split >= nb)) return DPG_ERR_UNSUPPORTED;
+    if (idx_out && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
     const size_t split_lds = split_lds_bytes(n_split, split != nullptr);
     const int32_t *cells = (const int32_t *)(w + p.off_cells);
     if (split) {
@@ -519,7 +525,9 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
                                                     remap, stream);
     if (!stable) {
-        const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb + split_lds;
+        const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb + split_lds +
+                           (idx_out ? sizeof(uint32_t) * p.tile : 0);
+        if (lds + 1024 > kMaxPartitionLds) return DPG_ERR_UNSUPPORTED;
         if (wide) {
             const void *fn = split ? (const void *)k_part_scatter_unstable<1024, 16, true>
                                    : (const void *)k_part_scatter_unstable<1024, 16, false>;
@@ -528,14 +536,19 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
             hipLaunchKernelGGL((split ? k_part_scatter_unstable<1024, 16, true> : k_part_scatter_unstable<1024, 16, false>),
                                dim3((unsigned)p.n_tiles), dim3(1024), lds, stream, (const uint32_t *)keys_in, p.n,
                                shift, p.nbits, limit, p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0,
-                               key_mul, remap, split, cells, n_split);
+                               key_mul, remap, split, cells, n_split, idx_out);
         } else {
             if (p.per != 32 || p.threads != kPartThreads) return DPG_ERR_UNSUPPORTED;
+            if (lds > 64 * 1024) {
+                const void *fn = split ? (const void *)k_part_scatter_unstable<kPartThreads, 32, true>
+                                       : (const void *)k_part_scatter_unstable<kPartThreads, 32, false>;
+                DPG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            }
             hipLaunchKernelGGL((split ? k_part_scatter_unstable<kPartThreads, 32, true>
                                       : k_part_scatter_unstable<kPartThreads, 32, false>),
                                dim3((unsigned)p.n_tiles), dim3(kPartThreads), lds, stream, (const uint32_t *)keys_in,
                                p.n, shift, p.nbits, limit, p.n_tiles, cnt, (uint32_t *)keys_out, inv,
-                               local_inv ? 1 : 0, key_mul, remap, split, cells, n_split);
+                               local_inv ? 1 : 0, key_mul, remap, split, cells, n_split, idx_out);
         }
         DPG_HIP(hipGetLastError());
         return DPG_OK;

@@ -26,6 +26,9 @@ namespace dpg {
 
 constexpr int64_t kMaxRuns = 8192;
 constexpr int64_t kMaxTwoPassRuns = (int64_t)1 << 20;  // 12 fine bits x 8 coarse bits
+// the partition pass that also records every rid's list position stages the
+// tile twice in LDS, which leaves room for 2^11 digits
+constexpr int64_t kMaxScatterRuns = 2048;
 constexpr size_t kLdsRegionBytes = 64 * 1024;
 constexpr size_t kCachedRegionBytes = 4 << 20;
 
@@ -89,8 +92,8 @@ static void layout_workspace(RetrievePlan *p) {
             p->off_items = take((size_t)(B + 1) * 4);
         }
         p->off_run = take((size_t)M * 4);
-        p->off_inv = take((size_t)M * 4);
-        p->off_internal = take((size_t)M * p->rec_bytes);
+        p->off_inv = take((size_t)M * 4);  // slots, or list positions when the probe scatters
+        p->off_internal = take(p->scatter ? 0 : (size_t)M * p->rec_bytes);
     }
     p->workspace = off;
 }
@@ -115,7 +118,17 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     // and III more -- net 4% faster at 4 bytes, 25% slower at 8 bytes.
     const bool small = R == 4 || R == 8 || R == 16;
     const int lg_wide = floor_log2(kProbeWideRegionBytes / (size_t)R);
-    const bool want_wide = small && dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_CACHED &&
+    // Phase III form 3: no INTERNAL and no gather; the cached probe writes
+    // each record to its place in dst (two-phase DPG).  Chosen by default for
+    // records of whole 64-byte sectors, whose scattered writes fill whole
+    // sectors: at 2^26 rids 2.84 / 4.00 / 7.29 ms against 3.53 / 6.73 / 12.28
+    // for the three-phase form at 64 / 128 / 256 bytes.  Scattered records
+    // that end mid-sector are far slower (8.3 ms against 5.7 at 100 bytes).
+    // gather = -1: automatic without this form (callers that need INTERNAL).
+    const bool sector_rows = R >= 64 && R % 64 == 0;
+    const bool want_scatter = (gather == 3 || (gather == 0 && sector_rows)) && !sampled && !two_pass &&
+                              dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_LDS;
+    const bool want_wide = !want_scatter && small && dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_CACHED &&
                            (probe == DPG_PROBE_LDS || R == 4) && (log2_run <= 0 || log2_run <= lg_wide) &&
                            ((N + ((int64_t)1 << lg_wide) - 1) >> lg_wide) <= kMaxWideBuckets;
     if (probe == DPG_PROBE_AUTO) probe = want_wide ? DPG_PROBE_LDS : DPG_PROBE_CACHED;
@@ -136,6 +149,7 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     // distribute (its count matrix then stays at a quarter of the rid list):
     // lengthen the runs if needed
     const int64_t max_runs = two_pass ? kMaxTwoPassRuns
+                             : want_scatter ? kMaxScatterRuns
                              : sampled ? kMaxWideBuckets
                              : (dist_mode == 1 || log2_run > 0) ? kMaxRuns : kMaxWideBuckets;
     while (((N + ((int64_t)1 << lg) - 1) >> lg) > max_runs) ++lg;
@@ -193,6 +207,10 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
         p->part_tile = p->dist_tile;
     }
     p->probe_wide = probe == DPG_PROBE_LDS && want_wide && p->dist_mode == DIST_PARTITION;
+    if (want_scatter && p->dist_mode == DIST_PARTITION) {
+        p->scatter = true;
+        p->gather_lds = false;
+    }
     if (probe == DPG_PROBE_LDS && want_wide && !p->probe_wide && lg > lg_lds) {
         probe = DPG_PROBE_CACHED;  // the narrow LDS probe cannot hold this region
         p->probe = probe;
@@ -298,13 +316,14 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
 }
 
 dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids, int algo,
-                              RetrievePlan *p) {
+                              RetrievePlan *p, bool allow_scatter) {
     if (algo < DPG_ALGO_AUTO || algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
     int probe = ctx ? (int)ctx->opt_probe : 0;
     int log2_run = ctx ? (int)ctx->opt_log2_run : 0;
     int dist_tile = ctx ? (int)ctx->opt_dist_tile : 0;
     int dist_mode = ctx ? (int)ctx->opt_distribute : 0;
-    const int gather = ctx ? (int)ctx->opt_gather : 0;
+    int gather = ctx ? (int)ctx->opt_gather : 0;
+    if (!allow_scatter && (gather == 3 || gather == 0)) gather = -1;
     if (algo == DPG_ALGO_AUTO) {
         // Measured on MI355X (2^26 records): direct retrieval is faster at every
         // record size from 8 to 256 bytes, so it is the default unless the
@@ -339,14 +358,14 @@ extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32
     out->log2_run = p.log2_run;
     out->dist_tile = p.dist_tile;
     out->distribute = p.algo == DPG_ALGO_DPG ? dpg::dist_option_value(p.dist_mode) : 0;
-    out->gather = p.algo == DPG_ALGO_DPG ? (p.gather_lds ? 2 : 1) : 0;
+    out->gather = p.algo == DPG_ALGO_DPG ? (p.scatter ? 3 : p.gather_lds ? 2 : 1) : 0;
     out->n_runs = p.n_runs;
     out->n_tiles = p.n_tiles;
     out->workspace_bytes = p.workspace;
     if (p.algo == DPG_ALGO_DPG && n_rids > 0) {
         out->ws_run_off = p.dist_mode == dpg::DIST_TWO_PASS ? 0 : p.off_bucket;
         out->ws_rid_run = p.off_run;
-        out->ws_internal = p.off_internal;
+        out->ws_internal = p.scatter ? 0 : p.off_internal;
     }
     return DPG_OK;
 }

@@ -21,7 +21,7 @@ JOIN_FACT_ORDER, JOIN_DIM_ORDER = 0, 1
 PROBE_AUTO, PROBE_CACHED, PROBE_LDS = 0, 1, 2
 OPT_LOG2_RUN, OPT_PROBE, OPT_DIST_TILE, OPT_XCD_REMAP, OPT_USE_TUNED, OPT_DISTRIBUTE, OPT_GATHER = 1, 2, 3, 4, 5, 6, 7
 DIST_AUTO, DIST_APPEND, DIST_PARTITION, DIST_SAMPLED, DIST_TWO_PASS = 0, 1, 2, 3, 4
-GATHER_AUTO, GATHER_CACHED, GATHER_LDS = 0, 1, 2
+GATHER_AUTO, GATHER_CACHED, GATHER_LDS, GATHER_NONE = 0, 1, 2, 3  # NONE: the probe scatters (two-phase DPG)
 
 _VP, _I32, _I64, _SZ, _DBL = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
 

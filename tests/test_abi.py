@@ -52,9 +52,14 @@ def test_plan_constraints(rec_bytes):
         assert p.n_tiles * p.n_runs <= max(n, 1024 * 8192) // 4 + 8192
         if p.probe == dpg.PROBE_LDS:  # 128 KiB regions for 4..16-byte records, else 64 KiB
             assert L * rec_bytes <= (128 if rec_bytes in (4, 8, 16) else 64) * 1024
-        # workspace holds the runs, inv and INTERNAL at least
-        assert p.workspace_bytes >= n * (8 + rec_bytes)
-        assert p.ws_internal + n * rec_bytes <= p.workspace_bytes
+        # workspace holds the runs, the slots (or list positions) and INTERNAL,
+        # which the two-phase form (Phase III "none") does without
+        assert p.gather in (1, 2, 3) and (p.gather == 3) == (rec_bytes % 64 == 0)
+        assert p.workspace_bytes >= n * (8 + (0 if p.gather == 3 else rec_bytes))
+        if p.gather == 3:
+            assert p.ws_internal == 0
+        else:
+            assert p.ws_internal + n * rec_bytes <= p.workspace_bytes
         assert p.ws_rid_run + 4 * n <= p.workspace_bytes
         d = dpg.plan_retrieve(n, rec_bytes, n, dpg.ALGO_DIRECT)
         assert d.algo == dpg.ALGO_DIRECT and d.workspace_bytes == 256
@@ -149,14 +154,20 @@ def test_batch_validation_without_device():
 
 def test_plan_phase_forms():
     """The planner's Phase I / Phase III forms: one partition pass for up to
-    4096 runs; Phase III staged in LDS for 4-, 8- and 16-byte records."""
+    4096 runs; Phase III staged in LDS for 4-, 8- and 16-byte records; no
+    Phase III (the probe scatters, at most 2048 runs) for whole 64-byte
+    sectors; the cached gather otherwise."""
     for rec in (4, 8, 16):
         p = dpg.plan_retrieve(1 << 26, rec, 1 << 26, dpg.ALGO_DPG)
         assert p.distribute == dpg.DIST_PARTITION and p.gather == dpg.GATHER_LDS, rec
-    for rec in (12, 32, 100, 256):
+    for rec in (12, 32, 100, 96):
         p = dpg.plan_retrieve(1 << 26, rec, 1 << 26, dpg.ALGO_DPG)
         assert p.distribute == dpg.DIST_PARTITION and p.gather == dpg.GATHER_CACHED, rec
         assert p.n_runs <= 4096
+    for rec in (64, 128, 256, 4096):
+        p = dpg.plan_retrieve(1 << 26, rec, 1 << 26, dpg.ALGO_DPG)
+        assert p.distribute == dpg.DIST_PARTITION and p.gather == dpg.GATHER_NONE, rec
+        assert p.n_runs <= 2048 and p.ws_internal == 0
     p = dpg.plan_retrieve(1 << 26, 8, 1 << 26, dpg.ALGO_DIRECT)
     assert p.distribute == 0 and p.gather == 0
 

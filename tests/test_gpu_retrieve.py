@@ -66,6 +66,9 @@ VARIANTS = {
     "dpg-lds-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_PARTITION, gather=2)),
     "dpg-lds-gather-wide": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=3, dist=dpg.DIST_PARTITION,
                                                gather=2)),
+    # two phases: the probe writes every record to its place in dst
+    "dpg-scatter": (dpg.ALGO_DPG, dict(gather=dpg.GATHER_NONE)),
+    "dpg-scatter-short-runs": (dpg.ALGO_DPG, dict(gather=dpg.GATHER_NONE, log2_run=6)),
     # skew-balanced runs from a sorted sample (Section 2.3)
     "dpg-sampled": (dpg.ALGO_DPG, dict(dist=dpg.DIST_SAMPLED)),
     "dpg-sampled-short-runs": (dpg.ALGO_DPG, dict(dist=dpg.DIST_SAMPLED, log2_run=3)),
@@ -164,7 +167,8 @@ def test_phase_products_match_figure1(ctx):
                                                (50000, 50000, 8, "same", dpg.PROBE_CACHED, 4, 2)]:
         src = synth.record_bytes(n, rec, seed=n)
         rids = make_rids(kind, n, m, rec, seed=n)
-        configure(ctx, probe=probe, log2_run=lg, dist=dist)
+        # INTERNAL is the product checked here: a Phase III that reads it
+        configure(ctx, probe=probe, log2_run=lg, dist=dist, gather=dpg.GATHER_CACHED)
         try:
             plan = ctx.plan_retrieve(n, rec, m, dpg.ALGO_DPG)
             ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=DEV)
