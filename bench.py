@@ -174,7 +174,8 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         best, tuned_ms = ctx.autotune_retrieve(src, rids, dst, reps=2, dpg_only=True)
         tuned = {"ms": round(tuned_ms, 4), "log2_run": best.log2_run, "n_runs": best.n_runs,
                  "probe": {1: "cached", 2: "lds"}.get(best.probe, "?"),
-                 "distribute": {1: "append", 2: "partition"}.get(best.distribute, "?")}
+                 "distribute": {1: "append", 2: "partition", 3: "sampled", 4: "two-pass"}.get(best.distribute, "?"),
+                 "gather": {1: "cached", 2: "lds", 3: "none (probe scatters)"}.get(best.gather, "?")}
         ctx.tune_clear()
     plan = ctx.plan_retrieve(n, R, m, dpg.ALGO_DPG)
     ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
@@ -220,8 +221,9 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
             "workload": f"DPG record retrieval, N=M=2^{args.log2n}, {R}-byte records, rids {args.pattern}",
             "n_src": n, "n_rids": m, "rec_bytes": R, "rid_pattern": args.pattern,
             "algo": "dpg", "log2_run": plan.log2_run, "n_runs": plan.n_runs, "dist_tile": plan.dist_tile,
-            "distribute": {1: "append", 2: "partition"}.get(plan.distribute, "?"),
+            "distribute": {1: "append", 2: "partition", 3: "sampled", 4: "two-pass"}.get(plan.distribute, "?"),
             "probe": {1: "cached", 2: "lds"}.get(plan.probe, "?"),
+            "gather": {1: "cached", 2: "lds", 3: "none (probe scatters)"}.get(plan.gather, "?"),
             "autotuned": tuned,
         },
         "roofline": roofline_entry(prof_dpg, dpg_kernels, counters, wkey),
