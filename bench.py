@@ -213,7 +213,8 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     # counter data apply only to the same shape and DPG plan
     wkey = f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}:dist{plan.distribute}"
     dpg_kernels = ["k_part_hist", "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable", "k_dist_hist",
-                   "k_dist_scatter", "k_probe_cached", "k_probe_lds", "k_gather_phase", "k_gather_lds"]
+                   "k_dist_scatter", "k_probe_cached", "k_probe_lds", "k_gather_phase", "k_gather_lds",
+                   "k_probe_scatter"]
     out = {
         "value": round(delivered / (ms_dpg * 1e-3) / 1e9, 2),
         "ms_per_step": round(ms_dpg, 4),
