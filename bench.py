@@ -238,6 +238,19 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         "kernels_ms_per_step": {k: round(v["ms"] / v["launches"], 4) for k, v in prof_dpg.items()},
         "wall_s_timed": round(wall_dpg, 4),
     }
+    # the problem's floor for any method, B_min = 4M + R * (records touched) +
+    # R * M, over each method's whole step; and a plain device copy of 4 GiB
+    # as the practical read + write ceiling
+    touched = int(torch.unique(rids).numel()) if args.pattern == "uniform" else min(n, m)
+    b_min = 4.0 * m + R * touched + R * m
+    out["eta_min"] = {"bytes": b_min, "dpg": round(b_min / (ms_dpg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
+                      "direct": round(b_min / (ms_direct * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    a = torch.empty(1 << 32, dtype=torch.uint8, device=dev).fill_(1)
+    b = torch.empty_like(a)
+    copy_ms, _ = time_steps(lambda: b.copy_(a), 5, 1, torch)
+    out["copy_ceiling"] = {"GB_per_s": round(2.0 * a.numel() / (copy_ms * 1e-3) / 1e9, 1),
+                           "what": "torch copy_ of 4 GiB device to device (reads and writes 4 GiB)"}
+    del a, b
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
