@@ -257,7 +257,7 @@ def test_full_size_headline_config(ctx, algo):
     torch.cuda.empty_cache()
 
 
-def test_config1_full_oracle(ctx):
+def test_2p20_records_of_100B_full_oracle(ctx):
     """2^20 records of 100 B, random permutation: every output byte vs the oracle."""
     n, rec = 1 << 20, 100
     seed = synth.SEED_BASE
