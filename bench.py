@@ -317,10 +317,16 @@ def bench_join(args, ctx, dpg, synth, torch, np):
             for algo, aname in ((dpg.ALGO_DPG, "dpg"), (dpg.ALGO_DIRECT, "direct")):
                 ws = torch.empty(max(1, ctx.fk_join_workspace_bytes(n_fact, 16, 0, n_dim, 64, order, algo)),
                                  dtype=torch.uint8, device=dev)
+                ctx.profile_enable(True)
+                ctx.profile_reset()
                 ms, _ = time_steps(lambda: ctx.fk_join(fact, dim, 0, order, out=out, algo=algo, workspace=ws),
                                    steps, 1, torch)
+                prof = ctx.profile_collect()
+                ctx.profile_enable(False)
+                ctx.profile_reset()
                 res[f"zipf{s}_{oname}_{aname}"] = {"ms": round(ms, 3),
-                                                   "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
+                                                   "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2),
+                                                   "roofline": roofline_entry(prof, list(prof), None)}
                 del ws
         if s == 0.0:
             # the same join over non-dense keys: dimension keys are distinct
