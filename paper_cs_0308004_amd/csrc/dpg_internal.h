@@ -219,6 +219,12 @@ dpg_status run_distribute_probe(dpg_ctx *ctx, const RetrievePlan &p, const void 
 // Phase III staged through LDS (plans with gather_lds, after
 // run_distribute_probe with local_inv).
 dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void *dst, hipStream_t stream);
+// LDS of one workgroup of the LDS-staged gather: a tile of T records of R
+// bytes, an int32 and a uint16 table over the 2^nbits runs, and one int32 per
+// 64 slots (plus two) for the segment index at each 64-slot boundary.
+inline size_t gather_lds_bytes(int64_t T, int R, int nbits) {
+    return (size_t)T * R + 6u * ((size_t)1 << nbits) + 4u * (size_t)((T + 63) / 64 + 2);
+}
 // dpg_sort_records; with key_bytes <= 4, *sorted_keys (when given) receives the
 // address inside the workspace of the n sorted keys as big-endian uint32 (key
 // bytes first, zero padding), valid until the workspace is used again, else null.

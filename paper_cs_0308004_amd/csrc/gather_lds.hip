@@ -8,9 +8,11 @@
 // in the tile's segments laid end to end in run order.
 //
 // One workgroup per tile copies the tile's segments into LDS with coalesced
-// loads (each LDS slot finds its segment by a binary search over the
-// segments' starts), then writes the tile's output rows in rid-list order,
-// each read from its slot in LDS.  Every global access is then coalesced,
+// loads, then writes the tile's output rows in rid-list order, each read from
+// its slot in LDS.  Each LDS slot finds its segment by a binary search over
+// the segments' starts, narrowed first by a table that holds, for every 64th
+// slot, the segment containing it: a wave's 64 consecutive slots then search
+// only the few segments of their own 64-slot cell.  Every global access is then coalesced,
 // where the cached gather spends one cache-line request per small record.
 // Used for records of 4, 8 and 16 bytes, where a tile fits the LDS.
 #include "dev_common.h"
@@ -24,8 +26,22 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGatherThreads = 1024;
 constexpr int kGatherPer = 8;  // elements per thread per round, all loads in flight together
+constexpr int kOutVec = 4;     // 16-byte output vectors per thread per round (VEC)
+constexpr int kMaxGatherTile = 65535;  // segment starts are held as uint16
 
-template <typename E, int WE, bool NT>
+template <typename E>
+__device__ __forceinline__ void put16(u32x4 &o, int j, const E &v) {
+    if constexpr (sizeof(E) == 4) {
+        o[j] = v;
+    } else {
+        o[2 * j] = v.x;
+        o[2 * j + 1] = v.y;
+    }
+}
+
+// VEC: records of 4 or 8 bytes (WE == 1) written as 16-byte vectors of
+// consecutive output rows (dst and the slot array 16-byte aligned).
+template <typename E, int WE, bool NT, bool VEC>
 __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restrict__ internal,
                                                                const int32_t *__restrict__ slot, E *__restrict__ dst,
                                                                int64_t n, int T, int nbits, int64_t nT,
@@ -35,8 +51,9 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
     extern __shared__ __align__(16) char smem[];
     const int nb = 1 << nbits;
     E *s_rec = (E *)smem;                                         // T * WE elements
-    int32_t *s_off = (int32_t *)(smem + sizeof(E) * (size_t)T * WE);  // INTERNAL start of each run's segment
-    int32_t *s_start = s_off + nb;                                // segment length, then start in s_rec
+    int32_t *s_base = (int32_t *)(smem + sizeof(E) * (size_t)T * WE);  // INTERNAL start, then start - LDS start
+    uint16_t *s_start = (uint16_t *)(s_base + nb);                // segment length, then start in s_rec
+    int32_t *s_cell = (int32_t *)(s_start + nb);                  // segment of slot 64c, c <= ceil(V / 64)
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_total;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -46,8 +63,8 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
     for (int d = threadIdx.x; d < nb; d += kGatherThreads) {
         const int32_t o = off[t * nb + d];
         const int32_t next = t + 1 < nT ? off[(t + 1) * nb + d] : bucket_off[d + 1];
-        s_off[d] = o;
-        s_start[d] = next - o;
+        s_base[d] = o;
+        s_start[d] = (uint16_t)(next - o);
     }
     __syncthreads();
     // exclusive prefix of the segment lengths: wave w scans the w-th slice,
@@ -65,7 +82,7 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
                 const int32_t y = __shfl_up(inc, s, 64);
                 if (lane >= s) inc += y;
             }
-            if (d < d_hi) s_start[d] = carry + inc - c;
+            if (d < d_hi) s_start[d] = (uint16_t)(carry + inc - c);
             carry += __shfl(inc, 63, 64);
         }
         if (lane == 0) s_wsum[wave] = carry;
@@ -76,32 +93,55 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
             before += v < wave ? s_wsum[v] : 0;
             all += s_wsum[v];
         }
-        for (int d = d_lo + lane; d < d_hi; d += 64) s_start[d] += before;
+        for (int d = d_lo + lane; d < d_hi; d += 64) {
+            const int32_t st = s_start[d] + before;
+            s_start[d] = (uint16_t)st;
+            s_base[d] -= st;  // INTERNAL index of slot q in segment d: s_base[d] + q
+        }
         if (threadIdx.x == 0) s_total = all;
     }
     __syncthreads();
     const int V = s_total;  // records of valid rids in this tile (<= cnt)
+    // cell table: for c < ceil(V / 64) the segment holding slot 64c, and
+    // after the last cell the segment holding slot V - 1 (largest d with
+    // s_start[d] <= slot: that segment is non-empty and holds the slot)
+    const int n_cell = (V + 63) >> 6;
+    for (int c = threadIdx.x; c <= n_cell && V > 0; c += kGatherThreads) {
+        const int q = min(c << 6, V - 1);
+        int d = 0;
+        for (int step = nb >> 1; step > 0; step >>= 1)
+            if (s_start[d + step] <= q) d += step;
+        s_cell[c] = d;
+    }
+    __syncthreads();
     // segments -> LDS
     const int total_in = V * WE;
     for (int x0 = 0; x0 < total_in; x0 += kGatherThreads * kGatherPer) {
-        int q[kGatherPer], d[kGatherPer];
+        int q[kGatherPer], d[kGatherPer], hi[kGatherPer];
+        int span = 0;
 #pragma unroll
         for (int k = 0; k < kGatherPer; ++k) {
-            q[k] = min(x0 + (int)threadIdx.x + k * kGatherThreads, total_in - 1);
-            d[k] = 0;
+            q[k] = min(x0 + (int)threadIdx.x + k * kGatherThreads, total_in - 1) / WE;
+            const int c = q[k] >> 6;
+            d[k] = s_cell[c];
+            hi[k] = s_cell[c + 1];
+            span = max(span, hi[k] - d[k]);
         }
-        // largest d with s_start[d] <= slot: that segment is non-empty and
-        // holds the slot (binary lifting, the lanes' searches interleaved)
-        for (int step = nb >> 1; step > 0; step >>= 1) {
+        // largest d in [s_cell[c], s_cell[c + 1]] with s_start[d] <= slot
+        // (binary lifting, clamped to the range; the searches interleaved)
+        for (int step = span > 0 ? 1 << (31 - __clz(span)) : 0; step > 0; step >>= 1) {
 #pragma unroll
-            for (int k = 0; k < kGatherPer; ++k)
-                if (s_start[d[k] + step] <= q[k] / WE) d[k] += step;
+            for (int k = 0; k < kGatherPer; ++k) {
+                const int e = min(d[k] + step, hi[k]);
+                if (s_start[e] <= q[k]) d[k] = e;
+            }
         }
         E v[kGatherPer];
 #pragma unroll
         for (int k = 0; k < kGatherPer; ++k) {
-            const int qr = q[k] / WE, w = q[k] - qr * WE;
-            v[k] = internal[(int64_t)(s_off[d[k]] + (qr - s_start[d[k]])) * WE + w];
+            const int x = min(x0 + (int)threadIdx.x + k * kGatherThreads, total_in - 1);
+            const int w = x - q[k] * WE;
+            v[k] = internal[(int64_t)(s_base[d[k]] + q[k]) * WE + w];
         }
 #pragma unroll
         for (int k = 0; k < kGatherPer; ++k) {
@@ -113,7 +153,36 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
     // LDS -> output rows in rid-list order (invalid rids: slot 0, undefined row)
     const int total_out = cnt * WE;
     E *out = dst + base * WE;
-    for (int y0 = 0; y0 < total_out; y0 += kGatherThreads * kGatherPer) {
+    int done = 0;  // output elements written by the vector loop
+    if constexpr (VEC) {
+        static_assert(WE == 1 && (sizeof(E) == 4 || sizeof(E) == 8), "16-byte vectors of whole records");
+        constexpr int VO = 16 / (int)sizeof(E);  // rows per vector
+        typedef int32_t i32v __attribute__((ext_vector_type(VO)));
+        const int nvec = cnt / VO;
+        const i32v *slot_v = (const i32v *)(slot + base);
+        u32x4 *out_v = (u32x4 *)out;
+        for (int y0 = 0; y0 < nvec; y0 += kGatherThreads * kOutVec) {
+            i32v q[kOutVec];
+#pragma unroll
+            for (int k = 0; k < kOutVec; ++k) q[k] = slot_v[min(y0 + (int)threadIdx.x + k * kGatherThreads, nvec - 1)];
+#pragma unroll
+            for (int k = 0; k < kOutVec; ++k) {
+                const int y = y0 + (int)threadIdx.x + k * kGatherThreads;
+                if (y < nvec) {
+                    u32x4 o = {0u, 0u, 0u, 0u};
+#pragma unroll
+                    for (int j = 0; j < VO; ++j) {
+                        const int qq = min(max((int)q[k][j], 0), max(V - 1, 0));
+                        put16(o, j, V > 0 ? s_rec[qq] : E{});
+                    }
+                    if constexpr (NT) __builtin_nontemporal_store(o, out_v + y);
+                    else out_v[y] = o;
+                }
+            }
+        }
+        done = nvec * VO;
+    }
+    for (int y0 = done; y0 < total_out; y0 += kGatherThreads * kGatherPer) {
         int32_t q[kGatherPer];
 #pragma unroll
         for (int k = 0; k < kGatherPer; ++k) {
@@ -134,20 +203,19 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
     }
 }
 
-template <typename E, int WE>
+template <typename E, int WE, bool VEC>
 static dpg_status launch_gather_lds_t(const RetrievePlan &p, const void *internal, const int32_t *slot, void *dst,
                                       const int32_t *off, const int32_t *bucket_off, int remap, hipStream_t stream) {
-    const int nb = 1 << p.part_nbits;
-    const size_t lds = sizeof(E) * (size_t)p.part_tile * WE + 2 * sizeof(int32_t) * nb;
+    const size_t lds = gather_lds_bytes(p.part_tile, (int)sizeof(E) * WE, p.part_nbits);
     const bool nt = (double)p.n_rids * p.rec_bytes > 256.0 * 1024 * 1024;
     const int64_t nT = (p.n_rids + p.part_tile - 1) / p.part_tile;
-    if (nT > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
+    if (nT > 0x7fffffffLL || p.part_tile > kMaxGatherTile || p.part_tile % 64 != 0) return DPG_ERR_UNSUPPORTED;
 #define DPG_LAUNCH_GLDS(NTV)                                                                                      \
     do {                                                                                                          \
         if (lds > 64 * 1024)                                                                                      \
-            DPG_HIP(hipFuncSetAttribute((const void *)k_gather_lds<E, WE, NTV>,                                  \
+            DPG_HIP(hipFuncSetAttribute((const void *)k_gather_lds<E, WE, NTV, VEC>,                             \
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));                   \
-        hipLaunchKernelGGL((k_gather_lds<E, WE, NTV>), dim3((unsigned)nT), dim3(kGatherThreads), lds, stream,      \
+        hipLaunchKernelGGL((k_gather_lds<E, WE, NTV, VEC>), dim3((unsigned)nT), dim3(kGatherThreads), lds, stream, \
                            (const E *)internal, slot, (E *)dst, p.n_rids, p.part_tile, p.part_nbits, nT, off,     \
                            bucket_off, remap);                                                                    \
     } while (0)
@@ -173,14 +241,18 @@ dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void
     ProfScope prof(ctx, K_GATHER_LDS, 4.0 * M + 2.0 * R * M, stream);
     const int remap = xcd_remap_flag(ctx);
     const bool a16 = ((uintptr_t)dst % 16) == 0, a8 = ((uintptr_t)dst % 8) == 0;
+    const bool vec = a16 && ((uintptr_t)slot % 16) == 0;  // tiles start at multiples of 64 rows
     switch (p.rec_bytes) {
-        case 4: return launch_gather_lds_t<uint32_t, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
+        case 4:
+            if (vec) return launch_gather_lds_t<uint32_t, 1, true>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            return launch_gather_lds_t<uint32_t, 1, false>(p, internal, slot, dst, off, bucket_off, remap, stream);
         case 8:
-            if (a8) return launch_gather_lds_t<u32x2, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
-            return launch_gather_lds_t<uint32_t, 2>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            if (vec) return launch_gather_lds_t<u32x2, 1, true>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            if (a8) return launch_gather_lds_t<u32x2, 1, false>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            return launch_gather_lds_t<uint32_t, 2, false>(p, internal, slot, dst, off, bucket_off, remap, stream);
         case 16:
-            if (a16) return launch_gather_lds_t<u32x4, 1>(p, internal, slot, dst, off, bucket_off, remap, stream);
-            return launch_gather_lds_t<uint32_t, 4>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            if (a16) return launch_gather_lds_t<u32x4, 1, false>(p, internal, slot, dst, off, bucket_off, remap, stream);
+            return launch_gather_lds_t<uint32_t, 4, false>(p, internal, slot, dst, off, bucket_off, remap, stream);
     }
     return DPG_ERR_UNSUPPORTED;
 }

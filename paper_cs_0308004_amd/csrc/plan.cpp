@@ -98,8 +98,7 @@ static void layout_workspace(RetrievePlan *p) {
     p->workspace = off;
 }
 
-// LDS a workgroup of the LDS-staged gather may use: the tile's records plus
-// two int32 tables over the runs.
+// LDS a workgroup of the LDS-staged gather may use (gather_lds_bytes).
 constexpr size_t kGatherLdsBytes = 150 * 1024;
 
 static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, int dist_mode, int gather) {
@@ -202,7 +201,7 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     // gather is then coalesced.
     if ((p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) && gather != 1 &&
         (R == 4 || R == 8 || R == 16)) {
-        const size_t lds = (size_t)p->dist_tile * R + 8u * ((size_t)1 << p->part_nbits);
+        const size_t lds = gather_lds_bytes(p->dist_tile, R, p->part_nbits);
         p->gather_lds = lds <= kGatherLdsBytes;
         p->part_tile = p->dist_tile;
     }
@@ -258,7 +257,7 @@ dpg_status make_hash_lookup_plan(int64_t n_queries, int32_t log2_slots, int log2
         p->n_tiles = pp.n_tiles;
         p->n_chunks = pp.n_chunks;
         if (gather != 1) {
-            const size_t lds = (size_t)pp.tile * 4 + 8u * ((size_t)1 << bits);
+            const size_t lds = gather_lds_bytes(pp.tile, 4, bits);
             p->gather_lds = lds <= kGatherLdsBytes;
             p->part_tile = pp.tile;
         }
@@ -287,7 +286,7 @@ dpg_status make_split_lookup_plan(int64_t n_queries, int64_t n_runs, int gather,
         p->n_tiles = pp.n_tiles;
         p->n_chunks = pp.n_chunks;
         if (gather != 1) {
-            const size_t lds = (size_t)pp.tile * 4 + 8u * ((size_t)1 << bits);
+            const size_t lds = gather_lds_bytes(pp.tile, 4, bits);
             p->gather_lds = lds <= kGatherLdsBytes;
             p->part_tile = pp.tile;
         }
