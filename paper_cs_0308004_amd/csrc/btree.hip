@@ -477,7 +477,7 @@ dpg_status dpg_btree_lookup(dpg_ctx *ctx, const void *tree, int64_t n_keys, cons
         DPG_HIP(hipGetLastError());
     }
     // Phase I: each query into the run of the first subtree whose largest key is not below it
-    const PartPlan pp = plan_partition(r.n_rids, r.part_nbits, 4, false);
+    const PartPlan pp = dist_partition(r);
     int32_t *item_off = p.lds ? (int32_t *)(w + r.off_items) : nullptr;
     int32_t *run_off = nullptr;
     dpg_status st = launch_partition(ctx, pp, queries, nullptr, w + r.off_run, nullptr, (int32_t *)(w + r.off_inv),

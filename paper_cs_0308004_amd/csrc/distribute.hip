@@ -152,7 +152,7 @@ static dpg_status launch_distribute_sampled(dpg_ctx *ctx, const RetrievePlan &p,
         hipLaunchKernelGGL(k_dist_splitters, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, a, s, B, split);
         DPG_HIP(hipGetLastError());
     }
-    const PartPlan pp = plan_partition(M, p.part_nbits, 4, false);
+    const PartPlan pp = dist_partition(p);
     return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv), 0,
                             (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0, /*stable=*/false,
                             local_inv, 1u, split, B - 1);
@@ -186,13 +186,13 @@ dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t 
     if (p.dist_mode == DIST_TWO_PASS) return launch_distribute_two_pass(ctx, p, rids, w, stream);
     if (p.dist_mode == DIST_PARTITION && p.scatter) {
         // two-phase DPG: the runs, and beside each rid its list position
-        const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+        const PartPlan pp = dist_partition(p);
         return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, nullptr, p.log2_run,
                                 (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0, /*stable=*/false,
                                 false, 1u, nullptr, 0, (uint32_t *)(w + p.off_inv));
     }
     if (p.dist_mode == DIST_PARTITION) {
-        const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+        const PartPlan pp = dist_partition(p);
         int32_t *item_off = p.probe == DPG_PROBE_LDS ? (int32_t *)(w + p.off_items) : nullptr;
         return launch_partition(ctx, pp, rids, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv),
                                 p.log2_run, (uint64_t)p.n_src, w + p.off_part, stream, nullptr, item_off,

@@ -39,16 +39,18 @@ __device__ __forceinline__ void put16(u32x4 &o, int j, const E &v) {
     }
 }
 
-// VEC: records of 4 or 8 bytes (WE == 1) written as 16-byte vectors of
-// consecutive output rows (dst and the slot array 16-byte aligned).
-template <typename E, int WE, bool NT, bool VEC>
-__global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restrict__ internal,
-                                                               const int32_t *__restrict__ slot, E *__restrict__ dst,
-                                                               int64_t n, int T, int nbits, int64_t nT,
-                                                               const int32_t *__restrict__ off,
-                                                               const int32_t *__restrict__ bucket_off, int remap) {
+// Stages the records of distribute tile t in LDS: the tile's run segments of
+// INTERNAL (run d's share starts at off[t][d] and ends where tile t + 1's
+// share starts, or at the end of run d) are copied, laid end to end in run
+// order, to the start of smem with coalesced loads.  Returns V, the number of
+// records staged; the caller synchronises before reading them.  LDS layout
+// after the T * WE records: an int32 and a uint16 table over the 2^nbits
+// runs, then the 64-slot cell table (gather_lds_bytes).
+template <typename E, int WE>
+__device__ __forceinline__ int stage_tile(const E *__restrict__ internal, int T, int nbits, int64_t t, int64_t nT,
+                                          const int32_t *__restrict__ off, const int32_t *__restrict__ bucket_off,
+                                          char *smem) {
     constexpr int W = kGatherThreads / 64;
-    extern __shared__ __align__(16) char smem[];
     const int nb = 1 << nbits;
     E *s_rec = (E *)smem;                                         // T * WE elements
     int32_t *s_base = (int32_t *)(smem + sizeof(E) * (size_t)T * WE);  // INTERNAL start, then start - LDS start
@@ -57,9 +59,6 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_total;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int64_t t = xcd_tile(blockIdx.x, nT, remap);
-    const int64_t base = t * T;
-    const int cnt = (int)min((int64_t)T, n - base);
     for (int d = threadIdx.x; d < nb; d += kGatherThreads) {
         const int32_t o = off[t * nb + d];
         const int32_t next = t + 1 < nT ? off[(t + 1) * nb + d] : bucket_off[d + 1];
@@ -149,6 +148,23 @@ __global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restri
             if (x < total_in) s_rec[x] = v[k];
         }
     }
+    return V;
+}
+
+// VEC: records of 4 or 8 bytes (WE == 1) written as 16-byte vectors of
+// consecutive output rows (dst and the slot array 16-byte aligned).
+template <typename E, int WE, bool NT, bool VEC>
+__global__ __launch_bounds__(kGatherThreads) void k_gather_lds(const E *__restrict__ internal,
+                                                               const int32_t *__restrict__ slot, E *__restrict__ dst,
+                                                               int64_t n, int T, int nbits, int64_t nT,
+                                                               const int32_t *__restrict__ off,
+                                                               const int32_t *__restrict__ bucket_off, int remap) {
+    extern __shared__ __align__(16) char smem[];
+    E *s_rec = (E *)smem;  // T * WE elements
+    const int64_t t = xcd_tile(blockIdx.x, nT, remap);
+    const int64_t base = t * T;
+    const int cnt = (int)min((int64_t)T, n - base);
+    const int V = stage_tile<E, WE>(internal, T, nbits, t, nT, off, bucket_off, smem);
     __syncthreads();
     // LDS -> output rows in rid-list order (invalid rids: slot 0, undefined row)
     const int total_out = cnt * WE;
@@ -231,7 +247,7 @@ dpg_status launch_gather_lds(dpg_ctx *ctx, const RetrievePlan &p, void *ws, void
         return DPG_ERR_UNSUPPORTED;
     if (p.n_rids <= 0) return DPG_OK;
     char *w = (char *)ws;
-    const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+    const PartPlan pp = dist_partition(p);
     if (pp.tile != p.part_tile) return DPG_ERR_UNSUPPORTED;
     const int32_t *off = (const int32_t *)(w + p.off_part + pp.off_cnt);
     const int32_t *bucket_off = (const int32_t *)(w + p.off_part + pp.off_bucket);

@@ -389,7 +389,7 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
     }
     // Phase I: distribute z = key * kHashMul by its top bits (the index partition)
     char *w = (char *)workspace;
-    const PartPlan pp = plan_partition(p.n_rids, p.part_nbits, 4, false);
+    const PartPlan pp = dist_partition(p);
     const bool lds_probe = p.probe == DPG_PROBE_LDS;
     int32_t *item_off = lds_probe ? (int32_t *)(w + p.off_items) : nullptr;
     int32_t *run_off = nullptr;

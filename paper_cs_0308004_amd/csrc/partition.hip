@@ -416,16 +416,16 @@ static int part_per(int key_bytes, bool has_val) {
     return 16;
 }
 
-PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val) {
+PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per) {
     PartPlan p;
     p.n = n;
     p.nbits = nbits;
     p.key_bytes = key_bytes;
     p.has_val = has_val;
     p.per = part_per(key_bytes, has_val);
-    if (nbits > kMaxDigitBits) {  // wide unstable pass: 1024 threads x 16 keys
+    if (nbits > kMaxDigitBits) {  // wide unstable pass: 1024 threads x 8 or 16 keys
         p.threads = 1024;
-        p.per = 16;
+        p.per = wide_per == 8 ? 8 : 16;
     }
     p.tile = p.threads * p.per;
     p.n_tiles = n > 0 ? (n + p.tile - 1) / p.tile : 0;
@@ -473,7 +473,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (p.n <= 0) return DPG_OK;
     const bool wide = p.nbits > kMaxDigitBits;
     if (p.nbits < 1 || p.nbits > kMaxWideBits) return DPG_ERR_UNSUPPORTED;
-    if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || p.per != 16))
+    if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || (p.per != 8 && p.per != 16)))
         return DPG_ERR_UNSUPPORTED;
     if (local_inv && stable) return DPG_ERR_UNSUPPORTED;
     if (key_mul != 1 && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
@@ -529,12 +529,13 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                            (idx_out ? sizeof(uint32_t) * p.tile : 0);
         if (lds + 1024 > kMaxPartitionLds) return DPG_ERR_UNSUPPORTED;
         if (wide) {
-            const void *fn = split ? (const void *)k_part_scatter_unstable<1024, 16, true>
-                                   : (const void *)k_part_scatter_unstable<1024, 16, false>;
+            if (p.threads != 1024 || (p.per != 8 && p.per != 16)) return DPG_ERR_UNSUPPORTED;
+            auto fn = p.per == 8 ? (split ? k_part_scatter_unstable<1024, 8, true> : k_part_scatter_unstable<1024, 8, false>)
+                                 : (split ? k_part_scatter_unstable<1024, 16, true>
+                                          : k_part_scatter_unstable<1024, 16, false>);
             if (lds > 64 * 1024)
-                DPG_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-            hipLaunchKernelGGL((split ? k_part_scatter_unstable<1024, 16, true> : k_part_scatter_unstable<1024, 16, false>),
-                               dim3((unsigned)p.n_tiles), dim3(1024), lds, stream, (const uint32_t *)keys_in, p.n,
+                DPG_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            hipLaunchKernelGGL(fn, dim3((unsigned)p.n_tiles), dim3(1024), lds, stream, (const uint32_t *)keys_in, p.n,
                                shift, p.nbits, limit, p.n_tiles, cnt, (uint32_t *)keys_out, inv, local_inv ? 1 : 0,
                                key_mul, remap, split, cells, n_split, idx_out);
         } else {

@@ -63,7 +63,7 @@ static void layout_workspace(RetrievePlan *p) {
     if (p->algo == DPG_ALGO_DPG) {
         const int64_t B = p->n_runs, M = p->n_rids;
         if (p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) {
-            const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+            const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per);
             p->off_part = take(pp.workspace);
             p->off_bucket = p->off_part + pp.off_bucket;
             p->off_items = take((size_t)((1 << p->part_nbits) + 1) * 4);
@@ -198,10 +198,22 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     }
     // Phase III through LDS when a partition tile's records fit (records of
     // 4, 8 or 16 bytes, one LDS element each): every global access of the
-    // gather is then coalesced.
+    // gather is then coalesced.  A 1024-thread partition pass halves its tile
+    // when that makes the records fit (16-byte records over more than 256
+    // runs).
     if ((p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) && gather != 1 &&
         (R == 4 || R == 8 || R == 16)) {
-        const size_t lds = gather_lds_bytes(p->dist_tile, R, p->part_nbits);
+        size_t lds = gather_lds_bytes(p->dist_tile, R, p->part_nbits);
+        if (lds > kGatherLdsBytes && p->part_nbits > kMaxDigitBits && !want_scatter) {
+            const PartPlan ph = plan_partition(M, p->part_nbits, 4, false, 8);
+            if (gather_lds_bytes(ph.tile, R, p->part_nbits) <= kGatherLdsBytes) {
+                p->wide_per = 8;
+                p->dist_tile = ph.tile;
+                p->n_tiles = ph.n_tiles;
+                p->n_chunks = ph.n_chunks;
+                lds = gather_lds_bytes(ph.tile, R, p->part_nbits);
+            }
+        }
         p->gather_lds = lds <= kGatherLdsBytes;
         p->part_tile = p->dist_tile;
     }

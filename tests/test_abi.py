@@ -170,6 +170,14 @@ def test_plan_phase_forms():
         assert p.n_runs <= 2048 and p.ws_internal == 0
     p = dpg.plan_retrieve(1 << 26, 8, 1 << 26, dpg.ALGO_DIRECT)
     assert p.distribute == 0 and p.gather == 0
+    # 16-byte records over more than 256 runs: the 1024-thread partition pass
+    # takes tiles of 8192 rids (not 16384), so that a tile's records fit the
+    # LDS of the gather; 8-byte records keep tiles of 16384
+    p = dpg.plan_retrieve(1 << 28, 16, 1 << 28, dpg.ALGO_DPG)
+    assert p.n_runs == 1024 and p.gather == dpg.GATHER_LDS and p.dist_tile == 8192
+    assert p.n_tiles == (1 << 28) // 8192
+    p = dpg.plan_retrieve(1 << 28, 8, 1 << 28, dpg.ALGO_DPG)
+    assert p.n_runs == 1024 and p.gather == dpg.GATHER_LDS and p.dist_tile == 16384
 
 
 def test_hash_index_layout_and_validation():

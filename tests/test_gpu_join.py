@@ -108,12 +108,17 @@ def test_join_full_size_sampled(ctx):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("dist", [dpg.DIST_APPEND, dpg.DIST_SAMPLED, dpg.DIST_TWO_PASS],
-                         ids=["append", "sampled", "two-pass"])
+@pytest.mark.parametrize("form", [(dpg.DIST_APPEND, 2), (dpg.DIST_SAMPLED, 2), (dpg.DIST_TWO_PASS, 2),
+                                  (dpg.DIST_PARTITION, 6), (dpg.DIST_PARTITION, 0)],
+                         ids=["append", "sampled", "two-pass", "partition-938-runs", "partition-default"])
 @pytest.mark.parametrize("order", [dpg.JOIN_FACT_ORDER, dpg.JOIN_DIM_ORDER], ids=["move", "sort"])
-def test_join_phase_i_forms(ctx, order, dist):
+def test_join_phase_i_forms(ctx, order, form):
     """Every Phase I form gives the same join (the fused assembly reads
-    INTERNAL through one slot per row, which the two-pass form composes)."""
+    INTERNAL through one slot per row, which the two-pass form composes).
+    Runs of 4 rows give thousands of runs; runs of 64 give 938, which the
+    1024-thread partition pass cuts into tiles of 8192 rows when the moved
+    rows are 16 bytes (the dimension-order join)."""
+    dist, log2_run = form
     n_fact, n_dim = 60001, 1 << 14
     seed = synth.SEED_BASE + 77
     fact = synth.fact_table(n_fact, n_dim, 1.2, seed, permute_ids=False)
@@ -121,7 +126,7 @@ def test_join_phase_i_forms(ctx, order, dist):
     fn = oracle.fk_join_fact_order if order == dpg.JOIN_FACT_ORDER else oracle.fk_join_dim_order
     want = fn(fact, dim, 0)
     ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
-    ctx.set_option(dpg.OPT_LOG2_RUN, 2)  # thousands of runs
+    ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
     try:
         got = ctx.fk_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 0, order, algo=dpg.ALGO_DPG)
         torch.cuda.synchronize()
