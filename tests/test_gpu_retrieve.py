@@ -90,6 +90,7 @@ CASES = [
     (12345, 30000, 16, "uniform"),
     (7777, 7777, 4, "perm"),
     (3001, 3001, 12, "reverse"),
+    (40009, 50021, 12, "uniform"),  # 12-byte records over several distribute tiles
     (9000, 9000, 36, "perm"),
     (8192, 8192, 64, "blocked"),
     (4000, 4000, 128, "identity"),
