@@ -170,7 +170,9 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
 /* ------------------------------------------------------------------------- */
 size_t dpg_autotune_workspace_bytes(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes,
                                     int64_t n_rids);
-/* dpg_only = 1: consider DPG plans only (to find the best DPG configuration). */
+/* dpg_only = 1: consider DPG plans only (to find the best DPG configuration).
+ * *best (may be null) receives the fastest plan, described as
+ * dpg_plan_retrieve describes a plan; *best_ms (may be null) its time. */
 dpg_status dpg_autotune_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t rec_bytes,
                                  const int32_t *rids, int64_t n_rids, void *dst, void *workspace,
                                  size_t workspace_bytes, int32_t reps, int32_t dpg_only,

@@ -198,6 +198,8 @@ dpg_status make_retrieve_plan_explicit(int64_t n_src, int32_t rec_bytes, int64_t
                                        int log2_run, int dist_tile, int dist_mode, RetrievePlan *plan,
                                        int gather = 0);
 TuneKey tune_key(int32_t rec_bytes, int64_t n_src, int64_t n_rids);
+// The public description of a plan (dpg_plan_retrieve, dpg_autotune_retrieve).
+void plan_to_public(const RetrievePlan &p, dpg_plan *out);
 // Plan of a batch lookup whose queries are partitioned into n_runs <= 4096
 // runs by splitters (one unstable pass); INTERNAL holds an int32 rid per
 // query; lds_probe: work items of at most 16384 queries per run.

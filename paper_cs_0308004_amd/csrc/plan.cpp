@@ -355,6 +355,24 @@ dpg_status make_retrieve_plan(const dpg_ctx *ctx, int64_t n_src, int32_t rec_byt
                                        gather);
 }
 
+void plan_to_public(const RetrievePlan &p, dpg_plan *out) {
+    std::memset(out, 0, sizeof(*out));
+    out->algo = p.algo;
+    out->probe = p.algo == DPG_ALGO_DPG ? p.probe : 0;
+    out->log2_run = p.log2_run;
+    out->dist_tile = p.dist_tile;
+    out->distribute = p.algo == DPG_ALGO_DPG ? dist_option_value(p.dist_mode) : 0;
+    out->gather = p.algo == DPG_ALGO_DPG ? (p.scatter ? 3 : p.gather_lds ? 2 : 1) : 0;
+    out->n_runs = p.n_runs;
+    out->n_tiles = p.n_tiles;
+    out->workspace_bytes = p.workspace;
+    if (p.algo == DPG_ALGO_DPG && p.n_rids > 0) {
+        out->ws_run_off = p.dist_mode == DIST_TWO_PASS ? 0 : p.off_bucket;
+        out->ws_rid_run = p.off_run;
+        out->ws_internal = p.scatter ? 0 : p.off_internal;
+    }
+}
+
 }  // namespace dpg
 
 extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32_t rec_bytes, int64_t n_rids,
@@ -363,21 +381,7 @@ extern "C" dpg_status dpg_plan_retrieve(const dpg_ctx *ctx, int64_t n_src, int32
     dpg::RetrievePlan p;
     const dpg_status st = dpg::make_retrieve_plan(ctx, n_src, rec_bytes, n_rids, algo, &p);
     if (st != DPG_OK) return st;
-    std::memset(out, 0, sizeof(*out));
-    out->algo = p.algo;
-    out->probe = p.algo == DPG_ALGO_DPG ? p.probe : 0;
-    out->log2_run = p.log2_run;
-    out->dist_tile = p.dist_tile;
-    out->distribute = p.algo == DPG_ALGO_DPG ? dpg::dist_option_value(p.dist_mode) : 0;
-    out->gather = p.algo == DPG_ALGO_DPG ? (p.scatter ? 3 : p.gather_lds ? 2 : 1) : 0;
-    out->n_runs = p.n_runs;
-    out->n_tiles = p.n_tiles;
-    out->workspace_bytes = p.workspace;
-    if (p.algo == DPG_ALGO_DPG && n_rids > 0) {
-        out->ws_run_off = p.dist_mode == dpg::DIST_TWO_PASS ? 0 : p.off_bucket;
-        out->ws_rid_run = p.off_run;
-        out->ws_internal = p.scatter ? 0 : p.off_internal;
-    }
+    dpg::plan_to_public(p, out);
     return DPG_OK;
 }
 

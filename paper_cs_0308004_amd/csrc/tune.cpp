@@ -121,17 +121,7 @@ dpg_status dpg_autotune_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, i
     TuneEntry e{best_c.algo, best_p.algo == DPG_ALGO_DPG ? best_p.probe : 0, best_p.log2_run, 0,
                 best_p.algo == DPG_ALGO_DPG ? dist_option_value(best_p.dist_mode) : 0, best_t};
     ctx->tuned[tune_key(rec_bytes, n_src, n_rids)] = e;
-    if (best) {
-        *best = dpg_plan{};
-        best->algo = best_p.algo;
-        best->probe = e.probe;
-        best->log2_run = best_p.log2_run;
-        best->dist_tile = best_p.dist_tile;
-        best->distribute = e.dist_mode;
-        best->n_runs = best_p.n_runs;
-        best->n_tiles = best_p.n_tiles;
-        best->workspace_bytes = best_p.workspace;
-    }
+    if (best) plan_to_public(best_p, best);
     if (best_ms) *best_ms = best_t;
     return DPG_OK;
 }

@@ -34,6 +34,11 @@ def test_autotune_records_and_auto_follows(tmp_path):
         # best DPG configuration only
         bd, _ = ctx.autotune_retrieve(s_t, r_t, reps=1, dpg_only=True)
         assert bd.algo == dpg.ALGO_DPG
+        # the reported plan is the one AUTO now uses, field by field
+        auto = ctx.plan_retrieve(n, rec, n, dpg.ALGO_AUTO)
+        for field, _ in dpg.Plan._fields_:
+            assert getattr(auto, field) == getattr(bd, field), field
+        assert bd.gather in (dpg.GATHER_CACHED, dpg.GATHER_LDS, dpg.GATHER_NONE)
         path = os.path.join(tmp_path, "tune.txt")
         ctx.tune_save(path)
         ctx.tune_clear()
