@@ -36,20 +36,27 @@ __device__ __forceinline__ uint32_t digit_of(K key, int shift, uint32_t mask) {
 }
 
 // Splitter buckets.  With ascending splitters s[0..ns), the bucket of a key
-// is the number of splitters below it.  A table over the top kSplitCellBits
-// bits of the key narrows the search: cell_lo[h] = number of splitters whose
-// top bits are below h, so the splitters below a key with top bits h are the
-// first cell_lo[h] plus those of [cell_lo[h], cell_lo[h+1]) below it.
+// is the number of splitters below it.  A table of kSplitCells cells narrows
+// the search: cell h holds the keys k with k >> shift == h, where shift is
+// the smallest that fits the largest splitter in kSplitCellBits bits (so
+// the cells span the splitters' range, whatever the key width), and
+// cell_lo[h] = number of splitters below h << shift.  The splitters below a
+// key of cell h are then the first cell_lo[h] plus those of
+// [cell_lo[h], cell_lo[h+1]) below it; a key beyond the last cell lies above
+// every splitter.  cell_lo[kSplitCells + 1] holds shift.
 constexpr int kSplitCellBits = 12;
 constexpr int kSplitCells = 1 << kSplitCellBits;
+constexpr int kSplitTable = kSplitCells + 2;  // int32 entries of the cell table
 
 struct SplitLds {
     const uint32_t *s = nullptr;  // splitters in LDS (null: digits)
     const int32_t *cell_lo = nullptr;
+    int shift = 32 - kSplitCellBits;
 };
 
 __device__ __forceinline__ uint32_t split_bucket(const SplitLds &sp, uint32_t key) {
-    const uint32_t h = key >> (32 - kSplitCellBits);
+    const uint32_t h = key >> sp.shift;
+    if (h >= (uint32_t)kSplitCells) return (uint32_t)sp.cell_lo[kSplitCells];
     int l = sp.cell_lo[h], r = sp.cell_lo[h + 1];
     while (l < r) {
         const int m = (l + r) >> 1;
@@ -67,31 +74,41 @@ __device__ __forceinline__ uint32_t bucket_of(uint32_t key, int shift, uint32_t 
     else return digit_of(key, shift, mask);
 }
 
-// Stage the splitters and their cell table (if any) in LDS at `lds`.
+// Stage the splitters and their cell table (if any) in LDS at `lds`; the
+// shift is read from the table in global memory, written by an earlier launch.
 __device__ __forceinline__ SplitLds stage_splitters(uint32_t *lds, const uint32_t *split, const int32_t *cell_lo,
                                                     int ns) {
     SplitLds sp;
     if (!split) return sp;
     for (int i = threadIdx.x; i < ns; i += blockDim.x) lds[i] = split[i];
     int32_t *lo = (int32_t *)(lds + ns);
-    for (int i = threadIdx.x; i <= kSplitCells; i += blockDim.x) lo[i] = cell_lo[i];
+    for (int i = threadIdx.x; i < kSplitTable; i += blockDim.x) lo[i] = cell_lo[i];
     sp.s = lds;
     sp.cell_lo = lo;
+    sp.shift = cell_lo[kSplitCells + 1];
     return sp;
 }
 
-static size_t split_lds_bytes(int ns, bool on) { return on ? 4 * ((size_t)ns + kSplitCells + 1) : 0; }
+static size_t split_lds_bytes(int ns, bool on) { return on ? 4 * ((size_t)ns + kSplitTable) : 0; }
 
-// cell_lo[h] for h in [0, kSplitCells]: splitters below h << (32 - bits).
+// The cell table: cell_lo[h] for h in [0, kSplitCells] = splitters below
+// h << shift, and cell_lo[kSplitCells + 1] = shift.
 __global__ __launch_bounds__(256) void k_split_cells(const uint32_t *__restrict__ split, int ns,
                                                      int32_t *__restrict__ cell_lo) {
     const int h = blockIdx.x * 256 + threadIdx.x;
-    if (h > kSplitCells) return;
+    if (h >= kSplitTable) return;
+    const uint32_t top = ns > 0 ? split[ns - 1] : 0u;
+    const int width = top ? 32 - __clz(top) : 0;  // bits of the largest splitter
+    const int shift = width > kSplitCellBits ? width - kSplitCellBits : 0;
+    if (h == kSplitCells + 1) {
+        cell_lo[h] = shift;
+        return;
+    }
     if (h == kSplitCells) {
         cell_lo[h] = ns;
         return;
     }
-    const uint32_t bound = (uint32_t)h << (32 - kSplitCellBits);
+    const uint64_t bound = (uint64_t)h << shift;
     int l = 0, r = ns;
     while (l < r) {
         const int m = (l + r) >> 1;
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
     SplitLds sp;  // splitters, if any, after the digit tables
     if constexpr (SPLIT) sp = stage_splitters((uint32_t *)(s_glob + nb), split, cell_lo, n_split);
     // the input position of every element of the tile, when idx_out is given
-    uint32_t *s_idx = (uint32_t *)(s_glob + nb) + (SPLIT ? n_split + kSplitCells + 1 : 0);
+    uint32_t *s_idx = (uint32_t *)(s_glob + nb) + (SPLIT ? n_split + kSplitTable : 0);
     __shared__ int32_t s_wsum[W];
     __shared__ int32_t s_nvalid;
     const uint32_t mask = (uint32_t)nb - 1;
@@ -441,7 +458,7 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int w
     p.off_csum = take((size_t)p.n_chunks * nb * 4);
     p.off_total = take((size_t)nb * 4);
     p.off_bucket = take((size_t)(nb + 1) * 4);
-    p.off_cells = take((size_t)(kSplitCells + 1) * 4);
+    p.off_cells = take((size_t)kSplitTable * 4);
     p.workspace = off;
     return p;
 }
@@ -484,7 +501,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     const size_t split_lds = split_lds_bytes(n_split, split != nullptr);
     const int32_t *cells = (const int32_t *)(w + p.off_cells);
     if (split) {
-        hipLaunchKernelGGL(k_split_cells, dim3((kSplitCells + 1 + 255) / 256), dim3(256), 0, stream, split, n_split,
+        hipLaunchKernelGGL(k_split_cells, dim3((kSplitTable + 255) / 256), dim3(256), 0, stream, split, n_split,
                            (int32_t *)(w + p.off_cells));
         DPG_HIP(hipGetLastError());
     }
