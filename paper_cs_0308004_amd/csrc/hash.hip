@@ -174,33 +174,54 @@ __global__ __launch_bounds__(kHashProbeThreads) void k_hash_probe_lds(
 #pragma unroll
         for (int k = 0; k < kHashProbeBatch; ++k)
             zz[k] = zrun[k0 + min(j0 + (int)threadIdx.x + k * kHashProbeThreads, cnt - 1)];
+        // 1. the home slot, from LDS; a query whose slot holds another key
+        // needs the overflow range of that slot
+        int32_t r[kHashProbeBatch];
+        uint32_t qk[kHashProbeBatch], hk[kHashProbeBatch];
+        bool need[kHashProbeBatch];
 #pragma unroll
         for (int k = 0; k < kHashProbeBatch; ++k) {
             const int j = j0 + (int)threadIdx.x + k * kHashProbeThreads;
-            if (j >= cnt) break;
             const uint32_t z = zz[k];
-            const uint32_t q = z * kHashMulInv, h = slot_of(z, s);
-            const int64_t local = (int64_t)h - base;
-            int32_t r = -1;
-            if (local >= 0 && local < L) {
+            qk[k] = z * kHashMulInv;
+            hk[k] = slot_of(z, s);
+            const int64_t local = (int64_t)hk[k] - base;
+            r[k] = -1;
+            need[k] = false;
+            if (j < cnt && local >= 0 && local < L) {
                 const uint2 sl = s_slots[local];
                 if (sl.y != DPG_HASH_EMPTY) {
-                    if (sl.x == q) {
-                        r = (int32_t)sl.y;
-                    } else {
-                        const int64_t a = max((int64_t)ov_off[h], (int64_t)0);
-                        const int64_t e = min((int64_t)ov_off[h + 1], n_keys);
-                        for (int64_t x = a; x < e; ++x) {
-                            const uint2 o = ov[x];
-                            if (o.x == q) {
-                                r = (int32_t)o.y;
-                                break;
-                            }
-                        }
-                    }
+                    if (sl.x == qk[k]) r[k] = (int32_t)sl.y;
+                    else need[k] = true;
                 }
             }
-            internal[k0 + j] = r;
+        }
+        // 2. the overflow ranges, all loads in flight together
+        int64_t a[kHashProbeBatch], e[kHashProbeBatch];
+#pragma unroll
+        for (int k = 0; k < kHashProbeBatch; ++k) {
+            a[k] = 0;
+            e[k] = 0;
+            if (need[k]) {
+                a[k] = max((int64_t)ov_off[hk[k]], (int64_t)0);
+                e[k] = min((int64_t)ov_off[hk[k] + 1], n_keys);
+            }
+        }
+        // 3. the first key of each range that matches
+#pragma unroll
+        for (int k = 0; k < kHashProbeBatch; ++k) {
+            for (int64_t x = a[k]; x < e[k]; ++x) {
+                const uint2 o = ov[x];
+                if (o.x == qk[k]) {
+                    r[k] = (int32_t)o.y;
+                    break;
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kHashProbeBatch; ++k) {
+            const int j = j0 + (int)threadIdx.x + k * kHashProbeThreads;
+            if (j < cnt) internal[k0 + j] = r[k];
         }
     }
 }
