@@ -54,6 +54,9 @@ def parse():
                     help="1: also run the autotuner over the DPG plans and report its pick")
     ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,btree,skew,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--join-zipf", default="0,0.8,1.2", help="Zipf exponents of the join section")
+    ap.add_argument("--join-variants", default="move_dpg,move_direct,sort_dpg,sort_direct,keyed",
+                    help="join variants to time: move_dpg, move_direct, sort_dpg, sort_direct, keyed")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates rocprofv3 byte counters)")
     ap.add_argument("--counters", default=os.path.join(ROOT, "profiles", "counters.json"),
@@ -105,8 +108,13 @@ def cpu_baseline(src_dev, rids_np, rec_bytes, target_s):
     }
 
 
+NO_CPU = False  # --no-cpu: no oracle timings (their entries are null)
+
+
 def oracle_rate(fn, units: float, unit: str, sample: str):
     """The oracle timed on a bounded sample of a section's workload (one core)."""
+    if NO_CPU:
+        return None
     t0 = time.perf_counter()
     fn()
     dt = time.perf_counter() - t0
@@ -155,13 +163,6 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         rids = synth.rids_blocked(n, R, seed, backend="torch", device=dev)
     m = rids.numel()
     dst = torch.empty((m, R), dtype=torch.uint8, device=dev)
-    if args.calib_copy:
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
-        b = torch.empty_like(a)
-        torch.cuda.synchronize()
-        b.copy_(a)  # reads and writes exactly 1 GiB
-        torch.cuda.synchronize()
-        del a, b
     tuned = None
     if args.log2_run or args.probe or args.dist:
         ctx.set_option(dpg.OPT_LOG2_RUN, args.log2_run)
@@ -311,10 +312,13 @@ def bench_join(args, ctx, dpg, synth, torch, np):
     out = torch.empty((n_fact, 80), dtype=torch.uint8, device=dev)
     res = {}
     steps = max(2, args.steps // 3)
-    for s in (0.0, 0.8, 1.2):
+    variants = set(v for v in args.join_variants.split(",") if v)
+    for s in (float(z) for z in args.join_zipf.split(",") if z):
         fact = synth.fact_table(n_fact, n_dim, s, seed, backend="torch", device=dev)
         for order, oname in ((dpg.JOIN_FACT_ORDER, "dpg_move"), (dpg.JOIN_DIM_ORDER, "dpg_sort")):
             for algo, aname in ((dpg.ALGO_DPG, "dpg"), (dpg.ALGO_DIRECT, "direct")):
+                if f"{oname[4:]}_{aname}" not in variants:
+                    continue
                 ws = torch.empty(max(1, ctx.fk_join_workspace_bytes(n_fact, 16, 0, n_dim, 64, order, algo)),
                                  dtype=torch.uint8, device=dev)
                 ctx.profile_enable(True)
@@ -328,7 +332,7 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                                                    "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2),
                                                    "roofline": roofline_entry(prof, list(prof), None)}
                 del ws
-        if s == 0.0:
+        if s == 0.0 and "keyed" in variants:
             # the same join over non-dense keys: dimension keys are distinct
             # odd uint32, and the fk column holds the key of the row it names
             keys = (2 * synth.rids_permutation(1 << 30, seed, backend="torch", device=dev, count=n_dim).to(torch.int64)
@@ -350,6 +354,7 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                                                      "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
                     del ws
             del dim_k, fact_k, keys, index
+        if s == 0.0:
             import oracle
 
             f_host, d_host = fact[: 1 << 22].cpu().numpy(), dim.cpu().numpy()
@@ -706,7 +711,9 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
 
 
 def main():
+    global NO_CPU
     args = parse()
+    NO_CPU = args.no_cpu
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is not built)", file=sys.stderr)
@@ -722,6 +729,13 @@ def main():
         with open(args.counters) as f:
             counters = json.load(f)
     ctx = dpg.Context(0)
+    if args.calib_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads and writes exactly 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     out = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u8", "data": "synthetic"}
