@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
-    ap.add_argument("--only", default="", help="comma list of sections: retrieve,sort,join,smj,hash,btree,skew,serve (default all)")
+    ap.add_argument("--only", default="",
+                    help="comma list of sections: retrieve,small,sort,join,smj,hash,btree,skew,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--join-zipf", default="0,0.8,1.2", help="Zipf exponents of the join section")
     ap.add_argument("--join-variants", default="move_dpg,move_direct,sort_dpg,sort_direct,keyed",
@@ -246,6 +247,22 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     b_min = 4.0 * m + R * touched + R * m
     out["eta_min"] = {"bytes": b_min, "dpg": round(b_min / (ms_dpg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4),
                       "direct": round(b_min / (ms_direct * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+    # each method's own algorithmic bytes over its whole step:
+    #   DPG, three phases: 24M + R*N + 3R*M (distribute: rids read twice and
+    #     run + inv written, 16M; probe: run 4M + source R*N + INTERNAL R*M;
+    #     gather: inv 4M + INTERNAL R*M + dst R*M)
+    #   DPG, two phases (the probe writes dst): 24M + R*N + R*M
+    #   direct: 4M + f*M + R*M, f = bytes of the 64-byte sectors a record
+    #     touches, on average over the record offsets
+    f_r = 64.0 * sum(((j * R) % 64 + R + 63) // 64 for j in range(64)) / 64.0
+    two_phase = plan.gather == 3
+    b_dpg = 24.0 * m + R * touched + (1 if two_phase else 3) * R * m
+    b_direct = 4.0 * m + f_r * m + R * m
+    out["eta_alg"] = {
+        "dpg": {"form": "two phases" if two_phase else "three phases", "bytes": b_dpg,
+                "frac": round(b_dpg / (ms_dpg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)},
+        "direct": {"sector_bytes_per_record": f_r, "bytes": b_direct,
+                   "frac": round(b_direct / (ms_direct * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}}
     a = torch.empty(1 << 32, dtype=torch.uint8, device=dev).fill_(1)
     b = torch.empty_like(a)
     copy_ms, _ = time_steps(lambda: b.copy_(a), 5, 1, torch)
@@ -261,6 +278,55 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     del src, rids, dst, ws
     torch.cuda.empty_cache()
     return out, cpu
+
+
+def bench_small(args, ctx, dpg, synth, torch, np):
+    """2^20 records of 100 B and a permutation of 2^20 rids (the paper's
+    1M x 100 B workload): source and output fit the 256 MiB Infinity Cache,
+    so each call is timed warm (repeated on the same buffers) and cold (a
+    1 GiB write before every call evicts the cache).  Median and minimum of
+    20 calls, HIP events around each call."""
+    dev = "cuda:0"
+    n, R = 1 << 20, 100
+    seed = synth.SEED_BASE + 1
+    src = synth.record_bytes(n, R, seed, backend="torch", device=dev)
+    rids = synth.rids_permutation(n, seed, backend="torch", device=dev)
+    dst = torch.empty((n, R), dtype=torch.uint8, device=dev)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    log("bench: 2^20 x 100 B retrieval, warm and cold")
+    res = {"workload": "2^20 records of 100 B (10-byte key + 90-byte payload), rids a permutation of 2^20; "
+                       "cold: a 1 GiB write before each call"}
+    reps = 20
+    for algo, name in ((dpg.ALGO_DPG, "dpg"), (dpg.ALGO_DIRECT, "direct")):
+        plan = ctx.plan_retrieve(n, R, n, algo)
+        ws = torch.empty(max(1, plan.workspace_bytes), dtype=torch.uint8, device=dev)
+        call = lambda: ctx.retrieve(src, rids, dst=dst, algo=algo, workspace=ws)
+        entry = {}
+        for mode in ("warm", "cold"):
+            for _ in range(3):
+                call()
+            times = []
+            for _ in range(reps):
+                if mode == "cold":
+                    flush.fill_(1)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                call()
+                e1.record()
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1) * 1e3)
+            times.sort()
+            med = times[reps // 2]
+            entry[mode] = {"median_us": round(med, 1), "min_us": round(times[0], 1),
+                           "GB_per_s": round(n * R / (med * 1e-6) / 1e9, 1)}
+        pick = torch.arange(0, n, 4099, device=dev)
+        if not torch.equal(dst[pick], src[rids[pick].to(torch.int64)]):
+            raise SystemExit(f"bench: 2^20 x 100 B {name} retrieval differs from src[rids]")
+        res[name] = entry
+        del ws
+    del src, rids, dst, flush
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_sort(args, ctx, dpg, synth, torch, np):
@@ -723,7 +789,8 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "sort", "join", "smj", "hash", "btree", "skew", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "small", "sort", "join", "smj", "hash", "btree",
+                                                          "skew", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -743,6 +810,8 @@ def main():
     if "retrieve" in only:
         r, cpu = bench_retrieve(args, ctx, dpg, synth, torch, np, counters)
         out.update(r)
+    if "small" in only:
+        out["small_1m_x_100B"] = bench_small(args, ctx, dpg, synth, torch, np)
     if "sort" in only:
         out["sort"] = bench_sort(args, ctx, dpg, synth, torch, np)
     if "join" in only:
