@@ -176,6 +176,7 @@ struct RetrievePlan {
     bool scatter = false;      // two phases: the probe writes dst[pos] directly (no INTERNAL, no gather)
     int part_tile = 0;         // rids per partition tile (gather_lds)
     int wide_per = 16;         // rids per thread of a 1024-thread partition pass (8: half-size tiles)
+    bool part_wide = false;    // the one-pass distribute takes the 1024-thread pass at any run count
     // DIST_SAMPLED: the sample, its sorted copy, its sort scratch, the splitters
     int64_t n_sample = 0;
     size_t off_sample = 0, off_sample2 = 0, off_spart = 0, off_split = 0;

@@ -28,13 +28,15 @@ struct PartPlan {
 // Layout of the scratch one pass needs (count matrix and bucket offsets).
 // nbits up to kMaxDigitBits for any pass; up to kMaxWideBits only for uint32
 // keys without values, which are then partitioned without stability, by
-// 1024-thread workgroups of wide_per (8 or 16) keys per thread.
-PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per = 16);
+// 1024-thread workgroups of wide_per (8 or 16) keys per thread.  wide: use
+// that 1024-thread unstable pass for any digit width (uint32 keys without
+// values only).
+PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per = 16, bool wide = false);
 
 // The partition pass of a planned one-pass DPG distribute (DIST_PARTITION or
 // DIST_SAMPLED).
 inline PartPlan dist_partition(const RetrievePlan &p) {
-    return plan_partition(p.n_rids, p.part_nbits, 4, false, p.wide_per);
+    return plan_partition(p.n_rids, p.part_nbits, 4, false, p.wide_per, p.part_wide);
 }
 
 // One pass: elements whose key is < limit (any key if limit is 0) move to the

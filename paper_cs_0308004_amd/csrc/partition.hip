@@ -433,14 +433,14 @@ static int part_per(int key_bytes, bool has_val) {
     return 16;
 }
 
-PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per) {
+PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per, bool wide) {
     PartPlan p;
     p.n = n;
     p.nbits = nbits;
     p.key_bytes = key_bytes;
     p.has_val = has_val;
     p.per = part_per(key_bytes, has_val);
-    if (nbits > kMaxDigitBits) {  // wide unstable pass: 1024 threads x 8 or 16 keys
+    if (nbits > kMaxDigitBits || (wide && key_bytes == 4 && !has_val)) {  // 1024 threads x 8 or 16 keys
         p.threads = 1024;
         p.per = wide_per == 8 ? 8 : 16;
     }
@@ -488,7 +488,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     int32_t *bucket_off = (int32_t *)(w + p.off_bucket);
     if (bucket_off_dev) *bucket_off_dev = bucket_off;
     if (p.n <= 0) return DPG_OK;
-    const bool wide = p.nbits > kMaxDigitBits;
+    const bool wide = p.threads == 1024;  // the 1024-thread unstable pass
     if (p.nbits < 1 || p.nbits > kMaxWideBits) return DPG_ERR_UNSUPPORTED;
     if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || (p.per != 8 && p.per != 16)))
         return DPG_ERR_UNSUPPORTED;

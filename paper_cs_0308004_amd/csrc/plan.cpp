@@ -63,7 +63,7 @@ static void layout_workspace(RetrievePlan *p) {
     if (p->algo == DPG_ALGO_DPG) {
         const int64_t B = p->n_runs, M = p->n_rids;
         if (p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) {
-            const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per);
+            const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per, p->part_wide);
             p->off_part = take(pp.workspace);
             p->off_bucket = p->off_part + pp.off_bucket;
             p->off_items = take((size_t)((1 << p->part_nbits) + 1) * 4);
@@ -97,6 +97,10 @@ static void layout_workspace(RetrievePlan *p) {
     }
     p->workspace = off;
 }
+
+// Rid lists shorter than this take partition tiles of 8192 rids (8 per
+// thread), so that Phase I still spreads over 2 x 256 CUs.
+constexpr int64_t kSmallTileRids = (int64_t)1 << 23;
 
 // LDS a workgroup of the LDS-staged gather may use (gather_lds_bytes).
 constexpr size_t kGatherLdsBytes = 150 * 1024;
@@ -138,9 +142,9 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     } else if (probe == DPG_PROBE_LDS) {
         lg = want_wide ? lg_wide : lg_lds;
     } else {
-        // records under 16 bytes: 2 MiB regions (the probe's random reads then
+        // records up to 16 bytes: 2 MiB regions (the probe's random reads then
         // hit L2 most); larger records: 4 MiB (measured at 2^26 rids)
-        lg = floor_log2((R < 16 ? kCachedRegionBytes / 2 : kCachedRegionBytes) / (size_t)R);
+        lg = floor_log2((R <= 16 ? kCachedRegionBytes / 2 : kCachedRegionBytes) / (size_t)R);
         if (lg < 0) lg = 0;
     }
     if (lg > lg_n) lg = lg_n;
@@ -152,6 +156,13 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
                              : sampled ? kMaxWideBuckets
                              : (dist_mode == 1 || log2_run > 0) ? kMaxRuns : kMaxWideBuckets;
     while (((N + ((int64_t)1 << lg) - 1) >> lg) > max_runs) ++lg;
+    // The LDS-staged gather of 8- and 16-byte records reads a tile of 8192
+    // rids as one segment per run: past 1024 runs the segments fall under 8
+    // rids and it slows down (2^28 records of 16 bytes: 6.25 ms with 2048
+    // runs, 5.86 ms with 1024), so automatic runs stop at 1024 there.
+    if (log2_run <= 0 && probe == DPG_PROBE_CACHED && (R == 8 || R == 16) && !want_scatter && !two_pass &&
+        dist_mode != DIST_APPEND + 1 && gather != 1)
+        while (((N + ((int64_t)1 << lg) - 1) >> lg) > 1024) ++lg;
     if (probe == DPG_PROBE_LDS && lg > (want_wide ? lg_wide : lg_lds)) probe = DPG_PROBE_CACHED;
     p->probe = probe;
     p->log2_run = lg;
@@ -172,7 +183,9 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
         p->dist_mode = DIST_SAMPLED;
         p->part_nbits = std::max(1, bit_length((uint64_t)(p->n_runs - 1)));
         p->n_sample = std::max<int64_t>(1, std::min<int64_t>(M, kSampleFactor * p->n_runs));
-        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+        p->part_wide = true;
+        p->wide_per = M < kSmallTileRids ? 8 : 16;
+        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per, true);
         p->dist_tile = pp.tile;
         p->n_tiles = pp.n_tiles;
         p->n_chunks = pp.n_chunks;
@@ -181,7 +194,12 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
         p->dist_mode = DIST_PARTITION;
         p->part_nbits = bit_length((uint64_t)(p->n_runs - 1));
         if (p->part_nbits < 1) p->part_nbits = 1;
-        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false);
+        // the 1024-thread unstable pass at any run count: at 2^26 rids it
+        // beats the 256-thread pass even with twice the runs (0.22 ms at 512
+        // runs against 0.27 ms at 256)
+        p->part_wide = true;
+        p->wide_per = M < kSmallTileRids ? 8 : 16;
+        const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per, true);
         p->dist_tile = pp.tile;
         p->n_tiles = pp.n_tiles;
         p->n_chunks = pp.n_chunks;
@@ -198,22 +216,22 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     }
     // Phase III through LDS when a partition tile's records fit (records of
     // 4, 8 or 16 bytes, one LDS element each): every global access of the
-    // gather is then coalesced.  A 1024-thread partition pass halves its tile
-    // when that makes the records fit (16-byte records over more than 256
-    // runs).
+    // gather is then coalesced.  The partition tile is then 16384 rids for
+    // 4-byte records and 8192 (8 per thread) otherwise, so that two gather
+    // workgroups share a CU up to 8-byte records and 16-byte records fit.
     if ((p->dist_mode == DIST_PARTITION || p->dist_mode == DIST_SAMPLED) && gather != 1 &&
         (R == 4 || R == 8 || R == 16)) {
-        size_t lds = gather_lds_bytes(p->dist_tile, R, p->part_nbits);
-        if (lds > kGatherLdsBytes && p->part_nbits > kMaxDigitBits && !want_scatter) {
-            const PartPlan ph = plan_partition(M, p->part_nbits, 4, false, 8);
-            if (gather_lds_bytes(ph.tile, R, p->part_nbits) <= kGatherLdsBytes) {
-                p->wide_per = 8;
-                p->dist_tile = ph.tile;
-                p->n_tiles = ph.n_tiles;
-                p->n_chunks = ph.n_chunks;
-                lds = gather_lds_bytes(ph.tile, R, p->part_nbits);
-            }
+        int per = R == 4 && M >= kSmallTileRids ? 16 : 8;
+        PartPlan pt = plan_partition(M, p->part_nbits, 4, false, per, true);
+        if (per == 16 && gather_lds_bytes(pt.tile, R, p->part_nbits) > kGatherLdsBytes) {
+            per = 8;
+            pt = plan_partition(M, p->part_nbits, 4, false, per, true);
         }
+        p->wide_per = per;
+        p->dist_tile = pt.tile;
+        p->n_tiles = pt.n_tiles;
+        p->n_chunks = pt.n_chunks;
+        const size_t lds = gather_lds_bytes(pt.tile, R, p->part_nbits);
         p->gather_lds = lds <= kGatherLdsBytes;
         p->part_tile = p->dist_tile;
     }

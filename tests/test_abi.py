@@ -170,14 +170,20 @@ def test_plan_phase_forms():
         assert p.n_runs <= 2048 and p.ws_internal == 0
     p = dpg.plan_retrieve(1 << 26, 8, 1 << 26, dpg.ALGO_DIRECT)
     assert p.distribute == 0 and p.gather == 0
-    # 16-byte records over more than 256 runs: the 1024-thread partition pass
-    # takes tiles of 8192 rids (not 16384), so that a tile's records fit the
-    # LDS of the gather; 8-byte records keep tiles of 16384
-    p = dpg.plan_retrieve(1 << 28, 16, 1 << 28, dpg.ALGO_DPG)
-    assert p.n_runs == 1024 and p.gather == dpg.GATHER_LDS and p.dist_tile == 8192
-    assert p.n_tiles == (1 << 28) // 8192
-    p = dpg.plan_retrieve(1 << 28, 8, 1 << 28, dpg.ALGO_DPG)
-    assert p.n_runs == 1024 and p.gather == dpg.GATHER_LDS and p.dist_tile == 16384
+    # the one-pass distribute takes the 1024-thread partition pass at any run
+    # count; with the LDS-staged gather its tiles are 16384 rids for 4-byte
+    # records and 8192 otherwise, and automatic runs of 8- and 16-byte records
+    # stop at 1024 (2 MiB regions below that)
+    for n, rec, runs, tile in ((1 << 26, 4, 2048, 16384), (1 << 26, 8, 256, 8192), (1 << 26, 16, 512, 8192),
+                               (1 << 28, 8, 1024, 8192), (1 << 28, 16, 1024, 8192)):
+        p = dpg.plan_retrieve(n, rec, n, dpg.ALGO_DPG)
+        assert (p.n_runs, p.gather, p.dist_tile) == (runs, dpg.GATHER_LDS, tile), (n, rec)
+        assert p.n_tiles == n // tile
+    # short rid lists take tiles of 8192 rids so that Phase I fills the chip
+    p = dpg.plan_retrieve(1 << 20, 100, 1 << 20, dpg.ALGO_DPG)
+    assert p.dist_tile == 8192 and p.n_tiles == 128
+    p = dpg.plan_retrieve(1 << 26, 100, 1 << 26, dpg.ALGO_DPG)
+    assert p.dist_tile == 16384 and p.n_runs == 2048
 
 
 def test_hash_index_layout_and_validation():
