@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--log2-run", type=int, default=0, help="force L = 2^v records per run (0: planner's choice)")
     ap.add_argument("--probe", type=int, default=0, help="1 cached, 2 LDS (0: planner's choice)")
     ap.add_argument("--dist", type=int, default=0, help="Phase I: 1 append, 2 partition (0: planner's choice)")
+    ap.add_argument("--gather", type=int, default=0,
+                    help="Phase III: 1 cached, 2 LDS, 3 none (the probe writes dst) (0: planner's choice)")
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
     ap.add_argument("--only", default="",
@@ -165,10 +167,11 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     m = rids.numel()
     dst = torch.empty((m, R), dtype=torch.uint8, device=dev)
     tuned = None
-    if args.log2_run or args.probe or args.dist:
+    if args.log2_run or args.probe or args.dist or args.gather:
         ctx.set_option(dpg.OPT_LOG2_RUN, args.log2_run)
         ctx.set_option(dpg.OPT_PROBE, args.probe)
         ctx.set_option(dpg.OPT_DISTRIBUTE, args.dist)
+        ctx.set_option(dpg.OPT_GATHER, args.gather)
     elif args.autotune:
         # the autotuner's pick is reported next to the planner's default plan,
         # which is what is timed (a fixed plan keeps profiles comparable)
@@ -273,7 +276,7 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
         cpu = cpu_baseline(src, rids_np, R, args.cpu_seconds)
-    for opt in (dpg.OPT_LOG2_RUN, dpg.OPT_PROBE, dpg.OPT_DISTRIBUTE):
+    for opt in (dpg.OPT_LOG2_RUN, dpg.OPT_PROBE, dpg.OPT_DISTRIBUTE, dpg.OPT_GATHER):
         ctx.set_option(opt, 0)
     del src, rids, dst, ws
     torch.cuda.empty_cache()
