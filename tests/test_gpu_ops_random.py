@@ -55,7 +55,7 @@ def random_queries(rng, np_rng, keys: np.ndarray, m: int) -> np.ndarray:
     return q
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(40))
 def test_random_join_matches_oracle(ctx, case):
     rng = random.Random(0x51 + case)
     np_rng = np.random.default_rng(0x51 + case)
@@ -84,7 +84,7 @@ def test_random_join_matches_oracle(ctx, case):
         configure(ctx, {})
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(40))
 def test_random_hash_lookup_matches_oracle(ctx, case):
     rng = random.Random(0x61 + case)
     np_rng = np.random.default_rng(0x61 + case)
@@ -106,7 +106,7 @@ def test_random_hash_lookup_matches_oracle(ctx, case):
         configure(ctx, {})
 
 
-@pytest.mark.parametrize("case", range(24))
+@pytest.mark.parametrize("case", range(40))
 def test_random_btree_lookup_matches_oracle(ctx, case):
     rng = random.Random(0x71 + case)
     np_rng = np.random.default_rng(0x71 + case)

@@ -1,4 +1,4 @@
-"""Seeded random retrievals against the oracle: record sizes, source and list
+"""Seeded random retrievals against the oracle (200 cases): record sizes, source and list
 lengths, rid patterns, source alignment and forced plan options drawn at
 random, so that combinations no hand-written case names are covered too
 (every Phase I / II / III form, tile counts around the partition tile,
@@ -55,7 +55,7 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("case", range(80))
+@pytest.mark.parametrize("case", range(200))
 def test_random_retrieval_matches_oracle(ctx, case):
     R, src_np, rids_np, opts, offset = draw(case)
     want = oracle.retrieve(src_np, rids_np)
