@@ -83,31 +83,78 @@ def time_steps(fn, steps, warmup, torch):
     return e0.elapsed_time(e1) / steps, wall
 
 
+def time_and_profile(ctx, fn, steps, warmup, torch):
+    """Time `steps` calls with per-kernel profiling off (the reported
+    ms/step), then run the same number of calls again with HIP events around
+    every launch for the per-kernel durations.  Returns (ms, wall_s, prof)."""
+    ms, wall = time_steps(fn, steps, warmup, torch)
+    ctx.profile_enable(True)
+    ctx.profile_reset()
+    try:
+        for _ in range(steps):
+            fn()
+        torch.cuda.synchronize()
+        prof = ctx.profile_collect()
+    finally:
+        ctx.profile_enable(False)
+        ctx.profile_reset()
+    return ms, wall, prof
+
+
+def host_threads() -> int:
+    """Host cores this process may use (at most 16, the GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def timed_oracle(fn, items, threads):
+    """Wall time of fn over every item, on `threads` host threads (the
+    oracle's C routines release the GIL, so the items run in parallel)."""
+    import concurrent.futures as cf
+
+    t0 = time.perf_counter()
+    if threads == 1:
+        for it in items:
+            fn(it)
+    else:
+        with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+            list(ex.map(fn, items))
+    return time.perf_counter() - t0
+
+
 def cpu_baseline(src_dev, rids_np, rec_bytes, target_s):
-    """The oracle (single-threaded C loop) on a bounded prefix of the rid list,
-    against the full source copied to host memory."""
+    """The oracle's retrieval loop, as it stands, on a bounded prefix of the
+    rid list against the full source copied to host memory: once on one
+    core, and once with the prefix cut into disjoint slices run on every host
+    core at the same time."""
     import oracle
 
     src = src_dev.cpu().numpy()
     m_total = rids_np.size
     m = min(m_total, 1 << 20)
-    t0 = time.perf_counter()
-    oracle.retrieve(src, rids_np[:m])
-    dt = time.perf_counter() - t0
+    dt = timed_oracle(lambda r: oracle.retrieve(src, r), [rids_np[:m]], 1)
     if dt < target_s and m < m_total:
         m = int(min(m_total, m * max(1.0, target_s / max(dt, 1e-3))))
-        t0 = time.perf_counter()
-        oracle.retrieve(src, rids_np[:m])
-        dt = time.perf_counter() - t0
+        dt = timed_oracle(lambda r: oracle.retrieve(src, r), [rids_np[:m]], 1)
+    threads = host_threads()
+    step = -(-m // (4 * threads))
+    slices = [rids_np[a:min(m, a + step)] for a in range(0, m, step)]
+    dt_all = timed_oracle(lambda r: oracle.retrieve(src, r), slices, threads)
     del src
+    cpu = platform.processor() or platform.machine()
     return {
-        "value": round(m * rec_bytes / dt / 1e9, 3),
+        "value": round(m * rec_bytes / dt_all / 1e9, 3),
         "unit": "GB/s",
-        "cores": 1,
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"first {m} of {m_total} rids over the full {rec_bytes}-byte source; "
-                  f"{dt:.2f} s single-threaded on {platform.processor() or platform.machine()} "
-                  f"(host reports {os.cpu_count()} logical CPUs)",
+        "sample": f"first {m} of {m_total} rids over the full {rec_bytes}-byte source, cut into "
+                  f"{len(slices)} slices on {threads} threads: {dt_all:.2f} s ({cpu}; host reports "
+                  f"{os.cpu_count()} logical CPUs)",
+        "single_core": {"value": round(m * rec_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
+                        "sample": f"the same {m} rids on one thread: {dt:.2f} s"},
     }
 
 
@@ -115,14 +162,18 @@ NO_CPU = False  # --no-cpu: no oracle timings (their entries are null)
 
 
 def oracle_rate(fn, units: float, unit: str, sample: str):
-    """The oracle timed on a bounded sample of a section's workload (one core)."""
+    """The oracle timed on a bounded sample of a section's workload: one call
+    of fn on one core, then one call per host core, all at once (independent
+    copies of the same work; the throughput counts every copy)."""
     if NO_CPU:
         return None
-    t0 = time.perf_counter()
-    fn()
-    dt = time.perf_counter() - t0
-    return {"value": round(units / dt, 1), "unit": unit, "cores": 1, "kind": "oracle",
-            "sample": f"{sample}; {dt:.2f} s single-threaded"}
+    dt1 = timed_oracle(lambda _: fn(), [None], 1)
+    threads = host_threads()
+    dtn = timed_oracle(lambda _: fn(), [None] * threads, threads)
+    return {"value": round(threads * units / dtn, 1), "unit": unit, "cores": threads, "kind": "oracle",
+            "sample": f"{sample}: {threads} copies at once on {threads} threads, {dtn:.2f} s",
+            "single_core": {"value": round(units / dt1, 1), "unit": unit, "cores": 1,
+                            "sample": f"one copy on one thread, {dt1:.2f} s"}}
 
 
 def roofline_entry(prof: dict, kernels: list[str], counters: dict | None, workload_key: str | None = None):
@@ -194,17 +245,8 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         ctx.retrieve(src, rids, dst=dst, algo=dpg.ALGO_DIRECT, workspace=ws_direct, stream=stream)
 
     log(f"bench: plan L=2^{plan.log2_run} runs={plan.n_runs} tile={plan.dist_tile} probe={plan.probe}")
-    ctx.profile_enable(True)
-    step_dpg()
-    torch.cuda.synchronize()
-    ctx.profile_reset()
-    ms_dpg, wall_dpg = time_steps(step_dpg, args.steps, args.warmup, torch)
-    prof_dpg = ctx.profile_collect()
-    ctx.profile_reset()
-    ms_direct, _ = time_steps(step_direct, args.steps, args.warmup, torch)
-    prof_direct = ctx.profile_collect()
-    ctx.profile_enable(False)
-    ctx.profile_reset()
+    ms_dpg, wall_dpg, prof_dpg = time_and_profile(ctx, step_dpg, args.steps, args.warmup, torch)
+    ms_direct, _, prof_direct = time_and_profile(ctx, step_direct, args.steps, args.warmup, torch)
     log(f"bench: dpg {ms_dpg:.3f} ms/step, direct {ms_direct:.3f} ms/step")
     # the timed output, spot-checked against the generator
     sample = np.random.default_rng(0).integers(0, m, 256)
@@ -266,12 +308,7 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
                 "frac": round(b_dpg / (ms_dpg * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)},
         "direct": {"sector_bytes_per_record": f_r, "bytes": b_direct,
                    "frac": round(b_direct / (ms_direct * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}}
-    a = torch.empty(1 << 32, dtype=torch.uint8, device=dev).fill_(1)
-    b = torch.empty_like(a)
-    copy_ms, _ = time_steps(lambda: b.copy_(a), 5, 1, torch)
-    out["copy_ceiling"] = {"GB_per_s": round(2.0 * a.numel() / (copy_ms * 1e-3) / 1e9, 1),
-                           "what": "torch copy_ of 4 GiB device to device (reads and writes 4 GiB)"}
-    del a, b
+    out["copy_ceiling"] = copy_ceiling(ctx, torch)
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
@@ -281,6 +318,28 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     del src, rids, dst, ws
     torch.cuda.empty_cache()
     return out, cpu
+
+
+def copy_ceiling(ctx, torch):
+    """The library's plain streaming copy (dpg_stream_copy) of 4 GiB, device
+    to device, over its launch shapes: the practical read + write ceiling of
+    a phase that reads its bytes once and writes them once."""
+    a = torch.empty(1 << 32, dtype=torch.uint8, device="cuda:0").fill_(1)
+    b = torch.empty_like(a)
+    shapes = {}
+    for per in (4, 8, 16):
+        for nt in (True, False):
+            ms, _ = time_steps(lambda: ctx.stream_copy(a, b, per, nt), 5, 2, torch)
+            shapes[f"{per}x16B_{'nt' if nt else 'plain'}"] = round(2.0 * a.numel() / (ms * 1e-3) / 1e9, 1)
+    if not torch.equal(a[::4099], b[::4099]):
+        raise SystemExit("bench: the streaming copy differs from its source")
+    torch_ms, _ = time_steps(lambda: b.copy_(a), 5, 2, torch)
+    del a, b
+    torch.cuda.empty_cache()
+    best = max(shapes, key=shapes.get)
+    return {"GB_per_s": shapes[best], "shape": best, "shapes_GB_per_s": shapes,
+            "torch_copy_GB_per_s": round(2.0 * (1 << 32) / (torch_ms * 1e-3) / 1e9, 1),
+            "what": "k_stream_copy of 4 GiB device to device (reads and writes 4 GiB); best launch shape"}
 
 
 def bench_small(args, ctx, dpg, synth, torch, np):
@@ -344,14 +403,9 @@ def bench_sort(args, ctx, dpg, synth, torch, np):
     steps = max(2, args.steps // 3)
     for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
         ws = torch.empty(ctx.sort_workspace_bytes(n, R, 0, 10, algo), dtype=torch.uint8, device=dev)
-        ctx.profile_enable(True)
-        ctx.profile_reset()
-        ms, _ = time_steps(lambda: ctx.sort_records(src, 0, 10, dst=dst, perm=perm, algo=algo, workspace=ws),
-                           steps, 1, torch)
-        prof = ctx.profile_collect()
-        ctx.profile_enable(False)
-        ctx.profile_reset()
-        calls = steps + 1
+        ms, _, prof = time_and_profile(
+            ctx, lambda: ctx.sort_records(src, 0, 10, dst=dst, perm=perm, algo=algo, workspace=ws), steps, 1, torch)
+        calls = steps
         res[name] = {"ms": round(ms, 3), "records_per_s": round(n / (ms * 1e-3), 1),
                      "GB_per_s": round(n * R / (ms * 1e-3) / 1e9, 2),
                      "kernels_ms_per_sort": {k: round(v["ms"] / calls, 4) for k, v in prof.items()},
@@ -390,13 +444,8 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                     continue
                 ws = torch.empty(max(1, ctx.fk_join_workspace_bytes(n_fact, 16, 0, n_dim, 64, order, algo)),
                                  dtype=torch.uint8, device=dev)
-                ctx.profile_enable(True)
-                ctx.profile_reset()
-                ms, _ = time_steps(lambda: ctx.fk_join(fact, dim, 0, order, out=out, algo=algo, workspace=ws),
-                                   steps, 1, torch)
-                prof = ctx.profile_collect()
-                ctx.profile_enable(False)
-                ctx.profile_reset()
+                ms, _, prof = time_and_profile(
+                    ctx, lambda: ctx.fk_join(fact, dim, 0, order, out=out, algo=algo, workspace=ws), steps, 1, torch)
                 res[f"zipf{s}_{oname}_{aname}"] = {"ms": round(ms, 3),
                                                    "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2),
                                                    "roofline": roofline_entry(prof, list(prof), None)}
@@ -466,21 +515,17 @@ def bench_smj(args, ctx, dpg, synth, torch, np):
     for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
         ws = torch.empty(ctx.sort_merge_join_workspace_bytes(n, R, 0, n, R, 0, 4, algo), dtype=torch.uint8,
                          device=dev)
-        ctx.profile_enable(True)
-        ctx.profile_reset()
         got = []
-        ms, _ = time_steps(lambda: got.append(ctx.sort_merge_join(rel[0], rel[1], 0, 0, 4, algo=algo, out=out,
-                                                                   workspace=ws)), steps, 1, torch)
-        prof = ctx.profile_collect()
-        ctx.profile_enable(False)
-        ctx.profile_reset()
+        ms, _, prof = time_and_profile(
+            ctx, lambda: got.append(ctx.sort_merge_join(rel[0], rel[1], 0, 0, 4, algo=algo, out=out, workspace=ws)),
+            steps, 1, torch)
         rows = got[-1]
         if rows.shape[0] != want_rows or not torch.equal(rows[:, 0:4], rows[:, R:R + 4]):
             raise SystemExit(f"bench: {name} sort-merge join result is wrong")
         kk = rows[:, 0:4].flip(1).contiguous().view(torch.int32).view(-1).to(torch.int64) & 0xFFFFFFFF
         if not bool((kk[1:] >= kk[:-1]).all()):
             raise SystemExit(f"bench: {name} sort-merge join result is not in key order")
-        calls = steps + 1
+        calls = steps
         res[name] = {"ms": round(ms, 3), "input_rows_per_s": round(2 * n / (ms * 1e-3), 1),
                      "kernels_ms_per_join": {k: round(v["ms"] / calls, 4) for k, v in prof.items()},
                      "roofline": roofline_entry(prof, list(prof), None)}
@@ -520,15 +565,9 @@ def bench_hash(args, ctx, dpg, synth, torch, np):
     res = {"workload": f"batch lookup of 2^26 uint32 keys (80% stored) in a hash index of 2^24 distinct keys, "
                        f"2^{s} slots + overflow array", "build_s": round(build_s, 4)}
     for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
-        ctx.profile_enable(True)
-        ctx.hash_lookup(index, n, s, queries, out, algo=algo, workspace=ws, stream=stream)
-        torch.cuda.synchronize()
-        ctx.profile_reset()
-        ms, _ = time_steps(lambda: ctx.hash_lookup(index, n, s, queries, out, algo=algo, workspace=ws,
-                                                   stream=stream), args.steps, args.warmup, torch)
-        prof = ctx.profile_collect()
-        ctx.profile_enable(False)
-        ctx.profile_reset()
+        ms, _, prof = time_and_profile(
+            ctx, lambda: ctx.hash_lookup(index, n, s, queries, out, algo=algo, workspace=ws, stream=stream),
+            args.steps, args.warmup, torch)
         got = out.cpu().numpy()
         want = np.where(hit.cpu().numpy(), pick.cpu().numpy(), -1)
         if not np.array_equal(got, want):
@@ -575,15 +614,9 @@ def bench_btree(args, ctx, dpg, synth, torch, np):
            "build_s": round(build_s, 4)}
     want = np.where(hit.cpu().numpy(), pick.cpu().numpy(), -1)
     for name, algo in (("dpg", dpg.ALGO_DPG), ("direct", dpg.ALGO_DIRECT)):
-        ctx.profile_enable(True)
-        ctx.btree_lookup(tree, n, queries, out, algo=algo, workspace=ws, stream=stream)
-        torch.cuda.synchronize()
-        ctx.profile_reset()
-        ms, _ = time_steps(lambda: ctx.btree_lookup(tree, n, queries, out, algo=algo, workspace=ws,
-                                                    stream=stream), args.steps, args.warmup, torch)
-        prof = ctx.profile_collect()
-        ctx.profile_enable(False)
-        ctx.profile_reset()
+        ms, _, prof = time_and_profile(
+            ctx, lambda: ctx.btree_lookup(tree, n, queries, out, algo=algo, workspace=ws, stream=stream),
+            args.steps, args.warmup, torch)
         if not np.array_equal(out.cpu().numpy(), want):
             raise SystemExit(f"bench: {name} B+ tree lookup differs from the stored rids")
         res[name] = {"ms": round(ms, 4), "lookups_per_s": round(m / (ms * 1e-3), 1),

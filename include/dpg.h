@@ -506,6 +506,17 @@ void dpg_server_destroy(dpg_server *server);
 /* the algorithm must read and write, excluding cache effects) are recorded.  */
 /* ------------------------------------------------------------------------- */
 dpg_status dpg_profile_enable(dpg_ctx *ctx, int on);
+
+/* Measurement ceiling (not part of the method): copy `bytes` (a multiple of
+ * 16) from src to dst, both 16-byte aligned and not overlapping, as a plain
+ * stream of 16-byte vectors -- each lane loads vectors_per_lane (2, 4, 8 or 16)
+ * vectors before storing them, nontemporal = 1 uses streaming stores.  The
+ * read + write rate this reaches on large buffers is the practical roof the
+ * probe and gather phases (which also read once and write once) are held
+ * against.  DPG_ERR_INVALID_ARG for a bad size, alignment, overlap or
+ * option. */
+dpg_status dpg_stream_copy(dpg_ctx *ctx, const void *src, void *dst, size_t bytes, int32_t vectors_per_lane,
+                           int32_t nontemporal, hipStream_t stream);
 dpg_status dpg_profile_reset(dpg_ctx *ctx);
 /* Synchronizes the recorded events and folds them into per-kernel totals.
  * *n_kernels receives the number of distinct kernels seen. */

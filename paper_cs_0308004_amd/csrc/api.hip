@@ -12,7 +12,8 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_join_assemble", "k_batch",           "k_part_hist",     "k_part_scatter",   "k_part_hist_wide",
     "k_part_scatter_unstable", "k_gather_lds", "k_hash_home", "k_hash_mark", "k_hash_place",
     "k_hash_ov_off", "k_hash_direct", "k_hash_probe", "k_hash_probe_lds", "k_smj_keys", "k_smj_ranges",
-    "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds", "k_probe_scatter"};
+    "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds", "k_probe_scatter",
+    "k_stream_copy"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 
@@ -241,6 +242,17 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
         if (bad) return DPG_ERR_RID_OUT_OF_RANGE;
     }
     return run_retrieve(ctx, plan, src, rids, dst, workspace, stream);
+}
+
+dpg_status dpg_stream_copy(dpg_ctx *ctx, const void *src, void *dst, size_t bytes, int32_t vectors_per_lane,
+                           int32_t nontemporal, hipStream_t stream) {
+    if (!ctx || bytes % 16 != 0 || ((uintptr_t)src) % 16 != 0 || ((uintptr_t)dst) % 16 != 0 ||
+        (bytes > 0 && (!src || !dst)) || ranges_overlap(src, bytes, dst, bytes) ||
+        (nontemporal != 0 && nontemporal != 1))
+        return DPG_ERR_INVALID_ARG;
+    if (vectors_per_lane != 2 && vectors_per_lane != 4 && vectors_per_lane != 8 && vectors_per_lane != 16)
+        return DPG_ERR_INVALID_ARG;
+    return launch_stream_copy(ctx, src, dst, bytes, vectors_per_lane, nontemporal != 0, stream);
 }
 
 dpg_status dpg_profile_enable(dpg_ctx *ctx, int on) {

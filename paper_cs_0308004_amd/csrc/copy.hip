@@ -286,6 +286,62 @@ dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t l
     }
 }
 
+// Plain streaming copy: the practical read + write ceiling against which the
+// copy phases are measured.  Each workgroup copies one contiguous tile of
+// 256 * PER 16-byte vectors; a lane issues its PER loads before its first
+// store.  Stores are nontemporal unless asked otherwise.
+template <int PER, bool NT>
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4 *__restrict__ src, u32x4 *__restrict__ dst,
+                                                      int64_t n) {
+    const int64_t base = (int64_t)blockIdx.x * (256 * PER) + threadIdx.x;
+    u32x4 v[PER];
+    if (base + (int64_t)(PER - 1) * 256 < n) {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) v[k] = src[base + k * 256];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            if constexpr (NT) __builtin_nontemporal_store(v[k], dst + base + k * 256);
+            else dst[base + k * 256] = v[k];
+        }
+        return;
+    }
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = base + k * 256;
+        if (i < n) {
+            if constexpr (NT) __builtin_nontemporal_store(src[i], dst + i);
+            else dst[i] = src[i];
+        }
+    }
+}
+
+dpg_status launch_stream_copy(dpg_ctx *ctx, const void *src, void *dst, size_t bytes, int per, bool nt,
+                              hipStream_t stream) {
+    const int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return DPG_OK;
+    ProfScope prof(ctx, K_STREAM_COPY, 2.0 * (double)bytes, stream);
+    const int64_t grid = (n + 256 * per - 1) / (256 * per);
+    if (grid > 0x7fffffffLL) return DPG_ERR_UNSUPPORTED;
+#define DPG_LAUNCH_COPY(P)                                                                                    \
+    do {                                                                                                      \
+        if (nt)                                                                                               \
+            hipLaunchKernelGGL((k_stream_copy<P, true>), dim3((unsigned)grid), dim3(256), 0, stream,          \
+                               (const u32x4 *)src, (u32x4 *)dst, n);                                          \
+        else                                                                                                  \
+            hipLaunchKernelGGL((k_stream_copy<P, false>), dim3((unsigned)grid), dim3(256), 0, stream,         \
+                               (const u32x4 *)src, (u32x4 *)dst, n);                                          \
+    } while (0)
+    switch (per) {
+        case 2: DPG_LAUNCH_COPY(2); break;
+        case 4: DPG_LAUNCH_COPY(4); break;
+        case 8: DPG_LAUNCH_COPY(8); break;
+        case 16: DPG_LAUNCH_COPY(16); break;
+        default: return DPG_ERR_INVALID_ARG;
+    }
+#undef DPG_LAUNCH_COPY
+    DPG_HIP(hipGetLastError());
+    return DPG_OK;
+}
+
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t value) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = value;

@@ -76,6 +76,7 @@ enum KernelId {
     K_BT_PROBE,          //   DPG Phase II, walks over one run's subtrees through the caches
     K_BT_PROBE_LDS,      //   the same with the run's leaves staged in LDS
     K_PROBE_SCATTER,     // two-phase DPG: Phase II writes each record to its place in dst
+    K_STREAM_COPY,       // plain streaming copy (the measured copy ceiling)
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -251,6 +252,9 @@ dpg_status launch_probe_scatter(dpg_ctx *ctx, const void *src, int64_t limit, co
 dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t limit, const int32_t *idx,
                          void *dst, int64_t n, int rec_bytes, double alg_bytes, hipStream_t stream);
 dpg_status launch_fill_i32(dpg_ctx *ctx, int32_t *p, int64_t n, int32_t value, hipStream_t stream);
+// Plain copy of bytes / 16 16-byte vectors, per (2, 4, 8 or 16) vectors per lane.
+dpg_status launch_stream_copy(dpg_ctx *ctx, const void *src, void *dst, size_t bytes, int per, bool nt,
+                              hipStream_t stream);
 
 // ---- distribute (distribute.hip) ----
 dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,

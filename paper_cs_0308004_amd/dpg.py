@@ -141,6 +141,7 @@ SIGNATURES = {
     "dpg_tune_save": (_I32, [_VP, ctypes.c_char_p]),
     "dpg_tune_load": (_I32, [_VP, ctypes.c_char_p]),
     "dpg_profile_enable": (_I32, [_VP, ctypes.c_int]),
+    "dpg_stream_copy": (_I32, [_VP, _VP, _VP, _SZ, _I32, _I32, _VP]),
     "dpg_profile_reset": (_I32, [_VP]),
     "dpg_profile_collect": (_I32, [_VP, ctypes.POINTER(_I32)]),
     "dpg_profile_entry": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(_I64),
@@ -480,6 +481,14 @@ class Context:
         return workspace
 
     # ---- profiling -----------------------------------------------------
+    def stream_copy(self, src, dst, vectors_per_lane: int = 8, nontemporal: bool = True, stream=None):
+        """Plain device copy of src into dst (same byte size; the copy-ceiling kernel)."""
+        nbytes = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nbytes:
+            raise ValueError("src and dst differ in size")
+        _check(lib().dpg_stream_copy(self.handle, _addr(src), _addr(dst), nbytes, vectors_per_lane,
+                                     int(nontemporal), _stream(stream)), "dpg_stream_copy")
+
     def profile_enable(self, on: bool = True):
         _check(lib().dpg_profile_enable(self.handle, int(on)), "dpg_profile_enable")
 

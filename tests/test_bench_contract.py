@@ -48,3 +48,9 @@ def test_bench_line_contract():
     cpu = d["cpu_baseline"]
     assert cpu["kind"] == "oracle" and cpu["value"] > 0 and cpu["cores"] >= 1
     assert cpu["unit"] == "GB/s" and cpu["sample"]
+    assert cpu["single_core"]["cores"] == 1 and cpu["single_core"]["value"] > 0
+    # the timed steps run without per-kernel events; the kernels come from a
+    # second, profiled pass
+    assert set(d["kernels_ms_per_step"]) >= {"k_probe_cached", "k_gather_phase"}
+    ceil = d["copy_ceiling"]
+    assert ceil["GB_per_s"] == max(ceil["shapes_GB_per_s"].values()) > 0

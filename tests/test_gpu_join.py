@@ -71,43 +71,6 @@ def test_join_fk_offset_and_check(ctx, order):
         assert bool((out == 9).all())
 
 
-def test_join_full_size_sampled(ctx):
-    """Dimension 2^24 x 64 B, fact 2^28 x 16 B with Zipf(1.2) keys: the
-    benchmark's join workload.  Sampled rows against the oracle evaluated row
-    by row from the generator; the dimension-order output is checked in full for
-    nondecreasing keys, and its fact rows are a permutation of the input's."""
-    n_dim, n_fact, s = 1 << 24, 1 << 28, 1.2
-    seed = synth.SEED_BASE + 3
-    fact = synth.fact_table(n_fact, n_dim, s, seed, backend="torch", device=DEV)
-    dim = synth.dim_table(n_dim, seed, backend="torch", device=DEV)
-    idx = np.unique(np.random.default_rng(4).integers(0, n_fact, 20000))
-    fact_rows = synth.records_at(idx, 16, seed, synth.STREAM_FACT)
-    fk = synth.zipf_fk_at(n_dim, s, idx.astype(np.uint64), seed)
-    fact_rows[:, 0:4] = fk.astype(np.uint32).view(np.uint8).reshape(-1, 4)
-    dim_rows = synth.records_at(fk, 64, seed, synth.STREAM_DIM)
-    dim_rows[:, 0:4] = fk.astype(np.uint32).view(np.uint8).reshape(-1, 4)
-    # the oracle on a small problem holding just the sampled rows: mini fact
-    # row k points at mini dimension row k, then its key bytes are restored
-    mini_fact = fact_rows.copy()
-    mini_fact[:, 0:4] = np.arange(idx.size, dtype=np.uint32).view(np.uint8).reshape(-1, 4)
-    want = oracle.fk_join_fact_order(mini_fact, dim_rows, 0)
-    want[:, 0:4] = fact_rows[:, 0:4]
-    out = ctx.fk_join(fact, dim, 0, dpg.JOIN_FACT_ORDER, algo=dpg.ALGO_DPG)
-    torch.cuda.synchronize()
-    assert np.array_equal(out[torch.from_numpy(idx).to(DEV)].cpu().numpy(), want)
-    del out
-    out = ctx.fk_join(fact, dim, 0, dpg.JOIN_DIM_ORDER, algo=dpg.ALGO_DPG)
-    torch.cuda.synchronize()
-    ofk = out[:, 0:4].contiguous().view(torch.int32).reshape(-1).long()
-    assert bool((ofk[1:] >= ofk[:-1]).all())
-    assert torch.equal(out[:, 16:20], out[:, 0:4])
-    a = torch.sort(fact[:, 4:12].contiguous().view(torch.int64).reshape(-1))[0]
-    b = torch.sort(out[:, 4:12].contiguous().view(torch.int64).reshape(-1))[0]
-    assert torch.equal(a, b)
-    del fact, dim, out, ofk, a, b
-    torch.cuda.empty_cache()
-
-
 @pytest.mark.parametrize("form", [(dpg.DIST_APPEND, 2), (dpg.DIST_SAMPLED, 2), (dpg.DIST_TWO_PASS, 2),
                                   (dpg.DIST_PARTITION, 6), (dpg.DIST_PARTITION, 0)],
                          ids=["append", "sampled", "two-pass", "partition-938-runs", "partition-default"])
