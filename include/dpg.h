@@ -485,7 +485,9 @@ dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_ser
 /* Queue a request (its dst is ignored: the output is allocated in the arena at
  * admission).  Invalid requests are accepted as FAILED tickets: INVALID_ARG
  * for a malformed request or one whose inputs overlap the arena, BUSY for one
- * whose output and workspace can never fit the arena. */
+ * whose output and workspace (each rounded up to 256 bytes) exceed what the
+ * arena can ever hold for requests: its size less the batch workspaces the
+ * server keeps per stream slot. */
 dpg_status dpg_server_submit(dpg_server *server, const dpg_request *req, uint64_t *ticket);
 /* *dst: device address of the output once DONE (valid until released). */
 dpg_status dpg_server_poll(dpg_server *server, uint64_t ticket, int32_t *state, dpg_status *status,
@@ -497,7 +499,9 @@ dpg_status dpg_server_next_completed(dpg_server *server, int32_t timeout_ms, uin
 dpg_status dpg_server_release(dpg_server *server, uint64_t ticket);
 dpg_status dpg_server_stats_get(dpg_server *server, dpg_server_stats *out);
 dpg_status dpg_server_reset_stats(dpg_server *server);
-/* Finishes all submitted work, then frees the server (not the arena). */
+/* Finishes all submitted work, then frees the server (not the arena).  Queued
+ * requests that cannot be admitted once no work is left in flight (their
+ * memory is held by outputs not yet released) fail with DPG_ERR_BUSY. */
 void dpg_server_destroy(dpg_server *server);
 
 /* ------------------------------------------------------------------------- */

@@ -13,7 +13,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_part_scatter_unstable", "k_gather_lds", "k_hash_home", "k_hash_mark", "k_hash_place",
     "k_hash_ov_off", "k_hash_direct", "k_hash_probe", "k_hash_probe_lds", "k_smj_keys", "k_smj_ranges",
     "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds", "k_probe_scatter",
-    "k_stream_copy"};
+    "k_stream_copy", "k_scan_small"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 

@@ -77,6 +77,7 @@ enum KernelId {
     K_BT_PROBE_LDS,      //   the same with the run's leaves staged in LDS
     K_PROBE_SCATTER,     // two-phase DPG: Phase II writes each record to its place in dst
     K_STREAM_COPY,       // plain streaming copy (the measured copy ceiling)
+    K_SCAN_SMALL,        // Phase I bucket boundaries, whole column scan in one workgroup
     K_COUNT
 };
 const char *kernel_name(int id);

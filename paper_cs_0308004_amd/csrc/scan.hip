@@ -201,9 +201,78 @@ dpg_status launch_scan_1d(dpg_ctx *ctx, int32_t *a, int64_t n, int32_t *scratch,
     return DPG_OK;
 }
 
+// The whole column scan in one workgroup, for count matrices of at most
+// kScanSmallMax entries (lists of a few million rids or fewer), where the
+// four-kernel form costs more in launches than in work: the matrix is read
+// into LDS in column-major order (rows are read whole, so the loads stay
+// coalesced), scanned there as one array, and written back.
+constexpr int64_t kScanSmallMax = 15360;  // 60 KiB of LDS
+
+__global__ __launch_bounds__(kScan1dThreads) void k_scan_small(int32_t *__restrict__ cnt, int nT, int B,
+                                                               int32_t *__restrict__ bucket_off,
+                                                               int32_t *__restrict__ item_off, int chunk) {
+    extern __shared__ int32_t s_col[];  // nT * B entries, s_col[b * nT + t] = cnt[t][b]
+    __shared__ int32_t s_w[kScan1dThreads / 64];
+    __shared__ int32_t s_total, s_part, s_carry;
+    const int n = nT * B;
+    for (int k = threadIdx.x; k < n; k += kScan1dThreads) {
+        const int t = k / B, b = k - t * B;
+        s_col[b * nT + t] = cnt[k];
+    }
+    __syncthreads();
+    // every thread scans one contiguous segment of the column-major array
+    const int per = (n + kScan1dThreads - 1) / kScan1dThreads;
+    const int lo = min(n, (int)threadIdx.x * per), hi = min(n, lo + per);
+    int32_t sum = 0;
+    for (int k = lo; k < hi; ++k) sum += s_col[k];
+    int32_t run = block_exclusive_scan(sum, s_w, &s_total);
+    for (int k = lo; k < hi; ++k) {
+        const int32_t v = s_col[k];
+        s_col[k] = run;
+        run += v;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < n; k += kScan1dThreads) {
+        const int t = k / B, b = k - t * B;
+        cnt[k] = s_col[b * nT + t];
+    }
+    const int32_t total = s_total;
+    if (threadIdx.x == 0) {
+        bucket_off[B] = total;
+        s_carry = 0;
+    }
+    for (int b = threadIdx.x; b < B; b += kScan1dThreads) bucket_off[b] = s_col[b * nT];
+    if (!item_off) return;
+    // item_off[b] = sum over b' < b of ceil(elements of bucket b' / chunk)
+    __syncthreads();
+    for (int b0 = 0; b0 < B; b0 += kScan1dThreads) {
+        const int b = b0 + threadIdx.x;
+        int32_t u = 0;
+        if (b < B) {
+            const int32_t len = (b + 1 < B ? s_col[(b + 1) * nT] : total) - s_col[b * nT];
+            u = (len + chunk - 1) / chunk;
+        }
+        const int32_t ex = block_exclusive_scan(u, s_w, &s_part);
+        const int32_t carry = s_carry;
+        if (b < B) item_off[b] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) s_carry = carry + s_part;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) item_off[B] = s_carry;
+}
+
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
                               hipStream_t stream) {
+    if (nT * (int64_t)B <= kScanSmallMax) {
+        // one workgroup; chunk sums and column totals are not needed
+        ProfScope prof(ctx, K_SCAN_SMALL, 8.0 * nT * B + 4.0 * B, stream);
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScan1dThreads), (size_t)nT * B * sizeof(int32_t), stream, cnt,
+                           (int)nT, B, bucket_off, item_off, item_chunk > 0 ? item_chunk : 1);
+        DPG_HIP(hipGetLastError());
+        return DPG_OK;
+    }
     const unsigned gy = (unsigned)((B + 255) / 256);
     {
         ProfScope prof(ctx, K_SCAN_CHUNKS, 4.0 * nT * B + 4.0 * nC * B, stream);

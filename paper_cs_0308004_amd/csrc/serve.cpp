@@ -37,74 +37,12 @@
 #include <unordered_map>
 #include <vector>
 
+#include "admission.h"
 #include "dpg_internal.h"
 
 namespace dpg {
 
 using Clock = std::chrono::steady_clock;
-
-// First-fit allocator over [0, size) with coalescing; offsets are aligned.
-class Arena {
-   public:
-    Arena(size_t size, size_t align) : size_(size), align_(align) {
-        if (size_ > 0) free_[0] = size_;
-    }
-    // returns false when no free block fits
-    bool alloc(size_t bytes, size_t *off) {
-        const size_t need = align_up(bytes ? bytes : 1, align_);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= need) {
-                *off = it->first;
-                const size_t rest = it->second - need;
-                const size_t at = it->first;
-                free_.erase(it);
-                if (rest) free_[at + need] = rest;
-                used_[at] = need;
-                in_use_ += need;
-                high_water_ = std::max(high_water_, in_use_);
-                return true;
-            }
-        }
-        return false;
-    }
-    bool release(size_t off) {
-        auto u = used_.find(off);
-        if (u == used_.end()) return false;
-        size_t start = off, len = u->second;
-        in_use_ -= len;
-        used_.erase(u);
-        auto next = free_.lower_bound(start);
-        if (next != free_.end() && start + len == next->first) {
-            len += next->second;
-            next = free_.erase(next);
-        }
-        if (next != free_.begin()) {
-            auto prev = std::prev(next);
-            if (prev->first + prev->second == start) {
-                start = prev->first;
-                len += prev->second;
-                free_.erase(prev);
-            }
-        }
-        free_[start] = len;
-        return true;
-    }
-    size_t size() const { return size_; }
-    size_t in_use() const { return in_use_; }
-    size_t high_water() const { return high_water_; }
-    size_t largest_free() const {
-        size_t m = 0;
-        for (auto &f : free_) m = std::max(m, f.second);
-        return m;
-    }
-    size_t free_blocks() const { return free_.size(); }
-
-   private:
-    size_t size_, align_;
-    size_t in_use_ = 0, high_water_ = 0;
-    std::map<size_t, size_t> free_;  // offset -> length
-    std::map<size_t, size_t> used_;  // offset -> length
-};
 
 }  // namespace dpg
 
@@ -149,6 +87,7 @@ struct dpg_server {
     dpg_ctx *ctx = nullptr;
     dpg_server_config cfg{};
     dpg::Arena *arena = nullptr;
+    size_t capacity = 0;  // arena bytes requests can ever hold (the slots keep the rest)
     char *base = nullptr;
     std::vector<dpg::Slot> slots;
     std::mutex mu;
@@ -252,36 +191,33 @@ static void scheduler(dpg_server *s) {
         }
         // 2. admission, in arrival order: reserve the output and, for work
         //    that runs on its own, its workspace
+        bool any_busy = false;
+        for (Slot &sl : s->slots) any_busy |= sl.busy;
+        // Nothing will free memory when the server is stopping with no work
+        // in flight or waiting: a head request that does not fit then fails.
+        const bool nothing_will_free = s->stop && !any_busy && s->admitted.empty();
         while (!s->pending.empty()) {
             const uint64_t t = s->pending.front();
             Ticket &tk = s->tickets[t];
-            if (tk.out_bytes + tk.ws_bytes > s->arena->size()) {
+            const AdmitResult r = admit_head(*s->arena, s->capacity, tk.out_bytes, tk.ws_bytes, nothing_will_free);
+            if (r.kind == ADMIT_WAIT) break;
+            s->pending.pop_front();
+            changed = true;
+            if (r.kind == ADMIT_FAIL) {
                 tk.state = T_FAILED;
                 tk.status = DPG_ERR_BUSY;
                 s->n_failed++;
                 s->completed.push_back(t);
-                s->pending.pop_front();
-                changed = true;
                 continue;
             }
-            if (tk.out_bytes > 0) {
-                if (!s->arena->alloc(tk.out_bytes, &tk.out_off)) break;
-                tk.has_out = true;
-            }
-            if (tk.ws_bytes > 0) {
-                if (!s->arena->alloc(tk.ws_bytes, &tk.ws_off)) {
-                    if (tk.has_out) s->arena->release(tk.out_off);
-                    tk.has_out = false;
-                    break;
-                }
-                tk.has_ws = true;
-            }
+            tk.out_off = r.out_off;
+            tk.ws_off = r.ws_off;
+            tk.has_out = r.has_out;
+            tk.has_ws = r.has_ws;
             tk.req.dst = tk.has_out ? s->base + tk.out_off : nullptr;
             tk.state = T_ADMITTED;
             tk.admit = Clock::now();
             s->admitted.push_back(t);
-            s->pending.pop_front();
-            changed = true;
         }
         // 3. launches on free slots: the run of batched tickets at the head
         //    (up to max_batch_requests), or the single unbatched head ticket
@@ -417,6 +353,7 @@ dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_ser
         }
     }
     (void)hipSetDevice(prev);
+    s->capacity = s->arena->size() - s->arena->in_use();
     if (st != DPG_OK) {
         for (Slot &sl : s->slots) {
             if (sl.graph) dpg_batch_graph_destroy(sl.graph);

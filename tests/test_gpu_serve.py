@@ -158,3 +158,44 @@ def test_budget_backpressure_and_failures(ctx):
         assert st["failed"] == 2
     finally:
         server.close()
+
+
+def test_request_between_capacity_and_arena_size_fails(ctx):
+    """The slot workspaces take part of the arena for good: a request whose
+    output fits the arena but not what is left for requests fails with BUSY
+    at once instead of blocking the queue, the requests behind it are served,
+    and closing the server with an output still held does not wait for it."""
+    budget = 16 << 20
+    server = dpg.Server(ctx, budget, max_inflight=2, max_batch_requests=8)
+    slot_ws = dpg.lib().dpg_batch_graph_workspace_bytes(ctx.handle, 8)
+    capacity = budget - 2 * ((slot_ws + 255) // 256 * 256)
+    assert capacity < budget
+    try:
+        n = (capacity + budget) // 2 // 100  # output between the capacity and the arena size
+        assert capacity < n * 100 <= budget
+        src = torch.zeros((n, 100), dtype=torch.uint8, device=DEV)
+        rids = torch.zeros(n, dtype=torch.int32, device=DEV)
+        big = dpg.Request(dpg.REQ_RETRIEVE, dpg.ALGO_DIRECT, src.data_ptr(), n, 100, 0, rids.data_ptr(), None, n,
+                          0, 0, None)
+        tb = server.submit(big)
+        reqs = build_requests(12, seed=11, max_log2=12)
+        got = run_all(server, reqs)
+        for i, (_, _, want) in enumerate(reqs):
+            assert np.array_equal(got[i], want)
+        state, st, dst, _ = server.poll(tb)
+        assert state == dpg.TICKET_FAILED and st == dpg.ERR_BUSY and dst is None
+        # an output held while the server closes: a queued request that can
+        # then never be admitted fails instead of keeping close() waiting
+        half = capacity // 2 // 100 + 1
+        hold = dpg.Request(dpg.REQ_RETRIEVE, dpg.ALGO_DIRECT, src.data_ptr(), half, 100, 0, rids.data_ptr(), None,
+                           half, 0, 0, None)
+        t1 = server.submit(hold)
+        while server.poll(t1)[0] not in (dpg.TICKET_DONE, dpg.TICKET_FAILED):
+            time.sleep(0.001)
+        assert server.poll(t1)[0] == dpg.TICKET_DONE
+        t2 = server.submit(hold)
+        t0 = time.perf_counter()
+        server.close()
+        assert time.perf_counter() - t0 < 10.0
+    finally:
+        server.close()
