@@ -159,6 +159,26 @@ dpg_status dpg_retrieve(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t re
                         void *workspace, size_t workspace_bytes, dpg_algo algo,
                         int check_rids, hipStream_t stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * retrieval as dpg_retrieve (same arguments, plans, kernels, validation and
+ * results), with its workspace taken from a static device array of the
+ * library instead of the caller.  The array holds DPG_NOALLOC_SCRATCH_BYTES
+ * bytes on every device the library runs on, for the life of the process;
+ * its device address is looked up when a context is created on the device.
+ * A shape whose workspace (dpg_retrieve_workspace_bytes) exceeds that size
+ * returns DPG_ERR_WORKSPACE_TOO_SMALL and enqueues nothing (for DPG at 100 B
+ * records, about 600,000 rids fit; direct retrieval needs 256 bytes).  The
+ * call allocates no device memory, and with per-kernel profiling off
+ * (dpg_profile_enable) makes no allocation at all.  `stream` must belong to
+ * ctx's device.  Every call on a device shares that device's array: calls that can
+ * overlap on one device (different streams, or several host threads) race
+ * and give undefined results; serialize them on one stream. */
+#define DPG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+dpg_status dpg_retrieve_noalloc(dpg_ctx *ctx, const void *src, int64_t n_src, int32_t rec_bytes,
+                                const int32_t *rids, int64_t n_rids, void *dst, dpg_algo algo, int check_rids,
+                                hipStream_t stream);
+
 /* ------------------------------------------------------------------------- */
 /* Autotuning.  dpg_autotune_retrieve times every candidate plan for one     */
 /* retrieval shape on the caller's buffers (direct retrieval; DPG with each  */

@@ -142,6 +142,7 @@ dpg_status dpg_create(int device, dpg_ctx **out) {
         delete ctx;
         return DPG_ERR_HIP;
     }
+    scratch_init(ctx);  // with `device` current
     (void)hipSetDevice(prev);
     *ctx->host_flag = 0;
     *out = ctx;

@@ -129,6 +129,9 @@ struct dpg_ctx {
     std::map<dpg::TuneKey, dpg::TuneEntry> tuned;
     // pinned host word used to read device flags
     int32_t *host_flag = nullptr;
+    // device address of the library's static scratch array on this device
+    // (dpg_retrieve_noalloc), looked up once per device at creation
+    void *scratch = nullptr;
 };
 
 namespace dpg {
@@ -265,6 +268,9 @@ dpg_status launch_probe_lds(dpg_ctx *ctx, const RetrievePlan &p, const void *src
                             hipStream_t stream);
 
 int xcd_remap_flag(const dpg_ctx *ctx);
+// Look up the device address of the static scratch array on ctx->device (the
+// current device) once per device and store it in ctx->scratch.
+void scratch_init(dpg_ctx *ctx);
 
 // Validate one batch request and tell whether a batch would run it as direct
 // work inside the persistent launch; *own_ws is the workspace it needs when run

@@ -87,6 +87,7 @@ SIGNATURES = {
     "dpg_plan_retrieve": (_I32, [_VP, _I64, _I32, _I64, _I32, ctypes.POINTER(Plan)]),
     "dpg_retrieve_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I64, _I32]),
     "dpg_retrieve": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _I32, _VP]),
+    "dpg_retrieve_noalloc": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _I32, _I32, _VP]),
     "dpg_sort_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I32, _I32]),
     "dpg_sort_records": (_I32, [_VP, _VP, _I64, _I32, _I32, _I32, _VP, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_fk_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32]),
