@@ -466,8 +466,10 @@ def bench_join(args, ctx, dpg, synth, torch, np):
                 for algo, aname in ((dpg.ALGO_DPG, "dpg"), (dpg.ALGO_DIRECT, "direct"), (dpg.ALGO_AUTO, "auto")):
                     ws = torch.empty(ctx.key_join_workspace_bytes(n_fact, 16, 0, n_dim, 64, lg_slots, order, algo),
                                      dtype=torch.uint8, device=dev)
+                    # unchecked keys: no stream synchronization inside the timed calls
                     ms, _ = time_steps(lambda: ctx.key_join(fact_k, dim_k, 0, index, lg_slots, order, out=out,
-                                                            algo=algo, workspace=ws), steps, 1, torch)
+                                                            algo=algo, workspace=ws, check_fk=False), steps, 1,
+                                       torch)
                     res[f"keyed_{oname}_{aname}"] = {"ms": round(ms, 3),
                                                      "out_GB_per_s": round(n_fact * 80 / (ms * 1e-3) / 1e9, 2)}
                     del ws
@@ -692,11 +694,14 @@ def bench_skew_multipass(args, ctx, dpg, synth, torch, np):
     return res
 
 
-def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
+def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0, algo=None, mode_names=None):
     """4096 requests (75 % retrievals, 25 % fact-order or dimension-order
     joins), N log-uniform in [2^10, 2^max_log2], record size uniform over
     {16, 64, 100, 256} B, rids a random permutation of [0, N); tables resident;
-    Poisson arrivals; admission under a 64 GiB arena."""
+    Poisson arrivals; admission under a 64 GiB arena.  algo: the requests'
+    algorithm (default AUTO); mode_names: the server modes to run (default
+    all)."""
+    algo = dpg.ALGO_AUTO if algo is None else algo
     dev = "cuda:0"
     n_req = args.serve_requests
     seed = synth.SEED_BASE + 4 + seed_off
@@ -713,7 +718,7 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
         if rng.random() < 0.75:
             base = bases[rng.integers(0, 4)]
             rids = base[base < n].contiguous()  # a uniformly random permutation of [0, n)
-            reqs.append(dpg.Request(dpg.REQ_RETRIEVE, dpg.ALGO_AUTO, tables[R].data_ptr(), n, R, 0,
+            reqs.append(dpg.Request(dpg.REQ_RETRIEVE, algo, tables[R].data_ptr(), n, R, 0,
                                     rids.data_ptr(), None, n, 0, 0, None))
             keep.append(rids)
             shapes.append(("retrieve", n, R))
@@ -724,7 +729,7 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
             fact = synth.record_bytes(n, 16, seed * 7 + k, synth.STREAM_FACT, backend="torch", device=dev)
             fact[:, 0:4] = fk.view(torch.uint8).reshape(-1, 4)
             order = int(rng.integers(0, 2))
-            reqs.append(dpg.Request(dpg.REQ_FK_JOIN, dpg.ALGO_AUTO, tables[R].data_ptr(), n_dim, R, 16, None,
+            reqs.append(dpg.Request(dpg.REQ_FK_JOIN, algo, tables[R].data_ptr(), n_dim, R, 16, None,
                                     fact.data_ptr(), n, 0, order, None))
             keep.append(fact)
             shapes.append(("join", n, R))
@@ -762,15 +767,18 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0):
                 t = server.next_completed(0)
         return server.stats()
 
+    algo_name = {dpg.ALGO_AUTO: "AUTO", dpg.ALGO_DPG: "DPG", dpg.ALGO_DIRECT: "direct"}[algo]
     res = {"workload": f"{n_req} requests: 75% retrieval, 25% FK join (either order); N log-uniform "
                        f"[2^10, 2^{max_log2}]; record size uniform over {{16,64,100,256}} B; random-permutation rids; "
-                       f"resident tables; Poisson arrivals; 64 GiB HBM budget",
+                       f"resident tables; Poisson arrivals; 64 GiB HBM budget; algorithm {algo_name}",
            "output_GB_total": round(out_bytes / 1e9, 2)}
     budget = 64 << 30
     modes = {"batched_graph": dict(max_inflight=4, max_batch_requests=256, use_graph=True),
              "batched_eager": dict(max_inflight=4, max_batch_requests=256, use_graph=False),
              "batched_window": dict(max_inflight=4, max_batch_requests=256, use_graph=False, batch_window_us=50),
              "per_request": dict(max_inflight=4, max_batch_requests=1, use_graph=False)}
+    if mode_names:
+        modes = {k: v for k, v in modes.items() if k in mode_names}
     servers = {}
     try:
         sat = {}
@@ -865,6 +873,11 @@ def main():
         # the same mix restricted to small requests (N up to 2^14), where
         # launch cost rather than HBM bandwidth decides throughput
         out["serving_small"] = bench_serve(args, ctx, dpg, synth, torch, np, max_log2=14, seed_off=1)
+        # the small-request mix with every retrieval and fact-order join
+        # planned as DPG: the batch runs their phases as steps of the
+        # persistent launch, per-request launches run each phase alone
+        out["serving_small_dpg"] = bench_serve(args, ctx, dpg, synth, torch, np, max_log2=14, seed_off=1,
+                                               algo=dpg.ALGO_DPG, mode_names=("batched_graph", "per_request"))
     if cpu is not None:
         out["cpu_baseline"] = cpu
     ctx.close()

@@ -219,10 +219,11 @@ size_t dpg_sort_workspace_bytes(const dpg_ctx *ctx, int64_t n, int32_t rec_bytes
  * (nullable, uint32[n]) receives perm.  key_bytes in [1, 64].  copy_algo picks
  * the retrieval used for the copy phase (DPG, direct, or AUTO).  The pairs
  * are sorted on the first 4 key bytes, then every group of equal prefixes is
- * put in order by the remaining bytes and the index.  For keys longer than 4
- * bytes the call synchronizes the stream once, to learn whether some group is
- * longer than 64 records (then the pairs are sorted over the whole key
- * instead).  src, dst, perm_out and workspace must not overlap. */
+ * put in order by the remaining bytes and the index.  If some group is longer
+ * than 64 records, the pairs are sorted over the whole key instead: the
+ * device decides (the passes for that case are always enqueued and return at
+ * once when not needed), so the call never synchronizes.  src, dst, perm_out
+ * and workspace must not overlap. */
 dpg_status dpg_sort_records(dpg_ctx *ctx, const void *src, int64_t n, int32_t rec_bytes,
                             int32_t key_offset, int32_t key_bytes, void *dst, uint32_t *perm_out,
                             void *workspace, size_t workspace_bytes, dpg_algo copy_algo,
@@ -275,6 +276,15 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
                                const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
                                void *out, int64_t out_capacity, int64_t *out_rows, void *workspace,
                                size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream);
+/* The same join without any host synchronization (it can be captured in a
+ * graph): out_rows_dev is a DEVICE int64 (8-byte aligned) that receives the
+ * number of result rows; the first min(that number, out_capacity) rows are
+ * written, out_capacity below 2^31 - 1.  A count above out_capacity means the
+ * output was cut short; a count of 2^31 or more leaves the rows unspecified. */
+dpg_status dpg_sort_merge_join_async(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                                     const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                                     void *out, int64_t out_capacity, int64_t *out_rows_dev, void *workspace,
+                                     size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Hash index and batch lookup (Section 4.2.3, batch lookup in hash indexes): */
@@ -334,16 +344,18 @@ dpg_status dpg_hash_lookup(dpg_ctx *ctx, const void *index, int64_t n_keys, int3
  * algo is DPG_ALGO_DIRECT); fact row i then joins dimension row j_i, the
  * smallest row holding its key, exactly as dpg_fk_join joins row fk_i (same
  * output layout, both orders, same algo meaning for the move).  Every fk must
- * be a key of the index: DPG_ERR_FK_OUT_OF_RANGE otherwise (checked on the
- * device; the call synchronizes the stream once).  out must not overlap
- * fact, dim, index or workspace. */
+ * be a key of the index.  check_fk = 1: verified on the device first
+ * (DPG_ERR_FK_OUT_OF_RANGE otherwise, with one stream synchronization);
+ * check_fk = 0: never synchronizes, and a missing key is undefined
+ * behaviour (no out-of-bounds access, unspecified row contents).  out must
+ * not overlap fact, dim, index or workspace. */
 size_t dpg_key_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
                                     int64_t n_dim, int32_t dim_bytes, int32_t log2_slots, dpg_join_order order,
                                     dpg_algo algo);
 dpg_status dpg_key_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t fact_bytes, int32_t fk_offset,
                         const void *dim, int64_t n_dim, int32_t dim_bytes, const void *index, int32_t log2_slots,
                         void *out, dpg_join_order order, void *workspace, size_t workspace_bytes, dpg_algo algo,
-                        hipStream_t stream);
+                        int check_fk, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
 /* Enhanced B+ tree and batch lookup (Section 4.2.3, batch lookup in B+ tree  */
@@ -397,11 +409,16 @@ dpg_status dpg_btree_lookup(dpg_ctx *ctx, const void *tree, int64_t n_keys, cons
                             dpg_algo algo, hipStream_t stream);
 
 /* ------------------------------------------------------------------------- */
-/* Batches: many retrieval / join requests of uneven size in one call.  All   */
-/* direct-algorithm work of the batch (direct retrievals, direct fact-order   */
-/* joins) runs in ONE launch of a persistent, queue-driven kernel; requests   */
-/* planned as DPG and dimension-order joins run their own phase sequence in   */
-/* the same stream.  Every output equals that of the request run alone.       */
+/* Batches: many retrieval / join requests of uneven size in one call.  The   */
+/* work of every request runs in ONE launch of a persistent, queue-driven     */
+/* kernel whose work items are (request, step, tile): a direct retrieval or   */
+/* direct fact-order join is one copy step; a request planned as DPG          */
+/* (retrieval, or fact-order join moving the dimension rows) is the chain of  */
+/* Section 2.1's phases -- run histogram, run boundaries, distribute, probe,  */
+/* gather -- each step starting once the step before it (same request) has   */
+/* finished.  Dimension-order joins (a stable sort of the keys) run their own */
+/* phase sequence in the same stream.  Every output equals that of the        */
+/* request run alone.                                                         */
 /* ------------------------------------------------------------------------- */
 typedef enum { DPG_REQ_RETRIEVE = 0, DPG_REQ_FK_JOIN = 1 } dpg_request_kind;
 
@@ -418,8 +435,19 @@ typedef struct {
     int32_t fk_offset;     /* join: byte offset of the uint32 foreign key */
     int32_t order;         /* join: dpg_join_order */
     void *dst;             /* output rows (n x rec_bytes, or n x (fact_bytes + rec_bytes)) */
+    /* graph batches only (dpg_batch_graph_launch), for a request planned as
+     * DPG: device scratch of dpg_batch_request_workspace_bytes bytes or more,
+     * 256-byte aligned; ignored by dpg_batch_run, which keeps every request's
+     * scratch in the batch workspace */
+    void *workspace;
+    size_t workspace_bytes;
 } dpg_request;
 
+/* Scratch the steps of one request need inside a graph batch
+ * (dpg_request.workspace): its run histogram and boundaries, RID_RUN, inv and
+ * INTERNAL when it is planned as DPG; 0 for direct work or an invalid
+ * request. */
+size_t dpg_batch_request_workspace_bytes(const dpg_ctx *ctx, const dpg_request *req);
 /* Workspace for dpg_batch_run (0 if a request is invalid). */
 size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n);
 /* Validates every request first (same rules as the single calls, no device
@@ -428,16 +456,25 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
                          size_t workspace_bytes, hipStream_t stream);
 
 /* A captured graph of the persistent batch launch, bound to a workspace: each
- * dpg_batch_graph_launch uploads the new requests' descriptors and replays
- * the graph.  Graph batches carry direct-algorithm work only (a request that
- * would be planned as DPG, or a dimension-order join, returns
- * DPG_ERR_UNSUPPORTED).  Capture needs a non-default stream. */
+ * dpg_batch_graph_launch uploads the new requests' steps and replays the
+ * graph.  Graph batches carry direct and DPG work (a DPG request brings its
+ * scratch in dpg_request.workspace, dpg_batch_request_workspace_bytes:
+ * DPG_ERR_WORKSPACE_TOO_SMALL otherwise);
+ * a dimension-order join returns DPG_ERR_UNSUPPORTED.  Capture needs a
+ * non-default stream.  Launches on one graph must not overlap: launch again
+ * once the previous launch has finished. */
 typedef struct dpg_batch_graph dpg_batch_graph;
 size_t dpg_batch_graph_workspace_bytes(const dpg_ctx *ctx, int32_t max_requests);
 dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *workspace,
                                   size_t workspace_bytes, hipStream_t stream, dpg_batch_graph **out);
 dpg_status dpg_batch_graph_launch(dpg_batch_graph *graph, const dpg_request *reqs, int32_t n,
                                   hipStream_t stream);
+/* 1 once request `request` (index in the array of the last launch) has
+ * finished, while the rest of the batch may still run: the kernel writes a
+ * completion word in host memory when the request's last step ends (outputs
+ * then readable by any stream or the host); 0 otherwise. */
+int32_t dpg_batch_graph_request_done(const dpg_batch_graph *graph, int32_t request);
+/* Waits for the last launch to finish, then frees the graph (not its workspace). */
 void dpg_batch_graph_destroy(dpg_batch_graph *graph);
 
 /* ------------------------------------------------------------------------- */
@@ -458,12 +495,14 @@ void dpg_arena_destroy(dpg_arena *arena);
 
 /* ------------------------------------------------------------------------- */
 /* Serving: continuous batching under an HBM budget.  A scheduler thread      */
-/* admits submitted requests in arrival order while their output (plus, for   */
-/* requests that run on their own, their workspace) fits the arena, and      */
-/* launches admitted requests on the first free stream slot: consecutive     */
-/* small direct-work requests together as one persistent batch launch (a     */
-/* graph replay with use_graph), others alone through their dedicated        */
-/* kernels.  Requests arriving while batches run                             */
+/* admits submitted requests in arrival order while their output (plus their */
+/* workspace or DPG scratch) fits the arena, and launches admitted requests   */
+/* on the first free stream slot: consecutive small requests together as one */
+/* persistent batch launch (a graph replay with use_graph) whose DPG and      */
+/* direct work share the kernel, others alone through their dedicated        */
+/* kernels.  A batched request completes when its own last step ends (the    */
+/* kernel sets its completion word), not when its whole batch does.          */
+/* Requests arriving while batches run                                       */
 /* are admitted and launched on the next free slot, so their work overlaps on */
 /* the device.  With max_batch_requests = 1 every request is launched alone   */
 /* through its single-request entry point (the per-request baseline).        */
@@ -476,7 +515,7 @@ typedef struct {
     int32_t max_inflight;        /* stream slots, 1..16 */
     int32_t max_batch_requests;  /* requests per launch; 1 = per-request launches */
     int32_t use_graph;           /* 1: replay a captured batch graph per launch */
-    int32_t batch_max_kib;       /* direct-work requests with larger outputs run alone
+    int32_t batch_max_kib;       /* requests with larger outputs run alone
                                     through their dedicated kernels (0: 4096 KiB) */
     int32_t batch_window_us;     /* a partial batch waits up to this long for more
                                     requests before launching (0: launch at once) */

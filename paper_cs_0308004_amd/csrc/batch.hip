@@ -1,21 +1,41 @@
-// Batched execution of many retrieval / join requests of uneven size.
+// Batched execution of many retrieval / join requests of uneven size in ONE
+// launch of the persistent kernel k_batch.
 //
-// Direct-algorithm work of every request in the batch (retrievals planned as
-// direct, and fact-order joins planned as direct) runs in ONE launch of the
-// persistent kernel k_batch: a fixed grid of workgroups pulls work items from
-// a device queue (one atomic counter); an item is a tile of output rows of one
-// request.  Each output row is A[ia] || B[ib] (retrieval: src[rid], no B;
-// fact-order join: fact[i] || dim[fk_i]), so one kernel serves both kinds and
-// every record size.  Every workgroup leaves the loop once the queue is
-// exhausted; nothing waits on the host.
+// A fixed grid of workgroups pulls work items from a device queue (one atomic
+// counter).  An item is one tile of one step of one request:
 //
-// Requests planned as DPG, and dimension-order joins, run their own phase
-// sequence (the same code as dpg_retrieve / dpg_fk_join) in the same stream,
-// so every request's output is bit-identical alone and in any batch.
+//   OP_COPY     a tile of output rows A[ia] || B[ib] (retrieval: src[rid], no
+//               B; fact-order join: fact[i] || dim[fk_i]); the same step is
+//               the DPG probe (INTERNAL[k] = src[run[k]]) and the DPG gather
+//               (dst[i] = INTERNAL[inv[i]], or fact[i] || INTERNAL[inv[i]])
+//   OP_ZERO     clears a request's run histogram
+//   OP_HIST     a tile of rids counted into the run histogram (Phase I)
+//   OP_SCAN     the run boundaries: exclusive scan of the histogram
+//   OP_SCATTER  a tile of rids placed into their runs (RID_RUN) with each
+//               rid's slot recorded (inv)
 //
-// The batch header (item count, descriptor count) lives in device memory, so a
-// captured graph of [reset queue, k_batch] can be replayed with new requests:
-// only the descriptor upload changes (dpg_batch_graph_*).
+// A request planned as direct retrieval is one OP_COPY step; a request
+// planned as DPG is the chain ZERO -> HIST -> SCAN -> SCATTER -> COPY (probe)
+// -> COPY (gather), the three phases of Section 2.1.  The queue lists every
+// request's first step, then every request's second step, and so on, so a
+// step rarely waits.  Before its first item of a step, a workgroup waits until
+// every item of the step before it (same request) has finished: those items
+// were taken from the queue earlier, by workgroups that are running, so the
+// wait ends; a bounded spin (a timeout flag in the header) keeps a kernel
+// from running on if that ever failed.  Each finished item bumps its step's
+// counter; the last item of a request's last step also writes the launch's
+// sequence number into the request's completion word, which lives in host
+// memory, so a host thread learns that the request is done while the batch
+// is still running.
+//
+// Dimension-order (DPG-Sort) joins need a stable sort of the foreign keys and
+// run their own phase sequence in the same stream (dpg_batch_run); graph
+// batches do not take them.
+//
+// The batch header (item count, step count, sequence number) lives in device
+// memory, so a captured graph of [reset queue and counters, k_batch] is
+// replayed with new requests: only the header and step upload changes
+// (dpg_batch_graph_*).
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -26,14 +46,20 @@
 
 namespace dpg {
 
+enum BatchOp : int32_t { OP_COPY = 0, OP_ZERO = 1, OP_HIST = 2, OP_SCAN = 3, OP_SCATTER = 4 };
+
 struct BatchDesc {
-    const uint32_t *a;      // retrieval source records / fact rows
-    const int32_t *idx_a;   // rids (retrieval) or null (row i of A)
-    const uint32_t *b;      // dimension rows (join) or null
+    // OP_COPY: out row j = A[ia] || B[ib], ia = idx_a ? idx_a[j] : j,
+    // ib = idx_b ? idx_b[j] : word fk_word of A row ia (when wb > 0)
+    const uint32_t *a;
+    const int32_t *idx_a;
+    const uint32_t *b;
+    const int32_t *idx_b;
     uint32_t *out;
     int64_t lim_a, lim_b;   // row counts of A and B (indices outside read row 0)
-    int64_t n_rows;         // output rows
-    int64_t item_start;     // first work item of this request
+    int64_t n_rows;         // rows of the step: output rows, or rids of a distribute step
+    int64_t item_start;     // first work item of this step
+    int64_t n_items;
     int32_t wa, wb;         // dwords taken from A and from B per output row
     int32_t fk_word;        // word of the A row holding the foreign key (join)
     int32_t tile_rows;      // output rows per work item
@@ -41,18 +67,33 @@ struct BatchDesc {
     int32_t request;        // index in the caller's request array
     int32_t vec;            // dwords per access: 4 when rows and pointers are 16-byte aligned, else 1
     int32_t nt;             // nontemporal output stores
+    int32_t op;             // BatchOp
+    int32_t dep;            // step whose items must all have finished first (-1: none)
+    int32_t last;           // 1: the request is done when this step is
+    // distribute steps: rid of element i = ids[i * id_stride + id_word], valid
+    // in [0, lim_a) (else 0); run of a rid = rid >> lg_run, n_runs runs
+    const uint32_t *ids;
+    int32_t id_stride, id_word;
+    int32_t lg_run, n_runs;
+    int32_t *hist, *fill, *run_off, *run, *inv;
 };
 
 struct BatchHeader {
     int64_t total_items;
     int32_t n_desc;
+    uint32_t seq;      // launch sequence number, written into the completion words
+    int32_t timeout;   // set when a dependency wait gave up (never in a correct run)
     int32_t pad;
 };
 
 constexpr int kBatchThreads = 256;
 constexpr int kBatchPer = 16;
 constexpr int kBatchMaxTileRows = 2048;
-constexpr int kBatchItemWords = 16384;  // ~64 KiB of output per work item
+constexpr int kBatchItemWords = 16384;   // ~64 KiB of output per work item
+constexpr int kBatchDistTile = 4096;     // rids per distribute item (16 per thread)
+constexpr int kBatchMaxRuns = 2048;      // runs of a request distributed inside the batch
+constexpr int kBatchSteps = 6;           // steps of a DPG request
+constexpr uint64_t kBatchWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time counter
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -105,16 +146,136 @@ __device__ __forceinline__ void batch_copy(const BatchDesc &d, const int32_t *s_
     }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__restrict__ hdr,
+__device__ __forceinline__ void copy_item(const BatchDesc &d, int64_t local, int32_t *s_ia, int32_t *s_ib) {
+    const int64_t row0 = local * d.tile_rows;
+    const int rows = (int)min((int64_t)d.tile_rows, d.n_rows - row0);
+    {
+        const auto *ga = as_global(d.a);
+        const auto *gi = as_global(d.idx_a);
+        const auto *gib = as_global(d.idx_b);
+        const int64_t lim_a = d.lim_a, lim_b = d.lim_b;
+        const int wa = d.wa, fk_word = d.fk_word;
+        auto clamp_a = [=](int64_t ia) -> int64_t { return (ia >= 0 && ia < lim_a) ? ia : 0; };
+        auto clamp_b = [=](int64_t ib) -> int32_t { return (ib >= 0 && ib < lim_b) ? (int32_t)ib : 0; };
+        if (d.idx_a) stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(gi[row0 + j]); });
+        else stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(row0 + j); });
+        if (d.wb > 0) {
+            if (d.idx_b) {
+                stage_rows(s_ib, rows, [&](int j) { return clamp_b(gib[row0 + j]); });
+            } else {
+                auto fk = [=](int64_t ia) -> int32_t { return clamp_b((int64_t)ga[ia * wa + fk_word]); };
+                if (d.idx_a) stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(gi[row0 + j])); });
+                else stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(row0 + j)); });
+            }
+        }
+    }
+    __syncthreads();
+    if (d.vec == 4) {
+        if (d.nt) batch_copy<u32x4, true>(d, s_ia, s_ib, rows, row0);
+        else batch_copy<u32x4, false>(d, s_ia, s_ib, rows, row0);
+    } else {
+        if (d.nt) batch_copy<uint32_t, true>(d, s_ia, s_ib, rows, row0);
+        else batch_copy<uint32_t, false>(d, s_ia, s_ib, rows, row0);
+    }
+}
+
+// rid of distribute element i (clamped to the source; a rid outside it takes
+// record 0, as the copies do)
+__device__ __forceinline__ int32_t batch_rid(const BatchDesc &d, int64_t i) {
+    const int64_t r = (int64_t)as_global(d.ids)[i * d.id_stride + d.id_word];
+    return (r >= 0 && r < d.lim_a) ? (int32_t)r : 0;
+}
+
+// OP_HIST: the item's rids counted per run in LDS, then added to the request's histogram.
+__device__ __forceinline__ void hist_item(const BatchDesc &d, int64_t local, int32_t *s_h) {
+    for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads) s_h[b] = 0;
+    __syncthreads();
+    const int64_t i0 = local * kBatchDistTile;
+#pragma unroll 4
+    for (int k = 0; k < kBatchDistTile / kBatchThreads; ++k) {
+        const int64_t i = i0 + k * kBatchThreads + threadIdx.x;
+        if (i < d.n_rows) atomicAdd(&s_h[batch_rid(d, i) >> d.lg_run], 1);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads)
+        if (s_h[b]) atomicAdd(&d.hist[b], s_h[b]);
+}
+
+// OP_SCAN: run_off = exclusive scan of the histogram (run_off[B] = all rids);
+// fill starts at run_off, for the scatter's segment reservations.
+__device__ __forceinline__ void scan_item(const BatchDesc &d, int32_t *s_w) {
+    constexpr int PER = kBatchMaxRuns / kBatchThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b0 = threadIdx.x * PER;
+    int32_t v[PER], sum = 0;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        v[k] = b0 + k < d.n_runs ? as_global(d.hist)[b0 + k] : 0;
+        sum += v[k];
+    }
+    int32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    int32_t base = 0;
+    for (int w = 0; w < wave; ++w) base += s_w[w];
+    int32_t run = base + inc - sum;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (b0 + k < d.n_runs) {
+            d.run_off[b0 + k] = run;
+            d.fill[b0 + k] = run;
+        }
+        run += v[k];
+    }
+    if (threadIdx.x == kBatchThreads - 1) d.run_off[d.n_runs] = run;
+}
+
+// OP_SCATTER: every rid of the item takes a slot in its run: a rank inside the
+// item from LDS atomics, plus one segment per run reserved with one global
+// atomic; run[slot] = rid, inv[i] = slot.  The order inside a run is
+// unspecified (inv makes the result exact).
+__device__ __forceinline__ void scatter_item(const BatchDesc &d, int64_t local, int32_t *s_cnt, int32_t *s_base) {
+    constexpr int PER = kBatchDistTile / kBatchThreads;
+    for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads) s_cnt[b] = 0;
+    __syncthreads();
+    const int64_t i0 = local * kBatchDistTile;
+    int32_t rid[PER], rank[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = i0 + k * kBatchThreads + threadIdx.x;
+        rid[k] = i < d.n_rows ? batch_rid(d, i) : -1;
+        rank[k] = rid[k] >= 0 ? atomicAdd(&s_cnt[rid[k] >> d.lg_run], 1) : 0;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads)
+        s_base[b] = s_cnt[b] ? atomicAdd(&d.fill[b], s_cnt[b]) : 0;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (rid[k] < 0) continue;
+        const int64_t i = i0 + k * kBatchThreads + threadIdx.x;
+        const int32_t slot = s_base[rid[k] >> d.lg_run] + rank[k];
+        d.run[slot] = rid[k];
+        d.inv[i] = slot;
+    }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict__ hdr,
                                                          const BatchDesc *__restrict__ descs,
                                                          uint32_t *__restrict__ queue,
-                                                         uint32_t *__restrict__ done) {
+                                                         uint32_t *__restrict__ done,
+                                                         uint32_t *__restrict__ host_done) {
     __shared__ int64_t s_item;
-    __shared__ int s_req;
-    __shared__ int32_t s_ia[kBatchMaxTileRows];
-    __shared__ int32_t s_ib[kBatchMaxTileRows];
+    __shared__ int s_desc;
+    __shared__ int32_t s_mem[2 * kBatchMaxTileRows];  // also 2 x kBatchMaxRuns for the distribute steps
     const int64_t total_items = hdr->total_items;
     const int n_desc = hdr->n_desc;
+    const uint32_t seq = hdr->seq;
     for (;;) {
         if (threadIdx.x == 0) {
             const int64_t item = (int64_t)atomicAdd(queue, 1u);
@@ -128,42 +289,50 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__re
                     else hi = mid - 1;
                 }
                 r = lo;
+                // wait for the step this one depends on (items taken earlier,
+                // by running workgroups)
+                const int dep = descs[r].dep;
+                if (dep >= 0) {
+                    const uint32_t need = (uint32_t)descs[dep].n_items;
+                    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                    while (__hip_atomic_load(&done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                        __builtin_amdgcn_s_sleep(2);
+                        if (__builtin_amdgcn_s_memrealtime() - t0 > kBatchWaitTicks) {
+                            atomicOr(&hdr->timeout, 1);
+                            break;
+                        }
+                    }
+                    __threadfence();  // acquire: the dependency's writes are visible
+                }
             }
-            s_req = r;
+            s_desc = r;
         }
         __syncthreads();
         const int64_t item = s_item;
-        const int r = s_req;
+        const int r = s_desc;
         if (item >= total_items) break;  // queue exhausted: uniform exit
         const BatchDesc d = descs[r];
-        const int64_t row0 = (item - d.item_start) * d.tile_rows;
-        const int rows = (int)min((int64_t)d.tile_rows, d.n_rows - row0);
-        {
-            const auto *ga = as_global(d.a);
-            const auto *gi = as_global(d.idx_a);
-            const int64_t lim_a = d.lim_a, lim_b = d.lim_b;
-            const int wa = d.wa, fk_word = d.fk_word;
-            auto clamp_a = [=](int64_t ia) -> int64_t { return (ia >= 0 && ia < lim_a) ? ia : 0; };
-            if (d.idx_a) stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(gi[row0 + j]); });
-            else stage_rows(s_ia, rows, [&](int j) { return (int32_t)clamp_a(row0 + j); });
-            if (d.wb > 0) {
-                auto fk = [=](int64_t ia) -> int32_t {
-                    const int64_t ib = ga[ia * wa + fk_word];
-                    return ib < lim_b ? (int32_t)ib : 0;
-                };
-                if (d.idx_a) stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(gi[row0 + j])); });
-                else stage_rows(s_ib, rows, [&](int j) { return fk(clamp_a(row0 + j)); });
-            }
+        const int64_t local = item - d.item_start;
+        switch (d.op) {
+            case OP_COPY: copy_item(d, local, s_mem, s_mem + kBatchMaxTileRows); break;
+            case OP_ZERO:
+                for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads) d.hist[b] = 0;
+                break;
+            case OP_HIST: hist_item(d, local, s_mem); break;
+            case OP_SCAN: scan_item(d, s_mem); break;
+            case OP_SCATTER: scatter_item(d, local, s_mem, s_mem + kBatchMaxRuns); break;
+            default: break;
         }
         __syncthreads();
-        if (d.vec == 4) {
-            if (d.nt) batch_copy<u32x4, true>(d, s_ia, s_ib, rows, row0);
-            else batch_copy<u32x4, false>(d, s_ia, s_ib, rows, row0);
-        } else {
-            if (d.nt) batch_copy<uint32_t, true>(d, s_ia, s_ib, rows, row0);
-            else batch_copy<uint32_t, false>(d, s_ia, s_ib, rows, row0);
+        if (threadIdx.x == 0) {
+            __threadfence();  // release: this item's writes before its count
+            const uint32_t prev = atomicAdd(&done[r], 1u);
+            if (d.last && host_done && prev + 1 == (uint32_t)d.n_items) {
+                // the request is complete: publish to the host
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+                __hip_atomic_store(&host_done[d.request], seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            }
         }
-        if (threadIdx.x == 0 && done) atomicAdd(&done[d.request], 1u);
         __syncthreads();
     }
 }
@@ -172,9 +341,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BatchHeader *__re
 // host side
 // ---------------------------------------------------------------------------
 struct BatchRequestPlan {
-    bool direct = false;    // handled by k_batch
-    int64_t items = 0;      // work items (direct) ...
-    size_t ws_bytes = 0;    // ... or workspace of its own phase sequence
+    bool direct = false;    // one copy step in k_batch
+    bool dpg = false;       // the DPG step chain in k_batch
+    bool own = false;       // its own phase sequence outside k_batch (dimension-order joins)
+    int64_t items = 0;      // copy items (direct)
+    size_t ws_bytes = 0;    // scratch: the DPG steps' arrays, or the own sequence's workspace
+    int lg_run = 0, n_runs = 0;  // DPG: run length and count
 };
 
 // With `arena` non-null the output is not placed yet: it will live somewhere in
@@ -232,45 +404,77 @@ static int tile_rows_for(int words) {
     return rows;
 }
 
+// Scratch of a request's DPG steps: hist, fill, run_off (runs + 1), run, inv
+// (one int32 per rid each) and INTERNAL (one moved row per rid).
+struct DpgScratch {
+    size_t off_hist = 0, off_fill = 0, off_run_off = 0, off_run = 0, off_inv = 0, off_internal = 0, bytes = 0;
+};
+
+static DpgScratch dpg_scratch(int64_t n, int n_runs, int moved_bytes) {
+    DpgScratch s;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    s.off_hist = take((size_t)n_runs * 4);
+    s.off_fill = take((size_t)n_runs * 4);
+    s.off_run_off = take((size_t)(n_runs + 1) * 4);
+    s.off_run = take((size_t)n * 4);
+    s.off_inv = take((size_t)n * 4);
+    s.off_internal = take((size_t)n * moved_bytes);
+    s.bytes = off;
+    return s;
+}
+
 static dpg_status plan_request(const dpg_ctx *ctx, const dpg_request &q, BatchRequestPlan *bp) {
     *bp = BatchRequestPlan();
     if (q.algo < DPG_ALGO_AUTO || q.algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
-    if (q.kind == DPG_REQ_RETRIEVE) {
-        RetrievePlan rp;
-        const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp);
-        if (st != DPG_OK) return st;
-        if (rp.algo == DPG_ALGO_DIRECT) {
-            bp->direct = true;
-            const int tr = tile_rows_for(q.rec_bytes / 4);
-            bp->items = (q.n + tr - 1) / tr;
-        } else {
-            bp->ws_bytes = rp.workspace;
-        }
+    const bool retrieve = q.kind == DPG_REQ_RETRIEVE;
+    size_t own_ws = 0;
+    if (!retrieve) {
+        own_ws = dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
+                                             (dpg_join_order)q.order, (dpg_algo)q.algo);
+        if (own_ws == 0) return DPG_ERR_INVALID_ARG;
+    }
+    RetrievePlan rp;
+    const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp, retrieve);
+    if (st != DPG_OK) return st;
+    if (!retrieve && q.order == DPG_JOIN_DIM_ORDER) {
+        bp->own = true;
+        bp->ws_bytes = own_ws;
         return DPG_OK;
     }
-    const size_t ws = dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
-                                                  (dpg_join_order)q.order, (dpg_algo)q.algo);
-    if (ws == 0) return DPG_ERR_INVALID_ARG;
-    RetrievePlan rp;
-    const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp);
-    if (st != DPG_OK) return st;
-    if (q.order == DPG_JOIN_FACT_ORDER && rp.algo == DPG_ALGO_DIRECT) {
+    if (rp.algo == DPG_ALGO_DIRECT) {
         bp->direct = true;
-        const int tr = tile_rows_for((q.fact_bytes + q.rec_bytes) / 4);
+        const int tr = tile_rows_for((retrieve ? q.rec_bytes : q.fact_bytes + q.rec_bytes) / 4);
         bp->items = (q.n + tr - 1) / tr;
-    } else {
-        bp->ws_bytes = ws;
+        return DPG_OK;
     }
+    // DPG inside the batch: the planner's run length, lengthened until the
+    // runs fit one distribute step
+    bp->dpg = true;
+    const int64_t N = q.n_src > 0 ? q.n_src : 1;
+    int lg = rp.log2_run;
+    while (((N + ((int64_t)1 << lg) - 1) >> lg) > kBatchMaxRuns) ++lg;
+    bp->lg_run = lg;
+    bp->n_runs = (int)((N + ((int64_t)1 << lg) - 1) >> lg);
+    bp->ws_bytes = dpg_scratch(q.n, bp->n_runs, q.rec_bytes).bytes;
     return DPG_OK;
 }
 
 struct BatchLayout {
-    size_t off_hdr = 0, off_desc = 0, off_queue = 0, off_done = 0, off_req = 0;
-    std::vector<size_t> req_off;  // per request: workspace of its own phase sequence
+    size_t off_hdr = 0, off_queue = 0, off_done = 0, off_desc = 0;
+    int32_t n_desc_cap = 0;
+    std::vector<size_t> req_off;  // per request: its DPG scratch or own-sequence workspace
     size_t total = 0;
 };
 
-static BatchLayout batch_layout(int32_t n_desc_cap, int32_t n, const std::vector<BatchRequestPlan> &plans) {
+// The header and the steps sit together, so one copy uploads both; the queue
+// word and the step counters sit together, so one fill kernel clears both
+// before k_batch runs.
+static BatchLayout batch_layout(int32_t n_desc_cap, const std::vector<BatchRequestPlan> &plans) {
     BatchLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -278,15 +482,23 @@ static BatchLayout batch_layout(int32_t n_desc_cap, int32_t n, const std::vector
         off = align_up(off + bytes);
         return at;
     };
+    L.n_desc_cap = n_desc_cap > 0 ? n_desc_cap : 1;
     L.off_hdr = take(sizeof(BatchHeader));
-    L.off_queue = take(sizeof(uint32_t));
-    L.off_desc = take((size_t)(n_desc_cap > 0 ? n_desc_cap : 1) * sizeof(BatchDesc));
-    L.off_done = take((size_t)(n > 0 ? n : 1) * sizeof(uint32_t));
+    L.off_desc = L.off_hdr + sizeof(BatchHeader);
+    off = align_up(L.off_desc + (size_t)L.n_desc_cap * sizeof(BatchDesc));
+    L.off_queue = take(sizeof(uint32_t) * (1 + (size_t)L.n_desc_cap));
+    L.off_done = L.off_queue + sizeof(uint32_t);
     L.req_off.assign(plans.size(), 0);
     for (size_t i = 0; i < plans.size(); ++i)
-        if (!plans[i].direct && plans[i].ws_bytes) L.req_off[i] = take(plans[i].ws_bytes);
+        if ((plans[i].dpg || plans[i].own) && plans[i].ws_bytes) L.req_off[i] = take(plans[i].ws_bytes);
     L.total = off;
     return L;
+}
+
+static int32_t steps_of(const std::vector<BatchRequestPlan> &plans) {
+    int32_t n = 0;
+    for (const auto &p : plans) n += p.direct ? 1 : p.dpg ? kBatchSteps : 0;
+    return n;
 }
 
 static dpg_status plan_batch(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n,
@@ -302,70 +514,167 @@ static dpg_status plan_batch(const dpg_ctx *ctx, const dpg_request *reqs, int32_
     return DPG_OK;
 }
 
-// Descriptors of the direct work, in request order.
+static void copy_shape(BatchDesc &d) {
+    d.op = OP_COPY;
+    d.tile_rows = tile_rows_for(d.wa + d.wb);
+    const uintptr_t al = (uintptr_t)d.a | (uintptr_t)d.b | (uintptr_t)d.out;
+    d.vec = (d.wa % 4 == 0 && d.wb % 4 == 0 && al % 16 == 0) ? 4 : 1;
+    const uint64_t we = (uint64_t)(d.wa + d.wb) / (uint64_t)d.vec;
+    d.magic = we > 1 ? (uint32_t)((0x100000000ull + we - 1) / we) : 0u;  // one element per row: j = e
+    d.nt = (double)d.n_rows * (d.wa + d.wb) * 4 > 256.0 * 1024 * 1024 ? 1 : 0;
+    d.n_items = (d.n_rows + d.tile_rows - 1) / d.tile_rows;
+}
+
+// The steps of the batch, in queue order: every request's first step, then
+// every request's second step, ...; scratch[i] is request i's DPG scratch.
 static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans,
-                        std::vector<BatchDesc> *descs, BatchHeader *hdr) {
+                        const std::vector<char *> &scratch, std::vector<BatchDesc> *descs, BatchHeader *hdr) {
     descs->clear();
-    int64_t items = 0;
+    std::vector<std::vector<BatchDesc>> chains(n);
     for (int32_t i = 0; i < n; ++i) {
-        if (!plans[i].direct || plans[i].items == 0) continue;
+        const BatchRequestPlan &p = plans[i];
         const dpg_request &q = reqs[i];
-        BatchDesc d{};
-        if (q.kind == DPG_REQ_RETRIEVE) {
-            d.a = (const uint32_t *)q.src;
-            d.idx_a = q.rids;
-            d.lim_a = q.n_src;
-            d.wa = q.rec_bytes / 4;
-            d.wb = 0;
-        } else {
-            d.a = (const uint32_t *)q.fact;
-            d.idx_a = nullptr;
-            d.lim_a = q.n;
-            d.b = (const uint32_t *)q.src;
-            d.lim_b = q.n_src;
-            d.wa = q.fact_bytes / 4;
-            d.wb = q.rec_bytes / 4;
-            d.fk_word = q.fk_offset / 4;
+        if (!p.direct && !p.dpg) continue;
+        const bool retrieve = q.kind == DPG_REQ_RETRIEVE;
+        BatchDesc base{};
+        base.request = i;
+        base.dep = -1;
+        if (q.n == 0) {
+            // nothing to move: one empty step marks the request done
+            BatchDesc e = base;
+            e.op = OP_ZERO;
+            e.n_items = 1;
+            e.last = 1;
+            chains[i].push_back(e);
+            continue;
         }
-        d.out = (uint32_t *)q.dst;
-        d.n_rows = q.n;
-        d.tile_rows = tile_rows_for(d.wa + d.wb);
-        const uintptr_t al = (uintptr_t)d.a | (uintptr_t)d.b | (uintptr_t)d.out;
-        d.vec = (d.wa % 4 == 0 && d.wb % 4 == 0 && al % 16 == 0) ? 4 : 1;
-        const uint64_t we = (uint64_t)(d.wa + d.wb) / (uint64_t)d.vec;
-        d.magic = we > 1 ? (uint32_t)((0x100000000ull + we - 1) / we) : 0u;  // one element per row: j = e
-        d.nt = (double)q.n * (d.wa + d.wb) * 4 > 256.0 * 1024 * 1024 ? 1 : 0;
-        d.item_start = items;
-        d.request = i;
-        items += plans[i].items;
-        descs->push_back(d);
+        if (p.direct) {
+            BatchDesc d = base;
+            if (retrieve) {
+                d.a = (const uint32_t *)q.src;
+                d.idx_a = q.rids;
+                d.lim_a = q.n_src;
+                d.wa = q.rec_bytes / 4;
+            } else {
+                d.a = (const uint32_t *)q.fact;
+                d.lim_a = q.n;
+                d.b = (const uint32_t *)q.src;
+                d.lim_b = q.n_src;
+                d.wa = q.fact_bytes / 4;
+                d.wb = q.rec_bytes / 4;
+                d.fk_word = q.fk_offset / 4;
+            }
+            d.out = (uint32_t *)q.dst;
+            d.n_rows = q.n;
+            copy_shape(d);
+            d.last = 1;
+            chains[i].push_back(d);
+            continue;
+        }
+        const DpgScratch sc = dpg_scratch(q.n, p.n_runs, q.rec_bytes);
+        char *w = scratch[i];
+        BatchDesc dist = base;
+        dist.ids = retrieve ? (const uint32_t *)q.rids : (const uint32_t *)q.fact;
+        dist.id_stride = retrieve ? 1 : q.fact_bytes / 4;
+        dist.id_word = retrieve ? 0 : q.fk_offset / 4;
+        dist.lim_a = q.n_src;
+        dist.n_rows = q.n;
+        dist.lg_run = p.lg_run;
+        dist.n_runs = p.n_runs;
+        dist.hist = (int32_t *)(w + sc.off_hist);
+        dist.fill = (int32_t *)(w + sc.off_fill);
+        dist.run_off = (int32_t *)(w + sc.off_run_off);
+        dist.run = (int32_t *)(w + sc.off_run);
+        dist.inv = (int32_t *)(w + sc.off_inv);
+        const int64_t dist_items = (q.n + kBatchDistTile - 1) / kBatchDistTile;
+        BatchDesc z = dist, h = dist, s = dist, x = dist;
+        z.op = OP_ZERO;
+        z.n_items = 1;
+        h.op = OP_HIST;
+        h.n_items = dist_items;
+        s.op = OP_SCAN;
+        s.n_items = 1;
+        x.op = OP_SCATTER;
+        x.n_items = dist_items;
+        uint32_t *internal = (uint32_t *)(w + sc.off_internal);
+        // Phase II: INTERNAL[k] = src[run[k]]
+        BatchDesc pr = base;
+        pr.a = (const uint32_t *)q.src;
+        pr.idx_a = dist.run;
+        pr.lim_a = q.n_src;
+        pr.wa = q.rec_bytes / 4;
+        pr.out = internal;
+        pr.n_rows = q.n;
+        copy_shape(pr);
+        // Phase III: dst[i] = INTERNAL[inv[i]], or fact[i] || INTERNAL[inv[i]]
+        BatchDesc g = base;
+        if (retrieve) {
+            g.a = internal;
+            g.idx_a = dist.inv;
+            g.lim_a = q.n;
+            g.wa = q.rec_bytes / 4;
+        } else {
+            g.a = (const uint32_t *)q.fact;
+            g.lim_a = q.n;
+            g.b = internal;
+            g.idx_b = dist.inv;
+            g.lim_b = q.n;
+            g.wa = q.fact_bytes / 4;
+            g.wb = q.rec_bytes / 4;
+        }
+        g.out = (uint32_t *)q.dst;
+        g.n_rows = q.n;
+        copy_shape(g);
+        g.last = 1;
+        chains[i] = {z, h, s, x, pr, g};
+    }
+    // queue order: step k of every request, for k = 0, 1, ...
+    std::vector<int32_t> prev_index(n, -1);
+    int64_t items = 0;
+    for (int k = 0; k < kBatchSteps; ++k) {
+        for (int32_t i = 0; i < n; ++i) {
+            if ((int)chains[i].size() <= k) continue;
+            BatchDesc d = chains[i][k];
+            d.dep = prev_index[i];
+            d.item_start = items;
+            items += d.n_items;
+            prev_index[i] = (int32_t)descs->size();
+            descs->push_back(d);
+        }
     }
     hdr->total_items = items;
     hdr->n_desc = (int32_t)descs->size();
+    hdr->seq = 0;
+    hdr->timeout = 0;
     hdr->pad = 0;
 }
 
 static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans) {
     double b = 0;
     for (int32_t i = 0; i < n; ++i) {
-        if (!plans[i].direct) continue;
         const dpg_request &q = reqs[i];
-        const double row = q.kind == DPG_REQ_RETRIEVE ? q.rec_bytes : q.fact_bytes + q.rec_bytes;
-        b += (double)q.n * (2.0 * row + (q.kind == DPG_REQ_RETRIEVE ? 4.0 : 0.0));
+        const double M = (double)q.n, R = q.rec_bytes;
+        const double row = q.kind == DPG_REQ_RETRIEVE ? R : q.fact_bytes + R;
+        const double F = q.kind == DPG_REQ_RETRIEVE ? 0.0 : q.fact_bytes;
+        if (plans[i].direct) b += M * (2.0 * row + (q.kind == DPG_REQ_RETRIEVE ? 4.0 : 0.0));
+        // DPG: distribute 16 per rid (rids read twice, run and inv written),
+        // probe 4 + 2R, gather inv 4 + INTERNAL R + fact F read, row written
+        else if (plans[i].dpg) b += M * (16.0 + 4.0 + 2.0 * R + 4.0 + R + F + row);
     }
     return b;
 }
 
 static int batch_grid(const dpg_ctx *ctx) { return ctx->n_cu * 4; }
 
-static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &L, double bytes, bool with_done,
-                                      hipStream_t stream) {
-    dpg_status st = launch_fill_i32(ctx, (int32_t *)(w + L.off_queue), 1, 0, stream);
+static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &L, double bytes,
+                                      uint32_t *host_done, hipStream_t stream) {
+    // queue word and every step counter back to zero
+    dpg_status st = launch_fill_i32(ctx, (int32_t *)(w + L.off_queue), 1 + (int64_t)L.n_desc_cap, 0, stream);
     if (st != DPG_OK) return st;
     ProfScope prof(ctx, K_BATCH, bytes, stream);
     hipLaunchKernelGGL(k_batch, dim3((unsigned)batch_grid(ctx)), dim3(kBatchThreads), 0, stream,
-                       (const BatchHeader *)(w + L.off_hdr), (const BatchDesc *)(w + L.off_desc),
-                       (uint32_t *)(w + L.off_queue), with_done ? (uint32_t *)(w + L.off_done) : nullptr);
+                       (BatchHeader *)(w + L.off_hdr), (const BatchDesc *)(w + L.off_desc),
+                       (uint32_t *)(w + L.off_queue), (uint32_t *)(w + L.off_done), host_done);
     DPG_HIP(hipGetLastError());
     return DPG_OK;
 }
@@ -375,29 +684,25 @@ static dpg_status run_own_sequences(dpg_ctx *ctx, const dpg_request *reqs, int32
                                     const std::vector<BatchRequestPlan> &plans, char *w, const BatchLayout &L,
                                     hipStream_t stream) {
     for (int32_t i = 0; i < n; ++i) {
-        if (plans[i].direct) continue;
+        if (!plans[i].own) continue;
         const dpg_request &q = reqs[i];
-        dpg_status st;
-        if (q.kind == DPG_REQ_RETRIEVE)
-            st = dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w + L.req_off[i],
-                              plans[i].ws_bytes, (dpg_algo)q.algo, 0, stream);
-        else
-            st = dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
-                             (dpg_join_order)q.order, w + L.req_off[i], plans[i].ws_bytes, (dpg_algo)q.algo, 0,
-                             stream);
+        const dpg_status st = dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes,
+                                          q.dst, (dpg_join_order)q.order, w + L.req_off[i], plans[i].ws_bytes,
+                                          (dpg_algo)q.algo, 0, stream);
         if (st != DPG_OK) return st;
     }
     return DPG_OK;
 }
 
 dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const void *arena, size_t arena_bytes,
-                              bool *direct, size_t *own_ws) {
+                              bool *batchable, size_t *own_ws, size_t *batch_ws) {
     dpg_status st = validate_request(q, arena, arena_bytes);
     if (st != DPG_OK) return st;
     BatchRequestPlan bp;
     st = plan_request(ctx, q, &bp);
     if (st != DPG_OK) return st;
-    *direct = bp.direct;
+    *batchable = bp.direct || bp.dpg;
+    *batch_ws = bp.dpg ? bp.ws_bytes : 0;
     *own_ws = q.kind == DPG_REQ_RETRIEVE
                   ? dpg_retrieve_workspace_bytes(ctx, q.n_src, q.rec_bytes, q.n, (dpg_algo)q.algo)
                   : dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
@@ -414,21 +719,33 @@ struct dpg_batch_graph {
     dpg::BatchLayout layout;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // pinned staging of header + descriptors, so the upload is asynchronous;
-    // `uploaded` marks when the previous upload has been consumed
+    // pinned staging of header + steps, so the upload is asynchronous (it is
+    // reused once the previous launch, whose upload precedes it in the
+    // stream, has finished)
     char *staging = nullptr;
-    hipEvent_t uploaded = nullptr;
-    bool upload_pending = false;
+    // per-request completion words (host memory the kernel writes) and the
+    // sequence number of the last launch
+    uint32_t *host_done = nullptr;
+    uint32_t seq = 0;
+    // recorded after every launch: destroy waits on it before freeing host_done
+    hipEvent_t finished = nullptr;
+    bool launched = false;
 };
 
 using namespace dpg;
 
 extern "C" {
 
+size_t dpg_batch_request_workspace_bytes(const dpg_ctx *ctx, const dpg_request *req) {
+    BatchRequestPlan bp;
+    if (!req || validate_request(*req) != DPG_OK || plan_request(ctx, *req, &bp) != DPG_OK) return 0;
+    return bp.dpg ? bp.ws_bytes : 0;
+}
+
 size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n) {
     std::vector<BatchRequestPlan> plans;
     if (plan_batch(ctx, reqs, n, &plans) != DPG_OK) return 0;
-    return batch_layout(n, n, plans).total;
+    return batch_layout(steps_of(plans), plans).total;
 }
 
 dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void *workspace, size_t workspace_bytes,
@@ -436,7 +753,7 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
     std::vector<BatchRequestPlan> plans;
     dpg_status st = plan_batch(ctx, reqs, n, &plans);
     if (st != DPG_OK) return st;
-    const BatchLayout L = batch_layout(n, n, plans);
+    const BatchLayout L = batch_layout(steps_of(plans), plans);
     if (n > 0) {
         if (workspace_bytes < L.total) return DPG_ERR_WORKSPACE_TOO_SMALL;
         if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
@@ -444,15 +761,19 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
     if (!ctx) return DPG_ERR_INVALID_ARG;
     if (n == 0) return DPG_OK;
     char *w = (char *)workspace;
+    std::vector<char *> scratch(n, nullptr);
+    for (int32_t i = 0; i < n; ++i) scratch[i] = w + L.req_off[i];
     std::vector<BatchDesc> descs;
     BatchHeader hdr;
-    build_descs(reqs, n, plans, &descs, &hdr);
+    build_descs(reqs, n, plans, scratch, &descs, &hdr);
     if (hdr.total_items > 0) {
-        // pageable source: the copy is staged before hipMemcpyAsync returns
-        DPG_HIP(hipMemcpyAsync(w + L.off_hdr, &hdr, sizeof(hdr), hipMemcpyHostToDevice, stream));
-        DPG_HIP(hipMemcpyAsync(w + L.off_desc, descs.data(), descs.size() * sizeof(BatchDesc),
-                               hipMemcpyHostToDevice, stream));
-        st = launch_batch_kernel(ctx, w, L, batch_bytes(reqs, n, plans), false, stream);
+        // header and steps in one copy (pageable source: staged before
+        // hipMemcpyAsync returns)
+        std::vector<char> up(sizeof(hdr) + descs.size() * sizeof(BatchDesc));
+        std::memcpy(up.data(), &hdr, sizeof(hdr));
+        std::memcpy(up.data() + sizeof(hdr), descs.data(), descs.size() * sizeof(BatchDesc));
+        DPG_HIP(hipMemcpyAsync(w + L.off_hdr, up.data(), up.size(), hipMemcpyHostToDevice, stream));
+        st = launch_batch_kernel(ctx, w, L, batch_bytes(reqs, n, plans), nullptr, stream);
         if (st != DPG_OK) return st;
     }
     return run_own_sequences(ctx, reqs, n, plans, w, L, stream);
@@ -460,17 +781,17 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
 
 size_t dpg_batch_graph_workspace_bytes(const dpg_ctx *ctx, int32_t max_requests) {
     (void)ctx;
-    if (max_requests < 1) return 0;
+    if (max_requests < 1 || max_requests > (INT32_MAX / kBatchSteps)) return 0;
     std::vector<BatchRequestPlan> none;
-    return batch_layout(max_requests, max_requests, none).total;
+    return batch_layout(max_requests * kBatchSteps, none).total;
 }
 
 dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *workspace, size_t workspace_bytes,
                                   hipStream_t stream, dpg_batch_graph **out) {
-    if (!ctx || !out || max_requests < 1) return DPG_ERR_INVALID_ARG;
+    if (!ctx || !out || max_requests < 1 || max_requests > (INT32_MAX / kBatchSteps)) return DPG_ERR_INVALID_ARG;
     *out = nullptr;
     std::vector<BatchRequestPlan> none;
-    const BatchLayout L = batch_layout(max_requests, max_requests, none);
+    const BatchLayout L = batch_layout(max_requests * kBatchSteps, none);
     if (workspace_bytes < L.total) return DPG_ERR_WORKSPACE_TOO_SMALL;
     if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
     dpg_batch_graph *g = new dpg_batch_graph();
@@ -478,23 +799,22 @@ dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *work
     g->max_requests = max_requests;
     g->ws = (char *)workspace;
     g->layout = L;
-    if (hipHostMalloc((void **)&g->staging, L.off_desc - L.off_hdr + (size_t)max_requests * sizeof(BatchDesc),
-                      hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&g->uploaded, hipEventDisableTiming) != hipSuccess) {
-        if (g->staging) (void)hipHostFree(g->staging);
-        delete g;
+    const size_t staging = sizeof(BatchHeader) + (size_t)L.n_desc_cap * sizeof(BatchDesc);
+    if (hipHostMalloc((void **)&g->staging, staging, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&g->host_done, (size_t)max_requests * sizeof(uint32_t), hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipEventCreateWithFlags(&g->finished, hipEventDisableTiming) != hipSuccess) {
+        dpg_batch_graph_destroy(g);
         return DPG_ERR_HIP;
     }
-    // the copied span also covers the queue word between header and
-    // descriptors (the graph zeroes it again before k_batch runs)
-    std::memset(g->staging, 0, L.off_desc - L.off_hdr);
-    // capture [reset queue, k_batch]; profiling events are not captured
+    std::memset(g->host_done, 0, (size_t)max_requests * sizeof(uint32_t));
+    // capture [reset queue and counters, k_batch]; profiling events are not captured
     const bool prof = ctx->profiling;
     ctx->profiling = false;
     dpg_status st = DPG_OK;
     if (hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal) != hipSuccess) st = DPG_ERR_HIP;
     if (st == DPG_OK) {
-        st = launch_batch_kernel(ctx, g->ws, L, 0, false, stream);
+        st = launch_batch_kernel(ctx, g->ws, L, 0, g->host_done, stream);
         hipGraph_t graph = nullptr;
         if (hipStreamEndCapture(stream, &graph) != hipSuccess) st = DPG_ERR_HIP;
         g->graph = graph;
@@ -513,6 +833,11 @@ dpg_status dpg_batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, i
     return dpg::batch_graph_launch(g, reqs, n, stream, true);
 }
 
+int32_t dpg_batch_graph_request_done(const dpg_batch_graph *g, int32_t request) {
+    if (!g || request < 0 || request >= g->max_requests || g->seq == 0) return 0;
+    return __atomic_load_n(&g->host_done[request], __ATOMIC_ACQUIRE) == g->seq ? 1 : 0;
+}
+
 }  // extern "C"
 
 namespace dpg {
@@ -524,26 +849,36 @@ dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32
     std::vector<BatchRequestPlan> plans;
     dpg_status st = plan_batch(g->ctx, reqs, n, &plans);
     if (st != DPG_OK) return st;
-    for (int32_t i = 0; i < n; ++i)
-        if (!plans[i].direct) return DPG_ERR_UNSUPPORTED;  // graph batches carry direct work only
+    // DPG steps take their scratch from each request's own workspace
+    std::vector<char *> scratch(n, nullptr);
+    for (int32_t i = 0; i < n; ++i) {
+        if (plans[i].own) return DPG_ERR_UNSUPPORTED;  // dimension-order joins are not graph work
+        if (!plans[i].dpg || reqs[i].n == 0) continue;
+        if (reqs[i].workspace_bytes < plans[i].ws_bytes) return DPG_ERR_WORKSPACE_TOO_SMALL;
+        if (!reqs[i].workspace || ((uintptr_t)reqs[i].workspace) % kAlign) return DPG_ERR_INVALID_ARG;
+        scratch[i] = (char *)reqs[i].workspace;
+    }
     if (n == 0) return DPG_OK;
     std::vector<BatchDesc> descs;
     BatchHeader hdr;
-    build_descs(reqs, n, plans, &descs, &hdr);
-    // the staging buffer may still feed the previous upload
-    if (g->upload_pending) DPG_HIP(hipEventSynchronize(g->uploaded));
-    // header and descriptors keep their workspace layout: one contiguous copy
-    const size_t span = g->layout.off_desc - g->layout.off_hdr + descs.size() * sizeof(BatchDesc);
+    build_descs(reqs, n, plans, scratch, &descs, &hdr);
+    hdr.seq = ++g->seq;
+    if (hdr.seq == 0) hdr.seq = ++g->seq;  // 0 is "never launched"
+    // the staging buffer may still feed the previous launch's upload
+    if (g->launched && hipEventQuery(g->finished) != hipSuccess) DPG_HIP(hipEventSynchronize(g->finished));
     std::memcpy(g->staging, &hdr, sizeof(hdr));
-    if (!descs.empty())
-        std::memcpy(g->staging + (g->layout.off_desc - g->layout.off_hdr), descs.data(),
-                    descs.size() * sizeof(BatchDesc));
-    DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_hdr, g->staging, span, hipMemcpyHostToDevice, stream));
-    DPG_HIP(hipEventRecord(g->uploaded, stream));
-    g->upload_pending = true;
-    if (!replay) return launch_batch_kernel(g->ctx, g->ws, g->layout, batch_bytes(reqs, n, plans), false, stream);
-    ProfScope prof(g->ctx, K_BATCH, batch_bytes(reqs, n, plans), stream);
-    DPG_HIP(hipGraphLaunch(g->exec, stream));
+    if (!descs.empty()) std::memcpy(g->staging + sizeof(hdr), descs.data(), descs.size() * sizeof(BatchDesc));
+    DPG_HIP(hipMemcpyAsync(g->ws + g->layout.off_hdr, g->staging, sizeof(hdr) + descs.size() * sizeof(BatchDesc),
+                           hipMemcpyHostToDevice, stream));
+    if (!replay) {
+        st = launch_batch_kernel(g->ctx, g->ws, g->layout, batch_bytes(reqs, n, plans), g->host_done, stream);
+        if (st != DPG_OK) return st;
+    } else {
+        ProfScope prof(g->ctx, K_BATCH, batch_bytes(reqs, n, plans), stream);
+        DPG_HIP(hipGraphLaunch(g->exec, stream));
+    }
+    DPG_HIP(hipEventRecord(g->finished, stream));
+    g->launched = true;
     return DPG_OK;
 }
 
@@ -553,11 +888,12 @@ extern "C" {
 
 void dpg_batch_graph_destroy(dpg_batch_graph *g) {
     if (!g) return;
-    if (g->upload_pending) (void)hipEventSynchronize(g->uploaded);
+    if (g->launched) (void)hipEventSynchronize(g->finished);  // the kernel writes host_done
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->uploaded) (void)hipEventDestroy(g->uploaded);
+    if (g->finished) (void)hipEventDestroy(g->finished);
     if (g->staging) (void)hipHostFree(g->staging);
+    if (g->host_done) (void)hipHostFree(g->host_done);
     delete g;
 }
 

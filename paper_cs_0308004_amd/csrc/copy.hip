@@ -40,20 +40,24 @@ __host__ __device__ constexpr int aligned_tile(int raw, int rec_bytes) {
     return t > 0 ? t : raw;
 }
 
-template <typename E, int WE>
+// TR > 0 (records of a fixed WE only): tiles of TR records, PER elements per
+// lane as needed (the last lanes of a tile repeat its last element); TR must
+// be a multiple of the 256-byte alignment step.
+template <typename E, int WE, int TR = 0>
 struct GatherShape {
     static constexpr int kEDw = sizeof(E) / 4;
     static constexpr int kInRange = (WE > 0 && WE * kEDw >= 16 && WE * kEDw <= 64);
-    static constexpr int PER = kInRange ? WE : 32 / kEDw;        // elements per thread
-    static constexpr int TILE = WE > 0 ? aligned_tile((256 * PER) / WE, WE * (int)sizeof(E)) : 0;
+    static constexpr int PER = TR > 0 ? (TR * WE + 255) / 256 : kInRange ? WE : 32 / kEDw;  // elements per thread
+    static constexpr int TILE = TR > 0 ? TR : WE > 0 ? aligned_tile((256 * PER) / WE, WE * (int)sizeof(E)) : 0;
+    static_assert(TR == 0 || (WE > 0 && aligned_tile(TR, WE * (int)sizeof(E)) == TR), "tile breaks the alignment");
 };
 
-template <typename E, int WE, bool NT>
+template <typename E, int WE, bool NT, int TR = 0>
 __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int32_t *__restrict__ idx,
                                             E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,
                                             uint32_t magic, int tile_rt, int remap) {
     extern __shared__ int32_t s_idx[];
-    using S = GatherShape<E, WE>;
+    using S = GatherShape<E, WE, TR>;
     constexpr int PER = S::PER;
     const int we = WE > 0 ? WE : we_rt;
     const int tile = WE > 0 ? S::TILE : tile_rt;
@@ -96,11 +100,11 @@ __device__ __forceinline__ void gather_tile(const E *__restrict__ src, const int
 
 // Three kernel symbols for the three roles, so profiles tell them apart.
 #define DPG_GATHER_KERNEL(NAME)                                                                              \
-    template <typename E, int WE, bool NT>                                                                   \
+    template <typename E, int WE, bool NT, int TR>                                                           \
     __global__ __launch_bounds__(256) void NAME(const E *__restrict__ src, const int32_t *__restrict__ idx, \
                                                 E *__restrict__ dst, int64_t n, int64_t limit, int we_rt,    \
                                                 uint32_t magic, int tile_rt, int remap) {                    \
-        gather_tile<E, WE, NT>(src, idx, dst, n, limit, we_rt, magic, tile_rt, remap);                      \
+        gather_tile<E, WE, NT, TR>(src, idx, dst, n, limit, we_rt, magic, tile_rt, remap);                  \
     }
 DPG_GATHER_KERNEL(k_direct_gather)
 DPG_GATHER_KERNEL(k_probe_cached)
@@ -219,10 +223,10 @@ dpg_status launch_probe_scatter(dpg_ctx *ctx, const void *src, int64_t limit, co
     return launch_scatter_t<uint32_t, 0>(src, run, pos, n_valid, dst, n, limit, we, remap, nt, stream);
 }
 
-template <typename E, int WE>
+template <typename E, int WE, int TR = 0>
 static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx, void *dst, int64_t n,
                                   int64_t limit, int we, int remap, hipStream_t stream) {
-    using S = GatherShape<E, WE>;
+    using S = GatherShape<E, WE, TR>;
     int tile;
     uint32_t magic = 0;
     if constexpr (WE > 0) {
@@ -241,10 +245,10 @@ static dpg_status launch_gather_t(int role, const void *src, const int32_t *idx,
 #define DPG_LAUNCH_ROLE(KERNEL)                                                                                    \
     do {                                                                                                           \
         if (nt)                                                                                                    \
-            hipLaunchKernelGGL((KERNEL<E, WE, true>), dim3((unsigned)grid), dim3(256), lds, stream, (const E *)src, \
-                               idx, (E *)dst, n, limit, we, magic, tile, remap);                                  \
+            hipLaunchKernelGGL((KERNEL<E, WE, true, TR>), dim3((unsigned)grid), dim3(256), lds, stream,             \
+                               (const E *)src, idx, (E *)dst, n, limit, we, magic, tile, remap);                  \
         else                                                                                                       \
-            hipLaunchKernelGGL((KERNEL<E, WE, false>), dim3((unsigned)grid), dim3(256), lds, stream,                \
+            hipLaunchKernelGGL((KERNEL<E, WE, false, TR>), dim3((unsigned)grid), dim3(256), lds, stream,            \
                                (const E *)src, idx, (E *)dst, n, limit, we, magic, tile, remap);                  \
     } while (0)
     if (role == K_PROBE_CACHED) DPG_LAUNCH_ROLE(k_probe_cached);
@@ -281,7 +285,15 @@ dpg_status launch_gather(dpg_ctx *ctx, int kernel_id, const void *src, int64_t l
     switch (we) {
         case 1: return launch_gather_t<uint32_t, 1>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
         case 3: return launch_gather_t<uint32_t, 3>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
-        case 25: return launch_gather_t<uint32_t, 25>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+        case 25:
+            // 100-byte records: tiles measured at 2^26 records -- 64 rows for
+            // random reads, 128 for the probe's region-local reads, 192 for
+            // the gather's reads from the run streams (256 rows: 1-2% slower)
+            if (kernel_id == K_PROBE_CACHED)
+                return launch_gather_t<uint32_t, 25, 128>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            if (kernel_id == K_GATHER_PHASE)
+                return launch_gather_t<uint32_t, 25, 192>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
+            return launch_gather_t<uint32_t, 25, 64>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
         default: return launch_gather_t<uint32_t, 0>(kernel_id, src, idx, dst, n, limit, we, remap, stream);
     }
 }

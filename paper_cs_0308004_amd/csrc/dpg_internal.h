@@ -272,13 +272,13 @@ int xcd_remap_flag(const dpg_ctx *ctx);
 // current device) once per device and store it in ctx->scratch.
 void scratch_init(dpg_ctx *ctx);
 
-// Validate one batch request and tell whether a batch would run it as direct
-// work inside the persistent launch; *own_ws is the workspace it needs when run
-// through its single-request entry point.
 // Validate and plan one request whose output will be placed later somewhere in
-// [arena, arena + arena_bytes) (the serving engine's arena).
+// [arena, arena + arena_bytes) (the serving engine's arena): *batchable tells
+// whether the persistent batch launch can run all its work; *own_ws is the
+// workspace of its single-request entry point; *batch_ws the scratch its
+// steps need inside a graph batch (0 for direct work).
 dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const void *arena, size_t arena_bytes,
-                              bool *direct, size_t *own_ws);
+                              bool *batchable, size_t *own_ws, size_t *batch_ws);
 // Upload a batch into a bound batch graph's workspace and run it: replay the
 // captured graph, or (replay = false) launch its two kernels directly.
 dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream,

@@ -361,12 +361,14 @@ extern "C" size_t dpg_key_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_fac
 extern "C" dpg_status dpg_key_join(dpg_ctx *ctx, const void *fact, int64_t n_fact, int32_t fact_bytes,
                                    int32_t fk_offset, const void *dim, int64_t n_dim, int32_t dim_bytes,
                                    const void *index, int32_t log2_slots, void *out, dpg_join_order order,
-                                   void *workspace, size_t workspace_bytes, dpg_algo algo, hipStream_t stream) {
+                                   void *workspace, size_t workspace_bytes, dpg_algo algo, int check_fk,
+                                   hipStream_t stream) {
     KeyJoinPlan p;
     dpg_status st = make_key_join_plan(ctx, n_fact, fact_bytes, fk_offset, n_dim, dim_bytes, log2_slots, order,
                                        algo, &p);
     if (st != DPG_OK) return st;
     const JoinPlan &jp = p.join;
+    if (check_fk != 0 && check_fk != 1) return DPG_ERR_INVALID_ARG;
     if (n_fact > 0 && (!fact || !out)) return DPG_ERR_INVALID_ARG;
     if (n_dim > 0 && !dim) return DPG_ERR_INVALID_ARG;
     if (!index || ((uintptr_t)index) % kAlign) return DPG_ERR_INVALID_ARG;
@@ -396,11 +398,14 @@ extern "C" dpg_status dpg_key_join(dpg_ctx *ctx, const void *fact, int64_t n_fac
     st = dpg_hash_lookup(ctx, index, n_dim, log2_slots, raw, n_fact, rid, w + p.off_lookup, p.lookup_bytes, algo,
                          stream);
     if (st != DPG_OK) return st;
-    // 2. every key must have a dimension row
-    bool bad = false;
-    st = check_ids(ctx, rid, n_fact, n_dim, (int32_t *)(w + jp.off_flag), stream, &bad);
-    if (st != DPG_OK) return st;
-    if (bad) return DPG_ERR_FK_OUT_OF_RANGE;
+    // 2. every key must have a dimension row (checked when asked: one stream
+    //    synchronization; otherwise a missing key's rid, -1, is read as row 0)
+    if (check_fk) {
+        bool bad = false;
+        st = check_ids(ctx, rid, n_fact, n_dim, (int32_t *)(w + jp.off_flag), stream, &bad);
+        if (st != DPG_OK) return st;
+        if (bad) return DPG_ERR_FK_OUT_OF_RANGE;
+    }
     if (!fact_order) {
         hipLaunchKernelGGL(k_join_iota, dim3((unsigned)((n_fact + 255) / 256)), dim3(256), 0, stream,
                            (uint32_t *)(w + jp.off_vals[0]), n_fact);

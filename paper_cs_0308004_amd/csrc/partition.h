@@ -60,12 +60,15 @@ inline PartPlan dist_partition(const RetrievePlan &p) {
 // non-null) holds the 2^nbits + 1 bucket boundaries.
 // item_off / item_chunk (optional) as for the column scan: work items of at
 // most item_chunk elements per bucket, for the LDS probe.
+// gate (stable passes only; may be null): a device word; the pass's kernels
+// return at once when it is zero, leaving every output as it was, so a host
+// can enqueue passes that the device decides to skip.
 dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in, const uint32_t *vals_in,
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev,
                             int32_t *item_off = nullptr, int item_chunk = 0, bool stable = true,
                             bool local_inv = false, uint32_t key_mul = 1, const uint32_t *split = nullptr,
-                            int n_split = 0, uint32_t *idx_out = nullptr);
+                            int n_split = 0, uint32_t *idx_out = nullptr, const int32_t *gate = nullptr);
 
 // Exclusive scan of a[0..n) in place; *total = the sum (device).  scratch:
 // scan_1d_scratch_bytes(n).
@@ -73,8 +76,10 @@ size_t scan_1d_scratch_bytes(int64_t n);
 dpg_status launch_scan_1d(dpg_ctx *ctx, int32_t *a, int64_t n, int32_t *scratch, int32_t *total,
                           hipStream_t stream);
 
+// gate (may be null): a device word; every kernel of the scan returns at once
+// when it is zero (the scan then writes nothing).
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
-                              hipStream_t stream);
+                              hipStream_t stream, const int32_t *gate = nullptr);
 
 }  // namespace dpg

@@ -142,7 +142,9 @@ __global__ __launch_bounds__(kPartThreads) void k_part_hist(const K *__restrict_
                                                             int nbits, uint64_t limit, int T, uint32_t key_mul,
                                                             int32_t *__restrict__ cnt,
                                                             const uint32_t *__restrict__ split,
-                                                            const int32_t *__restrict__ cell_lo, int n_split) {
+                                                            const int32_t *__restrict__ cell_lo, int n_split,
+                                                            const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ int32_t h[kPartWaves][kMaxDigitBuckets];
     extern __shared__ uint32_t s_split_h[];
     const int nb = 1 << nbits;
@@ -228,7 +230,8 @@ template <typename K, bool HAS_VAL, int PER>
 __global__ __launch_bounds__(kPartThreads) void k_part_scatter(
     const K *__restrict__ keys, const uint32_t *__restrict__ vals, int64_t n, int shift, int nbits,
     uint64_t limit, int64_t nT, const int32_t *__restrict__ off, K *__restrict__ keys_out,
-    uint32_t *__restrict__ vals_out, int32_t *__restrict__ inv, int remap) {
+    uint32_t *__restrict__ vals_out, int32_t *__restrict__ inv, int remap, const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     constexpr int T = kPartThreads * PER;
     extern __shared__ __align__(16) char smem[];
     K *s_key = (K *)smem;
@@ -466,12 +469,12 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int w
 template <typename K, bool HAS_VAL, int PER>
 static dpg_status launch_scatter_t(const PartPlan &p, const void *keys_in, const uint32_t *vals_in, void *keys_out,
                                    uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit, const int32_t *off,
-                                   int remap, hipStream_t stream) {
+                                   int remap, const int32_t *gate, hipStream_t stream) {
     constexpr int T = kPartThreads * PER;
     const size_t lds = sizeof(K) * T + (HAS_VAL ? sizeof(uint32_t) * T : 0);
     hipLaunchKernelGGL((k_part_scatter<K, HAS_VAL, PER>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), lds, stream,
                        (const K *)keys_in, vals_in, p.n, shift, p.nbits, limit, p.n_tiles, off, (K *)keys_out,
-                       vals_out, inv, remap);
+                       vals_out, inv, remap, gate);
     DPG_HIP(hipGetLastError());
     return DPG_OK;
 }
@@ -480,7 +483,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                             void *keys_out, uint32_t *vals_out, int32_t *inv, int shift, uint64_t limit,
                             void *scratch, hipStream_t stream, int32_t **bucket_off_dev, int32_t *item_off,
                             int item_chunk, bool stable, bool local_inv, uint32_t key_mul, const uint32_t *split,
-                            int n_split, uint32_t *idx_out) {
+                            int n_split, uint32_t *idx_out, const int32_t *gate) {
     char *w = (char *)scratch;
     int32_t *cnt = (int32_t *)(w + p.off_cnt);
     int32_t *csum = (int32_t *)(w + p.off_csum);
@@ -498,6 +501,9 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (!split) n_split = 0;
     if (split && (stable || p.key_bytes != 4 || p.has_val || n_split < 0 || n_split >= nb)) return DPG_ERR_UNSUPPORTED;
     if (idx_out && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
+    // a gate (device word: the pass runs only if it is non-zero) is taken by
+    // the stable 256-thread pass only
+    if (gate && (!stable || wide || split)) return DPG_ERR_UNSUPPORTED;
     const size_t split_lds = split_lds_bytes(n_split, split != nullptr);
     const int32_t *cells = (const int32_t *)(w + p.off_cells);
     if (split) {
@@ -517,16 +523,16 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         else if (p.key_bytes == 8)
             hipLaunchKernelGGL((k_part_hist<uint64_t, false>), dim3((unsigned)p.n_tiles), dim3(kPartThreads), 0, stream,
                                (const uint64_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, 1u, cnt, nullptr,
-                               nullptr, 0);
+                               nullptr, 0, gate);
         else
             hipLaunchKernelGGL((split ? k_part_hist<uint32_t, true> : k_part_hist<uint32_t, false>),
                                dim3((unsigned)p.n_tiles), dim3(kPartThreads), split_lds,
                                stream, (const uint32_t *)keys_in, p.n, shift, p.nbits, limit, p.tile, key_mul, cnt,
-                               split, cells, n_split);
+                               split, cells, n_split, gate);
         DPG_HIP(hipGetLastError());
     }
     dpg_status st = launch_column_scan(ctx, cnt, p.n_tiles, nb, csum, p.n_chunks, total, bucket_off, item_off,
-                                       item_chunk, stream);
+                                       item_chunk, stream, gate);
     if (st != DPG_OK) return st;
     ProfScope prof(ctx, stable ? K_PART_SCATTER : K_PART_SCATTER_UNSTABLE,
                    2.0 * elem * p.n + (inv ? 4.0 * p.n : 0.0) + 4.0 * p.n_tiles * nb, stream);
@@ -534,13 +540,13 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (p.key_bytes == 8) {
         if (p.has_val)
             return launch_scatter_t<uint64_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit,
-                                                        cnt, remap, stream);
+                                                        cnt, remap, gate, stream);
         return launch_scatter_t<uint64_t, false, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
-                                                     remap, stream);
+                                                     remap, gate, stream);
     }
     if (p.has_val)
         return launch_scatter_t<uint32_t, true, 16>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
-                                                    remap, stream);
+                                                    remap, gate, stream);
     if (!stable) {
         const size_t lds = sizeof(uint32_t) * p.tile + 2 * sizeof(int32_t) * nb + split_lds +
                            (idx_out ? sizeof(uint32_t) * p.tile : 0);
@@ -572,7 +578,7 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
         return DPG_OK;
     }
     return launch_scatter_t<uint32_t, false, 32>(p, keys_in, vals_in, keys_out, vals_out, inv, shift, limit, cnt,
-                                                 remap, stream);
+                                                 remap, gate, stream);
 }
 
 }  // namespace dpg

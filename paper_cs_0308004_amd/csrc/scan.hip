@@ -13,7 +13,9 @@ constexpr int kScanChunkRows = 32;
 
 // csum[b][c] = sum of cnt[t][b] over the rows t of chunk c.
 __global__ __launch_bounds__(256) void k_scan_chunks(const int32_t *__restrict__ cnt, int64_t nT, int B,
-                                                     int32_t *__restrict__ csum, int64_t nC) {
+                                                     int32_t *__restrict__ csum, int64_t nC,
+                                                     const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * 256 + threadIdx.x;
     if (b >= B) return;
@@ -35,7 +37,8 @@ __device__ __forceinline__ int32_t wave_inclusive_scan(int32_t x) {
 
 // One wave per run b: exclusive scan of csum[b][*] in place, total[b] = sum.
 __global__ __launch_bounds__(256) void k_scan_cols(int32_t *__restrict__ csum, int64_t nC, int B,
-                                                   int32_t *__restrict__ total) {
+                                                   int32_t *__restrict__ total, const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (b >= B) return;
@@ -55,7 +58,8 @@ __global__ __launch_bounds__(256) void k_scan_cols(int32_t *__restrict__ csum, i
 // item_off[b] = sum over b' < b of ceil(total[b'] / chunk).
 __global__ __launch_bounds__(1024) void k_scan_base(const int32_t *__restrict__ total, int B,
                                                     int32_t *__restrict__ run_off, int32_t *__restrict__ item_off,
-                                                    int chunk) {
+                                                    int chunk, const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ int32_t wsum[2][16];
     __shared__ int32_t carry[2];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -95,7 +99,9 @@ __global__ __launch_bounds__(1024) void k_scan_base(const int32_t *__restrict__ 
 // cnt[t][b] <- run_off[b] + rids of run b in tiles before t.
 __global__ __launch_bounds__(256) void k_scan_apply(int32_t *__restrict__ cnt, int64_t nT, int B,
                                                     const int32_t *__restrict__ csum, int64_t nC,
-                                                    const int32_t *__restrict__ run_off) {
+                                                    const int32_t *__restrict__ run_off,
+                                                    const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int64_t c = blockIdx.x;
     const int b = blockIdx.y * 256 + threadIdx.x;
     if (b >= B) return;
@@ -210,7 +216,9 @@ constexpr int64_t kScanSmallMax = 15360;  // 60 KiB of LDS
 
 __global__ __launch_bounds__(kScan1dThreads) void k_scan_small(int32_t *__restrict__ cnt, int nT, int B,
                                                                int32_t *__restrict__ bucket_off,
-                                                               int32_t *__restrict__ item_off, int chunk) {
+                                                               int32_t *__restrict__ item_off, int chunk,
+                                                               const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     extern __shared__ int32_t s_col[];  // nT * B entries, s_col[b * nT + t] = cnt[t][b]
     __shared__ int32_t s_w[kScan1dThreads / 64];
     __shared__ int32_t s_total, s_part, s_carry;
@@ -264,35 +272,36 @@ __global__ __launch_bounds__(kScan1dThreads) void k_scan_small(int32_t *__restri
 
 dpg_status launch_column_scan(dpg_ctx *ctx, int32_t *cnt, int64_t nT, int B, int32_t *csum, int64_t nC,
                               int32_t *total, int32_t *bucket_off, int32_t *item_off, int item_chunk,
-                              hipStream_t stream) {
+                              hipStream_t stream, const int32_t *gate) {
     if (nT * (int64_t)B <= kScanSmallMax) {
         // one workgroup; chunk sums and column totals are not needed
         ProfScope prof(ctx, K_SCAN_SMALL, 8.0 * nT * B + 4.0 * B, stream);
         hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(kScan1dThreads), (size_t)nT * B * sizeof(int32_t), stream, cnt,
-                           (int)nT, B, bucket_off, item_off, item_chunk > 0 ? item_chunk : 1);
+                           (int)nT, B, bucket_off, item_off, item_chunk > 0 ? item_chunk : 1, gate);
         DPG_HIP(hipGetLastError());
         return DPG_OK;
     }
     const unsigned gy = (unsigned)((B + 255) / 256);
     {
         ProfScope prof(ctx, K_SCAN_CHUNKS, 4.0 * nT * B + 4.0 * nC * B, stream);
-        hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nC, gy), dim3(256), 0, stream, cnt, nT, B, csum, nC);
+        hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nC, gy), dim3(256), 0, stream, cnt, nT, B, csum, nC, gate);
         DPG_HIP(hipGetLastError());
     }
     {
         ProfScope prof(ctx, K_SCAN_COLS, 8.0 * nC * B, stream);
-        hipLaunchKernelGGL(k_scan_cols, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, stream, csum, nC, B, total);
+        hipLaunchKernelGGL(k_scan_cols, dim3((unsigned)((B + 3) / 4)), dim3(256), 0, stream, csum, nC, B, total, gate);
         DPG_HIP(hipGetLastError());
     }
     {
         ProfScope prof(ctx, K_SCAN_BASE, 12.0 * B, stream);
-        hipLaunchKernelGGL(k_scan_base, dim3(1), dim3(1024), 0, stream, total, B, bucket_off, item_off, item_chunk);
+        hipLaunchKernelGGL(k_scan_base, dim3(1), dim3(1024), 0, stream, total, B, bucket_off, item_off, item_chunk,
+                           gate);
         DPG_HIP(hipGetLastError());
     }
     {
         ProfScope prof(ctx, K_SCAN_APPLY, 8.0 * nT * B + 4.0 * nC * B, stream);
         hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nC, gy), dim3(256), 0, stream, cnt, nT, B, csum, nC,
-                           bucket_off);
+                           bucket_off, gate);
         DPG_HIP(hipGetLastError());
     }
     return DPG_OK;

@@ -11,21 +11,26 @@
 //     whole arena fails at once.  Batches of direct work use a descriptor
 //     workspace each slot owns, so launching never allocates.
 //   * Batching: whenever one of the `max_inflight` stream slots is free, the
-//     run of small direct-work requests at the head of the admitted queue (up
-//     to max_batch_requests, outputs up to batch_max_kib each) is launched
-//     there as one persistent batch -- a replay of the slot's captured graph,
-//     or the same two kernels launched directly -- after waiting up to
-//     batch_window_us for a partial batch to fill; any other request runs
-//     alone through its single-request entry point, whose dedicated kernels
-//     are faster for large outputs and need no batching to hide launch cost.
-//     A batch that would hold a single request also takes that path, so
+//     small requests of the admitted queue (in admission order, up to
+//     max_batch_requests, outputs up to batch_max_kib each; requests that run
+//     alone keep their place between them) are launched there as one
+//     persistent batch -- a replay of the slot's captured graph, or
+//     the same two kernels launched directly -- after waiting up to
+//     batch_window_us for a partial batch to fill.  A batch carries direct
+//     work and DPG work alike (a DPG request's steps use scratch reserved for
+//     it at admission); dimension-order joins and large requests run alone
+//     through their single-request entry point, whose dedicated kernels are
+//     faster for large outputs and need no batching to hide launch cost.  A
+//     batch that would hold a single request also takes that path, so
 //     batching costs nothing at low load.  With max_batch_requests = 1 every
 //     request takes it (the per-request baseline).
 //     Requests arriving while batches run are admitted and launched on the
 //     next free slot, so their work overlaps on the device.
-//   * Completion: a batch's event marks all its requests done; their latency
-//     is completion time minus submit time (host steady clock).  Outputs stay
-//     valid until released.
+//   * Completion: a request of a persistent batch is done as soon as the
+//     kernel sets its completion word (host memory), while the rest of the
+//     batch may still run; a request launched alone, when its stream event
+//     fires.  Latency is completion time minus submit time (host steady
+//     clock).  Outputs stay valid until released.
 // One scheduler thread owns the context and all HIP calls.
 #include <algorithm>
 #include <chrono>
@@ -62,6 +67,7 @@ struct Ticket {
     dpg_status status = DPG_OK;
     bool batched = false;          // runs inside a slot's persistent batch launch
     size_t own_ws = 0;             // workspace of its single-request entry point
+    bool finished = false;         // completed (DONE or FAILED) while its batch may still run
     size_t out_off = 0, out_bytes = 0, ws_off = 0, ws_bytes = 0;
     bool has_out = false, has_ws = false;
     Clock::time_point submit, admit, done;
@@ -71,7 +77,8 @@ struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t event = nullptr;
     bool busy = false;
-    std::vector<uint64_t> tickets;
+    bool batch_launch = false;      // tickets run as one persistent batch (per-request completion words)
+    std::vector<uint64_t> tickets;  // in the order of the launched request array
     dpg_batch_graph *graph = nullptr;
     size_t batch_ws_off = 0, batch_ws_bytes = 0;  // descriptors of a batch of direct work
 };
@@ -111,30 +118,56 @@ struct dpg_server {
 
 namespace dpg {
 
+// One ticket is finished: its workspace goes back to the arena, its output
+// stays until released.
+static void finish_ticket(dpg_server *s, uint64_t t, dpg_status st, Clock::time_point now) {
+    auto it = s->tickets.find(t);
+    if (it == s->tickets.end()) return;
+    Ticket &tk = it->second;
+    if (tk.finished) return;
+    tk.finished = true;
+    tk.done = now;
+    if (tk.has_ws) s->arena->release(tk.ws_off);
+    tk.has_ws = false;
+    if (st == DPG_OK) {
+        tk.state = T_DONE;
+        s->n_completed++;
+        s->bytes_delivered += (double)tk.out_bytes;
+        s->latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - tk.submit).count());
+    } else {
+        tk.state = T_FAILED;
+        tk.status = st;
+        s->n_failed++;
+    }
+    s->completed.push_back(t);
+    s->last_done = now;
+}
+
+// The slot's launch has ended (its stream event): every ticket not yet
+// finished is, and the slot is free.
 static void finish_batch(dpg_server *s, Slot &sl, dpg_status st) {
     const auto now = Clock::now();
-    for (uint64_t t : sl.tickets) {
-        auto it = s->tickets.find(t);
-        if (it == s->tickets.end()) continue;
-        Ticket &tk = it->second;
-        tk.done = now;
-        if (tk.has_ws) s->arena->release(tk.ws_off);
-        tk.has_ws = false;
-        if (st == DPG_OK) {
-            tk.state = T_DONE;
-            s->n_completed++;
-            s->bytes_delivered += (double)tk.out_bytes;
-            s->latencies_ms.push_back(std::chrono::duration<double, std::milli>(now - tk.submit).count());
-        } else {
-            tk.state = T_FAILED;
-            tk.status = st;
-            s->n_failed++;
-        }
-        s->completed.push_back(t);
-    }
-    s->last_done = now;
+    for (uint64_t t : sl.tickets) finish_ticket(s, t, st, now);
     sl.tickets.clear();
     sl.busy = false;
+    sl.batch_launch = false;
+}
+
+// Requests of a running persistent batch whose completion word is set are
+// finished before the rest of the batch.
+static bool finish_done_requests(dpg_server *s, Slot &sl) {
+    if (!sl.batch_launch) return false;
+    bool any = false;
+    const auto now = Clock::now();
+    for (size_t i = 0; i < sl.tickets.size(); ++i) {
+        auto it = s->tickets.find(sl.tickets[i]);
+        if (it == s->tickets.end() || it->second.finished) continue;
+        if (dpg_batch_graph_request_done(sl.graph, (int32_t)i)) {
+            finish_ticket(s, sl.tickets[i], DPG_OK, now);
+            any = true;
+        }
+    }
+    return any;
 }
 
 // Launch `batch` on the slot: batched tickets together in one persistent
@@ -146,11 +179,12 @@ static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> 
     const Ticket &first = s->tickets[batch[0]];
     // A batch of one runs through the single-request entry point (no
     // descriptor upload), borrowing the idle slot's descriptor workspace.
-    const bool alone = first.batched && batch.size() == 1 && first.own_ws <= sl.batch_ws_bytes;
+    const bool alone = first.batched && batch.size() == 1 && (first.has_ws || first.own_ws <= sl.batch_ws_bytes);
     if (!first.batched || alone) {
         const dpg_request &q = first.req;
-        char *w = alone ? s->base + sl.batch_ws_off : (first.has_ws ? s->base + first.ws_off : nullptr);
-        const size_t wb = alone ? sl.batch_ws_bytes : first.ws_bytes;
+        const bool slot_ws = alone && !first.has_ws;
+        char *w = slot_ws ? s->base + sl.batch_ws_off : (first.has_ws ? s->base + first.ws_off : nullptr);
+        const size_t wb = slot_ws ? sl.batch_ws_bytes : first.ws_bytes;
         st = q.kind == DPG_REQ_RETRIEVE
                  ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w, wb, (dpg_algo)q.algo, 0,
                                 sl.stream)
@@ -159,13 +193,21 @@ static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> 
     } else {
         std::vector<dpg_request> reqs;
         reqs.reserve(batch.size());
-        for (uint64_t t : batch) reqs.push_back(s->tickets[t].req);
+        for (uint64_t t : batch) {
+            const Ticket &tk = s->tickets[t];
+            dpg_request q = tk.req;
+            // the scratch of a DPG request's steps, reserved at admission
+            q.workspace = tk.has_ws ? s->base + tk.ws_off : nullptr;
+            q.workspace_bytes = tk.has_ws ? tk.ws_bytes : 0;
+            reqs.push_back(q);
+        }
         const int32_t n = (int32_t)reqs.size();
         st = batch_graph_launch(sl.graph, reqs.data(), n, sl.stream, s->cfg.use_graph != 0);
     }
     if (st != DPG_OK) return st;
     if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
     sl.tickets = batch;
+    sl.batch_launch = first.batched && !alone;
     sl.busy = true;
     s->batches++;
     for (uint64_t t : batch) s->tickets[t].state = T_RUNNING;
@@ -180,6 +222,7 @@ static void scheduler(dpg_server *s) {
         // 1. completions
         for (Slot &sl : s->slots) {
             if (!sl.busy) continue;
+            changed |= finish_done_requests(s, sl);
             const hipError_t q = hipEventQuery(sl.event);
             if (q == hipSuccess) {
                 finish_batch(s, sl, DPG_OK);
@@ -219,34 +262,44 @@ static void scheduler(dpg_server *s) {
             tk.admit = Clock::now();
             s->admitted.push_back(t);
         }
-        // 3. launches on free slots: the run of batched tickets at the head
-        //    (up to max_batch_requests), or the single unbatched head ticket
+        // 3. launches on free slots: an unbatched ticket at the head runs
+        //    alone; otherwise the batched tickets of the admitted queue, in
+        //    admission order (up to max_batch_requests), run as one batch --
+        //    unbatched tickets between them keep their place and take the
+        //    next free slot once they reach the head
         bool window_wait = false;
         for (Slot &sl : s->slots) {
             if (sl.busy || s->admitted.empty()) continue;
             std::vector<uint64_t> batch;
             const bool batched = s->tickets[s->admitted.front()].batched;
-            if (batched && s->cfg.batch_window_us > 0 && !s->stop) {
-                // a partial batch waits (up to the window) for more requests
-                size_t run = 0;
-                for (uint64_t t : s->admitted) {
-                    if (!s->tickets[t].batched || (int32_t)run >= s->cfg.max_batch_requests) break;
-                    ++run;
-                }
-                const double waited =
-                    std::chrono::duration<double, std::micro>(Clock::now() - s->tickets[s->admitted.front()].admit)
-                        .count();
-                if ((int32_t)run < s->cfg.max_batch_requests && run == s->admitted.size() &&
-                    waited < s->cfg.batch_window_us) {
-                    window_wait = true;
-                    break;
-                }
-            }
-            while (!s->admitted.empty() && (int32_t)batch.size() < s->cfg.max_batch_requests &&
-                   s->tickets[s->admitted.front()].batched == batched) {
+            if (!batched) {
                 batch.push_back(s->admitted.front());
                 s->admitted.pop_front();
-                if (!batched) break;
+            } else {
+                size_t avail = 0;
+                for (uint64_t t : s->admitted) {
+                    if ((int32_t)avail >= s->cfg.max_batch_requests) break;
+                    avail += s->tickets[t].batched ? 1 : 0;
+                }
+                if (s->cfg.batch_window_us > 0 && !s->stop && (int32_t)avail < s->cfg.max_batch_requests) {
+                    // a partial batch waits (up to the window) for more requests
+                    const double waited = std::chrono::duration<double, std::micro>(
+                                              Clock::now() - s->tickets[s->admitted.front()].admit)
+                                              .count();
+                    if (waited < s->cfg.batch_window_us) {
+                        window_wait = true;
+                        break;
+                    }
+                }
+                for (auto it = s->admitted.begin();
+                     it != s->admitted.end() && (int32_t)batch.size() < s->cfg.max_batch_requests;) {
+                    if (s->tickets[*it].batched) {
+                        batch.push_back(*it);
+                        it = s->admitted.erase(it);
+                    } else {
+                        ++it;
+                    }
+                }
             }
             const auto t_launch = Clock::now();
             const dpg_status st = launch_on_slot(s, sl, batch);
@@ -376,14 +429,17 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
     tk.req.dst = nullptr;
     tk.out_bytes = output_bytes(*req);
     tk.submit = Clock::now();
-    bool direct = false;
-    size_t own_ws = 0;
+    bool batchable = false;
+    size_t own_ws = 0, batch_ws = 0;
     // the output will live somewhere in the arena: inputs must lie outside it
-    tk.status = plan_batch_request(s->ctx, tk.req, s->base, s->cfg.arena_bytes, &direct, &own_ws);
+    tk.status = plan_batch_request(s->ctx, tk.req, s->base, s->cfg.arena_bytes, &batchable, &own_ws, &batch_ws);
     if (tk.status == DPG_OK) {
         const size_t max_batched = (size_t)(s->cfg.batch_max_kib > 0 ? s->cfg.batch_max_kib : 4096) << 10;
-        tk.batched = direct && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
-        tk.ws_bytes = tk.batched ? 0 : own_ws;
+        tk.batched = batchable && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
+        // direct work in a batch needs no workspace of its own; DPG steps
+        // need scratch (enough for the single-request entry point too, which
+        // runs a batch of one)
+        tk.ws_bytes = !tk.batched ? own_ws : batch_ws ? std::max(own_ws, batch_ws) : 0;
         tk.own_ws = own_ws;
     } else {
         tk.state = T_FAILED;

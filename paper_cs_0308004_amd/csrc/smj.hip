@@ -112,67 +112,74 @@ __device__ __forceinline__ int64_t smj_row_of(const int32_t *off, int64_t l, int
 constexpr int kSmjPer = 32;
 constexpr int kSmjEmitCap = 2048;
 
+// Result rows [0, n_out) in tiles of `tile` rows, grid-stride over the
+// tiles.  n_dev (may be null): the row count is min(*n_dev, n_out), read on
+// the device (the caller then sizes n_out by the output's capacity).
 __global__ __launch_bounds__(256) void k_smj_emit(const uint32_t *__restrict__ R, int wr, int64_t nr,
                                                   const uint32_t *__restrict__ S, int ws, int64_t ns,
                                                   const int32_t *__restrict__ off, const int32_t *__restrict__ lo,
                                                   uint32_t *__restrict__ out, int64_t n_out, int tile,
-                                                  uint32_t magic) {
+                                                  uint32_t magic, const unsigned long long *__restrict__ n_dev) {
     extern __shared__ int32_t s_ab[];
     __shared__ int32_t s_off[kSmjEmitCap], s_lo[kSmjEmitCap];
     __shared__ int64_t s_span[2];
     int32_t *s_a = s_ab, *s_b = s_ab + tile;
-    const int64_t base = (int64_t)blockIdx.x * tile;
-    const int cnt = (int)min((int64_t)tile, n_out - base);
-    if (threadIdx.x == 0) s_span[0] = smj_row_of(off, 0, nr, base);
-    if (threadIdx.x == 64) s_span[1] = smj_row_of(off, 0, nr, base + cnt - 1);
-    __syncthreads();
-    const int64_t af = s_span[0], span = s_span[1] - af + 1;
-    const bool staged = span <= kSmjEmitCap;
-    if (staged)
-        for (int i = threadIdx.x; i < (int)span; i += 256) {
-            s_off[i] = off[af + i];
-            s_lo[i] = lo[af + i];
+    if (n_dev) n_out = min(n_out, (int64_t)*n_dev);
+    for (int64_t t = blockIdx.x; t * tile < n_out; t += gridDim.x) {
+        const int64_t base = t * tile;
+        const int cnt = (int)min((int64_t)tile, n_out - base);
+        if (threadIdx.x == 0) s_span[0] = smj_row_of(off, 0, nr, base);
+        if (threadIdx.x == 64) s_span[1] = smj_row_of(off, 0, nr, base + cnt - 1);
+        __syncthreads();
+        const int64_t af = s_span[0], span = s_span[1] - af + 1;
+        const bool staged = span <= kSmjEmitCap;
+        if (staged)
+            for (int i = threadIdx.x; i < (int)span; i += 256) {
+                s_off[i] = off[af + i];
+                s_lo[i] = lo[af + i];
+            }
+        __syncthreads();
+        for (int j = threadIdx.x; j < cnt; j += 256) {
+            const int64_t o = base + j;
+            int64_t a, first, start;
+            if (staged) {
+                const int i = (int)smj_row_of(s_off, 0, span, o);
+                a = af + i;
+                first = s_off[i];
+                start = s_lo[i];
+            } else {
+                a = smj_row_of(off, af, af + span, o);
+                first = off[a];
+                start = lo[a];
+            }
+            int64_t b = start + (o - first);
+            b = (b >= 0 && b < ns) ? b : 0;
+            s_a[j] = (int32_t)a;
+            s_b[j] = (int32_t)b;
         }
-    __syncthreads();
-    for (int j = threadIdx.x; j < cnt; j += 256) {
-        const int64_t o = base + j;
-        int64_t a, first, start;
-        if (staged) {
-            const int i = (int)smj_row_of(s_off, 0, span, o);
-            a = af + i;
-            first = s_off[i];
-            start = s_lo[i];
-        } else {
-            a = smj_row_of(off, af, af + span, o);
-            first = off[a];
-            start = lo[a];
+        __syncthreads();
+        const int W = wr + ws;
+        const int total = cnt * W;
+        int64_t src[kSmjPer];
+        bool from_r[kSmjPer];
+    #pragma unroll
+        for (int k = 0; k < kSmjPer; ++k) {
+            const int e = min((int)threadIdx.x + k * 256, total - 1);
+            const int j = (int)__umulhi((uint32_t)e, magic);
+            const int w = e - j * W;
+            from_r[k] = w < wr;
+            src[k] = from_r[k] ? (int64_t)s_a[j] * wr + w : (int64_t)s_b[j] * ws + (w - wr);
         }
-        int64_t b = start + (o - first);
-        b = (b >= 0 && b < ns) ? b : 0;
-        s_a[j] = (int32_t)a;
-        s_b[j] = (int32_t)b;
-    }
-    __syncthreads();
-    const int W = wr + ws;
-    const int total = cnt * W;
-    int64_t src[kSmjPer];
-    bool from_r[kSmjPer];
-#pragma unroll
-    for (int k = 0; k < kSmjPer; ++k) {
-        const int e = min((int)threadIdx.x + k * 256, total - 1);
-        const int j = (int)__umulhi((uint32_t)e, magic);
-        const int w = e - j * W;
-        from_r[k] = w < wr;
-        src[k] = from_r[k] ? (int64_t)s_a[j] * wr + w : (int64_t)s_b[j] * ws + (w - wr);
-    }
-    uint32_t v[kSmjPer];
-#pragma unroll
-    for (int k = 0; k < kSmjPer; ++k) v[k] = from_r[k] ? R[src[k]] : S[src[k]];
-    uint32_t *o = out + base * W;
-#pragma unroll
-    for (int k = 0; k < kSmjPer; ++k) {
-        const int e = threadIdx.x + k * 256;
-        if (e < total) __builtin_nontemporal_store(v[k], o + e);
+        uint32_t v[kSmjPer];
+    #pragma unroll
+        for (int k = 0; k < kSmjPer; ++k) v[k] = from_r[k] ? R[src[k]] : S[src[k]];
+        uint32_t *o = out + base * W;
+    #pragma unroll
+        for (int k = 0; k < kSmjPer; ++k) {
+            const int e = threadIdx.x + k * 256;
+            if (e < total) __builtin_nontemporal_store(v[k], o + e);
+        }
+        __syncthreads();  // the tile's LDS tables are reused by the next tile
     }
 }
 
@@ -239,14 +246,28 @@ size_t dpg_sort_merge_join_workspace_bytes(const dpg_ctx *ctx, int64_t n_r, int3
     return p.workspace;
 }
 
-dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
-                               const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
-                               void *out, int64_t out_capacity, int64_t *out_rows, void *workspace,
-                               size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream) {
+}  // extern "C"
+
+namespace dpg {
+
+// dst = *src (one int64 on the device).
+__global__ void k_smj_count_out(const unsigned long long *__restrict__ src, int64_t *__restrict__ dst) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = (int64_t)*src;
+}
+
+// The join; rows_dev null: the host learns the row count (one stream
+// synchronization) and rejects an output that is too small before writing any
+// row; rows_dev non-null: never synchronizes, the count goes to *rows_dev and
+// at most out_capacity rows are written.
+static dpg_status smj_run(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r, const void *s,
+                          int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes, void *out,
+                          int64_t out_capacity, int64_t *out_rows, int64_t *rows_dev, void *workspace,
+                          size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream) {
     SmjPlan p;
     dpg_status st = make_smj_plan(ctx, n_r, rec_r, key_off_r, n_s, rec_s, key_off_s, key_bytes, sort_copy_algo, &p);
     if (st != DPG_OK) return st;
-    if (!out_rows || out_capacity < 0) return DPG_ERR_INVALID_ARG;
+    if ((!out_rows && !rows_dev) || out_capacity < 0) return DPG_ERR_INVALID_ARG;
+    if (rows_dev && (((uintptr_t)rows_dev) % 8 || out_capacity >= INT32_MAX)) return DPG_ERR_INVALID_ARG;
     if ((n_r > 0 && (!r || ((uintptr_t)r) % 4)) || (n_s > 0 && (!s || ((uintptr_t)s) % 4))) return DPG_ERR_INVALID_ARG;
     if (out_capacity > 0 && (!out || ((uintptr_t)out) % 4)) return DPG_ERR_INVALID_ARG;
     if (workspace_bytes < p.workspace) return DPG_ERR_WORKSPACE_TOO_SMALL;
@@ -257,10 +278,20 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
         ranges_overlap(out, ob, workspace, p.workspace) || ranges_overlap(workspace, p.workspace, r, rb) ||
         ranges_overlap(workspace, p.workspace, s, sb))
         return DPG_ERR_INVALID_ARG;
+    if (rows_dev && (ranges_overlap(rows_dev, 8, out, ob) || ranges_overlap(rows_dev, 8, workspace, p.workspace)))
+        return DPG_ERR_INVALID_ARG;
     if (!ctx) return DPG_ERR_INVALID_ARG;
-    *out_rows = 0;
-    if (n_r == 0 || n_s == 0) return DPG_OK;
     char *w = (char *)workspace;
+    unsigned long long *total = (unsigned long long *)(w + p.off_total);
+    if (out_rows) *out_rows = 0;
+    if (n_r == 0 || n_s == 0) {
+        if (!rows_dev) return DPG_OK;
+        dpg_status st0 = launch_fill_i32(ctx, (int32_t *)total, 2, 0, stream);
+        if (st0 != DPG_OK) return st0;
+        hipLaunchKernelGGL(k_smj_count_out, dim3(1), dim3(64), 0, stream, total, rows_dev);
+        DPG_HIP(hipGetLastError());
+        return DPG_OK;
+    }
     // 1. sort both relations on the join key (Section 3, DPG copy phase); a
     //    key of at most 4 bytes comes out of the sort as sorted uint32 values
     const bool key32 = key_bytes <= 4;
@@ -290,7 +321,6 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
     }
     // 2. merge: key ranges and the number of result rows
     int32_t *lo = (int32_t *)(w + p.off_lo), *cnt = (int32_t *)(w + p.off_cnt);
-    unsigned long long *total = (unsigned long long *)(w + p.off_total);
     st = launch_fill_i32(ctx, (int32_t *)total, 2, 0, stream);
     if (st != DPG_OK) return st;
     {
@@ -306,12 +336,19 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
         DPG_HIP(hipGetLastError());
     }
     unsigned long long n_out = 0;
-    DPG_HIP(hipMemcpyAsync(&n_out, total, sizeof(n_out), hipMemcpyDeviceToHost, stream));
-    DPG_HIP(hipStreamSynchronize(stream));
-    *out_rows = (int64_t)n_out;
-    if ((int64_t)n_out > out_capacity) return DPG_ERR_WORKSPACE_TOO_SMALL;
-    if (n_out >= (unsigned long long)INT32_MAX) return DPG_ERR_UNSUPPORTED;
-    if (n_out == 0) return DPG_OK;
+    if (rows_dev) {
+        hipLaunchKernelGGL(k_smj_count_out, dim3(1), dim3(64), 0, stream, total, rows_dev);
+        DPG_HIP(hipGetLastError());
+        n_out = (unsigned long long)out_capacity;  // the emit reads the count on the device
+        if (n_out == 0) return DPG_OK;
+    } else {
+        DPG_HIP(hipMemcpyAsync(&n_out, total, sizeof(n_out), hipMemcpyDeviceToHost, stream));
+        DPG_HIP(hipStreamSynchronize(stream));
+        *out_rows = (int64_t)n_out;
+        if ((int64_t)n_out > out_capacity) return DPG_ERR_WORKSPACE_TOO_SMALL;
+        if (n_out >= (unsigned long long)INT32_MAX) return DPG_ERR_UNSUPPORTED;
+        if (n_out == 0) return DPG_OK;
+    }
     // 3. first result row of every R row, then the rows themselves
     st = launch_scan_1d(ctx, cnt, n_r, (int32_t *)(w + p.off_scan), (int32_t *)total, stream);
     if (st != DPG_OK) return st;
@@ -329,13 +366,36 @@ dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t
     if (tile >= step) tile = tile / step * step;
     if (tile < 1) return DPG_ERR_UNSUPPORTED;
     const uint32_t magic = (uint32_t)((0x100000000ull + (uint64_t)W - 1) / (uint64_t)W);
-    const int64_t grid = ((int64_t)n_out + tile - 1) / tile;
+    int64_t grid = ((int64_t)n_out + tile - 1) / tile;
+    if (rows_dev && grid > (int64_t)ctx->n_cu * 16) grid = (int64_t)ctx->n_cu * 16;  // tiles grid-stride
     ProfScope prof(ctx, K_SMJ_EMIT, (double)n_out * (2.0 * (rec_r + rec_s) + 8.0), stream);
     hipLaunchKernelGGL(k_smj_emit, dim3((unsigned)grid), dim3(256), 2 * (size_t)tile * sizeof(int32_t), stream,
                        (const uint32_t *)(w + p.off_r), wr, n_r, (const uint32_t *)(w + p.off_s), wsd, n_s, cnt, lo,
-                       (uint32_t *)out, (int64_t)n_out, tile, magic);
+                       (uint32_t *)out, (int64_t)n_out, tile, magic, rows_dev ? total : nullptr);
     DPG_HIP(hipGetLastError());
     return DPG_OK;
+}
+
+}  // namespace dpg
+
+extern "C" {
+
+dpg_status dpg_sort_merge_join(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                               const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                               void *out, int64_t out_capacity, int64_t *out_rows, void *workspace,
+                               size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream) {
+    if (!out_rows) return DPG_ERR_INVALID_ARG;
+    return smj_run(ctx, r, n_r, rec_r, key_off_r, s, n_s, rec_s, key_off_s, key_bytes, out, out_capacity, out_rows,
+                   nullptr, workspace, workspace_bytes, sort_copy_algo, stream);
+}
+
+dpg_status dpg_sort_merge_join_async(dpg_ctx *ctx, const void *r, int64_t n_r, int32_t rec_r, int32_t key_off_r,
+                                     const void *s, int64_t n_s, int32_t rec_s, int32_t key_off_s, int32_t key_bytes,
+                                     void *out, int64_t out_capacity, int64_t *out_rows_dev, void *workspace,
+                                     size_t workspace_bytes, dpg_algo sort_copy_algo, hipStream_t stream) {
+    if (!out_rows_dev) return DPG_ERR_INVALID_ARG;
+    return smj_run(ctx, r, n_r, rec_r, key_off_r, s, n_s, rec_s, key_off_s, key_bytes, out, out_capacity, nullptr,
+                   out_rows_dev, workspace, workspace_bytes, sort_copy_algo, stream);
 }
 
 }  // extern "C"

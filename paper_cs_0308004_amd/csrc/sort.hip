@@ -26,23 +26,38 @@ namespace dpg {
 template <typename K>
 __global__ __launch_bounds__(256) void k_sort_extract(const uint8_t *__restrict__ src, int rec_bytes, int64_t n,
                                                       const uint32_t *__restrict__ order, int koff, int nbytes,
-                                                      K *__restrict__ keys, uint32_t *__restrict__ idx) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= n) return;
-    const uint32_t r = order ? order[j] : (uint32_t)j;
-    const uint8_t *rec = src + (int64_t)r * rec_bytes;
+                                                      K *__restrict__ keys, uint32_t *__restrict__ idx,
+                                                      const int32_t *__restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int a = koff & ~3, s = koff - a;
-    const uint32_t *w = (const uint32_t *)(rec + a);
     const int need = (s + nbytes + 3) / 4;  // dwords overlapping the key bytes (1..3), all inside the record
-    const uint32_t d0 = w[0];
-    const uint32_t d1 = need > 1 ? w[1] : 0u;
-    const uint32_t d2 = need > 2 ? w[2] : 0u;
-    const uint64_t lo = (uint64_t)d0 | ((uint64_t)d1 << 32);
-    uint64_t x = s ? ((lo >> (8 * s)) | ((uint64_t)d2 << (64 - 8 * s))) : lo;  // little-endian key bytes
-    if (nbytes < 8) x &= (uint64_t(1) << (8 * nbytes)) - 1;
-    if constexpr (sizeof(K) == 8) keys[j] = __builtin_bswap64(x);
-    else keys[j] = __builtin_bswap32((uint32_t)x);
-    idx[j] = r;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
+        const uint32_t r = order ? order[j] : (uint32_t)j;
+        const uint32_t *w = (const uint32_t *)(src + (int64_t)r * rec_bytes + a);
+        const uint32_t d0 = w[0];
+        const uint32_t d1 = need > 1 ? w[1] : 0u;
+        const uint32_t d2 = need > 2 ? w[2] : 0u;
+        const uint64_t lo = (uint64_t)d0 | ((uint64_t)d1 << 32);
+        uint64_t x = s ? ((lo >> (8 * s)) | ((uint64_t)d2 << (64 - 8 * s))) : lo;  // little-endian key bytes
+        if (nbytes < 8) x &= (uint64_t(1) << (8 * nbytes)) - 1;
+        if constexpr (sizeof(K) == 8) keys[j] = __builtin_bswap64(x);
+        else keys[j] = __builtin_bswap32((uint32_t)x);
+        idx[j] = r;
+    }
+}
+
+// Grid of the extraction: a grid-stride loop over at most 64 workgroups per CU
+// (a gated-off launch then costs few empty workgroups).
+static unsigned extract_grid(const dpg_ctx *ctx, int64_t n) {
+    const int64_t want = (n + 255) / 256, cap = (int64_t)ctx->n_cu * 64;
+    return (unsigned)(want < cap ? (want > 0 ? want : 1) : cap);
+}
+
+// dst[j] = src[j] when *gate is non-zero.
+__global__ __launch_bounds__(256) void k_gated_copy(const uint32_t *__restrict__ src, uint32_t *__restrict__ dst,
+                                                    int64_t n, const int32_t *__restrict__ gate) {
+    if (*gate == 0) return;
+    for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) dst[j] = src[j];
 }
 
 constexpr int kMaxTieGroup = 64;
@@ -141,14 +156,14 @@ static dpg_status make_sort_plan(const dpg_ctx *ctx, int64_t n, int32_t rec_byte
 // order) into buffer `cur`, then LSD-sort it by its bytes; returns the buffer
 // holding the result.
 static dpg_status sort_chunk(dpg_ctx *ctx, const SortPlan &p, const void *src, char *w, int c,
-                             const uint32_t *order, int *cur, hipStream_t stream) {
+                             const uint32_t *order, int *cur, const int32_t *gate, hipStream_t stream) {
     const int nbytes = p.key_bytes - 8 * c < 8 ? p.key_bytes - 8 * c : 8;
     const int dst_buf = order && (const char *)order == w + p.off_idx[*cur] ? 1 - *cur : *cur;
     {
         ProfScope prof(ctx, K_SORT_EXTRACT, (double)p.n * (64.0 + 12.0 + (order ? 4.0 : 0.0)), stream);
-        hipLaunchKernelGGL(k_sort_extract<uint64_t>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_sort_extract<uint64_t>, dim3(extract_grid(ctx, p.n)), dim3(256), 0, stream,
                            (const uint8_t *)src, p.rec_bytes, p.n, order, p.key_offset + 8 * c, nbytes,
-                           (uint64_t *)(w + p.off_keys[dst_buf]), (uint32_t *)(w + p.off_idx[dst_buf]));
+                           (uint64_t *)(w + p.off_keys[dst_buf]), (uint32_t *)(w + p.off_idx[dst_buf]), gate);
         DPG_HIP(hipGetLastError());
     }
     *cur = dst_buf;
@@ -156,7 +171,8 @@ static dpg_status sort_chunk(dpg_ctx *ctx, const SortPlan &p, const void *src, c
         const int other = 1 - *cur;
         const dpg_status st = launch_partition(ctx, p.part64, w + p.off_keys[*cur], (const uint32_t *)(w + p.off_idx[*cur]),
                                                w + p.off_keys[other], (uint32_t *)(w + p.off_idx[other]), nullptr,
-                                               56 - 8 * byte, 0, w + p.off_part, stream, nullptr);
+                                               56 - 8 * byte, 0, w + p.off_part, stream, nullptr, nullptr, 0, true,
+                                               false, 1, nullptr, 0, nullptr, gate);
         if (st != DPG_OK) return st;
         *cur = other;
     }
@@ -170,9 +186,9 @@ static dpg_status sort_prefix(dpg_ctx *ctx, const SortPlan &p, const void *src, 
     const int nbytes = p.key_bytes < 4 ? p.key_bytes : 4;
     {
         ProfScope prof(ctx, K_SORT_EXTRACT, (double)p.n * (64.0 + 8.0), stream);
-        hipLaunchKernelGGL(k_sort_extract<uint32_t>, dim3((unsigned)((p.n + 255) / 256)), dim3(256), 0, stream,
+        hipLaunchKernelGGL(k_sort_extract<uint32_t>, dim3(extract_grid(ctx, p.n)), dim3(256), 0, stream,
                            (const uint8_t *)src, p.rec_bytes, p.n, nullptr, p.key_offset, nbytes,
-                           (uint32_t *)(w + p.off_keys[0]), (uint32_t *)(w + p.off_idx[0]));
+                           (uint32_t *)(w + p.off_keys[0]), (uint32_t *)(w + p.off_idx[0]), nullptr);
         DPG_HIP(hipGetLastError());
     }
     *cur = 0;
@@ -209,17 +225,23 @@ static dpg_status run_sort(dpg_ctx *ctx, const SortPlan &p, const void *src, voi
                                (const uint8_t *)src, p.rec_bytes, p.key_offset + 4, p.key_bytes - 4, flag);
             DPG_HIP(hipGetLastError());
         }
-        DPG_HIP(hipMemcpyAsync(ctx->host_flag, flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-        DPG_HIP(hipStreamSynchronize(stream));
-        if (*ctx->host_flag) {
-            // long runs of equal prefixes: full LSD over the key, last 8-byte chunk first
-            const int chunks = (p.key_bytes + 7) / 8;
-            cur = 0;
-            for (int c = chunks - 1; c >= 0; --c) {
-                const uint32_t *order = c == chunks - 1 ? nullptr : (const uint32_t *)(w + p.off_idx[cur]);
-                st = sort_chunk(ctx, p, src, w, c, order, &cur, stream);
-                if (st != DPG_OK) return st;
-            }
+        // Long runs of equal prefixes: full LSD over the key, last 8-byte
+        // chunk first.  The passes are always enqueued; the fix-up's flag
+        // gates them on the device (they return at once when it is 0), and
+        // a gated copy brings their result into the fix-up's buffer, so the
+        // call never waits on the host.
+        const int fixed = cur;
+        const int chunks = (p.key_bytes + 7) / 8;
+        int fb = 0;
+        for (int c = chunks - 1; c >= 0; --c) {
+            const uint32_t *order = c == chunks - 1 ? nullptr : (const uint32_t *)(w + p.off_idx[fb]);
+            st = sort_chunk(ctx, p, src, w, c, order, &fb, flag, stream);
+            if (st != DPG_OK) return st;
+        }
+        if (fb != fixed) {
+            hipLaunchKernelGGL(k_gated_copy, dim3(extract_grid(ctx, p.n)), dim3(256), 0, stream,
+                               (const uint32_t *)(w + p.off_idx[fb]), (uint32_t *)(w + p.off_idx[fixed]), p.n, flag);
+            DPG_HIP(hipGetLastError());
         }
     }
     const int32_t *sorted = (const int32_t *)(w + p.off_idx[cur]);

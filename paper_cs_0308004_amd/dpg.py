@@ -46,7 +46,7 @@ class Request(ctypes.Structure):
     """dpg_request: one retrieval or join of a batch."""
     _fields_ = [("kind", _I32), ("algo", _I32), ("src", _VP), ("n_src", _I64), ("rec_bytes", _I32),
                 ("fact_bytes", _I32), ("rids", _VP), ("fact", _VP), ("n", _I64), ("fk_offset", _I32),
-                ("order", _I32), ("dst", _VP)]
+                ("order", _I32), ("dst", _VP), ("workspace", _VP), ("workspace_bytes", _SZ)]
 
 
 def retrieve_request(src, rids, dst, algo: int = ALGO_AUTO) -> Request:
@@ -95,6 +95,8 @@ SIGNATURES = {
     "dpg_sort_merge_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32, _I32]),
     "dpg_sort_merge_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64,
                                    ctypes.POINTER(_I64), _VP, _SZ, _I32, _VP]),
+    "dpg_sort_merge_join_async": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _I32, _I32, _VP, _I64, _VP,
+                                         _VP, _SZ, _I32, _VP]),
     "dpg_hash_index_bytes": (_SZ, [_I64, _I32]),
     "dpg_hash_ov_off_offset": (_SZ, [_I32]),
     "dpg_hash_ov_offset": (_SZ, [_I32]),
@@ -104,7 +106,7 @@ SIGNATURES = {
     "dpg_hash_lookup": (_I32, [_VP, _VP, _I64, _I32, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
     "dpg_key_join_workspace_bytes": (_SZ, [_VP, _I64, _I32, _I32, _I64, _I32, _I32, _I32, _I32]),
     "dpg_key_join": (_I32, [_VP, _VP, _I64, _I32, _I32, _VP, _I64, _I32, _VP, _I32, _VP, _I32, _VP, _SZ, _I32,
-                            _VP]),
+                            _I32, _VP]),
     "dpg_btree_bytes": (_SZ, [_I64]),
     "dpg_btree_levels": (_I32, [_I64]),
     "dpg_btree_level_offset": (_SZ, [_I64, _I32]),
@@ -113,11 +115,13 @@ SIGNATURES = {
     "dpg_btree_build": (_I32, [_VP, _VP, _I64, _VP, _SZ, _VP, _SZ, _VP]),
     "dpg_btree_lookup_workspace_bytes": (_SZ, [_VP, _I64, _I64, _I32]),
     "dpg_btree_lookup": (_I32, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _SZ, _I32, _VP]),
+    "dpg_batch_request_workspace_bytes": (_SZ, [_VP, ctypes.POINTER(Request)]),
     "dpg_batch_workspace_bytes": (_SZ, [_VP, ctypes.POINTER(Request), _I32]),
     "dpg_batch_run": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP, _SZ, _VP]),
     "dpg_batch_graph_workspace_bytes": (_SZ, [_VP, _I32]),
     "dpg_batch_graph_create": (_I32, [_VP, _I32, _VP, _SZ, _VP, ctypes.POINTER(_VP)]),
     "dpg_batch_graph_launch": (_I32, [_VP, ctypes.POINTER(Request), _I32, _VP]),
+    "dpg_batch_graph_request_done": (_I32, [_VP, _I32]),
     "dpg_batch_graph_destroy": (None, [_VP]),
     "dpg_arena_create": (_I32, [ctypes.c_size_t, _SZ, _SZ, ctypes.POINTER(_VP)]),
     "dpg_arena_alloc": (_I32, [_VP, _SZ, ctypes.POINTER(ctypes.c_size_t)]),
@@ -368,6 +372,27 @@ class Context:
             return out[: n_out.value]
         raise DPGError(ERR_WORKSPACE_TOO_SMALL, "dpg_sort_merge_join")
 
+    def sort_merge_join_async(self, r, s, key_off_r: int, key_off_s: int, key_bytes: int, out, rows,
+                              algo: int = ALGO_AUTO, workspace=None, stream=None):
+        """The same join without a host synchronization: `out` is a
+        (capacity, rec_r + rec_s) uint8 device tensor, `rows` a one-element
+        int64 device tensor that receives the number of result rows (at most
+        `capacity` of them are written)."""
+        import torch
+
+        nr, ns = r.shape[0], s.shape[0]
+        rec_r, rec_s = _rec_bytes(r), _rec_bytes(s)
+        if workspace is None:
+            need = self.sort_merge_join_workspace_bytes(nr, rec_r, key_off_r, ns, rec_s, key_off_s, key_bytes, algo)
+            if need == 0:
+                raise DPGError(ERR_INVALID_ARG, "dpg_sort_merge_join_workspace_bytes")
+            workspace = torch.empty(need, dtype=torch.uint8, device=r.device)
+        _check(lib().dpg_sort_merge_join_async(self.handle, _addr(r), nr, rec_r, key_off_r, _addr(s), ns, rec_s,
+                                               key_off_s, key_bytes, _addr(out), out.shape[0], _addr(rows),
+                                               _addr(workspace), workspace.numel(), algo, _stream(stream)),
+               "dpg_sort_merge_join_async")
+        return workspace
+
     # ---- hash index and batch lookup (Section 4.2.3) --------------------
     def hash_build(self, keys, log2_slots: int, stream=None):
         """Build the hash index of a uint32 key tensor (rid = position); returns
@@ -409,7 +434,7 @@ class Context:
                                                   log2_slots, order, algo)
 
     def key_join(self, fact, dim, fk_offset: int, index, log2_slots: int, order: int = 0, out=None,
-                 algo: int = ALGO_AUTO, workspace=None, stream=None):
+                 algo: int = ALGO_AUTO, workspace=None, stream=None, check_fk: bool = True):
         """Join fact rows to the dimension row holding their fk as a key
         (index: the hash index of the dimension keys, rid = dimension row)."""
         import torch
@@ -425,7 +450,7 @@ class Context:
             workspace = torch.empty(need, dtype=torch.uint8, device=fact.device)
         _check(lib().dpg_key_join(self.handle, _addr(fact), nf, fb, fk_offset, _addr(dim), nd, db, _addr(index),
                                   log2_slots, _addr(out), order, _addr(workspace), workspace.numel(), algo,
-                                  _stream(stream)), "dpg_key_join")
+                                  int(check_fk), _stream(stream)), "dpg_key_join")
         return out
 
     # ---- enhanced B+ tree and batch lookup (Section 4.2.3) -------------
@@ -467,6 +492,10 @@ class Context:
     def batch_workspace_bytes(self, reqs) -> int:
         arr = (Request * len(reqs))(*reqs)
         return lib().dpg_batch_workspace_bytes(self.handle, arr, len(reqs))
+
+    def batch_request_workspace_bytes(self, req) -> int:
+        """Scratch of one request's steps inside a graph batch (0: direct work)."""
+        return lib().dpg_batch_request_workspace_bytes(self.handle, ctypes.byref(req))
 
     def batch_run(self, reqs, workspace=None, stream=None):
         import torch
@@ -532,6 +561,10 @@ class BatchGraph:
     def launch(self, reqs, stream):
         arr = (Request * len(reqs))(*reqs)
         _check(lib().dpg_batch_graph_launch(self.handle, arr, len(reqs), _stream(stream)), "dpg_batch_graph_launch")
+
+    def request_done(self, index: int) -> bool:
+        """Whether request `index` of the last launch has finished."""
+        return bool(lib().dpg_batch_graph_request_done(self.handle, index))
 
     def close(self):
         if self.handle:

@@ -150,6 +150,17 @@ def test_batch_validation_without_device():
     assert lib.dpg_batch_run(None, arr5, 1, WS, 1 << 30, None) == dpg.ERR_INVALID_ARG
     assert lib.dpg_batch_graph_workspace_bytes(None, 0) == 0
     assert lib.dpg_batch_graph_workspace_bytes(None, 16) > 0
+    # scratch of a request's steps in a graph batch: none for direct work; for
+    # DPG the run arrays, RID_RUN, inv (4 bytes per rid each) and INTERNAL
+    assert lib.dpg_batch_request_workspace_bytes(None, ctypes.byref(good)) == 0
+    q = dpg.Request.from_buffer_copy(good)
+    q.algo = dpg.ALGO_DPG
+    assert lib.dpg_batch_request_workspace_bytes(None, ctypes.byref(q)) >= 10 * (4 + 4 + 16)
+    q.n = 1 << 20
+    q.n_src = 1 << 20
+    assert lib.dpg_batch_request_workspace_bytes(None, ctypes.byref(q)) >= (1 << 20) * (8 + 16)
+    q.rec_bytes = 6
+    assert lib.dpg_batch_request_workspace_bytes(None, ctypes.byref(q)) == 0
 
 
 def test_plan_phase_forms():
@@ -294,7 +305,7 @@ def test_key_join_validation():
     assert lib.dpg_key_join_workspace_bytes(None, 5000, 16, 0, 300, 64, 9, 5, dpg.ALGO_DPG) == 0  # order
     IX, OUT = 0x50000000, 0x60000000
     call = lambda ix, out, ws, wsb: lib.dpg_key_join(None, SRC, 5000, 16, 0, DST, 300, 64, ix, 9, out,
-                                                      dpg.JOIN_FACT_ORDER, ws, wsb, dpg.ALGO_DPG, None)
+                                                      dpg.JOIN_FACT_ORDER, ws, wsb, dpg.ALGO_DPG, 1, None)
     assert call(IX, OUT, WS, need) == E.ERR_INVALID_ARG            # valid, but no context
     assert call(IX, OUT, WS, need - 1) == E.ERR_WORKSPACE_TOO_SMALL
     assert call(IX + 16, OUT, WS, need) == E.ERR_INVALID_ARG       # misaligned index

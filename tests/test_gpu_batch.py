@@ -94,27 +94,71 @@ def test_batch_rejects_invalid_request(ctx):
         assert bool((k[2] == 3).all())
 
 
+def with_scratch(ctx, reqs):
+    """Give every request the scratch its steps need in a graph batch (none
+    for direct work).  Returns the buffers (keep them alive)."""
+    bufs = []
+    for q in reqs:
+        need = ctx.batch_request_workspace_bytes(q)
+        assert (need > 0) == (q.algo == dpg.ALGO_DPG) or q.algo == dpg.ALGO_AUTO
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=DEV)
+        q.workspace, q.workspace_bytes = ws.data_ptr(), need
+        bufs.append(ws)
+    return bufs
+
+
 def test_graph_replays_match_eager(ctx):
+    """Replays of one captured persistent batch with new requests: direct and
+    DPG retrievals and fact-order joins, every replay against the oracle, with
+    the program's own eager work between replays.  Every request's completion
+    word is set once the stream has finished."""
     stream = torch.cuda.Stream()
     graph = dpg.BatchGraph(ctx, 256, stream)
-    for round_, (n_req, seed) in enumerate([(200, 11), (37, 12), (200, 11), (5, 13)]):
-        reqs, keep, expects = make_mix(n_req, seed, algos=(dpg.ALGO_DIRECT, dpg.ALGO_AUTO), orders=(0,))
+    for round_, (n_req, seed) in enumerate([(200, 11), (37, 12), (200, 11), (5, 13), (60, 15)]):
+        reqs, keep, expects = make_mix(n_req, seed, algos=(dpg.ALGO_DIRECT, dpg.ALGO_DPG, dpg.ALGO_AUTO), orders=(0,))
+        scratch = with_scratch(ctx, reqs)
         torch.cuda.synchronize()  # inputs were uploaded on the default stream
         with torch.cuda.stream(stream):
             graph.launch(reqs, stream)
         stream.synchronize()
-        for k, want in zip(keep, expects):
-            assert np.array_equal(k[2].cpu().numpy(), want), f"replay {round_}"
+        for i, (k, want) in enumerate(zip(keep, expects)):
+            assert np.array_equal(k[2].cpu().numpy(), want), f"replay {round_}, request {i}"
+            assert graph.request_done(i), f"replay {round_}, request {i}"
+        del scratch
         # eager work of the program's own between replays
         x = torch.randn(1 << 20, device=DEV)
         torch.cuda.synchronize()
         assert float(x.abs().sum()) > 0
-    # DPG-planned requests are not graph work
+    # a DPG request without scratch, and a dimension-order join, are refused
     reqs, keep, _ = make_mix(3, seed=14, algos=(dpg.ALGO_DPG,), kinds=("retrieve",))
+    with pytest.raises(dpg.DPGError) as e:
+        graph.launch(reqs, stream)
+    assert e.value.status == dpg.ERR_WORKSPACE_TOO_SMALL
+    reqs, keep, _ = make_mix(2, seed=16, algos=(dpg.ALGO_DIRECT,), kinds=("join",), orders=(1,))
     with pytest.raises(dpg.DPGError) as e:
         graph.launch(reqs, stream)
     assert e.value.status == dpg.ERR_UNSUPPORTED
     graph.close()
+
+
+@pytest.mark.parametrize("log2_run", [0, 2, 5])
+def test_batch_dpg_steps_many_runs(ctx, log2_run):
+    """DPG requests inside the persistent launch with forced short runs (up to
+    the 2048 runs one distribute step takes; longer runs beyond that), empty
+    and single-row requests among them: each output equals the oracle's."""
+    ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
+    try:
+        reqs, keep, expects = make_mix(40, seed=30 + log2_run, algos=(dpg.ALGO_DPG,), orders=(0,), max_log2=15)
+        extra, keep2, exp2 = make_mix(6, seed=40 + log2_run, algos=(dpg.ALGO_DPG,), kinds=("retrieve",), max_log2=1)
+        # an empty request between them
+        s_t, r_t, d_t = keep2[0]
+        empty = dpg.retrieve_request(s_t, r_t[:0], d_t[:0], dpg.ALGO_DPG)
+        ctx.batch_run(reqs + [empty] + extra)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(dpg.OPT_LOG2_RUN, 0)
+    for i, (k, want) in enumerate(zip(keep + keep2, expects + exp2)):
+        assert np.array_equal(k[2].cpu().numpy(), want), i
 
 
 def test_batch_large_mixed_sizes(ctx):

@@ -105,8 +105,10 @@ def test_sort_full_oracle(ctx, n):
 def test_sort_full_key_passes(ctx):
     """Keys whose first four bytes take only 1500 values: groups of equal
     prefixes hold about 1300 records, beyond the fix-up's limit of 64, so the
-    pairs are sorted over the whole 10-byte key instead.  2 * 10^6 records of
-    100 B against the oracle; the profile shows the full-key passes ran."""
+    pairs are sorted over the whole 10-byte key instead -- decided on the
+    device, without a host synchronization.  2 * 10^6 records of 100 B
+    against the oracle; the fix-up's flag (the first word of the workspace)
+    shows that the full-key passes ran, and that uniform keys skip them."""
     n, rec = 2_000_000, 100
     seed = synth.SEED_BASE + 92
     src_h = synth.record_bytes(n, rec, seed)
@@ -114,21 +116,17 @@ def test_sort_full_key_passes(ctx):
     src_h[:, 0:4] = pool[synth.uniform_at(1500, np.arange(n, dtype=np.uint64), seed, synth.STREAM_FK)]
     want_dst, want_perm = oracle.sort_records(src_h, 0, 10)
     src = torch.from_numpy(src_h).to(DEV)
+    uniform = torch.from_numpy(synth.record_bytes(n, rec, seed)).to(DEV)
     for algo in (dpg.ALGO_DPG, dpg.ALGO_DIRECT):
-        ctx.profile_enable(True)
-        ctx.profile_reset()
-        try:
-            dst, perm = ctx.sort_records(src, 0, 10, algo=algo)
-            prof = ctx.profile_collect()
-        finally:
-            ctx.profile_enable(False)
-            ctx.profile_reset()
-        # one extraction of the 4-byte prefixes, then one per 8-byte key chunk
-        assert prof["k_sort_extract"]["launches"] == 3
+        ws = torch.empty(ctx.sort_workspace_bytes(n, rec, 0, 10, algo), dtype=torch.uint8, device=DEV)
+        dst, perm = ctx.sort_records(src, 0, 10, algo=algo, workspace=ws)
+        assert int(ws[:4].view(torch.int32).item()) == 1
         assert np.array_equal(perm.cpu().numpy().astype(np.int64), want_perm), f"perm, algo {algo}"
         assert np.array_equal(dst.cpu().numpy(), want_dst), f"records, algo {algo}"
-        del dst, perm
-    del src
+        ctx.sort_records(uniform, 0, 10, algo=algo, workspace=ws)
+        assert int(ws[:4].view(torch.int32).item()) == 0
+        del dst, perm, ws
+    del src, uniform
     free_device()
 
 

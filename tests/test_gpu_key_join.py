@@ -70,3 +70,13 @@ def test_key_join_missing_key(ctx):
         with pytest.raises(dpg.DPGError) as e:
             ctx.key_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 0, index, 8, order)
         assert e.value.status == dpg.ERR_FK_OUT_OF_RANGE
+        # unchecked: no synchronization and no error; every row whose key
+        # exists is still the oracle's (fact order: all rows but row 777)
+        got = ctx.key_join(torch.from_numpy(fact).to(DEV), torch.from_numpy(dim).to(DEV), 0, index, 8, order,
+                           check_fk=False)
+        torch.cuda.synchronize()
+        if order == dpg.JOIN_FACT_ORDER:
+            good = np.ones(len(fact), dtype=bool)
+            good[777] = False
+            want = oracle.key_join(fact[good], dim, 0, 4, 0)
+            assert np.array_equal(got.cpu().numpy()[good], want)

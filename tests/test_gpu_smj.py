@@ -128,3 +128,59 @@ def test_smj_full_size(ctx):
             assert torch.equal(out[s0:s0 + want.shape[0]], want), key
         del out
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("case", [CASES[0], CASES[2], CASES[4], CASES[6], CASES[10]],
+                         ids=lambda c: f"r{c[0]}x{c[1]}-s{c[3]}x{c[4]}-k{c[6]}")
+def test_smj_async_matches_oracle_and_cuts_at_capacity(ctx, case):
+    """dpg_sort_merge_join_async: no host synchronization, the row count in
+    device memory; with room for every row the output equals the oracle's,
+    with room for half of them it holds the first half and the count is still
+    the full one."""
+    nr, rr, kr, ns, rs, ks, kb, nk = case
+    pool = key_pool(nk, kb)
+    r = relation(nr, rr, kr, kb, pool, seed=nr + 11)
+    s = relation(ns, rs, ks, kb, pool, seed=ns + 12)
+    want = oracle.sort_merge_join(r, s, kr, ks, kb)
+    rt, st = torch.from_numpy(r).to(DEV), torch.from_numpy(s).to(DEV)
+    for cap in (want.shape[0] + 5, want.shape[0] // 2):
+        out = torch.full((max(cap, 1), rr + rs), 7, dtype=torch.uint8, device=DEV)[:cap]
+        rows = torch.full((1,), -1, dtype=torch.int64, device=DEV)
+        ctx.sort_merge_join_async(rt, st, kr, ks, kb, out, rows, algo=dpg.ALGO_DPG)
+        torch.cuda.synchronize()
+        assert int(rows.item()) == want.shape[0]
+        k = min(cap, want.shape[0])
+        assert np.array_equal(out[:k].cpu().numpy(), want[:k])
+        assert bool((out[k:] == 7).all())
+
+
+def test_smj_async_in_a_captured_graph(ctx):
+    """The asynchronous join (both sorts, the merge, the emit) captured into a
+    HIP graph and replayed three times, with eager work between replays;
+    every replay against the oracle."""
+    nr, rr, kr, ns, rs, ks, kb, nk = CASES[0]
+    pool = key_pool(nk, kb)
+    r = relation(nr, rr, kr, kb, pool, seed=nr + 11)
+    s = relation(ns, rs, ks, kb, pool, seed=ns + 12)
+    want = oracle.sort_merge_join(r, s, kr, ks, kb)
+    rt, st = torch.from_numpy(r).to(DEV), torch.from_numpy(s).to(DEV)
+    out = torch.empty((want.shape[0] + 16, rr + rs), dtype=torch.uint8, device=DEV)
+    rows = torch.zeros(1, dtype=torch.int64, device=DEV)
+    need = ctx.sort_merge_join_workspace_bytes(nr, rr, kr, ns, rs, ks, kb, dpg.ALGO_DPG)
+    ws = torch.empty(need, dtype=torch.uint8, device=DEV)
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=stream):
+        ctx.sort_merge_join_async(rt, st, kr, ks, kb, out, rows, algo=dpg.ALGO_DPG, workspace=ws,
+                                  stream=torch.cuda.current_stream())
+    for rep in range(3):
+        out.fill_(0)
+        rows.fill_(-1)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert int(rows.item()) == want.shape[0], rep
+        assert np.array_equal(out[:want.shape[0]].cpu().numpy(), want), rep
+        x = torch.randn(1 << 16, device=DEV)
+        assert float(x.abs().sum()) > 0
