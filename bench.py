@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--autotune", type=int, default=1,
                     help="1: also run the autotuner over the DPG plans and report its pick")
     ap.add_argument("--only", default="",
-                    help="comma list of sections: retrieve,small,sort,join,smj,hash,btree,skew,serve (default all)")
+                    help="comma list of sections: retrieve,small,sweep,sort,join,smj,hash,btree,skew,serve (default all)")
     ap.add_argument("--serve-requests", type=int, default=4096)
     ap.add_argument("--join-zipf", default="0,0.8,1.2", help="Zipf exponents of the join section")
     ap.add_argument("--join-variants", default="move_dpg,move_direct,sort_dpg,sort_direct,keyed",
@@ -342,6 +342,49 @@ def copy_ceiling(ctx, torch):
             "what": "k_stream_copy of 4 GiB device to device (reads and writes 4 GiB); best launch shape"}
 
 
+def bench_sweep(args, ctx, dpg, synth, torch, np):
+    """The record-size and rid-pattern sweep at 2^26 records: R in {8, 16,
+    32, 64, 100, 128, 256} B, rids a permutation, uniform draws with repeats,
+    or shuffled 4 KB runs; the default DPG plan against the direct gather,
+    each timed over a few steps without per-kernel events (a spot check of
+    the output against src[rids] for each)."""
+    dev = "cuda:0"
+    n = 1 << args.log2n
+    steps = max(3, args.steps // 4)
+    res = {"workload": f"2^{args.log2n} source records and rids, R in {{8,16,32,64,100,128,256}} B, rids "
+                       "perm / uniform / blocked", "ms": {}}
+    for R in (8, 16, 32, 64, 100, 128, 256):
+        seed = synth.SEED_BASE + 50 + R
+        src = synth.record_bytes(n, R, seed, backend="torch", device=dev)
+        dst = torch.empty_like(src)
+        for pattern in ("perm", "uniform", "blocked"):
+            if pattern == "perm":
+                rids = synth.rids_permutation(n, seed, backend="torch", device=dev)
+            elif pattern == "uniform":
+                rids = synth.rids_uniform(n, n, seed, backend="torch", device=dev)
+            else:
+                rids = synth.rids_blocked(n, R, seed, backend="torch", device=dev)
+            plan = ctx.plan_retrieve(n, R, n, dpg.ALGO_DPG)
+            ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+            wsd = torch.empty(256, dtype=torch.uint8, device=dev)
+            t_dpg, _ = time_steps(lambda: ctx.retrieve(src, rids, dst=dst, algo=dpg.ALGO_DPG, workspace=ws),
+                                  steps, 2, torch)
+            pick = torch.arange(0, n, 65537, device=dev)
+            if not torch.equal(dst[pick], src[rids[pick].long()]):
+                raise SystemExit(f"bench: sweep R={R} {pattern}: DPG output differs from src[rids]")
+            t_dir, _ = time_steps(lambda: ctx.retrieve(src, rids, dst=dst, algo=dpg.ALGO_DIRECT, workspace=wsd),
+                                  steps, 2, torch)
+            form = {1: "three phases, cached gather", 2: "three phases, LDS gather", 3: "two phases"}.get(plan.gather)
+            res["ms"][f"{R}B_{pattern}"] = {"dpg": round(t_dpg, 4), "direct": round(t_dir, 4),
+                                            "dpg_over_direct": round(t_dir / t_dpg, 3), "dpg_form": form,
+                                            "runs": plan.n_runs}
+            log(f"bench: sweep {R} B {pattern}: dpg {t_dpg:.3f} ms, direct {t_dir:.3f} ms")
+            del rids, ws
+        del src, dst
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_small(args, ctx, dpg, synth, torch, np):
     """2^20 records of 100 B and a permutation of 2^20 rids (the paper's
     1M x 100 B workload): source and output fit the 256 MiB Infinity Cache,
@@ -415,9 +458,32 @@ def bench_sort(args, ctx, dpg, synth, torch, np):
     keys = [bytes(r) for r in k8]
     if keys != sorted(keys):
         raise SystemExit("bench: sort output not sorted")
+    host = src[: 1 << 20].cpu().numpy()  # the oracle's sample, uniform keys
+    # the same records with the first four key bytes drawn from 4096 values:
+    # groups of about 24,000 equal prefixes send the pairs through the
+    # full-key passes (the device raises the flag, the gated passes run)
+    pool = synth.record_bytes(4096, 4, seed, stream=synth.STREAM_MIX, backend="torch", device=dev)
+    pick = synth.uniform_at(4096, torch.arange(n, device=dev), seed, synth.STREAM_FK, backend="torch", device=dev)
+    src[:, 0:4] = pool[pick]
+    del pool, pick
+    ws = torch.empty(ctx.sort_workspace_bytes(n, R, 0, 10, dpg.ALGO_DPG), dtype=torch.uint8, device=dev)
+    ms, _, prof = time_and_profile(
+        ctx, lambda: ctx.sort_records(src, 0, 10, dst=dst, perm=perm, algo=dpg.ALGO_DPG, workspace=ws), steps, 1,
+        torch)
+    if int(ws[:4].view(torch.int32).item()) != 1:
+        raise SystemExit("bench: the tied-prefix sort did not take the full-key passes")
+    k8 = dst[::99991, 0:10].cpu().numpy()
+    keys = [bytes(r) for r in k8]
+    if keys != sorted(keys):
+        raise SystemExit("bench: tied-prefix sort output not sorted")
+    res["dpg_full_key_passes"] = {
+        "workload": "the same 10^8 records with key bytes 0-3 drawn from 4096 values (groups of ~24,000 equal "
+                    "prefixes: the full-key LSD passes run)",
+        "ms": round(ms, 3), "records_per_s": round(n / (ms * 1e-3), 1),
+        "kernels_ms_per_sort": {k: round(v["ms"] / steps, 4) for k, v in prof.items()}}
+    del ws
     import oracle
 
-    host = src[: 1 << 20].cpu().numpy()
     res["cpu_oracle"] = oracle_rate(lambda: oracle.sort_records(host, 0, 10), 1 << 20, "records/s",
                                     "the first 2^20 of the records")
     del src, dst, perm, host
@@ -833,8 +899,8 @@ def main():
 
     from paper_cs_0308004_amd import dpg, synth
 
-    only = set(s for s in args.only.split(",") if s) or {"retrieve", "small", "sort", "join", "smj", "hash", "btree",
-                                                          "skew", "serve"}
+    only = set(s for s in args.only.split(",") if s) or {"retrieve", "small", "sweep", "sort", "join", "smj", "hash",
+                                                          "btree", "skew", "serve"}
     counters = None
     if os.path.exists(args.counters):
         with open(args.counters) as f:
@@ -856,6 +922,8 @@ def main():
         out.update(r)
     if "small" in only:
         out["small_1m_x_100B"] = bench_small(args, ctx, dpg, synth, torch, np)
+    if "sweep" in only:
+        out["sweep_2p26"] = bench_sweep(args, ctx, dpg, synth, torch, np)
     if "sort" in only:
         out["sort"] = bench_sort(args, ctx, dpg, synth, torch, np)
     if "join" in only:

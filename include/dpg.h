@@ -416,9 +416,10 @@ dpg_status dpg_btree_lookup(dpg_ctx *ctx, const void *tree, int64_t n_keys, cons
 /* (retrieval, or fact-order join moving the dimension rows) is the chain of  */
 /* Section 2.1's phases -- run histogram, run boundaries, distribute, probe,  */
 /* gather -- each step starting once the step before it (same request) has   */
-/* finished.  Dimension-order joins (a stable sort of the keys) run their own */
-/* phase sequence in the same stream.  Every output equals that of the        */
-/* request run alone.                                                         */
+/* finished.  A dimension-order join (Section 4.2.1) is the chain of its     */
+/* stable 8-bit passes over the (fk, row) pairs, then the move of the fact    */
+/* rows into fk order (DPG chain or one copy) fused with the read of the      */
+/* dimension rows.  Every output equals that of the request run alone.        */
 /* ------------------------------------------------------------------------- */
 typedef enum { DPG_REQ_RETRIEVE = 0, DPG_REQ_FK_JOIN = 1 } dpg_request_kind;
 
@@ -435,8 +436,9 @@ typedef struct {
     int32_t fk_offset;     /* join: byte offset of the uint32 foreign key */
     int32_t order;         /* join: dpg_join_order */
     void *dst;             /* output rows (n x rec_bytes, or n x (fact_bytes + rec_bytes)) */
-    /* graph batches only (dpg_batch_graph_launch), for a request planned as
-     * DPG: device scratch of dpg_batch_request_workspace_bytes bytes or more,
+    /* graph batches only (dpg_batch_graph_launch), for a request whose steps
+     * need scratch (DPG work, dimension-order joins): device scratch of
+     * dpg_batch_request_workspace_bytes bytes or more,
      * 256-byte aligned; ignored by dpg_batch_run, which keeps every request's
      * scratch in the batch workspace */
     void *workspace;
@@ -445,8 +447,10 @@ typedef struct {
 
 /* Scratch the steps of one request need inside a graph batch
  * (dpg_request.workspace): its run histogram and boundaries, RID_RUN, inv and
- * INTERNAL when it is planned as DPG; 0 for direct work or an invalid
- * request. */
+ * INTERNAL when it is planned as DPG; for a dimension-order join the two
+ * (fk, i) buffers and the digit counts of the stable sort passes, plus the
+ * DPG arrays of the fact-row move when that is planned as DPG; 0 for direct
+ * work or an invalid request. */
 size_t dpg_batch_request_workspace_bytes(const dpg_ctx *ctx, const dpg_request *req);
 /* Workspace for dpg_batch_run (0 if a request is invalid). */
 size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n);
@@ -457,10 +461,10 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
 
 /* A captured graph of the persistent batch launch, bound to a workspace: each
  * dpg_batch_graph_launch uploads the new requests' steps and replays the
- * graph.  Graph batches carry direct and DPG work (a DPG request brings its
- * scratch in dpg_request.workspace, dpg_batch_request_workspace_bytes:
- * DPG_ERR_WORKSPACE_TOO_SMALL otherwise);
- * a dimension-order join returns DPG_ERR_UNSUPPORTED.  Capture needs a
+ * graph.  Graph batches carry every kind of request; one whose steps need
+ * scratch (DPG work, dimension-order joins) brings it in
+ * dpg_request.workspace, dpg_batch_request_workspace_bytes of it
+ * (DPG_ERR_WORKSPACE_TOO_SMALL otherwise).  Capture needs a
  * non-default stream.  Launches on one graph must not overlap: launch again
  * once the previous launch has finished. */
 typedef struct dpg_batch_graph dpg_batch_graph;

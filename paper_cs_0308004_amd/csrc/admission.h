@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <iterator>
 #include <map>
+#include <vector>
 
 namespace dpg {
 
@@ -121,6 +122,24 @@ inline AdmitResult admit_head(Arena &a, size_t capacity, size_t out_bytes, size_
     }
     r.kind = ADMIT_OK;
     return r;
+}
+
+// What a free stream slot launches from the admitted queue (flags: for each
+// admitted request in admission order, whether a persistent batch can carry
+// it).  An unbatched request at the head runs alone; otherwise the batched
+// requests of the queue, in order, up to max_batch, form one batch --
+// unbatched requests between them keep their place.  Returns the queue
+// positions taken (empty for an empty queue).
+inline std::vector<size_t> select_launch(const std::vector<bool> &batched, int max_batch) {
+    std::vector<size_t> take;
+    if (batched.empty()) return take;
+    if (!batched[0] || max_batch <= 1) {
+        take.push_back(0);
+        return take;
+    }
+    for (size_t i = 0; i < batched.size() && (int)take.size() < max_batch; ++i)
+        if (batched[i]) take.push_back(i);
+    return take;
 }
 
 }  // namespace dpg

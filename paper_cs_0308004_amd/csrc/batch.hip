@@ -13,6 +13,8 @@
 //   OP_SCAN     the run boundaries: exclusive scan of the histogram
 //   OP_SCATTER  a tile of rids placed into their runs (RID_RUN) with each
 //               rid's slot recorded (inv)
+//   OP_SHIST, OP_SSCAN, OP_SSCATTER
+//               one stable 8-bit pass of a dimension-order join's sort
 //
 // A request planned as direct retrieval is one OP_COPY step; a request
 // planned as DPG is the chain ZERO -> HIST -> SCAN -> SCATTER -> COPY (probe)
@@ -28,13 +30,16 @@
 // memory, so a host thread learns that the request is done while the batch
 // is still running.
 //
-// Dimension-order (DPG-Sort) joins need a stable sort of the foreign keys and
-// run their own phase sequence in the same stream (dpg_batch_run); graph
-// batches do not take them.
+// A dimension-order (DPG-Sort) join is the chain of its stable 8-bit passes
+// over the (fk, i) pairs (SHIST -> SSCAN -> SSCATTER per pass, low digit
+// first, as many passes as the dimension's key bits need), then the move of
+// the fact rows into fk order (the DPG chain over the sorted row numbers, or
+// one copy when direct pays) fused with the read of the dimension rows in fk
+// order: the final COPY writes fact[i_j] || dim[fk_j].
 //
-// The batch header (item count, step count, sequence number) lives in device
-// memory, so a captured graph of [reset queue and counters, k_batch] is
-// replayed with new requests: only the header and step upload changes
+// The batch header (item count, step count, sequence number, queue word) and
+// the steps (with their counters) live in device memory and are uploaded in
+// one copy, so a captured graph of k_batch is replayed with new requests
 // (dpg_batch_graph_*).
 #include <algorithm>
 #include <cstring>
@@ -46,7 +51,16 @@
 
 namespace dpg {
 
-enum BatchOp : int32_t { OP_COPY = 0, OP_ZERO = 1, OP_HIST = 2, OP_SCAN = 3, OP_SCATTER = 4 };
+enum BatchOp : int32_t {
+    OP_COPY = 0,
+    OP_ZERO = 1,
+    OP_HIST = 2,
+    OP_SCAN = 3,
+    OP_SCATTER = 4,
+    OP_SHIST = 5,     // stable sort pass: digit counts of a tile -> cnt[t][digit]
+    OP_SSCAN = 6,     // stable sort pass: column scan of cnt (run boundaries per tile)
+    OP_SSCATTER = 7   // stable sort pass: (key, val) of a tile to their places, input order kept per digit
+};
 
 struct BatchDesc {
     // OP_COPY: out row j = A[ia] || B[ib], ia = idx_a ? idx_a[j] : j,
@@ -76,6 +90,15 @@ struct BatchDesc {
     int32_t id_stride, id_word;
     int32_t lg_run, n_runs;
     int32_t *hist, *fill, *run_off, *run, *inv;
+    // stable sort passes: key of element i as for the distribute (ids), its
+    // value vals_in[i] (or i when null); digit (key >> shift) & 255; cnt the
+    // (tiles x 256) count matrix
+    const uint32_t *vals_in;
+    uint32_t *keys_out, *vals_out;
+    int32_t *cnt;
+    int32_t shift, n_tiles;
+    uint32_t done;          // items of this step finished (uploaded as 0)
+    uint32_t pad;
 };
 
 struct BatchHeader {
@@ -83,7 +106,7 @@ struct BatchHeader {
     int32_t n_desc;
     uint32_t seq;      // launch sequence number, written into the completion words
     int32_t timeout;   // set when a dependency wait gave up (never in a correct run)
-    int32_t pad;
+    uint32_t queue;    // next work item (uploaded as 0)
 };
 
 constexpr int kBatchThreads = 256;
@@ -93,6 +116,8 @@ constexpr int kBatchItemWords = 16384;   // ~64 KiB of output per work item
 constexpr int kBatchDistTile = 4096;     // rids per distribute item (16 per thread)
 constexpr int kBatchMaxRuns = 2048;      // runs of a request distributed inside the batch
 constexpr int kBatchSteps = 6;           // steps of a DPG request
+constexpr int kSortDigits = 256;         // 8-bit digits of the stable passes
+constexpr int kBatchMaxSteps = 3 * 4 + kBatchSteps;  // most steps of one request (a dimension-order join)
 constexpr uint64_t kBatchWaitTicks = 200000000ull;  // 2 s of the 100 MHz real-time counter
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -265,10 +290,115 @@ __device__ __forceinline__ void scatter_item(const BatchDesc &d, int64_t local, 
     }
 }
 
-__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict__ hdr,
-                                                         const BatchDesc *__restrict__ descs,
-                                                         uint32_t *__restrict__ queue,
-                                                         uint32_t *__restrict__ done,
+// Stable sort passes of the dimension-order join (the DPG-Sort join's sort
+// of (fk, i) pairs by fk, Section 4.2.1).  A tile is kBatchDistTile elements;
+// wave w holds the tile's elements [1024 w, 1024 (w + 1)), row k of it being
+// the 64 elements from 1024 w + 64 k, one per lane -- the order in which ranks
+// are given, so equal digits keep input order.
+__device__ __forceinline__ uint32_t sort_key(const BatchDesc &d, int64_t i) {
+    return as_global(d.ids)[i * d.id_stride + d.id_word];
+}
+
+__device__ __forceinline__ void shist_item(const BatchDesc &d, int64_t t, int32_t *s_h) {
+    constexpr int PER = kBatchDistTile / kBatchThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = threadIdx.x; j < (kBatchThreads / 64) * kSortDigits; j += kBatchThreads) s_h[j] = 0;
+    __syncthreads();
+    const int64_t i0 = t * kBatchDistTile + wave * 64 * PER + lane;
+#pragma unroll 4
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = i0 + k * 64;
+        if (i < d.n_rows) atomicAdd(&s_h[wave * kSortDigits + ((sort_key(d, i) >> d.shift) & 255)], 1);
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < kSortDigits; g += kBatchThreads) {
+        int32_t c = 0;
+#pragma unroll
+        for (int w = 0; w < kBatchThreads / 64; ++w) c += s_h[w * kSortDigits + g];
+        d.cnt[t * kSortDigits + g] = c;
+    }
+}
+
+// cnt[t][g] <- (elements of digits below g) + (elements of digit g in tiles before t)
+__device__ __forceinline__ void sscan_item(const BatchDesc &d, int32_t *s_w) {
+    static_assert(kBatchThreads == kSortDigits, "one thread per digit");
+    const int g = threadIdx.x, lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    auto *c = as_global(d.cnt);
+    const int T = d.n_tiles;
+    int32_t total = 0;
+    int t = 0;
+    for (; t + 8 <= T; t += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(t + u) * kSortDigits + g];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) total += v[u];
+    }
+    for (; t < T; ++t) total += c[(int64_t)t * kSortDigits + g];
+    int32_t inc = total;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    int32_t run = inc - total;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (t = 0; t < T; ++t) {
+        const int64_t at = (int64_t)t * kSortDigits + g;
+        const int32_t v = c[at];
+        c[at] = run;
+        run += v;
+    }
+}
+
+__device__ __forceinline__ void sscatter_item(const BatchDesc &d, int64_t t, int32_t *s_cnt) {
+    constexpr int PER = kBatchDistTile / kBatchThreads;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = threadIdx.x; j < (kBatchThreads / 64) * kSortDigits; j += kBatchThreads) s_cnt[j] = 0;
+    __syncthreads();
+    int32_t *mine = s_cnt + wave * kSortDigits;
+    const int64_t i0 = t * kBatchDistTile + wave * 64 * PER + lane;
+    uint32_t key[PER], val[PER];
+    int32_t rank[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = i0 + k * 64;
+        const bool valid = i < d.n_rows;
+        key[k] = valid ? sort_key(d, i) : 0u;
+        val[k] = valid ? (d.vals_in ? as_global(d.vals_in)[i] : (uint32_t)i) : 0u;
+        const uint32_t g = (key[k] >> d.shift) & 255u;
+        const uint64_t peers = match_lanes(g, 8, __ballot(valid));
+        const uint64_t below = peers & lanemask_lt();
+        const int32_t head = valid ? mine[g] : 0;
+        rank[k] = valid ? head + __popcll(below) : -1;
+        if (valid && below == 0) mine[g] = head + __popcll(peers);
+    }
+    __syncthreads();
+    // per digit: exclusive prefix over the waves
+    if (threadIdx.x < kSortDigits) {
+        int32_t run = 0;
+#pragma unroll
+        for (int w = 0; w < kBatchThreads / 64; ++w) {
+            const int32_t v = s_cnt[w * kSortDigits + threadIdx.x];
+            s_cnt[w * kSortDigits + threadIdx.x] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    const auto *c = as_global(d.cnt);
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        if (rank[k] < 0) continue;
+        const uint32_t g = (key[k] >> d.shift) & 255u;
+        const int64_t pos = (int64_t)c[t * kSortDigits + g] + mine[g] + rank[k];
+        d.keys_out[pos] = key[k];
+        d.vals_out[pos] = val[k];
+    }
+}
+
+__global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict__ hdr, BatchDesc *__restrict__ descs,
                                                          uint32_t *__restrict__ host_done) {
     __shared__ int64_t s_item;
     __shared__ int s_desc;
@@ -278,7 +408,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
     const uint32_t seq = hdr->seq;
     for (;;) {
         if (threadIdx.x == 0) {
-            const int64_t item = (int64_t)atomicAdd(queue, 1u);
+            const int64_t item = (int64_t)atomicAdd(&hdr->queue, 1u);
             s_item = item;
             int r = -1;
             if (item < total_items) {
@@ -295,7 +425,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
                 if (dep >= 0) {
                     const uint32_t need = (uint32_t)descs[dep].n_items;
                     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-                    while (__hip_atomic_load(&done[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    while (__hip_atomic_load(&descs[dep].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         __builtin_amdgcn_s_sleep(2);
                         if (__builtin_amdgcn_s_memrealtime() - t0 > kBatchWaitTicks) {
                             atomicOr(&hdr->timeout, 1);
@@ -321,12 +451,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
             case OP_HIST: hist_item(d, local, s_mem); break;
             case OP_SCAN: scan_item(d, s_mem); break;
             case OP_SCATTER: scatter_item(d, local, s_mem, s_mem + kBatchMaxRuns); break;
+            case OP_SHIST: shist_item(d, local, s_mem); break;
+            case OP_SSCAN: sscan_item(d, s_mem); break;
+            case OP_SSCATTER: sscatter_item(d, local, s_mem); break;
             default: break;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             __threadfence();  // release: this item's writes before its count
-            const uint32_t prev = atomicAdd(&done[r], 1u);
+            const uint32_t prev = atomicAdd(&descs[r].done, 1u);
             if (d.last && host_done && prev + 1 == (uint32_t)d.n_items) {
                 // the request is complete: publish to the host
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
@@ -341,12 +474,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
 // host side
 // ---------------------------------------------------------------------------
 struct BatchRequestPlan {
-    bool direct = false;    // one copy step in k_batch
-    bool dpg = false;       // the DPG step chain in k_batch
-    bool own = false;       // its own phase sequence outside k_batch (dimension-order joins)
+    bool direct = false;    // one copy step
+    bool dpg = false;       // retrieval or fact-order join: the DPG step chain
+    bool sortjoin = false;  // dimension-order join: stable passes over (fk, i), then the move of the fact rows
+    bool move_dpg = false;  // dimension-order join: the fact rows move by the DPG chain (else one copy step)
+    int passes = 0;         // dimension-order join: 8-bit stable passes over the foreign keys
     int64_t items = 0;      // copy items (direct)
-    size_t ws_bytes = 0;    // scratch: the DPG steps' arrays, or the own sequence's workspace
-    int lg_run = 0, n_runs = 0;  // DPG: run length and count
+    size_t ws_bytes = 0;    // scratch of the steps
+    int lg_run = 0, n_runs = 0;  // DPG chain: run length and count over the moved rows
+    int32_t steps = 0;      // steps in the queue
 };
 
 // With `arena` non-null the output is not placed yet: it will live somewhere in
@@ -428,52 +564,92 @@ static DpgScratch dpg_scratch(int64_t n, int n_runs, int moved_bytes) {
     return s;
 }
 
+// Scratch of a dimension-order join: two (key, value) buffers of the stable
+// passes, their count matrix, then the move's DPG scratch (if any).
+struct SortJoinScratch {
+    size_t off_keys[2] = {0, 0}, off_vals[2] = {0, 0}, off_cnt = 0, off_move = 0, bytes = 0;
+};
+
+static SortJoinScratch sortjoin_scratch(int64_t n, const BatchRequestPlan &p, int fact_bytes) {
+    SortJoinScratch s;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = off;
+        off = align_up(off + bytes);
+        return at;
+    };
+    const int64_t tiles = (n + kBatchDistTile - 1) / kBatchDistTile;
+    for (int b = 0; b < 2; ++b) {
+        s.off_keys[b] = take((size_t)n * 4);
+        s.off_vals[b] = take((size_t)n * 4);
+    }
+    s.off_cnt = take((size_t)tiles * kSortDigits * 4);
+    s.off_move = take(p.move_dpg ? dpg_scratch(n, p.n_runs, fact_bytes).bytes : 0);
+    s.bytes = off;
+    return s;
+}
+
+static void runs_for(const RetrievePlan &rp, int64_t n_src, BatchRequestPlan *bp) {
+    // the planner's run length, lengthened until the runs fit one distribute step
+    const int64_t N = n_src > 0 ? n_src : 1;
+    int lg = rp.log2_run;
+    while (((N + ((int64_t)1 << lg) - 1) >> lg) > kBatchMaxRuns) ++lg;
+    bp->lg_run = lg;
+    bp->n_runs = (int)((N + ((int64_t)1 << lg) - 1) >> lg);
+}
+
 static dpg_status plan_request(const dpg_ctx *ctx, const dpg_request &q, BatchRequestPlan *bp) {
     *bp = BatchRequestPlan();
     if (q.algo < DPG_ALGO_AUTO || q.algo > DPG_ALGO_DPG) return DPG_ERR_INVALID_ARG;
     const bool retrieve = q.kind == DPG_REQ_RETRIEVE;
-    size_t own_ws = 0;
-    if (!retrieve) {
-        own_ws = dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
-                                             (dpg_join_order)q.order, (dpg_algo)q.algo);
-        if (own_ws == 0) return DPG_ERR_INVALID_ARG;
-    }
+    if (!retrieve && dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
+                                                 (dpg_join_order)q.order, (dpg_algo)q.algo) == 0)
+        return DPG_ERR_INVALID_ARG;
+    const bool dim_order = !retrieve && q.order == DPG_JOIN_DIM_ORDER;
+    // the moved rows: retrieval source / dimension rows, or (dimension order) the fact rows
+    const int64_t mv_n = dim_order ? q.n : q.n_src;
+    const int mv_bytes = dim_order ? q.fact_bytes : q.rec_bytes;
     RetrievePlan rp;
-    const dpg_status st = make_retrieve_plan(ctx, q.n_src, q.rec_bytes, q.n, q.algo, &rp, retrieve);
+    const dpg_status st = make_retrieve_plan(ctx, mv_n, mv_bytes, q.n, q.algo, &rp, retrieve);
     if (st != DPG_OK) return st;
-    if (!retrieve && q.order == DPG_JOIN_DIM_ORDER) {
-        bp->own = true;
-        bp->ws_bytes = own_ws;
+    if (q.n == 0) {
+        bp->direct = true;
+        bp->steps = 1;
+        return DPG_OK;
+    }
+    if (dim_order) {
+        bp->sortjoin = true;
+        const int fk_bits = q.n_src > 1 ? bit_length((uint64_t)(q.n_src - 1)) : 1;
+        bp->passes = (fk_bits + 7) / 8;
+        bp->move_dpg = rp.algo == DPG_ALGO_DPG;
+        if (bp->move_dpg) runs_for(rp, mv_n, bp);
+        bp->ws_bytes = sortjoin_scratch(q.n, *bp, q.fact_bytes).bytes;
+        bp->steps = 3 * bp->passes + (bp->move_dpg ? kBatchSteps : 1);
         return DPG_OK;
     }
     if (rp.algo == DPG_ALGO_DIRECT) {
         bp->direct = true;
         const int tr = tile_rows_for((retrieve ? q.rec_bytes : q.fact_bytes + q.rec_bytes) / 4);
         bp->items = (q.n + tr - 1) / tr;
+        bp->steps = 1;
         return DPG_OK;
     }
-    // DPG inside the batch: the planner's run length, lengthened until the
-    // runs fit one distribute step
     bp->dpg = true;
-    const int64_t N = q.n_src > 0 ? q.n_src : 1;
-    int lg = rp.log2_run;
-    while (((N + ((int64_t)1 << lg) - 1) >> lg) > kBatchMaxRuns) ++lg;
-    bp->lg_run = lg;
-    bp->n_runs = (int)((N + ((int64_t)1 << lg) - 1) >> lg);
+    runs_for(rp, mv_n, bp);
     bp->ws_bytes = dpg_scratch(q.n, bp->n_runs, q.rec_bytes).bytes;
+    bp->steps = kBatchSteps;
     return DPG_OK;
 }
 
 struct BatchLayout {
-    size_t off_hdr = 0, off_queue = 0, off_done = 0, off_desc = 0;
+    size_t off_hdr = 0, off_desc = 0;
     int32_t n_desc_cap = 0;
     std::vector<size_t> req_off;  // per request: its DPG scratch or own-sequence workspace
     size_t total = 0;
 };
 
-// The header and the steps sit together, so one copy uploads both; the queue
-// word and the step counters sit together, so one fill kernel clears both
-// before k_batch runs.
+// The header and the steps sit together, so one copy uploads both, with the
+// queue word and every step's counter at zero: the launch is k_batch alone.
 static BatchLayout batch_layout(int32_t n_desc_cap, const std::vector<BatchRequestPlan> &plans) {
     BatchLayout L;
     size_t off = 0;
@@ -483,21 +659,18 @@ static BatchLayout batch_layout(int32_t n_desc_cap, const std::vector<BatchReque
         return at;
     };
     L.n_desc_cap = n_desc_cap > 0 ? n_desc_cap : 1;
-    L.off_hdr = take(sizeof(BatchHeader));
+    L.off_hdr = take(sizeof(BatchHeader) + (size_t)L.n_desc_cap * sizeof(BatchDesc));
     L.off_desc = L.off_hdr + sizeof(BatchHeader);
-    off = align_up(L.off_desc + (size_t)L.n_desc_cap * sizeof(BatchDesc));
-    L.off_queue = take(sizeof(uint32_t) * (1 + (size_t)L.n_desc_cap));
-    L.off_done = L.off_queue + sizeof(uint32_t);
     L.req_off.assign(plans.size(), 0);
     for (size_t i = 0; i < plans.size(); ++i)
-        if ((plans[i].dpg || plans[i].own) && plans[i].ws_bytes) L.req_off[i] = take(plans[i].ws_bytes);
+        if (plans[i].ws_bytes) L.req_off[i] = take(plans[i].ws_bytes);
     L.total = off;
     return L;
 }
 
 static int32_t steps_of(const std::vector<BatchRequestPlan> &plans) {
     int32_t n = 0;
-    for (const auto &p : plans) n += p.direct ? 1 : p.dpg ? kBatchSteps : 0;
+    for (const auto &p : plans) n += p.steps;
     return n;
 }
 
@@ -525,17 +698,64 @@ static void copy_shape(BatchDesc &d) {
     d.n_items = (d.n_rows + d.tile_rows - 1) / d.tile_rows;
 }
 
+// The DPG chain that moves rows `src` (n_src rows of mv_bytes) in the order of
+// the ids (element i's id: ids[i * id_stride + id_word]) into INTERNAL, and
+// the distribute arrays, in scratch w: ZERO, HIST, SCAN, SCATTER, then the
+// probe (Phase II).  *internal and *inv receive INTERNAL and the slots for the
+// gather step the caller adds.
+static void dpg_chain(const BatchDesc &base, const BatchRequestPlan &p, int64_t n, const uint32_t *ids,
+                      int id_stride, int id_word, const void *src, int64_t n_src, int mv_bytes, char *w,
+                      std::vector<BatchDesc> *chain, uint32_t **internal, const int32_t **inv) {
+    const DpgScratch sc = dpg_scratch(n, p.n_runs, mv_bytes);
+    BatchDesc dist = base;
+    dist.ids = ids;
+    dist.id_stride = id_stride;
+    dist.id_word = id_word;
+    dist.lim_a = n_src;
+    dist.n_rows = n;
+    dist.lg_run = p.lg_run;
+    dist.n_runs = p.n_runs;
+    dist.hist = (int32_t *)(w + sc.off_hist);
+    dist.fill = (int32_t *)(w + sc.off_fill);
+    dist.run_off = (int32_t *)(w + sc.off_run_off);
+    dist.run = (int32_t *)(w + sc.off_run);
+    dist.inv = (int32_t *)(w + sc.off_inv);
+    const int64_t dist_items = (n + kBatchDistTile - 1) / kBatchDistTile;
+    BatchDesc z = dist, h = dist, s = dist, x = dist;
+    z.op = OP_ZERO;
+    z.n_items = 1;
+    h.op = OP_HIST;
+    h.n_items = dist_items;
+    s.op = OP_SCAN;
+    s.n_items = 1;
+    x.op = OP_SCATTER;
+    x.n_items = dist_items;
+    *internal = (uint32_t *)(w + sc.off_internal);
+    // Phase II: INTERNAL[k] = src[run[k]]
+    BatchDesc pr = base;
+    pr.a = (const uint32_t *)src;
+    pr.idx_a = dist.run;
+    pr.lim_a = n_src;
+    pr.wa = mv_bytes / 4;
+    pr.out = *internal;
+    pr.n_rows = n;
+    copy_shape(pr);
+    *inv = dist.inv;
+    for (const BatchDesc &d : {z, h, s, x, pr}) chain->push_back(d);
+}
+
 // The steps of the batch, in queue order: every request's first step, then
-// every request's second step, ...; scratch[i] is request i's DPG scratch.
+// every request's second step, ...; scratch[i] is request i's scratch.
 static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans,
                         const std::vector<char *> &scratch, std::vector<BatchDesc> *descs, BatchHeader *hdr) {
     descs->clear();
     std::vector<std::vector<BatchDesc>> chains(n);
+    int max_steps = 0;
     for (int32_t i = 0; i < n; ++i) {
         const BatchRequestPlan &p = plans[i];
         const dpg_request &q = reqs[i];
-        if (!p.direct && !p.dpg) continue;
         const bool retrieve = q.kind == DPG_REQ_RETRIEVE;
+        std::vector<BatchDesc> &chain = chains[i];
         BatchDesc base{};
         base.request = i;
         base.dep = -1;
@@ -544,11 +764,8 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
             BatchDesc e = base;
             e.op = OP_ZERO;
             e.n_items = 1;
-            e.last = 1;
-            chains[i].push_back(e);
-            continue;
-        }
-        if (p.direct) {
+            chain.push_back(e);
+        } else if (p.direct) {
             BatchDesc d = base;
             if (retrieve) {
                 d.a = (const uint32_t *)q.src;
@@ -567,71 +784,100 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
             d.out = (uint32_t *)q.dst;
             d.n_rows = q.n;
             copy_shape(d);
-            d.last = 1;
-            chains[i].push_back(d);
-            continue;
-        }
-        const DpgScratch sc = dpg_scratch(q.n, p.n_runs, q.rec_bytes);
-        char *w = scratch[i];
-        BatchDesc dist = base;
-        dist.ids = retrieve ? (const uint32_t *)q.rids : (const uint32_t *)q.fact;
-        dist.id_stride = retrieve ? 1 : q.fact_bytes / 4;
-        dist.id_word = retrieve ? 0 : q.fk_offset / 4;
-        dist.lim_a = q.n_src;
-        dist.n_rows = q.n;
-        dist.lg_run = p.lg_run;
-        dist.n_runs = p.n_runs;
-        dist.hist = (int32_t *)(w + sc.off_hist);
-        dist.fill = (int32_t *)(w + sc.off_fill);
-        dist.run_off = (int32_t *)(w + sc.off_run_off);
-        dist.run = (int32_t *)(w + sc.off_run);
-        dist.inv = (int32_t *)(w + sc.off_inv);
-        const int64_t dist_items = (q.n + kBatchDistTile - 1) / kBatchDistTile;
-        BatchDesc z = dist, h = dist, s = dist, x = dist;
-        z.op = OP_ZERO;
-        z.n_items = 1;
-        h.op = OP_HIST;
-        h.n_items = dist_items;
-        s.op = OP_SCAN;
-        s.n_items = 1;
-        x.op = OP_SCATTER;
-        x.n_items = dist_items;
-        uint32_t *internal = (uint32_t *)(w + sc.off_internal);
-        // Phase II: INTERNAL[k] = src[run[k]]
-        BatchDesc pr = base;
-        pr.a = (const uint32_t *)q.src;
-        pr.idx_a = dist.run;
-        pr.lim_a = q.n_src;
-        pr.wa = q.rec_bytes / 4;
-        pr.out = internal;
-        pr.n_rows = q.n;
-        copy_shape(pr);
-        // Phase III: dst[i] = INTERNAL[inv[i]], or fact[i] || INTERNAL[inv[i]]
-        BatchDesc g = base;
-        if (retrieve) {
-            g.a = internal;
-            g.idx_a = dist.inv;
+            chain.push_back(d);
+        } else if (p.dpg) {
+            uint32_t *internal;
+            const int32_t *inv;
+            dpg_chain(base, p, q.n, retrieve ? (const uint32_t *)q.rids : (const uint32_t *)q.fact,
+                      retrieve ? 1 : q.fact_bytes / 4, retrieve ? 0 : q.fk_offset / 4, q.src, q.n_src, q.rec_bytes,
+                      scratch[i], &chain, &internal, &inv);
+            // Phase III: dst[i] = INTERNAL[inv[i]], or fact[i] || INTERNAL[inv[i]]
+            BatchDesc g = base;
+            if (retrieve) {
+                g.a = internal;
+                g.idx_a = inv;
+                g.lim_a = q.n;
+                g.wa = q.rec_bytes / 4;
+            } else {
+                g.a = (const uint32_t *)q.fact;
+                g.lim_a = q.n;
+                g.b = internal;
+                g.idx_b = inv;
+                g.lim_b = q.n;
+                g.wa = q.fact_bytes / 4;
+                g.wb = q.rec_bytes / 4;
+            }
+            g.out = (uint32_t *)q.dst;
+            g.n_rows = q.n;
+            copy_shape(g);
+            chain.push_back(g);
+        } else if (p.sortjoin) {
+            // (fk, i) pairs sorted by fk with stable 8-bit passes, low digit
+            // first; pass 0 reads the keys from the fact rows, its values are
+            // the row numbers
+            const SortJoinScratch sc = sortjoin_scratch(q.n, p, q.fact_bytes);
+            char *w = scratch[i];
+            const int64_t tiles = (q.n + kBatchDistTile - 1) / kBatchDistTile;
+            int cur = -1;
+            for (int pass = 0; pass < p.passes; ++pass) {
+                const int out = cur == 0 ? 1 : 0;
+                BatchDesc h = base;
+                h.ids = cur < 0 ? (const uint32_t *)q.fact : (const uint32_t *)(w + sc.off_keys[cur]);
+                h.id_stride = cur < 0 ? q.fact_bytes / 4 : 1;
+                h.id_word = cur < 0 ? q.fk_offset / 4 : 0;
+                h.vals_in = cur < 0 ? nullptr : (const uint32_t *)(w + sc.off_vals[cur]);
+                h.keys_out = (uint32_t *)(w + sc.off_keys[out]);
+                h.vals_out = (uint32_t *)(w + sc.off_vals[out]);
+                h.cnt = (int32_t *)(w + sc.off_cnt);
+                h.shift = 8 * pass;
+                h.n_rows = q.n;
+                h.n_tiles = (int32_t)tiles;
+                BatchDesc c = h, x = h;
+                h.op = OP_SHIST;
+                h.n_items = tiles;
+                c.op = OP_SSCAN;
+                c.n_items = 1;
+                x.op = OP_SSCATTER;
+                x.n_items = tiles;
+                chain.push_back(h);
+                chain.push_back(c);
+                chain.push_back(x);
+                cur = out;
+            }
+            const int32_t *fk_sorted = (const int32_t *)(w + sc.off_keys[cur]);
+            const int32_t *i_sorted = (const int32_t *)(w + sc.off_vals[cur]);
+            // out[j] = fact[i_j] || dim[fk_j]: the fact rows move by DPG (or
+            // directly), the dimension rows are read in fk order
+            BatchDesc g = base;
+            if (p.move_dpg) {
+                uint32_t *internal;
+                const int32_t *inv;
+                dpg_chain(base, p, q.n, (const uint32_t *)i_sorted, 1, 0, q.fact, q.n, q.fact_bytes,
+                          w + sc.off_move, &chain, &internal, &inv);
+                g.a = internal;
+                g.idx_a = inv;
+            } else {
+                g.a = (const uint32_t *)q.fact;
+                g.idx_a = i_sorted;
+            }
             g.lim_a = q.n;
-            g.wa = q.rec_bytes / 4;
-        } else {
-            g.a = (const uint32_t *)q.fact;
-            g.lim_a = q.n;
-            g.b = internal;
-            g.idx_b = dist.inv;
-            g.lim_b = q.n;
+            g.b = (const uint32_t *)q.src;
+            g.idx_b = fk_sorted;
+            g.lim_b = q.n_src;
             g.wa = q.fact_bytes / 4;
             g.wb = q.rec_bytes / 4;
+            g.out = (uint32_t *)q.dst;
+            g.n_rows = q.n;
+            copy_shape(g);
+            chain.push_back(g);
         }
-        g.out = (uint32_t *)q.dst;
-        g.n_rows = q.n;
-        copy_shape(g);
-        g.last = 1;
-        chains[i] = {z, h, s, x, pr, g};
+        if (!chain.empty()) chain.back().last = 1;
+        max_steps = std::max(max_steps, (int)chain.size());
     }
     // queue order: step k of every request, for k = 0, 1, ...
     std::vector<int32_t> prev_index(n, -1);
     int64_t items = 0;
-    for (int k = 0; k < kBatchSteps; ++k) {
+    for (int k = 0; k < max_steps; ++k) {
         for (int32_t i = 0; i < n; ++i) {
             if ((int)chains[i].size() <= k) continue;
             BatchDesc d = chains[i][k];
@@ -646,7 +892,7 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     hdr->n_desc = (int32_t)descs->size();
     hdr->seq = 0;
     hdr->timeout = 0;
-    hdr->pad = 0;
+    hdr->queue = 0;
 }
 
 static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans) {
@@ -660,6 +906,11 @@ static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<
         // DPG: distribute 16 per rid (rids read twice, run and inv written),
         // probe 4 + 2R, gather inv 4 + INTERNAL R + fact F read, row written
         else if (plans[i].dpg) b += M * (16.0 + 4.0 + 2.0 * R + 4.0 + R + F + row);
+        // dimension-order join: every pass reads and writes (fk, i) pairs
+        // (pass 0 reads fk from the fact rows), then the move of the fact
+        // rows and the assembly with the dimension rows in fk order
+        else if (plans[i].sortjoin)
+            b += M * (16.0 * plans[i].passes + (plans[i].move_dpg ? 24.0 + 4.0 * F : 4.0 + F) + 4.0 + R + row);
     }
     return b;
 }
@@ -668,29 +919,10 @@ static int batch_grid(const dpg_ctx *ctx) { return ctx->n_cu * 4; }
 
 static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &L, double bytes,
                                       uint32_t *host_done, hipStream_t stream) {
-    // queue word and every step counter back to zero
-    dpg_status st = launch_fill_i32(ctx, (int32_t *)(w + L.off_queue), 1 + (int64_t)L.n_desc_cap, 0, stream);
-    if (st != DPG_OK) return st;
     ProfScope prof(ctx, K_BATCH, bytes, stream);
     hipLaunchKernelGGL(k_batch, dim3((unsigned)batch_grid(ctx)), dim3(kBatchThreads), 0, stream,
-                       (BatchHeader *)(w + L.off_hdr), (const BatchDesc *)(w + L.off_desc),
-                       (uint32_t *)(w + L.off_queue), (uint32_t *)(w + L.off_done), host_done);
+                       (BatchHeader *)(w + L.off_hdr), (BatchDesc *)(w + L.off_desc), host_done);
     DPG_HIP(hipGetLastError());
-    return DPG_OK;
-}
-
-// The phase sequences of requests not handled by k_batch.
-static dpg_status run_own_sequences(dpg_ctx *ctx, const dpg_request *reqs, int32_t n,
-                                    const std::vector<BatchRequestPlan> &plans, char *w, const BatchLayout &L,
-                                    hipStream_t stream) {
-    for (int32_t i = 0; i < n; ++i) {
-        if (!plans[i].own) continue;
-        const dpg_request &q = reqs[i];
-        const dpg_status st = dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes,
-                                          q.dst, (dpg_join_order)q.order, w + L.req_off[i], plans[i].ws_bytes,
-                                          (dpg_algo)q.algo, 0, stream);
-        if (st != DPG_OK) return st;
-    }
     return DPG_OK;
 }
 
@@ -701,8 +933,8 @@ dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const vo
     BatchRequestPlan bp;
     st = plan_request(ctx, q, &bp);
     if (st != DPG_OK) return st;
-    *batchable = bp.direct || bp.dpg;
-    *batch_ws = bp.dpg ? bp.ws_bytes : 0;
+    *batchable = true;
+    *batch_ws = bp.ws_bytes;
     *own_ws = q.kind == DPG_REQ_RETRIEVE
                   ? dpg_retrieve_workspace_bytes(ctx, q.n_src, q.rec_bytes, q.n, (dpg_algo)q.algo)
                   : dpg_fk_join_workspace_bytes(ctx, q.n, q.fact_bytes, q.fk_offset, q.n_src, q.rec_bytes,
@@ -739,7 +971,7 @@ extern "C" {
 size_t dpg_batch_request_workspace_bytes(const dpg_ctx *ctx, const dpg_request *req) {
     BatchRequestPlan bp;
     if (!req || validate_request(*req) != DPG_OK || plan_request(ctx, *req, &bp) != DPG_OK) return 0;
-    return bp.dpg ? bp.ws_bytes : 0;
+    return bp.ws_bytes;
 }
 
 size_t dpg_batch_workspace_bytes(const dpg_ctx *ctx, const dpg_request *reqs, int32_t n) {
@@ -776,22 +1008,22 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
         st = launch_batch_kernel(ctx, w, L, batch_bytes(reqs, n, plans), nullptr, stream);
         if (st != DPG_OK) return st;
     }
-    return run_own_sequences(ctx, reqs, n, plans, w, L, stream);
+    return DPG_OK;
 }
 
 size_t dpg_batch_graph_workspace_bytes(const dpg_ctx *ctx, int32_t max_requests) {
     (void)ctx;
-    if (max_requests < 1 || max_requests > (INT32_MAX / kBatchSteps)) return 0;
+    if (max_requests < 1 || max_requests > (INT32_MAX / kBatchMaxSteps)) return 0;
     std::vector<BatchRequestPlan> none;
-    return batch_layout(max_requests * kBatchSteps, none).total;
+    return batch_layout(max_requests * kBatchMaxSteps, none).total;
 }
 
 dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *workspace, size_t workspace_bytes,
                                   hipStream_t stream, dpg_batch_graph **out) {
-    if (!ctx || !out || max_requests < 1 || max_requests > (INT32_MAX / kBatchSteps)) return DPG_ERR_INVALID_ARG;
+    if (!ctx || !out || max_requests < 1 || max_requests > (INT32_MAX / kBatchMaxSteps)) return DPG_ERR_INVALID_ARG;
     *out = nullptr;
     std::vector<BatchRequestPlan> none;
-    const BatchLayout L = batch_layout(max_requests * kBatchSteps, none);
+    const BatchLayout L = batch_layout(max_requests * kBatchMaxSteps, none);
     if (workspace_bytes < L.total) return DPG_ERR_WORKSPACE_TOO_SMALL;
     if (!workspace || ((uintptr_t)workspace) % kAlign) return DPG_ERR_INVALID_ARG;
     dpg_batch_graph *g = new dpg_batch_graph();
@@ -808,7 +1040,8 @@ dpg_status dpg_batch_graph_create(dpg_ctx *ctx, int32_t max_requests, void *work
         return DPG_ERR_HIP;
     }
     std::memset(g->host_done, 0, (size_t)max_requests * sizeof(uint32_t));
-    // capture [reset queue and counters, k_batch]; profiling events are not captured
+    // capture k_batch (the upload before each replay resets the queue and
+    // the counters); profiling events are not captured
     const bool prof = ctx->profiling;
     ctx->profiling = false;
     dpg_status st = DPG_OK;
@@ -849,11 +1082,11 @@ dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32
     std::vector<BatchRequestPlan> plans;
     dpg_status st = plan_batch(g->ctx, reqs, n, &plans);
     if (st != DPG_OK) return st;
-    // DPG steps take their scratch from each request's own workspace
+    if (steps_of(plans) > g->layout.n_desc_cap) return DPG_ERR_INVALID_ARG;  // not reached: at most kBatchMaxSteps each
+    // DPG and sort steps take their scratch from each request's own workspace
     std::vector<char *> scratch(n, nullptr);
     for (int32_t i = 0; i < n; ++i) {
-        if (plans[i].own) return DPG_ERR_UNSUPPORTED;  // dimension-order joins are not graph work
-        if (!plans[i].dpg || reqs[i].n == 0) continue;
+        if (plans[i].ws_bytes == 0) continue;
         if (reqs[i].workspace_bytes < plans[i].ws_bytes) return DPG_ERR_WORKSPACE_TOO_SMALL;
         if (!reqs[i].workspace || ((uintptr_t)reqs[i].workspace) % kAlign) return DPG_ERR_INVALID_ARG;
         scratch[i] = (char *)reqs[i].workspace;

@@ -83,6 +83,13 @@ struct Slot {
     size_t batch_ws_off = 0, batch_ws_bytes = 0;  // descriptors of a batch of direct work
 };
 
+// Batches of fewer requests launch the batch kernel directly even with
+// use_graph.
+constexpr int32_t kGraphMinRequests = 16;
+// With this many slots busy, a partial batch waits for a slot to finish
+// (the device is fed meanwhile), so that requests gather into larger batches.
+constexpr int kHoldBusySlots = 2;
+
 static size_t output_bytes(const dpg_request &q) {
     const int64_t row = q.kind == DPG_REQ_RETRIEVE ? q.rec_bytes : (int64_t)q.fact_bytes + q.rec_bytes;
     return (size_t)(q.n > 0 ? q.n : 0) * (size_t)(row > 0 ? row : 0);
@@ -202,7 +209,11 @@ static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> 
             reqs.push_back(q);
         }
         const int32_t n = (int32_t)reqs.size();
-        st = batch_graph_launch(sl.graph, reqs.data(), n, sl.stream, s->cfg.use_graph != 0);
+        // a graph replay costs more host time than launching the kernel
+        // (about 16 us more per launch here): it is used for batches that
+        // amortize it
+        st = batch_graph_launch(sl.graph, reqs.data(), n, sl.stream,
+                                s->cfg.use_graph != 0 && n >= kGraphMinRequests);
     }
     if (st != DPG_OK) return st;
     if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
@@ -268,20 +279,27 @@ static void scheduler(dpg_server *s) {
         //    unbatched tickets between them keep their place and take the
         //    next free slot once they reach the head
         bool window_wait = false;
+        int busy = 0;
+        for (Slot &sl : s->slots) busy += sl.busy ? 1 : 0;
         for (Slot &sl : s->slots) {
             if (sl.busy || s->admitted.empty()) continue;
             std::vector<uint64_t> batch;
             const bool batched = s->tickets[s->admitted.front()].batched;
-            if (!batched) {
-                batch.push_back(s->admitted.front());
-                s->admitted.pop_front();
-            } else {
+            if (batched && s->cfg.max_batch_requests > 1 && busy >= kHoldBusySlots && !s->stop) {
                 size_t avail = 0;
-                for (uint64_t t : s->admitted) {
-                    if ((int32_t)avail >= s->cfg.max_batch_requests) break;
-                    avail += s->tickets[t].batched ? 1 : 0;
-                }
-                if (s->cfg.batch_window_us > 0 && !s->stop && (int32_t)avail < s->cfg.max_batch_requests) {
+                for (size_t k = 0; k < s->admitted.size() && (int32_t)avail < s->cfg.max_batch_requests &&
+                                   k < (size_t)4 * (size_t)s->cfg.max_batch_requests;
+                     ++k)
+                    avail += s->tickets[s->admitted[k]].batched ? 1 : 0;
+                if ((int32_t)avail < s->cfg.max_batch_requests) break;  // the batch fills while the device works
+            }
+            if (batched && s->cfg.batch_window_us > 0 && !s->stop) {
+                size_t avail = 0;
+                for (size_t k = 0; k < s->admitted.size() && (int32_t)avail < s->cfg.max_batch_requests &&
+                                   k < (size_t)4 * (size_t)s->cfg.max_batch_requests;
+                     ++k)
+                    avail += s->tickets[s->admitted[k]].batched ? 1 : 0;
+                if ((int32_t)avail < s->cfg.max_batch_requests) {
                     // a partial batch waits (up to the window) for more requests
                     const double waited = std::chrono::duration<double, std::micro>(
                                               Clock::now() - s->tickets[s->admitted.front()].admit)
@@ -291,17 +309,17 @@ static void scheduler(dpg_server *s) {
                         break;
                     }
                 }
-                for (auto it = s->admitted.begin();
-                     it != s->admitted.end() && (int32_t)batch.size() < s->cfg.max_batch_requests;) {
-                    if (s->tickets[*it].batched) {
-                        batch.push_back(*it);
-                        it = s->admitted.erase(it);
-                    } else {
-                        ++it;
-                    }
-                }
             }
+            // the head of the queue decides (a bounded look-ahead keeps a
+            // launch's host cost independent of the queue's length)
+            const size_t look = std::min(s->admitted.size(), (size_t)4 * (size_t)s->cfg.max_batch_requests);
+            std::vector<bool> flags(look);
+            for (size_t k = 0; k < look; ++k) flags[k] = s->tickets[s->admitted[k]].batched;
+            const std::vector<size_t> take = select_launch(flags, s->cfg.max_batch_requests);
+            for (size_t k : take) batch.push_back(s->admitted[k]);
+            for (size_t k = take.size(); k-- > 0;) s->admitted.erase(s->admitted.begin() + (std::ptrdiff_t)take[k]);
             const auto t_launch = Clock::now();
+            ++busy;
             const dpg_status st = launch_on_slot(s, sl, batch);
             s->launch_s += std::chrono::duration<double>(Clock::now() - t_launch).count();
             if (st != DPG_OK) {

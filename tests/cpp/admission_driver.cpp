@@ -82,5 +82,19 @@ int main() {
         AdmitResult r = admit_head(a, a.size(), 1000, 0, false);
         check(r.kind == ADMIT_OK && r.out_off == got[1].out_off, "fifth takes the freed block");
     }
+    {
+        // launch selection: the head decides; batched requests are taken in
+        // order past unbatched ones, up to the batch limit
+        using V = std::vector<bool>;
+        check(select_launch(V{}, 8).empty(), "empty queue: nothing to launch");
+        std::vector<size_t> t = select_launch(V{false, true, true}, 8);
+        check(t.size() == 1 && t[0] == 0, "unbatched head runs alone");
+        t = select_launch(V{true, false, true, true, false, true}, 8);
+        check(t == std::vector<size_t>({0, 2, 3, 5}), "batched requests taken past unbatched ones");
+        t = select_launch(V{true, true, true, true, true}, 3);
+        check(t == std::vector<size_t>({0, 1, 2}), "batch limit");
+        t = select_launch(V{true, true, true}, 1);
+        check(t.size() == 1 && t[0] == 0, "per-request mode takes the head only");
+    }
     return failures ? 1 : 0;
 }

@@ -100,7 +100,8 @@ def with_scratch(ctx, reqs):
     bufs = []
     for q in reqs:
         need = ctx.batch_request_workspace_bytes(q)
-        assert (need > 0) == (q.algo == dpg.ALGO_DPG) or q.algo == dpg.ALGO_AUTO
+        sorts = q.kind == dpg.REQ_FK_JOIN and q.order == 1 and q.n > 0
+        assert (need > 0) == (q.algo == dpg.ALGO_DPG or sorts) or q.algo == dpg.ALGO_AUTO or q.n == 0
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=DEV)
         q.workspace, q.workspace_bytes = ws.data_ptr(), need
         bufs.append(ws)
@@ -109,13 +110,13 @@ def with_scratch(ctx, reqs):
 
 def test_graph_replays_match_eager(ctx):
     """Replays of one captured persistent batch with new requests: direct and
-    DPG retrievals and fact-order joins, every replay against the oracle, with
-    the program's own eager work between replays.  Every request's completion
-    word is set once the stream has finished."""
+    DPG retrievals, fact-order and dimension-order joins, every replay against
+    the oracle, with the program's own eager work between replays.  Every
+    request's completion word is set once the stream has finished."""
     stream = torch.cuda.Stream()
     graph = dpg.BatchGraph(ctx, 256, stream)
     for round_, (n_req, seed) in enumerate([(200, 11), (37, 12), (200, 11), (5, 13), (60, 15)]):
-        reqs, keep, expects = make_mix(n_req, seed, algos=(dpg.ALGO_DIRECT, dpg.ALGO_DPG, dpg.ALGO_AUTO), orders=(0,))
+        reqs, keep, expects = make_mix(n_req, seed, algos=(dpg.ALGO_DIRECT, dpg.ALGO_DPG, dpg.ALGO_AUTO))
         scratch = with_scratch(ctx, reqs)
         torch.cuda.synchronize()  # inputs were uploaded on the default stream
         with torch.cuda.stream(stream):
@@ -129,7 +130,7 @@ def test_graph_replays_match_eager(ctx):
         x = torch.randn(1 << 20, device=DEV)
         torch.cuda.synchronize()
         assert float(x.abs().sum()) > 0
-    # a DPG request without scratch, and a dimension-order join, are refused
+    # a DPG request, or a dimension-order join, without scratch is refused
     reqs, keep, _ = make_mix(3, seed=14, algos=(dpg.ALGO_DPG,), kinds=("retrieve",))
     with pytest.raises(dpg.DPGError) as e:
         graph.launch(reqs, stream)
@@ -137,8 +138,33 @@ def test_graph_replays_match_eager(ctx):
     reqs, keep, _ = make_mix(2, seed=16, algos=(dpg.ALGO_DIRECT,), kinds=("join",), orders=(1,))
     with pytest.raises(dpg.DPGError) as e:
         graph.launch(reqs, stream)
-    assert e.value.status == dpg.ERR_UNSUPPORTED
+    assert e.value.status == dpg.ERR_WORKSPACE_TOO_SMALL
     graph.close()
+
+
+@pytest.mark.parametrize("n_dim_log2", [0, 8, 9, 17, 25])
+def test_batch_dim_order_passes(ctx, n_dim_log2):
+    """Dimension-order joins inside the persistent launch with 1 to 4 stable
+    passes (dimension tables of 1, 2^8, 2^9, 2^17 and 2^25 rows), uniform and
+    heavily repeated keys, DPG and direct moves of the fact rows: each output
+    equals the oracle's (foreign-key order, ties in fact order)."""
+    n_dim = 1 << n_dim_log2
+    reqs, keep, expects = [], [], []
+    dim = synth.dim_table(n_dim, seed=n_dim_log2, dim_bytes=64 if n_dim_log2 < 20 else 16)
+    d_t = torch.from_numpy(dim).to(DEV)
+    for k, (n, skew, algo) in enumerate([(1, 0.0, dpg.ALGO_DPG), (5000, 0.0, dpg.ALGO_DIRECT),
+                                         (70000, 1.2, dpg.ALGO_DPG), (200003, 0.0, dpg.ALGO_DPG),
+                                         (4096, 2.0, dpg.ALGO_AUTO)]):
+        fact = synth.fact_table(n, n_dim, skew, seed=100 * n_dim_log2 + k)
+        expects.append(oracle.fk_join_dim_order(fact, dim, 0))
+        f_t = torch.from_numpy(fact).to(DEV)
+        dst = torch.empty((n, fact.shape[1] + dim.shape[1]), dtype=torch.uint8, device=DEV)
+        reqs.append(dpg.join_request(f_t, d_t, dst, 0, 1, algo))
+        keep.append((f_t, d_t, dst))
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    for i, (k, want) in enumerate(zip(keep, expects)):
+        assert np.array_equal(k[2].cpu().numpy(), want), i
 
 
 @pytest.mark.parametrize("log2_run", [0, 2, 5])

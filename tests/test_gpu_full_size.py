@@ -219,3 +219,37 @@ def test_join_dim_order_2p28_full_oracle(ctx, join_tables):
                    * len(outs))
     del outs
     free_device()
+
+
+# ---------------------------------------------------------------------------
+# The record-size and rid-pattern sweep at its full size (2^26 records)
+# ---------------------------------------------------------------------------
+SWEEP = [(r, "perm") for r in (4, 8, 16, 32, 64, 128, 256)] + \
+        [(r, p) for r in (16, 100, 256) for p in ("uniform", "blocked")]
+
+
+@pytest.mark.parametrize("rec,pattern", SWEEP, ids=[f"{r}B-{p}" for r, p in SWEEP])
+def test_retrieve_2p26_sweep_full_oracle(ctx, rec, pattern):
+    """2^26 source records of R bytes, 2^26 rids (a permutation, uniform draws
+    with repeats, or shuffled 4 KB runs), the default DPG plan for that shape:
+    every output byte against the oracle, in chunks of 2^22 rids."""
+    n = 1 << 26
+    seed = synth.SEED_BASE + 5 + rec
+    src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
+    if pattern == "perm":
+        rids = synth.rids_permutation(n, seed, backend="torch", device=DEV)
+    elif pattern == "uniform":
+        rids = synth.rids_uniform(n, n, seed, backend="torch", device=DEV)
+    else:
+        rids = synth.rids_blocked(n, rec, seed, backend="torch", device=DEV)
+    out = ctx.retrieve(src, rids, algo=dpg.ALGO_DPG)
+    rids_h = rids.cpu().numpy()
+    src_h = src.cpu().numpy()
+    del src
+    step = 1 << 22
+    chunks = [(a, min(n, a + step)) for a in range(0, n, step)]
+    compare_chunks(f"retrieve 2^26 x {rec} B {pattern}", chunks,
+                   fetch=lambda c: out[c[0]:c[1]].cpu().numpy(),
+                   expect=lambda c: oracle.retrieve(src_h, rids_h[c[0]:c[1]]))
+    del rids, out
+    free_device()

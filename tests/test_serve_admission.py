@@ -1,7 +1,8 @@
 """The serving engine's host-only admission rule and arena (csrc/admission.h),
 built with the host compiler into a small driver and run on the CPU: capacity
 less the slot workspaces, rounding, waiting under fragmentation, failing when
-the server stops with nothing in flight, head-of-line order."""
+the server stops with nothing in flight, head-of-line order, and which
+requests a free stream slot launches together."""
 import os
 import shutil
 import subprocess
@@ -22,4 +23,4 @@ def test_admission_rule(tmp_path):
     lines = r.stdout.splitlines()
     assert lines and all(ln.startswith("ok ") for ln in lines), r.stdout
     assert r.returncode == 0
-    assert len(lines) == 13
+    assert len(lines) == 18

@@ -37,8 +37,10 @@ def test_noalloc_matches_retrieve_two_calls():
                 assert noalloc(ctx, src, rids, dst, algo, stream) == dpg.OK
                 torch.cuda.synchronize()
                 assert torch.equal(dst, want), f"algo {algo}, {m} rids of {rec} B"
-        # DPG over 2^20 rids of 100 B needs more than the array holds
-        n = m = 1 << 20
+        # DPG over 2^21 rids of 100 B (an output larger than the cache the
+        # two-phase form writes through, so INTERNAL is in the workspace)
+        # needs more than the array holds
+        n = m = 1 << 21
         assert ctx.retrieve_workspace_bytes(n, 100, m, dpg.ALGO_DPG) > SCRATCH_BYTES
         src = torch.from_numpy(synth.record_bytes(n, 100, seed=3)).to(DEV)
         rids = torch.from_numpy(synth.rids_permutation(n, seed=3)).to(DEV)
