@@ -28,7 +28,7 @@ struct PartPlan {
 // Layout of the scratch one pass needs (count matrix and bucket offsets).
 // nbits up to kMaxDigitBits for any pass; up to kMaxWideBits only for uint32
 // keys without values, which are then partitioned without stability, by
-// 1024-thread workgroups of wide_per (8 or 16) keys per thread.  wide: use
+// 1024-thread workgroups of wide_per (8, 16, or 32 up to 2^11 digits) keys per thread.  wide: use
 // that 1024-thread unstable pass for any digit width (uint32 keys without
 // values only).
 PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int wide_per = 16, bool wide = false);

@@ -359,22 +359,57 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
         s_cnt[d] = 0;
         s_glob[d] = off[t * nb + d];
     }
+    // Tiles of 32768 (1024 threads x 32): the rank and digit of every
+    // element share one register (rank + 1 in the low 16 bits, 0 for an
+    // invalid element; the digit above), keys load from the tile's base with
+    // 32-bit lane offsets and are tested in 32 bits, so that the keys and
+    // ranks fit the registers of the workgroup.  Smaller tiles keep a
+    // register per rank and recompute the digit.
+    constexpr bool kPacked = THREADS == 1024 && PER == 32;
+    static_assert(!kPacked || !SPLIT, "packed ranks: digits only");
     uint32_t key[PER];
+    int32_t rank[kPacked ? 1 : PER];
+    uint32_t rd[kPacked ? PER : 1];
+    uint32_t bkt[SPLIT ? PER : 1];
+    if constexpr (kPacked) {
+        const uint32_t *__restrict__ kt = keys + base;
+        if (cnt == T) {
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = k * THREADS + threadIdx.x;
-        key[k] = keys[base + min(e, cnt - 1)] * key_mul;
-    }
-    __syncthreads();
-    int32_t rank[PER];
-    uint32_t bkt[PER];
+            for (int k = 0; k < PER; ++k) key[k] = kt[k * THREADS + threadIdx.x] * key_mul;
+        } else {
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int e = k * THREADS + threadIdx.x;
-        const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
-        const uint32_t d = bucket_of<SPLIT>(key[k], shift, mask, sp);
-        if constexpr (SPLIT) bkt[k] = d;  // a splitter search is kept, a digit recomputed
-        rank[k] = rank_by_atomic(s_cnt, d, valid);
+            for (int k = 0; k < PER; ++k) key[k] = kt[min(k * THREADS + (int)threadIdx.x, cnt - 1)] * key_mul;
+        }
+        __syncthreads();
+        const bool any_key = limit == 0 || limit > 0xffffffffull;
+        const uint32_t lim32 = (uint32_t)limit;
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = k * THREADS + threadIdx.x;
+            const bool valid = e < cnt && (any_key || key[k] < lim32);
+            const uint32_t d = digit_of(key[k], shift, mask);
+            const uint32_t r1 = (uint32_t)(rank_by_atomic(s_cnt, d, valid) + 1);
+            // one opaque instruction, so that the compiler keeps the packed
+            // word rather than the digit and the rank apart
+            uint32_t x;
+            asm("v_lshl_or_b32 %0, %1, 16, %2" : "=v"(x) : "v"(d), "v"(r1));
+            rd[k] = x;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = k * THREADS + threadIdx.x;
+            key[k] = keys[base + min(e, cnt - 1)] * key_mul;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = k * THREADS + threadIdx.x;
+            const bool valid = e < cnt && (limit == 0 || (uint64_t)key[k] < limit);
+            const uint32_t d = bucket_of<SPLIT>(key[k], shift, mask, sp);
+            if constexpr (SPLIT) bkt[k] = d;  // a splitter search is kept, a digit recomputed
+            rank[k] = rank_by_atomic(s_cnt, d, valid);
+        }
     }
     __syncthreads();
     // exclusive prefix of the digit counts: wave w scans the w-th slice of
@@ -411,11 +446,19 @@ __global__ __launch_bounds__(THREADS) void k_part_scatter_unstable(
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         const int e = k * THREADS + threadIdx.x;
-        if (rank[k] >= 0) {
-            const uint32_t d = SPLIT ? bkt[k] : digit_of(key[k], shift, mask);
-            s_key[s_cnt[d] + rank[k]] = key[k];
-            if (idx_out) s_idx[s_cnt[d] + rank[k]] = (uint32_t)(base + e);
-            if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rank[k];
+        int32_t rk;
+        uint32_t d;
+        if constexpr (kPacked) {
+            rk = (int32_t)(rd[k] & 0xffffu) - 1;
+            d = rd[k] >> 16;
+        } else {
+            rk = rank[k];
+            d = SPLIT ? bkt[k] : digit_of(key[k], shift, mask);
+        }
+        if (rk >= 0) {
+            s_key[s_cnt[d] + rk] = key[k];
+            if (idx_out) s_idx[s_cnt[d] + rk] = (uint32_t)(base + e);
+            if (inv) inv[base + e] = (local_inv ? s_cnt[d] : s_glob[d]) + rk;
         } else if (inv && e < cnt) {
             inv[base + e] = 0;
         }
@@ -445,7 +488,7 @@ PartPlan plan_partition(int64_t n, int nbits, int key_bytes, bool has_val, int w
     p.per = part_per(key_bytes, has_val);
     if (nbits > kMaxDigitBits || (wide && key_bytes == 4 && !has_val)) {  // 1024 threads x 8 or 16 keys
         p.threads = 1024;
-        p.per = wide_per == 8 ? 8 : 16;
+        p.per = wide_per == 8 ? 8 : wide_per == 32 && nbits <= 11 && !has_val ? 32 : 16;
     }
     p.tile = p.threads * p.per;
     p.n_tiles = n > 0 ? (n + p.tile - 1) / p.tile : 0;
@@ -493,7 +536,8 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
     if (p.n <= 0) return DPG_OK;
     const bool wide = p.threads == 1024;  // the 1024-thread unstable pass
     if (p.nbits < 1 || p.nbits > kMaxWideBits) return DPG_ERR_UNSUPPORTED;
-    if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 || (p.per != 8 && p.per != 16)))
+    if (wide && (stable || p.key_bytes != 4 || p.has_val || p.threads != 1024 ||
+                 (p.per != 8 && p.per != 16 && p.per != 32) || (p.per == 32 && (split || idx_out))))
         return DPG_ERR_UNSUPPORTED;
     if (local_inv && stable) return DPG_ERR_UNSUPPORTED;
     if (key_mul != 1 && (stable || p.key_bytes != 4 || p.has_val)) return DPG_ERR_UNSUPPORTED;
@@ -552,10 +596,13 @@ dpg_status launch_partition(dpg_ctx *ctx, const PartPlan &p, const void *keys_in
                            (idx_out ? sizeof(uint32_t) * p.tile : 0);
         if (lds + 1024 > kMaxPartitionLds) return DPG_ERR_UNSUPPORTED;
         if (wide) {
-            if (p.threads != 1024 || (p.per != 8 && p.per != 16)) return DPG_ERR_UNSUPPORTED;
-            auto fn = p.per == 8 ? (split ? k_part_scatter_unstable<1024, 8, true> : k_part_scatter_unstable<1024, 8, false>)
-                                 : (split ? k_part_scatter_unstable<1024, 16, true>
-                                          : k_part_scatter_unstable<1024, 16, false>);
+            if (p.threads != 1024 || (p.per != 8 && p.per != 16 && p.per != 32)) return DPG_ERR_UNSUPPORTED;
+            // 32 rids per thread (tiles of 32768, no splitters): segments of
+            // twice the length per run for the same count matrix
+            auto fn = p.per == 32  ? k_part_scatter_unstable<1024, 32, false>
+                      : p.per == 8 ? (split ? k_part_scatter_unstable<1024, 8, true> : k_part_scatter_unstable<1024, 8, false>)
+                                   : (split ? k_part_scatter_unstable<1024, 16, true>
+                                            : k_part_scatter_unstable<1024, 16, false>);
             if (lds > 64 * 1024)
                 DPG_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
             hipLaunchKernelGGL(fn, dim3((unsigned)p.n_tiles), dim3(1024), lds, stream, (const uint32_t *)keys_in, p.n,

@@ -86,8 +86,10 @@ struct Slot {
 // Batches of fewer requests launch the batch kernel directly even with
 // use_graph.
 constexpr int32_t kGraphMinRequests = 16;
-// With this many slots busy, a partial batch waits for a slot to finish
-// (the device is fed meanwhile), so that requests gather into larger batches.
+// With this many slots busy and requests still waiting for admission (the
+// server is saturated), a partial batch waits for a slot to finish (the
+// device is fed meanwhile), so that requests gather into larger batches.
+// Below saturation nothing waits for admission, and a request starts at once.
 constexpr int kHoldBusySlots = 2;
 
 static size_t output_bytes(const dpg_request &q) {
@@ -281,11 +283,12 @@ static void scheduler(dpg_server *s) {
         bool window_wait = false;
         int busy = 0;
         for (Slot &sl : s->slots) busy += sl.busy ? 1 : 0;
+        const bool saturated = !s->pending.empty();
         for (Slot &sl : s->slots) {
             if (sl.busy || s->admitted.empty()) continue;
             std::vector<uint64_t> batch;
             const bool batched = s->tickets[s->admitted.front()].batched;
-            if (batched && s->cfg.max_batch_requests > 1 && busy >= kHoldBusySlots && !s->stop) {
+            if (batched && s->cfg.max_batch_requests > 1 && busy >= kHoldBusySlots && saturated && !s->stop) {
                 size_t avail = 0;
                 for (size_t k = 0; k < s->admitted.size() && (int32_t)avail < s->cfg.max_batch_requests &&
                                    k < (size_t)4 * (size_t)s->cfg.max_batch_requests;

@@ -196,8 +196,11 @@ def test_plan_phase_forms():
     # short rid lists take tiles of 8192 rids so that Phase I fills the chip
     p = dpg.plan_retrieve(1 << 20, 100, 1 << 20, dpg.ALGO_DPG)
     assert p.dist_tile == 8192 and p.n_tiles == 128
+    # 1025..2048 runs of a long rid list: tiles of 32768 rids
     p = dpg.plan_retrieve(1 << 26, 100, 1 << 26, dpg.ALGO_DPG)
-    assert p.dist_tile == 16384 and p.n_runs == 2048
+    assert p.dist_tile == 32768 and p.n_runs == 2048 and p.n_tiles == 2048
+    p = dpg.plan_retrieve(1 << 25, 100, 1 << 25, dpg.ALGO_DPG)
+    assert p.dist_tile == 16384 and p.n_runs == 1024
 
 
 def test_hash_index_layout_and_validation():

@@ -61,10 +61,14 @@ def test_retrieve_2p23x100B_full_oracle(ctx, algo):
 @pytest.mark.parametrize("algo", [dpg.ALGO_DPG, dpg.ALGO_DIRECT], ids=["dpg", "direct"])
 def test_retrieve_2p26x100B_headline_full_oracle(ctx, algo):
     """The headline workload: 2^26 records of 100 B, a permutation of 2^26
-    rids, the default plan.  All 6.7 GB of output against the oracle, in
-    chunks of 2^22 rids."""
+    rids, the default plan (for DPG: 2048 runs, partition tiles of 32768
+    rids).  All 6.7 GB of output against the oracle, in chunks of 2^22
+    rids."""
     n, rec = 1 << 26, 100
     seed = synth.SEED_BASE + 1
+    if algo == dpg.ALGO_DPG:
+        plan = ctx.plan_retrieve(n, rec, n, algo)
+        assert (plan.n_runs, plan.dist_tile, plan.distribute) == (2048, 32768, dpg.DIST_PARTITION)
     src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
     rids = synth.rids_permutation(n, seed, backend="torch", device=DEV)
     rids_h = rids.cpu().numpy()

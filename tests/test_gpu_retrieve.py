@@ -60,6 +60,9 @@ VARIANTS = {
     "dpg-partition-long-runs": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=12, dist=dpg.DIST_PARTITION)),
     # 257..4096 runs: the 12-bit partition pass
     "dpg-wide-partition": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=4, dist=dpg.DIST_PARTITION)),
+    # distribute tiles of 32768 rids (32 per thread of a 1024-thread pass)
+    "dpg-partition-tile-32768": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, log2_run=6, dist=dpg.DIST_PARTITION,
+                                                    gather=1, dist_tile=32768)),
     # Phase III forms: through the caches, or a distribute tile staged in LDS
     # (the latter applies to 4..16-byte records with the partition distribute)
     "dpg-cached-gather": (dpg.ALGO_DPG, dict(probe=dpg.PROBE_CACHED, dist=dpg.DIST_PARTITION, gather=1)),
@@ -123,6 +126,18 @@ def test_retrieve_matches_oracle(ctx, case, variant):
     finally:
         configure(ctx)
     assert np.array_equal(got.cpu().numpy(), expect), f"{variant} {case}"
+
+
+def test_partition_tile_option_takes_effect(ctx):
+    """The 32768-rid distribute tile is planned when asked for (up to 2^11
+    runs, not with the two-phase scatter) -- the variant above runs it."""
+    configure(ctx, **VARIANTS["dpg-partition-tile-32768"][1])
+    try:
+        assert ctx.plan_retrieve(65537, 100, 80000, dpg.ALGO_DPG).dist_tile == 32768
+        ctx.set_option(dpg.OPT_LOG2_RUN, 5)  # 2049 runs (12-bit digits): 16384-rid tiles
+        assert ctx.plan_retrieve(65537, 100, 80000, dpg.ALGO_DPG).dist_tile == 16384
+    finally:
+        configure(ctx)
 
 
 def test_empty_rid_list(ctx):
