@@ -176,6 +176,21 @@ def oracle_rate(fn, units: float, unit: str, sample: str):
                             "sample": f"one copy on one thread, {dt1:.2f} s"}}
 
 
+# Sources of the retrieval kernels and their launch shapes: counter data
+# taken before a change to any of them no longer describe the kernels.
+RETRIEVAL_SOURCES = ("copy.hip", "partition.hip", "partition.h", "scan.hip", "distribute.hip", "plan.cpp",
+                     "dev_common.h")
+
+
+def retrieval_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in RETRIEVAL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0308004_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:12]
+
+
 def roofline_entry(prof: dict, kernels: list[str], counters: dict | None, workload_key: str | None = None):
     """The dominant kernel: algorithmic bytes per launch over its average
     launch duration (HIP events on the kernel's own stream)."""
@@ -196,6 +211,7 @@ def roofline_entry(prof: dict, kernels: list[str], counters: dict | None, worklo
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4),
         "traffic": traffic,
+        "traffic_key": workload_key,
         "avg_launch_ms": round(avg_ms, 4),
         "alg_bytes_per_launch": bytes_per_launch,
     }
@@ -257,8 +273,9 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
     if not np.array_equal(got, synth.records_at(rids_np[sample], R, seed)):
         raise SystemExit("bench: DPG output differs from the generator's records")
     delivered = m * R
-    # counter data apply only to the same shape and DPG plan
-    wkey = f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}:dist{plan.distribute}"
+    # counter data apply only to the same shape, DPG plan and kernel sources
+    wkey = (f"{n}x{R}:{args.pattern}:L{plan.log2_run}:probe{plan.probe}:runs{plan.n_runs}:dist{plan.distribute}"
+            f":tile{plan.dist_tile}:gather{plan.gather}:src{retrieval_source_hash()}")
     dpg_kernels = ["k_part_hist", "k_part_scatter", "k_part_hist_wide", "k_part_scatter_unstable", "k_dist_hist",
                    "k_dist_scatter", "k_probe_cached", "k_probe_lds", "k_gather_phase", "k_gather_lds",
                    "k_probe_scatter"]

@@ -4,6 +4,13 @@
   python -m paper_cs_0308004_amd.rocprof_summary bytes <fetch_dir> <write_dir> <reqsize_dir> <out.md>
          <counters.json> <workload key> -- <command...>
 
+  python -m paper_cs_0308004_amd.rocprof_summary counters <out.md> <kernel,kernel,...> <dir> [<dir>...]
+         -- <command...>
+
+`counters` averages every counter of each run directory (rocprofv3 --pmc
+<counters>) per dispatch of the named kernels, and derives the LDS and
+instruction ratios the counters allow (CU_NUM = 256 compute units).
+
 `bytes` reads three counter runs of the same command (rocprofv3 --pmc
 FETCH_SIZE; --pmc WRITE_SIZE; --pmc TCC_EA0_RDREQ_32B_sum TCC_EA0_RDREQ_64B_sum
 TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_DRAM_sum).  The command must include a
@@ -152,6 +159,68 @@ def bytes_report(fetch_dir, write_dir, req_dir, out_md, out_json, workload, comm
                    "kernels": kernels}, f, indent=1)
 
 
+CU_NUM = 256
+
+
+def counters_report(out_md: str, kernels: list[str], dirs: list[str], command: str):
+    """Mean of each counter per dispatch, per kernel, over the runs in dirs."""
+    per = defaultdict(lambda: defaultdict(list))  # kernel -> counter -> values (one per dispatch)
+    passes = []
+    for d in dirs:
+        names = set()
+        for name, c in dispatch_counters(d).values():
+            k = short_name(name)
+            if k not in kernels:
+                continue
+            for cn, v in c.items():
+                per[k][cn].append(v)
+                names.add(cn)
+        passes.append(sorted(names))
+    lines = ["# Instruction and LDS counters per dispatch", "",
+             f"Command: `{command}`", "",
+             "Runs (one per counter set, each `rocprofv3 --pmc <set> --output-format csv -- <command>`):", ""]
+    lines += [f"* `{' '.join(p)}`" for p in passes]
+    lines += ["", "Mean per dispatch:", ""]
+    counters = sorted({cn for k in per for cn in per[k]})
+    lines.append("| counter | " + " | ".join(kernels) + " |")
+    lines.append("|---|" + "---:|" * len(kernels))
+    mean = {k: {cn: sum(v) / len(v) for cn, v in per[k].items()} for k in per}
+    for cn in counters:
+        lines.append(f"| {cn} | " + " | ".join(f"{mean.get(k, {}).get(cn, float('nan')):.4g}" for k in kernels) + " |")
+
+    def ratio(k, a, b, scale=1.0):
+        m = mean.get(k, {})
+        if a in m and b in m and m[b]:
+            return scale * m[a] / m[b]
+        return None
+
+    derived = [
+        ("LDS busy, % of CU cycles (SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE x 256))",
+         lambda k: ratio(k, "SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE", 100.0 / CU_NUM)),
+        ("LDS bank-conflict cycles per LDS busy cycle (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE)",
+         lambda k: ratio(k, "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE")),
+        ("waves waiting to issue an LDS instruction, % of wave cycles (SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES)",
+         lambda k: ratio(k, "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", 100.0)),
+        ("waves waiting on anything, % of wave cycles (SQ_WAIT_ANY / SQ_WAVE_CYCLES)",
+         lambda k: ratio(k, "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", 100.0)),
+        ("LDS instructions per wave", lambda k: ratio(k, "SQ_INSTS_LDS", "SQ_WAVES")),
+        ("VALU instructions per wave", lambda k: ratio(k, "SQ_INSTS_VALU", "SQ_WAVES")),
+        ("vector memory reads per wave", lambda k: ratio(k, "SQ_INSTS_VMEM_RD", "SQ_WAVES")),
+        ("VALU busy, % of CU cycles (SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE x 256))",
+         lambda k: ratio(k, "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", 100.0 / CU_NUM)),
+        ("mean resident waves per CU (SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE x 256))",
+         lambda k: ratio(k, "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE", 1.0 / CU_NUM)),
+    ]
+    lines += ["", "Derived:", "", "| ratio | " + " | ".join(kernels) + " |", "|---|" + "---:|" * len(kernels)]
+    for label, fn in derived:
+        vals = [fn(k) for k in kernels]
+        if all(v is None for v in vals):
+            continue
+        lines.append(f"| {label} | " + " | ".join("-" if v is None else f"{v:.3g}" for v in vals) + " |")
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def main(argv):
     if "--" not in argv:
         raise SystemExit(__doc__)
@@ -161,6 +230,8 @@ def main(argv):
         stats_report(args[1], args[2], command)
     elif args[0] == "bytes":
         bytes_report(args[1], args[2], args[3], args[4], args[5], args[6], command)
+    elif args[0] == "counters":
+        counters_report(args[1], args[2].split(","), args[3:], command)
     else:
         raise SystemExit(__doc__)
 
