@@ -106,13 +106,38 @@ __device__ __forceinline__ int bt_rank(const uint32_t *node, uint32_t q) {
     return c;
 }
 
-// The same count for a node in LDS, by a branch-free binary search (entries
-// ascending): five halving steps, then one more comparison for the count 32.
-__device__ __forceinline__ int bt_rank_lds(const uint32_t *node, uint32_t q) {
+// Nodes staged in LDS are stored swizzled: entry i of node c at
+// c * 32 + (i ^ (c & 31)).  Lanes walking different nodes read the same entry
+// index in the same step; unswizzled, every node starts on bank 0 and those
+// reads all fall on one bank.
+__device__ __forceinline__ int bt_sw(int c, int i) { return c * kBtFan + (i ^ (c & (kBtFan - 1))); }
+
+// Number of the 32 keys of swizzled node c below q, by a branch-free binary
+// search (entries ascending): five halving steps, then one more comparison
+// for the count 32.
+__device__ __forceinline__ int bt_rank_lds_sw(const uint32_t *base, int c, uint32_t q) {
     int pos = 0;
 #pragma unroll
-    for (int step = kBtFan / 2; step > 0; step >>= 1) pos += node[pos + step - 1] < q ? step : 0;
-    return pos + (node[pos] < q ? 1 : 0);
+    for (int step = kBtFan / 2; step > 0; step >>= 1) pos += base[bt_sw(c, pos + step - 1)] < q ? step : 0;
+    return pos + (base[bt_sw(c, pos)] < q ? 1 : 0);
+}
+
+// Element k of v (k in 0..3).
+__device__ __forceinline__ uint32_t u4_at(const u32x4 &v, int k) {
+    return k == 0 ? v.x : k == 1 ? v.y : k == 2 ? v.z : v.w;
+}
+
+// Store the 4 entries 4m..4m+3 of node c (v, in entry order) to their
+// swizzled places: the 16-byte group m ^ (c >> 2 & 7), permuted inside by c & 3.
+__device__ __forceinline__ void bt_store4_sw(uint32_t *base, int c, int m, const u32x4 &v) {
+    const int x = c & (kBtFan - 1);
+    const int lo = x & 3;
+    u32x4 w;
+    w.x = u4_at(v, 0 ^ lo);
+    w.y = u4_at(v, 1 ^ lo);
+    w.z = u4_at(v, 2 ^ lo);
+    w.w = u4_at(v, 3 ^ lo);
+    *(u32x4 *)(base + c * kBtFan + 4 * (m ^ (x >> 2))) = w;
 }
 
 // Root-to-leaf walk: the rid of the first entry whose key is q, or -1.  The
@@ -217,21 +242,23 @@ __global__ __launch_bounds__(kBtProbeThreads) void k_bt_probe_lds(
     const int nbr = (int)min((int64_t)G, n0 - blk0);  // blocks of this run (>= 1: every query has a run)
     const int nt = (nbr + kBtFan - 1) / kBtFan;        // its level-1 nodes
     {
+        // swizzled staging (bt_sw): 16-byte groups of a node move whole
         const u32x4 *k4 = (const u32x4 *)(leaf_keys + blk0 * kBtFan);
         const u32x4 *r4 = (const u32x4 *)(leaf_rids + blk0 * kBtFan);
-        u32x4 *sk4 = (u32x4 *)s_key;
-        u32x4 *sr4 = (u32x4 *)s_rid;
         const int n4 = nbr * (kBtFan / 4);
 #pragma unroll 4
         for (int e = threadIdx.x; e < n4; e += kBtProbeThreads) {
-            sk4[e] = k4[e];
-            sr4[e] = r4[e];
+            const int c = e / (kBtFan / 4), m = e % (kBtFan / 4);
+            bt_store4_sw(s_key, c, m, k4[e]);
+            bt_store4_sw((uint32_t *)s_rid, c, m, (u32x4)r4[e]);
         }
-        for (int c = threadIdx.x; c < nt * kBtFan; c += kBtProbeThreads)
-            s_l1[c] = level1 ? level1[blk0 + c] : (c == 0 ? leaf_keys[kBtFan - 1] : kBtPad);
+        for (int e = threadIdx.x; e < nt * kBtFan; e += kBtProbeThreads)
+            s_l1[bt_sw(e / kBtFan, e % kBtFan)] =
+                level1 ? level1[blk0 + e] : (e == 0 ? leaf_keys[kBtFan - 1] : kBtPad);
     }
     __syncthreads();
-    if (threadIdx.x < kBtTop) s_top[threadIdx.x] = (int)threadIdx.x < nt ? s_l1[threadIdx.x * kBtFan + kBtFan - 1] : kBtPad;
+    if (threadIdx.x < kBtTop)
+        s_top[threadIdx.x] = (int)threadIdx.x < nt ? s_l1[bt_sw((int)threadIdx.x, kBtFan - 1)] : kBtPad;
     __syncthreads();
     for (int j0 = 0; j0 < cnt; j0 += kBtProbeThreads * kBtProbeBatch) {
         uint32_t qq[kBtProbeBatch];
@@ -253,12 +280,12 @@ __global__ __launch_bounds__(kBtProbeThreads) void k_bt_probe_lds(
                 t += (v.x < q) + (v.y < q) + (v.z < q) + (v.w < q);
             }
             if (t < nt) {
-                const int r1 = bt_rank_lds(s_l1 + t * kBtFan, q);
+                const int r1 = bt_rank_lds_sw(s_l1, t, q);
                 const int c = t * kBtFan + r1;
                 if (r1 < kBtFan && c < nbr) {
-                    const int r0 = bt_rank_lds(s_key + c * kBtFan, q);
+                    const int r0 = bt_rank_lds_sw(s_key, c, q);
                     if (r0 < kBtFan) {
-                        const int e = c * kBtFan + r0;
+                        const int e = bt_sw(c, r0);
                         if (s_key[e] == q) res = s_rid[e];
                     }
                 }

@@ -160,6 +160,7 @@ def bytes_report(fetch_dir, write_dir, req_dir, out_md, out_json, workload, comm
 
 
 CU_NUM = 256
+XCD_NUM = 8  # GRBM_GUI_ACTIVE comes summed over the XCDs: per XCD it is the kernel's cycles
 
 
 def counters_report(out_md: str, kernels: list[str], dirs: list[str], command: str):
@@ -194,22 +195,28 @@ def counters_report(out_md: str, kernels: list[str], dirs: list[str], command: s
             return scale * m[a] / m[b]
         return None
 
+    # GRBM_GUI_ACTIVE / 8 = the kernel's cycles; SQ_WAVE_CYCLES and
+    # SQ_WAIT_ANY count in units of 4 cycles (the OccupancyPercent and
+    # LdsUtil expressions of rocprofv3 -L use the same scales)
+    per_cu = XCD_NUM * 100.0 / CU_NUM
     derived = [
-        ("LDS busy, % of CU cycles (SQ_LDS_IDX_ACTIVE / (GRBM_GUI_ACTIVE x 256))",
-         lambda k: ratio(k, "SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE", 100.0 / CU_NUM)),
-        ("LDS bank-conflict cycles per LDS busy cycle (SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE)",
-         lambda k: ratio(k, "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE")),
-        ("waves waiting to issue an LDS instruction, % of wave cycles (SQ_WAIT_INST_LDS / SQ_WAVE_CYCLES)",
-         lambda k: ratio(k, "SQ_WAIT_INST_LDS", "SQ_WAVE_CYCLES", 100.0)),
+        ("LDS busy, % of CU cycles (SQ_LDS_IDX_ACTIVE / (cycles x 256))",
+         lambda k: ratio(k, "SQ_LDS_IDX_ACTIVE", "GRBM_GUI_ACTIVE", per_cu)),
+        ("LDS bank conflicts per access (SQ_LDS_BANK_CONFLICT / (SQ_LDS_IDX_ACTIVE - SQ_LDS_BANK_CONFLICT))",
+         lambda k: (lambda m: m["SQ_LDS_BANK_CONFLICT"] / (m["SQ_LDS_IDX_ACTIVE"] - m["SQ_LDS_BANK_CONFLICT"])
+                    if "SQ_LDS_BANK_CONFLICT" in m and m.get("SQ_LDS_IDX_ACTIVE", 0) > m["SQ_LDS_BANK_CONFLICT"]
+                    else None)(mean.get(k, {}))),
+        ("LDS busy cycles spent in bank conflicts, %",
+         lambda k: ratio(k, "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", 100.0)),
         ("waves waiting on anything, % of wave cycles (SQ_WAIT_ANY / SQ_WAVE_CYCLES)",
          lambda k: ratio(k, "SQ_WAIT_ANY", "SQ_WAVE_CYCLES", 100.0)),
         ("LDS instructions per wave", lambda k: ratio(k, "SQ_INSTS_LDS", "SQ_WAVES")),
         ("VALU instructions per wave", lambda k: ratio(k, "SQ_INSTS_VALU", "SQ_WAVES")),
         ("vector memory reads per wave", lambda k: ratio(k, "SQ_INSTS_VMEM_RD", "SQ_WAVES")),
-        ("VALU busy, % of CU cycles (SQ_ACTIVE_INST_VALU / (GRBM_GUI_ACTIVE x 256))",
-         lambda k: ratio(k, "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", 100.0 / CU_NUM)),
-        ("mean resident waves per CU (SQ_WAVE_CYCLES / (GRBM_GUI_ACTIVE x 256))",
-         lambda k: ratio(k, "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE", 1.0 / CU_NUM)),
+        ("VALU busy, % of CU cycles (SQ_ACTIVE_INST_VALU / (cycles x 256))",
+         lambda k: ratio(k, "SQ_ACTIVE_INST_VALU", "GRBM_GUI_ACTIVE", per_cu)),
+        ("mean resident waves per CU (4 SQ_WAVE_CYCLES / (cycles x 256))",
+         lambda k: ratio(k, "SQ_WAVE_CYCLES", "GRBM_GUI_ACTIVE", 4.0 * XCD_NUM / CU_NUM)),
     ]
     lines += ["", "Derived:", "", "| ratio | " + " | ".join(kernels) + " |", "|---|" + "---:|" * len(kernels)]
     for label, fn in derived:
