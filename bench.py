@@ -326,6 +326,31 @@ def bench_retrieve(args, ctx, dpg, synth, torch, np, counters):
         "direct": {"sector_bytes_per_record": f_r, "bytes": b_direct,
                    "frac": round(b_direct / (ms_direct * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}}
     out["copy_ceiling"] = copy_ceiling(ctx, torch)
+    if not (args.log2_run or args.probe or args.dist or args.gather) and R % 4 == 0:
+        # Phase II as the paper states it: every source run loaded whole into
+        # LDS (runs of <= 64 KiB from two partition passes), then the gather
+        # through the composed slots
+        del ws
+        ctx.set_option(dpg.OPT_DISTRIBUTE, dpg.DIST_TWO_PASS)
+        ctx.set_option(dpg.OPT_PROBE, dpg.PROBE_LDS)
+        plan_l = ctx.plan_retrieve(n, R, m, dpg.ALGO_DPG)
+        if plan_l.probe == dpg.PROBE_LDS:
+            ws = torch.empty(plan_l.workspace_bytes, dtype=torch.uint8, device=dev)
+            ms_l, _, prof_l = time_and_profile(ctx, step_dpg, args.steps, args.warmup, torch)
+            got = dst[torch.from_numpy(sample).to(dev)].cpu().numpy()
+            if not np.array_equal(got, synth.records_at(rids_np[sample], R, seed)):
+                raise SystemExit("bench: the LDS-probe DPG output differs from the generator's records")
+            out["dpg_lds_probe"] = {
+                "what": "Phase II with each source run staged whole in LDS (two partition passes into "
+                        f"{plan_l.n_runs} runs of 2^{plan_l.log2_run} records)",
+                "value": round(delivered / (ms_l * 1e-3) / 1e9, 2), "unit": "GB/s", "ms_per_step": round(ms_l, 4),
+                "over_default_dpg": round(ms_dpg / ms_l, 4),
+                "kernels_ms_per_step": {k: round(v["ms"] / v["launches"], 4) for k, v in prof_l.items()},
+                "roofline": roofline_entry(prof_l, ["k_probe_lds"], None),
+            }
+        ctx.set_option(dpg.OPT_DISTRIBUTE, 0)
+        ctx.set_option(dpg.OPT_PROBE, 0)
+        ws = None
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle baseline")
@@ -661,6 +686,10 @@ def bench_hash(args, ctx, dpg, synth, torch, np):
                      "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()},
                      "roofline": roofline_entry(prof, list(prof), None)}
     res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
+    # what bounds the probe, from its LDS and instruction counters
+    # (profiles/lookups_probe_counters.md)
+    res["dpg"]["roofline"]["limiter"] = ("latency of dependent reads (query, slot, overflow range) at 13.5 "
+                                         "waves per CU: LDS busy <10 %, VALU 19 %, waves waiting 75 %")
     import oracle
 
     k_host = keys.cpu().numpy().view(np.uint32)
@@ -708,6 +737,10 @@ def bench_btree(args, ctx, dpg, synth, torch, np):
                      "kernels_ms": {k: round(v["ms"] / v["launches"], 4) for k, v in prof.items()},
                      "roofline": roofline_entry(prof, list(prof), None)}
     res["dpg_over_direct"] = round(res["direct"]["ms"] / res["dpg"]["ms"], 4)
+    # what bounds the probe, from its LDS and instruction counters
+    # (profiles/lookups_probe_counters.md)
+    res["dpg"]["roofline"]["limiter"] = ("instruction issue and LDS latency: VALU busy 46 %, LDS busy 28 % "
+                                         "(1.5 bank conflicts per access with swizzled nodes), waves waiting 70 %")
     import oracle
 
     k_host = keys[: 1 << 22].cpu().numpy().view(np.uint32)

@@ -13,7 +13,7 @@ static const char *const kKernelNames[K_COUNT] = {
     "k_part_scatter_unstable", "k_gather_lds", "k_hash_home", "k_hash_mark", "k_hash_place",
     "k_hash_ov_off", "k_hash_direct", "k_hash_probe", "k_hash_probe_lds", "k_smj_keys", "k_smj_ranges",
     "k_smj_emit", "k_bt_level", "k_bt_direct", "k_bt_probe", "k_bt_probe_lds", "k_probe_scatter",
-    "k_stream_copy", "k_scan_small"};
+    "k_stream_copy", "k_scan_small", "k_run_bounds"};
 
 const char *kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kKernelNames[id] : "unknown"; }
 
@@ -84,6 +84,13 @@ dpg_status run_retrieve(dpg_ctx *ctx, const RetrievePlan &p, const void *src, co
         const int32_t *n_valid = (const int32_t *)(w + p.off_bucket) + (1 << p.part_nbits);
         return launch_probe_scatter(ctx, src, p.n_src, (const int32_t *)(w + p.off_run),
                                     (const int32_t *)(w + p.off_inv), n_valid, dst, p.n_rids, p.rec_bytes, stream);
+    }
+    if (p.dist_mode == DIST_TWO_PASS && p.probe == DPG_PROBE_LDS) {
+        // runs staged in LDS: Phase III through the composed slots, one pass
+        const dpg_status st = run_distribute_probe(ctx, p, src, rids, ws, stream, false);
+        if (st != DPG_OK) return st;
+        return launch_gather(ctx, K_GATHER_PHASE, w + p.off_internal, p.n_rids, (const int32_t *)(w + p.off_inv),
+                             dst, p.n_rids, p.rec_bytes, 4.0 * M + 2.0 * R * M, stream);
     }
     if (p.dist_mode == DIST_TWO_PASS) {
         // Phase III in two passes, coarse first: u[j] = INTERNAL[inv_c[j]] in

@@ -158,6 +158,36 @@ static dpg_status launch_distribute_sampled(dpg_ctx *ctx, const RetrievePlan &p,
                             local_inv, 1u, split, B - 1);
 }
 
+// Run boundaries of a list sorted by run (the two-pass distribute's output):
+// run_off[b] = first position whose run is >= b, for b in [0, B], over the
+// first *n_valid entries.  Each position k writes the boundaries of the runs
+// after its predecessor's up to its own; the last position also closes the
+// runs after its own.
+__global__ __launch_bounds__(256) void k_run_bounds(const int32_t *__restrict__ run, int64_t M,
+                                                    const int32_t *__restrict__ n_valid, int shift, int B,
+                                                    int32_t *__restrict__ run_off) {
+    const int64_t nv = min((int64_t)*n_valid, M);
+    if (nv == 0) {
+        for (int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x; b <= B; b += (int64_t)gridDim.x * 256)
+            run_off[b] = 0;
+        return;
+    }
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < nv; k += (int64_t)gridDim.x * 256) {
+        const int r = min(run[k] >> shift, B - 1);
+        const int rp = k > 0 ? min(run[k - 1] >> shift, B - 1) : -1;
+        for (int b = rp + 1; b <= r; ++b) run_off[b] = (int32_t)k;
+        if (k == nv - 1)
+            for (int b = r + 1; b <= B; ++b) run_off[b] = (int32_t)nv;
+    }
+}
+
+// Work items of the LDS probe: items[b] = ceil(len(run b) / P), scanned later.
+__global__ __launch_bounds__(256) void k_run_items(const int32_t *__restrict__ run_off, int B, int P,
+                                                   int32_t *__restrict__ items) {
+    const int b = blockIdx.x * 256 + threadIdx.x;
+    if (b < B) items[b] = (run_off[b + 1] - run_off[b] + P - 1) / P;
+}
+
 // Phase I in two passes (the multi-pass DPG of Section 7): the rids are
 // partitioned by the fine bits of their run index (unstable), then that list
 // by the coarse bits (stable), so the final list is in run order; inv_f and
@@ -169,13 +199,39 @@ static dpg_status launch_distribute_two_pass(dpg_ctx *ctx, const RetrievePlan &p
     const int64_t M = p.n_rids;
     const PartPlan pf = plan_partition(M, p.lg_fine, 4, false);
     const PartPlan pc = plan_partition(M, p.lg_coarse, 4, false);
+    if (p.probe == DPG_PROBE_LDS) {
+        // the first pass leaves the slots of dropped rids unwritten; filled
+        // with an invalid rid, they are dropped by the second pass too, so
+        // that its output is exactly the valid rids in run order (the run
+        // boundaries below rely on that order)
+        dpg_status st = launch_fill_i32(ctx, (int32_t *)(w + p.off_run_f), M, (int32_t)p.n_src, stream);
+        if (st != DPG_OK) return st;
+    }
     dpg_status st = launch_partition(ctx, pf, rids, nullptr, w + p.off_run_f, nullptr, (int32_t *)(w + p.off_inv_f),
                                      p.log2_run, (uint64_t)p.n_src, w + p.off_part, stream, nullptr, nullptr, 0,
                                      /*stable=*/false);
     if (st != DPG_OK) return st;
-    return launch_partition(ctx, pc, w + p.off_run_f, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv_c),
-                            p.log2_run + p.lg_fine, (uint64_t)p.n_src, w + p.off_part2, stream, nullptr, nullptr, 0,
-                            /*stable=*/true);
+    st = launch_partition(ctx, pc, w + p.off_run_f, nullptr, w + p.off_run, nullptr, (int32_t *)(w + p.off_inv_c),
+                          p.log2_run + p.lg_fine, (uint64_t)p.n_src, w + p.off_part2, stream, nullptr, nullptr, 0,
+                          /*stable=*/true);
+    if (st != DPG_OK || p.probe != DPG_PROBE_LDS) return st;
+    // the LDS probe needs every run's boundaries: the list is in run order,
+    // so they are where the run changes; then each run's work items
+    const int B = (int)p.n_runs;
+    const int32_t *n_valid = (const int32_t *)(w + p.off_part2 + pc.off_bucket) + (1 << p.lg_coarse);
+    int32_t *run_off = (int32_t *)(w + p.off_bucket);
+    int32_t *items = (int32_t *)(w + p.off_items);
+    {
+        ProfScope prof(ctx, K_RUN_BOUNDS, 8.0 * M + 8.0 * B, stream);
+        const int64_t grid = std::min<int64_t>((M + 255) / 256, (int64_t)ctx->n_cu * 16);
+        hipLaunchKernelGGL(k_run_bounds, dim3((unsigned)std::max<int64_t>(grid, 1)), dim3(256), 0, stream,
+                           (const int32_t *)(w + p.off_run), M, n_valid, p.log2_run, B, run_off);
+        DPG_HIP(hipGetLastError());
+        hipLaunchKernelGGL(k_run_items, dim3((unsigned)((B + 255) / 256)), dim3(256), 0, stream, run_off, B,
+                           p.probe_chunk, items);
+        DPG_HIP(hipGetLastError());
+    }
+    return launch_scan_1d(ctx, items, B, (int32_t *)(w + p.off_scan), items + B, stream);
 }
 
 dpg_status launch_distribute(dpg_ctx *ctx, const RetrievePlan &p, const int32_t *rids, void *ws,

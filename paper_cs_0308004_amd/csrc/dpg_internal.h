@@ -78,6 +78,7 @@ enum KernelId {
     K_PROBE_SCATTER,     // two-phase DPG: Phase II writes each record to its place in dst
     K_STREAM_COPY,       // plain streaming copy (the measured copy ceiling)
     K_SCAN_SMALL,        // Phase I bucket boundaries, whole column scan in one workgroup
+    K_RUN_BOUNDS,        // two-pass Phase I for the LDS probe: run boundaries and work items
     K_COUNT
 };
 const char *kernel_name(int id);
@@ -187,8 +188,10 @@ struct RetrievePlan {
     size_t off_sample = 0, off_sample2 = 0, off_spart = 0, off_split = 0;
     // DIST_TWO_PASS: digit widths, the fine pass's runs and slots, the coarse
     // pass's slots and scratch, and the intermediate record array of Phase III
+    // (with the LDS probe: the runs' boundaries at off_bucket, their work
+    // items at off_items and the scan scratch at off_scan instead)
     int lg_fine = 0, lg_coarse = 0;
-    size_t off_run_f = 0, off_inv_f = 0, off_inv_c = 0, off_part2 = 0, off_u = 0;
+    size_t off_run_f = 0, off_inv_f = 0, off_inv_c = 0, off_part2 = 0, off_u = 0, off_scan = 0;
     size_t workspace = 0;
 };
 

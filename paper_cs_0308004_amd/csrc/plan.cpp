@@ -85,7 +85,16 @@ static void layout_workspace(RetrievePlan *p) {
             p->off_run_f = take((size_t)M * 4);
             p->off_inv_f = take((size_t)M * 4);
             p->off_inv_c = take((size_t)M * 4);
-            p->off_u = take((size_t)M * p->rec_bytes);
+            if (p->probe == DPG_PROBE_LDS) {
+                // the LDS probe: every run's boundaries and work items, found
+                // from the sorted list; Phase III is then one pass through
+                // the composed slots
+                p->off_bucket = take((size_t)(B + 1) * 4);
+                p->off_items = take((size_t)(B + 1) * 4);
+                p->off_scan = take(scan_1d_scratch_bytes(B));
+            } else {
+                p->off_u = take((size_t)M * p->rec_bytes);
+            }
         } else {
             p->off_cnt = take((size_t)p->n_tiles * B * 4);
             p->off_csum = take((size_t)p->n_chunks * B * 4);
@@ -113,9 +122,10 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     const int lg_n = ilog2_ceil(N);
     const int lg_lds = floor_log2(kLdsRegionBytes / (size_t)R);
     const bool sampled = dist_mode == DIST_SAMPLED + 1, two_pass = dist_mode == DIST_TWO_PASS + 1;
-    // runs of uneven width (sampled) or without per-run boundaries (two-pass)
-    // are probed through the caches
-    if (sampled || two_pass) probe = DPG_PROBE_CACHED;
+    // runs of uneven width (sampled) are probed through the caches; so are
+    // the two-pass runs unless the LDS probe is asked for (their boundaries
+    // are then found from the sorted list)
+    if (sampled || (two_pass && probe != DPG_PROBE_LDS)) probe = DPG_PROBE_CACHED;
     // records of one 4-, 8- or 16-byte element: the wide LDS probe (128 KiB
     // regions, a whole run per work item) when the runs fit one partition
     // pass.  Chosen by default for 4-byte records only: at 2^26 rids its probe
@@ -140,7 +150,7 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
     const bool cache_out = R >= 24 && (double)M * R <= kScatterCacheBytes;
     const bool want_scatter = (gather == 3 || (gather == 0 && (sector_rows || cache_out))) && !sampled &&
                               !two_pass && dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_LDS;
-    const bool want_wide = !want_scatter && small && dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_CACHED &&
+    const bool want_wide = !want_scatter && !two_pass && small && dist_mode != DIST_APPEND + 1 && probe != DPG_PROBE_CACHED &&
                            (probe == DPG_PROBE_LDS || R == 4) && (log2_run <= 0 || log2_run <= lg_wide) &&
                            ((N + ((int64_t)1 << lg_wide) - 1) >> lg_wide) <= kMaxWideBuckets;
     if (probe == DPG_PROBE_AUTO) probe = want_wide ? DPG_PROBE_LDS : DPG_PROBE_CACHED;

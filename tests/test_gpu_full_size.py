@@ -85,6 +85,36 @@ def test_retrieve_2p26x100B_headline_full_oracle(ctx, algo):
     free_device()
 
 
+def test_retrieve_2p26x100B_two_pass_lds_probe_full_oracle(ctx):
+    """The headline workload with every source run staged in LDS for the
+    probe (Section 2.1's Phase II as stated): 2^17 runs of 512 records from
+    two partition passes.  All 6.7 GB of output against the oracle."""
+    n, rec = 1 << 26, 100
+    seed = synth.SEED_BASE + 1
+    for opt, v in ((dpg.OPT_DISTRIBUTE, dpg.DIST_TWO_PASS), (dpg.OPT_PROBE, dpg.PROBE_LDS)):
+        ctx.set_option(opt, v)
+    try:
+        plan = ctx.plan_retrieve(n, rec, n, dpg.ALGO_DPG)
+        assert (plan.probe, plan.n_runs) == (dpg.PROBE_LDS, 1 << 17)
+        src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
+        rids = synth.rids_permutation(n, seed, backend="torch", device=DEV)
+        out = ctx.retrieve(src, rids, algo=dpg.ALGO_DPG)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_option(dpg.OPT_DISTRIBUTE, 0)
+        ctx.set_option(dpg.OPT_PROBE, 0)
+    rids_h = rids.cpu().numpy()
+    src_h = src.cpu().numpy()
+    del src
+    step = 1 << 22
+    chunks = [(a, min(n, a + step)) for a in range(0, n, step)]
+    compare_chunks("retrieve 2^26 x 100 B, two-pass LDS probe", chunks,
+                   fetch=lambda c: out[c[0]:c[1]].cpu().numpy(),
+                   expect=lambda c: oracle.retrieve(src_h, rids_h[c[0]:c[1]]))
+    del rids, out
+    free_device()
+
+
 # ---------------------------------------------------------------------------
 # Key-pointer sort (Section 3)
 # ---------------------------------------------------------------------------

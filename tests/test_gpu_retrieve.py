@@ -78,6 +78,10 @@ VARIANTS = {
     # two partition passes and a two-pass gather (multi-pass DPG, Section 7)
     "dpg-two-pass": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS)),
     "dpg-two-pass-short-runs": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS, log2_run=1)),
+    # the same two passes with every run staged in LDS for the probe (run
+    # boundaries found from the sorted list; Phase III in one pass)
+    "dpg-two-pass-lds": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS, probe=dpg.PROBE_LDS)),
+    "dpg-two-pass-lds-short-runs": (dpg.ALGO_DPG, dict(dist=dpg.DIST_TWO_PASS, probe=dpg.PROBE_LDS, log2_run=1)),
     "auto": (dpg.ALGO_AUTO, {}),
 }
 
@@ -136,6 +140,45 @@ def test_partition_tile_option_takes_effect(ctx):
         assert ctx.plan_retrieve(65537, 100, 80000, dpg.ALGO_DPG).dist_tile == 32768
         ctx.set_option(dpg.OPT_LOG2_RUN, 5)  # 2049 runs (12-bit digits): 16384-rid tiles
         assert ctx.plan_retrieve(65537, 100, 80000, dpg.ALGO_DPG).dist_tile == 16384
+    finally:
+        configure(ctx)
+
+
+@pytest.mark.parametrize("variant", ["dpg-two-pass-lds", "dpg-two-pass", "dpg-cached"])
+def test_unchecked_out_of_range_rids_leave_valid_rows_exact(ctx, variant):
+    """Without the rid check, an rid outside the source gives an undefined
+    row but touches nothing outside the buffers: every row of a valid rid
+    still equals the oracle's (the two-pass distribute drops invalid rids in
+    its first pass and fills the slots it leaves)."""
+    n_src, n_rids, rec = 40000, 70001, 100
+    seed = synth.SEED_BASE + 77
+    src = synth.record_bytes(n_src, rec, seed)
+    rids = synth.rids_uniform(n_src, n_rids, seed)
+    bad = np.arange(0, n_rids, 97)
+    rids[bad] = np.where(bad % 2 == 0, n_src + bad, -1 - bad).astype(np.int32)
+    ok = np.ones(n_rids, dtype=bool)
+    ok[bad] = False
+    algo, opts = VARIANTS[variant]
+    configure(ctx, **opts)
+    try:
+        got = ctx.retrieve(torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV), algo=algo)
+        torch.cuda.synchronize()
+    finally:
+        configure(ctx)
+    assert np.array_equal(got.cpu().numpy()[ok], oracle.retrieve(src, rids[ok]))
+
+
+def test_two_pass_lds_plan(ctx):
+    """The LDS probe over two-pass runs: regions of at most 64 KiB (512
+    records of 100 B), 2^17 runs at 2^26 records, no intermediate array."""
+    configure(ctx, **VARIANTS["dpg-two-pass-lds"][1])
+    try:
+        p = ctx.plan_retrieve(1 << 26, 100, 1 << 26, dpg.ALGO_DPG)
+        assert (p.probe, p.distribute, p.log2_run, p.n_runs) == (dpg.PROBE_LDS, dpg.DIST_TWO_PASS, 9, 1 << 17)
+        q = ctx.plan_retrieve(1 << 26, 100, 1 << 26, dpg.ALGO_DPG)
+        configure(ctx, dist=dpg.DIST_TWO_PASS)
+        c = ctx.plan_retrieve(1 << 26, 100, 1 << 26, dpg.ALGO_DPG)
+        assert c.probe == dpg.PROBE_CACHED and q.workspace_bytes < c.workspace_bytes
     finally:
         configure(ctx)
 
