@@ -203,16 +203,8 @@ static void plan_dpg(RetrievePlan *p, int probe, int log2_run, int dist_tile, in
         p->part_nbits = std::max(1, bit_length((uint64_t)(p->n_runs - 1)));
         p->n_sample = std::max<int64_t>(1, std::min<int64_t>(M, kSampleFactor * p->n_runs));
         p->part_wide = true;
+        // (splitter buckets: tiles of at most 16384 rids)
         p->wide_per = M < kSmallTileRids ? 8 : 16;
-        // 1025..2048 runs: tiles of 32768 rids, so that a tile's segment per
-        // run averages 16 rids rather than 8 (at 2^26 rids of 100 B, 2048
-        // runs: 0.235 against 0.254 ms; at 1024 runs the 16384 tile is
-        // faster).  Not with the two-phase scatter, whose pass also records
-        // positions.
-        if (M >= kSmallTileRids && p->part_nbits == 11 && !want_scatter) p->wide_per = 32;
-        // a distribute tile asked for explicitly: 8192, 16384 or 32768 rids
-        if (dist_tile == 8192 || dist_tile == 16384 || (dist_tile == 32768 && !want_scatter))
-            p->wide_per = dist_tile / 1024;
         const PartPlan pp = plan_partition(M, p->part_nbits, 4, false, p->wide_per, true);
         p->dist_tile = pp.tile;
         p->n_tiles = pp.n_tiles;

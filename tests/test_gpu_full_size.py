@@ -37,20 +37,49 @@ def free_device():
 # ---------------------------------------------------------------------------
 # Retrieval (Section 2)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("algo", [dpg.ALGO_DPG, dpg.ALGO_DIRECT], ids=["dpg", "direct"])
-def test_retrieve_2p23x100B_full_oracle(ctx, algo):
+# (algorithm, Phase I flavour, expected distribute tile): the default
+# partition pass, splitter runs from a sample, the two-pass distribute and its
+# LDS probe, and direct retrieval
+# (2048 runs: log2 of the run length forced to 12)
+P23_VARIANTS = {
+    "dpg": (dpg.ALGO_DPG, 0, 0, 0, 16384),
+    "dpg-2048-runs": (dpg.ALGO_DPG, 0, 0, 12, 32768),
+    "dpg-sampled": (dpg.ALGO_DPG, dpg.DIST_SAMPLED, 0, 0, 16384),
+    "dpg-sampled-2048-runs": (dpg.ALGO_DPG, dpg.DIST_SAMPLED, 0, 12, 16384),
+    "dpg-two-pass": (dpg.ALGO_DPG, dpg.DIST_TWO_PASS, 0, 0, None),
+    "dpg-two-pass-lds": (dpg.ALGO_DPG, dpg.DIST_TWO_PASS, dpg.PROBE_LDS, 0, None),
+    "direct": (dpg.ALGO_DIRECT, 0, 0, 0, None),
+}
+
+
+@pytest.mark.parametrize("variant", list(P23_VARIANTS))
+def test_retrieve_2p23x100B_full_oracle(ctx, variant):
     """2^23 records of 100 B, a permutation: 839 MB of output (nontemporal
-    stores) and, for DPG, partition tiles of 16384 rids (16 per thread)."""
+    stores) and, for the one-pass DPG distribute, partition tiles of 16384
+    rids (16 per thread); every Phase I flavour at this size."""
+    algo, dist, probe, log2_run, tile = P23_VARIANTS[variant]
     n, rec = 1 << 23, 100
     seed = synth.SEED_BASE + 23
     src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
     rids = synth.rids_permutation(n, seed, backend="torch", device=DEV)
-    plan = ctx.plan_retrieve(n, rec, n, algo)
-    if algo == dpg.ALGO_DPG:
-        assert plan.dist_tile == 16384 and plan.distribute == dpg.DIST_PARTITION
+    ctx.set_option(dpg.OPT_DISTRIBUTE, dist)
+    ctx.set_option(dpg.OPT_PROBE, probe)
+    ctx.set_option(dpg.OPT_LOG2_RUN, log2_run)
+    try:
+        plan = ctx.plan_retrieve(n, rec, n, algo)
+        if tile is not None:
+            assert plan.dist_tile == tile
+        if dist:
+            assert plan.distribute == dist
+        if log2_run:
+            assert plan.n_runs == 2048
+        out = ctx.retrieve(src, rids, algo=algo)
+        torch.cuda.synchronize()
+    finally:
+        for opt in (dpg.OPT_DISTRIBUTE, dpg.OPT_PROBE, dpg.OPT_LOG2_RUN):
+            ctx.set_option(opt, 0)
     src_h, rids_h = src.cpu().numpy(), rids.cpu().numpy()
     assert np.array_equal(rids_h[:1000], synth.rids_permutation(n, seed, count=1000))
-    out = ctx.retrieve(src, rids, algo=algo)
     got = out.cpu().numpy()
     want = oracle.retrieve(src_h, rids_h)
     assert np.array_equal(got, want)
