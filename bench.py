@@ -138,24 +138,44 @@ def cpu_baseline(src_dev, rids_np, rec_bytes, target_s):
     dt = timed_oracle(lambda r: oracle.retrieve(src, r), [rids_np[:m]], 1)
     if dt < target_s and m < m_total:
         m = int(min(m_total, m * max(1.0, target_s / max(dt, 1e-3))))
-        dt = timed_oracle(lambda r: oracle.retrieve(src, r), [rids_np[:m]], 1)
     threads = host_threads()
     step = -(-m // (4 * threads))
     slices = [rids_np[a:min(m, a + step)] for a in range(0, m, step)]
-    dt_all = timed_oracle(lambda r: oracle.retrieve(src, r), slices, threads)
+    # medians of three runs each
+    dts = sorted(timed_oracle(lambda r: oracle.retrieve(src, r), [rids_np[:m]], 1) for _ in range(3))
+    dts_all = sorted(timed_oracle(lambda r: oracle.retrieve(src, r), slices, threads) for _ in range(3))
+    dt, dt_all = dts[1], dts_all[1]
     del src
-    cpu = platform.processor() or platform.machine()
     return {
         "value": round(m * rec_bytes / dt_all / 1e9, 3),
         "unit": "GB/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"first {m} of {m_total} rids over the full {rec_bytes}-byte source, cut into "
-                  f"{len(slices)} slices on {threads} threads: {dt_all:.2f} s ({cpu}; host reports "
-                  f"{os.cpu_count()} logical CPUs)",
+                  f"{len(slices)} slices on {threads} threads: median of 3 runs {dt_all:.2f} s ({host_desc()})",
         "single_core": {"value": round(m * rec_bytes / dt / 1e9, 3), "unit": "GB/s", "cores": 1,
-                        "sample": f"the same {m} rids on one thread: {dt:.2f} s"},
+                        "sample": f"the same {m} rids on one thread: median of 3 runs {dt:.2f} s"},
     }
+
+
+def host_desc() -> str:
+    """CPU model, logical CPUs and RAM of the host the oracle ran on."""
+    model = platform.processor() or platform.machine()
+    mem = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem = f", {int(line.split()[1]) / 2 ** 20:.0f} GiB RAM"
+                    break
+    except OSError:
+        pass
+    return f"{model}; host reports {os.cpu_count()} logical CPUs{mem}"
 
 
 NO_CPU = False  # --no-cpu: no oracle timings (their entries are null)
