@@ -228,6 +228,47 @@ def test_sort_1e8x100B_full_oracle(ctx):
     free_device()
 
 
+def test_sort_1e8x100B_full_key_passes_full_oracle(ctx):
+    """The benchmark's tied-prefix sort: the same 10^8 records of 100 B with
+    key bytes 0-3 drawn from 4096 values, so that groups of about 24,000
+    equal prefixes send the pairs through the full-key passes (the flag in
+    the workspace's first word shows it).  Both copy phases, every byte,
+    compared with the oracle group by group as above."""
+    n, rec = 100_000_000, 100
+    seed = synth.SEED_BASE + 2
+    src = synth.record_bytes(n, rec, seed, backend="torch", device=DEV)
+    pool = synth.record_bytes(4096, 4, seed, stream=synth.STREAM_MIX, backend="torch", device=DEV)
+    pick = synth.uniform_at(4096, torch.arange(n, device=DEV), seed, synth.STREAM_FK, backend="torch", device=DEV)
+    src[:, 0:4] = pool[pick]
+    del pool, pick
+    outs = []
+    for algo in (dpg.ALGO_DPG, dpg.ALGO_DIRECT):
+        ws = torch.empty(ctx.sort_workspace_bytes(n, rec, 0, 10, algo), dtype=torch.uint8, device=DEV)
+        dst, perm = ctx.sort_records(src, 0, 10, algo=algo, workspace=ws)
+        assert int(ws[:4].view(torch.int32).item()) == 1, "the full-key passes did not run"
+        outs.append((dst, perm))
+        del ws
+    src_h = src.cpu().numpy()
+    del src
+    order, starts = groups_by_small_key(src_h[:, 0] >> 2, 64)
+
+    def fetch(g):
+        a, b = int(starts[g]), int(starts[g + 1])
+        parts = []
+        for dst, perm in outs:
+            parts += [dst[a:b].cpu().numpy(), perm[a:b].cpu().numpy().astype(np.int64)]
+        return tuple(parts)
+
+    def expect(g):
+        sel = order[starts[g]:starts[g + 1]]
+        d, p = oracle.sort_records(src_h[sel], 0, 10)
+        return (d, sel[p]) * len(outs)
+
+    compare_chunks("sort 10^8 x 100 B, tied prefixes (dpg, direct)", range(64), fetch, expect)
+    del outs
+    free_device()
+
+
 # ---------------------------------------------------------------------------
 # Foreign-key joins (Section 4.2.1)
 # ---------------------------------------------------------------------------
