@@ -479,7 +479,6 @@ struct BatchRequestPlan {
     bool sortjoin = false;  // dimension-order join: stable passes over (fk, i), then the move of the fact rows
     bool move_dpg = false;  // dimension-order join: the fact rows move by the DPG chain (else one copy step)
     int passes = 0;         // dimension-order join: 8-bit stable passes over the foreign keys
-    int64_t items = 0;      // copy items (direct)
     size_t ws_bytes = 0;    // scratch of the steps
     int lg_run = 0, n_runs = 0;  // DPG chain: run length and count over the moved rows
     int32_t steps = 0;      // steps in the queue
@@ -629,8 +628,6 @@ static dpg_status plan_request(const dpg_ctx *ctx, const dpg_request &q, BatchRe
     }
     if (rp.algo == DPG_ALGO_DIRECT) {
         bp->direct = true;
-        const int tr = tile_rows_for((retrieve ? q.rec_bytes : q.fact_bytes + q.rec_bytes) / 4);
-        bp->items = (q.n + tr - 1) / tr;
         bp->steps = 1;
         return DPG_OK;
     }
@@ -927,13 +924,12 @@ static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &
 }
 
 dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const void *arena, size_t arena_bytes,
-                              bool *batchable, size_t *own_ws, size_t *batch_ws) {
+                              size_t *own_ws, size_t *batch_ws) {
     dpg_status st = validate_request(q, arena, arena_bytes);
     if (st != DPG_OK) return st;
     BatchRequestPlan bp;
     st = plan_request(ctx, q, &bp);
     if (st != DPG_OK) return st;
-    *batchable = true;
     *batch_ws = bp.ws_bytes;
     *own_ws = q.kind == DPG_REQ_RETRIEVE
                   ? dpg_retrieve_workspace_bytes(ctx, q.n_src, q.rec_bytes, q.n, (dpg_algo)q.algo)

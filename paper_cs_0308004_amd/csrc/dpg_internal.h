@@ -276,14 +276,14 @@ int xcd_remap_flag(const dpg_ctx *ctx);
 void scratch_init(dpg_ctx *ctx);
 
 // Validate and plan one request whose output will be placed later somewhere in
-// [arena, arena + arena_bytes) (the serving engine's arena): *batchable tells
-// whether the persistent batch launch can run all its work; *own_ws is the
+// [arena, arena + arena_bytes) (the serving engine's arena): *own_ws is the
 // workspace of its single-request entry point; *batch_ws the scratch its
-// steps need inside a graph batch (0 for direct work).
+// steps need inside a graph batch (0 for direct work).  Every valid request
+// can run inside the persistent batch launch.
 dpg_status plan_batch_request(const dpg_ctx *ctx, const dpg_request &q, const void *arena, size_t arena_bytes,
-                              bool *batchable, size_t *own_ws, size_t *batch_ws);
+                              size_t *own_ws, size_t *batch_ws);
 // Upload a batch into a bound batch graph's workspace and run it: replay the
-// captured graph, or (replay = false) launch its two kernels directly.
+// captured graph, or (replay = false) launch k_batch directly.
 dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32_t n, hipStream_t stream,
                               bool replay);
 

@@ -450,13 +450,12 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
     tk.req.dst = nullptr;
     tk.out_bytes = output_bytes(*req);
     tk.submit = Clock::now();
-    bool batchable = false;
     size_t own_ws = 0, batch_ws = 0;
     // the output will live somewhere in the arena: inputs must lie outside it
-    tk.status = plan_batch_request(s->ctx, tk.req, s->base, s->cfg.arena_bytes, &batchable, &own_ws, &batch_ws);
+    tk.status = plan_batch_request(s->ctx, tk.req, s->base, s->cfg.arena_bytes, &own_ws, &batch_ws);
     if (tk.status == DPG_OK) {
         const size_t max_batched = (size_t)(s->cfg.batch_max_kib > 0 ? s->cfg.batch_max_kib : 4096) << 10;
-        tk.batched = batchable && s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
+        tk.batched = s->cfg.max_batch_requests > 1 && tk.out_bytes <= max_batched;
         // direct work in a batch needs no workspace of its own; DPG steps
         // need scratch (enough for the single-request entry point too, which
         // runs a batch of one)
