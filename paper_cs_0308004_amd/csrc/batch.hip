@@ -345,7 +345,18 @@ __device__ __forceinline__ void sscan_item(const BatchDesc &d, int32_t *s_w) {
     __syncthreads();
     int32_t run = inc - total;
     for (int w = 0; w < wave; ++w) run += s_w[w];
-    for (t = 0; t < T; ++t) {
+    // eight tiles' counts loaded together, then replaced by their offsets
+    for (t = 0; t + 8 <= T; t += 8) {
+        int32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = c[(int64_t)(t + u) * kSortDigits + g];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            c[(int64_t)(t + u) * kSortDigits + g] = run;
+            run += v[u];
+        }
+    }
+    for (; t < T; ++t) {
         const int64_t at = (int64_t)t * kSortDigits + g;
         const int32_t v = c[at];
         c[at] = run;

@@ -167,6 +167,25 @@ def test_batch_dim_order_passes(ctx, n_dim_log2):
         assert np.array_equal(k[2].cpu().numpy(), want), i
 
 
+def test_batch_dim_order_large(ctx):
+    """Two dimension-order joins of 2^22 + 3 fact rows (1025 sort tiles, so
+    the count-matrix scan walks a long column) in one batch, with the DPG
+    and the direct move of the fact rows, Zipf(1.2) keys over 2^20
+    dimension rows: each output equals the oracle's."""
+    n, n_dim = (1 << 22) + 3, 1 << 20
+    dim = synth.dim_table(n_dim, seed=61, dim_bytes=16)
+    fact = synth.fact_table(n, n_dim, 1.2, seed=62)
+    want = oracle.fk_join_dim_order(fact, dim, 0)
+    d_t, f_t = torch.from_numpy(dim).to(DEV), torch.from_numpy(fact).to(DEV)
+    outs = [torch.empty((n, fact.shape[1] + dim.shape[1]), dtype=torch.uint8, device=DEV) for _ in range(2)]
+    reqs = [dpg.join_request(f_t, d_t, outs[0], 0, 1, dpg.ALGO_DPG),
+            dpg.join_request(f_t, d_t, outs[1], 0, 1, dpg.ALGO_DIRECT)]
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    for o in outs:
+        assert np.array_equal(o.cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("log2_run", [0, 2, 5])
 def test_batch_dpg_steps_many_runs(ctx, log2_run):
     """DPG requests inside the persistent launch with forced short runs (up to
