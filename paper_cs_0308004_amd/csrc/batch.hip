@@ -1,8 +1,8 @@
 // Batched execution of many retrieval / join requests of uneven size in ONE
 // launch of the persistent kernel k_batch.
 //
-// A fixed grid of workgroups pulls work items from a device queue (one atomic
-// counter).  An item is one tile of one step of one request:
+// A fixed grid of workgroups pulls work items from a device queue.  An item is
+// one tile of one step of one request:
 //
 //   OP_COPY     a tile of output rows A[ia] || B[ib] (retrieval: src[rid], no
 //               B; fact-order join: fact[i] || dim[fk_i]); the same step is
@@ -20,15 +20,19 @@
 // planned as DPG is the chain ZERO -> HIST -> SCAN -> SCATTER -> COPY (probe)
 // -> COPY (gather), the three phases of Section 2.1.  The queue lists every
 // request's first step, then every request's second step, and so on, so a
-// step rarely waits.  Before its first item of a step, a workgroup waits until
-// every item of the step before it (same request) has finished: those items
-// were taken from the queue earlier, by workgroups that are running, so the
-// wait ends; a bounded spin (a timeout flag in the header) keeps a kernel
-// from running on if that ever failed.  Each finished item bumps its step's
-// counter; the last item of a request's last step also writes the launch's
-// sequence number into the request's completion word, which lives in host
-// memory, so a host thread learns that the request is done while the batch
-// is still running.
+// step rarely waits.  Atomics on one word are serialized by the device (about
+// 20-30 ns each here), so the queue word is touched as little as possible:
+// when no step depends on another, workgroup b starts with item b and only
+// the items after the grid's first round come from the queue.  Before an
+// item, a workgroup waits until every item of the step this one depends on
+// (an earlier step of the same request) has finished: those items were taken
+// from the queue earlier, by workgroups that are running, so the wait ends;
+// a bounded spin (a timeout flag in the header) keeps a kernel from running
+// on if that ever failed.
+// Each finished item bumps its step's counter; the last item of a request's
+// last step also writes the launch's sequence number into the request's
+// completion word, which lives in host memory, so a host thread learns that
+// the request is done while the batch is still running.
 //
 // A dimension-order (DPG-Sort) join is the chain of its stable 8-bit passes
 // over the (fk, i) pairs (SHIST -> SSCAN -> SSCATTER per pass, low digit
@@ -104,9 +108,11 @@ struct BatchDesc {
 struct BatchHeader {
     int64_t total_items;
     int32_t n_desc;
-    uint32_t seq;      // launch sequence number, written into the completion words
-    int32_t timeout;   // set when a dependency wait gave up (never in a correct run)
-    uint32_t queue;    // next work item (uploaded as 0)
+    uint32_t seq;         // launch sequence number, written into the completion words
+    int32_t timeout;      // set when a dependency wait gave up (never in a correct run)
+    uint32_t queue;       // work items taken from the queue (uploaded as 0)
+    int32_t no_deps;      // 1: no step waits on another (workgroup b then starts with item b)
+    int32_t pad;
 };
 
 constexpr int kBatchThreads = 256;
@@ -146,22 +152,24 @@ __device__ __forceinline__ void batch_copy(const BatchDesc &d, const int32_t *s_
     const auto *B = as_global((const E *)(d.b ? d.b : d.a));
     auto *o = as_global((E *)d.out + row0 * W);
     const int total = rows * W;
-    for (int e0 = 0; e0 < total; e0 += kBatchThreads * kBatchPer) {
-        int64_t off[kBatchPer];
-        bool in_a[kBatchPer];
+    // 16 dwords or 8 16-byte vectors in flight per lane
+    constexpr int PER = VEC == 4 ? kBatchPer / 2 : kBatchPer;
+    for (int e0 = 0; e0 < total; e0 += kBatchThreads * PER) {
+        int64_t off[PER];
+        bool in_a[PER];
 #pragma unroll
-        for (int k = 0; k < kBatchPer; ++k) {
+        for (int k = 0; k < PER; ++k) {
             const int e = min(e0 + (int)threadIdx.x + k * kBatchThreads, total - 1);
             const int j = W == 1 ? e : (int)__umulhi((uint32_t)e, d.magic);
             const int w = e - j * W;
             in_a[k] = w < wa;
             off[k] = in_a[k] ? (int64_t)s_ia[j] * wa + w : (int64_t)s_ib[j] * wb + (w - wa);
         }
-        E v[kBatchPer];
+        E v[PER];
 #pragma unroll
-        for (int k = 0; k < kBatchPer; ++k) v[k] = (in_a[k] ? A : B)[off[k]];
+        for (int k = 0; k < PER; ++k) v[k] = (in_a[k] ? A : B)[off[k]];
 #pragma unroll
-        for (int k = 0; k < kBatchPer; ++k) {
+        for (int k = 0; k < PER; ++k) {
             const int e = e0 + threadIdx.x + k * kBatchThreads;
             if (e < total) {
                 if constexpr (NT) __builtin_nontemporal_store(v[k], o + e);
@@ -364,27 +372,34 @@ __device__ __forceinline__ void sscan_item(const BatchDesc &d, int32_t *s_w) {
     }
 }
 
+// Two passes over the tile's rows, so that no element stays in registers
+// across the barrier (the persistent kernel's register budget is the largest
+// step's): the first counts each wave's digits, row by row; after the
+// per-digit prefix over the waves, the second reads the rows again (from the
+// cache), ranks each element among the equal digits before it and writes
+// (key, value) to its place.
 __device__ __forceinline__ void sscatter_item(const BatchDesc &d, int64_t t, int32_t *s_cnt) {
     constexpr int PER = kBatchDistTile / kBatchThreads;
+    constexpr int ROWS = 4;  // rows loaded together
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int j = threadIdx.x; j < (kBatchThreads / 64) * kSortDigits; j += kBatchThreads) s_cnt[j] = 0;
     __syncthreads();
     int32_t *mine = s_cnt + wave * kSortDigits;
     const int64_t i0 = t * kBatchDistTile + wave * 64 * PER + lane;
-    uint32_t key[PER], val[PER];
-    int32_t rank[PER];
+    for (int k0 = 0; k0 < PER; k0 += ROWS) {
+        uint32_t key[ROWS];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        const int64_t i = i0 + k * 64;
-        const bool valid = i < d.n_rows;
-        key[k] = valid ? sort_key(d, i) : 0u;
-        val[k] = valid ? (d.vals_in ? as_global(d.vals_in)[i] : (uint32_t)i) : 0u;
-        const uint32_t g = (key[k] >> d.shift) & 255u;
-        const uint64_t peers = match_lanes(g, 8, __ballot(valid));
-        const uint64_t below = peers & lanemask_lt();
-        const int32_t head = valid ? mine[g] : 0;
-        rank[k] = valid ? head + __popcll(below) : -1;
-        if (valid && below == 0) mine[g] = head + __popcll(peers);
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = i0 + (k0 + k) * 64;
+            key[k] = i < d.n_rows ? sort_key(d, i) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const bool valid = i0 + (k0 + k) * 64 < d.n_rows;
+            const uint32_t g = (key[k] >> d.shift) & 255u;
+            const uint64_t peers = match_lanes(g, 8, __ballot(valid));
+            if (valid && (peers & lanemask_lt()) == 0) mine[g] += __popcll(peers);
+        }
     }
     __syncthreads();
     // per digit: exclusive prefix over the waves
@@ -399,13 +414,30 @@ __device__ __forceinline__ void sscatter_item(const BatchDesc &d, int64_t t, int
     }
     __syncthreads();
     const auto *c = as_global(d.cnt);
+    for (int k0 = 0; k0 < PER; k0 += ROWS) {
+        uint32_t key[ROWS], val[ROWS];
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-        if (rank[k] < 0) continue;
-        const uint32_t g = (key[k] >> d.shift) & 255u;
-        const int64_t pos = (int64_t)c[t * kSortDigits + g] + mine[g] + rank[k];
-        d.keys_out[pos] = key[k];
-        d.vals_out[pos] = val[k];
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = i0 + (k0 + k) * 64;
+            const bool valid = i < d.n_rows;
+            key[k] = valid ? sort_key(d, i) : 0u;
+            val[k] = valid ? (d.vals_in ? as_global(d.vals_in)[i] : (uint32_t)i) : 0u;
+        }
+#pragma unroll
+        for (int k = 0; k < ROWS; ++k) {
+            const int64_t i = i0 + (k0 + k) * 64;
+            const bool valid = i < d.n_rows;
+            const uint32_t g = (key[k] >> d.shift) & 255u;
+            const uint64_t peers = match_lanes(g, 8, __ballot(valid));
+            const uint64_t below = peers & lanemask_lt();
+            const int32_t head = valid ? mine[g] : 0;
+            if (valid && below == 0) mine[g] = head + __popcll(peers);
+            if (valid) {
+                const int64_t pos = (int64_t)c[t * kSortDigits + g] + head + __popcll(below);
+                d.keys_out[pos] = key[k];
+                d.vals_out[pos] = val[k];
+            }
+        }
     }
 }
 
@@ -417,9 +449,26 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
     const int64_t total_items = hdr->total_items;
     const int n_desc = hdr->n_desc;
     const uint32_t seq = hdr->seq;
+    // Without dependencies workgroup b starts with item b: no workgroup ever
+    // waits, so an item held by a workgroup not yet running delays nobody,
+    // and the grid's first round takes no atomic.  The queue hands out the
+    // items after the first round (or all of them when steps depend on each
+    // other, so that every item is taken by a running workgroup, in order).
+    // With dependencies a quarter of the grid works: the waits between steps
+    // leave most workgroups idle anyway, and fewer of them polling and
+    // taking items run the chains faster (measured: 2^20 DPG retrievals in
+    // one batch, a batch of 64 DPG retrievals of 2^14 records).
+    const int64_t first_dyn = hdr->no_deps ? (int64_t)gridDim.x : 0;
+    bool first = hdr->no_deps != 0;
+    if (!hdr->no_deps && blockIdx.x >= (gridDim.x + 3) / 4) return;
     for (;;) {
         if (threadIdx.x == 0) {
-            const int64_t item = (int64_t)atomicAdd(&hdr->queue, 1u);
+            int64_t item;
+            if (first) {
+                item = blockIdx.x < total_items ? (int64_t)blockIdx.x : total_items;
+            } else {
+                item = first_dyn + (int64_t)atomicAdd(&hdr->queue, 1u);
+            }
             s_item = item;
             int r = -1;
             if (item < total_items) {
@@ -436,8 +485,10 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
                 if (dep >= 0) {
                     const uint32_t need = (uint32_t)descs[dep].n_items;
                     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                    int pause = 1;
                     while (__hip_atomic_load(&descs[dep].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                        __builtin_amdgcn_s_sleep(2);
+                        for (int k = 0; k < pause; ++k) __builtin_amdgcn_s_sleep(8);
+                        pause = pause < 16 ? 2 * pause : 16;
                         if (__builtin_amdgcn_s_memrealtime() - t0 > kBatchWaitTicks) {
                             atomicOr(&hdr->timeout, 1);
                             break;
@@ -449,10 +500,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
             s_desc = r;
         }
         __syncthreads();
+        first = false;
         const int64_t item = s_item;
         const int r = s_desc;
         if (item >= total_items) break;  // queue exhausted: uniform exit
-        const BatchDesc d = descs[r];
+        const BatchDesc &d = descs[r];  // fields read where used (scalar loads), not held in registers
         const int64_t local = item - d.item_start;
         switch (d.op) {
             case OP_COPY: copy_item(d, local, s_mem, s_mem + kBatchMaxTileRows); break;
@@ -901,6 +953,10 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     hdr->seq = 0;
     hdr->timeout = 0;
     hdr->queue = 0;
+    hdr->no_deps = 1;
+    for (const BatchDesc &d : *descs)
+        if (d.dep >= 0) hdr->no_deps = 0;
+    hdr->pad = 0;
 }
 
 static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans) {
@@ -923,7 +979,17 @@ static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<
     return b;
 }
 
-static int batch_grid(const dpg_ctx *ctx) { return ctx->n_cu * 4; }
+// The persistent grid: as many workgroups as fit on the device at once (more
+// would only start as others exit, with the queue already drained).
+static int batch_grid(const dpg_ctx *ctx) {
+    static const int per_cu = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, kBatchThreads, 0) != hipSuccess || nb < 1)
+            nb = 2;
+        return nb;
+    }();
+    return ctx->n_cu * per_cu;
+}
 
 static dpg_status launch_batch_kernel(dpg_ctx *ctx, char *w, const BatchLayout &L, double bytes,
                                       uint32_t *host_done, hipStream_t stream) {
