@@ -466,6 +466,8 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
             int64_t item;
             if (first) {
                 item = blockIdx.x < total_items ? (int64_t)blockIdx.x : total_items;
+            } else if (first_dyn >= total_items) {
+                item = total_items;  // the first round took every item: no atomic
             } else {
                 item = first_dyn + (int64_t)atomicAdd(&hdr->queue, 1u);
             }
@@ -584,11 +586,13 @@ static dpg_status validate_request(const dpg_request &q, const void *arena = nul
     return DPG_ERR_INVALID_ARG;
 }
 
-// Output rows per work item: about kBatchItemWords dwords, and a multiple of
-// 256 / gcd(row bytes, 256) rows so that every item's output starts on a
-// 256-byte boundary of the (256-byte aligned) output.
-static int tile_rows_for(int words) {
-    int rows = kBatchItemWords / words;
+// Output rows per work item: about item_words dwords (kBatchItemWords or
+// more), and a multiple of 256 / gcd(row bytes, 256) rows so that every
+// item's output starts on a 256-byte boundary of the (256-byte aligned)
+// output.
+static int tile_rows_for(int words, int64_t item_words = kBatchItemWords) {
+    int64_t rows64 = item_words / words;
+    int rows = (int)(rows64 < kBatchMaxTileRows ? rows64 : kBatchMaxTileRows);
     if (rows < 1) rows = 1;
     if (rows > kBatchMaxTileRows) rows = kBatchMaxTileRows;
     int a = words * 4, b = 256;
@@ -747,9 +751,9 @@ static dpg_status plan_batch(const dpg_ctx *ctx, const dpg_request *reqs, int32_
     return DPG_OK;
 }
 
-static void copy_shape(BatchDesc &d) {
+static void copy_shape(BatchDesc &d, int64_t item_words = kBatchItemWords) {
     d.op = OP_COPY;
-    d.tile_rows = tile_rows_for(d.wa + d.wb);
+    d.tile_rows = tile_rows_for(d.wa + d.wb, item_words);
     const uintptr_t al = (uintptr_t)d.a | (uintptr_t)d.b | (uintptr_t)d.out;
     d.vec = (d.wa % 4 == 0 && d.wb % 4 == 0 && al % 16 == 0) ? 4 : 1;
     const uint64_t we = (uint64_t)(d.wa + d.wb) / (uint64_t)d.vec;
@@ -807,7 +811,8 @@ static void dpg_chain(const BatchDesc &base, const BatchRequestPlan &p, int64_t 
 // The steps of the batch, in queue order: every request's first step, then
 // every request's second step, ...; scratch[i] is request i's scratch.
 static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans,
-                        const std::vector<char *> &scratch, std::vector<BatchDesc> *descs, BatchHeader *hdr) {
+                        const std::vector<char *> &scratch, int64_t workers, std::vector<BatchDesc> *descs,
+                        BatchHeader *hdr) {
     descs->clear();
     std::vector<std::vector<BatchDesc>> chains(n);
     int max_steps = 0;
@@ -937,6 +942,24 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     // queue order: step k of every request, for k = 0, 1, ...
     std::vector<int32_t> prev_index(n, -1);
     int64_t items = 0;
+    // Copy items sized so that the batch's copy work spreads over about one
+    // item per working workgroup: each item taken from the queue costs a
+    // serialized atomic, while a workgroup copies a larger item as fast.
+    bool deps = false;
+    double copy_words = 0;
+    for (const auto &chain : chains) {
+        deps |= chain.size() > 1;
+        for (const BatchDesc &d : chain)
+            if (d.op == OP_COPY) copy_words += (double)d.n_rows * (d.wa + d.wb);
+    }
+    // (without dependencies a little under one item per workgroup, so that
+    // the first round usually takes every item)
+    const double working = deps ? (double)((workers + 3) / 4) : 0.8 * (double)workers;
+    const int64_t item_words = std::max<int64_t>(kBatchItemWords, (int64_t)(copy_words / std::max(working, 1.0)));
+    if (item_words > kBatchItemWords)
+        for (auto &chain : chains)
+            for (BatchDesc &d : chain)
+                if (d.op == OP_COPY) copy_shape(d, item_words);
     for (int k = 0; k < max_steps; ++k) {
         for (int32_t i = 0; i < n; ++i) {
             if ((int)chains[i].size() <= k) continue;
@@ -1070,7 +1093,7 @@ dpg_status dpg_batch_run(dpg_ctx *ctx, const dpg_request *reqs, int32_t n, void 
     for (int32_t i = 0; i < n; ++i) scratch[i] = w + L.req_off[i];
     std::vector<BatchDesc> descs;
     BatchHeader hdr;
-    build_descs(reqs, n, plans, scratch, &descs, &hdr);
+    build_descs(reqs, n, plans, scratch, batch_grid(ctx), &descs, &hdr);
     if (hdr.total_items > 0) {
         // header and steps in one copy (pageable source: staged before
         // hipMemcpyAsync returns)
@@ -1167,7 +1190,7 @@ dpg_status batch_graph_launch(dpg_batch_graph *g, const dpg_request *reqs, int32
     if (n == 0) return DPG_OK;
     std::vector<BatchDesc> descs;
     BatchHeader hdr;
-    build_descs(reqs, n, plans, scratch, &descs, &hdr);
+    build_descs(reqs, n, plans, scratch, batch_grid(g->ctx), &descs, &hdr);
     hdr.seq = ++g->seq;
     if (hdr.seq == 0) hdr.seq = ++g->seq;  // 0 is "never launched"
     // the staging buffer may still feed the previous launch's upload
