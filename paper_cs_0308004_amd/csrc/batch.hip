@@ -112,7 +112,7 @@ struct BatchHeader {
     int32_t timeout;      // set when a dependency wait gave up (never in a correct run)
     uint32_t queue;       // work items taken from the queue (uploaded as 0)
     int32_t no_deps;      // 1: no step waits on another (workgroup b then starts with item b)
-    int32_t pad;
+    int32_t n_work;       // workgroups that take items when steps depend on each other
 };
 
 constexpr int kBatchThreads = 256;
@@ -454,13 +454,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
     // and the grid's first round takes no atomic.  The queue hands out the
     // items after the first round (or all of them when steps depend on each
     // other, so that every item is taken by a running workgroup, in order).
-    // With dependencies a quarter of the grid works: the waits between steps
-    // leave most workgroups idle anyway, and fewer of them polling and
-    // taking items run the chains faster (measured: 2^20 DPG retrievals in
-    // one batch, a batch of 64 DPG retrievals of 2^14 records).
+    // With dependencies only the first n_work workgroups (a quarter to a
+    // half of the grid, by the widest step) take items: the waits between
+    // steps leave most workgroups idle anyway, and every workgroup that
+    // polls and takes items from the queue costs its atomics.
     const int64_t first_dyn = hdr->no_deps ? (int64_t)gridDim.x : 0;
     bool first = hdr->no_deps != 0;
-    if (!hdr->no_deps && blockIdx.x >= (gridDim.x + 3) / 4) return;
+    if (!hdr->no_deps && (int)blockIdx.x >= hdr->n_work) return;
     for (;;) {
         if (threadIdx.x == 0) {
             int64_t item;
@@ -947,14 +947,23 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     // serialized atomic, while a workgroup copies a larger item as fast.
     bool deps = false;
     double copy_words = 0;
+    std::vector<int64_t> step_items(max_steps, 0);  // items of step k over all requests
     for (const auto &chain : chains) {
         deps |= chain.size() > 1;
-        for (const BatchDesc &d : chain)
-            if (d.op == OP_COPY) copy_words += (double)d.n_rows * (d.wa + d.wb);
+        for (size_t k = 0; k < chain.size(); ++k) {
+            step_items[k] += chain[k].n_items;
+            if (chain[k].op == OP_COPY) copy_words += (double)chain[k].n_rows * (chain[k].wa + chain[k].wb);
+        }
     }
+    // With dependencies the widest step (at the default item size) decides
+    // how many workgroups work: a quarter of the grid for narrow chains, up
+    // to a half for wide ones (measured on single 2^16- and 2^20-row DPG
+    // retrievals and a batch of 64 DPG retrievals of 2^14 rows).
+    const int64_t widest = step_items.empty() ? 0 : *std::max_element(step_items.begin(), step_items.end());
+    const int32_t n_work = (int32_t)std::min<int64_t>(std::max<int64_t>(widest, (workers + 3) / 4), (workers + 1) / 2);
     // (without dependencies a little under one item per workgroup, so that
     // the first round usually takes every item)
-    const double working = deps ? (double)((workers + 3) / 4) : 0.8 * (double)workers;
+    const double working = deps ? (double)n_work : 0.8 * (double)workers;
     const int64_t item_words = std::max<int64_t>(kBatchItemWords, (int64_t)(copy_words / std::max(working, 1.0)));
     if (item_words > kBatchItemWords)
         for (auto &chain : chains)
@@ -979,7 +988,7 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     hdr->no_deps = 1;
     for (const BatchDesc &d : *descs)
         if (d.dep >= 0) hdr->no_deps = 0;
-    hdr->pad = 0;
+    hdr->n_work = deps ? n_work : (int32_t)workers;
 }
 
 static double batch_bytes(const dpg_request *reqs, int32_t n, const std::vector<BatchRequestPlan> &plans) {
