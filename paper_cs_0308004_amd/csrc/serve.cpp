@@ -179,51 +179,73 @@ static bool finish_done_requests(dpg_server *s, Slot &sl) {
     return any;
 }
 
-// Launch `batch` on the slot: batched tickets together in one persistent
-// launch (graph replay when available), or one unbatched ticket through its
-// single-request entry point with the workspace reserved at admission.
-static dpg_status launch_on_slot(dpg_server *s, Slot &sl, std::vector<uint64_t> &batch) {
-    dpg_ctx *ctx = s->ctx;
-    dpg_status st = DPG_OK;
+// What a slot's launch needs, copied out of the tickets under the server lock
+// so that the HIP calls can run without it.
+struct LaunchWork {
+    bool single = false;        // one ticket through its single-request entry point
+    dpg_request q{};            // (single) the request
+    char *w = nullptr;          // (single) its workspace
+    size_t wb = 0;
+    std::vector<dpg_request> reqs;  // (batch) the requests, in ticket order
+};
+
+// Take `batch` onto the slot (under the lock): batched tickets together in
+// one persistent launch (graph replay when available), or one unbatched
+// ticket through its single-request entry point with the workspace reserved
+// at admission.
+static LaunchWork prepare_launch(dpg_server *s, Slot &sl, const std::vector<uint64_t> &batch) {
+    LaunchWork w;
     const Ticket &first = s->tickets[batch[0]];
     // A batch of one runs through the single-request entry point (no
     // descriptor upload), borrowing the idle slot's descriptor workspace.
     const bool alone = first.batched && batch.size() == 1 && (first.has_ws || first.own_ws <= sl.batch_ws_bytes);
     if (!first.batched || alone) {
-        const dpg_request &q = first.req;
+        w.single = true;
+        w.q = first.req;
         const bool slot_ws = alone && !first.has_ws;
-        char *w = slot_ws ? s->base + sl.batch_ws_off : (first.has_ws ? s->base + first.ws_off : nullptr);
-        const size_t wb = slot_ws ? sl.batch_ws_bytes : first.ws_bytes;
-        st = q.kind == DPG_REQ_RETRIEVE
-                 ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w, wb, (dpg_algo)q.algo, 0,
-                                sl.stream)
-                 : dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
-                               (dpg_join_order)q.order, w, wb, (dpg_algo)q.algo, 0, sl.stream);
+        w.w = slot_ws ? s->base + sl.batch_ws_off : (first.has_ws ? s->base + first.ws_off : nullptr);
+        w.wb = slot_ws ? sl.batch_ws_bytes : first.ws_bytes;
     } else {
-        std::vector<dpg_request> reqs;
-        reqs.reserve(batch.size());
+        w.reqs.reserve(batch.size());
         for (uint64_t t : batch) {
             const Ticket &tk = s->tickets[t];
             dpg_request q = tk.req;
             // the scratch of a DPG request's steps, reserved at admission
             q.workspace = tk.has_ws ? s->base + tk.ws_off : nullptr;
             q.workspace_bytes = tk.has_ws ? tk.ws_bytes : 0;
-            reqs.push_back(q);
+            w.reqs.push_back(q);
         }
-        const int32_t n = (int32_t)reqs.size();
-        // a graph replay costs more host time than launching the kernel
-        // (about 16 us more per launch here): it is used for batches that
-        // amortize it
-        st = batch_graph_launch(sl.graph, reqs.data(), n, sl.stream,
-                                s->cfg.use_graph != 0 && n >= kGraphMinRequests);
     }
-    if (st != DPG_OK) return st;
-    if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
     sl.tickets = batch;
     sl.batch_launch = first.batched && !alone;
     sl.busy = true;
     s->batches++;
     for (uint64_t t : batch) s->tickets[t].state = T_RUNNING;
+    return w;
+}
+
+// The slot's HIP work (without the server lock: only the scheduler thread
+// touches the context, the slots and their streams).
+static dpg_status launch_work(dpg_server *s, Slot &sl, const LaunchWork &w) {
+    dpg_ctx *ctx = s->ctx;
+    dpg_status st;
+    if (w.single) {
+        const dpg_request &q = w.q;
+        st = q.kind == DPG_REQ_RETRIEVE
+                 ? dpg_retrieve(ctx, q.src, q.n_src, q.rec_bytes, q.rids, q.n, q.dst, w.w, w.wb, (dpg_algo)q.algo, 0,
+                                sl.stream)
+                 : dpg_fk_join(ctx, q.fact, q.n, q.fact_bytes, q.fk_offset, q.src, q.n_src, q.rec_bytes, q.dst,
+                               (dpg_join_order)q.order, w.w, w.wb, (dpg_algo)q.algo, 0, sl.stream);
+    } else {
+        const int32_t n = (int32_t)w.reqs.size();
+        // a graph replay costs more host time than launching the kernel
+        // (about 16 us more per launch here): it is used for batches that
+        // amortize it
+        st = batch_graph_launch(sl.graph, w.reqs.data(), n, sl.stream,
+                                s->cfg.use_graph != 0 && n >= kGraphMinRequests);
+    }
+    if (st != DPG_OK) return st;
+    if (hipEventRecord(sl.event, sl.stream) != hipSuccess) return DPG_ERR_HIP;
     return DPG_OK;
 }
 
@@ -321,14 +343,19 @@ static void scheduler(dpg_server *s) {
             const std::vector<size_t> take = select_launch(flags, s->cfg.max_batch_requests);
             for (size_t k : take) batch.push_back(s->admitted[k]);
             for (size_t k = take.size(); k-- > 0;) s->admitted.erase(s->admitted.begin() + (std::ptrdiff_t)take[k]);
-            const auto t_launch = Clock::now();
             ++busy;
-            const dpg_status st = launch_on_slot(s, sl, batch);
-            s->launch_s += std::chrono::duration<double>(Clock::now() - t_launch).count();
-            if (st != DPG_OK) {
-                sl.tickets = batch;
-                finish_batch(s, sl, st);
-            }
+            const LaunchWork work = prepare_launch(s, sl, batch);
+            // Submitters are not held up by the launch's host work, so the
+            // next launch finds the requests that arrived meanwhile (with the
+            // lock held they came one per launch, and saturated servers
+            // launched batches of one).
+            lk.unlock();
+            const auto t_launch = Clock::now();
+            const dpg_status st = launch_work(s, sl, work);
+            const double dt = std::chrono::duration<double>(Clock::now() - t_launch).count();
+            lk.lock();
+            s->launch_s += dt;
+            if (st != DPG_OK) finish_batch(s, sl, st);
             changed = true;
         }
         if (changed) s->done_cv.notify_all();
