@@ -482,8 +482,9 @@ int32_t dpg_batch_graph_request_done(const dpg_batch_graph *graph, int32_t reque
 void dpg_batch_graph_destroy(dpg_batch_graph *graph);
 
 /* ------------------------------------------------------------------------- */
-/* Device-memory arena: first-fit allocator with coalescing over an address   */
-/* range the caller owns.  Host bookkeeping only (never touches the memory).  */
+/* Device-memory arena: best-fit allocator with coalescing over an address    */
+/* range the caller owns (the smallest free block that fits, the lowest among */
+/* equals; O(log n) per call).  Host bookkeeping only (never touches memory). */
 /* The serving engine carves request outputs and workspaces out of one.       */
 /* ------------------------------------------------------------------------- */
 typedef struct dpg_arena dpg_arena;

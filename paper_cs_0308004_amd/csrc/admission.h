@@ -1,4 +1,4 @@
-// Host-only pieces of the serving engine that need no device: the first-fit
+// Host-only pieces of the serving engine that need no device: the best-fit
 // arena allocator and the admission rule.  Kept free of HIP so that they can
 // be built and tested on their own.
 #pragma once
@@ -7,35 +7,38 @@
 #include <cstddef>
 #include <iterator>
 #include <map>
+#include <set>
+#include <utility>
 #include <vector>
 
 namespace dpg {
 
-// First-fit allocator over [0, size) with coalescing; block lengths are
-// rounded up to `align`.
+// Best-fit allocator over [0, size) with coalescing; block lengths are
+// rounded up to `align`.  A request takes the smallest free block that holds
+// it (the lowest such block among equals), found in O(log n) through an index
+// of the free blocks by length: a serving arena holds thousands of small
+// blocks, and a first-fit walk over the holes in address order cost the
+// scheduler most of its time under load.
 class Arena {
    public:
     Arena(size_t size, size_t align) : size_(size), align_(align) {
-        if (size_ > 0) free_[0] = size_;
+        if (size_ > 0) add_free(0, size_);
     }
     size_t rounded(size_t bytes) const { return (std::max<size_t>(bytes, 1) + align_ - 1) / align_ * align_; }
     // returns false when no free block fits
     bool alloc(size_t bytes, size_t *off) {
         const size_t need = rounded(bytes);
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= need) {
-                *off = it->first;
-                const size_t rest = it->second - need;
-                const size_t at = it->first;
-                free_.erase(it);
-                if (rest) free_[at + need] = rest;
-                used_[at] = need;
-                in_use_ += need;
-                high_water_ = std::max(high_water_, in_use_);
-                return true;
-            }
-        }
-        return false;
+        auto it = by_len_.lower_bound({need, 0});
+        if (it == by_len_.end()) return false;
+        const size_t at = it->second, len = it->first;
+        by_len_.erase(it);
+        free_.erase(at);
+        if (len > need) add_free(at + need, len - need);
+        *off = at;
+        used_[at] = need;
+        in_use_ += need;
+        high_water_ = std::max(high_water_, in_use_);
+        return true;
     }
     bool release(size_t off) {
         auto u = used_.find(off);
@@ -46,6 +49,7 @@ class Arena {
         auto next = free_.lower_bound(start);
         if (next != free_.end() && start + len == next->first) {
             len += next->second;
+            by_len_.erase({next->second, next->first});
             next = free_.erase(next);
         }
         if (next != free_.begin()) {
@@ -53,27 +57,29 @@ class Arena {
             if (prev->first + prev->second == start) {
                 start = prev->first;
                 len += prev->second;
+                by_len_.erase({prev->second, prev->first});
                 free_.erase(prev);
             }
         }
-        free_[start] = len;
+        add_free(start, len);
         return true;
     }
     size_t size() const { return size_; }
     size_t in_use() const { return in_use_; }
     size_t high_water() const { return high_water_; }
-    size_t largest_free() const {
-        size_t m = 0;
-        for (auto &f : free_) m = std::max(m, f.second);
-        return m;
-    }
+    size_t largest_free() const { return by_len_.empty() ? 0 : by_len_.rbegin()->first; }
     size_t free_blocks() const { return free_.size(); }
 
    private:
+    void add_free(size_t at, size_t len) {
+        free_[at] = len;
+        by_len_.insert({len, at});
+    }
     size_t size_, align_;
     size_t in_use_ = 0, high_water_ = 0;
-    std::map<size_t, size_t> free_;  // offset -> length
-    std::map<size_t, size_t> used_;  // offset -> length
+    std::map<size_t, size_t> free_;                // offset -> length
+    std::set<std::pair<size_t, size_t>> by_len_;   // (length, offset) of every free block
+    std::map<size_t, size_t> used_;                // offset -> length
 };
 
 // What admission does with the request at the head of the queue.

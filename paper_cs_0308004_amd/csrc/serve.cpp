@@ -2,7 +2,7 @@
 // HBM budget.
 //
 //   * Arena: the caller hands the server one device region (the budget); a
-//     first-fit allocator with coalescing carves request outputs and batch
+//     best-fit allocator with coalescing carves request outputs and batch
 //     workspaces out of it, so admission accounts for every byte the server
 //     uses.
 //   * Admission: requests are admitted in arrival order (head-of-line order,
@@ -79,6 +79,10 @@ struct Slot {
     bool busy = false;
     bool batch_launch = false;      // tickets run as one persistent batch (per-request completion words)
     std::vector<uint64_t> tickets;  // in the order of the launched request array
+    std::vector<uint8_t> seen_done; // (batch) completion word already seen, per ticket
+    std::vector<size_t> newly_done; // (batch) tickets whose completion word the last poll found set
+    hipError_t polled = hipErrorNotReady;  // the last poll's event query
+    Clock::time_point poll_time;           // and when it was taken
     dpg_batch_graph *graph = nullptr;
     size_t batch_ws_off = 0, batch_ws_bytes = 0;  // descriptors of a batch of direct work
 };
@@ -154,29 +158,27 @@ static void finish_ticket(dpg_server *s, uint64_t t, dpg_status st, Clock::time_
 
 // The slot's launch has ended (its stream event): every ticket not yet
 // finished is, and the slot is free.
-static void finish_batch(dpg_server *s, Slot &sl, dpg_status st) {
-    const auto now = Clock::now();
+static void finish_batch(dpg_server *s, Slot &sl, dpg_status st, Clock::time_point now) {
     for (uint64_t t : sl.tickets) finish_ticket(s, t, st, now);
     sl.tickets.clear();
     sl.busy = false;
     sl.batch_launch = false;
 }
 
-// Requests of a running persistent batch whose completion word is set are
-// finished before the rest of the batch.
-static bool finish_done_requests(dpg_server *s, Slot &sl) {
-    if (!sl.batch_launch) return false;
-    bool any = false;
-    const auto now = Clock::now();
-    for (size_t i = 0; i < sl.tickets.size(); ++i) {
-        auto it = s->tickets.find(sl.tickets[i]);
-        if (it == s->tickets.end() || it->second.finished) continue;
-        if (dpg_batch_graph_request_done(sl.graph, (int32_t)i)) {
-            finish_ticket(s, sl.tickets[i], DPG_OK, now);
-            any = true;
-        }
-    }
-    return any;
+// Polls a busy slot (without the server lock: only the scheduler thread
+// touches the slots): the requests of a running persistent batch whose
+// completion word is newly set, which finish before the rest of the batch,
+// then the slot's event.
+static void poll_slot(Slot &sl) {
+    sl.newly_done.clear();
+    if (sl.batch_launch)
+        for (size_t i = 0; i < sl.tickets.size(); ++i)
+            if (!sl.seen_done[i] && dpg_batch_graph_request_done(sl.graph, (int32_t)i)) {
+                sl.seen_done[i] = 1;
+                sl.newly_done.push_back(i);
+            }
+    sl.polled = hipEventQuery(sl.event);
+    sl.poll_time = Clock::now();
 }
 
 // What a slot's launch needs, copied out of the tickets under the server lock
@@ -217,6 +219,7 @@ static LaunchWork prepare_launch(dpg_server *s, Slot &sl, const std::vector<uint
         }
     }
     sl.tickets = batch;
+    sl.seen_done.assign(batch.size(), 0);
     sl.batch_launch = first.batched && !alone;
     sl.busy = true;
     s->batches++;
@@ -254,16 +257,23 @@ static void scheduler(dpg_server *s) {
     std::unique_lock<std::mutex> lk(s->mu);
     for (;;) {
         bool changed = false;
-        // 1. completions
+        // 1. completions: the device is polled without the lock, so that
+        //    submitters and clients are not held up by the polling
+        lk.unlock();
+        for (Slot &sl : s->slots)
+            if (sl.busy) poll_slot(sl);
+        lk.lock();
         for (Slot &sl : s->slots) {
             if (!sl.busy) continue;
-            changed |= finish_done_requests(s, sl);
-            const hipError_t q = hipEventQuery(sl.event);
-            if (q == hipSuccess) {
-                finish_batch(s, sl, DPG_OK);
+            for (size_t i : sl.newly_done) {
+                finish_ticket(s, sl.tickets[i], DPG_OK, sl.poll_time);
                 changed = true;
-            } else if (q != hipErrorNotReady) {
-                finish_batch(s, sl, DPG_ERR_HIP);
+            }
+            if (sl.polled == hipSuccess) {
+                finish_batch(s, sl, DPG_OK, sl.poll_time);
+                changed = true;
+            } else if (sl.polled != hipErrorNotReady) {
+                finish_batch(s, sl, DPG_ERR_HIP, sl.poll_time);
                 changed = true;
             }
         }
@@ -355,7 +365,7 @@ static void scheduler(dpg_server *s) {
             const double dt = std::chrono::duration<double>(Clock::now() - t_launch).count();
             lk.lock();
             s->launch_s += dt;
-            if (st != DPG_OK) finish_batch(s, sl, st);
+            if (st != DPG_OK) finish_batch(s, sl, st, Clock::now());
             changed = true;
         }
         if (changed) s->done_cv.notify_all();

@@ -17,7 +17,7 @@ def test_alloc_free_coalesce():
     assert a.stats()["in_use"] == 256 + 1024 + 256
     a.free(y)
     assert a.stats()["free_blocks"] == 2
-    w = a.alloc(900)  # first fit reuses the hole
+    w = a.alloc(900)  # the hole is the smallest block that fits
     assert w == y
     a.free(w)
     a.free(x)
@@ -69,3 +69,18 @@ def test_random_against_model():
     for addr in list(live):
         a.free(addr)
     assert a.stats()["free_blocks"] == 1
+
+
+def test_best_fit_takes_the_smallest_hole():
+    """Of the free blocks that hold a request, the smallest is taken (the
+    lowest address among equals), so small requests do not split the large
+    holes."""
+    a = dpg.Arena(BASE, 1 << 20, 256)
+    blocks = [a.alloc(n) for n in (4096, 256, 1024, 256, 1024, 256, 2048, 256)]
+    for k in (0, 2, 4, 6):
+        a.free(blocks[k])  # holes of 4096, 1024, 1024 and 2048 bytes, then the rest
+    assert a.alloc(1000) == blocks[2]
+    assert a.alloc(1024) == blocks[4]
+    assert a.alloc(1500) == blocks[6]
+    assert a.alloc(3000) == blocks[0]
+    assert a.alloc(4096) == blocks[7] + 256  # only the tail is left
