@@ -23,11 +23,14 @@ def ctx():
     c.close()
 
 
-def build_requests(n_req, seed, max_log2=15):
+def build_requests(n_req, seed, max_log2=15, sizes=None):
+    """n_req requests of N log-uniform in [1, 2^max_log2] (or N = sizes[k])."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_req):
         n = int(np.exp(rng.uniform(0, np.log(1 << max_log2))))
+        if sizes is not None:
+            n = sizes[k]
         if rng.random() < 0.75:
             rec = int(rng.choice([16, 64, 100, 256]))
             n_src = max(1, n)
@@ -101,6 +104,25 @@ def test_server_outputs_match_oracle(ctx, mode):
         assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
         if mode != "per-request":
             assert st["batches"] < len(reqs)
+    finally:
+        server.close()
+
+
+def test_server_requests_up_to_2p22_rows_match_oracle(ctx):
+    """Requests of the serving mix's full size range (up to 2^22 rows): the
+    large ones run alone through their single-request entry points, the
+    small ones in graph batches beside them; every output equals the
+    oracle's."""
+    sizes = [1 << 22, (1 << 21) + 77, 1 << 20, 3 << 18, 1000, 1 << 14, 5000, 1 << 16, (1 << 22) - 3, 1 << 19,
+             300, 1 << 12]
+    reqs = build_requests(len(sizes), seed=11, sizes=sizes)
+    server = dpg.Server(ctx, 8 << 30, max_inflight=4, max_batch_requests=64, use_graph=True)
+    try:
+        got = run_all(server, reqs)
+        for i, (_, _, want) in enumerate(reqs):
+            assert np.array_equal(got[i], want), (i, sizes[i])
+        st = server.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
     finally:
         server.close()
 
