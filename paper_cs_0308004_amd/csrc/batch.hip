@@ -490,13 +490,15 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
                     int pause = 1;
                     while (__hip_atomic_load(&descs[dep].done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
                         for (int k = 0; k < pause; ++k) __builtin_amdgcn_s_sleep(8);
-                        pause = pause < 16 ? 2 * pause : 16;
+                        pause = pause < 4 ? 2 * pause : 4;
                         if (__builtin_amdgcn_s_memrealtime() - t0 > kBatchWaitTicks) {
                             atomicOr(&hdr->timeout, 1);
                             break;
                         }
                     }
-                    __threadfence();  // acquire: the dependency's writes are visible
+                    // acquire only: the dependency's writes are visible (an
+                    // invalidate of this XCD's L2, no write-back)
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 }
             }
             s_desc = r;
@@ -523,7 +525,11 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
         }
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();  // release: this item's writes before its count
+            // release only: this item's writes before its count (a
+            // write-back of this XCD's L2; a full fence would also
+            // invalidate it, throwing away the lines that the other items
+            // on this XCD still read, such as a probe's source region)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             const uint32_t prev = atomicAdd(&descs[r].done, 1u);
             if (d.last && host_done && prev + 1 == (uint32_t)d.n_items) {
                 // the request is complete: publish to the host
