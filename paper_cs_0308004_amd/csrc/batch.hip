@@ -118,7 +118,7 @@ struct BatchHeader {
 constexpr int kBatchThreads = 256;
 constexpr int kBatchPer = 16;
 constexpr int kBatchMaxTileRows = 2048;
-constexpr int kBatchItemWords = 16384;   // ~64 KiB of output per work item
+constexpr int kBatchItemWords = 8192;    // at least ~32 KiB of output per copy item
 constexpr int kBatchDistTile = 4096;     // rids per distribute item (16 per thread)
 constexpr int kBatchMaxRuns = 2048;      // runs of a request distributed inside the batch
 constexpr int kBatchSteps = 6;           // steps of a DPG request
