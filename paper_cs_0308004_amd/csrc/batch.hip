@@ -21,9 +21,10 @@
 // -> COPY (gather), the three phases of Section 2.1.  The queue lists every
 // request's first step, then every request's second step, and so on, so a
 // step rarely waits.  Atomics on one word are serialized by the device (about
-// 20-30 ns each here), so the queue word is touched as little as possible:
-// when no step depends on another, workgroup b starts with item b and only
-// the items after the grid's first round come from the queue.  Before an
+// 20-30 ns each here), so the queue is touched as little as possible: when
+// no step depends on another, workgroup b starts with item b and only the
+// items after the grid's first round come from the queue, and the queue is
+// eight words, each handing out every eighth item in order.  Before an
 // item, a workgroup waits until every item of the step this one depends on
 // (an earlier step of the same request) has finished: those items were taken
 // from the queue earlier, by workgroups that are running, so the wait ends;
@@ -41,7 +42,7 @@
 // one copy when direct pays) fused with the read of the dimension rows in fk
 // order: the final COPY writes fact[i_j] || dim[fk_j].
 //
-// The batch header (item count, step count, sequence number, queue word) and
+// The batch header (item count, step count, sequence number, queue words) and
 // the steps (with their counters) live in device memory and are uploaded in
 // one copy, so a captured graph of k_batch is replayed with new requests
 // (dpg_batch_graph_*).
@@ -84,7 +85,6 @@ struct BatchDesc {
     uint32_t magic;         // ceil(2^32 / ((wa + wb) / vec)) for the row division
     int32_t request;        // index in the caller's request array
     int32_t vec;            // dwords per access: 4 when rows and pointers are 16-byte aligned, else 1
-    int32_t nt;             // nontemporal output stores
     int32_t op;             // BatchOp
     int32_t dep;            // step whose items must all have finished first (-1: none)
     int32_t last;           // 1: the request is done when this step is
@@ -105,14 +105,19 @@ struct BatchDesc {
     uint32_t pad;
 };
 
+// Queue words: workgroup b takes its items from queue b % 8 (item 8p + q is
+// the p-th of queue q), so the serialized atomics of one word are spread
+// over eight.
+constexpr int kBatchQueues = 8;
+
 struct BatchHeader {
     int64_t total_items;
     int32_t n_desc;
     uint32_t seq;         // launch sequence number, written into the completion words
     int32_t timeout;      // set when a dependency wait gave up (never in a correct run)
-    uint32_t queue;       // work items taken from the queue (uploaded as 0)
     int32_t no_deps;      // 1: no step waits on another (workgroup b then starts with item b)
     int32_t n_work;       // workgroups that take items when steps depend on each other
+    uint32_t queue[kBatchQueues];  // work items taken from each queue (uploaded as 0)
 };
 
 constexpr int kBatchThreads = 256;
@@ -203,13 +208,12 @@ __device__ __forceinline__ void copy_item(const BatchDesc &d, int64_t local, int
         }
     }
     __syncthreads();
-    if (d.vec == 4) {
-        if (d.nt) batch_copy<u32x4, true>(d, s_ia, s_ib, rows, row0);
-        else batch_copy<u32x4, false>(d, s_ia, s_ib, rows, row0);
-    } else {
-        if (d.nt) batch_copy<uint32_t, true>(d, s_ia, s_ib, rows, row0);
-        else batch_copy<uint32_t, false>(d, s_ia, s_ib, rows, row0);
-    }
+    // Nontemporal stores: the lines an item writes leave this XCD's L2
+    // without waiting for the release fence's write-back, which then has
+    // little to write (a 2^20-row DPG retrieval as a batch of one: 277 ->
+    // 256 us).
+    if (d.vec == 4) batch_copy<u32x4, true>(d, s_ia, s_ib, rows, row0);
+    else batch_copy<uint32_t, true>(d, s_ia, s_ib, rows, row0);
 }
 
 // rid of distribute element i (clamped to the source; a rid outside it takes
@@ -460,7 +464,13 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
     // polls and takes items from the queue costs its atomics.
     const int64_t first_dyn = hdr->no_deps ? (int64_t)gridDim.x : 0;
     bool first = hdr->no_deps != 0;
-    if (!hdr->no_deps && (int)blockIdx.x >= hdr->n_work) return;
+    const int n_active = hdr->no_deps ? (int)gridDim.x : hdr->n_work;
+    if ((int)blockIdx.x >= n_active) return;
+    // This workgroup's queue word.  Each queue hands out its items in global
+    // order and has working workgroups, so the earliest unfinished item is
+    // always running or about to be taken: every dependency wait ends.
+    const int n_q = n_active < kBatchQueues ? n_active : kBatchQueues;
+    const int q = (int)blockIdx.x % n_q;
     for (;;) {
         if (threadIdx.x == 0) {
             int64_t item;
@@ -469,7 +479,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
             } else if (first_dyn >= total_items) {
                 item = total_items;  // the first round took every item: no atomic
             } else {
-                item = first_dyn + (int64_t)atomicAdd(&hdr->queue, 1u);
+                item = first_dyn + (int64_t)n_q * (int64_t)atomicAdd(&hdr->queue[q], 1u) + q;
             }
             s_item = item;
             int r = -1;
@@ -764,7 +774,6 @@ static void copy_shape(BatchDesc &d, int64_t item_words = kBatchItemWords) {
     d.vec = (d.wa % 4 == 0 && d.wb % 4 == 0 && al % 16 == 0) ? 4 : 1;
     const uint64_t we = (uint64_t)(d.wa + d.wb) / (uint64_t)d.vec;
     d.magic = we > 1 ? (uint32_t)((0x100000000ull + we - 1) / we) : 0u;  // one element per row: j = e
-    d.nt = (double)d.n_rows * (d.wa + d.wb) * 4 > 256.0 * 1024 * 1024 ? 1 : 0;
     d.n_items = (d.n_rows + d.tile_rows - 1) / d.tile_rows;
 }
 
@@ -990,7 +999,7 @@ static void build_descs(const dpg_request *reqs, int32_t n, const std::vector<Ba
     hdr->n_desc = (int32_t)descs->size();
     hdr->seq = 0;
     hdr->timeout = 0;
-    hdr->queue = 0;
+    for (int k = 0; k < kBatchQueues; ++k) hdr->queue[k] = 0;
     hdr->no_deps = 1;
     for (const BatchDesc &d : *descs)
         if (d.dep >= 0) hdr->no_deps = 0;
