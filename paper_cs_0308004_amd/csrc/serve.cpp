@@ -242,8 +242,8 @@ static dpg_status launch_work(dpg_server *s, Slot &sl, const LaunchWork &w) {
     } else {
         const int32_t n = (int32_t)w.reqs.size();
         // a graph replay costs more host time than launching the kernel
-        // (about 16 us more per launch here): it is used for batches that
-        // amortize it
+        // (30-45 against about 10 us per batch here): it is used for
+        // batches that amortize it
         st = batch_graph_launch(sl.graph, w.reqs.data(), n, sl.stream,
                                 s->cfg.use_graph != 0 && n >= kGraphMinRequests);
     }
