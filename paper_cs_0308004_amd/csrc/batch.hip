@@ -18,7 +18,8 @@
 //
 // A request planned as direct retrieval is one OP_COPY step; a request
 // planned as DPG is the chain ZERO -> HIST -> SCAN -> SCATTER -> COPY (probe)
-// -> COPY (gather), the three phases of Section 2.1.  The queue lists every
+// -> COPY (gather), the three phases of Section 2.1 (DIST1 -> COPY -> COPY
+// when its rids fit one distribute tile).  The queue lists every
 // request's first step, then every request's second step, and so on, so a
 // step rarely waits.  Atomics on one word are serialized by the device (about
 // 20-30 ns each here), so the queue is touched as little as possible: when
@@ -64,7 +65,8 @@ enum BatchOp : int32_t {
     OP_SCATTER = 4,
     OP_SHIST = 5,     // stable sort pass: digit counts of a tile -> cnt[t][digit]
     OP_SSCAN = 6,     // stable sort pass: column scan of cnt (run boundaries per tile)
-    OP_SSCATTER = 7   // stable sort pass: (key, val) of a tile to their places, input order kept per digit
+    OP_SSCATTER = 7,  // stable sort pass: (key, val) of a tile to their places, input order kept per digit
+    OP_DIST1 = 8      // the whole distribute of a request of at most one tile, in LDS
 };
 
 struct BatchDesc {
@@ -302,6 +304,54 @@ __device__ __forceinline__ void scatter_item(const BatchDesc &d, int64_t local, 
     }
 }
 
+// OP_DIST1: the distribute of a request whose rids fit one tile, in one item:
+// the run counts, their exclusive scan and the slots all in LDS (no clear,
+// count and scan steps, no global atomics).  The order inside a run is
+// unspecified, as in OP_SCATTER.
+__device__ __forceinline__ void dist1_item(const BatchDesc &d, int32_t *s_start, int32_t *s_w) {
+    constexpr int PER = kBatchDistTile / kBatchThreads;
+    constexpr int PR = kBatchMaxRuns / kBatchThreads;
+    for (int b = threadIdx.x; b < d.n_runs; b += kBatchThreads) s_start[b] = 0;
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = k * kBatchThreads + threadIdx.x;
+        if (i < d.n_rows) atomicAdd(&s_start[batch_rid(d, i) >> d.lg_run], 1);
+    }
+    __syncthreads();
+    // exclusive scan of the counts, in place (thread t holds runs [PR t, PR (t + 1)))
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int b0 = threadIdx.x * PR;
+    int32_t sum = 0;
+    for (int k = 0; k < PR && b0 + k < d.n_runs; ++k) sum += s_start[b0 + k];
+    int32_t inc = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) s_w[wave] = inc;
+    __syncthreads();
+    int32_t run = inc - sum;
+    for (int w = 0; w < wave; ++w) run += s_w[w];
+    for (int k = 0; k < PR && b0 + k < d.n_runs; ++k) {
+        const int32_t c = s_start[b0 + k];
+        s_start[b0 + k] = run;
+        run += c;
+    }
+    __syncthreads();
+    // the rids again (read twice rather than held across the scan)
+#pragma unroll 4
+    for (int k = 0; k < PER; ++k) {
+        const int64_t i = k * kBatchThreads + threadIdx.x;
+        if (i >= d.n_rows) continue;
+        const int32_t rid = batch_rid(d, i);
+        const int32_t slot = atomicAdd(&s_start[rid >> d.lg_run], 1);
+        d.run[slot] = rid;
+        d.inv[i] = slot;
+    }
+}
+
 // Stable sort passes of the dimension-order join (the DPG-Sort join's sort
 // of (fk, i) pairs by fk, Section 4.2.1).  A tile is kBatchDistTile elements;
 // wave w holds the tile's elements [1024 w, 1024 (w + 1)), row k of it being
@@ -531,6 +581,7 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
             case OP_SHIST: shist_item(d, local, s_mem); break;
             case OP_SSCAN: sscan_item(d, s_mem); break;
             case OP_SSCATTER: sscatter_item(d, local, s_mem); break;
+            case OP_DIST1: dist1_item(d, s_mem, s_mem + kBatchMaxRuns); break;
             default: break;
         }
         __syncthreads();
@@ -779,8 +830,8 @@ static void copy_shape(BatchDesc &d, int64_t item_words = kBatchItemWords) {
 
 // The DPG chain that moves rows `src` (n_src rows of mv_bytes) in the order of
 // the ids (element i's id: ids[i * id_stride + id_word]) into INTERNAL, and
-// the distribute arrays, in scratch w: ZERO, HIST, SCAN, SCATTER, then the
-// probe (Phase II).  *internal and *inv receive INTERNAL and the slots for the
+// the distribute arrays, in scratch w: ZERO, HIST, SCAN, SCATTER (or DIST1
+// when the ids fit one tile), then the probe (Phase II).  *internal and *inv receive INTERNAL and the slots for the
 // gather step the caller adds.
 static void dpg_chain(const BatchDesc &base, const BatchRequestPlan &p, int64_t n, const uint32_t *ids,
                       int id_stride, int id_word, const void *src, int64_t n_src, int mv_bytes, char *w,
@@ -820,7 +871,15 @@ static void dpg_chain(const BatchDesc &base, const BatchRequestPlan &p, int64_t 
     pr.n_rows = n;
     copy_shape(pr);
     *inv = dist.inv;
-    for (const BatchDesc &d : {z, h, s, x, pr}) chain->push_back(d);
+    if (dist_items == 1) {
+        // one tile: the whole distribute is one item
+        BatchDesc one = dist;
+        one.op = OP_DIST1;
+        one.n_items = 1;
+        for (const BatchDesc &d : {one, pr}) chain->push_back(d);
+    } else {
+        for (const BatchDesc &d : {z, h, s, x, pr}) chain->push_back(d);
+    }
 }
 
 // The steps of the batch, in queue order: every request's first step, then

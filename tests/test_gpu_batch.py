@@ -142,6 +142,47 @@ def test_graph_replays_match_eager(ctx):
     graph.close()
 
 
+def test_batch_dpg_one_tile_boundary(ctx):
+    """DPG retrievals around the size where the whole distribute is one item
+    (at most 4096 rids) and where it takes the clear, count, scan and
+    distribute steps: permutations, repeated rids and out-of-order duplicates
+    over sources with 1, 5 and 33 runs, eagerly and by graph replay; each
+    output equals the oracle's."""
+    reqs, keep, expects = [], [], []
+    cases = [(1, 1, "perm"), (63, 63, "perm"), (4095, 4095, "perm"), (4096, 4096, "perm"), (4097, 4097, "perm"),
+             (8191, 8191, "perm"), (4096, 300, "repeat"), (4096, 1 << 20, "uniform"), (3000, 1 << 22, "uniform"),
+             (4097, 1 << 20, "uniform")]
+    for k, (n, n_src, kind) in enumerate(cases):
+        src = synth.record_bytes(n_src, 100, seed=500 + k)
+        if kind == "perm":
+            rids = synth.rids_permutation(n, seed=500 + k)
+        else:
+            rids = synth.rids_uniform(n_src, n, seed=500 + k)
+        expects.append(oracle.retrieve(src, rids))
+        s_t, r_t = torch.from_numpy(src).to(DEV), torch.from_numpy(rids).to(DEV)
+        dst = torch.empty((n, 100), dtype=torch.uint8, device=DEV)
+        reqs.append(dpg.retrieve_request(s_t, r_t, dst, dpg.ALGO_DPG))
+        keep.append((s_t, r_t, dst))
+    ctx.batch_run(reqs)
+    torch.cuda.synchronize()
+    for i, want in enumerate(expects):
+        assert np.array_equal(keep[i][2].cpu().numpy(), want), cases[i]
+    stream = torch.cuda.Stream()
+    graph = dpg.BatchGraph(ctx, 64, stream)
+    scratch = with_scratch(ctx, reqs)
+    for _ in range(2):
+        for _, _, dst in keep:
+            dst.zero_()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(stream):
+            graph.launch(reqs, stream)
+        stream.synchronize()
+        for i, want in enumerate(expects):
+            assert np.array_equal(keep[i][2].cpu().numpy(), want), cases[i]
+    del scratch
+    graph.close()
+
+
 @pytest.mark.parametrize("n_dim_log2", [0, 8, 9, 17, 25])
 def test_batch_dim_order_passes(ctx, n_dim_log2):
     """Dimension-order joins inside the persistent launch with 1 to 4 stable
