@@ -24,13 +24,15 @@
 // step rarely waits.  Atomics on one word are serialized by the device (about
 // 20-30 ns each here), so the queue is touched as little as possible: when
 // no step depends on another, workgroup b starts with item b and only the
-// items after the grid's first round come from the queue, and the queue is
-// eight words, each handing out every eighth item in order.  Before an
+// items after the grid's first round come from the queue, spread over eight
+// words (with dependencies, one word hands out every item).  Before an
 // item, a workgroup waits until every item of the step this one depends on
 // (an earlier step of the same request) has finished: those items were taken
 // from the queue earlier, by workgroups that are running, so the wait ends;
 // a bounded spin (a timeout flag in the header) keeps a kernel from running
-// on if that ever failed.
+// on if that ever failed, and the writes at positions computed by earlier
+// steps are bounds-checked, so such a kernel would still stay inside its
+// arrays.
 // Each finished item bumps its step's counter; the last item of a request's
 // last step also writes the launch's sequence number into the request's
 // completion word, which lives in host memory, so a host thread learns that
@@ -107,9 +109,9 @@ struct BatchDesc {
     uint32_t pad;
 };
 
-// Queue words: workgroup b takes its items from queue b % 8 (item 8p + q is
-// the p-th of queue q), so the serialized atomics of one word are spread
-// over eight.
+// Queue words of a batch without dependencies: workgroup b takes its items
+// after the grid's first round from queue b % 8 (item 8p + q is the p-th of
+// queue q), so the serialized atomics of one word are spread over eight.
 constexpr int kBatchQueues = 8;
 
 struct BatchHeader {
@@ -299,6 +301,7 @@ __device__ __forceinline__ void scatter_item(const BatchDesc &d, int64_t local, 
         if (rid[k] < 0) continue;
         const int64_t i = i0 + k * kBatchThreads + threadIdx.x;
         const int32_t slot = s_base[rid[k] >> d.lg_run] + rank[k];
+        if (slot < 0 || slot >= d.n_rows) continue;  // (only if a dependency wait gave up)
         d.run[slot] = rid[k];
         d.inv[i] = slot;
     }
@@ -486,8 +489,8 @@ __device__ __forceinline__ void sscatter_item(const BatchDesc &d, int64_t t, int
             const uint64_t below = peers & lanemask_lt();
             const int32_t head = valid ? mine[g] : 0;
             if (valid && below == 0) mine[g] = head + __popcll(peers);
-            if (valid) {
-                const int64_t pos = (int64_t)c[t * kSortDigits + g] + head + __popcll(below);
+            const int64_t pos = (int64_t)c[t * kSortDigits + g] + head + __popcll(below);
+            if (valid && pos >= 0 && pos < d.n_rows) {  // (always in range unless a dependency wait gave up)
                 d.keys_out[pos] = key[k];
                 d.vals_out[pos] = val[k];
             }
@@ -516,10 +519,14 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(BatchHeader *__restrict
     bool first = hdr->no_deps != 0;
     const int n_active = hdr->no_deps ? (int)gridDim.x : hdr->n_work;
     if ((int)blockIdx.x >= n_active) return;
-    // This workgroup's queue word.  Each queue hands out its items in global
-    // order and has working workgroups, so the earliest unfinished item is
-    // always running or about to be taken: every dependency wait ends.
-    const int n_q = n_active < kBatchQueues ? n_active : kBatchQueues;
+    // This workgroup's queue word.  Without dependencies nothing waits, and
+    // the items after the first round are spread over eight words.  With
+    // dependencies one word hands out every item, in order, and only to
+    // running workgroups, so a wait is always for items that running
+    // workgroups hold and it ends whatever else shares the device.  (With
+    // several words a word whose workgroups are not resident -- their XCD
+    // held by another kernel -- would stall the waits on its items.)
+    const int n_q = hdr->no_deps ? (n_active < kBatchQueues ? n_active : kBatchQueues) : 1;
     const int q = (int)blockIdx.x % n_q;
     for (;;) {
         if (threadIdx.x == 0) {
