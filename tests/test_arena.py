@@ -84,3 +84,19 @@ def test_best_fit_takes_the_smallest_hole():
     assert a.alloc(1500) == blocks[6]
     assert a.alloc(3000) == blocks[0]
     assert a.alloc(4096) == blocks[7] + 256  # only the tail is left
+
+
+def test_best_fit_ties_take_the_lowest_address():
+    """Among free blocks of the same length the lowest address is taken, and
+    freeing everything coalesces back to one block."""
+    a = dpg.Arena(BASE, 1 << 16, 256)
+    blocks = [a.alloc(512) for _ in range(8)]
+    for k in (5, 1, 3):  # three holes of 512 bytes, freed out of order
+        a.free(blocks[k])
+    assert a.alloc(300) == blocks[1]
+    assert a.alloc(512) == blocks[3]
+    assert a.alloc(1) == blocks[5]
+    for b in blocks:
+        a.free(b)
+    st = a.stats()
+    assert st["free_blocks"] == 1 and st["largest_free"] == 1 << 16 and st["in_use"] == 0
