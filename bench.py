@@ -895,15 +895,21 @@ def bench_serve(args, ctx, dpg, synth, torch, np, max_log2=22, seed_off=0, algo=
     arrivals = np.cumsum(rng.exponential(1.0, n_req))  # unit-rate Poisson process, scaled by the rate
 
     def run(server, rate):
-        """Submit at Poisson arrival times (rate requests/s; None: all at once),
-        release outputs as they complete; returns the server's stats."""
+        """Submit at Poisson arrival times (rate requests/s; None: all at once,
+        in one submit_many call), release outputs as they complete; returns
+        the server's stats."""
         server.reset_stats()
         pending = {}
         t0 = time.perf_counter()
         k = done = checked = 0
+        if rate is None:
+            # saturation: the whole queue handed over as one burst
+            for i, t in enumerate(server.submit_many(reqs)):
+                pending[t] = i
+            k = n_req
         while done < n_req:
             now = time.perf_counter() - t0
-            while k < n_req and (rate is None or arrivals[k] / rate <= now):
+            while k < n_req and arrivals[k] / rate <= now:
                 pending[server.submit(reqs[k])] = k
                 k += 1
             t = server.next_completed(0 if k < n_req else 50)

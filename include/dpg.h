@@ -553,6 +553,11 @@ dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_ser
  * arena can ever hold for requests: its size less the batch workspaces the
  * server keeps per stream slot. */
 dpg_status dpg_server_submit(dpg_server *server, const dpg_request *req, uint64_t *ticket);
+/* Queue n requests in order, as n calls of dpg_server_submit would, taking the
+ * server lock once (a client handing over a burst); tickets[i] receives
+ * request i's ticket.  DPG_ERR_INVALID_ARG, with nothing queued, for a null
+ * pointer, n < 0 or a server being destroyed. */
+dpg_status dpg_server_submit_many(dpg_server *server, const dpg_request *reqs, int32_t n, uint64_t *tickets);
 /* *dst: device address of the output once DONE (valid until released). */
 dpg_status dpg_server_poll(dpg_server *server, uint64_t ticket, int32_t *state, dpg_status *status,
                            void **dst, double *latency_ms);

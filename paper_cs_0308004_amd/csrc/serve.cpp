@@ -480,12 +480,16 @@ dpg_status dpg_server_create(dpg_ctx *ctx, const dpg_server_config *cfg, dpg_ser
     return DPG_OK;
 }
 
-dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ticket) {
-    if (!s || !req || !ticket) return DPG_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace dpg {
+
+// A request's ticket, planned without the server lock.
+static Ticket make_ticket(dpg_server *s, const dpg_request &req) {
     Ticket tk;
-    tk.req = *req;
+    tk.req = req;
     tk.req.dst = nullptr;
-    tk.out_bytes = output_bytes(*req);
+    tk.out_bytes = output_bytes(req);
     tk.submit = Clock::now();
     size_t own_ws = 0, batch_ws = 0;
     // the output will live somewhere in the arena: inputs must lie outside it
@@ -501,23 +505,53 @@ dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ti
     } else {
         tk.state = T_FAILED;
     }
+    return tk;
+}
+
+// Queue a planned ticket (under the server lock).
+static uint64_t enqueue_ticket(dpg_server *s, Ticket &tk) {
+    const uint64_t id = s->next_ticket++;
+    if (!s->any_submit) {
+        s->first_submit = tk.submit;
+        s->any_submit = true;
+    }
+    s->submitted++;
+    const bool failed = tk.state == T_FAILED;
+    if (failed) {
+        tk.done = tk.submit;
+        s->n_failed++;
+    }
+    s->tickets.emplace(id, tk);
+    if (failed) s->completed.push_back(id);
+    else s->pending.push_back(id);
+    return id;
+}
+
+}  // namespace dpg
+
+extern "C" {
+
+dpg_status dpg_server_submit(dpg_server *s, const dpg_request *req, uint64_t *ticket) {
+    if (!s || !req || !ticket) return DPG_ERR_INVALID_ARG;
+    Ticket tk = make_ticket(s, *req);
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) return DPG_ERR_INVALID_ARG;
-        *ticket = s->next_ticket++;
-        if (!s->any_submit) {
-            s->first_submit = tk.submit;
-            s->any_submit = true;
-        }
-        s->submitted++;
-        const bool failed = tk.state == T_FAILED;
-        if (failed) {
-            tk.done = tk.submit;
-            s->n_failed++;
-        }
-        s->tickets.emplace(*ticket, tk);
-        if (failed) s->completed.push_back(*ticket);
-        else s->pending.push_back(*ticket);
+        *ticket = enqueue_ticket(s, tk);
+    }
+    s->cv.notify_one();
+    return DPG_OK;
+}
+
+dpg_status dpg_server_submit_many(dpg_server *s, const dpg_request *reqs, int32_t n, uint64_t *tickets) {
+    if (!s || n < 0 || (n > 0 && (!reqs || !tickets))) return DPG_ERR_INVALID_ARG;
+    std::vector<Ticket> tks;
+    tks.reserve((size_t)n);
+    for (int32_t i = 0; i < n; ++i) tks.push_back(make_ticket(s, reqs[i]));
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        if (s->stop) return DPG_ERR_INVALID_ARG;
+        for (int32_t i = 0; i < n; ++i) tickets[i] = enqueue_ticket(s, tks[(size_t)i]);
     }
     s->cv.notify_one();
     return DPG_OK;

@@ -131,6 +131,7 @@ SIGNATURES = {
     "dpg_arena_destroy": (None, [_VP]),
     "dpg_server_create": (_I32, [_VP, ctypes.POINTER(ServerConfig), ctypes.POINTER(_VP)]),
     "dpg_server_submit": (_I32, [_VP, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "dpg_server_submit_many": (_I32, [_VP, ctypes.POINTER(Request), _I32, ctypes.POINTER(ctypes.c_uint64)]),
     "dpg_server_poll": (_I32, [_VP, ctypes.c_uint64, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                ctypes.POINTER(_VP), ctypes.POINTER(_DBL)]),
     "dpg_server_next_completed": (_I32, [_VP, _I32, ctypes.POINTER(ctypes.c_uint64)]),
@@ -634,6 +635,13 @@ class Server:
         t = ctypes.c_uint64()
         _check(lib().dpg_server_submit(self.handle, ctypes.byref(req), ctypes.byref(t)), "dpg_server_submit")
         return t.value
+
+    def submit_many(self, reqs) -> list:
+        n = len(reqs)
+        arr = (Request * max(n, 1))(*reqs)
+        t = (ctypes.c_uint64 * max(n, 1))()
+        _check(lib().dpg_server_submit_many(self.handle, arr, n, t), "dpg_server_submit_many")
+        return list(t[:n])
 
     def poll(self, ticket: int):
         state, status, dst, lat = _I32(), _I32(), _VP(), _DBL()

@@ -59,11 +59,15 @@ def build_requests(n_req, seed, max_log2=15, sizes=None):
     return out
 
 
-def run_all(server, reqs, gap_s=0.0):
-    """Submit (optionally spaced in time), collect every output by polling its
-    own tickets (safe with several submitting threads), release."""
+def run_all(server, reqs, gap_s=0.0, many=False):
+    """Submit (optionally spaced in time, or all in one submit_many call),
+    collect every output by polling its own tickets (safe with several
+    submitting threads), release."""
     tickets = {}
-    for i, (req, _, _) in enumerate(reqs):
+    if many:
+        for i, t in enumerate(server.submit_many([req for req, _, _ in reqs])):
+            tickets[t] = i
+    for i, (req, _, _) in enumerate([] if many else reqs):
         tickets[server.submit(req)] = i
         if gap_s:
             time.sleep(gap_s)
@@ -104,6 +108,26 @@ def test_server_outputs_match_oracle(ctx, mode):
         assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
         if mode != "per-request":
             assert st["batches"] < len(reqs)
+    finally:
+        server.close()
+
+
+@pytest.mark.parametrize("mode", ["graph", "per-request"])
+def test_submit_many_matches_oracle(ctx, mode):
+    """A burst of requests handed over in one submit_many call: tickets in
+    request order, every output equals the oracle's; an empty burst queues
+    nothing."""
+    reqs = build_requests(120, seed=21)
+    kw = dict(graph=dict(max_batch_requests=64, use_graph=True),
+              **{"per-request": dict(max_batch_requests=1, use_graph=False)})[mode]
+    server = dpg.Server(ctx, 1 << 30, max_inflight=4, **kw)
+    try:
+        assert server.submit_many([]) == []
+        got = run_all(server, reqs, many=True)
+        for i, (_, _, want) in enumerate(reqs):
+            assert np.array_equal(got[i], want), i
+        st = server.stats()
+        assert st["completed"] == len(reqs) and st["failed"] == 0
     finally:
         server.close()
 
